@@ -1,0 +1,442 @@
+"""FP64 CPU oracle for the MASK hot path (arXiv 2208.02734).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import or call
+this module; only the tests, the smoke check and the CPU-baseline leg of the
+benchmark do.  It shares no code with the HIP path: it is plain numpy in
+float64, written to be checked against the paper by eye, and slow.
+
+What it computes, by paper passage:
+
+* ``plan_levels``      - the level schedule of Algorithm 1 (multilevel index
+                         construction), floor division.
+* ``splitmix64_keys``,
+  ``permutation``      - the random assignment of points to groups used in
+                         Section 4.2 ("randomly assigned"), made concrete as
+                         the argsort of SplitMix64 outputs (Steele, Lea and
+                         Flood, OOPSLA 2014).
+* ``chunk_offsets``    - ``split(data, ngroups)`` of Algorithm 1: nearly
+                         equal contiguous groups (first n mod C get one more).
+* ``lloyd``            - ``kmeans(nCentroids, points)`` of Algorithm 1 as
+                         Lloyd iterations with the first k group members as
+                         initial prototypes.
+* ``build``            - Algorithm 1 itself: per-group k-means at each level,
+                         bottom-up, keeping prototypes and labels.
+* ``query``            - the k-NN search of Algorithm 2 and the text of
+                         Section 3.3 ("Searching and data insertion"),
+                         generalised from the greedy choice to a beam of the
+                         r nearest prototypes at every level.
+* ``exact_knn``        - the k-nearest-neighbour query of the problem
+                         statement (Section 1) by exhaustive search.
+
+Readings of silent or garbled passages (each one is listed in the design doc):
+the ranking key at every selection is (distance, original id), so ties go to
+the lower id; squared Euclidean distance is ranked and its square root is
+reported; empty prototypes keep their previous value; the L1 update is the
+per-dimension lower median; only level 0 is shuffled; children of a
+prototype are the items whose label is that prototype.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# --------------------------------------------------------------------------
+# Level schedule (Algorithm 1, floor division)
+# --------------------------------------------------------------------------
+
+
+def plan_levels(n: int, length_group: int, n_centroids: int) -> List[Tuple[int, int]]:
+    """Algorithm 1: ngroups = n // lengthGroup; k-means with nCentroids in
+    each group; the next level groups the ngroups*nCentroids prototypes by
+    lengthGroup again; stop once fewer than one full group remains.
+
+    Returns [(n_groups, n_centroids)] bottom-up."""
+    if length_group < 1 or n_centroids < 1:
+        raise ValueError("length_group and n_centroids must be positive")
+    levels = []
+    ngroups = n // length_group
+    while ngroups >= 1:
+        levels.append((ngroups, n_centroids))
+        ngroups = (ngroups * n_centroids) // length_group
+        if len(levels) > 64:
+            raise ValueError("schedule does not shrink (n_centroids >= length_group)")
+    return levels
+
+
+# --------------------------------------------------------------------------
+# Random assignment to groups (Section 4.2) and split (Algorithm 1)
+# --------------------------------------------------------------------------
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64_keys(seed: int, n: int) -> np.ndarray:
+    """The (i+1)-th SplitMix64 output from state ``seed`` for i = 0..n-1:
+    state_i = seed + (i+1)*gamma (mod 2^64), then the 64-bit finaliser
+    z ^= z>>30; z *= M1; z ^= z>>27; z *= M2; z ^= z>>31."""
+    i = np.arange(1, n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + i * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def permutation(seed: int, n: int) -> np.ndarray:
+    """pi = points ordered by (key, index); the keys are distinct because the
+    finaliser is a bijection and the states are distinct for n < 2^64."""
+    keys = splitmix64_keys(seed, n)
+    return np.argsort(keys, kind="stable").astype(np.int64)
+
+
+def chunk_offsets(n_items: int, n_chunks: int) -> np.ndarray:
+    """Boundaries of ``split`` into n_chunks contiguous groups whose sizes
+    differ by at most one, the larger ones first."""
+    if n_chunks < 1 or n_chunks > n_items:
+        raise ValueError("need 1 <= n_chunks <= n_items")
+    base, extra = divmod(n_items, n_chunks)
+    sizes = np.full(n_chunks, base, dtype=np.int64)
+    sizes[:extra] += 1
+    off = np.zeros(n_chunks + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    return off
+
+
+# --------------------------------------------------------------------------
+# Dissimilarity delta (Section 1: Minkowski family; Euclidean in all
+# experiments).  Squared L2 is returned for "l2" and ranked; L1 for "l1".
+# --------------------------------------------------------------------------
+
+
+def pairwise(A: np.ndarray, B: np.ndarray, metric: str = "l2", block: int = 256) -> np.ndarray:
+    """delta(a_i, b_j) for all pairs, direct form in float64:
+    l2 -> sum_k (a_ik - b_jk)^2, l1 -> sum_k |a_ik - b_jk|."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    out = np.empty((A.shape[0], B.shape[0]), dtype=np.float64)
+    for s in range(0, A.shape[0], block):
+        diff = A[s:s + block, None, :] - B[None, :, :]
+        if metric == "l2":
+            out[s:s + block] = np.einsum("ijk,ijk->ij", diff, diff)
+        elif metric == "l1":
+            out[s:s + block] = np.abs(diff).sum(axis=2)
+        else:
+            raise ValueError(f"unknown metric {metric!r}")
+    return out
+
+
+def report_distance(dsq: np.ndarray, metric: str) -> np.ndarray:
+    """Value reported to the user: the Euclidean distance for l2 (square
+    root of the ranked squared distance), the L1 sum as is."""
+    return np.sqrt(dsq) if metric == "l2" else dsq
+
+
+# --------------------------------------------------------------------------
+# k-means (Lloyd) inside one group
+# --------------------------------------------------------------------------
+
+
+def assign(points: np.ndarray, centroids: np.ndarray, metric: str = "l2"):
+    """Label of each point = index of its nearest prototype, lowest index on
+    ties (numpy argmin returns the first minimum).  Also returns each point's
+    distance to that prototype."""
+    D = pairwise(points, centroids, metric)
+    labels = np.argmin(D, axis=1)
+    return labels, D[np.arange(points.shape[0]), labels]
+
+
+def lower_median(values: np.ndarray) -> np.ndarray:
+    """Per-column lower median: the floor((m-1)/2)-th order statistic."""
+    m = values.shape[0]
+    return np.sort(values, axis=0)[(m - 1) // 2]
+
+
+def update(points: np.ndarray, labels: np.ndarray, centroids: np.ndarray, metric: str = "l2"):
+    """New prototypes: the mean (l2) or the per-dimension lower median (l1)
+    of the members; a prototype with no member keeps its previous value."""
+    points = np.asarray(points, dtype=np.float64)
+    new = np.array(centroids, dtype=np.float64, copy=True)
+    counts = np.bincount(labels, minlength=centroids.shape[0])
+    for j in range(centroids.shape[0]):
+        if counts[j] == 0:
+            continue
+        members = points[labels == j]
+        if metric == "l2":
+            new[j] = members.sum(axis=0) / counts[j]
+        else:
+            new[j] = lower_median(members)
+    return new, counts
+
+
+@dataclasses.dataclass
+class LloydResult:
+    centroids: np.ndarray  # (k, d) float64
+    labels: np.ndarray  # (m,) int64, labels of the final assignment
+    inertia: np.ndarray  # (iters,) float64: I_t = sum delta(x, c^t_{a^t})
+
+
+def lloyd_step(points: np.ndarray, centroids: np.ndarray, metric: str = "l2"):
+    """One Lloyd iteration from C_t: assignment a^t, inertia I_t computed
+    with C_t, and the updated C_{t+1}."""
+    labels, dmin = assign(points, centroids, metric)
+    inertia = float(dmin.sum())
+    new, _ = update(points, labels, centroids, metric)
+    return labels, new, inertia
+
+
+def lloyd(points: np.ndarray, k: int, iters: int, metric: str = "l2",
+          init: Optional[np.ndarray] = None) -> LloydResult:
+    """kmeans(nCentroids, points) of Algorithm 1 as Lloyd's algorithm: the
+    initial prototypes are the first k points of the group, then ``iters``
+    rounds of (assign, update), then a final assignment so the labels belong
+    to the returned prototypes."""
+    points = np.asarray(points, dtype=np.float64)
+    if k < 1 or k > points.shape[0]:
+        raise ValueError("need 1 <= k <= group size")
+    C = np.array(points[:k] if init is None else init, dtype=np.float64, copy=True)
+    log = np.empty(iters, dtype=np.float64)
+    for t in range(iters):
+        _, C, log[t] = lloyd_step(points, C, metric)
+    labels, _ = assign(points, C, metric)
+    return LloydResult(centroids=C, labels=labels, inertia=log)
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1: multilevel index construction
+# --------------------------------------------------------------------------
+
+
+@dataclasses.dataclass
+class OracleIndex:
+    """protos[l] (n_l x d, chunk-major ids: chunk c holds ids c*k_l .. c*k_l+k_l-1)
+    for l = 0..L-1 (index 0 is the first centroid level above the data);
+    parents[l] gives, for each item of the level below (data points for
+    l = 0, in original row order; prototypes of level l-1 otherwise), the id
+    of its prototype at level l."""
+
+    data: np.ndarray  # (n, d) float64
+    protos: List[np.ndarray]
+    parents: List[np.ndarray]
+    levels: List[Tuple[int, int]]
+    metric: str
+    inertia: List[np.ndarray]  # per level, (n_chunks, iters)
+    _kids: Optional[List[List[np.ndarray]]] = None
+
+    @property
+    def n_levels(self) -> int:
+        return len(self.protos)
+
+    def children(self, level: int) -> List[np.ndarray]:
+        """children(p) for every prototype p of ``level``: ids of the items
+        one level down whose label is p, ascending."""
+        if self._kids is None:
+            self._kids = [self._children(l) for l in range(self.n_levels)]
+        return self._kids[level]
+
+    def _children(self, level: int) -> List[np.ndarray]:
+        par = self.parents[level]
+        n_l = self.protos[level].shape[0]
+        order = np.argsort(par, kind="stable")
+        counts = np.bincount(par, minlength=n_l)
+        off = np.zeros(n_l + 1, dtype=np.int64)
+        off[1:] = np.cumsum(counts)
+        return [order[off[p]:off[p + 1]] for p in range(n_l)]
+
+
+def build(X: np.ndarray, levels: Sequence[Tuple[int, int]], iters: int, seed: int,
+          metric: str = "l2", perm: Optional[np.ndarray] = None) -> OracleIndex:
+    """Algorithm 1 with explicit level sizes [(n_chunks, k)] bottom-up.
+
+    Level 0 (the data) is permuted by ``permutation(seed, n)`` (or the given
+    ``perm``) and split into n_chunks contiguous groups; every upper level
+    splits the previous level's prototypes, in chunk-major id order, the same
+    way without shuffling.  Each group runs ``lloyd`` independently."""
+    data = np.asarray(X, dtype=np.float64)
+    n = data.shape[0]
+    pi = permutation(seed, n) if perm is None else np.asarray(perm, dtype=np.int64)
+    items = data[pi]
+    item_ids = pi  # original id of each item in the current order
+    protos, parents, inertia = [], [], []
+    for (n_chunks, k) in levels:
+        off = chunk_offsets(items.shape[0], n_chunks)
+        P = np.empty((n_chunks * k, data.shape[1]), dtype=np.float64)
+        par = np.empty(items.shape[0], dtype=np.int64)
+        logs = np.empty((n_chunks, iters), dtype=np.float64)
+        for c in range(n_chunks):
+            res = lloyd(items[off[c]:off[c + 1]], k, iters, metric)
+            P[c * k:(c + 1) * k] = res.centroids
+            par[item_ids[off[c]:off[c + 1]]] = c * k + res.labels
+            logs[c] = res.inertia
+        protos.append(P)
+        parents.append(par)
+        inertia.append(logs)
+        items = P
+        item_ids = np.arange(P.shape[0], dtype=np.int64)
+    return OracleIndex(data=data, protos=protos, parents=parents, levels=list(levels),
+                       metric=metric, inertia=inertia)
+
+
+def index_from_arrays(X: np.ndarray, protos: Sequence[np.ndarray], parents: Sequence[np.ndarray],
+                      metric: str = "l2") -> OracleIndex:
+    """Wrap prototypes and parent arrays produced elsewhere (for instance
+    exported from the GPU) so that ``query`` can run on them."""
+    levels = [(0, 0)] * len(protos)
+    return OracleIndex(data=np.asarray(X, dtype=np.float64),
+                       protos=[np.asarray(p, dtype=np.float64) for p in protos],
+                       parents=[np.asarray(p, dtype=np.int64) for p in parents],
+                       levels=levels, metric=metric, inertia=[])
+
+
+# --------------------------------------------------------------------------
+# Algorithm 2: k-NN search, with a beam of r prototypes per level
+# --------------------------------------------------------------------------
+
+
+def smallest(dist: np.ndarray, ids: np.ndarray, m: int) -> np.ndarray:
+    """Positions of the m smallest entries ordered by (dist, id)."""
+    order = np.lexsort((ids, dist))
+    return order[:m]
+
+
+@dataclasses.dataclass
+class QueryTrace:
+    selected: List[np.ndarray]  # per level, top level first: selected prototype ids
+    candidates: List[np.ndarray]  # per level, top level first: candidate ids
+    cand_dist: List[np.ndarray]  # the ranked distance of each candidate
+
+
+def query_one(index: OracleIndex, q: np.ndarray, k: int, r: int,
+              trace: bool = False, forced: Optional[List[np.ndarray]] = None):
+    """Descent for one query.  Top level: rank all prototypes, keep the r
+    nearest.  Each lower level: the candidates are the children of the kept
+    prototypes; keep the r nearest of them (all when fewer).  Data layer: the
+    candidates are the points under the kept level-1 prototypes; return the
+    k nearest by (delta, original id), padded with (-1, inf).
+
+    ``forced`` replaces the selection made at each level (top level first) so
+    that the leaf result can be replayed on another implementation's choice."""
+    metric = index.metric
+    L = index.n_levels
+    q = np.asarray(q, dtype=np.float64)[None, :]
+    kids = [index.children(l) for l in range(L)]
+    cand = np.arange(index.protos[L - 1].shape[0], dtype=np.int64)
+    tr = QueryTrace([], [], [])
+    for l in range(L - 1, -1, -1):
+        d = pairwise(q, index.protos[l][cand], metric)[0]
+        sel = cand[smallest(d, cand, r)]
+        if forced is not None:
+            sel = np.asarray(forced[L - 1 - l], dtype=np.int64)
+        if trace:
+            tr.selected.append(sel)
+            tr.candidates.append(cand)
+            tr.cand_dist.append(d)
+        cand = (np.concatenate([kids[l][p] for p in sel]) if sel.size else
+                np.zeros(0, dtype=np.int64))
+    d = pairwise(q, index.data[cand], metric)[0] if cand.size else np.zeros(0)
+    pos = smallest(d, cand, k)
+    ids = np.full(k, -1, dtype=np.int64)
+    dist = np.full(k, np.inf, dtype=np.float64)
+    ids[:pos.size] = cand[pos]
+    dist[:pos.size] = report_distance(d[pos], metric)
+    if trace:
+        tr.candidates.append(cand)
+        tr.cand_dist.append(d)
+        return ids, dist, tr
+    return ids, dist
+
+
+def query(index: OracleIndex, Q: np.ndarray, k: int, r: int):
+    """``query_one`` for every row of Q; returns ids (nq x k) int64 and
+    reported distances (nq x k) float64."""
+    Q = np.asarray(Q, dtype=np.float64)
+    ids = np.empty((Q.shape[0], k), dtype=np.int64)
+    dist = np.empty((Q.shape[0], k), dtype=np.float64)
+    for i in range(Q.shape[0]):
+        ids[i], dist[i] = query_one(index, Q[i], k, r)
+    return ids, dist
+
+
+# --------------------------------------------------------------------------
+# Exhaustive k-NN (problem statement, Section 1)
+# --------------------------------------------------------------------------
+
+
+def exact_knn(X: np.ndarray, Q: np.ndarray, k: int, metric: str = "l2",
+              block: int = 1 << 16):
+    """The k nearest rows of X for each query by (delta, id), exhaustively.
+
+    l1, or small X: direct form on every pair.  l2 at scale: the expanded
+    form |x|^2 + |q|^2 - 2 q.x (a float64 matrix product) screens, keeping
+    every row within twice a rounding bound of the k-th screened value, and
+    the kept rows are re-scored in direct form, so the result is the
+    direct-form ranking."""
+    X64 = np.asarray(X, dtype=np.float64)
+    Q64 = np.asarray(Q, dtype=np.float64)
+    n, d = X64.shape
+    nq = Q64.shape[0]
+    kk = min(k, n)
+    ids = np.full((nq, k), -1, dtype=np.int64)
+    dist = np.full((nq, k), np.inf, dtype=np.float64)
+    if metric == "l1" or n * d <= (1 << 22):
+        for i in range(nq):
+            dd = pairwise(Q64[i:i + 1], X64, metric)[0]
+            pos = smallest(dd, np.arange(n), kk)
+            ids[i, :kk] = pos
+            dist[i, :kk] = report_distance(dd[pos], metric)
+        return ids, dist
+    xn = np.einsum("ij,ij->i", X64, X64)
+    xn_max = float(xn.max())
+    eps = 2.0 ** -53
+    for i0 in range(0, nq, 256):
+        Qb = Q64[i0:i0 + 256]
+        qn = np.einsum("ij,ij->i", Qb, Qb)
+        # Running shortlist of (screened value, id) per query, block by block.
+        best_v = np.full((Qb.shape[0], 0), np.inf)
+        best_i = np.zeros((Qb.shape[0], 0), dtype=np.int64)
+        bound = 4.0 * (d + 4) * eps * (qn + xn_max)  # |error| of each screened value
+        for s in range(0, n, block):
+            e = min(n, s + block)
+            S = xn[None, s:e] + qn[:, None] - 2.0 * (Qb @ X64[s:e].T)
+            v = np.concatenate([best_v, S], axis=1)
+            idx = np.concatenate([best_i, np.broadcast_to(np.arange(s, e), S.shape)], axis=1)
+            kth = np.partition(v, kk - 1, axis=1)[:, kk - 1]
+            keep = v <= (kth + 2.0 * bound)[:, None]
+            width = int(keep.sum(axis=1).max())
+            nv = np.full((Qb.shape[0], width), np.inf)
+            ni = np.full((Qb.shape[0], width), -1, dtype=np.int64)
+            for row in range(Qb.shape[0]):
+                sel = np.nonzero(keep[row])[0]
+                nv[row, :sel.size] = v[row, sel]
+                ni[row, :sel.size] = idx[row, sel]
+            best_v, best_i = nv, ni
+        for row in range(Qb.shape[0]):
+            cand = best_i[row][best_i[row] >= 0]
+            dd = pairwise(Qb[row:row + 1], X64[cand], "l2")[0]
+            pos = smallest(dd, cand, kk)
+            ids[i0 + row, :kk] = cand[pos]
+            dist[i0 + row, :kk] = np.sqrt(dd[pos])
+    return ids, dist
+
+
+# --------------------------------------------------------------------------
+# Sparse rows (Section 4.3 setting: high-dimensional, sparse, non-negative)
+# --------------------------------------------------------------------------
+
+
+def sparse_pairwise_l2(indptr_a, indices_a, values_a, B: np.ndarray) -> np.ndarray:
+    """Squared Euclidean distance between CSR rows a_i and dense rows b_j,
+    |a|^2 + |b|^2 - 2 a.b in float64 (rows are unit-norm, so there is no
+    cancellation to speak of at float64)."""
+    B = np.asarray(B, dtype=np.float64)
+    na = indptr_a.shape[0] - 1
+    out = np.empty((na, B.shape[0]), dtype=np.float64)
+    bn = np.einsum("ij,ij->i", B, B)
+    for i in range(na):
+        cols = indices_a[indptr_a[i]:indptr_a[i + 1]]
+        vals = values_a[indptr_a[i]:indptr_a[i + 1]].astype(np.float64)
+        out[i] = float(vals @ vals) + bn - 2.0 * (B[:, cols] @ vals)
+    return out

@@ -1,0 +1,95 @@
+"""Plant plausible mistakes in the oracle (on the CPU, by monkeypatching)
+and check that at least one pin fails for each: a pin that cannot fail
+pins nothing."""
+import numpy as np
+import pytest
+
+from oracle import mask_oracle as mo
+from tests import test_oracle_pins as pins
+
+
+def _fails(fn):
+    try:
+        fn()
+    except AssertionError:
+        return True
+    return False
+
+
+def test_wrong_sign_in_distance_is_caught(monkeypatch):
+    orig = mo.pairwise
+
+    def bad(A, B, metric="l2", block=256):
+        return orig(A, -np.asarray(B), metric, block)
+    monkeypatch.setattr(mo, "pairwise", bad)
+    assert _fails(pins.test_assign_matches_brute_force_loops)
+
+
+def test_dropped_dimension_is_caught(monkeypatch):
+    orig = mo.pairwise
+
+    def bad(A, B, metric="l2", block=256):
+        return orig(np.asarray(A)[:, 1:], np.asarray(B)[:, 1:], metric, block)
+    monkeypatch.setattr(mo, "pairwise", bad)
+    assert _fails(pins.test_probe_all_is_exact_knn)
+
+
+def test_biased_mean_is_caught(monkeypatch):
+    orig = mo.update
+
+    def bad(points, labels, centroids, metric="l2"):
+        new, counts = orig(points, labels, centroids, metric)
+        return new * (1 + 1e-6), counts
+    monkeypatch.setattr(mo, "update", bad)
+    assert _fails(pins.test_kmeans_one_prototype_is_the_mean)
+    assert _fails(pins.test_kmeans_matches_scipy_kmeans2_with_given_init)
+
+
+def test_empty_prototype_reset_is_caught(monkeypatch):
+    orig = mo.update
+
+    def bad(points, labels, centroids, metric="l2"):
+        new, counts = orig(points, labels, centroids, metric)
+        new[counts == 0] = 0.0
+        return new, counts
+    monkeypatch.setattr(mo, "update", bad)
+    assert _fails(pins.test_empty_prototype_keeps_its_value)
+
+
+def test_upper_median_is_caught(monkeypatch):
+    monkeypatch.setattr(mo, "lower_median",
+                        lambda v: np.sort(v, axis=0)[v.shape[0] // 2])
+    assert _fails(pins.test_lower_median_minimises_l1_and_is_a_data_value)
+
+
+def test_farthest_selection_is_caught(monkeypatch):
+    monkeypatch.setattr(mo, "smallest", lambda d, ids, m: np.lexsort((ids, -d))[:m])
+    assert _fails(pins.test_greedy_descent_follows_nearest_prototype)
+
+
+def test_transposed_chunking_is_caught(monkeypatch):
+    # groups taken as strided instead of contiguous slices
+    def bad(n_items, n_chunks):
+        off = np.zeros(n_chunks + 1, dtype=np.int64)
+        off[1:] = np.arange(1, n_chunks + 1) * (n_items // n_chunks)
+        off[-1] = n_items
+        return off
+    monkeypatch.setattr(mo, "chunk_offsets", bad)
+    assert _fails(pins.test_chunk_offsets_match_numpy_array_split)
+
+
+def test_off_by_one_schedule_is_caught(monkeypatch):
+    # stops while one full group is still left (">" instead of ">=")
+    def bad(n, lg, nc):
+        levels, ng = [], n // lg
+        while ng > 1:
+            levels.append((ng, nc))
+            ng = (ng * nc) // lg
+        return levels
+    monkeypatch.setattr(mo, "plan_levels", bad)
+    assert _fails(pins.test_level_schedule_tree_depths)
+
+
+def test_wrong_splitmix_constant_is_caught(monkeypatch):
+    monkeypatch.setattr(mo, "_M2", np.uint64(0x94D049BB133111EA))
+    assert _fails(pins.test_splitmix64_known_answers)

@@ -1,0 +1,338 @@
+"""Pins of the FP64 oracle to facts outside itself: the paper's printed
+integers, published known answers, closed forms, library routines, brute
+force on tiny inputs, and invariants of Lloyd's algorithm and of the
+descent.  CPU only."""
+import json
+import os
+
+import numpy as np
+import pytest
+from scipy.cluster.vq import kmeans2
+from scipy.spatial import cKDTree
+
+from oracle import compare as oc
+from oracle import mask_oracle as mo
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- schedule
+
+def test_level_schedule_worked_examples():
+    g = _golden("paper_level_schedule.json")
+    for case in g["cases"]:
+        lv = mo.plan_levels(case["n"], case["length_group"], case["n_centroids"])
+        m = len(case["first_levels"])
+        assert [list(x) for x in lv[:m]] == case["first_levels"], case["cite"]
+        sizes = [c * k for c, k in lv]
+        assert sizes[:m] == case["first_sizes"]
+        # the top level holds at most lengthGroup prototypes
+        assert sizes[-1] <= case["length_group"]
+
+
+def test_level_schedule_tree_depths():
+    g = _golden("paper_level_schedule.json")["depth_cases"]
+    for lg, nc, depth in g["rows"]:
+        assert len(mo.plan_levels(g["n"], lg, nc)) == depth, (lg, nc)
+
+
+def test_level_schedule_rejects_non_shrinking():
+    with pytest.raises(ValueError):
+        mo.plan_levels(1000, 4, 4)
+
+
+# ------------------------------------------------------------- permutation
+
+def test_splitmix64_known_answers():
+    g = _golden("splitmix64_known_answers.json")
+    keys = mo.splitmix64_keys(g["state"], len(g["outputs_hex"]))
+    assert [int(k) for k in keys] == [int(h, 16) for h in g["outputs_hex"]]
+
+
+def test_splitmix64_matches_python_integers():
+    # Arbitrary-precision Python arithmetic, masked to 64 bits, as a second
+    # route to the same published definition.
+    def mix(z):
+        M = (1 << 64) - 1
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        return z ^ (z >> 31)
+    seed = 0x1234_5678_9ABC_DEF1
+    keys = mo.splitmix64_keys(seed, 50)
+    for i in range(50):
+        st = (seed + (i + 1) * 0x9E3779B97F4A7C15) & ((1 << 64) - 1)
+        assert int(keys[i]) == mix(st)
+
+
+def test_permutation_is_bijection_and_sorted_by_key():
+    pi = mo.permutation(7, 10_000)
+    assert np.array_equal(np.sort(pi), np.arange(10_000))
+    keys = mo.splitmix64_keys(7, 10_000)
+    assert np.all(keys[pi][1:] > keys[pi][:-1])
+
+
+def test_chunk_offsets_match_numpy_array_split():
+    for n, c in [(10, 3), (20_000, 10), (1_000_003, 100), (7, 7)]:
+        parts = np.array_split(np.arange(n), c)
+        off = mo.chunk_offsets(n, c)
+        assert [p.size for p in parts] == np.diff(off).tolist()
+
+
+# ------------------------------------------------------------------- Lloyd
+
+def _blobs(seed, n_per, centers, sigma):
+    g = np.random.default_rng(seed)
+    pts = np.concatenate([c + sigma * g.standard_normal((n_per, len(c))) for c in centers])
+    return pts[g.permutation(pts.shape[0])]
+
+
+def test_assign_matches_brute_force_loops():
+    g = np.random.default_rng(1)
+    P = g.standard_normal((13, 3))
+    C = g.standard_normal((5, 3))
+    labels, dmin = mo.assign(P, C)
+    for i in range(13):
+        best, arg = None, None
+        for j in range(5):
+            s = 0.0
+            for t in range(3):
+                s += (P[i, t] - C[j, t]) ** 2
+            if best is None or s < best:
+                best, arg = s, j
+        assert labels[i] == arg
+        assert abs(dmin[i] - best) <= 1e-12 * max(best, 1)
+
+
+def test_assign_tie_goes_to_lowest_index():
+    P = np.array([[0.0, 0.0]])
+    C = np.array([[1.0, 0.0], [-1.0, 0.0], [0.0, 1.0]])
+    labels, _ = mo.assign(P, C)
+    assert labels[0] == 0
+
+
+def test_kmeans_one_prototype_is_the_mean():
+    g = np.random.default_rng(2)
+    P = g.uniform(-5, 5, (200, 7))
+    res = mo.lloyd(P, 1, 3)
+    np.testing.assert_allclose(res.centroids[0], P.mean(axis=0), rtol=0, atol=1e-12)
+    assert np.all(res.labels == 0)
+
+
+def test_kmeans_k_equals_m_is_identity():
+    g = np.random.default_rng(3)
+    P = g.standard_normal((12, 4))
+    res = mo.lloyd(P, 12, 5)
+    assert np.array_equal(res.labels, np.arange(12))
+    np.testing.assert_array_equal(res.centroids, P)
+    assert np.all(res.inertia == 0)
+
+
+def test_kmeans_matches_scipy_kmeans2_with_given_init():
+    P = _blobs(4, 40, [np.array([0, 0, 0.]), np.array([6, 0, 0.]), np.array([0, 6, 0.]),
+                       np.array([0, 0, 6.])], 1.0)
+    init = P[:4].copy()
+    res = mo.lloyd(P, 4, 10, init=init)
+    cb, lab = kmeans2(P, init.copy(), iter=10, minit="matrix")
+    np.testing.assert_allclose(res.centroids, cb, rtol=0, atol=1e-10)
+    assert np.array_equal(res.labels, lab)
+
+
+def test_kmeans_recovers_separated_cluster_means():
+    centers = [np.array([0.0, 0.0]), np.array([100.0, 0.0]), np.array([0.0, 100.0])]
+    P = _blobs(5, 50, centers, 0.5)
+    # one initial prototype inside each cloud
+    init = np.array([P[np.argmin(((P - c) ** 2).sum(1))] for c in centers])
+    res = mo.lloyd(P, 3, 4, init=init)
+    for j, c in enumerate(centers):
+        members = P[((P - c) ** 2).sum(1) < 100]
+        np.testing.assert_allclose(res.centroids[j], members.mean(axis=0), atol=1e-12)
+
+
+def test_lloyd_invariants_l2():
+    g = np.random.default_rng(6)
+    P = g.standard_normal((300, 5)) * g.uniform(0.2, 3, (300, 1))
+    res = mo.lloyd(P, 17, 25)
+    # inertia never increases
+    assert np.all(np.diff(res.inertia) <= 1e-9 * res.inertia[:-1])
+    # final labels are an argmin under the returned prototypes
+    D = ((P[:, None, :] - res.centroids[None]) ** 2).sum(-1)
+    assert np.all(D[np.arange(300), res.labels] <= D.min(axis=1))
+    # inertia of step t is the sum of nearest distances under C_t
+    labels, C1, I0 = mo.lloyd_step(P, P[:17])
+    D0 = ((P[:, None, :] - P[None, :17]) ** 2).sum(-1)
+    assert abs(I0 - D0.min(axis=1).sum()) <= 1e-9 * I0
+
+
+def test_empty_prototype_keeps_its_value():
+    P = np.array([[0.0], [0.1], [0.2], [10.0]])
+    C = np.array([[0.0], [50.0], [10.0]])
+    labels, new, _ = mo.lloyd_step(P, C)
+    assert labels.tolist() == [0, 0, 0, 2]
+    assert new[1, 0] == 50.0
+    np.testing.assert_allclose(new[0, 0], 0.1)
+
+
+def test_lower_median_minimises_l1_and_is_a_data_value():
+    g = np.random.default_rng(7)
+    for m in [1, 2, 3, 4, 9, 10]:
+        v = g.integers(-5, 6, size=(m, 3)).astype(float)
+        med = mo.lower_median(v)
+        for t in range(3):
+            col = sorted(v[:, t].tolist())
+            assert med[t] == col[(m - 1) // 2]
+            cost = lambda a: sum(abs(x - a) for x in col)  # noqa: E731
+            assert cost(med[t]) <= min(cost(x) for x in col) + 1e-12
+
+
+def test_lloyd_invariants_l1():
+    g = np.random.default_rng(8)
+    P = g.laplace(size=(200, 4))
+    res = mo.lloyd(P, 9, 15, metric="l1")
+    assert np.all(np.diff(res.inertia) <= 1e-9 * res.inertia[:-1])
+    D = np.abs(P[:, None, :] - res.centroids[None]).sum(-1)
+    assert np.all(D[np.arange(200), res.labels] <= D.min(axis=1))
+
+
+# ------------------------------------------------------------ build/query
+
+def _small_index(seed=11, n=600, d=5, levels=((6, 10), (2, 6), (1, 4)), iters=8):
+    g = np.random.default_rng(seed)
+    X = (g.standard_normal((n, d)) * 2 + g.integers(-8, 8, (n, 1))).astype(np.float32)
+    return X, mo.build(X, list(levels), iters, seed=99)
+
+
+def test_build_structure():
+    X, ix = _small_index()
+    assert [p.shape[0] for p in ix.protos] == [60, 12, 4]
+    assert ix.parents[0].shape[0] == 600
+    pi = mo.permutation(99, 600)
+    off = mo.chunk_offsets(600, 6)
+    for c in range(6):
+        members = pi[off[c]:off[c + 1]]
+        # every point of chunk c is labelled with a prototype of chunk c
+        assert np.all(ix.parents[0][members] // 10 == c)
+    # children partition each level
+    for l in range(3):
+        kids = ix.children(l)
+        allk = np.sort(np.concatenate(kids))
+        assert np.array_equal(allk, np.arange(ix.parents[l].shape[0]))
+    assert all(np.all(np.diff(log, axis=1) <= 1e-9 * log[:, :-1]) for log in ix.inertia)
+
+
+def test_probe_all_is_exact_knn():
+    X, ix = _small_index()
+    g = np.random.default_rng(12)
+    Q = g.standard_normal((25, 5)) * 3
+    ids, dist = mo.query(ix, Q, 7, r=10_000)
+    tree = cKDTree(X.astype(np.float64))
+    tdist, tids = tree.query(Q, k=7)
+    np.testing.assert_allclose(dist, tdist, rtol=1e-12)
+    # ids equal up to exact distance ties (none expected with continuous data)
+    assert np.array_equal(ids, tids)
+
+
+def test_one_to_one_ratio_is_exact():
+    # Section 5: one centroid per data point gives exact search.
+    g = np.random.default_rng(13)
+    X = g.standard_normal((120, 3)).astype(np.float32)
+    ix = mo.build(X, [(4, 30), (2, 60)], 3, seed=5)
+    Q = g.standard_normal((10, 3))
+    k = 5
+    ids, dist = mo.query(ix, Q, k, r=k)
+    tids, tdist = mo.exact_knn(X, Q, k)
+    assert np.array_equal(ids, tids)
+    np.testing.assert_allclose(dist, tdist, rtol=1e-12)
+
+
+def test_greedy_descent_follows_nearest_prototype():
+    X, ix = _small_index()
+    q = np.array([1.0, -2.0, 0.5, 0.0, 3.0])
+    ids, dist, tr = mo.query_one(ix, q, 3, 1, trace=True)
+    # at each level the chosen prototype is the nearest among the candidates
+    for sel, cand, d in zip(tr.selected, tr.candidates, tr.cand_dist):
+        assert sel.size == 1
+        assert d[list(cand).index(sel[0])] == d.min()
+    # the result lies inside the chosen level-1 prototype's children
+    leaf = set(ix.children(0)[tr.selected[-1][0]].tolist())
+    assert set(ids[ids >= 0].tolist()) <= leaf
+
+
+def test_query_pads_when_too_few_candidates():
+    g = np.random.default_rng(14)
+    X = g.standard_normal((40, 2)).astype(np.float32)
+    ix = mo.build(X, [(2, 10), (1, 2)], 5, seed=1)
+    ids, dist = mo.query(ix, g.standard_normal((3, 2)), 40, r=1)
+    for row_i, row_d in zip(ids, dist):
+        n_valid = (row_i >= 0).sum()
+        assert n_valid < 40
+        assert np.all(np.isinf(row_d[n_valid:]))
+        assert np.all(row_i[n_valid:] == -1)
+
+
+def test_exact_knn_screened_path_matches_kdtree():
+    g = np.random.default_rng(15)
+    X = (g.standard_normal((40_000, 128)) + 5).astype(np.float32)  # n*d > 2^22
+    Q = (g.standard_normal((30, 128)) + 5).astype(np.float32)
+    ids, dist = mo.exact_knn(X, Q, 10)
+    tree = cKDTree(X.astype(np.float64))
+    tdist, tids = tree.query(Q.astype(np.float64), k=10)
+    assert np.array_equal(ids, tids)
+    np.testing.assert_allclose(dist, tdist, rtol=1e-12)
+
+
+def test_l1_query_probe_all_is_exact():
+    g = np.random.default_rng(16)
+    X = g.standard_normal((300, 4)).astype(np.float32)
+    ix = mo.build(X, [(3, 20), (1, 6)], 5, seed=2, metric="l1")
+    Q = g.standard_normal((8, 4))
+    ids, dist = mo.query(ix, Q, 5, r=1000)
+    tree = cKDTree(X.astype(np.float64))
+    tdist, tids = tree.query(Q, k=5, p=1)
+    assert np.array_equal(ids, tids)
+    np.testing.assert_allclose(dist, tdist, rtol=1e-12)
+
+
+def test_sparse_distance_equals_dense_on_densified_rows():
+    from datagen import sample_sparse
+    S = sample_sparse(30, 64, 8, seed=3)
+    D = S.to_dense()
+    g = np.random.default_rng(17)
+    B = np.abs(g.standard_normal((5, 64)))
+    got = mo.sparse_pairwise_l2(S.indptr, S.indices, S.values, B)
+    ref = mo.pairwise(D, B)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------- comparator
+
+def test_comparator_accepts_self_and_near_ties_rejects_errors():
+    X, ix = _small_index()
+    g = np.random.default_rng(18)
+    Q = g.standard_normal((10, 5))
+    ids, dist = mo.query(ix, Q, 6, r=3)
+    true = oc.true_distances(X, Q, ids)
+    assert oc.check_knn(ids, dist, ids, dist, true).ok
+    # swap two neighbours that are far from tied -> rejected
+    bad = ids.copy()
+    bad[0, [0, 5]] = bad[0, [5, 0]]
+    tb = oc.true_distances(X, Q, bad)
+    assert not oc.check_knn(bad, tb, ids, dist, tb).ok
+    # a distance off by 1e-4 relative -> rejected
+    off = dist.copy()
+    off[1, 2] *= 1 + 1e-4
+    assert not oc.check_knn(ids, off, ids, dist, true).ok
+
+
+def test_recall_counts_ties():
+    true_ids = np.array([[1, 2, 3]])
+    true_dist = np.array([[1.0, 2.0, 3.0]])
+    got = np.array([[1, 2, 9]])
+    got_true = np.array([[1.0, 2.0, 3.0]])  # id 9 ties the 3rd distance
+    assert oc.recall_at_k(got, true_ids, true_dist, got_true, 3) == 1.0
+    got_true2 = np.array([[1.0, 2.0, 3.5]])
+    assert abs(oc.recall_at_k(got, true_ids, true_dist, got_true2, 3) - 2 / 3) < 1e-12
