@@ -1,0 +1,214 @@
+/*
+ * mask.h - C ABI of the MI355X (gfx950) implementation of the MASK hot path
+ * (multilevel approximate similarity search with k-means, arXiv 2208.02734).
+ *
+ * Two operations sit behind this boundary:
+ *   build  - Algorithm 1 (multilevel index construction): split the data into
+ *            groups, run k-means in every group, summarise the prototypes of
+ *            one level with k-means again, bottom-up;
+ *   query  - Algorithm 2 (k-NN search) and Section 3.3 (searching): descend
+ *            from the top level through the prototypes nearest to the query,
+ *            generalised from the single nearest prototype to a beam of the r
+ *            nearest at every level, and rank the data points under the
+ *            chosen leaves.
+ * The inputs follow the problem statement of Section 1: a dataset, a
+ * dissimilarity delta, the level sizes, the queries, k and the probe width r.
+ *
+ * Conventions for every call:
+ *   - every call returns a mask_status; none throws, aborts or prints;
+ *     mask_last_error() returns a thread-local description of the last
+ *     failure on the calling thread;
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary CPU memory;
+ *   - the caller owns every buffer it passes in; the library never frees
+ *     them and keeps no pointer to them after the call returns (build) or
+ *     after the stream reaches the enqueued work (query);
+ *   - invalid arguments return MASK_ERR_INVALID before anything is
+ *     allocated or enqueued; an allocation failure returns MASK_ERR_NOMEM
+ *     after releasing what the call allocated; a HIP runtime error returns
+ *     MASK_ERR_DEVICE.
+ */
+#ifndef MASK_H
+#define MASK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MASK_OK = 0,
+  MASK_ERR_INVALID = 1,     /* bad argument; nothing was allocated or enqueued */
+  MASK_ERR_NOMEM = 2,       /* device allocation failed */
+  MASK_ERR_DEVICE = 3,      /* a HIP runtime call failed */
+  MASK_ERR_UNSUPPORTED = 4, /* valid request this build does not implement */
+  MASK_ERR_BUSY = 5,        /* a request that can never fit the serving arena */
+  MASK_ERR_SHUTDOWN = 6     /* the server is shutting down */
+} mask_status;
+
+/* The dissimilarity delta (Section 1, Minkowski family).  Euclidean is the
+ * one every experiment of the paper uses; ranking uses the squared distance
+ * and the Euclidean distance is reported.  L1 ranks and reports sum |a-b|. */
+typedef enum { MASK_L2 = 0, MASK_L1 = 1 } mask_metric;
+
+/* Arithmetic of the distance screening.  MASK_FP32 is the plain form. */
+typedef enum { MASK_FP32 = 0, MASK_BF16 = 1, MASK_FP8_E4M3 = 2 } mask_precision;
+
+/* Optional device allocator (for instance PyTorch's caching allocator).
+ * alloc returns NULL on failure; free receives the size that was allocated.
+ * A NULL mask_allocator* means hipMalloc / hipFree. */
+typedef struct {
+  void* ctx;
+  void* (*alloc)(void* ctx, size_t bytes, void* hip_stream);
+  void (*free)(void* ctx, void* ptr, size_t bytes, void* hip_stream);
+} mask_allocator;
+
+typedef enum { MASK_DENSE = 0, MASK_CSR = 1 } mask_layout;
+
+/* A matrix of n rows (points or queries) with dim columns, device memory.
+ * DENSE: x is row-major n x dim float32 with row stride ld floats
+ *        (ld == 0 means ld = dim).
+ * CSR:   indptr int64[n+1], indices int32[nnz] (column ids, each < dim),
+ *        values float32[nnz].  (Sparse input: see mask_build.) */
+typedef struct {
+  int32_t layout;
+  int64_t n;
+  int32_t dim;
+  int32_t ld;
+  const float* x;
+  const int64_t* indptr;
+  const int32_t* indices;
+  const float* values;
+  int64_t nnz;
+} mask_matrix;
+
+/* One level of the index, bottom-up: the items of the level below (the data
+ * for levels[0]) are split into n_chunks contiguous groups of nearly equal
+ * size (Algorithm 1, split) and k-means with k prototypes runs in each. */
+typedef struct {
+  int32_t n_chunks;
+  int32_t k;
+} mask_level;
+
+typedef struct {
+  int32_t metric;        /* mask_metric */
+  int32_t precision;     /* mask_precision */
+  int32_t n_levels;      /* 1..16 */
+  const mask_level* levels; /* host array [n_levels], bottom-up */
+  int32_t lloyd_iters;   /* Lloyd iterations per level (>= 0) */
+  uint64_t seed;         /* seeds the level-0 permutation */
+  int32_t rerank_factor; /* precision forms: FP32 re-rank of rerank_factor*k*r */
+  const int32_t* perm;   /* optional device int32[n]: level-0 order; NULL = from seed */
+} mask_build_params;
+
+typedef struct mask_index mask_index;
+
+typedef struct {
+  int64_t n;
+  int32_t dim;
+  int32_t n_levels;
+  int32_t metric;
+  int32_t precision;
+  int64_t level_size[16];    /* prototypes per level, bottom-up */
+  int64_t device_bytes;      /* device memory held by the index */
+  int64_t refined_last_level;/* points re-scored in direct form by the last
+                                assignment of the build (plain form) */
+} mask_info;
+
+/* Level schedule of Algorithm 1: ngroups = n / length_group (floor); every
+ * level summarises the previous one with n_centroids prototypes per group;
+ * stop once fewer than one full group remains.  Writes up to cap levels to
+ * out (host) and the count to *n_levels.  MASK_ERR_INVALID when the schedule
+ * does not shrink (n_centroids >= length_group) or does not fit cap. */
+mask_status mask_plan_levels(int64_t n, int32_t length_group, int32_t n_centroids,
+                             mask_level* out, int32_t cap, int32_t* n_levels);
+
+/* Algorithm 1.  data: device matrix (DENSE; dim <= 256 for the MFMA
+ * assignment).  Level 0 is permuted by the argsort of the SplitMix64
+ * outputs h(seed, i) (or by p->perm) and split into levels[0].n_chunks
+ * groups; each group runs lloyd_iters Lloyd iterations starting from its
+ * first k members, then a final assignment.  Each chunk must hold at least k
+ * items.  The index copies what it needs: data may be freed after the call.
+ * Work runs on hip_stream (NULL = the null stream); the call returns after it
+ * completes.  On success *out owns device memory until mask_free. */
+mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
+                       const mask_allocator* a, void* hip_stream, mask_index** out);
+
+/* Algorithm 2 with a beam: for each of the q->n queries (device, DENSE,
+ * dim equal to the index's) keep the r nearest prototypes of the top level,
+ * then at each level below the r nearest children of those, then return the
+ * k nearest data points under the kept level-1 prototypes.  Ranking key:
+ * (distance, original id).  out_ids: device int32[q->n * k] (original data
+ * row ids), out_dist: device float32[q->n * k], rows ascending; slots beyond
+ * the candidate count hold id -1 and +inf.  1 <= k <= 512 and 1 <= r <= 512.
+ * Asynchronous on hip_stream; allocates nothing.  Each query's result does
+ * not depend on the other queries of the batch. */
+mask_status mask_query(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
+                       int32_t* out_ids, float* out_dist, void* hip_stream);
+
+/* mask_query plus the prototypes kept at every level: sel is device
+ * int32[q->n * n_levels * r], level-major from the top level down, each set
+ * of chunk-major prototype ids in no particular order, padded with -1. */
+mask_status mask_query_debug(const mask_index* ix, const mask_matrix* q, int32_t k,
+                             int32_t r, int32_t* out_ids, float* out_dist, int32_t* sel,
+                             void* hip_stream);
+
+/* Releases the index (NULL is allowed).  Must not race with queries. */
+mask_status mask_free(mask_index* ix);
+
+mask_status mask_index_info(const mask_index* ix, mask_info* out);
+
+/* Copies level `level` (1 = first prototype level, n_levels = top) to host
+ * memory: protos_host float32[n_l * dim] in chunk-major id order, and, when
+ * parent_host is not NULL, parent_host int32[n_{l-1}] = chunk-major id of the
+ * level-l prototype of each item one level down (original data row order
+ * for level 1).  Synchronous. */
+mask_status mask_export_level(const mask_index* ix, int32_t level, float* protos_host,
+                              int32_t* parent_host);
+
+/* Builds an index from prototypes and parents computed elsewhere (host
+ * arrays laid out as mask_export_level writes them), so that a query can be
+ * compared on an index shared with another implementation.  data as in
+ * mask_build; p supplies metric and precision. */
+mask_status mask_import(const mask_matrix* data, int32_t n_levels, const mask_level* levels,
+                        const float* const* protos_host, const int32_t* const* parents_host,
+                        const mask_build_params* p, const mask_allocator* a, void* hip_stream,
+                        mask_index** out);
+
+/* The batched per-group k-means of Algorithm 1 on its own (the build's
+ * inner loop): items (device, DENSE, n x dim) are split into n_chunks
+ * contiguous groups of nearly equal size; group c uses prototypes
+ * centroids[c*k .. c*k+k-1].  init: device float32[n_chunks*k*dim] starting
+ * prototypes, or NULL for the first k items of each group.  Runs `iters`
+ * Lloyd iterations, then a final assignment.  Outputs (device): centroids
+ * float32[n_chunks*k*dim], labels int32[n] (chunk-major prototype ids of the
+ * final assignment), inertia float64[iters*n_chunks] (sum over the group of
+ * delta(x, c^t_{a^t}) at iteration t; may be NULL).  Synchronous. */
+mask_status mask_kmeans(const mask_matrix* items, int32_t n_chunks, int32_t k, int32_t iters,
+                        int32_t metric, const float* init, float* centroids, int32_t* labels,
+                        double* inertia, const mask_allocator* a, void* hip_stream);
+
+const char* mask_last_error(void);
+
+/* Kernel timing for measurement: while enabled, the library's main kernels
+ * (assignment, refinement, update, member sort, descent) record HIP events
+ * on the stream they are launched on.  Enabling (or disabling) discards what
+ * was recorded.  Adds event records to every instrumented launch. */
+mask_status mask_timing_enable(int32_t on);
+
+/* Writes one line per kernel name, "name launches total_ms", plus the
+ * counters "descent_rows <candidate rows evaluated by the descent> 0",
+ * "refine_small_points <n> 0" and "refine_full_points <n> 0" (points the
+ * assignment re-scored in direct form on 2-3 prototypes / on the whole
+ * group), to buf (host,
+ * NUL-terminated, truncated to cap); *needed receives the full size.
+ * Waits for the recorded events. */
+mask_status mask_timing_report(char* buf, int64_t cap, int64_t* needed);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MASK_H */

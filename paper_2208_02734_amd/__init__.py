@@ -1,0 +1,330 @@
+"""Python binding of libmask.so, the MI355X (gfx950) implementation of the
+MASK hot path (multilevel approximate similarity search with k-means).
+
+Argument marshalling only: every step of the build and of the query runs in
+the library's HIP kernels.  PyTorch provides device memory (tensors, and the
+caching allocator the library allocates through) and the current stream.
+The functions keep the C names of ``include/mask.h``.  When the library is
+not built the import succeeds but every call raises ``MaskError``; there is
+no other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libmask.so")
+
+MASK_OK = 0
+_STATUS = {0: "MASK_OK", 1: "MASK_ERR_INVALID", 2: "MASK_ERR_NOMEM", 3: "MASK_ERR_DEVICE",
+           4: "MASK_ERR_UNSUPPORTED", 5: "MASK_ERR_BUSY", 6: "MASK_ERR_SHUTDOWN"}
+METRICS = {"l2": 0, "l1": 1}
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp8": 2}
+MAX_LEVELS = 16
+
+
+class MaskError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class mask_matrix(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_int32), ("n", ctypes.c_int64), ("dim", ctypes.c_int32),
+                ("ld", ctypes.c_int32), ("x", ctypes.c_void_p), ("indptr", ctypes.c_void_p),
+                ("indices", ctypes.c_void_p), ("values", ctypes.c_void_p),
+                ("nnz", ctypes.c_int64)]
+
+
+class mask_level(ctypes.Structure):
+    _fields_ = [("n_chunks", ctypes.c_int32), ("k", ctypes.c_int32)]
+
+
+class mask_build_params(ctypes.Structure):
+    _fields_ = [("metric", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("levels", ctypes.POINTER(mask_level)),
+                ("lloyd_iters", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("rerank_factor", ctypes.c_int32), ("perm", ctypes.c_void_p)]
+
+
+class mask_info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("metric", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("level_size", ctypes.c_int64 * MAX_LEVELS), ("device_bytes", ctypes.c_int64),
+                ("refined_last_level", ctypes.c_int64)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                            ctypes.c_void_p)
+
+
+class mask_allocator(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
+
+
+_lib = None
+
+EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_debug", "mask_free",
+            "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
+            "mask_last_error", "mask_timing_enable", "mask_timing_report"]
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises MaskError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise MaskError(3, f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2208_02734_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, VP = ctypes.POINTER, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    L.mask_plan_levels.argtypes = [I64, I32, I32, P(mask_level), I32, P(I32)]
+    L.mask_build.argtypes = [P(mask_matrix), P(mask_build_params), P(mask_allocator), VP, P(VP)]
+    L.mask_query.argtypes = [VP, P(mask_matrix), I32, I32, VP, VP, VP]
+    L.mask_query_debug.argtypes = [VP, P(mask_matrix), I32, I32, VP, VP, VP, VP]
+    L.mask_free.argtypes = [VP]
+    L.mask_index_info.argtypes = [VP, P(mask_info)]
+    L.mask_export_level.argtypes = [VP, I32, VP, VP]
+    L.mask_import.argtypes = [P(mask_matrix), I32, P(mask_level), P(VP), P(VP),
+                              P(mask_build_params), P(mask_allocator), VP, P(VP)]
+    L.mask_kmeans.argtypes = [P(mask_matrix), I32, I32, I32, I32, VP, VP, VP, VP,
+                              P(mask_allocator), VP]
+    L.mask_timing_enable.argtypes = [I32]
+    L.mask_timing_report.argtypes = [ctypes.c_char_p, I64, P(I64)]
+    L.mask_last_error.restype = ctypes.c_char_p
+    L.mask_last_error.argtypes = []
+    for name in EXPORTED:
+        if name != "mask_last_error":
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != MASK_OK:
+        raise MaskError(status, lib().mask_last_error().decode(errors="replace"))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dense(t) -> mask_matrix:
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2:
+        raise MaskError(1, "expected a 2-D float32 CUDA tensor")
+    if t.shape[0] > 0 and t.stride(1) != 1:
+        raise MaskError(1, "rows must be contiguous")
+    m = mask_matrix()
+    m.layout = 0
+    m.n = t.shape[0]
+    m.dim = t.shape[1]
+    m.ld = t.stride(0) if t.shape[0] > 1 else t.shape[1]
+    m.x = t.data_ptr()
+    return m
+
+
+class _TorchAllocator:
+    """mask_allocator backed by PyTorch's caching allocator."""
+
+    def __init__(self, device: int):
+        torch = _torch()
+        self.device = device
+
+        def _alloc(ctx, nbytes, stream):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), self.device, stream or 0)
+            except Exception:  # out of memory -> the library reports MASK_ERR_NOMEM
+                return None
+
+        def _free(ctx, ptr, nbytes, stream):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._a = _ALLOC_FN(_alloc)
+        self._f = _FREE_FN(_free)
+        self.struct = mask_allocator(None, self._a, self._f)
+
+
+class Index:
+    """Owner of a mask_index handle."""
+
+    def __init__(self, handle: int, allocator=None, metric: str = "l2"):
+        self.handle = ctypes.c_void_p(handle)
+        self._allocator = allocator  # keeps the callbacks alive as long as the index
+        self.metric = metric
+
+    def info(self) -> dict:
+        inf = mask_info()
+        _check(lib().mask_index_info(self.handle, ctypes.byref(inf)))
+        return {"n": inf.n, "dim": inf.dim, "n_levels": inf.n_levels, "metric": inf.metric,
+                "precision": inf.precision,
+                "level_size": [inf.level_size[i] for i in range(inf.n_levels)],
+                "device_bytes": inf.device_bytes,
+                "refined_last_level": inf.refined_last_level}
+
+    def export_level(self, level: int) -> Tuple[np.ndarray, np.ndarray]:
+        """(prototypes n_l x dim in chunk-major id order, parent id of each
+        item one level down)."""
+        inf = self.info()
+        n_l = inf["level_size"][level - 1]
+        n_below = inf["n"] if level == 1 else inf["level_size"][level - 2]
+        P = np.empty((n_l, inf["dim"]), dtype=np.float32)
+        par = np.empty(n_below, dtype=np.int32)
+        _check(lib().mask_export_level(self.handle, level, P.ctypes.data, par.ctypes.data))
+        return P, par
+
+    def free(self):
+        if self.handle and self.handle.value:
+            lib().mask_free(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _levels_array(levels: Sequence[Tuple[int, int]]):
+    arr = (mask_level * len(levels))()
+    for i, (c, k) in enumerate(levels):
+        arr[i].n_chunks = int(c)
+        arr[i].k = int(k)
+    return arr
+
+
+def mask_plan_levels(n: int, length_group: int, n_centroids: int) -> List[Tuple[int, int]]:
+    out = (mask_level * (MAX_LEVELS * 4))()
+    cnt = ctypes.c_int32()
+    _check(lib().mask_plan_levels(n, length_group, n_centroids, out, MAX_LEVELS * 4,
+                                  ctypes.byref(cnt)))
+    return [(out[i].n_chunks, out[i].k) for i in range(cnt.value)]
+
+
+def _params(levels, iters, seed, metric, precision, rerank_factor, perm):
+    lv = _levels_array(levels)
+    p = mask_build_params()
+    p.metric = METRICS[metric]
+    p.precision = PRECISIONS[precision]
+    p.n_levels = len(levels)
+    p.levels = lv
+    p.lloyd_iters = iters
+    p.seed = seed & 0xFFFFFFFFFFFFFFFF
+    p.rerank_factor = rerank_factor
+    p.perm = perm.data_ptr() if perm is not None else None
+    return p, lv
+
+
+def mask_build(data, levels: Sequence[Tuple[int, int]], iters: int = 30, seed: int = 0,
+               metric: str = "l2", precision: str = "fp32", perm=None, rerank_factor: int = 4,
+               stream=None, torch_allocator: bool = True) -> Index:
+    """Algorithm 1 on a device tensor (n x dim float32); returns the index."""
+    torch = _torch()
+    m = _dense(data)
+    if perm is not None and (perm.dtype != torch.int32 or not perm.is_cuda):
+        raise MaskError(1, "perm must be an int32 CUDA tensor")
+    p, lv = _params(levels, iters, seed, metric, precision, rerank_factor, perm)
+    alloc = _TorchAllocator(data.device.index or 0) if torch_allocator else None
+    h = ctypes.c_void_p()
+    _check(lib().mask_build(ctypes.byref(m), ctypes.byref(p),
+                            ctypes.byref(alloc.struct) if alloc else None,
+                            _stream_handle(stream), ctypes.byref(h)))
+    return Index(h.value, alloc, metric)
+
+
+def mask_query(index: Index, queries, k: int, r: int, stream=None, debug: bool = False):
+    """Descent for every row of ``queries``; returns (ids int32, dist float32)
+    tensors of shape (nq, k), plus the kept prototypes per level when
+    ``debug``."""
+    torch = _torch()
+    m = _dense(queries)
+    nq = queries.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    if debug:
+        L = index.info()["n_levels"]
+        sel = torch.empty((nq, L, r), dtype=torch.int32, device=queries.device)
+        _check(lib().mask_query_debug(index.handle, ctypes.byref(m), k, r, ids.data_ptr(),
+                                      dist.data_ptr(), sel.data_ptr(), _stream_handle(stream)))
+        return ids, dist, sel
+    _check(lib().mask_query(index.handle, ctypes.byref(m), k, r, ids.data_ptr(),
+                            dist.data_ptr(), _stream_handle(stream)))
+    return ids, dist
+
+
+def mask_free(index: Index):
+    index.free()
+
+
+def mask_import(data, levels: Sequence[Tuple[int, int]], protos: Sequence[np.ndarray],
+                parents: Sequence[np.ndarray], metric: str = "l2", stream=None,
+                torch_allocator: bool = True) -> Index:
+    """Index from prototypes (chunk-major, per level) and parent ids (per
+    level, for the items one level down), e.g. built by another
+    implementation."""
+    m = _dense(data)
+    L = len(levels)
+    P = [np.ascontiguousarray(p, dtype=np.float32) for p in protos]
+    Q = [np.ascontiguousarray(q, dtype=np.int32) for q in parents]
+    pp = (ctypes.c_void_p * L)(*[p.ctypes.data for p in P])
+    qq = (ctypes.c_void_p * L)(*[q.ctypes.data for q in Q])
+    prm, lv = _params(levels, 0, 0, metric, "fp32", 4, None)
+    alloc = _TorchAllocator(data.device.index or 0) if torch_allocator else None
+    h = ctypes.c_void_p()
+    _check(lib().mask_import(ctypes.byref(m), L, _levels_array(levels), pp, qq,
+                             ctypes.byref(prm), ctypes.byref(alloc.struct) if alloc else None,
+                             _stream_handle(stream), ctypes.byref(h)))
+    return Index(h.value, alloc, metric)
+
+
+def mask_kmeans(items, n_chunks: int, k: int, iters: int, init=None, metric: str = "l2",
+                stream=None):
+    """Batched per-group Lloyd on a device tensor; returns (centroids
+    (n_chunks*k x dim), labels int32, inertia float64 (iters x n_chunks))."""
+    torch = _torch()
+    m = _dense(items)
+    dim = items.shape[1]
+    cent = torch.empty((n_chunks * k, dim), dtype=torch.float32, device=items.device)
+    labels = torch.empty(items.shape[0], dtype=torch.int32, device=items.device)
+    inertia = torch.zeros((max(iters, 1), n_chunks), dtype=torch.float64, device=items.device)
+    if init is not None:
+        init = init.contiguous()
+    alloc = _TorchAllocator(items.device.index or 0)
+    _check(lib().mask_kmeans(ctypes.byref(m), n_chunks, k, iters, METRICS[metric],
+                             init.data_ptr() if init is not None else None, cent.data_ptr(),
+                             labels.data_ptr(), inertia.data_ptr(),
+                             ctypes.byref(alloc.struct), _stream_handle(stream)))
+    return cent, labels, inertia[:iters]
+
+
+def mask_timing_enable(on: bool = True):
+    _check(lib().mask_timing_enable(1 if on else 0))
+
+
+def mask_timing_report() -> dict:
+    """{kernel name: (launches, total milliseconds)} of the instrumented
+    launches since timing was enabled; "descent_rows" counts the candidate
+    rows the descent evaluated."""
+    need = ctypes.c_int64()
+    _check(lib().mask_timing_report(None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(int(need.value) + 1)
+    _check(lib().mask_timing_report(buf, len(buf), ctypes.byref(need)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out

@@ -1,0 +1,578 @@
+// Host runtime behind the C ABI of include/mask.h: argument checks, the
+// level loop of Algorithm 1, the layout of the finished index, and the
+// entry points.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "internal.hpp"
+
+namespace mask {
+
+namespace {
+thread_local std::string g_last_error;
+
+struct TimingState {
+  std::mutex mu;
+  bool on = false;
+  struct Rec { std::string name; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<std::pair<std::string, hipEvent_t>> open;  // started, not yet ended
+  unsigned long long* rows = nullptr;  // [0] descent rows, [1..2] refine counts
+};
+TimingState& timing() {
+  static TimingState t;
+  return t;
+}
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+bool timing_enabled() { return timing().on; }
+
+void timing_record(const char* name, hipStream_t s, bool start) {
+  TimingState& t = timing();
+  std::lock_guard<std::mutex> g(t.mu);
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, s);
+  if (start) {
+    t.open.push_back({name, e});
+  } else {
+    for (size_t i = t.open.size(); i-- > 0;) {
+      if (t.open[i].first == name) {
+        t.recs.push_back({name, t.open[i].second, e});
+        t.open.erase(t.open.begin() + i);
+        return;
+      }
+    }
+    (void)hipEventDestroy(e);
+  }
+}
+
+unsigned long long* timing_row_counter() { return timing().on ? timing().rows : nullptr; }
+unsigned long long* timing_refine_counter() {
+  return timing().on && timing().rows ? timing().rows + 1 : nullptr;
+}
+
+namespace {
+
+int bits_for(int64_t n) {
+  int b = 0;
+  while (b < 63 && ((int64_t)1 << b) < n) ++b;
+  return b;
+}
+
+int round_up4(int d) { return (d + 3) & ~3; }
+
+// split() of Algorithm 1: n_chunks contiguous groups whose sizes differ by at
+// most one, the larger ones first.
+std::vector<int64_t> split_offsets(int64_t n, int n_chunks) {
+  std::vector<int64_t> off(n_chunks + 1);
+  const int64_t base = n / n_chunks, extra = n % n_chunks;
+  off[0] = 0;
+  for (int c = 0; c < n_chunks; ++c) off[c + 1] = off[c] + base + (c < extra ? 1 : 0);
+  return off;
+}
+
+void make_plan(ChunkPlan& plan, int64_t n_items, int n_chunks, int k, Arena& a, hipStream_t s) {
+  plan.n_chunks = n_chunks;
+  plan.k = k;
+  plan.n_items = n_items;
+  plan.off = split_offsets(n_items, n_chunks);
+  plan.max_chunk = 0;
+  for (int c = 0; c < n_chunks; ++c)
+    plan.max_chunk = std::max(plan.max_chunk, plan.off[c + 1] - plan.off[c]);
+  plan.d_off = a.alloc<int64_t>(n_chunks + 1);
+  MASK_HIP(hipMemcpyAsync(plan.d_off, plan.off.data(), (n_chunks + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+}
+
+void check_dense(const mask_matrix* m, const char* what) {
+  MASK_CHECK(m != nullptr, std::string(what) + " is NULL");
+  MASK_CHECK(m->layout == MASK_DENSE, std::string(what) + ": only DENSE is supported here");
+  MASK_CHECK(m->n >= 0 && m->dim >= 1, std::string(what) + ": bad shape");
+  MASK_CHECK(m->ld == 0 || m->ld >= m->dim, std::string(what) + ": ld < dim");
+  MASK_CHECK(m->n == 0 || m->x != nullptr, std::string(what) + ": x is NULL");
+}
+
+int ld_of(const mask_matrix* m) { return m->ld ? m->ld : m->dim; }
+
+void check_levels(int64_t n, int n_levels, const mask_level* levels, std::vector<int64_t>& sizes) {
+  MASK_CHECK(n_levels >= 1 && n_levels <= kMaxLevels, "n_levels must be in [1, 16]");
+  MASK_CHECK(levels != nullptr, "levels is NULL");
+  sizes.assign(n_levels + 1, 0);
+  sizes[0] = n;
+  for (int l = 0; l < n_levels; ++l) {
+    const int64_t items = sizes[l];
+    const int C = levels[l].n_chunks, k = levels[l].k;
+    MASK_CHECK(C >= 1 && k >= 1, "level with n_chunks < 1 or k < 1");
+    MASK_CHECK(items / C >= k, "a chunk holds fewer items than its k");
+    sizes[l + 1] = (int64_t)C * k;
+    MASK_CHECK(sizes[l + 1] < ((int64_t)1 << 31), "level too large");
+  }
+}
+
+mask_status fail(const Error& e) {
+  set_error(e.msg);
+  return e.status;
+}
+
+// Orders every level so that the children of each prototype are contiguous
+// one level down, top-down: the top level keeps chunk-major order; the items
+// of each level below are stably sorted by the position of their parent.
+// labels[l] (l = 1..L) holds the chunk-major parent id of every item of level
+// l-1 in that level's build order; items0_orig maps level-0 build order to
+// data row ids; protos_cm[l] are the chunk-major prototypes.
+void finalize_layout(mask_index& ix, const std::vector<int32_t*>& labels,
+                     const std::vector<float*>& protos_cm, const float* items0,
+                     const uint32_t* items0_orig, Arena& scratch, hipStream_t s) {
+  const int L = ix.n_levels;
+  const int ld = ix.ld, dim = ix.dim;
+  int64_t max_items = 0;
+  for (int l = 0; l <= L; ++l) max_items = std::max(max_items, ix.level_n[l]);
+  uint32_t* keys = scratch.alloc<uint32_t>(max_items);
+  uint32_t* ord = scratch.alloc<uint32_t>(max_items);
+  SortWork sw;
+  sort_work_alloc(sw, max_items, false, scratch);
+
+  // top level: chunk-major order
+  const int64_t nL = ix.level_n[L];
+  ix.protos[L] = ix.mem.alloc<float>(nL * ld);
+  copy_rows(protos_cm[L], ld, nL, ld, ix.protos[L], ld, s);
+  ix.orig[L] = ix.mem.alloc<int32_t>(nL);
+  ix.inv[L] = ix.mem.alloc<int32_t>(nL);
+  iota_u32(reinterpret_cast<uint32_t*>(ix.orig[L]), nL, s);
+  iota_u32(reinterpret_cast<uint32_t*>(ix.inv[L]), nL, s);
+
+  for (int l = L; l >= 1; --l) {
+    const int64_t n_items = ix.level_n[l - 1];
+    const int64_t n_par = ix.level_n[l];
+    // key = position of the parent
+    map_u32(reinterpret_cast<const uint32_t*>(ix.inv[l]),
+            reinterpret_cast<const uint32_t*>(labels[l]), n_items, keys, s);
+    iota_u32(ord, n_items, s);
+    radix_sort_u32(keys, ord, n_items, bits_for(n_par), sw, s);
+    ix.child_off[l] = ix.mem.alloc<uint32_t>(n_par + 1);
+    offsets_from_sorted(keys, n_items, n_par, ix.child_off[l], s);
+    ix.protos[l - 1] = ix.mem.alloc<float>(n_items * ld);
+    ix.orig[l - 1] = ix.mem.alloc<int32_t>(n_items);
+    if (l - 1 >= 1) {
+      gather_rows(protos_cm[l - 1], ld, ord, n_items, ld, ix.protos[l - 1], ld, s);
+      MASK_HIP(hipMemcpyAsync(ix.orig[l - 1], ord, n_items * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, s));
+      ix.inv[l - 1] = ix.mem.alloc<int32_t>(n_items);
+      scatter_iota(ord, n_items, reinterpret_cast<uint32_t*>(ix.inv[l - 1]), s);
+    } else {
+      gather_rows(items0, ld, ord, n_items, ld, ix.protos[0], ld, s);
+      gather_u32(items0_orig, ord, n_items, reinterpret_cast<uint32_t*>(ix.orig[0]), s);
+    }
+  }
+  (void)dim;
+}
+
+struct BuildState {
+  std::vector<int32_t*> labels;   // [L+1], index 0 unused
+  std::vector<float*> protos_cm;  // [L+1], index 0 unused
+};
+
+// Lloyd at one level: `items` (n_items x ld, chunk-contiguous) -> prototypes
+// (chunk-major) and the final labels.  inertia_log: device [iters * C] or null.
+void run_level(const float* items, int64_t n_items, int ld, int dim, int C, int k, int iters,
+               int metric, const float* init, float* protos, int32_t* labels,
+               double* inertia_log, Arena& scratch, hipStream_t s, int64_t* refined) {
+  ChunkPlan plan;
+  make_plan(plan, n_items, C, k, scratch, s);
+  KmeansWork w;
+  kmeans_alloc(w, n_items, (int64_t)C * k, scratch);
+  row_norms(items, ld, n_items, w.item_norms, s);
+  if (init) copy_rows(init, ld, (int64_t)C * k, ld, protos, ld, s);
+  else kmeans_init_first(items, ld, plan, protos, s);
+  row_norms(protos, ld, (int64_t)C * k, w.proto_norms, s);
+  for (int t = 0; t < iters; ++t) {
+    kmeans_assign(items, ld, dim, plan, protos, labels, w, metric, s);
+    kmeans_update(items, ld, dim, plan, labels, protos, w, metric,
+                  inertia_log ? inertia_log + (int64_t)t * C : nullptr, s);
+  }
+  kmeans_assign(items, ld, dim, plan, protos, labels, w, metric, s);
+  if (refined) {
+    uint32_t cnt = 0;
+    MASK_HIP(hipMemcpyAsync(&cnt, w.refine_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    MASK_HIP(hipStreamSynchronize(s));
+    *refined = cnt;
+  }
+}
+
+DescentArgs descent_args(const mask_index& ix) {
+  DescentArgs a{};
+  a.n_levels = ix.n_levels;
+  a.dim = ix.dim;
+  a.ld = ix.ld;
+  a.metric = ix.metric;
+  for (int l = 0; l <= ix.n_levels; ++l) {
+    a.lv[l].protos = ix.protos[l];
+    a.lv[l].orig = ix.orig[l];
+    a.lv[l].inv = ix.inv[l];
+    a.lv[l].child_off = ix.child_off[l];
+    a.lv[l].n = ix.level_n[l];
+  }
+  return a;
+}
+
+mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
+                       int32_t* out_ids, float* out_dist, int32_t* sel, void* hip_stream) {
+  try {
+    MASK_CHECK(ix != nullptr, "index is NULL");
+    check_dense(q, "queries");
+    MASK_CHECK(q->dim == ix->dim, "query dim differs from the index dim");
+    MASK_CHECK(k >= 1 && k <= kMaxBeam, "k must be in [1, 512]");
+    MASK_CHECK(r >= 1 && r <= kMaxBeam, "r must be in [1, 512]");
+    MASK_CHECK(q->n < ((int64_t)1 << 31), "too many queries in one call");
+    if (q->n == 0) return MASK_OK;
+    MASK_CHECK(out_ids && out_dist, "output pointer is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    descent(descent_args(*ix), q->x, ld_of(q), q->n, k, r, out_ids, out_dist, sel,
+            timing_row_counter(), s);
+    return MASK_OK;
+  } catch (const Error& e) {
+    return fail(e);
+  }
+}
+
+}  // namespace
+}  // namespace mask
+
+using namespace mask;
+
+extern "C" {
+
+const char* mask_last_error(void) { return g_last_error.c_str(); }
+
+mask_status mask_timing_enable(int32_t on) {
+  try {
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    for (auto& r : t.recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    for (auto& o : t.open) (void)hipEventDestroy(o.second);
+    t.recs.clear();
+    t.open.clear();
+    if (on && !t.rows) MASK_HIP(hipMalloc(&t.rows, 4 * sizeof(unsigned long long)));
+    if (t.rows) MASK_HIP(hipMemset(t.rows, 0, 4 * sizeof(unsigned long long)));
+    t.on = on != 0;
+    return MASK_OK;
+  } catch (const Error& e) {
+    return fail(e);
+  }
+}
+
+mask_status mask_timing_report(char* buf, int64_t cap, int64_t* needed) {
+  try {
+    TimingState& t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    std::map<std::string, std::pair<int64_t, double>> agg;
+    for (auto& r : t.recs) {
+      MASK_HIP(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      MASK_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      auto& a = agg[r.name];
+      a.first += 1;
+      a.second += ms;
+    }
+    unsigned long long cnt[4] = {0, 0, 0, 0};
+    if (t.rows) MASK_HIP(hipMemcpy(cnt, t.rows, sizeof(cnt), hipMemcpyDeviceToHost));
+    std::ostringstream os;
+    for (auto& kv : agg) os << kv.first << " " << kv.second.first << " " << kv.second.second << "\n";
+    os << "descent_rows " << cnt[0] << " 0\n";
+    os << "refine_small_points " << cnt[1] << " 0\n";
+    os << "refine_full_points " << cnt[2] << " 0\n";
+    const std::string txt = os.str();
+    if (needed) *needed = (int64_t)txt.size() + 1;
+    if (buf && cap > 0) {
+      const size_t n = std::min<size_t>(txt.size(), (size_t)cap - 1);
+      std::memcpy(buf, txt.data(), n);
+      buf[n] = 0;
+    }
+    return MASK_OK;
+  } catch (const Error& e) {
+    return fail(e);
+  }
+}
+
+mask_status mask_plan_levels(int64_t n, int32_t length_group, int32_t n_centroids,
+                             mask_level* out, int32_t cap, int32_t* n_levels) {
+  try {
+    MASK_CHECK(n >= 0 && length_group >= 1 && n_centroids >= 1, "bad arguments");
+    MASK_CHECK(n_levels != nullptr, "n_levels is NULL");
+    MASK_CHECK(n_centroids < length_group, "the schedule does not shrink");
+    int count = 0;
+    int64_t ngroups = n / length_group;
+    while (ngroups >= 1) {
+      MASK_CHECK(count < cap, "more levels than cap");
+      MASK_CHECK(ngroups < ((int64_t)1 << 31), "too many groups");
+      if (out) out[count] = mask_level{(int32_t)ngroups, n_centroids};
+      ++count;
+      ngroups = (ngroups * n_centroids) / length_group;
+    }
+    *n_levels = count;
+    return MASK_OK;
+  } catch (const Error& e) {
+    return fail(e);
+  }
+}
+
+mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
+                       const mask_allocator* a, void* hip_stream, mask_index** out) {
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    MASK_CHECK(out != nullptr, "out is NULL");
+    *out = nullptr;
+    check_dense(data, "data");
+    MASK_CHECK(p != nullptr, "params is NULL");
+    MASK_CHECK(p->metric == MASK_L2 || p->metric == MASK_L1, "unknown metric");
+    MASK_CHECK(p->precision >= MASK_FP32 && p->precision <= MASK_FP8_E4M3, "unknown precision");
+    MASK_CHECK(p->lloyd_iters >= 0, "lloyd_iters < 0");
+    MASK_CHECK(data->n >= 1 && data->n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
+    std::vector<int64_t> sizes;
+    check_levels(data->n, p->n_levels, p->levels, sizes);
+    if (data->dim > kMaxDenseDim) throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};
+    if (p->metric != MASK_L2) throw Error{MASK_ERR_UNSUPPORTED, "L1 build"};
+    if (p->precision != MASK_FP32) throw Error{MASK_ERR_UNSUPPORTED, "precision form"};
+
+    auto ix = std::make_unique<mask_index>(a, s);
+    const int L = p->n_levels;
+    ix->n = data->n;
+    ix->dim = data->dim;
+    ix->ld = round_up4(data->dim);
+    ix->metric = p->metric;
+    ix->precision = p->precision;
+    ix->n_levels = L;
+    ix->levels.assign(p->levels, p->levels + L);
+    ix->level_n = sizes;
+    const int ld = ix->ld;
+    const int64_t n = data->n;
+
+    Arena scratch(a, s);
+    // level-0 order
+    uint32_t* perm = scratch.alloc<uint32_t>(n);
+    if (p->perm) {
+      MASK_HIP(hipMemcpyAsync(perm, p->perm, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    } else {
+      uint64_t* keys = scratch.alloc<uint64_t>(n);
+      SortWork sw;
+      sort_work_alloc(sw, n, true, scratch);
+      splitmix_keys(p->seed, n, keys, perm, s);
+      radix_sort_u64(keys, perm, n, 64, sw, s);
+    }
+    float* items0 = scratch.alloc<float>(n * ld);
+    gather_rows(data->x, ld_of(data), perm, n, data->dim, items0, ld, s);
+
+    BuildState st;
+    st.labels.assign(L + 1, nullptr);
+    st.protos_cm.assign(L + 1, nullptr);
+    for (int l = 1; l <= L; ++l) {
+      const int C = p->levels[l - 1].n_chunks, k = p->levels[l - 1].k;
+      const int64_t n_items = sizes[l - 1];
+      const float* items = (l == 1) ? items0 : st.protos_cm[l - 1];
+      st.protos_cm[l] = scratch.alloc<float>(sizes[l] * ld);
+      st.labels[l] = scratch.alloc<int32_t>(n_items);
+      Arena level_scratch(a, s);
+      run_level(items, n_items, ld, data->dim, C, k, p->lloyd_iters, p->metric, nullptr,
+                st.protos_cm[l], st.labels[l], nullptr, level_scratch, s,
+                l == 1 ? &ix->refined_last : nullptr);
+      MASK_HIP(hipStreamSynchronize(s));
+    }
+    finalize_layout(*ix, st.labels, st.protos_cm, items0, perm, scratch, s);
+    MASK_HIP(hipStreamSynchronize(s));
+    *out = ix.release();
+    return MASK_OK;
+  } catch (const Error& e) {
+    if (e.status != MASK_ERR_INVALID && e.status != MASK_ERR_UNSUPPORTED)
+      (void)hipStreamSynchronize(s);
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamSynchronize(s);
+    return fail(Error{MASK_ERR_NOMEM, "host allocation failed"});
+  }
+}
+
+mask_status mask_query(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
+                       int32_t* out_ids, float* out_dist, void* hip_stream) {
+  return query_impl(ix, q, k, r, out_ids, out_dist, nullptr, hip_stream);
+}
+
+mask_status mask_query_debug(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
+                             int32_t* out_ids, float* out_dist, int32_t* sel,
+                             void* hip_stream) {
+  if (!sel) {
+    set_error("sel is NULL");
+    return MASK_ERR_INVALID;
+  }
+  return query_impl(ix, q, k, r, out_ids, out_dist, sel, hip_stream);
+}
+
+mask_status mask_free(mask_index* ix) {
+  if (!ix) return MASK_OK;
+  (void)hipStreamSynchronize(ix->mem.stream());
+  delete ix;
+  return MASK_OK;
+}
+
+mask_status mask_index_info(const mask_index* ix, mask_info* out) {
+  if (!ix || !out) {
+    set_error("NULL argument");
+    return MASK_ERR_INVALID;
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->n = ix->n;
+  out->dim = ix->dim;
+  out->n_levels = ix->n_levels;
+  out->metric = ix->metric;
+  out->precision = ix->precision;
+  for (int l = 1; l <= ix->n_levels; ++l) out->level_size[l - 1] = ix->level_n[l];
+  out->device_bytes = (int64_t)ix->mem.bytes();
+  out->refined_last_level = ix->refined_last;
+  return MASK_OK;
+}
+
+mask_status mask_export_level(const mask_index* ix, int32_t level, float* protos_host,
+                              int32_t* parent_host) {
+  try {
+    MASK_CHECK(ix != nullptr, "index is NULL");
+    MASK_CHECK(level >= 1 && level <= ix->n_levels, "level out of range");
+    MASK_CHECK(protos_host != nullptr, "protos_host is NULL");
+    const int64_t nl = ix->level_n[level], nb = ix->level_n[level - 1];
+    const int ld = ix->ld, dim = ix->dim;
+    std::vector<float> P(nl * ld);
+    std::vector<int32_t> orig(nl);
+    MASK_HIP(hipMemcpy(P.data(), ix->protos[level], nl * ld * sizeof(float), hipMemcpyDeviceToHost));
+    MASK_HIP(hipMemcpy(orig.data(), ix->orig[level], nl * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t pos = 0; pos < nl; ++pos)
+      std::memcpy(protos_host + (int64_t)orig[pos] * dim, P.data() + pos * ld, dim * sizeof(float));
+    if (parent_host) {
+      std::vector<uint32_t> off(nl + 1);
+      std::vector<int32_t> orig_below(nb);
+      MASK_HIP(hipMemcpy(off.data(), ix->child_off[level], (nl + 1) * sizeof(uint32_t),
+                         hipMemcpyDeviceToHost));
+      MASK_HIP(hipMemcpy(orig_below.data(), ix->orig[level - 1], nb * sizeof(int32_t),
+                         hipMemcpyDeviceToHost));
+      for (int64_t p = 0; p < nl; ++p)
+        for (uint32_t q = off[p]; q < off[p + 1]; ++q) parent_host[orig_below[q]] = orig[p];
+    }
+    return MASK_OK;
+  } catch (const Error& e) {
+    return fail(e);
+  }
+}
+
+mask_status mask_import(const mask_matrix* data, int32_t n_levels, const mask_level* levels,
+                        const float* const* protos_host, const int32_t* const* parents_host,
+                        const mask_build_params* p, const mask_allocator* a, void* hip_stream,
+                        mask_index** out) {
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    MASK_CHECK(out != nullptr, "out is NULL");
+    *out = nullptr;
+    check_dense(data, "data");
+    MASK_CHECK(data->n >= 1 && data->n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
+    MASK_CHECK(protos_host && parents_host, "host arrays are NULL");
+    std::vector<int64_t> sizes;
+    check_levels(data->n, n_levels, levels, sizes);
+    const int metric = p ? p->metric : MASK_L2;
+    MASK_CHECK(metric == MASK_L2 || metric == MASK_L1, "unknown metric");
+    if (data->dim > kMaxQueryDim) throw Error{MASK_ERR_UNSUPPORTED, "dim above 4096"};
+    for (int l = 0; l < n_levels; ++l) {
+      MASK_CHECK(protos_host[l] && parents_host[l], "a level's host array is NULL");
+      for (int64_t i = 0; i < sizes[l]; ++i)
+        MASK_CHECK(parents_host[l][i] >= 0 && parents_host[l][i] < sizes[l + 1],
+                   "parent id out of range");
+    }
+    auto ix = std::make_unique<mask_index>(a, s);
+    const int L = n_levels;
+    ix->n = data->n;
+    ix->dim = data->dim;
+    ix->ld = round_up4(data->dim);
+    ix->metric = metric;
+    ix->precision = p ? p->precision : MASK_FP32;
+    ix->n_levels = L;
+    ix->levels.assign(levels, levels + L);
+    ix->level_n = sizes;
+    const int ld = ix->ld, dim = ix->dim;
+    Arena scratch(a, s);
+    float* items0 = scratch.alloc<float>(data->n * ld);
+    copy_rows(data->x, ld_of(data), data->n, dim, items0, ld, s);
+    uint32_t* ident = scratch.alloc<uint32_t>(data->n);
+    iota_u32(ident, data->n, s);
+    BuildState st;
+    st.labels.assign(L + 1, nullptr);
+    st.protos_cm.assign(L + 1, nullptr);
+    std::vector<float> padded;
+    for (int l = 1; l <= L; ++l) {
+      const int64_t nl = sizes[l];
+      padded.assign(nl * ld, 0.f);
+      for (int64_t i = 0; i < nl; ++i)
+        std::memcpy(padded.data() + i * ld, protos_host[l - 1] + i * dim, dim * sizeof(float));
+      st.protos_cm[l] = scratch.alloc<float>(nl * ld);
+      MASK_HIP(hipMemcpy(st.protos_cm[l], padded.data(), nl * ld * sizeof(float),
+                         hipMemcpyHostToDevice));
+      st.labels[l] = scratch.alloc<int32_t>(sizes[l - 1]);
+      MASK_HIP(hipMemcpy(st.labels[l], parents_host[l - 1], sizes[l - 1] * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
+    }
+    finalize_layout(*ix, st.labels, st.protos_cm, items0, ident, scratch, s);
+    MASK_HIP(hipStreamSynchronize(s));
+    *out = ix.release();
+    return MASK_OK;
+  } catch (const Error& e) {
+    if (e.status != MASK_ERR_INVALID && e.status != MASK_ERR_UNSUPPORTED)
+      (void)hipStreamSynchronize(s);
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamSynchronize(s);
+    return fail(Error{MASK_ERR_NOMEM, "host allocation failed"});
+  }
+}
+
+mask_status mask_kmeans(const mask_matrix* items, int32_t n_chunks, int32_t k, int32_t iters,
+                        int32_t metric, const float* init, float* centroids, int32_t* labels,
+                        double* inertia, const mask_allocator* a, void* hip_stream) {
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    check_dense(items, "items");
+    MASK_CHECK(items->n >= 1 && items->n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
+    MASK_CHECK(n_chunks >= 1 && k >= 1 && iters >= 0, "bad n_chunks, k or iters");
+    MASK_CHECK(items->n / n_chunks >= k, "a chunk holds fewer items than k");
+    MASK_CHECK(centroids && labels, "output pointer is NULL");
+    MASK_CHECK(metric == MASK_L2 || metric == MASK_L1, "unknown metric");
+    if (items->dim > kMaxDenseDim) throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};
+    if (metric != MASK_L2) throw Error{MASK_ERR_UNSUPPORTED, "L1 k-means"};
+    const int dim = items->dim, ld = round_up4(dim);
+    const int64_t n = items->n, np = (int64_t)n_chunks * k;
+    Arena scratch(a, s);
+    float* x = scratch.alloc<float>(n * ld);
+    copy_rows(items->x, ld_of(items), n, dim, x, ld, s);
+    float* P = scratch.alloc<float>(np * ld);
+    float* init_p = nullptr;
+    if (init) {
+      init_p = scratch.alloc<float>(np * ld);
+      copy_rows(init, dim, np, dim, init_p, ld, s);
+    }
+    run_level(x, n, ld, dim, n_chunks, k, iters, metric, init_p, P, labels, inertia, scratch, s,
+              nullptr);
+    copy_rows(P, ld, np, dim, centroids, dim, s);
+    MASK_HIP(hipStreamSynchronize(s));
+    return MASK_OK;
+  } catch (const Error& e) {
+    if (e.status != MASK_ERR_INVALID && e.status != MASK_ERR_UNSUPPORTED)
+      (void)hipStreamSynchronize(s);
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamSynchronize(s);
+    return fail(Error{MASK_ERR_NOMEM, "host allocation failed"});
+  }
+}
+
+}  // extern "C"

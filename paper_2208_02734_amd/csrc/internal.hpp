@@ -1,0 +1,290 @@
+// Internal declarations shared by the host runtime and the kernel files.
+// Everything here targets gfx950 (CDNA4): 64-lane wavefronts, MFMA, 160 KB
+// LDS per compute unit, 8 XCDs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mask.h"
+
+namespace mask {
+
+constexpr int kWave = 64;
+constexpr int kMaxLevels = 16;
+constexpr int kMaxDenseDim = 256;   // MFMA assignment keeps point rows in registers
+constexpr int kMaxQueryDim = 4096;  // the descent stages one query row in LDS
+constexpr int kMaxBeam = 512;       // r and k limit of one descent workgroup
+
+// ------------------------------------------------------------------ errors
+
+void set_error(const std::string& msg);
+
+struct Error {
+  mask_status status;
+  std::string msg;
+};
+
+#define MASK_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw ::mask::Error{MASK_ERR_DEVICE, std::string(#call) + ": " +              \
+                                               hipGetErrorString(e_)};              \
+  } while (0)
+
+#define MASK_CHECK(cond, msg)                                                       \
+  do {                                                                              \
+    if (!(cond)) throw ::mask::Error{MASK_ERR_INVALID, (msg)};                      \
+  } while (0)
+
+inline void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    throw Error{MASK_ERR_DEVICE, std::string("launch ") + what + ": " + hipGetErrorString(e)};
+}
+
+// ------------------------------------------------------------------ timing
+// When enabled (mask_timing_enable), instrumented launches record a pair of
+// HIP events on their stream; mask_timing_report sums the elapsed times per
+// kernel name.  Disabled, a ScopedTiming costs one branch.
+bool timing_enabled();
+void timing_record(const char* name, hipStream_t s, bool start);
+// Device counter the descent kernel adds its evaluated candidate rows to
+// while timing is enabled (null otherwise).
+unsigned long long* timing_row_counter();
+// Two device counters (points refined on 2-3 candidates, on the whole group)
+// while timing is enabled, null otherwise.
+unsigned long long* timing_refine_counter();
+
+struct ScopedTiming {
+  const char* name;
+  hipStream_t s;
+  bool on;
+  ScopedTiming(const char* n, hipStream_t st) : name(n), s(st), on(timing_enabled()) {
+    if (on) timing_record(name, s, true);
+  }
+  ~ScopedTiming() {
+    if (on) timing_record(name, s, false);
+  }
+};
+
+// -------------------------------------------------------------- allocation
+
+// Device memory owned by one object (an index or one build's scratch).  Every
+// allocation goes through the caller's mask_allocator when one is given.
+class Arena {
+ public:
+  Arena(const mask_allocator* a, hipStream_t s) : s_(s) {
+    if (a) { a_ = *a; has_ = true; }
+  }
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  ~Arena() { release(); }
+
+  void* alloc_bytes(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~size_t(255);
+    void* p = nullptr;
+    if (has_) {
+      p = a_.alloc(a_.ctx, bytes, (void*)s_);
+      if (!p) throw Error{MASK_ERR_NOMEM, "allocator returned NULL"};
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        throw Error{MASK_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+      }
+    }
+    blocks_.push_back({p, bytes});
+    bytes_ += bytes;
+    return p;
+  }
+  template <class T>
+  T* alloc(size_t count) {
+    return static_cast<T*>(alloc_bytes(count * sizeof(T)));
+  }
+  // Frees one allocation early (scratch that is no longer needed).
+  void free_one(void* p) {
+    for (size_t i = 0; i < blocks_.size(); ++i) {
+      if (blocks_[i].p == p) {
+        do_free(blocks_[i]);
+        bytes_ -= blocks_[i].bytes;
+        blocks_.erase(blocks_.begin() + i);
+        return;
+      }
+    }
+  }
+  void release() {
+    for (auto& b : blocks_) do_free(b);
+    blocks_.clear();
+    bytes_ = 0;
+  }
+  size_t bytes() const { return bytes_; }
+  hipStream_t stream() const { return s_; }
+  void set_stream(hipStream_t s) { s_ = s; }
+
+ private:
+  struct Block { void* p; size_t bytes; };
+  void do_free(const Block& b) {
+    if (has_) a_.free(a_.ctx, b.p, b.bytes, (void*)s_);
+    else (void)hipFree(b.p);
+  }
+  mask_allocator a_{};
+  bool has_ = false;
+  hipStream_t s_;
+  std::vector<Block> blocks_;
+  size_t bytes_ = 0;
+};
+
+// ------------------------------------------------------------- primitives
+// (prims.hip)
+
+// Workspace of the radix sort: ping-pong buffers, the per-wave digit
+// histogram table and the scan's tile sums, sized for up to cap_n keys.
+struct SortWork {
+  void* keys2 = nullptr;
+  uint32_t* vals2 = nullptr;
+  uint32_t* hist = nullptr;
+  uint32_t* sums = nullptr;
+  int64_t cap_n = 0;
+  bool wide = false;
+};
+void sort_work_alloc(SortWork& w, int64_t n, bool wide, Arena& a);
+
+// Stable LSD radix sort of (key, value) pairs on bits [0, key_bits), in place.
+void radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int key_bits, SortWork& w,
+                    hipStream_t s);
+void radix_sort_u64(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, SortWork& w,
+                    hipStream_t s);
+
+// Number of uint32 tile sums exclusive_scan_u32 needs for n elements.
+int64_t scan_sums_needed(int64_t n);
+// Exclusive scan of n uint32 values in place; the total goes to out_total
+// (device) when it is not null.  sums: scratch of scan_sums_needed(n).
+void exclusive_scan_u32(uint32_t* data, int64_t n, uint32_t* out_total, uint32_t* sums,
+                        hipStream_t s);
+
+// keys[i] = SplitMix64 output number i+1 from state seed; vals[i] = i.
+void splitmix_keys(uint64_t seed, int64_t n, uint64_t* keys, uint32_t* vals, hipStream_t s);
+
+// dst[i*ld_dst + c] = src[idx[i]*ld_src + c] for c < dim, zero for dim <= c < ld_dst.
+void gather_rows(const float* src, int ld_src, const uint32_t* idx, int64_t n, int dim,
+                 float* dst, int ld_dst, hipStream_t s);
+// Same with int32 indices.
+void gather_rows_i32(const float* src, int ld_src, const int32_t* idx, int64_t n, int dim,
+                     float* dst, int ld_dst, hipStream_t s);
+// dst[i*ld_dst + c] = src[i*ld_src + c] (c < dim), zero padding to ld_dst.
+void copy_rows(const float* src, int ld_src, int64_t n, int dim, float* dst, int ld_dst,
+               hipStream_t s);
+
+// out[i] = sum_c x[i*ld + c]^2 in float32 (fixed order).
+void row_norms(const float* x, int ld, int64_t n, float* out, hipStream_t s);
+
+// Offsets of the runs of a sorted key array: off[p] = first i with keys[i] >= p,
+// for p in [0, n_bins]; off[n_bins] = n.
+void offsets_from_sorted(const uint32_t* keys, int64_t n, int64_t n_bins, uint32_t* off,
+                         hipStream_t s);
+
+// out[i] = map[in[i]]
+void map_u32(const uint32_t* map, const uint32_t* in, int64_t n, uint32_t* out, hipStream_t s);
+// out[idx[i]] = i
+void scatter_iota(const uint32_t* idx, int64_t n, uint32_t* out, hipStream_t s);
+// out[i] = src[idx[i]]
+void gather_u32(const uint32_t* src, const uint32_t* idx, int64_t n, uint32_t* out,
+                hipStream_t s);
+void iota_u32(uint32_t* out, int64_t n, hipStream_t s);
+void fill_u32(uint32_t* out, int64_t n, uint32_t v, hipStream_t s);
+
+// ------------------------------------------------------------ k-means
+// (kmeans.hip)
+
+struct ChunkPlan {
+  int n_chunks = 0;
+  int k = 0;
+  int64_t n_items = 0;
+  int64_t max_chunk = 0;
+  std::vector<int64_t> off;  // host copy, n_chunks + 1
+  int64_t* d_off = nullptr;  // device copy
+};
+
+struct KmeansWork {
+  // device scratch sized for one level
+  uint32_t* sort_keys = nullptr;
+  uint32_t* sort_vals = nullptr;
+  SortWork sort;
+  uint32_t* member_off = nullptr;  // n_protos + 1
+  double* proto_inertia = nullptr; // n_protos
+  uint32_t* refine_count = nullptr; // [0] points with 2-3 candidates, [1] whole group
+  uint32_t* small_list = nullptr;   // n_items
+  int32_t* small_cand = nullptr;    // 3 * n_items candidate ids, ascending, -1 padded
+  uint32_t* full_list = nullptr;    // n_items
+  float* item_norms = nullptr;
+  float* proto_norms = nullptr;
+};
+
+void kmeans_alloc(KmeansWork& w, int64_t n_items, int64_t n_protos, Arena& scratch);
+
+// One assignment of every item to its nearest prototype of its chunk
+// (plain FP32 form: MFMA screening + direct-form certification).
+void kmeans_assign(const float* items, int ld, int dim, const ChunkPlan& plan,
+                   const float* protos, int32_t* labels, KmeansWork& w, int metric,
+                   hipStream_t s);
+// Update: new prototypes (mean of members; unchanged when empty), their
+// norms, and the inertia of the assignment under the old prototypes
+// (inertia_out[c] for chunk c, float64, may be null).
+void kmeans_update(const float* items, int ld, int dim, const ChunkPlan& plan,
+                   const int32_t* labels, float* protos, KmeansWork& w, int metric,
+                   double* inertia_out, hipStream_t s);
+// Prototype c*k+j := item off[c]+j.
+void kmeans_init_first(const float* items, int ld, const ChunkPlan& plan, float* protos,
+                       hipStream_t s);
+
+// ------------------------------------------------------------ descent
+// (query.hip)
+
+struct LevelView {
+  const float* protos;       // n x ld, position order
+  const int32_t* orig;       // position -> chunk-major id (data row id at level 0)
+  const int32_t* inv;        // chunk-major id -> position (levels >= 1)
+  const uint32_t* child_off; // n + 1 offsets into the level below (levels >= 1)
+  int64_t n;
+};
+
+struct DescentArgs {
+  LevelView lv[kMaxLevels + 1];  // lv[0] = data (leaf order), lv[l] = level l
+  int n_levels;
+  int dim;
+  int ld;
+  int metric;
+};
+
+void descent(const DescentArgs& a, const float* q, int ldq, int64_t nq, int k, int r,
+             int32_t* out_ids, float* out_dist, int32_t* sel, unsigned long long* rows,
+             hipStream_t s);
+
+}  // namespace mask
+
+// Host-visible structure behind the opaque mask_index handle.
+struct mask_index {
+  mask::Arena mem;
+  int64_t n = 0;
+  int dim = 0;
+  int ld = 0;
+  int metric = 0;
+  int precision = 0;
+  int n_levels = 0;
+  std::vector<mask_level> levels;
+  std::vector<int64_t> level_n;  // level_n[0] = n, level_n[l] = prototypes at level l
+  // device arrays; index 0 = data in leaf order
+  float* protos[mask::kMaxLevels + 1] = {};
+  int32_t* orig[mask::kMaxLevels + 1] = {};
+  int32_t* inv[mask::kMaxLevels + 1] = {};
+  uint32_t* child_off[mask::kMaxLevels + 1] = {};
+  int64_t refined_last = 0;
+  explicit mask_index(const mask_allocator* a, hipStream_t s) : mem(a, s) {}
+};

@@ -1,0 +1,77 @@
+"""The C-ABI library loads on a machine without a GPU, exports every entry
+point include/mask.h declares, and its host-only logic (level schedule,
+argument checks) behaves as documented.  No compute call is made."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2208_02734_amd as pk
+from oracle import mask_oracle as mo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "mask.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:mask_status|const char\*)\s+(mask_\w+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(pk.LIB_PATH):
+        pytest.skip("library not built")
+    return pk.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ["mask_build", "mask_query", "mask_free", "mask_plan_levels",
+                     "mask_export_level", "mask_import", "mask_query_debug", "mask_last_error"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert sorted(_declared()) == sorted(pk.EXPORTED)
+
+
+def test_plan_levels_matches_oracle_and_paper(L):
+    for n, lg, nc in [(80, 10, 5), (1600, 16, 8), (80000, 10, 5), (80000, 110, 55), (7, 10, 5)]:
+        assert pk.mask_plan_levels(n, lg, nc) == mo.plan_levels(n, lg, nc)
+
+
+def test_plan_levels_rejects_non_shrinking(L):
+    with pytest.raises(pk.MaskError) as e:
+        pk.mask_plan_levels(100, 4, 4)
+    assert e.value.status == 1
+
+
+def test_invalid_arguments_are_reported_without_device_work(L):
+    h = ctypes.c_void_p()
+    st = L.mask_build(None, None, None, None, ctypes.byref(h))
+    assert st == 1 and h.value is None
+    assert b"NULL" in L.mask_last_error()
+    m = pk.mask_matrix()
+    m.layout, m.n, m.dim, m.ld, m.x = 0, 100, 8, 0, 1234
+    # level with k larger than its chunk
+    p, lv = pk._params([(10, 20)], 5, 0, "l2", "fp32", 4, None)
+    st = L.mask_build(ctypes.byref(m), ctypes.byref(p), None, None, ctypes.byref(h))
+    assert st == 1 and b"fewer items" in L.mask_last_error()
+    # query on a NULL index
+    st = L.mask_query(None, ctypes.byref(m), 10, 4, None, None, None)
+    assert st == 1
+    # k out of range is rejected before the index is touched
+    assert L.mask_free(None) == 0
+
+
+def test_unsupported_requests(L):
+    h = ctypes.c_void_p()
+    m = pk.mask_matrix()
+    m.layout, m.n, m.dim, m.ld, m.x = 0, 1000, 300, 0, 1234
+    p, lv = pk._params([(2, 10)], 5, 0, "l2", "fp32", 4, None)
+    st = L.mask_build(ctypes.byref(m), ctypes.byref(p), None, None, ctypes.byref(h))
+    assert st == 4

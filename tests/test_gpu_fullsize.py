@@ -1,0 +1,71 @@
+"""Parity at the full benchmark size (1,000,000 x 128 Gaussian mixture,
+levels 100 x 1,000 -> 5,000 -> 100, 30 Lloyd iterations, 10,000 queries),
+in the launch configuration the benchmark times, on outputs the oracle can
+compute one by one: sampled queries re-run by the oracle on the exported
+index, and sampled level-1 assignments re-checked against the exported
+prototypes of their group."""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import compare as oc
+from oracle import mask_oracle as mo
+from tests.gpu_helpers import check_query_against_oracle, dev, host, oracle_index_from_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def built():
+    import torch
+    import paper_2208_02734_amd as pk
+    pk.lib()
+    cfg = datagen.config_scale()
+    X, Q = cfg.X, cfg.Q
+    print(f"full-size: n={X.shape[0]} d={X.shape[1]} levels={cfg.levels}", flush=True)
+    gix = pk.mask_build(dev(X), cfg.levels, iters=cfg.iters, seed=1)
+    torch.cuda.synchronize()
+    return pk, cfg, gix
+
+
+def test_fullsize_sampled_queries(built):
+    pk, cfg, gix = built
+    X, Q = cfg.X, cfg.Q
+    oix = oracle_index_from_gpu(X, gix)
+    g = np.random.default_rng(5)
+    rows = np.sort(g.choice(Q.shape[0], 24, replace=False))
+    for r in (16, 64):
+        ids, dist, sel = pk.mask_query(gix, dev(Q), cfg.k, r, debug=True)
+        ids, dist, sel = host(ids), host(dist), host(sel)
+        _, _, fails = check_query_against_oracle(oix, X, Q, cfg.k, r, ids, dist, sel, rows=rows)
+        assert not fails, (r, fails[:3])
+        # every row is sorted and padded consistently
+        assert np.all(np.diff(dist, axis=1) >= 0)
+
+
+def test_fullsize_sampled_assignments(built):
+    pk, cfg, gix = built
+    X = cfg.X
+    k = cfg.levels[0][1]
+    P, par = gix.export_level(1)
+    pi = mo.permutation(1, X.shape[0])
+    off = mo.chunk_offsets(X.shape[0], cfg.levels[0][0])
+    g = np.random.default_rng(6)
+    for c in g.choice(cfg.levels[0][0], 4, replace=False):
+        members = pi[off[c]:off[c + 1]]
+        sample = g.choice(members, 300, replace=False)
+        assert np.all(par[sample] // k == c)
+        D = mo.pairwise(X[sample], P[c * k:(c + 1) * k])
+        got = D[np.arange(sample.size), par[sample] - c * k]
+        assert np.all(got <= D.min(axis=1) * (1 + 1e-5))
+
+
+def test_fullsize_structure(built):
+    pk, cfg, gix = built
+    info = gix.info()
+    assert info["level_size"] == [c * k for c, k in cfg.levels]
+    # every item of every level has a parent in range
+    for lev in range(1, info["n_levels"] + 1):
+        P, par = gix.export_level(lev)
+        assert par.min() >= 0 and par.max() < P.shape[0]
+        assert np.all(np.isfinite(P))
