@@ -17,7 +17,7 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libmask.so")
+LIB_PATH = os.environ.get("MASK_LIBRARY") or os.path.join(_HERE, "_lib", "libmask.so")
 
 MASK_OK = 0
 _STATUS = {0: "MASK_OK", 1: "MASK_ERR_INVALID", 2: "MASK_ERR_NOMEM", 3: "MASK_ERR_DEVICE",

@@ -188,11 +188,11 @@ void run_level(const float* items, int64_t n_items, int ld, int dim, int C, int 
   ChunkPlan plan;
   make_plan(plan, n_items, C, k, scratch, s);
   KmeansWork w;
-  kmeans_alloc(w, n_items, (int64_t)C * k, scratch);
+  kmeans_alloc(w, n_items, C, k, scratch);
   row_norms(items, ld, n_items, w.item_norms, s);
   if (init) copy_rows(init, ld, (int64_t)C * k, ld, protos, ld, s);
   else kmeans_init_first(items, ld, plan, protos, s);
-  row_norms(protos, ld, (int64_t)C * k, w.proto_norms, s);
+  kmeans_proto_norms(protos, ld, (int64_t)C * k, w, s);
   for (int t = 0; t < iters; ++t) {
     kmeans_assign(items, ld, dim, plan, protos, labels, w, metric, s);
     kmeans_update(items, ld, dim, plan, labels, protos, w, metric,

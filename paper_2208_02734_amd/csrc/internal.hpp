@@ -222,12 +222,20 @@ struct KmeansWork {
   uint32_t* refine_count = nullptr; // [0] points with 2-3 candidates, [1] whole group
   uint32_t* small_list = nullptr;   // n_items
   int32_t* small_cand = nullptr;    // 3 * n_items candidate ids, ascending, -1 padded
-  uint32_t* full_list = nullptr;    // n_items
+  uint32_t* full_cnt = nullptr;     // n_chunks: points of each group re-scored on the group
+  uint32_t* full_list = nullptr;    // n_items, group c's entries start at the group offset
+  uint2* tiles = nullptr;           // (group, 64-point tile) pairs
+  uint32_t* tile_total = nullptr;
+  double* partial_d = nullptr;      // n_items * full_splits
+  int32_t* partial_j = nullptr;
+  int full_splits = 1;
+  int full_grid = 1;
   float* item_norms = nullptr;
   float* proto_norms = nullptr;
+  double* proto_norms64 = nullptr;
 };
 
-void kmeans_alloc(KmeansWork& w, int64_t n_items, int64_t n_protos, Arena& scratch);
+void kmeans_alloc(KmeansWork& w, int64_t n_items, int n_chunks, int k, Arena& scratch);
 
 // One assignment of every item to its nearest prototype of its chunk
 // (plain FP32 form: MFMA screening + direct-form certification).
@@ -240,6 +248,9 @@ void kmeans_assign(const float* items, int ld, int dim, const ChunkPlan& plan,
 void kmeans_update(const float* items, int ld, int dim, const ChunkPlan& plan,
                    const int32_t* labels, float* protos, KmeansWork& w, int metric,
                    double* inertia_out, hipStream_t s);
+// FP32 and FP64 squared norms of the prototypes (after init or import).
+void kmeans_proto_norms(const float* protos, int ld, int64_t n_protos, KmeansWork& w,
+                        hipStream_t s);
 // Prototype c*k+j := item off[c]+j.
 void kmeans_init_first(const float* items, int ld, const ChunkPlan& plan, float* protos,
                        hipStream_t s);

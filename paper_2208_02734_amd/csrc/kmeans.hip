@@ -18,6 +18,7 @@
 // under the old prototypes is accumulated in FP64 on the same pass.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace mask {
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_l2_mfma(
     const int64_t* __restrict__ chunk_off, int k, int tiles_per_chunk,
     int32_t* __restrict__ labels, uint32_t* __restrict__ refine_count,
     uint32_t* __restrict__ small_list, int32_t* __restrict__ small_cand,
-    uint32_t* __restrict__ full_list, float err_coef) {
+    uint32_t* __restrict__ full_cnt, uint32_t* __restrict__ full_list, float err_coef) {
   constexpr int KS = DP / 2;
   constexpr int LDW = LdsWidth<DP>::value;
   constexpr int BM = 4 * 32 * PB;
@@ -240,8 +241,9 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_l2_mfma(
             small_cand[3 * slot + 1] = c1i;
             small_cand[3 * slot + 2] = c2;
           } else {
-            const uint32_t slot = atomicAdd(&refine_count[1], 1u);
-            full_list[slot] = (uint32_t)p;
+            // per-group list: slots c0 .. c0 + group size - 1 belong to this group
+            const uint32_t slot = atomicAdd(&full_cnt[chunk], 1u);
+            full_list[c0 + slot] = (uint32_t)p;
           }
         }
       }
@@ -249,22 +251,25 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_l2_mfma(
   }
 }
 
-// Direct-form distance in a fixed order: four partial sums over the float4
-// lanes of the row, combined as (p0+p1)+(p2+p3).  ld is a multiple of 4 and
-// the padding is zero in both rows.
+// Direct-form distance in a fixed order, accumulated in FP64: the difference
+// of two FP32 values is exact in FP64, so the result carries only the FP64
+// rounding of the squares and sums.  Four partial sums over the float4 lanes
+// of the row, combined as (p0+p1)+(p2+p3).  ld is a multiple of 4 and the
+// padding is zero in both rows.
 template <int METRIC>
-__device__ inline float direct_dist(const float* __restrict__ x, const float* __restrict__ c,
-                                    int ld) {
+__device__ inline double direct_dist64(const float* __restrict__ x, const float* __restrict__ c,
+                                       int ld) {
   const float4* x4 = reinterpret_cast<const float4*>(x);
   const float4* c4 = reinterpret_cast<const float4*>(c);
-  float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
   for (int i = 0; i < ld / 4; ++i) {
     const float4 a = x4[i], b = c4[i];
-    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z, dw = a.w - b.w;
+    const double dx = (double)a.x - (double)b.x, dy = (double)a.y - (double)b.y,
+                 dz = (double)a.z - (double)b.z, dw = (double)a.w - (double)b.w;
     if (METRIC == 0) {
-      p0 = fmaf(dx, dx, p0); p1 = fmaf(dy, dy, p1); p2 = fmaf(dz, dz, p2); p3 = fmaf(dw, dw, p3);
+      p0 = fma(dx, dx, p0); p1 = fma(dy, dy, p1); p2 = fma(dz, dz, p2); p3 = fma(dw, dw, p3);
     } else {
-      p0 += fabsf(dx); p1 += fabsf(dy); p2 += fabsf(dz); p3 += fabsf(dw);
+      p0 += fabs(dx); p1 += fabs(dy); p2 += fabs(dz); p3 += fabs(dw);
     }
   }
   return (p0 + p1) + (p2 + p3);
@@ -296,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_refine_small(
     const int64_t wave_first = e - (threadIdx.x % kWave) / 4;
     if (wave_first >= (int64_t)count) break;
     const bool valid = e < (int64_t)count;
-    float dist = INFINITY;
+    double dist = INFINITY;
     int cand = 0x7fffffff;
     int64_t p = 0;
     int chunk = 0;
@@ -306,12 +311,12 @@ __global__ __launch_bounds__(kBlock) void k_refine_small(
       const int c = slot < 3 ? small_cand[3 * e + slot] : -1;
       if (c >= 0) {
         cand = c;
-        dist = direct_dist<METRIC>(items + p * ld, protos + ((int64_t)chunk * k + c) * ld, ld);
+        dist = direct_dist64<METRIC>(items + p * ld, protos + ((int64_t)chunk * k + c) * ld, ld);
       }
     }
 #pragma unroll
     for (int o = 1; o <= 2; o <<= 1) {
-      const float od = __shfl_xor(dist, o);
+      const double od = __shfl_xor(dist, o);
       const int oc = __shfl_xor(cand, o);
       if (od < dist || (od == dist && oc < cand)) { dist = od; cand = oc; }
     }
@@ -323,39 +328,229 @@ __global__ __launch_bounds__(kBlock) void k_refine_small(
   }
 }
 
-// Points whose uncertainty window holds four or more prototypes: one wave
-// per point, lanes over every prototype of its group.
-template <int METRIC>
-__global__ __launch_bounds__(kBlock) void k_refine_full(
-    const float* __restrict__ items, int ld, const float* __restrict__ protos,
-    const int64_t* __restrict__ chunk_off, int n_chunks, int k,
-    const uint32_t* __restrict__ refine_count, const uint32_t* __restrict__ full_list,
-    int32_t* __restrict__ labels, unsigned long long* __restrict__ stats) {
-  const int lane = threadIdx.x % kWave;
-  const int64_t wave0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const int64_t n_waves = (int64_t)gridDim.x * (kBlock / kWave);
-  const uint32_t count = refine_count[1];
-  for (int64_t e = wave0; e < (int64_t)count; e += n_waves) {
-    const int64_t p = full_list[e];
-    const int chunk = find_chunk(chunk_off, n_chunks, p);
-    const float* x = items + p * ld;
-    const float* cbase = protos + (int64_t)chunk * k * ld;
-    float best = INFINITY;
-    int bi = 0x7fffffff;
-    for (int j = lane; j < k; j += kWave) {
-      const float dj = direct_dist<METRIC>(x, cbase + (int64_t)j * ld, ld);
-      if (dj < best) { best = dj; bi = j; }
-    }
+// Points whose uncertainty window holds four or more prototypes are listed
+// per group (full_list[off_c + i], i < full_cnt[c]).  One block builds the
+// list of 64-point tiles over all groups.
+__global__ __launch_bounds__(kBlock) void k_full_tiles(const uint32_t* __restrict__ full_cnt,
+                                                      int n_chunks, uint2* __restrict__ tiles,
+                                                      uint32_t* __restrict__ tile_total) {
+  __shared__ uint32_t s_wave[kBlock / kWave];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  uint32_t carry = 0;
+  for (int base = 0; base < n_chunks; base += kBlock) {
+    const int c = base + threadIdx.x;
+    const uint32_t nt = c < n_chunks ? (full_cnt[c] + 63u) / 64u : 0u;
+    uint32_t x = nt;
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const float od = __shfl_xor(best, o);
-      const int oi = __shfl_xor(bi, o);
-      if (od < best || (od == best && oi < bi)) { best = od; bi = oi; }
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
     }
-    if (lane == 0) {
-      labels[p] = chunk * k + bi;
-      if (stats) atomicAdd(&stats[1], 1ull);
+    if (lane == kWave - 1) s_wave[wave] = x;
+    __syncthreads();
+    uint32_t wbase = 0, tot = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) {
+      if (w < wave) wbase += s_wave[w];
+      tot += s_wave[w];
     }
+    __syncthreads();
+    const uint32_t ex = carry + wbase + x - nt;
+    for (uint32_t t = 0; t < nt; ++t) tiles[ex + t] = make_uint2((uint32_t)c, t);
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *tile_total = carry;
+}
+
+// One wave per (tile of up to 64 listed points of one group, range of that
+// group's prototypes).  Lane i owns point i of the tile, whose row is staged
+// in LDS (row stride ld + 4 floats, so 16-byte reads of different rows spread
+// over the banks); every lane walks the same prototypes, read with
+// wave-uniform loads, and keeps its nearest (FP64 direct form, lowest index
+// on exact ties).  Partial results per range go to
+// partial_d/partial_j[list slot * S + s].
+template <int METRIC>
+__global__ __launch_bounds__(kWave) void k_refine_full(
+    const float* __restrict__ items, int ld, const float* __restrict__ protos,
+    const int64_t* __restrict__ chunk_off, int k, const uint32_t* __restrict__ full_cnt,
+    const uint32_t* __restrict__ full_list, const uint2* __restrict__ tiles,
+    const uint32_t* __restrict__ tile_total, int S, double* __restrict__ partial_d,
+    int32_t* __restrict__ partial_j) {
+  extern __shared__ float4 s_x[];  // 64 rows x (ld4 + 1) float4
+  const int lane = threadIdx.x;
+  const int ld4 = ld / 4, xs = ld4 + 1;
+  const int s = blockIdx.y;
+  const int R = (k + S - 1) / S;
+  const int jlo = s * R, jhi = min(k, jlo + R);
+  const uint32_t total = *tile_total;
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const uint2 tc = tiles[t];
+    const int c = (int)tc.x;
+    const uint32_t cnt = full_cnt[c];
+    const int np = (int)min(64u, cnt - tc.y * 64u);
+    const int64_t qbase = chunk_off[c] + (int64_t)tc.y * 64;
+    __syncthreads();  // the previous tile's rows are no longer read
+    for (int i = lane; i < np * ld4; i += kWave) {
+      const int row = i / ld4, c4 = i % ld4;
+      const int64_t p = full_list[qbase + row];
+      s_x[row * xs + c4] = reinterpret_cast<const float4*>(items + p * ld)[c4];
+    }
+    __syncthreads();
+    const float4* xr = s_x + (lane < np ? lane : 0) * xs;
+    double best_d = INFINITY;
+    int best_j = 0x7fffffff;
+    const float* cbase = protos + (int64_t)c * k * ld;
+    for (int j = jlo; j < jhi; ++j) {
+      const float4* crow = reinterpret_cast<const float4*>(cbase + (int64_t)j * ld);
+      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+      for (int i = 0; i < ld4; ++i) {
+        const float4 a = xr[i], b = crow[i];
+        const double dx = (double)a.x - (double)b.x, dy = (double)a.y - (double)b.y,
+                     dz = (double)a.z - (double)b.z, dw = (double)a.w - (double)b.w;
+        if (METRIC == 0) {
+          p0 = fma(dx, dx, p0); p1 = fma(dy, dy, p1); p2 = fma(dz, dz, p2); p3 = fma(dw, dw, p3);
+        } else {
+          p0 += fabs(dx); p1 += fabs(dy); p2 += fabs(dz); p3 += fabs(dw);
+        }
+      }
+      const double dd = (p0 + p1) + (p2 + p3);
+      if (dd < best_d) { best_d = dd; best_j = j; }  // j ascends: ties keep the lower
+    }
+    if (lane < np) {
+      partial_d[(qbase + lane) * S + s] = best_d;
+      partial_j[(qbase + lane) * S + s] = best_j;
+    }
+  }
+}
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// Squared-Euclidean variant of the whole-group re-scoring on FP64 MFMA
+// (v_mfma_f64_16x16x4f64): s_ij = x_i . c_j - |c_j|^2 / 2 in FP64 from the
+// FP32 coordinates, whose rounding (~1e-10 absolute at these norms) is far
+// below any gap that matters.  Block = 4 waves; one (tile of up to 64 listed
+// points of one group, range of that group's prototypes) per iteration; wave
+// w owns points 16w..16w+15 (MFMA columns), prototypes are the rows and are
+// staged through LDS 64 at a time.  MFMA k-slot (s, g) is dimension g*KS+s.
+// Operand lanes: A[i][k] from lane 16k+i, B[k][j] from lane 16k+j; result
+// register r of lane l holds row 4r + l/16, column l%16.
+// Each point keeps the largest s (lowest index on exact ties); the negated
+// value goes to partial_d so the merge takes the smallest.
+template <int DP>
+__global__ __launch_bounds__(kBlock) void k_refine_f64(
+    const float* __restrict__ items, int ld, const float* __restrict__ protos,
+    const double* __restrict__ pnorm64, const int64_t* __restrict__ chunk_off, int k,
+    const uint32_t* __restrict__ full_cnt, const uint32_t* __restrict__ full_list,
+    const uint2* __restrict__ tiles, const uint32_t* __restrict__ tile_total, int S,
+    double* __restrict__ partial_d, int32_t* __restrict__ partial_j) {
+  constexpr int KS = DP / 4;
+  constexpr int TP = 64;
+  constexpr int LDW = DP + 4;
+  constexpr int F4_PER_ROW = DP / 4;
+  __shared__ float s_c[TP * LDW];
+  __shared__ double s_hn[TP];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int col = lane & 15, g = lane >> 4;
+  const int s = blockIdx.y;
+  const int R = (k + S - 1) / S;
+  const int jlo = s * R, jhi = min(k, jlo + R);
+  const uint32_t total = *tile_total;
+  for (uint32_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const uint2 tc = tiles[t];
+    const int c = (int)tc.x;
+    const uint32_t cnt = full_cnt[c];
+    const int np = (int)min(64u, cnt - tc.y * 64u);
+    const int64_t qbase = chunk_off[c] + (int64_t)tc.y * 64;
+    const int pt = wave * 16 + col;  // this lane's point within the tile
+    double b[KS];
+    {
+      const int64_t p = pt < np ? (int64_t)full_list[qbase + pt] : 0;
+      const float* row = items + p * ld;
+#pragma unroll
+      for (int i = 0; i < KS; i += 4) {
+        const int cc = g * KS + i;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (pt < np && cc < ld) v = *reinterpret_cast<const float4*>(row + cc);
+        b[i] = v.x; b[i + 1] = v.y; b[i + 2] = v.z; b[i + 3] = v.w;
+      }
+    }
+    double best = -INFINITY;
+    int bj = 0x7fffffff;
+    const float* cbase = protos + (int64_t)c * k * ld;
+    const double* nbase = pnorm64 + (int64_t)c * k;
+    for (int j0 = jlo; j0 < jhi; j0 += TP) {
+      __syncthreads();  // the previous prototype tile is no longer read
+      for (int idx = threadIdx.x; idx < TP * F4_PER_ROW; idx += kBlock) {
+        const int row = idx / F4_PER_ROW, c4 = idx % F4_PER_ROW;
+        const int j = j0 + row;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j < jhi && c4 * 4 < ld) v = *reinterpret_cast<const float4*>(cbase + (int64_t)j * ld + c4 * 4);
+        *reinterpret_cast<float4*>(&s_c[row * LDW + c4 * 4]) = v;
+      }
+      if (threadIdx.x < TP) {
+        const int j = j0 + threadIdx.x;
+        s_hn[threadIdx.x] = (j < jhi) ? 0.5 * nbase[j] : INFINITY;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int pb = 0; pb < TP / 16; ++pb) {
+        doublex4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = -s_hn[pb * 16 + 4 * r + g];  // row 4r + lane/16
+        const float* arow = &s_c[(pb * 16 + col) * LDW + g * KS];
+#pragma unroll
+        for (int i = 0; i < KS; i += 4) {
+          const float4 a4 = *reinterpret_cast<const float4*>(arow + i);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a4.x, b[i], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a4.y, b[i + 1], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a4.z, b[i + 2], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a4.w, b[i + 3], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = j0 + pb * 16 + 4 * r + g;
+          if (acc[r] > best) { best = acc[r]; bj = j; }  // padded rows hold -inf
+        }
+      }
+    }
+    // lanes col, col+16, col+32, col+48 hold the same point
+#pragma unroll
+    for (int o = 16; o <= 32; o <<= 1) {
+      const double ov = __shfl_xor(best, o);
+      const int oj = __shfl_xor(bj, o);
+      if (ov > best || (ov == best && oj < bj)) { best = ov; bj = oj; }
+    }
+    if (g == 0 && pt < np) {
+      partial_d[(qbase + pt) * S + s] = -best;
+      partial_j[(qbase + pt) * S + s] = bj;
+    }
+  }
+}
+
+// Final label of every listed point: the nearest over the S ranges.
+__global__ __launch_bounds__(kBlock) void k_refine_merge(
+    const int64_t* __restrict__ chunk_off, int k, const uint32_t* __restrict__ full_cnt,
+    const uint32_t* __restrict__ full_list, const uint2* __restrict__ tiles,
+    const uint32_t* __restrict__ tile_total, int S, const double* __restrict__ partial_d,
+    const int32_t* __restrict__ partial_j, int32_t* __restrict__ labels,
+    unsigned long long* __restrict__ stats) {
+  const int lane = threadIdx.x % kWave;
+  const uint32_t total = *tile_total;
+  const uint32_t n_waves = gridDim.x * (kBlock / kWave);
+  for (uint32_t t = (blockIdx.x * kBlock + threadIdx.x) / kWave; t < total; t += n_waves) {
+    const uint2 tc = tiles[t];
+    const int c = (int)tc.x;
+    const uint32_t i = tc.y * 64u + lane;
+    if (i >= full_cnt[c]) continue;
+    const int64_t q = chunk_off[c] + i;
+    double bd = INFINITY;
+    int bj = 0x7fffffff;
+    for (int s = 0; s < S; ++s) {
+      const double d = partial_d[q * S + s];
+      const int j = partial_j[q * S + s];
+      if (d < bd || (d == bd && j < bj)) { bd = d; bj = j; }
+    }
+    labels[full_list[q]] = c * k + bj;
+    if (stats) atomicAdd(&stats[1], 1ull);
   }
 }
 
@@ -366,7 +561,7 @@ template <int J>
 __global__ __launch_bounds__(kBlock) void k_update_l2(
     const float* __restrict__ items, int ld, const uint32_t* __restrict__ members,
     const uint32_t* __restrict__ member_off, int64_t n_protos, float* __restrict__ protos,
-    float* __restrict__ pnorm, double* __restrict__ proto_inertia) {
+    float* __restrict__ pnorm, double* __restrict__ pnorm64, double* __restrict__ proto_inertia) {
   const int lane = threadIdx.x % kWave;
   const int64_t p = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   if (p >= n_protos) return;
@@ -380,21 +575,50 @@ __global__ __launch_bounds__(kBlock) void k_update_l2(
   }
   double inert = 0.0;
   const uint32_t m0 = member_off[p], m1 = member_off[p + 1];
-  for (uint32_t m = m0; m < m1; ++m) {
+  // four members in flight; member m adds into partial (m - m0) % 4, the
+  // partials are combined in a fixed order below
+  double part[4][J];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int j = 0; j < J; ++j) part[u][j] = 0.0;
+  uint32_t m = m0;
+  for (; m + 4 <= m1; m += 4) {
+    float xv[4][J];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float* row = items + (int64_t)members[m + u] * ld;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int c = lane + j * kWave;
+        xv[u][j] = (c < ld) ? row[c] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        part[u][j] += (double)xv[u][j];
+        const double d = (double)xv[u][j] - (double)c_old[j];
+        inert = fma(d, d, inert);
+      }
+  }
+  for (; m < m1; ++m) {
     const float* row = items + (int64_t)members[m] * ld;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
       const int c = lane + j * kWave;
-      if (c < ld) {
-        const float x = row[c];
-        sum[j] += (double)x;
-        const double d = (double)x - (double)c_old[j];
-        inert = fma(d, d, inert);
-      }
+      const float x = (c < ld) ? row[c] : 0.f;
+      part[(m - m0) & 3][j] += (double)x;
+      const double d = (double)x - (double)c_old[j];
+      inert = fma(d, d, inert);
     }
   }
+#pragma unroll
+  for (int j = 0; j < J; ++j) sum[j] = (part[0][j] + part[1][j]) + (part[2][j] + part[3][j]);
   const uint32_t cnt = m1 - m0;
   float nrm = 0.f;
+  double nrm64 = 0.0;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int c = lane + j * kWave;
@@ -403,15 +627,18 @@ __global__ __launch_bounds__(kBlock) void k_update_l2(
     if (c < ld) {
       protos[p * ld + c] = v;
       nrm = fmaf(v, v, nrm);
+      nrm64 = fma((double)v, (double)v, nrm64);
     }
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     nrm += __shfl_xor(nrm, o);
+    nrm64 += __shfl_xor(nrm64, o);
     inert += __shfl_xor(inert, o);
   }
   if (lane == 0) {
     pnorm[p] = nrm;
+    pnorm64[p] = nrm64;
     proto_inertia[p] = inert;
   }
 }
@@ -428,6 +655,16 @@ __global__ __launch_bounds__(kBlock) void k_chunk_inertia(const double* __restri
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
   if (lane == 0) out[c] = acc;
+}
+
+__global__ void k_row_norms64(const float* __restrict__ x, int ld, int64_t n,
+                              double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float* r = x + i * ld;
+  double acc = 0.0;
+  for (int c = 0; c < ld; ++c) acc = fma((double)r[c], (double)r[c], acc);
+  out[i] = acc;
 }
 
 __global__ void k_init_first(const float* __restrict__ items, int ld,
@@ -466,33 +703,67 @@ void launch_assign(const float* items, int ld, int dim, const ChunkPlan& plan,
   ScopedTiming timing("assign_l2_mfma", s);
   k_assign_l2_mfma<DP, PB, TN, MINB><<<grid, kBlock, 0, s>>>(
       items, ld, protos, w.proto_norms, w.item_norms, plan.d_off, plan.k, tiles, labels,
-      w.refine_count, w.small_list, w.small_cand, w.full_list, err_coef);
+      w.refine_count, w.small_list, w.small_cand, w.full_cnt, w.full_list, err_coef);
   check_launch("assign_l2_mfma");
+}
+
+template <int METRIC>
+void launch_full(const float* items, int ld, const ChunkPlan& plan, const float* protos,
+                 KmeansWork& w, hipStream_t s) {
+  const dim3 grid(w.full_grid, w.full_splits);
+  const size_t shm = (size_t)64 * (ld + 4) * sizeof(float);
+  k_refine_full<METRIC><<<grid, kWave, shm, s>>>(
+      items, ld, protos, plan.d_off, plan.k, w.full_cnt, w.full_list, w.tiles, w.tile_total,
+      w.full_splits, w.partial_d, w.partial_j);
+}
+
+template <int DP>
+void launch_full_f64(const float* items, int ld, const ChunkPlan& plan, const float* protos,
+                     KmeansWork& w, hipStream_t s) {
+  const dim3 grid(w.full_grid, w.full_splits);
+  k_refine_f64<DP><<<grid, kBlock, 0, s>>>(items, ld, protos, w.proto_norms64, plan.d_off,
+                                           plan.k, w.full_cnt, w.full_list, w.tiles,
+                                           w.tile_total, w.full_splits, w.partial_d,
+                                           w.partial_j);
 }
 
 void launch_refine(const float* items, int ld, const ChunkPlan& plan, const float* protos,
                    int32_t* labels, KmeansWork& w, int metric, hipStream_t s) {
   unsigned long long* stats = timing_refine_counter();
   ScopedTiming timing("refine", s);
-  if (metric == MASK_L2) {
+  if (metric == MASK_L2)
     k_refine_small<0><<<1024, kBlock, 0, s>>>(items, ld, protos, plan.d_off, plan.n_chunks,
                                               plan.k, w.refine_count, w.small_list, w.small_cand,
                                               labels, stats);
-    k_refine_full<0><<<512, kBlock, 0, s>>>(items, ld, protos, plan.d_off, plan.n_chunks, plan.k,
-                                            w.refine_count, w.full_list, labels, stats);
-  } else {
+  else
     k_refine_small<1><<<1024, kBlock, 0, s>>>(items, ld, protos, plan.d_off, plan.n_chunks,
                                               plan.k, w.refine_count, w.small_list, w.small_cand,
                                               labels, stats);
-    k_refine_full<1><<<512, kBlock, 0, s>>>(items, ld, protos, plan.d_off, plan.n_chunks, plan.k,
-                                            w.refine_count, w.full_list, labels, stats);
+  check_launch("refine_small");
+  k_full_tiles<<<1, kBlock, 0, s>>>(w.full_cnt, plan.n_chunks, w.tiles, w.tile_total);
+  check_launch("full_tiles");
+  if (metric == MASK_L2) {
+    const int dp = (ld + 15) & ~15;
+    if (dp <= 16) launch_full_f64<16>(items, ld, plan, protos, w, s);
+    else if (dp <= 32) launch_full_f64<32>(items, ld, plan, protos, w, s);
+    else if (dp <= 64) launch_full_f64<64>(items, ld, plan, protos, w, s);
+    else if (dp <= 96) launch_full_f64<96>(items, ld, plan, protos, w, s);
+    else if (dp <= 128) launch_full_f64<128>(items, ld, plan, protos, w, s);
+    else launch_full<0>(items, ld, plan, protos, w, s);
+  } else {
+    launch_full<1>(items, ld, plan, protos, w, s);
   }
-  check_launch("refine");
+  check_launch("refine_full");
+  k_refine_merge<<<256, kBlock, 0, s>>>(plan.d_off, plan.k, w.full_cnt, w.full_list, w.tiles,
+                                        w.tile_total, w.full_splits, w.partial_d, w.partial_j,
+                                        labels, stats);
+  check_launch("refine_merge");
 }
 
 }  // namespace
 
-void kmeans_alloc(KmeansWork& w, int64_t n_items, int64_t n_protos, Arena& a) {
+void kmeans_alloc(KmeansWork& w, int64_t n_items, int n_chunks, int k, Arena& a) {
+  const int64_t n_protos = (int64_t)n_chunks * k;
   w.sort_keys = a.alloc<uint32_t>(n_items);
   w.sort_vals = a.alloc<uint32_t>(n_items);
   sort_work_alloc(w.sort, n_items, false, a);
@@ -501,9 +772,27 @@ void kmeans_alloc(KmeansWork& w, int64_t n_items, int64_t n_protos, Arena& a) {
   w.refine_count = a.alloc<uint32_t>(4);
   w.small_list = a.alloc<uint32_t>(n_items);
   w.small_cand = a.alloc<int32_t>(3 * n_items);
+  w.full_cnt = a.alloc<uint32_t>(n_chunks);
   w.full_list = a.alloc<uint32_t>(n_items);
+  const int64_t max_tiles = n_items / 64 + n_chunks + 1;
+  w.tiles = a.alloc<uint2>(max_tiles);
+  w.tile_total = a.alloc<uint32_t>(4);
+  // prototype ranges of about 128 per wave, at most 64 ranges
+  w.full_splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, (k + 127) / 128));
+  w.full_grid = (int)std::min<int64_t>(max_tiles, 1024);
+  w.partial_d = a.alloc<double>(n_items * w.full_splits);
+  w.partial_j = a.alloc<int32_t>(n_items * w.full_splits);
   w.item_norms = a.alloc<float>(n_items);
   w.proto_norms = a.alloc<float>(n_protos);
+  w.proto_norms64 = a.alloc<double>(n_protos);
+}
+
+void kmeans_proto_norms(const float* protos, int ld, int64_t n_protos, KmeansWork& w,
+                        hipStream_t s) {
+  row_norms(protos, ld, n_protos, w.proto_norms, s);
+  k_row_norms64<<<grid_for(n_protos, kBlock), kBlock, 0, s>>>(protos, ld, n_protos,
+                                                            w.proto_norms64);
+  check_launch("row_norms64");
 }
 
 void kmeans_init_first(const float* items, int ld, const ChunkPlan& plan, float* protos,
@@ -519,12 +808,13 @@ void kmeans_assign(const float* items, int ld, int dim, const ChunkPlan& plan,
                    hipStream_t s) {
   if (metric != MASK_L2) throw Error{MASK_ERR_UNSUPPORTED, "assignment metric"};
   fill_u32(w.refine_count, 2, 0u, s);
+  fill_u32(w.full_cnt, plan.n_chunks, 0u, s);
   const int dp = (dim + 7) & ~7;
   if (dp <= 16) launch_assign<16, 2, 64>(items, ld, dim, plan, protos, labels, w, s);
   else if (dp <= 32) launch_assign<32, 2, 64>(items, ld, dim, plan, protos, labels, w, s);
   else if (dp <= 64) launch_assign<64, 2, 64>(items, ld, dim, plan, protos, labels, w, s);
   else if (dp <= 96) launch_assign<96, 2, 32>(items, ld, dim, plan, protos, labels, w, s);
-  else if (dp <= 128) launch_assign<128, 2, 64, 1>(items, ld, dim, plan, protos, labels, w, s);
+  else if (dp <= 128) launch_assign<128, 1, 32, 3>(items, ld, dim, plan, protos, labels, w, s);
   else if (dp <= 192) launch_assign<192, 1, 32>(items, ld, dim, plan, protos, labels, w, s);
   else if (dp <= 256) launch_assign<256, 1, 32>(items, ld, dim, plan, protos, labels, w, s);
   else throw Error{MASK_ERR_UNSUPPORTED, "dense dimension above 256"};
@@ -550,13 +840,13 @@ void kmeans_update(const float* items, int ld, int dim, const ChunkPlan& plan,
   ScopedTiming timing("update_l2", s);
   if (J <= 1)
     k_update_l2<1><<<grid, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off, np, protos,
-                                           w.proto_norms, w.proto_inertia);
+                                           w.proto_norms, w.proto_norms64, w.proto_inertia);
   else if (J <= 2)
     k_update_l2<2><<<grid, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off, np, protos,
-                                           w.proto_norms, w.proto_inertia);
+                                           w.proto_norms, w.proto_norms64, w.proto_inertia);
   else
     k_update_l2<4><<<grid, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off, np, protos,
-                                           w.proto_norms, w.proto_inertia);
+                                           w.proto_norms, w.proto_norms64, w.proto_inertia);
   check_launch("update_l2");
   if (inertia_out) {
     k_chunk_inertia<<<grid_for((int64_t)plan.n_chunks * kWave, kBlock), kBlock, 0, s>>>(

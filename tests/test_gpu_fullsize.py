@@ -39,8 +39,8 @@ def test_fullsize_sampled_queries(built):
         ids, dist, sel = host(ids), host(dist), host(sel)
         _, _, fails = check_query_against_oracle(oix, X, Q, cfg.k, r, ids, dist, sel, rows=rows)
         assert not fails, (r, fails[:3])
-        # every row is sorted and padded consistently
-        assert np.all(np.diff(dist, axis=1) >= 0)
+        # every row is sorted (padding is +inf at the end)
+        assert np.all(dist[:, 1:] >= dist[:, :-1])
 
 
 def test_fullsize_sampled_assignments(built):
