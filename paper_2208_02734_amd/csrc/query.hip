@@ -141,7 +141,9 @@ __device__ void block_select(uint64_t* buf, uint32_t m, uint32_t want, uint64_t*
   __syncthreads();
 }
 
-template <int TPR, int METRIC>
+// TPR lanes per candidate row; NV float4 of the row per lane (0: any number,
+// looped); U rows in flight per lane group.
+template <int TPR, int NV, int U, int METRIC>
 __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* __restrict__ Q,
                                                     int ldq, int64_t nq, int k, int r,
                                                     int32_t* __restrict__ out_ids,
@@ -172,6 +174,13 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* 
 
   const int grp = tid / TPR, gl = tid % TPR;
   constexpr int kGroups = kBlock / TPR;
+  constexpr int NQ = NV > 0 ? NV : 1;
+  float4 qv[NQ];
+#pragma unroll
+  for (int v = 0; v < NQ; ++v) {
+    const int c4 = gl + v * TPR;
+    qv[v] = (NV > 0 && c4 < ld4) ? s_q4[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   unsigned long long rows_seen = 0;
 
   for (int lev = L; lev >= 0; --lev) {
@@ -185,37 +194,84 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* 
     uint64_t thr = ~0ull;
     for (uint32_t base = 0; base < m; base += round) {
       const uint32_t end = (m - base < round) ? m : base + round;
-      for (uint32_t idx = base + grp; idx < end; idx += kGroups) {
-        // parent j: the last with s_pre[j] <= idx
+      for (uint32_t i0 = base + grp * U; i0 < end; i0 += kGroups * U) {
+        // parent of i0: the last j with s_pre[j] <= i0; later rows walk forward
         int lo = 0, hi = n_par - 1;
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
-          if (s_pre[mid] <= idx) lo = mid; else hi = mid - 1;
+          if (s_pre[mid] <= i0) lo = mid; else hi = mid - 1;
         }
-        const int64_t pos = (int64_t)s_beg[lo] + (idx - s_pre[lo]);
-        const float4* row = reinterpret_cast<const float4*>(V.protos + pos * ld);
-        float acc = 0.f;
-        for (int c4 = gl; c4 < ld4; c4 += TPR) {
-          const float4 x = row[c4];
-          const float4 qv = s_q4[c4];
-          const float dx = x.x - qv.x, dy = x.y - qv.y, dz = x.z - qv.z, dw = x.w - qv.w;
-          if (METRIC == 0) {
-            acc = fmaf(dx, dx, acc);
-            acc = fmaf(dy, dy, acc);
-            acc = fmaf(dz, dz, acc);
-            acc = fmaf(dw, dw, acc);
-          } else {
-            acc += fabsf(dx) + fabsf(dy) + fabsf(dz) + fabsf(dw);
+        int64_t pos[U];
+        bool val[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t idx = i0 + u;
+          val[u] = idx < end;
+          while (val[u] && lo + 1 < n_par && s_pre[lo + 1] <= idx) ++lo;
+          pos[u] = (int64_t)s_beg[lo] + (idx - s_pre[lo]);
+        }
+        float acc[U];
+        if constexpr (NV > 0) {
+          float4 x[U][NV];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const float4* row = reinterpret_cast<const float4*>(V.protos + (val[u] ? pos[u] : 0) * ld);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              const int c4 = gl + v * TPR;
+              x[u][v] = (val[u] && c4 < ld4) ? row[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            float s0 = 0.f;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              const float dx = x[u][v].x - qv[v].x, dy = x[u][v].y - qv[v].y,
+                          dz = x[u][v].z - qv[v].z, dw = x[u][v].w - qv[v].w;
+              if (METRIC == 0) {
+                s0 = fmaf(dx, dx, s0); s0 = fmaf(dy, dy, s0);
+                s0 = fmaf(dz, dz, s0); s0 = fmaf(dw, dw, s0);
+              } else {
+                s0 += fabsf(dx) + fabsf(dy) + fabsf(dz) + fabsf(dw);
+              }
+            }
+            acc[u] = s0;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const float4* row = reinterpret_cast<const float4*>(V.protos + (val[u] ? pos[u] : 0) * ld);
+            float s0 = 0.f;
+            for (int c4 = gl; c4 < ld4; c4 += TPR) {
+              const float4 xv = val[u] ? row[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+              const float4 q = s_q4[c4];
+              const float dx = xv.x - q.x, dy = xv.y - q.y, dz = xv.z - q.z, dw = xv.w - q.w;
+              if (METRIC == 0) {
+                s0 = fmaf(dx, dx, s0); s0 = fmaf(dy, dy, s0);
+                s0 = fmaf(dz, dz, s0); s0 = fmaf(dw, dw, s0);
+              } else {
+                s0 += fabsf(dx) + fabsf(dy) + fabsf(dz) + fabsf(dw);
+              }
+            }
+            acc[u] = s0;
           }
         }
 #pragma unroll
-        for (int o = TPR / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+          for (int o = TPR / 2; o >= 1; o >>= 1) acc[u] += __shfl_xor(acc[u], o);
+        }
         if (gl == 0) {
-          const uint32_t id = (uint32_t)V.orig[pos];
-          const uint64_t key = ((uint64_t)__float_as_uint(acc) << 32) | id;
-          if (key < thr) {
-            const uint32_t slot = atomicAdd(&sh.cnt, 1u);
-            if (slot < (uint32_t)kCap) s_buf[slot] = key;  // rounds keep slot < kCap
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (!val[u]) continue;
+            const uint32_t id = (uint32_t)V.orig[pos[u]];
+            const uint64_t key = ((uint64_t)__float_as_uint(acc[u]) << 32) | id;
+            if (key < thr) {
+              const uint32_t slot = atomicAdd(&sh.cnt, 1u);
+              if (slot < (uint32_t)kCap) s_buf[slot] = key;  // rounds keep slot < kCap
+            }
           }
         }
       }
@@ -303,18 +359,18 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* 
   if (rows_out && tid == 0) atomicAdd(rows_out, rows_seen);
 }
 
-template <int TPR>
+template <int TPR, int NV, int U>
 void launch_descent(const DescentArgs& a, const float* q, int ldq, int64_t nq, int k, int r,
                     int32_t* out_ids, float* out_dist, int32_t* sel, unsigned long long* rows,
                     hipStream_t s) {
   const size_t shm = (size_t)a.ld * sizeof(float);
   ScopedTiming timing("descent", s);
   if (a.metric == MASK_L2)
-    k_descent<TPR, 0><<<(unsigned)nq, kBlock, shm, s>>>(a, q, ldq, nq, k, r, out_ids, out_dist,
-                                                        sel, rows);
+    k_descent<TPR, NV, U, 0><<<(unsigned)nq, kBlock, shm, s>>>(a, q, ldq, nq, k, r, out_ids,
+                                                              out_dist, sel, rows);
   else
-    k_descent<TPR, 1><<<(unsigned)nq, kBlock, shm, s>>>(a, q, ldq, nq, k, r, out_ids, out_dist,
-                                                        sel, rows);
+    k_descent<TPR, NV, U, 1><<<(unsigned)nq, kBlock, shm, s>>>(a, q, ldq, nq, k, r, out_ids,
+                                                              out_dist, sel, rows);
   check_launch("descent");
 }
 
@@ -325,11 +381,15 @@ void descent(const DescentArgs& a, const float* q, int ldq, int64_t nq, int k, i
              hipStream_t s) {
   if (nq <= 0) return;
   const int f4 = a.ld / 4;
-  if (f4 <= 1) launch_descent<1>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else if (f4 <= 2) launch_descent<2>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else if (f4 <= 4) launch_descent<4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else if (f4 <= 8) launch_descent<8>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else launch_descent<16>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
+  if (f4 <= 1) launch_descent<1, 1, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
+  else if (f4 <= 2) launch_descent<2, 1, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
+  else if (f4 <= 4) launch_descent<4, 1, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
+  else if (f4 <= 8) launch_descent<8, 1, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
+  else if (f4 <= 16) launch_descent<16, 1, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
+  else if (f4 <= 32) launch_descent<16, 2, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
+  else if (f4 <= 64) launch_descent<16, 4, 2>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
+  else if (f4 <= 128) launch_descent<16, 8, 1>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
+  else launch_descent<16, 0, 1>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
 }
 
 }  // namespace mask
