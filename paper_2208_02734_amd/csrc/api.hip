@@ -339,7 +339,6 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
     std::vector<int64_t> sizes;
     check_levels(data->n, p->n_levels, p->levels, sizes);
     if (data->dim > kMaxDenseDim) throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};
-    if (p->metric != MASK_L2) throw Error{MASK_ERR_UNSUPPORTED, "L1 build"};
     if (p->precision != MASK_FP32) throw Error{MASK_ERR_UNSUPPORTED, "precision form"};
 
     auto ix = std::make_unique<mask_index>(a, s);
@@ -548,7 +547,6 @@ mask_status mask_kmeans(const mask_matrix* items, int32_t n_chunks, int32_t k, i
     MASK_CHECK(centroids && labels, "output pointer is NULL");
     MASK_CHECK(metric == MASK_L2 || metric == MASK_L1, "unknown metric");
     if (items->dim > kMaxDenseDim) throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};
-    if (metric != MASK_L2) throw Error{MASK_ERR_UNSUPPORTED, "L1 k-means"};
     const int dim = items->dim, ld = round_up4(dim);
     const int64_t n = items->n, np = (int64_t)n_chunks * k;
     Arena scratch(a, s);

@@ -657,6 +657,133 @@ __global__ __launch_bounds__(kBlock) void k_chunk_inertia(const double* __restri
   if (lane == 0) out[c] = acc;
 }
 
+// Direct-form assignment on the vector units, for metrics without an MFMA
+// form (L1) and for wide rows: one wave per 64 items of one group, item rows
+// staged in LDS with an odd row stride (conflict-free per-lane reads), every
+// lane walks all k prototypes of the group with wave-uniform loads.  The
+// per-element difference is exact in FP64 and accumulated in FP64, so the
+// labels agree with an FP64 evaluation except for gaps of about 1e-15.
+template <int METRIC>
+__global__ __launch_bounds__(kWave) void k_assign_direct(
+    const float* __restrict__ items, int ld, const float* __restrict__ protos,
+    const int64_t* __restrict__ chunk_off, int k, int tiles_per_chunk,
+    int32_t* __restrict__ labels) {
+  extern __shared__ float s_xr[];  // 64 rows x (ld + 1)
+  const int lane = threadIdx.x;
+  const int chunk = blockIdx.x / tiles_per_chunk, tile = blockIdx.x % tiles_per_chunk;
+  const int64_t c0 = chunk_off[chunk], c1 = chunk_off[chunk + 1];
+  const int64_t pbase = c0 + (int64_t)tile * 64;
+  if (pbase >= c1) return;
+  const int np = (int)min<int64_t>(64, c1 - pbase);
+  const int xs = ld + 1;
+  for (int i = lane; i < np * ld; i += kWave) {
+    const int row = i / ld, c = i % ld;
+    s_xr[row * xs + c] = items[(pbase + row) * ld + c];
+  }
+  __syncthreads();
+  const float* xr = s_xr + (lane < np ? lane : 0) * xs;
+  const float* cbase = protos + (int64_t)chunk * k * ld;
+  double best = INFINITY;
+  int bj = 0;
+  for (int j = 0; j < k; ++j) {
+    const float4* crow = reinterpret_cast<const float4*>(cbase + (int64_t)j * ld);
+    double a0 = 0.0, a1 = 0.0;
+    for (int i = 0; i < ld / 4; ++i) {
+      const float4 cv = crow[i];
+      const double d0 = (double)xr[4 * i] - (double)cv.x, d1 = (double)xr[4 * i + 1] - (double)cv.y,
+                   d2 = (double)xr[4 * i + 2] - (double)cv.z, d3 = (double)xr[4 * i + 3] - (double)cv.w;
+      if (METRIC == 0) {
+        a0 = fma(d0, d0, a0); a1 = fma(d1, d1, a1); a0 = fma(d2, d2, a0); a1 = fma(d3, d3, a1);
+      } else {
+        a0 += fabs(d0); a1 += fabs(d1); a0 += fabs(d2); a1 += fabs(d3);
+      }
+    }
+    const double dd = a0 + a1;
+    if (dd < best) { best = dd; bj = j; }  // ascending j: ties keep the lower
+  }
+  if (lane < np) labels[pbase + lane] = chunk * k + bj;
+}
+
+// Order-preserving map of float bits to unsigned keys.
+__device__ inline uint32_t float_key(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float key_float(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+// k-medians update (L1): one wave per prototype, lanes over dimensions; each
+// new coordinate is the lower median (order statistic floor((m-1)/2)) of the
+// members' values, found by a most-significant-bit-first radix select over
+// the order-preserving keys (32 passes over the member list); an empty
+// prototype keeps its value.  Also the FP64 L1 inertia under the old
+// prototype.
+template <int J>
+__global__ __launch_bounds__(kBlock) void k_update_l1(
+    const float* __restrict__ items, int ld, const uint32_t* __restrict__ members,
+    const uint32_t* __restrict__ member_off, int64_t n_protos, float* __restrict__ protos,
+    double* __restrict__ proto_inertia) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t p = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  if (p >= n_protos) return;
+  const uint32_t m0 = member_off[p], m1 = member_off[p + 1];
+  const uint32_t cnt = m1 - m0;
+  float c_old[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int c = lane + j * kWave;
+    c_old[j] = (c < ld) ? protos[p * ld + c] : 0.f;
+  }
+  double inert = 0.0;
+  for (uint32_t m = m0; m < m1; ++m) {
+    const float* row = items + (int64_t)members[m] * ld;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int c = lane + j * kWave;
+      if (c < ld) inert += fabs((double)row[c] - (double)c_old[j]);
+    }
+  }
+  if (cnt > 0) {
+    const uint32_t t = (cnt - 1) / 2;
+    uint32_t prefix[J], rank[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) { prefix[j] = 0; rank[j] = t; }
+    for (int b = 31; b >= 0; --b) {
+      const uint32_t hi_mask = (b == 31) ? 0u : (0xffffffffu << (b + 1));
+      uint32_t zeros[J];
+#pragma unroll
+      for (int j = 0; j < J; ++j) zeros[j] = 0;
+      for (uint32_t m = m0; m < m1; ++m) {
+        const float* row = items + (int64_t)members[m] * ld;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const int c = lane + j * kWave;
+          if (c < ld) {
+            const uint32_t key = float_key(row[c]);
+            zeros[j] += ((key & hi_mask) == prefix[j]) && !((key >> b) & 1u);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        if (rank[j] >= zeros[j]) {  // the wanted value has bit b set
+          rank[j] -= zeros[j];
+          prefix[j] |= 1u << b;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int c = lane + j * kWave;
+      if (c < ld) protos[p * ld + c] = key_float(prefix[j]);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) inert += __shfl_xor(inert, o);
+  if (lane == 0) proto_inertia[p] = inert;
+}
+
 __global__ void k_row_norms64(const float* __restrict__ x, int ld, int64_t n,
                               double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -806,7 +933,19 @@ void kmeans_init_first(const float* items, int ld, const ChunkPlan& plan, float*
 void kmeans_assign(const float* items, int ld, int dim, const ChunkPlan& plan,
                    const float* protos, int32_t* labels, KmeansWork& w, int metric,
                    hipStream_t s) {
-  if (metric != MASK_L2) throw Error{MASK_ERR_UNSUPPORTED, "assignment metric"};
+  if (metric == MASK_L1 || dim > kMaxDenseDim) {
+    const int tiles = (int)((plan.max_chunk + 63) / 64);
+    const size_t shm = (size_t)64 * (ld + 1) * sizeof(float);
+    ScopedTiming timing("assign_direct", s);
+    if (metric == MASK_L1)
+      k_assign_direct<1><<<(unsigned)(tiles * plan.n_chunks), kWave, shm, s>>>(
+          items, ld, protos, plan.d_off, plan.k, tiles, labels);
+    else
+      k_assign_direct<0><<<(unsigned)(tiles * plan.n_chunks), kWave, shm, s>>>(
+          items, ld, protos, plan.d_off, plan.k, tiles, labels);
+    check_launch("assign_direct");
+    return;
+  }
   fill_u32(w.refine_count, 2, 0u, s);
   fill_u32(w.full_cnt, plan.n_chunks, 0u, s);
   const int dp = (dim + 7) & ~7;
@@ -825,7 +964,6 @@ void kmeans_update(const float* items, int ld, int dim, const ChunkPlan& plan,
                    const int32_t* labels, float* protos, KmeansWork& w, int metric,
                    double* inertia_out, hipStream_t s) {
   (void)dim;
-  if (metric != MASK_L2) throw Error{MASK_ERR_UNSUPPORTED, "update metric"};
   const int64_t n = plan.n_items;
   const int64_t np = (int64_t)plan.n_chunks * plan.k;
   {
@@ -837,6 +975,21 @@ void kmeans_update(const float* items, int ld, int dim, const ChunkPlan& plan,
   }
   const int J = (ld + kWave - 1) / kWave;
   const unsigned grid = grid_for(np * kWave, kBlock);
+  if (metric == MASK_L1) {
+    ScopedTiming timing("update_l1", s);
+    if (J <= 1)
+      k_update_l1<1><<<grid, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off, np, protos,
+                                             w.proto_inertia);
+    else if (J <= 2)
+      k_update_l1<2><<<grid, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off, np, protos,
+                                             w.proto_inertia);
+    else if (J <= 4)
+      k_update_l1<4><<<grid, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off, np, protos,
+                                             w.proto_inertia);
+    else
+      throw Error{MASK_ERR_UNSUPPORTED, "L1 update of rows wider than 256"};
+    check_launch("update_l1");
+  } else {
   ScopedTiming timing("update_l2", s);
   if (J <= 1)
     k_update_l2<1><<<grid, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off, np, protos,
@@ -848,6 +1001,7 @@ void kmeans_update(const float* items, int ld, int dim, const ChunkPlan& plan,
     k_update_l2<4><<<grid, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off, np, protos,
                                            w.proto_norms, w.proto_norms64, w.proto_inertia);
   check_launch("update_l2");
+  }
   if (inertia_out) {
     k_chunk_inertia<<<grid_for((int64_t)plan.n_chunks * kWave, kBlock), kBlock, 0, s>>>(
         w.proto_inertia, plan.n_chunks, plan.k, inertia_out);

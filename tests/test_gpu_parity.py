@@ -301,3 +301,60 @@ def test_build_is_deterministic(pk):
         Pa, pa = a.export_level(lev)
         Pb, pb = b.export_level(lev)
         assert np.array_equal(pa, pb) and np.array_equal(Pa, Pb)
+
+
+# ------------------------------------------------------------------ L1 ---
+
+def test_one_lloyd_step_l1_matches_oracle(pk):
+    # k-medians: labels by sum |x - c|, update = per-dimension lower median
+    n, d, C, k = 2001, 12, 3, 30
+    X, _ = _mixture(n, d, 20, seed=131)
+    Xd = dev(X)
+    _, lab0, _ = pk.mask_kmeans(Xd, C, k, 0, metric="l1")
+    cent1, _, inert = pk.mask_kmeans(Xd, C, k, 1, metric="l1")
+    lab0, cent1, inert = host(lab0), host(cent1), host(inert)
+    off = mo.chunk_offsets(n, C)
+    for c in range(C):
+        pts = X[off[c]:off[c + 1]].astype(np.float64)
+        olab, onew, oin = mo.lloyd_step(pts, pts[:k], "l1")
+        glab = lab0[off[c]:off[c + 1]] - c * k
+        D = mo.pairwise(pts, pts[:k], "l1")
+        diff = np.nonzero(glab != olab)[0]
+        for i in diff:
+            a, b = D[i, glab[i]], D[i, olab[i]]
+            assert abs(a - b) <= 1e-12 * max(a, b), (c, i, a, b)
+        assert abs(inert[0, c] - oin) <= 1e-9 * oin
+        bad = set(glab[diff].tolist()) | set(olab[diff].tolist())
+        for j in range(k):
+            if j not in bad:
+                # the lower median is a data value: exact equality
+                assert np.array_equal(cent1[c * k + j], onew[j].astype(np.float32)), (c, j)
+
+
+def test_full_l1_build_matches_oracle_on_separated_clouds(pk):
+    # seed 58: every L1 assignment of the oracle build has a relative gap > 1e-4
+    X = _separated(58)
+    levels = mo.plan_levels(1600, 16, 8)
+    oix = mo.build(X, levels, 6, seed=58, metric="l1")
+    gix = pk.mask_build(dev(X), levels, iters=6, seed=58, metric="l1")
+    for lev in range(1, len(levels) + 1):
+        P, par = gix.export_level(lev)
+        assert np.array_equal(par, oix.parents[lev - 1]), lev
+        assert np.array_equal(P, oix.protos[lev - 1].astype(np.float32)), lev
+    gix.free()
+
+
+def test_l1_query_matches_oracle(pk):
+    X, Q = _mixture(5000, 20, 30, seed=141, nq=80)
+    gix = pk.mask_build(dev(X), [(5, 60), (1, 20)], iters=6, seed=3, metric="l1")
+    oix = oracle_index_from_gpu(X, gix, metric="l1")
+    for r, k in [(1, 5), (6, 10)]:
+        ids, dist, sel = pk.mask_query(gix, dev(Q), k, r, debug=True)
+        _, _, fails = check_query_against_oracle(oix, X, Q, k, r, host(ids), host(dist),
+                                                 host(sel))
+        assert not fails, (r, k, fails[:3])
+    # probe-all is exact L1 kNN
+    ids, dist = pk.mask_query(gix, dev(Q), 10, 512)
+    tids, tdist = mo.exact_knn(X, Q, 10, metric="l1")
+    true = oc.true_distances(X, Q, host(ids).astype(np.int64), "l1")
+    assert oc.check_knn(host(ids), host(dist), tids, tdist, true, REL).ok
