@@ -142,11 +142,26 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
  * k nearest data points under the kept level-1 prototypes.  Ranking key:
  * (distance, original id).  out_ids: device int32[q->n * k] (original data
  * row ids), out_dist: device float32[q->n * k], rows ascending; slots beyond
- * the candidate count hold id -1 and +inf.  1 <= k <= 512 and 1 <= r <= 512.
+ * the candidate count hold id -1 and +inf.  1 <= k <= 2048, 1 <= r <= 2048.
+ * Precision form (index built with MASK_BF16): rows are compared in BF16 and
+ * the data layer's min(rerank_factor * k * r, 2048) nearest by BF16 distance
+ * are re-ranked in FP32 direct form on the FP32 rows (all candidates in FP32
+ * when they are no more than that).
  * Asynchronous on hip_stream; allocates nothing.  Each query's result does
  * not depend on the other queries of the batch. */
 mask_status mask_query(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
                        int32_t* out_ids, float* out_dist, void* hip_stream);
+
+/* Ragged batch: query i uses k_i[i] and r_i[i] (device int32[q->n], each in
+ * [1, k_max] / [1, r_max]) and writes its k_i[i] results at out_ids +
+ * out_off[i] / out_dist + out_off[i] (device int64[q->n]).  k_max, r_max <=
+ * 2048 are host values bounding the per-query ones (they size the launch).
+ * Otherwise as mask_query; each query's result equals what mask_query
+ * returns for it alone with the same k and r. */
+mask_status mask_query_ragged(const mask_index* ix, const mask_matrix* q, const int32_t* k_i,
+                              const int32_t* r_i, const int64_t* out_off, int32_t k_max,
+                              int32_t r_max, int32_t* out_ids, float* out_dist,
+                              void* hip_stream);
 
 /* mask_query plus the prototypes kept at every level: sel is device
  * int32[q->n * n_levels * r], level-major from the top level down, each set

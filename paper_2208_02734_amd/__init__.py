@@ -69,7 +69,8 @@ class mask_allocator(ctypes.Structure):
 
 _lib = None
 
-EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_debug", "mask_free",
+EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_ragged",
+            "mask_query_debug", "mask_free",
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
             "mask_last_error", "mask_timing_enable", "mask_timing_report"]
 
@@ -88,6 +89,7 @@ def lib() -> ctypes.CDLL:
     L.mask_build.argtypes = [P(mask_matrix), P(mask_build_params), P(mask_allocator), VP, P(VP)]
     L.mask_query.argtypes = [VP, P(mask_matrix), I32, I32, VP, VP, VP]
     L.mask_query_debug.argtypes = [VP, P(mask_matrix), I32, I32, VP, VP, VP, VP]
+    L.mask_query_ragged.argtypes = [VP, P(mask_matrix), VP, VP, VP, I32, I32, VP, VP, VP]
     L.mask_free.argtypes = [VP]
     L.mask_index_info.argtypes = [VP, P(mask_info)]
     L.mask_export_level.argtypes = [VP, I32, VP, VP]
@@ -266,13 +268,33 @@ def mask_query(index: Index, queries, k: int, r: int, stream=None, debug: bool =
     return ids, dist
 
 
+def mask_query_ragged(index: Index, queries, k_i, r_i, stream=None):
+    """Per-query k and r (int32 CUDA tensors of length nq); returns
+    (ids, dist, offsets): query i's results are ids[offsets[i]:offsets[i+1]]."""
+    torch = _torch()
+    m = _dense(queries)
+    k_i = k_i.to(device=queries.device, dtype=torch.int32).contiguous()
+    r_i = r_i.to(device=queries.device, dtype=torch.int32).contiguous()
+    off = torch.zeros(queries.shape[0] + 1, dtype=torch.int64, device=queries.device)
+    off[1:] = torch.cumsum(k_i.to(torch.int64), 0)
+    total = int(off[-1].item())
+    ids = torch.empty(max(total, 1), dtype=torch.int32, device=queries.device)
+    dist = torch.empty(max(total, 1), dtype=torch.float32, device=queries.device)
+    k_max = int(k_i.max().item()) if queries.shape[0] else 1
+    r_max = int(r_i.max().item()) if queries.shape[0] else 1
+    _check(lib().mask_query_ragged(index.handle, ctypes.byref(m), k_i.data_ptr(), r_i.data_ptr(),
+                                   off.data_ptr(), k_max, r_max, ids.data_ptr(), dist.data_ptr(),
+                                   _stream_handle(stream)))
+    return ids[:total], dist[:total], off
+
+
 def mask_free(index: Index):
     index.free()
 
 
 def mask_import(data, levels: Sequence[Tuple[int, int]], protos: Sequence[np.ndarray],
-                parents: Sequence[np.ndarray], metric: str = "l2", stream=None,
-                torch_allocator: bool = True) -> Index:
+                parents: Sequence[np.ndarray], metric: str = "l2", precision: str = "fp32",
+                rerank_factor: int = 4, stream=None, torch_allocator: bool = True) -> Index:
     """Index from prototypes (chunk-major, per level) and parent ids (per
     level, for the items one level down), e.g. built by another
     implementation."""
@@ -282,7 +304,7 @@ def mask_import(data, levels: Sequence[Tuple[int, int]], protos: Sequence[np.nda
     Q = [np.ascontiguousarray(q, dtype=np.int32) for q in parents]
     pp = (ctypes.c_void_p * L)(*[p.ctypes.data for p in P])
     qq = (ctypes.c_void_p * L)(*[q.ctypes.data for q in Q])
-    prm, lv = _params(levels, 0, 0, metric, "fp32", 4, None)
+    prm, lv = _params(levels, 0, 0, metric, precision, rerank_factor, None)
     alloc = _TorchAllocator(data.device.index or 0) if torch_allocator else None
     h = ctypes.c_void_p()
     _check(lib().mask_import(ctypes.byref(m), L, _levels_array(levels), pp, qq,

@@ -68,6 +68,7 @@ int bits_for(int64_t n) {
 }
 
 int round_up4(int d) { return (d + 3) & ~3; }
+int bf16_stride(int ld) { return (ld + 7) & ~7; }
 
 // split() of Algorithm 1: n_chunks contiguous groups whose sizes differ by at
 // most one, the larger ones first.
@@ -173,6 +174,18 @@ void finalize_layout(mask_index& ix, const std::vector<int32_t*>& labels,
     }
   }
   (void)dim;
+  if (ix.precision == MASK_BF16) {
+    // BF16 copies of every level in position order, and the data row -> leaf
+    // position map used by the FP32 re-rank
+    ix.ldb = bf16_stride(ld);
+    for (int l = 0; l <= L; ++l) {
+      ix.protos_b[l] = ix.mem.alloc<uint16_t>(ix.level_n[l] * ix.ldb);
+      quantize_bf16(ix.protos[l], ld, ix.level_n[l], ix.protos_b[l], ix.ldb, nullptr, s);
+    }
+    ix.inv0 = ix.mem.alloc<int32_t>(ix.level_n[0]);
+    scatter_iota(reinterpret_cast<const uint32_t*>(ix.orig[0]), ix.level_n[0],
+                 reinterpret_cast<uint32_t*>(ix.inv0), s);
+  }
 }
 
 struct BuildState {
@@ -183,12 +196,20 @@ struct BuildState {
 // Lloyd at one level: `items` (n_items x ld, chunk-contiguous) -> prototypes
 // (chunk-major) and the final labels.  inertia_log: device [iters * C] or null.
 void run_level(const float* items, int64_t n_items, int ld, int dim, int C, int k, int iters,
-               int metric, const float* init, float* protos, int32_t* labels,
+               int metric, int precision, const float* init, float* protos, int32_t* labels,
                double* inertia_log, Arena& scratch, hipStream_t s, int64_t* refined) {
   ChunkPlan plan;
   make_plan(plan, n_items, C, k, scratch, s);
   KmeansWork w;
   kmeans_alloc(w, n_items, C, k, scratch);
+  if (precision == MASK_BF16 && metric == MASK_L2) {
+    w.precision = MASK_BF16;
+    w.ldb = bf16_stride(ld);
+    w.items_b = scratch.alloc<uint16_t>(n_items * w.ldb);
+    w.protos_b = scratch.alloc<uint16_t>((int64_t)C * k * w.ldb);
+    w.proto_norms_b = scratch.alloc<float>((int64_t)C * k);
+    quantize_bf16(items, ld, n_items, w.items_b, w.ldb, nullptr, s);
+  }
   row_norms(items, ld, n_items, w.item_norms, s);
   if (init) copy_rows(init, ld, (int64_t)C * k, ld, protos, ld, s);
   else kmeans_init_first(items, ld, plan, protos, s);
@@ -212,9 +233,14 @@ DescentArgs descent_args(const mask_index& ix) {
   a.n_levels = ix.n_levels;
   a.dim = ix.dim;
   a.ld = ix.ld;
+  a.ldb = ix.ldb;
   a.metric = ix.metric;
+  a.precision = ix.precision;
+  a.rerank_factor = ix.rerank_factor;
+  a.inv0 = ix.inv0;
   for (int l = 0; l <= ix.n_levels; ++l) {
     a.lv[l].protos = ix.protos[l];
+    a.lv[l].protos_b = ix.protos_b[l];
     a.lv[l].orig = ix.orig[l];
     a.lv[l].inv = ix.inv[l];
     a.lv[l].child_off = ix.child_off[l];
@@ -224,19 +250,32 @@ DescentArgs descent_args(const mask_index& ix) {
 }
 
 mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
+                       const int32_t* k_arr, const int32_t* r_arr, const int64_t* out_off,
                        int32_t* out_ids, float* out_dist, int32_t* sel, void* hip_stream) {
   try {
     MASK_CHECK(ix != nullptr, "index is NULL");
     check_dense(q, "queries");
     MASK_CHECK(q->dim == ix->dim, "query dim differs from the index dim");
-    MASK_CHECK(k >= 1 && k <= kMaxBeam, "k must be in [1, 512]");
-    MASK_CHECK(r >= 1 && r <= kMaxBeam, "r must be in [1, 512]");
+    MASK_CHECK(k >= 1 && k <= kMaxBeam, "k must be in [1, 2048]");
+    MASK_CHECK(r >= 1 && r <= kMaxBeam, "r must be in [1, 2048]");
     MASK_CHECK(q->n < ((int64_t)1 << 31), "too many queries in one call");
     if (q->n == 0) return MASK_OK;
     MASK_CHECK(out_ids && out_dist, "output pointer is NULL");
     hipStream_t s = (hipStream_t)hip_stream;
-    descent(descent_args(*ix), q->x, ld_of(q), q->n, k, r, out_ids, out_dist, sel,
-            timing_row_counter(), s);
+    QueryArgs qa{};
+    qa.Q = q->x;
+    qa.ldq = ld_of(q);
+    qa.nq = q->n;
+    qa.k = k;
+    qa.r = r;
+    qa.k_arr = k_arr;
+    qa.r_arr = r_arr;
+    qa.out_off = out_off;
+    qa.out_ids = out_ids;
+    qa.out_dist = out_dist;
+    qa.sel = sel;
+    qa.rows = timing_row_counter();
+    descent(descent_args(*ix), qa, s);
     return MASK_OK;
   } catch (const Error& e) {
     return fail(e);
@@ -339,7 +378,9 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
     std::vector<int64_t> sizes;
     check_levels(data->n, p->n_levels, p->levels, sizes);
     if (data->dim > kMaxDenseDim) throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};
-    if (p->precision != MASK_FP32) throw Error{MASK_ERR_UNSUPPORTED, "precision form"};
+    if (p->precision == MASK_FP8_E4M3) throw Error{MASK_ERR_UNSUPPORTED, "FP8 form"};
+    if (p->precision == MASK_BF16 && p->metric != MASK_L2)
+      throw Error{MASK_ERR_UNSUPPORTED, "BF16 form of L1"};
 
     auto ix = std::make_unique<mask_index>(a, s);
     const int L = p->n_levels;
@@ -351,6 +392,7 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
     ix->n_levels = L;
     ix->levels.assign(p->levels, p->levels + L);
     ix->level_n = sizes;
+    ix->rerank_factor = p->rerank_factor > 0 ? p->rerank_factor : 4;
     const int ld = ix->ld;
     const int64_t n = data->n;
 
@@ -379,8 +421,8 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
       st.protos_cm[l] = scratch.alloc<float>(sizes[l] * ld);
       st.labels[l] = scratch.alloc<int32_t>(n_items);
       Arena level_scratch(a, s);
-      run_level(items, n_items, ld, data->dim, C, k, p->lloyd_iters, p->metric, nullptr,
-                st.protos_cm[l], st.labels[l], nullptr, level_scratch, s,
+      run_level(items, n_items, ld, data->dim, C, k, p->lloyd_iters, p->metric, p->precision,
+                nullptr, st.protos_cm[l], st.labels[l], nullptr, level_scratch, s,
                 l == 1 ? &ix->refined_last : nullptr);
       MASK_HIP(hipStreamSynchronize(s));
     }
@@ -400,7 +442,20 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
 
 mask_status mask_query(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
                        int32_t* out_ids, float* out_dist, void* hip_stream) {
-  return query_impl(ix, q, k, r, out_ids, out_dist, nullptr, hip_stream);
+  return query_impl(ix, q, k, r, nullptr, nullptr, nullptr, out_ids, out_dist, nullptr,
+                    hip_stream);
+}
+
+mask_status mask_query_ragged(const mask_index* ix, const mask_matrix* q, const int32_t* k_i,
+                              const int32_t* r_i, const int64_t* out_off, int32_t k_max,
+                              int32_t r_max, int32_t* out_ids, float* out_dist,
+                              void* hip_stream) {
+  if (!k_i || !r_i || !out_off) {
+    set_error("k_i, r_i and out_off are required");
+    return MASK_ERR_INVALID;
+  }
+  return query_impl(ix, q, k_max, r_max, k_i, r_i, out_off, out_ids, out_dist, nullptr,
+                    hip_stream);
 }
 
 mask_status mask_query_debug(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
@@ -410,7 +465,7 @@ mask_status mask_query_debug(const mask_index* ix, const mask_matrix* q, int32_t
     set_error("sel is NULL");
     return MASK_ERR_INVALID;
   }
-  return query_impl(ix, q, k, r, out_ids, out_dist, sel, hip_stream);
+  return query_impl(ix, q, k, r, nullptr, nullptr, nullptr, out_ids, out_dist, sel, hip_stream);
 }
 
 mask_status mask_free(mask_index* ix) {
@@ -496,6 +551,8 @@ mask_status mask_import(const mask_matrix* data, int32_t n_levels, const mask_le
     ix->ld = round_up4(data->dim);
     ix->metric = metric;
     ix->precision = p ? p->precision : MASK_FP32;
+    MASK_CHECK(ix->precision == MASK_FP32 || ix->precision == MASK_BF16, "unsupported precision");
+    ix->rerank_factor = (p && p->rerank_factor > 0) ? p->rerank_factor : 4;
     ix->n_levels = L;
     ix->levels.assign(levels, levels + L);
     ix->level_n = sizes;
@@ -558,8 +615,8 @@ mask_status mask_kmeans(const mask_matrix* items, int32_t n_chunks, int32_t k, i
       init_p = scratch.alloc<float>(np * ld);
       copy_rows(init, dim, np, dim, init_p, ld, s);
     }
-    run_level(x, n, ld, dim, n_chunks, k, iters, metric, init_p, P, labels, inertia, scratch, s,
-              nullptr);
+    run_level(x, n, ld, dim, n_chunks, k, iters, metric, MASK_FP32, init_p, P, labels, inertia,
+              scratch, s, nullptr);
     copy_rows(P, ld, np, dim, centroids, dim, s);
     MASK_HIP(hipStreamSynchronize(s));
     return MASK_OK;

@@ -18,7 +18,8 @@ constexpr int kWave = 64;
 constexpr int kMaxLevels = 16;
 constexpr int kMaxDenseDim = 256;   // MFMA assignment keeps point rows in registers
 constexpr int kMaxQueryDim = 4096;  // the descent stages one query row in LDS
-constexpr int kMaxBeam = 512;       // r and k limit of one descent workgroup
+constexpr int kMaxBeam = 2048;      // r and k limit of one descent workgroup
+constexpr int kMaxRerank = 2048;    // largest FP32 re-rank set of the BF16 form
 
 // ------------------------------------------------------------------ errors
 
@@ -233,7 +234,18 @@ struct KmeansWork {
   float* item_norms = nullptr;
   float* proto_norms = nullptr;
   double* proto_norms64 = nullptr;
+  // BF16 form: rounded copies of the items and prototypes (row stride ldb)
+  int precision = MASK_FP32;
+  int ldb = 0;
+  uint16_t* items_b = nullptr;
+  uint16_t* protos_b = nullptr;
+  float* proto_norms_b = nullptr;
 };
+
+// out[i*ldb + c] = bf16(x[i*ld + c]) (round to nearest even), zero padding;
+// norms[i] = FP32 squared norm of the rounded row when norms is not null.
+void quantize_bf16(const float* x, int ld, int64_t n, uint16_t* out, int ldb, float* norms,
+                   hipStream_t s);
 
 void kmeans_alloc(KmeansWork& w, int64_t n_items, int n_chunks, int k, Arena& scratch);
 
@@ -260,6 +272,7 @@ void kmeans_init_first(const float* items, int ld, const ChunkPlan& plan, float*
 
 struct LevelView {
   const float* protos;       // n x ld, position order
+  const uint16_t* protos_b;  // n x ldb BF16 copy (BF16 form), position order
   const int32_t* orig;       // position -> chunk-major id (data row id at level 0)
   const int32_t* inv;        // chunk-major id -> position (levels >= 1)
   const uint32_t* child_off; // n + 1 offsets into the level below (levels >= 1)
@@ -268,15 +281,31 @@ struct LevelView {
 
 struct DescentArgs {
   LevelView lv[kMaxLevels + 1];  // lv[0] = data (leaf order), lv[l] = level l
+  const int32_t* inv0;           // data row id -> leaf position (BF16 re-rank)
   int n_levels;
   int dim;
   int ld;
+  int ldb;
   int metric;
+  int precision;
+  int rerank_factor;
 };
 
-void descent(const DescentArgs& a, const float* q, int ldq, int64_t nq, int k, int r,
-             int32_t* out_ids, float* out_dist, int32_t* sel, unsigned long long* rows,
-             hipStream_t s);
+struct QueryArgs {
+  const float* Q;
+  int ldq;
+  int64_t nq;
+  int k, r;                 // uniform values, or the maxima when k_arr / r_arr are set
+  const int32_t* k_arr;     // per-query k (device) or null
+  const int32_t* r_arr;     // per-query r (device) or null
+  const int64_t* out_off;   // per-query output offset (device) or null: qi * k
+  int32_t* out_ids;
+  float* out_dist;
+  int32_t* sel;
+  unsigned long long* rows;
+};
+
+void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
 
 }  // namespace mask
 
@@ -293,6 +322,10 @@ struct mask_index {
   std::vector<int64_t> level_n;  // level_n[0] = n, level_n[l] = prototypes at level l
   // device arrays; index 0 = data in leaf order
   float* protos[mask::kMaxLevels + 1] = {};
+  uint16_t* protos_b[mask::kMaxLevels + 1] = {};  // BF16 copies (BF16 form)
+  int ldb = 0;
+  int rerank_factor = 4;
+  int32_t* inv0 = nullptr;  // data row id -> leaf position (BF16 form)
   int32_t* orig[mask::kMaxLevels + 1] = {};
   int32_t* inv[mask::kMaxLevels + 1] = {};
   uint32_t* child_off[mask::kMaxLevels + 1] = {};

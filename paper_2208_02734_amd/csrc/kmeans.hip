@@ -657,6 +657,171 @@ __global__ __launch_bounds__(kBlock) void k_chunk_inertia(const double* __restri
   if (lane == 0) out[c] = acc;
 }
 
+// ------------------------------------------------------------- BF16 form
+// Round-to-nearest-even of FP32 to BF16 bits (inputs are finite).
+__device__ inline uint16_t bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// out[i*ldb + c] = bf16(x[i*ld + c]) for c < ld, zero up to ldb; norms[i] =
+// squared norm of the rounded row (FP32, fixed order) when norms != null.
+__global__ void k_quantize_bf16(const float* __restrict__ x, int ld, int64_t n,
+                                uint16_t* __restrict__ out, int ldb, float* __restrict__ norms) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.f;
+  for (int c = 0; c < ldb; ++c) {
+    const uint16_t b = c < ld ? bf16_rne(x[i * ld + c]) : (uint16_t)0;
+    out[i * ldb + c] = b;
+    const float v = bf16_to_f32(b);
+    acc = fmaf(v, v, acc);
+  }
+  if (norms) norms[i] = acc;
+}
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+__device__ inline bf16x8_t as_bf16x8(uint4 v) {
+  bf16x8_t r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  return r;
+}
+
+// BF16 screening on v_mfma_f32_32x32x16_bf16 (FP32 accumulate): s_ij =
+// x~_i . c~_j - |c~_j|^2 / 2 on the BF16-rounded rows, no certification.
+// Layout as the FP32 kernel (prototypes = rows, points = columns); MFMA
+// k-slot (s, h, e) is dimension 16s + 8h + e, so every lane feeds 8
+// consecutive BF16 of a row (one 16-byte load).  The running best per lane
+// is updated from the tile maximum (max3 chains), so the epilogue stays
+// short next to the MFMA work at small d.
+template <int DP, int PB, int TN, int MINB>
+__global__ __launch_bounds__(kBlock, MINB) void k_assign_bf16(
+    const uint16_t* __restrict__ items, int ldb, const uint16_t* __restrict__ protos,
+    const float* __restrict__ pnorm, const int64_t* __restrict__ chunk_off, int k,
+    int tiles_per_chunk, int32_t* __restrict__ labels) {
+  constexpr int KS = DP / 16;
+  constexpr int LDW = DP + 8;  // BF16 elements per LDS row (16-byte pad)
+  constexpr int BM = 4 * 32 * PB;
+  constexpr int V_PER_ROW = DP / 8;  // 16-byte vectors per row
+  constexpr int LOADS = TN * V_PER_ROW / kBlock;
+  static_assert(LOADS * kBlock == TN * V_PER_ROW, "tile must split evenly over the block");
+  __shared__ uint4 s_c4[2][TN * LDW / 8];
+  __shared__ float s_hn[2][TN];
+
+  const unsigned lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int chunk = (int)(lb / (unsigned)tiles_per_chunk);
+  const int tile = (int)(lb % (unsigned)tiles_per_chunk);
+  const int64_t c0 = chunk_off[chunk], c1 = chunk_off[chunk + 1];
+  const int64_t pbase = c0 + (int64_t)tile * BM;
+  if (pbase >= c1) return;
+
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int h = lane >> 5, col = lane & 31;
+  bf16x8_t bf[PB][KS];
+  int64_t pidx[PB];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb) {
+    const int64_t p = pbase + (wave * PB + pb) * 32 + col;
+    pidx[pb] = p;
+    const bool ok = p < c1;
+    const uint16_t* row = items + (ok ? p : c0) * (int64_t)ldb;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int c = 16 * s + 8 * h;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (ok && c < ldb) v = *reinterpret_cast<const uint4*>(row + c);
+      bf[pb][s] = as_bf16x8(v);
+    }
+  }
+  const uint16_t* cbase = protos + (int64_t)chunk * k * ldb;
+  const float* nbase = pnorm + (int64_t)chunk * k;
+  const int ntiles = (k + TN - 1) / TN;
+  uint4 stage[LOADS];
+  float hstage = INFINITY;
+  auto load_tile = [&](int t) {
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int idx = threadIdx.x + i * kBlock;
+      const int row = idx / V_PER_ROW, v8 = idx % V_PER_ROW;
+      const int j = t * TN + row;
+      stage[i] = (j < k && v8 * 8 < ldb)
+                     ? *reinterpret_cast<const uint4*>(cbase + (int64_t)j * ldb + v8 * 8)
+                     : make_uint4(0, 0, 0, 0);
+    }
+    if (threadIdx.x < TN) {
+      const int j = t * TN + threadIdx.x;
+      hstage = (j < k) ? 0.5f * nbase[j] : INFINITY;
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LOADS; ++i) {
+      const int idx = threadIdx.x + i * kBlock;
+      const int row = idx / V_PER_ROW, v8 = idx % V_PER_ROW;
+      s_c4[buf][(row * LDW) / 8 + v8] = stage[i];
+    }
+    if (threadIdx.x < TN) s_hn[buf][threadIdx.x] = hstage;
+  };
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+
+  float b1[PB];
+  int i1[PB];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb) { b1[pb] = -INFINITY; i1[pb] = 0; }
+
+  for (int t = 0; t < ntiles; ++t) {
+    const int buf = t & 1;
+    if (t + 1 < ntiles) load_tile(t + 1);
+#pragma unroll
+    for (int cb = 0; cb < TN / 32; ++cb) {
+      floatx16 acc[PB];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const float hv = s_hn[buf][cb * 32 + 8 * (i >> 2) + 4 * h + (i & 3)];
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb) acc[pb][i] = -hv;
+      }
+      const uint4* arow = &s_c4[buf][((cb * 32 + col) * LDW + 8 * h) / 8];
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const bf16x8_t a = as_bf16x8(arow[2 * s]);  // dims 16s + 8h .. +7
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb)
+          acc[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bf[pb][s], acc[pb], 0, 0, 0);
+      }
+      const int jbase = t * TN + cb * 32 + 4 * h;
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) {
+        float m = fmaxf(fmaxf(acc[pb][0], acc[pb][1]), acc[pb][2]);
+#pragma unroll
+        for (int i = 3; i < 15; i += 2) m = fmaxf(fmaxf(m, acc[pb][i]), acc[pb][i + 1]);
+        m = fmaxf(m, acc[pb][15]);
+        if (m > b1[pb]) {
+          // first register holding the maximum: lowest prototype index
+          int ii = 15;
+#pragma unroll
+          for (int i = 14; i >= 0; --i) ii = (acc[pb][i] == m) ? i : ii;
+          b1[pb] = m;
+          i1[pb] = jbase + 8 * (ii >> 2) + (ii & 3);
+        }
+      }
+    }
+    if (t + 1 < ntiles) store_tile(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb) {
+    const float o = __shfl_xor(b1[pb], 32);
+    const int oi = __shfl_xor(i1[pb], 32);
+    if (o > b1[pb] || (o == b1[pb] && oi < i1[pb])) { b1[pb] = o; i1[pb] = oi; }
+    if (h == 0 && pidx[pb] < c1) labels[pidx[pb]] = chunk * k + i1[pb];
+  }
+}
+
 // Direct-form assignment on the vector units, for metrics without an MFMA
 // form (L1) and for wide rows: one wave per 64 items of one group, item rows
 // staged in LDS with an odd row stride (conflict-free per-lane reads), every
@@ -854,6 +1019,16 @@ void launch_full_f64(const float* items, int ld, const ChunkPlan& plan, const fl
                                            w.partial_j);
 }
 
+template <int DP, int PB, int TN, int MINB>
+void launch_assign_bf16(const ChunkPlan& plan, int32_t* labels, KmeansWork& w, hipStream_t s) {
+  constexpr int BM = 4 * 32 * PB;
+  const int tiles = (int)((plan.max_chunk + BM - 1) / BM);
+  ScopedTiming timing("assign_bf16_mfma", s);
+  k_assign_bf16<DP, PB, TN, MINB><<<(unsigned)(tiles * plan.n_chunks), kBlock, 0, s>>>(
+      w.items_b, w.ldb, w.protos_b, w.proto_norms_b, plan.d_off, plan.k, tiles, labels);
+  check_launch("assign_bf16_mfma");
+}
+
 void launch_refine(const float* items, int ld, const ChunkPlan& plan, const float* protos,
                    int32_t* labels, KmeansWork& w, int metric, hipStream_t s) {
   unsigned long long* stats = timing_refine_counter();
@@ -930,9 +1105,30 @@ void kmeans_init_first(const float* items, int ld, const ChunkPlan& plan, float*
   check_launch("init_first");
 }
 
+void quantize_bf16(const float* x, int ld, int64_t n, uint16_t* out, int ldb, float* norms,
+                   hipStream_t s) {
+  if (n <= 0) return;
+  k_quantize_bf16<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, ld, n, out, ldb, norms);
+  check_launch("quantize_bf16");
+}
+
 void kmeans_assign(const float* items, int ld, int dim, const ChunkPlan& plan,
                    const float* protos, int32_t* labels, KmeansWork& w, int metric,
                    hipStream_t s) {
+  if (w.precision == MASK_BF16 && metric == MASK_L2) {
+    // re-quantise the current prototypes, then screen in BF16
+    quantize_bf16(protos, ld, (int64_t)plan.n_chunks * plan.k, w.protos_b, w.ldb,
+                  w.proto_norms_b, s);
+    const int dp = (w.ldb + 15) & ~15;
+    if (dp <= 16) launch_assign_bf16<16, 4, 128, 2>(plan, labels, w, s);
+    else if (dp <= 32) launch_assign_bf16<32, 4, 64, 2>(plan, labels, w, s);
+    else if (dp <= 64) launch_assign_bf16<64, 2, 64, 2>(plan, labels, w, s);
+    else if (dp <= 96) launch_assign_bf16<96, 2, 64, 2>(plan, labels, w, s);
+    else if (dp <= 128) launch_assign_bf16<128, 2, 64, 2>(plan, labels, w, s);
+    else if (dp <= 256) launch_assign_bf16<256, 1, 64, 2>(plan, labels, w, s);
+    else throw Error{MASK_ERR_UNSUPPORTED, "BF16 dimension above 256"};
+    return;
+  }
   if (metric == MASK_L1 || dim > kMaxDenseDim) {
     const int tiles = (int)((plan.max_chunk + 63) / 64);
     const size_t shm = (size_t)64 * (ld + 1) * sizeof(float);

@@ -1,5 +1,10 @@
 // Multilevel descent of Algorithm 2 with a beam of r prototypes per level.
 //
+// Precision form (BF16): every level's rows are read as BF16 (half the
+// bytes) and ranked with FP32 arithmetic against the FP32 query; at the data
+// layer the rerank_factor * k * r nearest by BF16 distance are re-ranked in
+// FP32 direct form on the FP32 rows, and the k nearest of those are returned.
+//
 // One workgroup (256 threads) runs the whole descent of one query, so a
 // query's result never depends on the rest of the batch.  At each level the
 // candidates are the children of the prototypes kept one level up (the top
@@ -20,7 +25,6 @@ namespace mask {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kCap = 2560;  // LDS key buffer; kCap - kMaxBeam >= 2048 new keys per round
 
 struct SelShared {
   uint64_t kmin, kmax, thr;
@@ -143,29 +147,53 @@ __device__ void block_select(uint64_t* buf, uint32_t m, uint32_t want, uint64_t*
 
 // TPR lanes per candidate row; NV float4 of the row per lane (0: any number,
 // looped); U rows in flight per lane group.
-template <int TPR, int NV, int U, int METRIC>
-__global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* __restrict__ Q,
-                                                    int ldq, int64_t nq, int k, int r,
-                                                    int32_t* __restrict__ out_ids,
-                                                    float* __restrict__ out_dist,
-                                                    int32_t* __restrict__ sel_out,
-                                                    unsigned long long* __restrict__ rows_out) {
+
+template <int NV, int TPR>
+struct QFrag {
+  float4 v[NV > 0 ? NV : 1][2];
+};
+
+__device__ inline float4 bf16_lo4(uint2 w) {
+  return make_float4(__uint_as_float(w.x << 16), __uint_as_float(w.x & 0xffff0000u),
+                     __uint_as_float(w.y << 16), __uint_as_float(w.y & 0xffff0000u));
+}
+
+template <int METRIC>
+__device__ inline float acc4(float s, float4 x, float4 q) {
+  const float dx = x.x - q.x, dy = x.y - q.y, dz = x.z - q.z, dw = x.w - q.w;
+  if (METRIC == 0) {
+    s = fmaf(dx, dx, s); s = fmaf(dy, dy, s); s = fmaf(dz, dz, s); s = fmaf(dw, dw, s);
+  } else {
+    s += fabsf(dx) + fabsf(dy) + fabsf(dz) + fabsf(dw);
+  }
+  return s;
+}
+
+// Descent of one query per workgroup.
+//   TPR lanes per candidate row, NV 16-byte vectors of the row per lane
+//   (0: any number, looped), U rows in flight per lane group; B16: rows are
+//   BF16; CAPB: largest beam / k / re-rank set; CAP: LDS key buffer.
+template <int TPR, int NV, int U, int METRIC, bool B16, int CAPB, int CAP>
+__global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa) {
   extern __shared__ float4 s_q4[];  // ld/4 float4
-  __shared__ uint64_t s_buf[kCap];
-  __shared__ uint64_t s_out[kMaxBeam];
-  __shared__ int32_t s_par[kMaxBeam];       // kept positions one level up
-  __shared__ uint32_t s_beg[kMaxBeam];      // first child position of each
-  __shared__ uint32_t s_pre[kMaxBeam + 1];  // prefix of child counts
+  __shared__ uint64_t s_buf[CAP];
+  __shared__ uint64_t s_out[CAPB];
+  __shared__ int32_t s_par[CAPB];       // kept positions one level up
+  __shared__ uint32_t s_beg[CAPB];      // first child position of each
+  __shared__ uint32_t s_pre[CAPB + 1];  // prefix of child counts
   __shared__ uint32_t s_hist[256];
   __shared__ uint64_t s_red[8];
   __shared__ SelShared sh;
 
   const int64_t qi = blockIdx.x;
-  if (qi >= nq) return;
+  if (qi >= qa.nq) return;
   const int tid = threadIdx.x, lane = tid % kWave;
-  const int ld = a.ld, ld4 = ld / 4;
+  const int ld = a.ld, ld4 = ld / 4, ldb = a.ldb;
+  const int k = qa.k_arr ? min(max(qa.k_arr[qi], 1), qa.k) : qa.k;
+  const int r = qa.r_arr ? min(max(qa.r_arr[qi], 1), qa.r) : qa.r;
+  const int64_t obase = qa.out_off ? qa.out_off[qi] : qi * (int64_t)qa.k;
   float* s_q = reinterpret_cast<float*>(s_q4);
-  for (int c = tid; c < ld; c += kBlock) s_q[c] = (c < a.dim) ? Q[qi * ldq + c] : 0.f;
+  for (int c = tid; c < ld; c += kBlock) s_q[c] = (c < a.dim) ? qa.Q[qi * qa.ldq + c] : 0.f;
 
   const int L = a.n_levels;
   int n_par = 1;
@@ -175,11 +203,19 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* 
   const int grp = tid / TPR, gl = tid % TPR;
   constexpr int kGroups = kBlock / TPR;
   constexpr int NQ = NV > 0 ? NV : 1;
-  float4 qv[NQ];
+  // query fragment: FP32 rows use 4 dims per vector, BF16 rows 8
+  float4 qv[NQ][2];
 #pragma unroll
   for (int v = 0; v < NQ; ++v) {
-    const int c4 = gl + v * TPR;
-    qv[v] = (NV > 0 && c4 < ld4) ? s_q4[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int c = gl + v * TPR;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (B16) {
+      qv[v][0] = (NV > 0 && 2 * c < ld4) ? s_q4[2 * c] : z;
+      qv[v][1] = (NV > 0 && 2 * c + 1 < ld4) ? s_q4[2 * c + 1] : z;
+    } else {
+      qv[v][0] = (NV > 0 && c < ld4) ? s_q4[c] : z;
+      qv[v][1] = z;
+    }
   }
   unsigned long long rows_seen = 0;
 
@@ -187,15 +223,26 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* 
     const LevelView V = a.lv[lev];
     const uint32_t m = s_pre[n_par];
     rows_seen += m;
-    const uint32_t want = (lev == 0) ? (uint32_t)k : (uint32_t)r;
-    const uint32_t round = kCap - want;
+    // the data layer of the BF16 form keeps an oversized set for the FP32 re-rank
+    uint32_t want = (lev == 0) ? (uint32_t)k : (uint32_t)r;
+    bool low = B16;  // rows read in BF16 at this level
+    bool rerank = false;
+    if (lev == 0 && B16) {
+      const int64_t R = min((int64_t)a.rerank_factor * k * r, (int64_t)CAPB);
+      if ((int64_t)m > R && R > k) {
+        want = (uint32_t)R;
+        rerank = true;
+      } else {
+        low = false;
+      }
+    }
+    const uint32_t round = CAP - want;
     if (tid == 0) { sh.cnt = 0; sh.thr = ~0ull; }
     __syncthreads();
     uint64_t thr = ~0ull;
     for (uint32_t base = 0; base < m; base += round) {
       const uint32_t end = (m - base < round) ? m : base + round;
       for (uint32_t i0 = base + grp * U; i0 < end; i0 += kGroups * U) {
-        // parent of i0: the last j with s_pre[j] <= i0; later rows walk forward
         int lo = 0, hi = n_par - 1;
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
@@ -211,13 +258,51 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* 
           pos[u] = (int64_t)s_beg[lo] + (idx - s_pre[lo]);
         }
         float acc[U];
-        if constexpr (NV > 0) {
-          float4 x[U][NV];
+        if (B16 && low) {
+          const int nb = ldb / 8;
+          if constexpr (NV > 0) {
+            uint4 x[U][NV];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const uint4* row = reinterpret_cast<const uint4*>(V.protos_b + (val[u] ? pos[u] : 0) * ldb);
+#pragma unroll
+              for (int v = 0; v < NV; ++v) {
+                const int c = gl + v * TPR;
+                x[u][v] = (val[u] && c < nb) ? row[c] : make_uint4(0, 0, 0, 0);
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              float s0 = 0.f;
+#pragma unroll
+              for (int v = 0; v < NV; ++v) {
+                s0 = acc4<METRIC>(s0, bf16_lo4(make_uint2(x[u][v].x, x[u][v].y)), qv[v][0]);
+                s0 = acc4<METRIC>(s0, bf16_lo4(make_uint2(x[u][v].z, x[u][v].w)), qv[v][1]);
+              }
+              acc[u] = s0;
+            }
+          } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const uint4* row = reinterpret_cast<const uint4*>(V.protos_b + (val[u] ? pos[u] : 0) * ldb);
+              float s0 = 0.f;
+              for (int c = gl; c < nb; c += TPR) {
+                const uint4 xv = val[u] ? row[c] : make_uint4(0, 0, 0, 0);
+                const float4 q0 = 2 * c < ld4 ? s_q4[2 * c] : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float4 q1 = 2 * c + 1 < ld4 ? s_q4[2 * c + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+                s0 = acc4<METRIC>(s0, bf16_lo4(make_uint2(xv.x, xv.y)), q0);
+                s0 = acc4<METRIC>(s0, bf16_lo4(make_uint2(xv.z, xv.w)), q1);
+              }
+              acc[u] = s0;
+            }
+          }
+        } else if (!B16 && NV > 0) {
+          float4 x[U][NQ];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const float4* row = reinterpret_cast<const float4*>(V.protos + (val[u] ? pos[u] : 0) * ld);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
+            for (int v = 0; v < NQ; ++v) {
               const int c4 = gl + v * TPR;
               x[u][v] = (val[u] && c4 < ld4) ? row[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
@@ -226,34 +311,18 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* 
           for (int u = 0; u < U; ++u) {
             float s0 = 0.f;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-              const float dx = x[u][v].x - qv[v].x, dy = x[u][v].y - qv[v].y,
-                          dz = x[u][v].z - qv[v].z, dw = x[u][v].w - qv[v].w;
-              if (METRIC == 0) {
-                s0 = fmaf(dx, dx, s0); s0 = fmaf(dy, dy, s0);
-                s0 = fmaf(dz, dz, s0); s0 = fmaf(dw, dw, s0);
-              } else {
-                s0 += fabsf(dx) + fabsf(dy) + fabsf(dz) + fabsf(dw);
-              }
-            }
+            for (int v = 0; v < NQ; ++v) s0 = acc4<METRIC>(s0, x[u][v], qv[v][0]);
             acc[u] = s0;
           }
         } else {
+          // FP32 rows, any width (also the data layer of the BF16 form when
+          // the re-rank set would hold every candidate)
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const float4* row = reinterpret_cast<const float4*>(V.protos + (val[u] ? pos[u] : 0) * ld);
             float s0 = 0.f;
-            for (int c4 = gl; c4 < ld4; c4 += TPR) {
-              const float4 xv = val[u] ? row[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
-              const float4 q = s_q4[c4];
-              const float dx = xv.x - q.x, dy = xv.y - q.y, dz = xv.z - q.z, dw = xv.w - q.w;
-              if (METRIC == 0) {
-                s0 = fmaf(dx, dx, s0); s0 = fmaf(dy, dy, s0);
-                s0 = fmaf(dz, dz, s0); s0 = fmaf(dw, dw, s0);
-              } else {
-                s0 += fabsf(dx) + fabsf(dy) + fabsf(dz) + fabsf(dw);
-              }
-            }
+            for (int c4 = gl; c4 < ld4; c4 += TPR)
+              s0 = acc4<METRIC>(s0, val[u] ? row[c4] : make_float4(0.f, 0.f, 0.f, 0.f), s_q4[c4]);
             acc[u] = s0;
           }
         }
@@ -270,13 +339,13 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* 
             const uint64_t key = ((uint64_t)__float_as_uint(acc[u]) << 32) | id;
             if (key < thr) {
               const uint32_t slot = atomicAdd(&sh.cnt, 1u);
-              if (slot < (uint32_t)kCap) s_buf[slot] = key;  // rounds keep slot < kCap
+              if (slot < (uint32_t)CAP) s_buf[slot] = key;  // rounds keep slot < CAP
             }
           }
         }
       }
       __syncthreads();
-      const uint32_t cnt = sh.cnt < (uint32_t)kCap ? sh.cnt : (uint32_t)kCap;
+      const uint32_t cnt = sh.cnt < (uint32_t)CAP ? sh.cnt : (uint32_t)CAP;
       if (cnt > want) {
         block_select(s_buf, cnt, want, s_out, s_hist, sh, s_red);
         if (tid == 0) sh.cnt = want;
@@ -284,24 +353,22 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* 
         thr = sh.thr;
       }
     }
-    const uint32_t kept = sh.cnt < want ? sh.cnt : want;
+    uint32_t kept = sh.cnt < want ? sh.cnt : want;
     if (lev > 0) {
-      // next level's parents: positions of the kept prototypes
       for (uint32_t j = tid; j < kept; j += kBlock) {
         const uint32_t id = (uint32_t)s_buf[j];
         const int32_t pos = V.inv[id];
         s_par[j] = pos;
         s_beg[j] = V.child_off[pos];
       }
-      if (sel_out) {
-        int32_t* so = sel_out + ((int64_t)qi * L + (L - lev)) * r;
-        for (int j = tid; j < r; j += kBlock)
+      if (qa.sel) {
+        int32_t* so = qa.sel + ((int64_t)qi * L + (L - lev)) * qa.r;
+        for (int j = tid; j < qa.r; j += kBlock)
           so[j] = (uint32_t)j < kept ? (int32_t)(uint32_t)s_buf[j] : -1;
       }
       __syncthreads();
       if (tid < kWave) {
-        // exclusive prefix of child counts, kMaxBeam / 64 = 8 per lane
-        constexpr int P = kMaxBeam / kWave;
+        constexpr int P = CAPB / kWave;
         uint32_t c[P], s = 0;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
@@ -328,12 +395,31 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* 
       n_par = (int)kept;
       __syncthreads();
       if (n_par == 0) {
-        if (tid == 0) s_pre[0] = 0;
         n_par = 1;  // one empty range
-        if (tid == 0) { s_beg[0] = 0; s_pre[1] = 0; }
+        if (tid == 0) { s_beg[0] = 0; s_pre[0] = 0; s_pre[1] = 0; }
         __syncthreads();
       }
     } else {
+      if (B16 && rerank) {
+        // FP32 direct form on the FP32 rows of the kept set, then the k nearest
+        for (uint32_t j = grp; j < kept; j += kGroups) {
+          const uint32_t id = (uint32_t)s_buf[j];
+          const int64_t pos = a.inv0[id];
+          const float4* row = reinterpret_cast<const float4*>(V.protos + pos * ld);
+          float s0 = 0.f;
+          for (int c4 = gl; c4 < ld4; c4 += TPR) s0 = acc4<METRIC>(s0, row[c4], s_q4[c4]);
+#pragma unroll
+          for (int o = TPR / 2; o >= 1; o >>= 1) s0 += __shfl_xor(s0, o);
+          if (gl == 0) s_out[j] = ((uint64_t)__float_as_uint(s0) << 32) | id;
+        }
+        __syncthreads();
+        for (uint32_t j = tid; j < kept; j += kBlock) s_buf[j] = s_out[j];
+        __syncthreads();
+        if (kept > (uint32_t)k) {
+          block_select(s_buf, kept, (uint32_t)k, s_out, s_hist, sh, s_red);
+          kept = k;
+        }
+      }
       // rank the kept keys and write the result row
       for (uint32_t j = tid; j < kept; j += kBlock) {
         const uint64_t v = s_buf[j];
@@ -351,45 +437,61 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, const float* 
           const float d2 = __uint_as_float((uint32_t)(v >> 32));
           dist = METRIC == 0 ? sqrtf(d2) : d2;
         }
-        out_ids[qi * k + j] = id;
-        out_dist[qi * k + j] = dist;
+        qa.out_ids[obase + j] = id;
+        qa.out_dist[obase + j] = dist;
       }
     }
   }
-  if (rows_out && tid == 0) atomicAdd(rows_out, rows_seen);
+  if (qa.rows && tid == 0) atomicAdd(qa.rows, rows_seen);
 }
 
-template <int TPR, int NV, int U>
-void launch_descent(const DescentArgs& a, const float* q, int ldq, int64_t nq, int k, int r,
-                    int32_t* out_ids, float* out_dist, int32_t* sel, unsigned long long* rows,
-                    hipStream_t s) {
+template <int TPR, int NV, int U, bool B16, int CAPB, int CAP>
+void launch3(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   const size_t shm = (size_t)a.ld * sizeof(float);
-  ScopedTiming timing("descent", s);
   if (a.metric == MASK_L2)
-    k_descent<TPR, NV, U, 0><<<(unsigned)nq, kBlock, shm, s>>>(a, q, ldq, nq, k, r, out_ids,
-                                                              out_dist, sel, rows);
+    k_descent<TPR, NV, U, 0, B16, CAPB, CAP><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
   else
-    k_descent<TPR, NV, U, 1><<<(unsigned)nq, kBlock, shm, s>>>(a, q, ldq, nq, k, r, out_ids,
-                                                              out_dist, sel, rows);
-  check_launch("descent");
+    k_descent<TPR, NV, U, 1, B16, CAPB, CAP><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
+}
+
+template <int TPR, int NV, int U, bool B16>
+void launch2(const DescentArgs& a, const QueryArgs& qa, int need, hipStream_t s) {
+  if (need <= 512) launch3<TPR, NV, U, B16, 512, 2560>(a, qa, s);
+  else launch3<TPR, NV, U, B16, 2048, 4096>(a, qa, s);
 }
 
 }  // namespace
 
-void descent(const DescentArgs& a, const float* q, int ldq, int64_t nq, int k, int r,
-             int32_t* out_ids, float* out_dist, int32_t* sel, unsigned long long* rows,
-             hipStream_t s) {
-  if (nq <= 0) return;
-  const int f4 = a.ld / 4;
-  if (f4 <= 1) launch_descent<1, 1, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else if (f4 <= 2) launch_descent<2, 1, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else if (f4 <= 4) launch_descent<4, 1, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else if (f4 <= 8) launch_descent<8, 1, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else if (f4 <= 16) launch_descent<16, 1, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else if (f4 <= 32) launch_descent<16, 2, 4>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else if (f4 <= 64) launch_descent<16, 4, 2>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else if (f4 <= 128) launch_descent<16, 8, 1>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
-  else launch_descent<16, 0, 1>(a, q, ldq, nq, k, r, out_ids, out_dist, sel, rows, s);
+void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
+  if (qa.nq <= 0) return;
+  ScopedTiming timing(a.precision == MASK_BF16 ? "descent_bf16" : "descent", s);
+  const bool b16 = a.precision == MASK_BF16;
+  int need = qa.k > qa.r ? qa.k : qa.r;
+  if (b16) {
+    const int64_t R = (int64_t)a.rerank_factor * qa.k * qa.r;
+    if (R > need) need = (int)(R < kMaxRerank ? R : kMaxRerank);
+  }
+  if (!b16) {
+    const int f4 = a.ld / 4;
+    if (f4 <= 1) launch2<1, 1, 4, false>(a, qa, need, s);
+    else if (f4 <= 2) launch2<2, 1, 4, false>(a, qa, need, s);
+    else if (f4 <= 4) launch2<4, 1, 4, false>(a, qa, need, s);
+    else if (f4 <= 8) launch2<8, 1, 4, false>(a, qa, need, s);
+    else if (f4 <= 16) launch2<16, 1, 4, false>(a, qa, need, s);
+    else if (f4 <= 32) launch2<16, 2, 4, false>(a, qa, need, s);
+    else if (f4 <= 64) launch2<16, 4, 2, false>(a, qa, need, s);
+    else launch2<16, 0, 1, false>(a, qa, need, s);
+  } else {
+    const int c8 = a.ldb / 8;
+    if (c8 <= 1) launch2<1, 1, 4, true>(a, qa, need, s);
+    else if (c8 <= 2) launch2<2, 1, 4, true>(a, qa, need, s);
+    else if (c8 <= 4) launch2<4, 1, 4, true>(a, qa, need, s);
+    else if (c8 <= 8) launch2<8, 1, 4, true>(a, qa, need, s);
+    else if (c8 <= 16) launch2<16, 1, 4, true>(a, qa, need, s);
+    else if (c8 <= 32) launch2<16, 2, 4, true>(a, qa, need, s);
+    else launch2<16, 0, 1, true>(a, qa, need, s);
+  }
+  check_launch("descent");
 }
 
 }  // namespace mask

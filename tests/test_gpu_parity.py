@@ -265,7 +265,7 @@ def test_empty_query_batch_and_bad_arguments(pk):
     with pytest.raises(pk.MaskError):
         pk.mask_query(gix, torch.zeros((3, 4), device="cuda"), 0, 2)
     with pytest.raises(pk.MaskError):
-        pk.mask_query(gix, torch.zeros((3, 4), device="cuda"), 5, 513)
+        pk.mask_query(gix, torch.zeros((3, 4), device="cuda"), 5, 2049)
 
 
 def test_single_level_index(pk):

@@ -1,0 +1,121 @@
+"""The precision form (BF16 distances, FP32 re-rank, FP64 sums) and ragged
+batches.  BF16 screening is not certified, so its build is pinned
+statistically against the FP64 oracle (label agreement, inertia ratio);
+the FP32 re-rank makes every returned distance exact to the FP32 tolerance,
+and re-ranking every candidate reproduces exhaustive search."""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import compare as oc
+from oracle import mask_oracle as mo
+from tests.gpu_helpers import dev, host, oracle_index_from_gpu
+
+pytestmark = pytest.mark.gpu
+REL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2208_02734_amd as pk
+    pk.lib()
+    return pk
+
+
+def _mixture(n, d, n_comp, seed, nq=0):
+    mix = datagen.mixture_params(seed, n_comp, d, sigma_mode="loguniform", sigma_low=0.1,
+                                 sigma_high=3.0)
+    X = datagen.sample_mixture(mix, n, seed + 1)
+    Q = datagen.sample_mixture(mix, nq, seed + 2) if nq else None
+    return X, Q
+
+
+def _nearest_agreement(X, gix, chunks, k):
+    """Fraction of level-1 labels equal to the FP64 nearest prototype of the
+    item's group (exported prototypes), and the worst relative excess."""
+    P, par = gix.export_level(1)
+    agree, worst = 0, 0.0
+    for c in range(chunks):
+        members = np.nonzero(par // k == c)[0]
+        D = mo.pairwise(X[members], P[c * k:(c + 1) * k])
+        got = D[np.arange(members.size), par[members] - c * k]
+        best = D.min(axis=1)
+        agree += int(np.sum(got <= best * (1 + 1e-12)))
+        worst = max(worst, float(np.max((got - best) / np.maximum(best, 1e-30))))
+    return agree / X.shape[0], worst
+
+
+@pytest.mark.parametrize("d", [96, 128])
+def test_bf16_build_labels_are_nearly_nearest(pk, d):
+    X, _ = _mixture(30_000, d, 60, seed=200 + d)
+    levels = [(6, 200), (1, 40)]
+    g16 = pk.mask_build(dev(X), levels, iters=10, seed=1, precision="bf16")
+    frac, worst = _nearest_agreement(X, g16, 6, 200)
+    # BF16 rounding of |x|, |c| ~ 10^2 moves a distance by ~1e-2 absolute
+    assert frac > 0.97, frac
+    assert worst < 0.05, worst
+    # inertia of the BF16 build within 1% of the FP32 build's
+    g32 = pk.mask_build(dev(X), levels, iters=10, seed=1)
+
+    def inertia(ix):
+        P, par = ix.export_level(1)
+        return float(((X.astype(np.float64) - P[par]) ** 2).sum())
+    assert inertia(g16) <= inertia(g32) * 1.01
+
+
+def test_bf16_query_distances_are_fp32_exact(pk):
+    X, Q = _mixture(20_000, 96, 50, seed=210, nq=100)
+    levels = [(10, 100), (1, 40)]
+    gix = pk.mask_build(dev(X), levels, iters=8, seed=2, precision="bf16", rerank_factor=4)
+    for r in (4, 16):
+        ids, dist = pk.mask_query(gix, dev(Q), 10, r)
+        ids, dist = host(ids).astype(np.int64), host(dist)
+        true = oc.true_distances(X, Q, ids)
+        v = ids >= 0
+        assert np.all(np.abs(dist[v] - true[v]) <= REL * true[v])
+        assert np.all(dist[:, 1:] >= dist[:, :-1])
+
+
+def test_bf16_rerank_of_everything_is_exact(pk):
+    # probe every prototype and re-rank all candidates: exhaustive search
+    X, Q = _mixture(4000, 32, 20, seed=220, nq=50)
+    levels = [(4, 50), (1, 20)]
+    oix = mo.build(X, levels, 5, seed=3)
+    gix = pk.mask_import(dev(X), levels, oix.protos, oix.parents, precision="bf16",
+                         rerank_factor=1000)
+    ids, dist = pk.mask_query(gix, dev(Q), 10, 2048)
+    tids, tdist = mo.exact_knn(X, Q, 10)
+    true = oc.true_distances(X, Q, host(ids).astype(np.int64))
+    assert oc.check_knn(host(ids), host(dist), tids, tdist, true, REL).ok
+
+
+def test_bf16_recall_close_to_fp32_on_shared_index(pk):
+    X, Q = _mixture(30_000, 64, 80, seed=230, nq=200)
+    levels = [(10, 300), (1, 60)]
+    oix = mo.build(X, levels, 6, seed=4)
+    g32 = pk.mask_import(dev(X), levels, oix.protos, oix.parents)
+    g16 = pk.mask_import(dev(X), levels, oix.protos, oix.parents, precision="bf16")
+    tids, tdist = mo.exact_knn(X, Q, 10)
+    rec = {}
+    for name, ix in (("fp32", g32), ("bf16", g16)):
+        ids, _ = pk.mask_query(ix, dev(Q), 10, 8)
+        ids = host(ids).astype(np.int64)
+        rec[name] = oc.recall_at_k(ids, tids, tdist, oc.true_distances(X, Q, ids), 10)
+    assert rec["bf16"] >= rec["fp32"] - 0.02, rec
+
+
+def test_ragged_rows_equal_single_queries(pk):
+    import torch
+    X, Q = _mixture(10_000, 48, 40, seed=240, nq=60)
+    gix = pk.mask_build(dev(X), [(5, 100), (1, 25)], iters=6, seed=5)
+    g = np.random.default_rng(9)
+    ks = g.integers(1, 40, size=60).astype(np.int32)
+    rs = g.choice([2, 8, 20], size=60).astype(np.int32)
+    ids, dist, off = pk.mask_query_ragged(gix, dev(Q), torch.from_numpy(ks), torch.from_numpy(rs))
+    ids, dist, off = host(ids), host(dist), host(off)
+    for i in range(60):
+        i1, d1 = pk.mask_query(gix, dev(Q[i:i + 1]), int(ks[i]), int(rs[i]))
+        assert np.array_equal(ids[off[i]:off[i + 1]], host(i1)[0])
+        assert np.array_equal(dist[off[i]:off[i + 1]], host(d1)[0])
