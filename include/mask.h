@@ -144,13 +144,20 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
  * row ids), out_dist: device float32[q->n * k], rows ascending; slots beyond
  * the candidate count hold id -1 and +inf.  1 <= k <= 2048, 1 <= r <= 2048.
  * Precision form (index built with MASK_BF16): rows are compared in BF16 and
- * the data layer's min(rerank_factor * k * r, 2048) nearest by BF16 distance
- * are re-ranked in FP32 direct form on the FP32 rows (all candidates in FP32
- * when they are no more than that).
+ * the data layer's R = min(rerank_factor * k * r, max(512, k, r)) nearest by
+ * BF16 distance are re-ranked in FP32 direct form on the FP32 rows (all
+ * candidates in FP32 when they are no more than R).
  * Asynchronous on hip_stream; allocates nothing.  Each query's result does
  * not depend on the other queries of the batch. */
 mask_status mask_query(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
                        int32_t* out_ids, float* out_dist, void* hip_stream);
+
+/* mask_query with a beam per level: r_levels (host int32[n_levels], top
+ * level first) gives the number of prototypes kept at each level, each in
+ * [1, 2048].  The uniform-beam descent is r_levels = {r, ..., r}. */
+mask_status mask_query_beams(const mask_index* ix, const mask_matrix* q, int32_t k,
+                             const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                             void* hip_stream);
 
 /* Ragged batch: query i uses k_i[i] and r_i[i] (device int32[q->n], each in
  * [1, k_max] / [1, r_max]) and writes its k_i[i] results at out_ids +

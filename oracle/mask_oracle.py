@@ -323,11 +323,13 @@ def query_one(index: OracleIndex, q: np.ndarray, k: int, r: int,
     L = index.n_levels
     q = np.asarray(q, dtype=np.float64)[None, :]
     kids = [index.children(l) for l in range(L)]
+    # r: one beam for every level, or one per level from the top level down
+    beams = [int(r)] * L if np.isscalar(r) else [int(x) for x in r]
     cand = np.arange(index.protos[L - 1].shape[0], dtype=np.int64)
     tr = QueryTrace([], [], [])
     for l in range(L - 1, -1, -1):
         d = pairwise(q, index.protos[l][cand], metric)[0]
-        sel = cand[smallest(d, cand, r)]
+        sel = cand[smallest(d, cand, beams[L - 1 - l])]
         if forced is not None:
             sel = np.asarray(forced[L - 1 - l], dtype=np.int64)
         if trace:

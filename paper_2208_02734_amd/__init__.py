@@ -69,7 +69,7 @@ class mask_allocator(ctypes.Structure):
 
 _lib = None
 
-EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_ragged",
+EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_beams", "mask_query_ragged",
             "mask_query_debug", "mask_free",
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
             "mask_last_error", "mask_timing_enable", "mask_timing_report"]
@@ -90,6 +90,7 @@ def lib() -> ctypes.CDLL:
     L.mask_query.argtypes = [VP, P(mask_matrix), I32, I32, VP, VP, VP]
     L.mask_query_debug.argtypes = [VP, P(mask_matrix), I32, I32, VP, VP, VP, VP]
     L.mask_query_ragged.argtypes = [VP, P(mask_matrix), VP, VP, VP, I32, I32, VP, VP, VP]
+    L.mask_query_beams.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP]
     L.mask_free.argtypes = [VP]
     L.mask_index_info.argtypes = [VP, P(mask_info)]
     L.mask_export_level.argtypes = [VP, I32, VP, VP]
@@ -265,6 +266,20 @@ def mask_query(index: Index, queries, k: int, r: int, stream=None, debug: bool =
         return ids, dist, sel
     _check(lib().mask_query(index.handle, ctypes.byref(m), k, r, ids.data_ptr(),
                             dist.data_ptr(), _stream_handle(stream)))
+    return ids, dist
+
+
+def mask_query_beams(index: Index, queries, k: int, beams: Sequence[int], stream=None):
+    """Descent keeping beams[i] prototypes at level i counted from the top;
+    returns (ids, dist) like mask_query."""
+    torch = _torch()
+    m = _dense(queries)
+    nq = queries.shape[0]
+    b = (ctypes.c_int32 * len(beams))(*[int(x) for x in beams])
+    ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    _check(lib().mask_query_beams(index.handle, ctypes.byref(m), k, b, ids.data_ptr(),
+                                  dist.data_ptr(), _stream_handle(stream)))
     return ids, dist
 
 

@@ -160,6 +160,15 @@ void finalize_layout(mask_index& ix, const std::vector<int32_t*>& labels,
     radix_sort_u32(keys, ord, n_items, bits_for(n_par), sw, s);
     ix.child_off[l] = ix.mem.alloc<uint32_t>(n_par + 1);
     offsets_from_sorted(keys, n_items, n_par, ix.child_off[l], s);
+    {
+      std::vector<uint32_t> off(n_par + 1);
+      MASK_HIP(hipMemcpyAsync(off.data(), ix.child_off[l], (n_par + 1) * sizeof(uint32_t),
+                              hipMemcpyDeviceToHost, s));
+      MASK_HIP(hipStreamSynchronize(s));
+      int64_t mx = 0;
+      for (int64_t p = 0; p < n_par; ++p) mx = std::max<int64_t>(mx, off[p + 1] - off[p]);
+      ix.max_children[l] = mx;
+    }
     ix.protos[l - 1] = ix.mem.alloc<float>(n_items * ld);
     ix.orig[l - 1] = ix.mem.alloc<int32_t>(n_items);
     if (l - 1 >= 1) {
@@ -238,6 +247,7 @@ DescentArgs descent_args(const mask_index& ix) {
   a.precision = ix.precision;
   a.rerank_factor = ix.rerank_factor;
   a.inv0 = ix.inv0;
+  a.max_leaf_children = ix.max_children[1];
   for (int l = 0; l <= ix.n_levels; ++l) {
     a.lv[l].protos = ix.protos[l];
     a.lv[l].protos_b = ix.protos_b[l];
@@ -251,7 +261,8 @@ DescentArgs descent_args(const mask_index& ix) {
 
 mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
                        const int32_t* k_arr, const int32_t* r_arr, const int64_t* out_off,
-                       int32_t* out_ids, float* out_dist, int32_t* sel, void* hip_stream) {
+                       int32_t* out_ids, float* out_dist, int32_t* sel, void* hip_stream,
+                       const int32_t* r_levels = nullptr) {
   try {
     MASK_CHECK(ix != nullptr, "index is NULL");
     check_dense(q, "queries");
@@ -275,6 +286,14 @@ mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, in
     qa.out_dist = out_dist;
     qa.sel = sel;
     qa.rows = timing_row_counter();
+    for (int l = 0; l <= kMaxLevels; ++l) qa.r_lev[l] = 0;
+    if (r_levels) {
+      MASK_CHECK(!sel, "per-level beams are not combined with the debug selections");
+      for (int d = 0; d < ix->n_levels; ++d) {
+        MASK_CHECK(r_levels[d] >= 1 && r_levels[d] <= kMaxBeam, "beam must be in [1, 2048]");
+        qa.r_lev[ix->n_levels - d] = r_levels[d];
+      }
+    }
     descent(descent_args(*ix), qa, s);
     return MASK_OK;
   } catch (const Error& e) {
@@ -444,6 +463,20 @@ mask_status mask_query(const mask_index* ix, const mask_matrix* q, int32_t k, in
                        int32_t* out_ids, float* out_dist, void* hip_stream) {
   return query_impl(ix, q, k, r, nullptr, nullptr, nullptr, out_ids, out_dist, nullptr,
                     hip_stream);
+}
+
+mask_status mask_query_beams(const mask_index* ix, const mask_matrix* q, int32_t k,
+                             const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                             void* hip_stream) {
+  if (!r_levels) {
+    set_error("r_levels is NULL");
+    return MASK_ERR_INVALID;
+  }
+  int32_t rmax = 1;
+  if (ix)
+    for (int d = 0; d < ix->n_levels; ++d) rmax = r_levels[d] > rmax ? r_levels[d] : rmax;
+  return query_impl(ix, q, k, rmax, nullptr, nullptr, nullptr, out_ids, out_dist, nullptr,
+                    hip_stream, r_levels);
 }
 
 mask_status mask_query_ragged(const mask_index* ix, const mask_matrix* q, const int32_t* k_i,

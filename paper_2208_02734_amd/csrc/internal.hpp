@@ -289,6 +289,7 @@ struct DescentArgs {
   int metric;
   int precision;
   int rerank_factor;
+  int64_t max_leaf_children;  // largest child count of a level-1 prototype
 };
 
 struct QueryArgs {
@@ -296,6 +297,7 @@ struct QueryArgs {
   int ldq;
   int64_t nq;
   int k, r;                 // uniform values, or the maxima when k_arr / r_arr are set
+  int r_lev[kMaxLevels + 1];  // beam per level (index = level), 0 = use r
   const int32_t* k_arr;     // per-query k (device) or null
   const int32_t* r_arr;     // per-query r (device) or null
   const int64_t* out_off;   // per-query output offset (device) or null: qi * k
@@ -326,6 +328,7 @@ struct mask_index {
   int ldb = 0;
   int rerank_factor = 4;
   int32_t* inv0 = nullptr;  // data row id -> leaf position (BF16 form)
+  int64_t max_children[mask::kMaxLevels + 1] = {};  // per level, largest child count
   int32_t* orig[mask::kMaxLevels + 1] = {};
   int32_t* inv[mask::kMaxLevels + 1] = {};
   uint32_t* child_off[mask::kMaxLevels + 1] = {};

@@ -50,7 +50,10 @@ __device__ inline uint64_t wave_max_u64(uint64_t v) {
 
 // Keeps the `want` smallest of buf[0..m) in buf[0..want) (any order) and
 // sets sh.thr to the largest kept key.  Keys must be distinct.  Called by
-// every thread of the block; m > want >= 1.
+// every thread of the block; m > want >= 1.  Most-significant-digit radix
+// select over the bits below the keys' common prefix, 8 bits per pass; the
+// digit histograms are double-buffered and every wave scans the histogram
+// itself, so a pass costs one barrier.  hist: 2 * 256 counters.
 __device__ void block_select(uint64_t* buf, uint32_t m, uint32_t want, uint64_t* out,
                              uint32_t* hist, SelShared& sh, uint64_t* red) {
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
@@ -63,69 +66,71 @@ __device__ void block_select(uint64_t* buf, uint32_t m, uint32_t want, uint64_t*
   lo = wave_min_u64(lo);
   hi = wave_max_u64(hi);
   if (lane == 0) { red[wave] = lo; red[4 + wave] = hi; }
+  for (uint32_t i = tid; i < 256; i += kBlock) hist[i] = 0;
+  if (tid == 0) { sh.n_out = 0; sh.thr = 0; }
   __syncthreads();
-  if (tid == 0) {
-    uint64_t a = red[0], b = red[4];
-    for (int w = 1; w < 4; ++w) {
-      a = red[w] < a ? red[w] : a;
-      b = red[4 + w] > b ? red[4 + w] : b;
-    }
-    sh.kmin = a;
-    sh.kmax = b;
-    sh.n_out = 0;
-    sh.thr = 0;
+  uint64_t kmin = red[0], kmax = red[4];
+#pragma unroll
+  for (int w = 1; w < 4; ++w) {
+    kmin = red[w] < kmin ? red[w] : kmin;
+    kmax = red[4 + w] > kmax ? red[4 + w] : kmax;
   }
-  __syncthreads();
-  const uint64_t diff = sh.kmin ^ sh.kmax;  // non-zero: keys are distinct and m >= 2
-  int top = 64 - __clzll((long long)diff);  // bits [top, 64) are common to all keys
-  uint64_t prefix = (top >= 64) ? 0ull : (sh.kmin >> top) << top;
+  const uint64_t diff = kmin ^ kmax;  // non-zero: keys are distinct and m >= 2
+  const int top = 64 - __clzll((long long)diff);  // bits [top, 64) are common to all keys
+  uint64_t prefix = (top >= 64) ? 0ull : (kmin >> top) << top;
   uint32_t need = want;
   int shift = top;
+  int pass = 0;
   for (;;) {
     const int w = shift < 8 ? shift : 8;
-    const int hi_bit = shift;  // bits >= hi_bit must equal prefix
+    const int hi_bit = shift;  // bits >= hi_bit equal the prefix
     shift -= w;
     const uint32_t nb = 1u << w;
-    for (uint32_t i = tid; i < nb; i += kBlock) hist[i] = 0;
-    __syncthreads();
+    uint32_t* h = hist + (pass & 1) * 256;
+    uint32_t* h_next = hist + ((pass + 1) & 1) * 256;
     for (uint32_t i = tid; i < m; i += kBlock) {
       const uint64_t v = buf[i];
       const bool match = (hi_bit >= 64) || (((v ^ prefix) >> hi_bit) == 0);
-      if (match) atomicAdd(&hist[(uint32_t)(v >> shift) & (nb - 1)], 1u);
+      if (match) atomicAdd(&h[(uint32_t)(v >> shift) & (nb - 1)], 1u);
     }
     __syncthreads();
-    if (wave == 0) {
-      // inclusive scan of nb <= 256 bins, 4 per lane
-      uint32_t c[4], s = 0;
+    // every wave finds the bin holding the need-th key: 4 bins per lane
+    uint32_t c[4], sum = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t b = lane * 4 + j;
-        c[j] = b < nb ? hist[b] : 0u;
-        s += c[j];
-      }
-      uint32_t x = s;
-#pragma unroll
-      for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-      }
-      uint32_t run = x - s;  // exclusive prefix of this lane's 4 bins
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t b = lane * 4 + j;
-        if (b < nb && run < need && run + c[j] >= need) {
-          sh.bin = b;
-          sh.below = run;
-          sh.bin_cnt = c[j];
-        }
-        run += c[j];
-      }
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t b = lane * 4 + j;
+      c[j] = b < nb ? h[b] : 0u;
+      sum += c[j];
     }
-    __syncthreads();
-    const uint32_t b = sh.bin, below = sh.below, bin_cnt = sh.bin_cnt;
+    uint32_t x = sum;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    uint32_t run = x - sum;
+    uint32_t found = 0;  // (bin + 1) on the lane that holds it
+    uint32_t f_below = 0, f_cnt = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t b = lane * 4 + j;
+      if (b < nb && run < need && run + c[j] >= need) {
+        found = b + 1;
+        f_below = run;
+        f_cnt = c[j];
+      }
+      run += c[j];
+    }
+    const uint64_t fm = __ballot(found != 0);
+    const int src = __ffsll((long long)fm) - 1;
+    const uint32_t b = __shfl(found, src) - 1;
+    const uint32_t below = __shfl(f_below, src);
+    const uint32_t bin_cnt = __shfl(f_cnt, src);
+    // the other buffer is free: every wave finished reading it last pass
+    for (uint32_t i = tid; i < 256; i += kBlock) h_next[i] = 0;
     need -= below;
     prefix |= (uint64_t)b << shift;
-    __syncthreads();
+    ++pass;
     if (bin_cnt == need || shift == 0) break;
   }
   // Kept: every key whose bits at and above `shift` do not exceed the prefix.
@@ -144,9 +149,6 @@ __device__ void block_select(uint64_t* buf, uint32_t m, uint32_t want, uint64_t*
   for (uint32_t i = tid; i < want; i += kBlock) buf[i] = out[i];
   __syncthreads();
 }
-
-// TPR lanes per candidate row; NV float4 of the row per lane (0: any number,
-// looped); U rows in flight per lane group.
 
 template <int NV, int TPR>
 struct QFrag {
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
   __shared__ int32_t s_par[CAPB];       // kept positions one level up
   __shared__ uint32_t s_beg[CAPB];      // first child position of each
   __shared__ uint32_t s_pre[CAPB + 1];  // prefix of child counts
-  __shared__ uint32_t s_hist[256];
+  __shared__ uint32_t s_hist[2 * 256];
   __shared__ uint64_t s_red[8];
   __shared__ SelShared sh;
 
@@ -224,11 +226,13 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
     const uint32_t m = s_pre[n_par];
     rows_seen += m;
     // the data layer of the BF16 form keeps an oversized set for the FP32 re-rank
-    uint32_t want = (lev == 0) ? (uint32_t)k : (uint32_t)r;
+    uint32_t want = (lev == 0) ? (uint32_t)k : (uint32_t)(qa.r_lev[lev] > 0 ? qa.r_lev[lev] : r);
     bool low = B16;  // rows read in BF16 at this level
     bool rerank = false;
     if (lev == 0 && B16) {
-      const int64_t R = min((int64_t)a.rerank_factor * k * r, (int64_t)CAPB);
+      // the re-rank set: rerank_factor * k * r candidates, at most CAPB
+      const int r1 = qa.r_lev[1] > 0 ? qa.r_lev[1] : r;
+      const int64_t R = min((int64_t)a.rerank_factor * k * r1, (int64_t)CAPB);
       if ((int64_t)m > R && R > k) {
         want = (uint32_t)R;
         rerank = true;
@@ -236,28 +240,44 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
         low = false;
       }
     }
+    // The first round is short (2 * want keys, at least 256): its exact
+    // selection sets the threshold cheaply; later rounds append only keys
+    // below the threshold and fill the buffer before the next selection.
     const uint32_t round = CAP - want;
+    const uint32_t first = min(round, max(2 * want, 256u));
     if (tid == 0) { sh.cnt = 0; sh.thr = ~0ull; }
     __syncthreads();
     uint64_t thr = ~0ull;
-    for (uint32_t base = 0; base < m; base += round) {
-      const uint32_t end = (m - base < round) ? m : base + round;
-      for (uint32_t i0 = base + grp * U; i0 < end; i0 += kGroups * U) {
-        int lo = 0, hi = n_par - 1;
+    for (uint32_t base = 0; base < m;) {
+      const uint32_t len = (base == 0) ? first : round;
+      const uint32_t end = (m - base < len) ? m : base + len;
+      // Each lane group takes a contiguous chunk of kChunk candidates: one
+      // binary search over the parents' prefix per chunk, then a forward walk.
+      // chunk = ceil(rows / groups) rounded up to U, between U and 8U
+      const uint32_t per = (end - base + kGroups - 1) / kGroups;
+      const uint32_t kChunk = min((uint32_t)(8 * U), max((uint32_t)U, (per + U - 1) / U * U));
+      for (uint32_t c0 = base + grp * kChunk; c0 < end; c0 += kGroups * kChunk) {
+      const uint32_t c1 = min(end, c0 + kChunk);
+      int lo = 0;
+      {
+        int hi = n_par - 1;
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
-          if (s_pre[mid] <= i0) lo = mid; else hi = mid - 1;
+          if (s_pre[mid] <= c0) lo = mid; else hi = mid - 1;
         }
+      }
+      for (uint32_t i0 = c0; i0 < c1; i0 += U) {
         int64_t pos[U];
         bool val[U];
+        uint32_t ids[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const uint32_t idx = i0 + u;
-          val[u] = idx < end;
+          val[u] = idx < c1;
           while (val[u] && lo + 1 < n_par && s_pre[lo + 1] <= idx) ++lo;
           pos[u] = (int64_t)s_beg[lo] + (idx - s_pre[lo]);
-        }
-        float acc[U];
+          ids[u] = (gl == 0 && val[u]) ? (uint32_t)V.orig[pos[u]] : 0u;  // issued with the row loads
+        }        float acc[U];
         if (B16 && low) {
           const int nb = ldb / 8;
           if constexpr (NV > 0) {
@@ -335,14 +355,14 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             if (!val[u]) continue;
-            const uint32_t id = (uint32_t)V.orig[pos[u]];
-            const uint64_t key = ((uint64_t)__float_as_uint(acc[u]) << 32) | id;
+            const uint64_t key = ((uint64_t)__float_as_uint(acc[u]) << 32) | ids[u];
             if (key < thr) {
               const uint32_t slot = atomicAdd(&sh.cnt, 1u);
               if (slot < (uint32_t)CAP) s_buf[slot] = key;  // rounds keep slot < CAP
             }
           }
         }
+      }
       }
       __syncthreads();
       const uint32_t cnt = sh.cnt < (uint32_t)CAP ? sh.cnt : (uint32_t)CAP;
@@ -352,6 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
         __syncthreads();
         thr = sh.thr;
       }
+      base = end;
     }
     uint32_t kept = sh.cnt < want ? sh.cnt : want;
     if (lev > 0) {
@@ -466,11 +487,9 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   if (qa.nq <= 0) return;
   ScopedTiming timing(a.precision == MASK_BF16 ? "descent_bf16" : "descent", s);
   const bool b16 = a.precision == MASK_BF16;
+  // LDS class from the beams and k; the BF16 re-rank set fits the class
   int need = qa.k > qa.r ? qa.k : qa.r;
-  if (b16) {
-    const int64_t R = (int64_t)a.rerank_factor * qa.k * qa.r;
-    if (R > need) need = (int)(R < kMaxRerank ? R : kMaxRerank);
-  }
+  for (int l = 1; l <= a.n_levels; ++l) need = qa.r_lev[l] > need ? qa.r_lev[l] : need;
   if (!b16) {
     const int f4 = a.ld / 4;
     if (f4 <= 1) launch2<1, 1, 4, false>(a, qa, need, s);

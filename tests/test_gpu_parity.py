@@ -358,3 +358,24 @@ def test_l1_query_matches_oracle(pk):
     tids, tdist = mo.exact_knn(X, Q, 10, metric="l1")
     true = oc.true_distances(X, Q, host(ids).astype(np.int64), "l1")
     assert oc.check_knn(host(ids), host(dist), tids, tdist, true, REL).ok
+
+
+def test_per_level_beams(pk):
+    X, Q = _mixture(8000, 40, 40, seed=151, nq=80)
+    gix = pk.mask_build(dev(X), [(8, 80), (1, 64), (1, 8)], iters=6, seed=6)
+    # uniform beams are the uniform descent, bit for bit
+    i1, d1 = pk.mask_query(gix, dev(Q), 10, 6)
+    i2, d2 = pk.mask_query_beams(gix, dev(Q), 10, [6, 6, 6])
+    assert np.array_equal(host(i1), host(i2)) and np.array_equal(host(d1), host(d2))
+    # a narrowing beam against the oracle's descent with the same beams
+    oix = oracle_index_from_gpu(X, gix)
+    beams = [2, 5, 12]
+    ids, dist = pk.mask_query_beams(gix, dev(Q), 10, beams)
+    ids, dist = host(ids).astype(np.int64), host(dist)
+    o_ids = np.empty_like(ids)
+    o_dist = np.empty(dist.shape)
+    for i in range(Q.shape[0]):
+        o_ids[i], o_dist[i] = mo.query_one(oix, Q[i], 10, beams)
+    true = oc.true_distances(X, Q, ids)
+    res = oc.check_knn(ids, dist, o_ids, o_dist, true, REL)
+    assert res.ok, res.messages
