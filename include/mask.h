@@ -214,6 +214,57 @@ mask_status mask_kmeans(const mask_matrix* items, int32_t n_chunks, int32_t k, i
 
 const char* mask_last_error(void);
 
+/* ------------------------------------------------------------- serving ---
+ * A request loop against a resident index (the serving form): requests are
+ * queued by mask_server_submit; a scheduler thread admits them in arrival
+ * order into ragged batches while they fit a batch-size limit and a free
+ * block of the device arena (memory admission), and keeps up to n_streams
+ * batches in flight, so requests arriving while others run join the next
+ * batch as soon as a stream and arena space are free (continuous batching).
+ * Each query's result equals mask_query's for it alone with the same k, r. */
+typedef struct mask_server mask_server;
+
+typedef struct {
+  int64_t arena_bytes;       /* device memory for in-flight batches (>= 4096) */
+  int32_t max_batch_queries; /* largest number of queries in one batch */
+  int32_t n_streams;         /* batches in flight at once, 1..16 */
+} mask_server_params;
+
+typedef struct {
+  int64_t submitted_requests, submitted_queries;
+  int64_t completed_requests, completed_queries;
+  int64_t batches, batched_queries;
+  int64_t peak_arena_bytes, arena_used_bytes;
+  int64_t queued_requests, inflight_batches;
+} mask_server_stats;
+
+/* Seconds on the steady clock the server stamps completions with; callers
+ * give arrival times on the same clock, so latency = t_done - t_arrival. */
+double mask_clock(void);
+
+/* The index must outlive the server.  The arena comes from the allocator
+ * (NULL: hipMalloc); staging memory of the same size is pinned host memory. */
+mask_status mask_server_create(const mask_index* ix, const mask_server_params* p,
+                               const mask_allocator* a, mask_server** out);
+
+/* Queues n_q query rows (host, n_q x dim, copied before return) with k and r
+ * and the caller's arrival time.  MASK_ERR_BUSY when the request could never
+ * fit the arena or the batch limit; MASK_ERR_SHUTDOWN during destroy. */
+mask_status mask_server_submit(mask_server* s, const float* q_host, int32_t n_q, int32_t k,
+                               int32_t r, double t_arrival, uint64_t* ticket);
+
+/* *done = 1 when the request has finished: then ids_host (int32[n_q*k]) and
+ * dist_host (float[n_q*k]) receive the rows (either may be NULL), *t_done
+ * the completion time, and the ticket is released.  *done = 0 otherwise. */
+mask_status mask_server_poll(mask_server* s, uint64_t ticket, int32_t* done, int32_t* ids_host,
+                             float* dist_host, double* t_done);
+
+mask_status mask_server_stats_get(mask_server* s, mask_server_stats* out);
+
+/* Serves every queued request, then stops the scheduler and frees the
+ * server.  Requests not polled are dropped. */
+mask_status mask_server_destroy(mask_server* s);
+
 /* Kernel timing for measurement: while enabled, the library's main kernels
  * (assignment, refinement, update, member sort, descent) record HIP events
  * on the stream they are launched on.  Enabling (or disabling) discards what

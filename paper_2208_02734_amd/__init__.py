@@ -67,12 +67,26 @@ class mask_allocator(ctypes.Structure):
     _fields_ = [("ctx", ctypes.c_void_p), ("alloc", _ALLOC_FN), ("free", _FREE_FN)]
 
 
+class mask_server_params(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_int64), ("max_batch_queries", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32)]
+
+
+class mask_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "submitted_requests", "submitted_queries", "completed_requests", "completed_queries",
+        "batches", "batched_queries", "peak_arena_bytes", "arena_used_bytes",
+        "queued_requests", "inflight_batches")]
+
+
 _lib = None
 
 EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_beams", "mask_query_ragged",
             "mask_query_debug", "mask_free",
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
-            "mask_last_error", "mask_timing_enable", "mask_timing_report"]
+            "mask_last_error", "mask_timing_enable", "mask_timing_report", "mask_clock",
+            "mask_server_create", "mask_server_submit", "mask_server_poll",
+            "mask_server_stats_get", "mask_server_destroy"]
 
 
 def lib() -> ctypes.CDLL:
@@ -100,10 +114,18 @@ def lib() -> ctypes.CDLL:
                               P(mask_allocator), VP]
     L.mask_timing_enable.argtypes = [I32]
     L.mask_timing_report.argtypes = [ctypes.c_char_p, I64, P(I64)]
+    L.mask_clock.restype = ctypes.c_double
+    L.mask_clock.argtypes = []
+    L.mask_server_create.argtypes = [VP, P(mask_server_params), P(mask_allocator), P(VP)]
+    L.mask_server_submit.argtypes = [VP, VP, I32, I32, I32, ctypes.c_double,
+                                     P(ctypes.c_uint64)]
+    L.mask_server_poll.argtypes = [VP, ctypes.c_uint64, P(I32), VP, VP, P(ctypes.c_double)]
+    L.mask_server_stats_get.argtypes = [VP, P(mask_server_stats)]
+    L.mask_server_destroy.argtypes = [VP]
     L.mask_last_error.restype = ctypes.c_char_p
     L.mask_last_error.argtypes = []
     for name in EXPORTED:
-        if name != "mask_last_error":
+        if name not in ("mask_last_error", "mask_clock"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -365,3 +387,64 @@ def mask_timing_report() -> dict:
         name, cnt, ms = line.split()
         out[name] = (int(cnt), float(ms))
     return out
+
+
+def mask_clock() -> float:
+    """Seconds on the server's steady clock."""
+    return lib().mask_clock()
+
+
+class MaskServer:
+    """Continuous-batching request loop on a resident index (host queries in,
+    host results out)."""
+
+    def __init__(self, index: Index, arena_bytes: int = 1 << 30, max_batch_queries: int = 65536,
+                 n_streams: int = 2):
+        p = mask_server_params(int(arena_bytes), int(max_batch_queries), int(n_streams))
+        h = ctypes.c_void_p()
+        _check(lib().mask_server_create(index.handle, ctypes.byref(p), None, ctypes.byref(h)))
+        self.handle = h
+        self.index = index
+        self.dim = index.info()["dim"]
+        self._pending = {}
+
+    def submit(self, queries: np.ndarray, k: int, r: int, t_arrival: Optional[float] = None) -> int:
+        q = np.ascontiguousarray(queries, dtype=np.float32)
+        if q.ndim != 2 or q.shape[1] != self.dim:
+            raise MaskError(1, "queries must be n x dim float32")
+        t = mask_clock() if t_arrival is None else float(t_arrival)
+        ticket = ctypes.c_uint64()
+        _check(lib().mask_server_submit(self.handle, q.ctypes.data, q.shape[0], int(k), int(r), t,
+                                        ctypes.byref(ticket)))
+        self._pending[ticket.value] = (q.shape[0], int(k))
+        return ticket.value
+
+    def poll(self, ticket: int):
+        """None while running; (ids (n x k), dist (n x k), t_done) when done."""
+        n, k = self._pending[ticket]
+        ids = np.empty((n, k), dtype=np.int32)
+        dist = np.empty((n, k), dtype=np.float32)
+        done = ctypes.c_int32()
+        t = ctypes.c_double()
+        _check(lib().mask_server_poll(self.handle, ticket, ctypes.byref(done), ids.ctypes.data,
+                                      dist.ctypes.data, ctypes.byref(t)))
+        if not done.value:
+            return None
+        del self._pending[ticket]
+        return ids, dist, t.value
+
+    def stats(self) -> dict:
+        st = mask_server_stats()
+        _check(lib().mask_server_stats_get(self.handle, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in mask_server_stats._fields_}
+
+    def close(self):
+        if self.handle and self.handle.value:
+            lib().mask_server_destroy(self.handle)
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     with open(os.path.join(ROOT, "include", "mask.h")) as f:
         text = f.read()
-    return sorted(set(re.findall(r"^\s*(?:mask_status|const char\*)\s+(mask_\w+)\s*\(", text, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:mask_status|const char\*|double)\s+(mask_\w+)\s*\(", text, re.M)))
 
 
 @pytest.fixture(scope="module")
