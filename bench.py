@@ -2,15 +2,25 @@
 """Benchmark of the MASK hot path on one MI355X.
 
 Workload: 1,000,000 x 128 Gaussian mixture (1,000 components, log-uniform
-sigma in [0.1, 3]), index levels 100 chunks x 1,000 -> 5,000 -> 100, 30
-Lloyd iterations, 10,000 queries, k = 10, beam r (default: the smallest
-r of the sweep that reaches recall@10 >= 0.95 against exhaustive FP64
-search).  A step is one pass of the whole hot path: mask_build on the
-device-resident data, then mask_query of the 10,000 queries.
+sigma in [0.1, 3]); index levels 100 chunks x 1,000 -> 5,000 -> 100; 30
+Lloyd iterations; 10,000 queries; k = 10.  Two forms are built on the same
+data: the plain FP32 form and the precision form (BF16 distances, FP32
+re-rank, FP64 sums).  For each form the cheapest beam configuration
+(prototypes kept per level, from a fixed list ordered by cost) that reaches
+recall@10 >= 0.95 against exhaustive FP64 search (the oracle, on a
+500-query sample) is selected.
 
-Prints one JSON line.  ``value`` is the query throughput (queries/s) of the
-plain FP32 form with the index resident; ``build_s`` is the index build
-time; kernel times come from HIP events recorded on the launch stream.
+A step is one pass of the whole hot path in the faster form: mask_build on
+the device-resident data, then the descent of the 10,000 queries.  ``value``
+is that form's query throughput (queries/s, index resident, median over the
+timed steps); ``build_s`` its median build time.  The serving section runs
+one Poisson request stream (1..512 queries per request, log-uniform; k
+uniform in [1, 100]; r in {8, 32}) through the continuous-batching loop for
+both forms and reports p50/p99 latency (completion minus scheduled arrival)
+and the completed queries/s.  Kernel times come from HIP events the library
+records on its launch stream.
+
+Prints one JSON line.
 """
 import argparse
 import json
@@ -22,8 +32,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3
+PEAK = {"fp32": 157.3, "bf16": 2500.0}  # dense MFMA TFLOP/s
 PEAK_HBM_GBS = 8000.0
+
+# beam candidates (top level first), cheapest first
+BEAMS = [(8, 64, 128), (16, 64, 160), (16, 96, 160), (16, 96, 176), (24, 96, 176),
+         (24, 128, 192), (32, 128, 224), (64, 192, 256), (128, 256, 320), (256, 512, 512)]
 
 
 def parse():
@@ -31,16 +45,66 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--r", type=int, default=128)
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--recall-sample", type=int, default=500)
+    ap.add_argument("--gate", type=float, default=0.95)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-rate", type=float, default=5000.0, help="requests/s")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sweep", type=str, default="",
-                    help="comma-separated r values: report recall and q/s for each")
-    ap.add_argument("--n", type=int, default=None, help="override the number of points")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--form", choices=["auto", "fp32", "bf16"], default="auto")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def serve_stream(pk, ix, pool, rate, seconds, seed):
+    """Open-loop Poisson arrivals through the serving loop of one index."""
+    import numpy as np
+    import datagen
+    rs = datagen.request_stream(rate, seconds, seed, pool.shape[0])
+    srv = pk.MaskServer(ix, arena_bytes=1 << 30, max_batch_queries=32768, n_streams=3)
+    t = srv.submit(pool[:64], 10, 8)  # first launches and staging outside the measurement
+    while srv.poll(t) is None:
+        pass
+    n = rs.t_arrival.shape[0]
+    t0 = pk.mask_clock() + 0.02
+    lat, order = [], []
+    i = q_done = 0
+    t_last = t0
+    while i < n or order:
+        now = pk.mask_clock()
+        while i < n and t0 + rs.t_arrival[i] <= now:
+            off, nq = int(rs.pool_offset[i]), int(rs.n_queries[i])
+            ta = t0 + float(rs.t_arrival[i])
+            order.append((srv.submit(pool[off:off + nq], int(rs.k[i]), int(rs.r[i]),
+                                     t_arrival=ta), ta, nq))
+            i += 1
+        # batches retire in about arrival order: poll the oldest few
+        j = 0
+        while j < min(8, len(order)):
+            tk, ta, nq = order[j]
+            res = srv.poll(tk)
+            if res is None:
+                j += 1
+                continue
+            lat.append(res[2] - ta)  # completion is stamped by the server's own thread
+            t_last = max(t_last, res[2])
+            q_done += nq
+            order.pop(j)
+    st = srv.stats()
+    srv.close()
+    lat = np.asarray(lat) * 1e3
+    return {"rate_req_s": rate, "requests": int(n), "queries": int(q_done),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "queries_per_s": round(q_done / max(t_last - t0, 1e-9), 1),
+            "batches": int(st["batches"]),
+            "peak_arena_MiB": round(st["peak_arena_bytes"] / 2**20, 1)}
 
 
 def main():
@@ -58,10 +122,9 @@ def main():
     pk.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t_gen = time.time()
-    cfg = datagen.config_scale(n=args.n)
+    cfg = datagen.config_scale()
     X, Q = cfg.X, cfg.Q
-    print(f"# data {X.shape} queries {Q.shape} generated in {time.time() - t_gen:.1f}s",
-          file=sys.stderr, flush=True)
+    log(f"data {X.shape} queries {Q.shape} generated in {time.time() - t_gen:.1f}s")
     Xd = torch.from_numpy(X).cuda()
     Qd = torch.from_numpy(Q).cuda()
     torch.cuda.synchronize()
@@ -70,92 +133,120 @@ def main():
     nq = Q.shape[0]
     stream = torch.cuda.current_stream()
 
-    def step(r):
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        e0.record(stream)
-        ix = pk.mask_build(Xd, levels, iters=args.iters, seed=1)
+    def timed(fn):
+        e1, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e1.record(stream)
-        ids, dist = pk.mask_query(ix, Qd, args.k, r)
+        out = fn()
         e2.record(stream)
         torch.cuda.synchronize()
-        return ix, ids, dist, e0.elapsed_time(e1), e1.elapsed_time(e2)
+        return out, e1.elapsed_time(e2)
+
+    # ---- ground truth for recall: the oracle's exhaustive FP64 kNN of a sample
+    from oracle import compare as oc
+    from oracle import mask_oracle as mo
+    g = np.random.default_rng(0)
+    sample = np.sort(g.choice(nq, min(args.recall_sample, nq), replace=False))
+    t = time.time()
+    tids, tdist = mo.exact_knn(X, Q[sample], args.k)
+    log(f"exhaustive FP64 kNN of {sample.size} queries on the host: {time.time() - t:.1f}s")
+
+    def recall_of(ids):
+        got = ids.cpu().numpy()[sample].astype(np.int64)
+        return oc.recall_at_k(got, tids, tdist, oc.true_distances(X, Q[sample], got), args.k)
+
+    def build(form):
+        return pk.mask_build(Xd, levels, iters=args.iters, seed=1, precision=form)
+
+    # ---- both forms: build, select the cheapest beams that pass the recall gate
+    forms = {}
+    for form in ("fp32", "bf16"):
+        ix, _ = timed(lambda: build(form))
+        ix.free()
+        ix, b_ms = timed(lambda: build(form))
+        chosen, tried = None, []
+        for beams in BEAMS:
+            timed(lambda: pk.mask_query_beams(ix, Qd, args.k, beams))
+            (ids, _), q_ms = timed(lambda: pk.mask_query_beams(ix, Qd, args.k, beams))
+            rec = recall_of(ids)
+            tried.append({"beams": list(beams), "recall@10": round(rec, 4),
+                          "queries_per_s": round(nq / (q_ms * 1e-3), 1)})
+            chosen = (beams, rec, q_ms)
+            if rec >= args.gate:
+                break
+        ix.free()
+        forms[form] = {"build_s": round(b_ms * 1e-3, 4), "beams": list(chosen[0]),
+                       "recall@10": round(chosen[1], 4),
+                       "queries_per_s": round(nq / (chosen[2] * 1e-3), 1), "tried": tried}
+        log(f"{form}: build {b_ms:.1f} ms; beams {chosen[0]} recall {chosen[1]:.4f} "
+            f"{nq / (chosen[2] * 1e-3):.0f} q/s")
+
+    form = args.form
+    if form == "auto":
+        form = max(("fp32", "bf16"), key=lambda f: (forms[f]["recall@10"] >= args.gate,
+                                                     forms[f]["queries_per_s"]))
+    beams = tuple(forms[form]["beams"])
+
+    # ---- timed steps: build + query in the selected form
+    def step():
+        ix, b = timed(lambda: build(form))
+        (ids, _), q = timed(lambda: pk.mask_query_beams(ix, Qd, args.k, beams))
+        return ix, ids, b, q
 
     for w in range(args.warmup):
-        ix, _, _, b_ms, q_ms = step(args.r)
+        ix, _, b_ms, q_ms = step()
         ix.free()
-        print(f"# warmup {w}: build {b_ms:.1f} ms, query {q_ms:.2f} ms", file=sys.stderr,
-              flush=True)
-
+        log(f"warmup {w}: build {b_ms:.1f} ms, query {q_ms:.2f} ms")
     pk.mask_timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     build_ms, query_ms = [], []
-    last = None
+    ix = None
     for s in range(args.steps):
-        if last is not None:
-            last[0].free()
-        last = step(args.r)
-        build_ms.append(last[3])
-        query_ms.append(last[4])
-        print(f"# step {s}: build {last[3]:.1f} ms, query {last[4]:.2f} ms", file=sys.stderr,
-              flush=True)
+        if ix is not None:
+            ix.free()
+        ix, ids, b_ms, q_ms = step()
+        build_ms.append(b_ms)
+        query_ms.append(q_ms)
+        log(f"step {s}: build {b_ms:.1f} ms, query {q_ms:.2f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kt = pk.mask_timing_report()
     pk.mask_timing_enable(False)
-    ix, ids, dist = last[0], last[1], last[2]
+    step_recall = recall_of(ids)
 
-    # ---- roofline of the dominant kernel (MFMA assignment) and of the descent
+    # ---- roofline of the dominant kernel (the build's MFMA assignment) and the descent
     flops_per_build = 0.0
     items = n
     for (C, k) in levels:
-        flops_per_build += 2.0 * items * k * d  # every item against the k prototypes of its chunk
+        flops_per_build += 2.0 * items * k * d  # every item against its chunk's k prototypes
         items = C * k
     flops_per_build *= (args.iters + 1)
-    a_cnt, a_ms = kt.get("assign_l2_mfma", (0, 0.0))
+    akey = "assign_l2_mfma" if form == "fp32" else "assign_bf16_mfma"
+    a_cnt, a_ms = kt.get(akey, (0, 0.0))
     assign_tflops = flops_per_build * args.steps / (a_ms * 1e-3) / 1e12 if a_ms else 0.0
-    d_cnt, d_ms = kt.get("descent", (0, 0.0))
+    dkey = "descent" if form == "fp32" else "descent_bf16"
+    d_cnt, d_ms = kt.get(dkey, (0, 0.0))
     rows = kt.get("descent_rows", (0, 0.0))[0]
-    ld = (d + 3) // 4 * 4
-    desc_bytes = rows * (ld * 4 + 4)
-    desc_gbs = desc_bytes / (d_ms * 1e-3) / 1e9 if d_ms else 0.0
+    row_bytes = ((d + 3) // 4 * 4) * 4 + 4 if form == "fp32" else ((d + 7) // 8 * 8) * 2 + 4
+    desc_gbs = rows * row_bytes / (d_ms * 1e-3) / 1e9 if d_ms else 0.0
     counters = ("descent_rows", "refine_small_points", "refine_full_points")
     kernels = {name: {"launches": c, "total_ms": round(ms, 3),
                       "avg_ms": round(ms / c, 4) if c else None}
                for name, (c, ms) in kt.items() if name not in counters}
-    refine_stats = {"small_per_build": kt.get("refine_small_points", (0, 0))[0] // args.steps,
-                    "full_per_build": kt.get("refine_full_points", (0, 0))[0] // args.steps}
 
-    # ---- recall against exhaustive FP64 search (the oracle), and the CPU baseline
-    result_recall = None
+    # ---- serving: the same request stream through both forms
+    serving = None
+    if not args.no_serve:
+        serving = {}
+        for f in ("fp32", "bf16"):
+            sx = build(f)
+            serving[f] = serve_stream(pk, sx, Q, args.serve_rate, args.serve_seconds, seed=55)
+            sx.free()
+            log(f"serving {f}: {serving[f]}")
+
+    # ---- CPU baseline: the oracle's FP64 descent on the same index, bounded sample
     cpu = None
-    sweep = {}
     if not args.no_cpu_baseline:
-        from oracle import compare as oc
-        from oracle import mask_oracle as mo
-        g = np.random.default_rng(0)
-        sample = np.sort(g.choice(nq, min(args.recall_sample, nq), replace=False))
-        t = time.time()
-        tids, tdist = mo.exact_knn(X, Q[sample], args.k)
-        print(f"# exact kNN of {sample.size} queries on the host: {time.time() - t:.1f}s",
-              file=sys.stderr, flush=True)
-
-        def recall_of(ids_np):
-            got = ids_np[sample].astype(np.int64)
-            got_true = oc.true_distances(X, Q[sample], got)
-            return oc.recall_at_k(got, tids, tdist, got_true, args.k)
-
-        result_recall = recall_of(ids.cpu().numpy())
-        for r in [int(x) for x in args.sweep.split(",") if x]:
-            e1, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e1.record(stream)
-            i2, _ = pk.mask_query(ix, Qd, args.k, r)
-            e2.record(stream)
-            torch.cuda.synchronize()
-            sweep[r] = {"recall@10": round(recall_of(i2.cpu().numpy()), 4),
-                        "queries_per_s": round(nq / (e1.elapsed_time(e2) * 1e-3), 1)}
-            print(f"# sweep r={r}: {sweep[r]}", file=sys.stderr, flush=True)
-        # the oracle's own descent on the same (exported) index, bounded sample
         protos, parents = [], []
         for lev in range(1, len(levels) + 1):
             P, par = ix.export_level(lev)
@@ -166,16 +257,16 @@ def main():
         t = time.time()
         done = 0
         while done < nq and (time.time() - t < args.cpu_seconds or done < 20):
-            mo.query_one(oix, Q[done], args.k, args.r)
+            mo.query_one(oix, Q[done], args.k, list(beams))
             done += 1
         el = time.time() - t
         cpu = {"value": round(done / el, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
-               "sample": f"FP64 numpy descent (r={args.r}, k={args.k}) of the first {done} "
-                         f"queries on the GPU-built index, single thread, {el:.1f}s"}
+               "sample": f"FP64 numpy descent (beams {list(beams)}, k={args.k}) of the first "
+                         f"{done} of the 10,000 queries on the GPU-built index, one thread, "
+                         f"{el:.1f}s"}
 
     q_med = statistics.median(query_ms)
     b_med = statistics.median(build_ms)
-    qs = sorted(query_ms)
     out = {
         "metric": "queries/s at recall@10>=0.95 vs FP64 oracle; p50/p99 latency; index build s",
         "value": round(nq / (q_med * 1e-3), 1),
@@ -187,28 +278,27 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if form == "bf16" else "f32",
         "data": "synthetic",
         "config": {"workload": "mixture-1M-d128: 1,000,000 x 128 Gaussian mixture "
                                "(1,000 comps), levels 100x1000->5000->100, 30 Lloyd iters, "
                                "10,000 queries",
-                   "k": args.k, "r": args.r, "form": "plain FP32"},
-        "recall@10": None if result_recall is None else round(result_recall, 4),
+                   "k": args.k, "beams": list(beams), "form": form},
+        "recall@10": round(step_recall, 4),
         "build_s": round(b_med * 1e-3, 4),
-        "query_batch_ms": {"p50": round(q_med, 3), "p99": round(qs[-1], 3)},
-        "roofline": {"bound": "mfma", "kernel": "assign_l2_mfma",
-                     "achieved": round(assign_tflops, 2), "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(assign_tflops / PEAK_FP32_TFLOPS, 4),
-                     "traffic": None},
-        "roofline_query": {"bound": "hbm", "kernel": "descent", "achieved": round(desc_gbs, 1),
+        "latency_ms": None if serving is None else {"p50": serving[form]["p50_ms"],
+                                                    "p99": serving[form]["p99_ms"]},
+        "roofline": {"bound": "mfma", "kernel": akey, "achieved": round(assign_tflops, 2),
+                     "peak": PEAK[form], "unit": "TFLOP/s",
+                     "frac": round(assign_tflops / PEAK[form], 4), "traffic": None},
+        "roofline_query": {"bound": "hbm", "kernel": dkey, "achieved": round(desc_gbs, 1),
                            "peak": PEAK_HBM_GBS, "unit": "GB/s",
                            "frac": round(desc_gbs / PEAK_HBM_GBS, 4), "traffic": None},
+        "forms": forms,
+        "serving": serving,
         "kernels": kernels,
-        "refined_points": refine_stats,
         "cpu_baseline": cpu,
     }
-    if sweep:
-        out["sweep"] = sweep
     print(json.dumps(out), flush=True)
     ix.free()
     return 0

@@ -99,7 +99,7 @@ typedef struct {
   const mask_level* levels; /* host array [n_levels], bottom-up */
   int32_t lloyd_iters;   /* Lloyd iterations per level (>= 0) */
   uint64_t seed;         /* seeds the level-0 permutation */
-  int32_t rerank_factor; /* precision forms: FP32 re-rank of rerank_factor*k*r */
+  int32_t rerank_factor; /* precision forms: FP32 re-rank of rerank_factor*k */
   const int32_t* perm;   /* optional device int32[n]: level-0 order; NULL = from seed */
 } mask_build_params;
 
@@ -144,9 +144,10 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
  * row ids), out_dist: device float32[q->n * k], rows ascending; slots beyond
  * the candidate count hold id -1 and +inf.  1 <= k <= 2048, 1 <= r <= 2048.
  * Precision form (index built with MASK_BF16): rows are compared in BF16 and
- * the data layer's R = min(rerank_factor * k * r, max(512, k, r)) nearest by
- * BF16 distance are re-ranked in FP32 direct form on the FP32 rows (all
- * candidates in FP32 when they are no more than R).
+ * the data layer's R = min(rerank_factor * k, C) nearest by BF16 distance
+ * are re-ranked in FP32 direct form on the FP32 rows, where C = 512 when k
+ * and every beam are at most 512 and 2048 otherwise (all candidates in FP32
+ * when they are no more than R, or when R <= k).
  * Asynchronous on hip_stream; allocates nothing.  Each query's result does
  * not depend on the other queries of the batch. */
 mask_status mask_query(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
@@ -228,6 +229,8 @@ typedef struct {
   int64_t arena_bytes;       /* device memory for in-flight batches (>= 4096) */
   int32_t max_batch_queries; /* largest number of queries in one batch */
   int32_t n_streams;         /* batches in flight at once, 1..16 */
+  int32_t batch_window_us;   /* a batch that is not full launches once its oldest
+                                request has been queued this long (0: at once) */
 } mask_server_params;
 
 typedef struct {

@@ -69,7 +69,7 @@ class mask_allocator(ctypes.Structure):
 
 class mask_server_params(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_int64), ("max_batch_queries", ctypes.c_int32),
-                ("n_streams", ctypes.c_int32)]
+                ("n_streams", ctypes.c_int32), ("batch_window_us", ctypes.c_int32)]
 
 
 class mask_server_stats(ctypes.Structure):
@@ -305,9 +305,12 @@ def mask_query_beams(index: Index, queries, k: int, beams: Sequence[int], stream
     return ids, dist
 
 
-def mask_query_ragged(index: Index, queries, k_i, r_i, stream=None):
+def mask_query_ragged(index: Index, queries, k_i, r_i, stream=None, k_max: int = 0,
+                      r_max: int = 0):
     """Per-query k and r (int32 CUDA tensors of length nq); returns
-    (ids, dist, offsets): query i's results are ids[offsets[i]:offsets[i+1]]."""
+    (ids, dist, offsets): query i's results are ids[offsets[i]:offsets[i+1]].
+    k_max / r_max: bounds passed to the library (raised to the largest k_i /
+    r_i when smaller)."""
     torch = _torch()
     m = _dense(queries)
     k_i = k_i.to(device=queries.device, dtype=torch.int32).contiguous()
@@ -317,8 +320,8 @@ def mask_query_ragged(index: Index, queries, k_i, r_i, stream=None):
     total = int(off[-1].item())
     ids = torch.empty(max(total, 1), dtype=torch.int32, device=queries.device)
     dist = torch.empty(max(total, 1), dtype=torch.float32, device=queries.device)
-    k_max = int(k_i.max().item()) if queries.shape[0] else 1
-    r_max = int(r_i.max().item()) if queries.shape[0] else 1
+    k_max = max(int(k_max), int(k_i.max().item()) if queries.shape[0] else 1)
+    r_max = max(int(r_max), int(r_i.max().item()) if queries.shape[0] else 1)
     _check(lib().mask_query_ragged(index.handle, ctypes.byref(m), k_i.data_ptr(), r_i.data_ptr(),
                                    off.data_ptr(), k_max, r_max, ids.data_ptr(), dist.data_ptr(),
                                    _stream_handle(stream)))
@@ -399,8 +402,9 @@ class MaskServer:
     host results out)."""
 
     def __init__(self, index: Index, arena_bytes: int = 1 << 30, max_batch_queries: int = 65536,
-                 n_streams: int = 2):
-        p = mask_server_params(int(arena_bytes), int(max_batch_queries), int(n_streams))
+                 n_streams: int = 2, batch_window_us: int = 0):
+        p = mask_server_params(int(arena_bytes), int(max_batch_queries), int(n_streams),
+                               int(batch_window_us))
         h = ctypes.c_void_p()
         _check(lib().mask_server_create(index.handle, ctypes.byref(p), None, ctypes.byref(h)))
         self.handle = h

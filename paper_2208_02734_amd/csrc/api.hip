@@ -210,7 +210,7 @@ void run_level(const float* items, int64_t n_items, int ld, int dim, int C, int 
   ChunkPlan plan;
   make_plan(plan, n_items, C, k, scratch, s);
   KmeansWork w;
-  kmeans_alloc(w, n_items, C, k, scratch);
+  kmeans_alloc(w, n_items, C, k, ld, scratch);
   if (precision == MASK_BF16 && metric == MASK_L2) {
     w.precision = MASK_BF16;
     w.ldb = bf16_stride(ld);

@@ -234,6 +234,9 @@ struct KmeansWork {
   float* item_norms = nullptr;
   float* proto_norms = nullptr;
   double* proto_norms64 = nullptr;
+  int32_t* slot_proto = nullptr;  // update work item slots (prototype or -1)
+  double* upd_sum = nullptr;      // slots x ld FP64 partial sums
+  double* upd_inert = nullptr;    // slots
   // BF16 form: rounded copies of the items and prototypes (row stride ldb)
   int precision = MASK_FP32;
   int ldb = 0;
@@ -247,7 +250,8 @@ struct KmeansWork {
 void quantize_bf16(const float* x, int ld, int64_t n, uint16_t* out, int ldb, float* norms,
                    hipStream_t s);
 
-void kmeans_alloc(KmeansWork& w, int64_t n_items, int n_chunks, int k, Arena& scratch);
+void kmeans_alloc(KmeansWork& w, int64_t n_items, int n_chunks, int k, int ld,
+                  Arena& scratch);
 
 // One assignment of every item to its nearest prototype of its chunk
 // (plain FP32 form: MFMA screening + direct-form certification).

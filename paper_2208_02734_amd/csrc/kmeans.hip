@@ -554,87 +554,191 @@ __global__ __launch_bounds__(kBlock) void k_refine_merge(
   }
 }
 
-// One wave per prototype: FP64 sums of the members in item order, the new
-// prototype (unchanged when empty), its FP32 squared norm, and the FP64
-// inertia of the members under the old prototype.
-template <int J>
-__global__ __launch_bounds__(kBlock) void k_update_l2(
+// Update of the L2 form: FP64 sums of each prototype's members, split into
+// work items of at most kUpdChunk members so that a large cluster is spread
+// over many waves.  Prototype p owns the item slots [p + m0 / S, p + 1 + m1 / S)
+// (S = kUpdChunk, [m0, m1) its member range): at least max(1, ceil(cnt / S))
+// of them, since floor(m1 / S) - floor(m0 / S) >= floor(cnt / S).  The first
+// max(1, ceil(cnt / S)) slots hold its items and the rest stay empty.  A
+// prototype with one item is finished by that item; the partial sums of a
+// larger one are combined in item order by k_update_finish.  Every sum has a
+// fixed order, so the result does not depend on scheduling.
+constexpr int kUpdChunk = 64;
+
+__global__ void k_update_slots(const uint32_t* __restrict__ member_off, int64_t n_protos,
+                               int32_t* __restrict__ slot_proto) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_protos) return;
+  const uint32_t m0 = member_off[p], m1 = member_off[p + 1];
+  const uint32_t cnt = m1 - m0;
+  const int64_t b0 = p + m0 / kUpdChunk, b1 = p + 1 + m1 / kUpdChunk;
+  const int64_t nch = cnt == 0 ? 1 : (cnt + kUpdChunk - 1) / kUpdChunk;
+  for (int64_t t = b0; t < b1; ++t) slot_proto[t] = (t - b0 < nch) ? (int32_t)p : -1;
+}
+
+// Mean (unchanged when empty) written to the prototype row with its FP32 and
+// FP64 squared norms; the FP64 sum of the 4-dim slice owned by one lane.
+__device__ inline void finish_slice(double t0, double t1, double t2, double t3, uint32_t cnt,
+                                    float4 c_old, float4* prow, bool own, float& nrm,
+                                    double& nrm64) {
+  float4 v = c_old;
+  if (cnt > 0) {
+    const double n = (double)cnt;
+    v = make_float4((float)(t0 / n), (float)(t1 / n), (float)(t2 / n), (float)(t3 / n));
+  }
+  nrm = 0.f;
+  nrm64 = 0.0;
+  if (own) {
+    *prow = v;
+    nrm = fmaf(v.x, v.x, fmaf(v.y, v.y, fmaf(v.z, v.z, v.w * v.w)));
+    nrm64 = fma((double)v.x, (double)v.x,
+                fma((double)v.y, (double)v.y, fma((double)v.z, (double)v.z, (double)v.w * v.w)));
+  }
+}
+
+// One wave per item slot.  LPR lanes per row (each one float4 of the row),
+// 64 / LPR rows per step, U steps in flight.  Row r of the item goes to lane
+// group (r % (64 / LPR)) and partial u = (r / (64 / LPR)) % U.
+template <int LPR, int U>
+__global__ __launch_bounds__(kBlock) void k_update_items(
     const float* __restrict__ items, int ld, const uint32_t* __restrict__ members,
-    const uint32_t* __restrict__ member_off, int64_t n_protos, float* __restrict__ protos,
-    float* __restrict__ pnorm, double* __restrict__ pnorm64, double* __restrict__ proto_inertia) {
+    const uint32_t* __restrict__ member_off, const int32_t* __restrict__ slot_proto,
+    int64_t n_slots, float* __restrict__ protos, float* __restrict__ pnorm,
+    double* __restrict__ pnorm64, double* __restrict__ proto_inertia,
+    double* __restrict__ part_sum, double* __restrict__ part_inert) {
+  constexpr int RPW = kWave / LPR;
+  const int lane = threadIdx.x % kWave;
+  const int64_t t = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  if (t >= n_slots) return;
+  const int32_t p = slot_proto[t];
+  if (p < 0) return;
+  const uint32_t m0 = member_off[p], m1 = member_off[p + 1];
+  const uint32_t cnt = m1 - m0;
+  const int64_t j = t - ((int64_t)p + m0 / kUpdChunk);
+  const uint32_t a = m0 + (uint32_t)j * kUpdChunk;
+  const uint32_t b = min(m1, a + (uint32_t)kUpdChunk);
+  const int f4 = ld / 4;
+  const int gl = lane % LPR, h = lane / LPR;
+  const bool act = gl < f4;
+  const float4* prow = reinterpret_cast<const float4*>(protos + (int64_t)p * ld) + gl;
+  const float4 c_old = act ? *prow : make_float4(0.f, 0.f, 0.f, 0.f);
+  // the item's member ids, one per lane
+  static_assert(kUpdChunk == kWave, "one member id per lane");
+  const uint32_t my_id = (a + lane < b) ? members[a + lane] : 0u;
+  double ps[U][4];
+#pragma unroll
+  for (int u = 0; u < U; ++u) ps[u][0] = ps[u][1] = ps[u][2] = ps[u][3] = 0.0;
+  double inert = 0.0;
+  for (uint32_t base = 0; base < b - a; base += RPW * U) {
+    float4 x[U];
+    bool val[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t r = base + u * RPW + h;
+      val[u] = r < b - a;
+      const uint32_t id = __shfl(my_id, (int)(val[u] ? r : 0));
+      const float4* row = reinterpret_cast<const float4*>(items + (int64_t)id * ld);
+      const float4 v = row[act ? gl : 0];
+      x[u] = (val[u] && act) ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!val[u] || !act) continue;
+      ps[u][0] += (double)x[u].x;
+      ps[u][1] += (double)x[u].y;
+      ps[u][2] += (double)x[u].z;
+      ps[u][3] += (double)x[u].w;
+      const double d0 = (double)x[u].x - (double)c_old.x, d1 = (double)x[u].y - (double)c_old.y;
+      const double d2 = (double)x[u].z - (double)c_old.z, d3 = (double)x[u].w - (double)c_old.w;
+      inert = fma(d0, d0, inert);
+      inert = fma(d1, d1, inert);
+      inert = fma(d2, d2, inert);
+      inert = fma(d3, d3, inert);
+    }
+  }
+  double tot[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    double acc = ps[0][e];
+#pragma unroll
+    for (int u = 1; u < U; ++u) acc += ps[u][e];
+    tot[e] = acc;
+  }
+  // lane groups hold disjoint rows: combine them (the same sum on every group)
+#pragma unroll
+  for (int o = LPR; o < kWave; o <<= 1)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) tot[e] += __shfl_xor(tot[e], o);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) inert += __shfl_xor(inert, o);
+  if (cnt <= (uint32_t)kUpdChunk) {
+    float nrm;
+    double nrm64;
+    finish_slice(tot[0], tot[1], tot[2], tot[3], cnt, c_old,
+                 reinterpret_cast<float4*>(protos + (int64_t)p * ld) + gl, act && h == 0, nrm,
+                 nrm64);
+#pragma unroll
+    for (int o = LPR / 2; o >= 1; o >>= 1) {
+      nrm += __shfl_xor(nrm, o);
+      nrm64 += __shfl_xor(nrm64, o);
+    }
+    if (lane == 0) {
+      pnorm[p] = nrm;
+      pnorm64[p] = nrm64;
+      proto_inertia[p] = inert;
+    }
+  } else {
+    if (act && h == 0) {
+      double* dst = part_sum + t * ld + 4 * gl;
+      dst[0] = tot[0];
+      dst[1] = tot[1];
+      dst[2] = tot[2];
+      dst[3] = tot[3];
+    }
+    if (lane == 0) part_inert[t] = inert;
+  }
+}
+
+// One wave per prototype with more than one item: item sums added in item
+// order, then the mean, norms and inertia as above.
+template <int LPR>
+__global__ __launch_bounds__(kBlock) void k_update_finish(
+    int ld, const uint32_t* __restrict__ member_off, int64_t n_protos,
+    float* __restrict__ protos, float* __restrict__ pnorm, double* __restrict__ pnorm64,
+    double* __restrict__ proto_inertia, const double* __restrict__ part_sum,
+    const double* __restrict__ part_inert) {
   const int lane = threadIdx.x % kWave;
   const int64_t p = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   if (p >= n_protos) return;
-  float c_old[J];
-  double sum[J];
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int c = lane + j * kWave;
-    c_old[j] = (c < ld) ? protos[p * ld + c] : 0.f;
-    sum[j] = 0.0;
-  }
-  double inert = 0.0;
   const uint32_t m0 = member_off[p], m1 = member_off[p + 1];
-  // four members in flight; member m adds into partial (m - m0) % 4, the
-  // partials are combined in a fixed order below
-  double part[4][J];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int j = 0; j < J; ++j) part[u][j] = 0.0;
-  uint32_t m = m0;
-  for (; m + 4 <= m1; m += 4) {
-    float xv[4][J];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const float* row = items + (int64_t)members[m + u] * ld;
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        const int c = lane + j * kWave;
-        xv[u][j] = (c < ld) ? row[c] : 0.f;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int j = 0; j < J; ++j) {
-        part[u][j] += (double)xv[u][j];
-        const double d = (double)xv[u][j] - (double)c_old[j];
-        inert = fma(d, d, inert);
-      }
-  }
-  for (; m < m1; ++m) {
-    const float* row = items + (int64_t)members[m] * ld;
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int c = lane + j * kWave;
-      const float x = (c < ld) ? row[c] : 0.f;
-      part[(m - m0) & 3][j] += (double)x;
-      const double d = (double)x - (double)c_old[j];
-      inert = fma(d, d, inert);
-    }
-  }
-#pragma unroll
-  for (int j = 0; j < J; ++j) sum[j] = (part[0][j] + part[1][j]) + (part[2][j] + part[3][j]);
   const uint32_t cnt = m1 - m0;
-  float nrm = 0.f;
-  double nrm64 = 0.0;
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int c = lane + j * kWave;
-    float v = c_old[j];
-    if (cnt > 0) v = (float)(sum[j] / (double)cnt);
-    if (c < ld) {
-      protos[p * ld + c] = v;
-      nrm = fmaf(v, v, nrm);
-      nrm64 = fma((double)v, (double)v, nrm64);
+  if (cnt <= (uint32_t)kUpdChunk) return;
+  const int64_t t0 = p + m0 / kUpdChunk;
+  const int nch = (int)((cnt + kUpdChunk - 1) / kUpdChunk);
+  const int f4 = ld / 4;
+  const int gl = lane % LPR, h = lane / LPR;
+  const bool act = gl < f4 && h == 0;
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  double inert = 0.0;
+  for (int i = 0; i < nch; ++i) {
+    if (act) {
+      const double* src = part_sum + (t0 + i) * ld + 4 * gl;
+      tot[0] += src[0];
+      tot[1] += src[1];
+      tot[2] += src[2];
+      tot[3] += src[3];
     }
+    inert += part_inert[t0 + i];
   }
+  float4* prow = reinterpret_cast<float4*>(protos + (int64_t)p * ld) + gl;
+  const float4 c_old = act ? *prow : make_float4(0.f, 0.f, 0.f, 0.f);
+  float nrm;
+  double nrm64;
+  finish_slice(tot[0], tot[1], tot[2], tot[3], cnt, c_old, prow, act, nrm, nrm64);
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) {
     nrm += __shfl_xor(nrm, o);
     nrm64 += __shfl_xor(nrm64, o);
-    inert += __shfl_xor(inert, o);
   }
   if (lane == 0) {
     pnorm[p] = nrm;
@@ -667,18 +771,39 @@ __device__ inline float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32
 
 // out[i*ldb + c] = bf16(x[i*ld + c]) for c < ld, zero up to ldb; norms[i] =
 // squared norm of the rounded row (FP32, fixed order) when norms != null.
-__global__ void k_quantize_bf16(const float* __restrict__ x, int ld, int64_t n,
-                                uint16_t* __restrict__ out, int ldb, float* __restrict__ norms) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// G lanes per row (G a power of two); each lane rounds 8 consecutive values
+// per step (two float4 loads, one 16-byte store) and the group adds the
+// squares of the rounded values.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_quantize_bf16(const float* __restrict__ x, int ld,
+                                                          int64_t n, uint16_t* __restrict__ out,
+                                                          int ldb, float* __restrict__ norms) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = t / G;
+  const int gl = (int)(t % G);
+  const bool live = i < n;  // every lane stays for the group sum
   float acc = 0.f;
-  for (int c = 0; c < ldb; ++c) {
-    const uint16_t b = c < ld ? bf16_rne(x[i * ld + c]) : (uint16_t)0;
-    out[i * ldb + c] = b;
-    const float v = bf16_to_f32(b);
-    acc = fmaf(v, v, acc);
+  if (live) {
+    for (int c = 8 * gl; c < ldb; c += 8 * G) {
+      const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 lo = c < ld ? *reinterpret_cast<const float4*>(x + i * ld + c) : z;
+      const float4 hi = c + 4 < ld ? *reinterpret_cast<const float4*>(x + i * ld + c + 4) : z;
+      const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+      uint32_t w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint16_t b0 = bf16_rne(v[2 * e]), b1 = bf16_rne(v[2 * e + 1]);
+        w[e] = (uint32_t)b0 | ((uint32_t)b1 << 16);
+        const float r0 = bf16_to_f32(b0), r1 = bf16_to_f32(b1);
+        acc = fmaf(r0, r0, acc);
+        acc = fmaf(r1, r1, acc);
+      }
+      *reinterpret_cast<uint4*>(out + i * ldb + c) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
   }
-  if (norms) norms[i] = acc;
+#pragma unroll
+  for (int o = G / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+  if (live && gl == 0 && norms) norms[i] = acc;
 }
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
@@ -1064,7 +1189,7 @@ void launch_refine(const float* items, int ld, const ChunkPlan& plan, const floa
 
 }  // namespace
 
-void kmeans_alloc(KmeansWork& w, int64_t n_items, int n_chunks, int k, Arena& a) {
+void kmeans_alloc(KmeansWork& w, int64_t n_items, int n_chunks, int k, int ld, Arena& a) {
   const int64_t n_protos = (int64_t)n_chunks * k;
   w.sort_keys = a.alloc<uint32_t>(n_items);
   w.sort_vals = a.alloc<uint32_t>(n_items);
@@ -1087,6 +1212,11 @@ void kmeans_alloc(KmeansWork& w, int64_t n_items, int n_chunks, int k, Arena& a)
   w.item_norms = a.alloc<float>(n_items);
   w.proto_norms = a.alloc<float>(n_protos);
   w.proto_norms64 = a.alloc<double>(n_protos);
+  // update work items (see k_update_slots)
+  const int64_t n_slots = n_protos + n_items / kUpdChunk;
+  w.slot_proto = a.alloc<int32_t>(n_slots);
+  w.upd_sum = a.alloc<double>(n_slots * ld);
+  w.upd_inert = a.alloc<double>(n_slots);
 }
 
 void kmeans_proto_norms(const float* protos, int ld, int64_t n_protos, KmeansWork& w,
@@ -1108,7 +1238,15 @@ void kmeans_init_first(const float* items, int ld, const ChunkPlan& plan, float*
 void quantize_bf16(const float* x, int ld, int64_t n, uint16_t* out, int ldb, float* norms,
                    hipStream_t s) {
   if (n <= 0) return;
-  k_quantize_bf16<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, ld, n, out, ldb, norms);
+  const int c8 = ldb / 8;
+  if (c8 <= 4)
+    k_quantize_bf16<4><<<grid_for(n * 4, kBlock), kBlock, 0, s>>>(x, ld, n, out, ldb, norms);
+  else if (c8 <= 8)
+    k_quantize_bf16<8><<<grid_for(n * 8, kBlock), kBlock, 0, s>>>(x, ld, n, out, ldb, norms);
+  else if (c8 <= 16)
+    k_quantize_bf16<16><<<grid_for(n * 16, kBlock), kBlock, 0, s>>>(x, ld, n, out, ldb, norms);
+  else
+    k_quantize_bf16<32><<<grid_for(n * 32, kBlock), kBlock, 0, s>>>(x, ld, n, out, ldb, norms);
   check_launch("quantize_bf16");
 }
 
@@ -1187,15 +1325,28 @@ void kmeans_update(const float* items, int ld, int dim, const ChunkPlan& plan,
     check_launch("update_l1");
   } else {
   ScopedTiming timing("update_l2", s);
-  if (J <= 1)
-    k_update_l2<1><<<grid, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off, np, protos,
-                                           w.proto_norms, w.proto_norms64, w.proto_inertia);
-  else if (J <= 2)
-    k_update_l2<2><<<grid, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off, np, protos,
-                                           w.proto_norms, w.proto_norms64, w.proto_inertia);
-  else
-    k_update_l2<4><<<grid, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off, np, protos,
-                                           w.proto_norms, w.proto_norms64, w.proto_inertia);
+  const int64_t n_slots = np + n / kUpdChunk;
+  k_update_slots<<<grid_for(np, kBlock), kBlock, 0, s>>>(w.member_off, np, w.slot_proto);
+  check_launch("update_slots");
+  const unsigned gi = grid_for(n_slots * kWave, kBlock);
+  const unsigned gf = grid_for(np * kWave, kBlock);
+  const int f4 = ld / 4;
+#define MASK_UPDATE(LPR, U)                                                                   \
+  do {                                                                                        \
+    k_update_items<LPR, U><<<gi, kBlock, 0, s>>>(items, ld, w.sort_vals, w.member_off,         \
+                                                 w.slot_proto, n_slots, protos, w.proto_norms, \
+                                                 w.proto_norms64, w.proto_inertia, w.upd_sum,  \
+                                                 w.upd_inert);                                 \
+    k_update_finish<LPR><<<gf, kBlock, 0, s>>>(ld, w.member_off, np, protos, w.proto_norms,    \
+                                               w.proto_norms64, w.proto_inertia, w.upd_sum,    \
+                                               w.upd_inert);                                   \
+  } while (0)
+  if (f4 <= 4) MASK_UPDATE(4, 4);
+  else if (f4 <= 8) MASK_UPDATE(8, 4);
+  else if (f4 <= 16) MASK_UPDATE(16, 4);
+  else if (f4 <= 32) MASK_UPDATE(32, 4);
+  else MASK_UPDATE(64, 8);
+#undef MASK_UPDATE
   check_launch("update_l2");
   }
   if (inertia_out) {

@@ -2,7 +2,7 @@
 //
 // Precision form (BF16): every level's rows are read as BF16 (half the
 // bytes) and ranked with FP32 arithmetic against the FP32 query; at the data
-// layer the rerank_factor * k * r nearest by BF16 distance are re-ranked in
+// layer the rerank_factor * k nearest by BF16 distance are re-ranked in
 // FP32 direct form on the FP32 rows, and the k nearest of those are returned.
 //
 // One workgroup (256 threads) runs the whole descent of one query, so a
@@ -51,9 +51,12 @@ __device__ inline uint64_t wave_max_u64(uint64_t v) {
 // Keeps the `want` smallest of buf[0..m) in buf[0..want) (any order) and
 // sets sh.thr to the largest kept key.  Keys must be distinct.  Called by
 // every thread of the block; m > want >= 1.  Most-significant-digit radix
-// select over the bits below the keys' common prefix, 8 bits per pass; the
-// digit histograms are double-buffered and every wave scans the histogram
-// itself, so a pass costs one barrier.  hist: 2 * 256 counters.
+// select over the bits below the keys' common prefix, 8 bits per pass.  The
+// digit histograms rotate over three buffers and every wave scans the
+// histogram itself, so a pass costs one barrier: pass p counts into buffer
+// p % 3 and clears buffer (p + 1) % 3, which was last read in pass p - 2
+// (before the barrier of pass p - 1) and is next counted into after the
+// barrier of pass p.  hist: 3 * 256 counters.
 __device__ void block_select(uint64_t* buf, uint32_t m, uint32_t want, uint64_t* out,
                              uint32_t* hist, SelShared& sh, uint64_t* red) {
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
@@ -86,8 +89,9 @@ __device__ void block_select(uint64_t* buf, uint32_t m, uint32_t want, uint64_t*
     const int hi_bit = shift;  // bits >= hi_bit equal the prefix
     shift -= w;
     const uint32_t nb = 1u << w;
-    uint32_t* h = hist + (pass & 1) * 256;
-    uint32_t* h_next = hist + ((pass + 1) & 1) * 256;
+    uint32_t* h = hist + (pass % 3) * 256;
+    uint32_t* h_next = hist + ((pass + 1) % 3) * 256;
+    for (uint32_t i = tid; i < 256; i += kBlock) h_next[i] = 0;
     for (uint32_t i = tid; i < m; i += kBlock) {
       const uint64_t v = buf[i];
       const bool match = (hi_bit >= 64) || (((v ^ prefix) >> hi_bit) == 0);
@@ -126,8 +130,6 @@ __device__ void block_select(uint64_t* buf, uint32_t m, uint32_t want, uint64_t*
     const uint32_t b = __shfl(found, src) - 1;
     const uint32_t below = __shfl(f_below, src);
     const uint32_t bin_cnt = __shfl(f_cnt, src);
-    // the other buffer is free: every wave finished reading it last pass
-    for (uint32_t i = tid; i < 256; i += kBlock) h_next[i] = 0;
     need -= below;
     prefix |= (uint64_t)b << shift;
     ++pass;
@@ -180,10 +182,10 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
   extern __shared__ float4 s_q4[];  // ld/4 float4
   __shared__ uint64_t s_buf[CAP];
   __shared__ uint64_t s_out[CAPB];
-  __shared__ int32_t s_par[CAPB];       // kept positions one level up
+  __shared__ uint32_t s_cnt[CAPB];      // child count of each kept prototype
   __shared__ uint32_t s_beg[CAPB];      // first child position of each
   __shared__ uint32_t s_pre[CAPB + 1];  // prefix of child counts
-  __shared__ uint32_t s_hist[2 * 256];
+  __shared__ uint32_t s_hist[3 * 256];
   __shared__ uint64_t s_red[8];
   __shared__ SelShared sh;
 
@@ -210,13 +212,15 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
 #pragma unroll
   for (int v = 0; v < NQ; ++v) {
     const int c = gl + v * TPR;
-    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    // plain loads under a condition (a select between an LDS and a private
+    // address would turn into flat loads and a scratch slot)
+    qv[v][0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    qv[v][1] = make_float4(0.f, 0.f, 0.f, 0.f);
     if (B16) {
-      qv[v][0] = (NV > 0 && 2 * c < ld4) ? s_q4[2 * c] : z;
-      qv[v][1] = (NV > 0 && 2 * c + 1 < ld4) ? s_q4[2 * c + 1] : z;
+      if (NV > 0 && 2 * c < ld4) qv[v][0] = s_q4[2 * c];
+      if (NV > 0 && 2 * c + 1 < ld4) qv[v][1] = s_q4[2 * c + 1];
     } else {
-      qv[v][0] = (NV > 0 && c < ld4) ? s_q4[c] : z;
-      qv[v][1] = z;
+      if (NV > 0 && c < ld4) qv[v][0] = s_q4[c];
     }
   }
   unsigned long long rows_seen = 0;
@@ -230,9 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
     bool low = B16;  // rows read in BF16 at this level
     bool rerank = false;
     if (lev == 0 && B16) {
-      // the re-rank set: rerank_factor * k * r candidates, at most CAPB
-      const int r1 = qa.r_lev[1] > 0 ? qa.r_lev[1] : r;
-      const int64_t R = min((int64_t)a.rerank_factor * k * r1, (int64_t)CAPB);
+      // the re-rank set: rerank_factor * k candidates, at most CAPB
+      const int64_t R = min((int64_t)a.rerank_factor * k, (int64_t)CAPB);
       if ((int64_t)m > R && R > k) {
         want = (uint32_t)R;
         rerank = true;
@@ -275,20 +278,27 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
           const uint32_t idx = i0 + u;
           val[u] = idx < c1;
           while (val[u] && lo + 1 < n_par && s_pre[lo + 1] <= idx) ++lo;
-          pos[u] = (int64_t)s_beg[lo] + (idx - s_pre[lo]);
-          ids[u] = (gl == 0 && val[u]) ? (uint32_t)V.orig[pos[u]] : 0u;  // issued with the row loads
-        }        float acc[U];
+          // an empty slot reads row 0 (present whenever the level has rows)
+          pos[u] = val[u] ? (int64_t)s_beg[lo] + (idx - s_pre[lo]) : 0;
+        }
+        // Every load below is unconditional (indexes are clamped, values
+        // selected afterwards), so the id and row loads of all U slots are in
+        // flight together instead of each waiting behind a branch.
+#pragma unroll
+        for (int u = 0; u < U; ++u) ids[u] = (uint32_t)V.orig[pos[u]];
+        float acc[U];
         if (B16 && low) {
           const int nb = ldb / 8;
           if constexpr (NV > 0) {
             uint4 x[U][NV];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-              const uint4* row = reinterpret_cast<const uint4*>(V.protos_b + (val[u] ? pos[u] : 0) * ldb);
+              const uint4* row = reinterpret_cast<const uint4*>(V.protos_b + pos[u] * ldb);
 #pragma unroll
               for (int v = 0; v < NV; ++v) {
                 const int c = gl + v * TPR;
-                x[u][v] = (val[u] && c < nb) ? row[c] : make_uint4(0, 0, 0, 0);
+                const uint4 t = row[c < nb ? c : 0];
+                x[u][v] = c < nb ? t : make_uint4(0, 0, 0, 0);
               }
             }
 #pragma unroll
@@ -304,10 +314,10 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
           } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-              const uint4* row = reinterpret_cast<const uint4*>(V.protos_b + (val[u] ? pos[u] : 0) * ldb);
+              const uint4* row = reinterpret_cast<const uint4*>(V.protos_b + pos[u] * ldb);
               float s0 = 0.f;
               for (int c = gl; c < nb; c += TPR) {
-                const uint4 xv = val[u] ? row[c] : make_uint4(0, 0, 0, 0);
+                const uint4 xv = row[c];
                 const float4 q0 = 2 * c < ld4 ? s_q4[2 * c] : make_float4(0.f, 0.f, 0.f, 0.f);
                 const float4 q1 = 2 * c + 1 < ld4 ? s_q4[2 * c + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
                 s0 = acc4<METRIC>(s0, bf16_lo4(make_uint2(xv.x, xv.y)), q0);
@@ -320,11 +330,12 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
           float4 x[U][NQ];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const float4* row = reinterpret_cast<const float4*>(V.protos + (val[u] ? pos[u] : 0) * ld);
+            const float4* row = reinterpret_cast<const float4*>(V.protos + pos[u] * ld);
 #pragma unroll
             for (int v = 0; v < NQ; ++v) {
               const int c4 = gl + v * TPR;
-              x[u][v] = (val[u] && c4 < ld4) ? row[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+              const float4 t = row[c4 < ld4 ? c4 : 0];
+              x[u][v] = c4 < ld4 ? t : make_float4(0.f, 0.f, 0.f, 0.f);
             }
           }
 #pragma unroll
@@ -339,10 +350,9 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
           // the re-rank set would hold every candidate)
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const float4* row = reinterpret_cast<const float4*>(V.protos + (val[u] ? pos[u] : 0) * ld);
+            const float4* row = reinterpret_cast<const float4*>(V.protos + pos[u] * ld);
             float s0 = 0.f;
-            for (int c4 = gl; c4 < ld4; c4 += TPR)
-              s0 = acc4<METRIC>(s0, val[u] ? row[c4] : make_float4(0.f, 0.f, 0.f, 0.f), s_q4[c4]);
+            for (int c4 = gl; c4 < ld4; c4 += TPR) s0 = acc4<METRIC>(s0, row[c4], s_q4[c4]);
             acc[u] = s0;
           }
         }
@@ -379,8 +389,9 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
       for (uint32_t j = tid; j < kept; j += kBlock) {
         const uint32_t id = (uint32_t)s_buf[j];
         const int32_t pos = V.inv[id];
-        s_par[j] = pos;
-        s_beg[j] = V.child_off[pos];
+        const uint32_t b0 = V.child_off[pos], b1 = V.child_off[pos + 1];
+        s_beg[j] = b0;
+        s_cnt[j] = b1 - b0;
       }
       if (qa.sel) {
         int32_t* so = qa.sel + ((int64_t)qi * L + (L - lev)) * qa.r;
@@ -395,7 +406,7 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
         for (int j = 0; j < P; ++j) {
           const uint32_t e = lane * P + j;
           c[j] = 0;
-          if (e < kept) c[j] = V.child_off[s_par[e] + 1] - s_beg[e];
+          if (e < kept) c[j] = s_cnt[e];
           s += c[j];
         }
         uint32_t x = s;
@@ -490,24 +501,28 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   // LDS class from the beams and k; the BF16 re-rank set fits the class
   int need = qa.k > qa.r ? qa.k : qa.r;
   for (int l = 1; l <= a.n_levels; ++l) need = qa.r_lev[l] > need ? qa.r_lev[l] : need;
+  // Lane groups per row width, measured on MI355X (1M-point mixtures, beams
+  // 16/96/160): few lanes per row, each with several 16-byte vectors, and one
+  // or two rows in flight per group beat wide groups -- more rows per wave
+  // means more independent loads in flight and less per-row bookkeeping.
   if (!b16) {
     const int f4 = a.ld / 4;
     if (f4 <= 1) launch2<1, 1, 4, false>(a, qa, need, s);
-    else if (f4 <= 2) launch2<2, 1, 4, false>(a, qa, need, s);
-    else if (f4 <= 4) launch2<4, 1, 4, false>(a, qa, need, s);
-    else if (f4 <= 8) launch2<8, 1, 4, false>(a, qa, need, s);
-    else if (f4 <= 16) launch2<16, 1, 4, false>(a, qa, need, s);
-    else if (f4 <= 32) launch2<16, 2, 4, false>(a, qa, need, s);
-    else if (f4 <= 64) launch2<16, 4, 2, false>(a, qa, need, s);
+    else if (f4 <= 2) launch2<1, 2, 2, false>(a, qa, need, s);
+    else if (f4 <= 4) launch2<1, 4, 1, false>(a, qa, need, s);
+    else if (f4 <= 8) launch2<2, 4, 2, false>(a, qa, need, s);
+    else if (f4 <= 16) launch2<4, 4, 2, false>(a, qa, need, s);
+    else if (f4 <= 32) launch2<8, 4, 2, false>(a, qa, need, s);
+    else if (f4 <= 64) launch2<8, 8, 1, false>(a, qa, need, s);
     else launch2<16, 0, 1, false>(a, qa, need, s);
   } else {
     const int c8 = a.ldb / 8;
     if (c8 <= 1) launch2<1, 1, 4, true>(a, qa, need, s);
-    else if (c8 <= 2) launch2<2, 1, 4, true>(a, qa, need, s);
-    else if (c8 <= 4) launch2<4, 1, 4, true>(a, qa, need, s);
-    else if (c8 <= 8) launch2<8, 1, 4, true>(a, qa, need, s);
-    else if (c8 <= 16) launch2<16, 1, 4, true>(a, qa, need, s);
-    else if (c8 <= 32) launch2<16, 2, 4, true>(a, qa, need, s);
+    else if (c8 <= 2) launch2<1, 2, 2, true>(a, qa, need, s);
+    else if (c8 <= 4) launch2<1, 4, 1, true>(a, qa, need, s);
+    else if (c8 <= 8) launch2<2, 4, 1, true>(a, qa, need, s);
+    else if (c8 <= 16) launch2<4, 4, 1, true>(a, qa, need, s);
+    else if (c8 <= 32) launch2<8, 4, 1, true>(a, qa, need, s);
     else launch2<16, 0, 1, true>(a, qa, need, s);
   }
   check_launch("descent");

@@ -9,7 +9,9 @@
 // the arena block, copies them to the device, runs the ragged descent and
 // copies the results back, all on one of n_streams streams.  Up to n_streams
 // batches are in flight at once; requests that arrive meanwhile wait for a
-// stream and for arena space.  A finished batch (its event completed) hands
+// stream and for arena space.  With a batching window, a batch that is not
+// full waits until its oldest request has been queued for the window, so
+// that requests arriving close together share one launch.  A finished batch (its event completed) hands
 // every request its rows and the completion time and returns its arena block.
 // Each query's result is the same alone or in any batch (the descent runs one
 // query per workgroup).
@@ -88,6 +90,7 @@ struct Request {
   std::vector<int32_t> ids;
   std::vector<float> dist;
   double t_arrival = 0, t_done = 0;
+  double t_submit = 0;  // steady clock at submission (batching window)
   int state = 0;  // 0 queued, 1 on the device, 2 done
 };
 
@@ -135,6 +138,7 @@ struct mask_server {
   std::mutex mu;
   std::condition_variable cv;
   std::deque<mask::Request*> queue;
+  int64_t queued_queries = 0;
   std::unordered_map<uint64_t, mask::Request*> reqs;
   std::vector<mask::Batch> inflight;
   uint64_t next_ticket = 1;
@@ -178,8 +182,18 @@ bool retire(mask_server* s) {
   return any;
 }
 
+// Seconds until the queued partial batch may launch (0: now).
+double hold_time(const mask_server* s) {
+  if (s->p.batch_window_us <= 0 || s->stop || s->queue.empty()) return 0.0;
+  if (s->queued_queries >= s->p.max_batch_queries) return 0.0;
+  const double ready = s->queue.front()->t_submit + 1e-6 * s->p.batch_window_us;
+  const double now = now_seconds();
+  return ready > now ? ready - now : 0.0;
+}
+
 bool launch_one(mask_server* s) {
   if (s->queue.empty()) return false;
+  if (hold_time(s) > 0.0) return false;
   int stream = -1;
   for (size_t i = 0; i < s->stream_busy.size(); ++i)
     if (!s->stream_busy[i]) { stream = (int)i; break; }
@@ -224,6 +238,7 @@ bool launch_one(mask_server* s) {
   for (size_t i = 0; i < count; ++i) {
     Request* r = s->queue.front();
     s->queue.pop_front();
+    s->queued_queries -= r->n_q;
     r->state = 1;
     B.reqs.push_back(r);
     for (int j = 0; j < r->n_q; ++j, ++qi) {
@@ -275,8 +290,10 @@ void worker_loop(mask_server* s) {
     }
     if (s->stop && s->queue.empty() && s->inflight.empty()) break;
     if (!progress) {
-      if (s->inflight.empty()) s->cv.wait_for(lk, std::chrono::milliseconds(2));
-      else s->cv.wait_for(lk, std::chrono::microseconds(20));
+      double wait = s->inflight.empty() ? 2e-3 : 20e-6;
+      const double hold = hold_time(s);
+      if (hold > 0.0 && hold < wait) wait = hold;
+      s->cv.wait_for(lk, std::chrono::duration<double>(wait));
     }
   }
 }
@@ -302,6 +319,8 @@ mask_status mask_server_create(const mask_index* ix, const mask_server_params* p
     MASK_CHECK(p->arena_bytes >= 4096, "arena_bytes too small");
     MASK_CHECK(p->max_batch_queries >= 1, "max_batch_queries < 1");
     MASK_CHECK(p->n_streams >= 1 && p->n_streams <= 16, "n_streams must be in [1, 16]");
+    MASK_CHECK(p->batch_window_us >= 0 && p->batch_window_us <= 1000000,
+               "batch_window_us must be in [0, 1e6]");
     *out = nullptr;
     auto s = std::make_unique<mask_server>(a);
     s->ix = ix;
@@ -342,6 +361,7 @@ mask_status mask_server_submit(mask_server* s, const float* q_host, int32_t n_q,
     rq->k = k;
     rq->r = r;
     rq->t_arrival = t_arrival;
+    rq->t_submit = now_seconds();
     rq->q.assign(q_host, q_host + (size_t)n_q * s->ix->dim);
     {
       std::lock_guard<std::mutex> g(s->mu);
@@ -352,6 +372,7 @@ mask_status mask_server_submit(mask_server* s, const float* q_host, int32_t n_q,
       rq->ticket = s->next_ticket++;
       s->reqs[rq->ticket] = rq;
       s->queue.push_back(rq);
+      s->queued_queries += n_q;
       s->st.submitted_requests += 1;
       s->st.submitted_queries += n_q;
       *ticket = rq->ticket;

@@ -292,6 +292,26 @@ def test_batch_invariance(pk):
     assert np.array_equal(host(d3), host(dist)[p])
 
 
+def test_query_identical_across_lds_classes_and_runs(pk):
+    # Selections that need several rounds and several radix passes: the
+    # result must not depend on the LDS class (forced through the ragged
+    # entry point's r_max) nor change between runs.
+    import torch
+    X, Q = _mixture(60_000, 64, 120, seed=107, nq=3000)
+    gix = pk.mask_build(dev(X), [(20, 300), (1, 100)], iters=6, seed=4)
+    ids, dist = pk.mask_query(gix, dev(Q), 10, 64)
+    ids, dist = host(ids), host(dist)
+    for _ in range(2):
+        i2, d2 = pk.mask_query(gix, dev(Q), 10, 64)
+        assert np.array_equal(host(i2), ids)
+        assert np.array_equal(host(d2), dist)
+    ks = torch.full((3000,), 10, dtype=torch.int32)
+    rs = torch.full((3000,), 64, dtype=torch.int32)
+    i3, d3, off = pk.mask_query_ragged(gix, dev(Q), ks, rs, k_max=10, r_max=600)
+    assert np.array_equal(host(i3).reshape(3000, 10), ids)
+    assert np.array_equal(host(d3).reshape(3000, 10), dist)
+
+
 def test_build_is_deterministic(pk):
     X, _ = _mixture(20_000, 16, 50, seed=111)
     levels = [(10, 100), (1, 50)]

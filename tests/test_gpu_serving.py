@@ -42,7 +42,9 @@ def _drain(srv, tickets, timeout=60.0):
 def test_results_in_the_mix_equal_results_alone(setup):
     pk, ix, Q = setup
     g = np.random.default_rng(11)
-    srv = pk.MaskServer(ix, arena_bytes=64 << 20, max_batch_queries=2048, n_streams=3)
+    # a 20 ms batching window: requests submitted back to back share launches
+    srv = pk.MaskServer(ix, arena_bytes=64 << 20, max_batch_queries=2048, n_streams=3,
+                        batch_window_us=20_000)
     reqs, tickets = [], []
     pos = 0
     for _ in range(120):
@@ -90,3 +92,20 @@ def test_latency_stamps(setup):
     ids, dist, t_done = _drain(srv, [t])[t]
     srv.close()
     assert t_done >= t0 and t_done - t0 < 5.0
+
+
+def test_batching_window_holds_partial_batches(setup):
+    pk, ix, Q = setup
+    srv = pk.MaskServer(ix, arena_bytes=16 << 20, max_batch_queries=64, n_streams=1,
+                        batch_window_us=50_000)
+    t0 = pk.mask_clock()
+    t1 = srv.submit(Q[:8], 5, 4, t_arrival=t0)
+    _, _, t_done = _drain(srv, [t1])[t1]
+    assert t_done - t0 >= 0.05  # a partial batch waits out the window
+    t0 = pk.mask_clock()
+    t2 = srv.submit(Q[:64], 5, 4, t_arrival=t0)  # a full batch launches at once
+    ids, _, t_done = _drain(srv, [t2])[t2]
+    srv.close()
+    assert t_done - t0 < 0.05
+    i1, _ = pk.mask_query(ix, dev(Q[:64]), 5, 4)
+    assert np.array_equal(ids, host(i1))
