@@ -70,8 +70,14 @@ typedef enum { MASK_DENSE = 0, MASK_CSR = 1 } mask_layout;
 /* A matrix of n rows (points or queries) with dim columns, device memory.
  * DENSE: x is row-major n x dim float32 with row stride ld floats
  *        (ld == 0 means ld = dim).
- * CSR:   indptr int64[n+1], indices int32[nnz] (column ids, each < dim),
- *        values float32[nnz].  (Sparse input: see mask_build.) */
+ * CSR:   indptr int64[n+1] rising from 0 to nnz, indices int32[nnz]
+ *        (column ids strictly increasing within a row, each < dim), values
+ *        float32[nnz]; nnz < 2^31, dim <= 16384.  CSR data (Section 4.3: the
+ *        high-dimensional sparse setting) builds a CSR index: L2 metric, FP32
+ *        form, distances |x|^2 + |c|^2 - 2 x.c evaluated in float64; its
+ *        queries are CSR as well.  mask_build, mask_import and mask_kmeans
+ *        check the structure on the device (MASK_ERR_INVALID); queries are
+ *        not checked. */
 typedef struct {
   int32_t layout;
   int64_t n;
@@ -115,6 +121,8 @@ typedef struct {
   int64_t device_bytes;      /* device memory held by the index */
   int64_t refined_last_level;/* points re-scored in direct form by the last
                                 assignment of the build (plain form) */
+  int32_t layout;            /* mask_layout of the data (CSR index or dense) */
+  int64_t nnz;               /* non-zeros of the data (CSR index) */
 } mask_info;
 
 /* Level schedule of Algorithm 1: ngroups = n / length_group (floor); every
@@ -125,8 +133,10 @@ typedef struct {
 mask_status mask_plan_levels(int64_t n, int32_t length_group, int32_t n_centroids,
                              mask_level* out, int32_t cap, int32_t* n_levels);
 
-/* Algorithm 1.  data: device matrix (DENSE; dim <= 256 for the MFMA
- * assignment).  Level 0 is permuted by the argsort of the SplitMix64
+/* Algorithm 1.  data: device matrix (DENSE with dim <= 256 for the MFMA
+ * assignment, or CSR: every level's prototypes are then dense rows, and the
+ * items of the next level are those prototypes with their zeros dropped).
+ * Level 0 is permuted by the argsort of the SplitMix64
  * outputs h(seed, i) (or by p->perm) and split into levels[0].n_chunks
  * groups; each group runs lloyd_iters Lloyd iterations starting from its
  * first k members, then a final assignment.  Each chunk must hold at least k
@@ -136,8 +146,8 @@ mask_status mask_plan_levels(int64_t n, int32_t length_group, int32_t n_centroid
 mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
                        const mask_allocator* a, void* hip_stream, mask_index** out);
 
-/* Algorithm 2 with a beam: for each of the q->n queries (device, DENSE,
- * dim equal to the index's) keep the r nearest prototypes of the top level,
+/* Algorithm 2 with a beam: for each of the q->n queries (device, DENSE, or
+ * CSR for a CSR index; dim equal to the index's) keep the r nearest prototypes of the top level,
  * then at each level below the r nearest children of those, then return the
  * k nearest data points under the kept level-1 prototypes.  Ranking key:
  * (distance, original id).  out_ids: device int32[q->n * k] (original data
@@ -201,7 +211,7 @@ mask_status mask_import(const mask_matrix* data, int32_t n_levels, const mask_le
                         mask_index** out);
 
 /* The batched per-group k-means of Algorithm 1 on its own (the build's
- * inner loop): items (device, DENSE, n x dim) are split into n_chunks
+ * inner loop): items (device, DENSE or CSR, n x dim) are split into n_chunks
  * contiguous groups of nearly equal size; group c uses prototypes
  * centroids[c*k .. c*k+k-1].  init: device float32[n_chunks*k*dim] starting
  * prototypes, or NULL for the first k items of each group.  Runs `iters`
@@ -246,7 +256,8 @@ typedef struct {
 double mask_clock(void);
 
 /* The index must outlive the server.  The arena comes from the allocator
- * (NULL: hipMalloc); staging memory of the same size is pinned host memory. */
+ * (NULL: hipMalloc); staging memory of the same size is pinned host memory.
+ * Dense indexes only (MASK_ERR_UNSUPPORTED for a CSR index). */
 mask_status mask_server_create(const mask_index* ix, const mask_server_params* p,
                                const mask_allocator* a, mask_server** out);
 

@@ -55,7 +55,8 @@ class mask_info(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("n_levels", ctypes.c_int32),
                 ("metric", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("level_size", ctypes.c_int64 * MAX_LEVELS), ("device_bytes", ctypes.c_int64),
-                ("refined_last_level", ctypes.c_int64)]
+                ("refined_last_level", ctypes.c_int64), ("layout", ctypes.c_int32),
+                ("nnz", ctypes.c_int64)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -148,6 +149,60 @@ def _stream_handle(stream) -> int:
     return int(stream.cuda_stream)
 
 
+class CsrTensor:
+    """CSR rows on the device: indptr int64[n+1], indices int32[nnz] (strictly
+    increasing within a row), values float32[nnz], ``n_cols`` columns."""
+
+    def __init__(self, indptr, indices, values, n_cols: int):
+        torch = _torch()
+        for t, dt in ((indptr, torch.int64), (indices, torch.int32), (values, torch.float32)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or t.dim() != 1:
+                raise MaskError(1, "CSR arrays: CUDA tensors indptr int64, indices int32, "
+                                   "values float32")
+        self.indptr = indptr.contiguous()
+        self.indices = indices.contiguous()
+        self.values = values.contiguous()
+        self.n_cols = int(n_cols)
+
+    @classmethod
+    def from_host(cls, indptr, indices, values, n_cols: int, device="cuda"):
+        torch = _torch()
+        return cls(torch.from_numpy(np.ascontiguousarray(indptr, dtype=np.int64)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(indices, dtype=np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(values, dtype=np.float32)).to(device),
+                   n_cols)
+
+    @property
+    def shape(self):
+        return (self.indptr.shape[0] - 1, self.n_cols)
+
+    @property
+    def device(self):
+        return self.indptr.device
+
+    def rows(self, lo: int, hi: int) -> "CsrTensor":
+        """Rows lo..hi-1 as a new CsrTensor (device copies)."""
+        ptr = self.indptr[lo:hi + 1]
+        b, e = int(ptr[0].item()), int(ptr[-1].item())
+        return CsrTensor((ptr - b).contiguous(), self.indices[b:e].clone(),
+                         self.values[b:e].clone(), self.n_cols)
+
+
+def _matrix(t) -> mask_matrix:
+    if isinstance(t, CsrTensor):
+        m = mask_matrix()
+        m.layout = 1
+        m.n = t.shape[0]
+        m.dim = t.n_cols
+        m.ld = 0
+        m.indptr = t.indptr.data_ptr()
+        m.indices = t.indices.data_ptr()
+        m.values = t.values.data_ptr()
+        m.nnz = t.indices.shape[0]
+        return m
+    return _dense(t)
+
+
 def _dense(t) -> mask_matrix:
     torch = _torch()
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2:
@@ -199,7 +254,8 @@ class Index:
                 "precision": inf.precision,
                 "level_size": [inf.level_size[i] for i in range(inf.n_levels)],
                 "device_bytes": inf.device_bytes,
-                "refined_last_level": inf.refined_last_level}
+                "refined_last_level": inf.refined_last_level,
+                "layout": "csr" if inf.layout == 1 else "dense", "nnz": inf.nnz}
 
     def export_level(self, level: int) -> Tuple[np.ndarray, np.ndarray]:
         """(prototypes n_l x dim in chunk-major id order, parent id of each
@@ -257,9 +313,10 @@ def _params(levels, iters, seed, metric, precision, rerank_factor, perm):
 def mask_build(data, levels: Sequence[Tuple[int, int]], iters: int = 30, seed: int = 0,
                metric: str = "l2", precision: str = "fp32", perm=None, rerank_factor: int = 4,
                stream=None, torch_allocator: bool = True) -> Index:
-    """Algorithm 1 on a device tensor (n x dim float32); returns the index."""
+    """Algorithm 1 on a device tensor (n x dim float32) or a CsrTensor;
+    returns the index."""
     torch = _torch()
-    m = _dense(data)
+    m = _matrix(data)
     if perm is not None and (perm.dtype != torch.int32 or not perm.is_cuda):
         raise MaskError(1, "perm must be an int32 CUDA tensor")
     p, lv = _params(levels, iters, seed, metric, precision, rerank_factor, perm)
@@ -276,7 +333,7 @@ def mask_query(index: Index, queries, k: int, r: int, stream=None, debug: bool =
     tensors of shape (nq, k), plus the kept prototypes per level when
     ``debug``."""
     torch = _torch()
-    m = _dense(queries)
+    m = _matrix(queries)
     nq = queries.shape[0]
     ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
     dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
@@ -295,7 +352,7 @@ def mask_query_beams(index: Index, queries, k: int, beams: Sequence[int], stream
     """Descent keeping beams[i] prototypes at level i counted from the top;
     returns (ids, dist) like mask_query."""
     torch = _torch()
-    m = _dense(queries)
+    m = _matrix(queries)
     nq = queries.shape[0]
     b = (ctypes.c_int32 * len(beams))(*[int(x) for x in beams])
     ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
@@ -312,7 +369,7 @@ def mask_query_ragged(index: Index, queries, k_i, r_i, stream=None, k_max: int =
     k_max / r_max: bounds passed to the library (raised to the largest k_i /
     r_i when smaller)."""
     torch = _torch()
-    m = _dense(queries)
+    m = _matrix(queries)
     k_i = k_i.to(device=queries.device, dtype=torch.int32).contiguous()
     r_i = r_i.to(device=queries.device, dtype=torch.int32).contiguous()
     off = torch.zeros(queries.shape[0] + 1, dtype=torch.int64, device=queries.device)
@@ -338,7 +395,7 @@ def mask_import(data, levels: Sequence[Tuple[int, int]], protos: Sequence[np.nda
     """Index from prototypes (chunk-major, per level) and parent ids (per
     level, for the items one level down), e.g. built by another
     implementation."""
-    m = _dense(data)
+    m = _matrix(data)
     L = len(levels)
     P = [np.ascontiguousarray(p, dtype=np.float32) for p in protos]
     Q = [np.ascontiguousarray(q, dtype=np.int32) for q in parents]
@@ -355,10 +412,10 @@ def mask_import(data, levels: Sequence[Tuple[int, int]], protos: Sequence[np.nda
 
 def mask_kmeans(items, n_chunks: int, k: int, iters: int, init=None, metric: str = "l2",
                 stream=None):
-    """Batched per-group Lloyd on a device tensor; returns (centroids
+    """Batched per-group Lloyd on a device tensor or CsrTensor; returns (centroids
     (n_chunks*k x dim), labels int32, inertia float64 (iters x n_chunks))."""
     torch = _torch()
-    m = _dense(items)
+    m = _matrix(items)
     dim = items.shape[1]
     cent = torch.empty((n_chunks * k, dim), dtype=torch.float32, device=items.device)
     labels = torch.empty(items.shape[0], dtype=torch.int32, device=items.device)

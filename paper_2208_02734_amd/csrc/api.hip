@@ -103,6 +103,40 @@ void check_dense(const mask_matrix* m, const char* what) {
 
 int ld_of(const mask_matrix* m) { return m->ld ? m->ld : m->dim; }
 
+void check_csr(const mask_matrix* m, const char* what) {
+  MASK_CHECK(m != nullptr, std::string(what) + " is NULL");
+  MASK_CHECK(m->layout == MASK_CSR, std::string(what) + ": CSR expected");
+  MASK_CHECK(m->n >= 0 && m->dim >= 1, std::string(what) + ": bad shape");
+  MASK_CHECK(m->nnz >= 0 && m->nnz < ((int64_t)1 << 31), std::string(what) + ": nnz out of range");
+  MASK_CHECK(m->n == 0 || m->indptr != nullptr, std::string(what) + ": indptr is NULL");
+  MASK_CHECK(m->nnz == 0 || (m->indices && m->values), std::string(what) + ": arrays are NULL");
+  if (m->dim > kMaxSparseDim)
+    throw Error{MASK_ERR_UNSUPPORTED, std::string(what) + ": more than 16384 columns"};
+}
+
+Csr csr_view(const mask_matrix* m) {
+  Csr c;
+  c.n = m->n;
+  c.cols = m->dim;
+  c.nnz = m->nnz;
+  c.ptr = const_cast<int64_t*>(m->indptr);
+  c.col = const_cast<int32_t*>(m->indices);
+  c.val = const_cast<float*>(m->values);
+  return c;
+}
+
+// Device-side structure check of a CSR argument (synchronises the stream).
+void validate_csr(const mask_matrix* m, const char* what, Arena& scratch, hipStream_t s) {
+  uint32_t* flag = scratch.alloc<uint32_t>(1);
+  csr_validate(m->indptr, m->indices, m->n, m->dim, m->nnz, flag, s);
+  uint32_t h = 0;
+  MASK_HIP(hipMemcpyAsync(&h, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  MASK_HIP(hipStreamSynchronize(s));
+  MASK_CHECK(h == 0, std::string(what) +
+                         ": indptr must rise from 0 to nnz and every row's column ids must "
+                         "be strictly increasing and below dim");
+}
+
 void check_levels(int64_t n, int n_levels, const mask_level* levels, std::vector<int64_t>& sizes) {
   MASK_CHECK(n_levels >= 1 && n_levels <= kMaxLevels, "n_levels must be in [1, 16]");
   MASK_CHECK(levels != nullptr, "levels is NULL");
@@ -131,7 +165,8 @@ mask_status fail(const Error& e) {
 // data row ids; protos_cm[l] are the chunk-major prototypes.
 void finalize_layout(mask_index& ix, const std::vector<int32_t*>& labels,
                      const std::vector<float*>& protos_cm, const float* items0,
-                     const uint32_t* items0_orig, Arena& scratch, hipStream_t s) {
+                     const uint32_t* items0_orig, Arena& scratch, hipStream_t s,
+                     const Csr* items0_csr = nullptr) {
   const int L = ix.n_levels;
   const int ld = ix.ld, dim = ix.dim;
   int64_t max_items = 0;
@@ -169,9 +204,18 @@ void finalize_layout(mask_index& ix, const std::vector<int32_t*>& labels,
       for (int64_t p = 0; p < n_par; ++p) mx = std::max<int64_t>(mx, off[p + 1] - off[p]);
       ix.max_children[l] = mx;
     }
-    ix.protos[l - 1] = ix.mem.alloc<float>(n_items * ld);
     ix.orig[l - 1] = ix.mem.alloc<int32_t>(n_items);
-    if (l - 1 >= 1) {
+    if (l - 1 >= 1 || !items0_csr) ix.protos[l - 1] = ix.mem.alloc<float>(n_items * ld);
+    if (l - 1 == 0 && items0_csr) {
+      // CSR data: rows in leaf order
+      Csr leaf;
+      csr_gather(*items0_csr, ord, n_items, leaf, ix.mem, scratch, s);
+      ix.sp_ptr = leaf.ptr;
+      ix.sp_col = leaf.col;
+      ix.sp_val = leaf.val;
+      ix.sp_nnz = leaf.nnz;
+      gather_u32(items0_orig, ord, n_items, reinterpret_cast<uint32_t*>(ix.orig[0]), s);
+    } else if (l - 1 >= 1) {
       gather_rows(protos_cm[l - 1], ld, ord, n_items, ld, ix.protos[l - 1], ld, s);
       MASK_HIP(hipMemcpyAsync(ix.orig[l - 1], ord, n_items * sizeof(int32_t),
                               hipMemcpyDeviceToDevice, s));
@@ -183,6 +227,13 @@ void finalize_layout(mask_index& ix, const std::vector<int32_t*>& labels,
     }
   }
   (void)dim;
+  if (ix.sparse) {
+    // FP64 norms of the dense prototype rows (position order)
+    for (int l = 1; l <= L; ++l) {
+      ix.norm64[l] = ix.mem.alloc<double>(ix.level_n[l]);
+      dense_norms64(ix.protos[l], ld, ix.level_n[l], ix.dim, ix.norm64[l], s);
+    }
+  }
   if (ix.precision == MASK_BF16) {
     // BF16 copies of every level in position order, and the data row -> leaf
     // position map used by the FP32 re-rank
@@ -237,6 +288,49 @@ void run_level(const float* items, int64_t n_items, int ld, int dim, int C, int 
   }
 }
 
+// Algorithm 1 on CSR data: level 0 is the permuted CSR rows, every level's
+// prototypes are dense rows, and the items of the next level are those
+// prototypes as CSR (zeros dropped).
+void build_sparse(mask_index& ix, const mask_matrix* data, const mask_build_params* p,
+                  const mask_allocator* a, hipStream_t s) {
+  const int L = p->n_levels;
+  const int64_t n = data->n;
+  const int ld = ix.ld;
+  const std::vector<int64_t>& sizes = ix.level_n;
+  Arena scratch(a, s);
+  validate_csr(data, "data", scratch, s);
+  uint32_t* perm = scratch.alloc<uint32_t>(n);
+  if (p->perm) {
+    MASK_HIP(hipMemcpyAsync(perm, p->perm, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  } else {
+    uint64_t* keys = scratch.alloc<uint64_t>(n);
+    SortWork sw;
+    sort_work_alloc(sw, n, true, scratch);
+    splitmix_keys(p->seed, n, keys, perm, s);
+    radix_sort_u64(keys, perm, n, 64, sw, s);
+  }
+  Csr items0;
+  csr_gather(csr_view(data), perm, n, items0, scratch, scratch, s);
+  BuildState st;
+  st.labels.assign(L + 1, nullptr);
+  st.protos_cm.assign(L + 1, nullptr);
+  Csr items = items0;
+  for (int l = 1; l <= L; ++l) {
+    const int C = p->levels[l - 1].n_chunks, k = p->levels[l - 1].k;
+    st.protos_cm[l] = scratch.alloc<float>(sizes[l] * ld);
+    st.labels[l] = scratch.alloc<int32_t>(sizes[l - 1]);
+    {
+      Arena level_scratch(a, s);
+      kmeans_sparse(items, ld, C, k, p->lloyd_iters, nullptr, st.protos_cm[l], st.labels[l],
+                    nullptr, level_scratch, s);
+      MASK_HIP(hipStreamSynchronize(s));
+    }
+    if (l < L) csr_from_dense(st.protos_cm[l], ld, sizes[l], ix.dim, items, scratch, scratch, s);
+  }
+  finalize_layout(ix, st.labels, st.protos_cm, nullptr, perm, scratch, s, &items0);
+  MASK_HIP(hipStreamSynchronize(s));
+}
+
 DescentArgs descent_args(const mask_index& ix) {
   DescentArgs a{};
   a.n_levels = ix.n_levels;
@@ -248,7 +342,9 @@ DescentArgs descent_args(const mask_index& ix) {
   a.rerank_factor = ix.rerank_factor;
   a.inv0 = ix.inv0;
   a.max_leaf_children = ix.max_children[1];
+  a.sparse = ix.sparse;
   for (int l = 0; l <= ix.n_levels; ++l) {
+    a.lv[l].norm64 = ix.norm64[l];
     a.lv[l].protos = ix.protos[l];
     a.lv[l].protos_b = ix.protos_b[l];
     a.lv[l].orig = ix.orig[l];
@@ -256,6 +352,9 @@ DescentArgs descent_args(const mask_index& ix) {
     a.lv[l].child_off = ix.child_off[l];
     a.lv[l].n = ix.level_n[l];
   }
+  a.lv[0].sp_ptr = ix.sp_ptr;
+  a.lv[0].sp_col = ix.sp_col;
+  a.lv[0].sp_val = ix.sp_val;
   return a;
 }
 
@@ -265,7 +364,8 @@ mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, in
                        const int32_t* r_levels = nullptr) {
   try {
     MASK_CHECK(ix != nullptr, "index is NULL");
-    check_dense(q, "queries");
+    if (ix->sparse) check_csr(q, "queries (CSR index)");
+    else check_dense(q, "queries");
     MASK_CHECK(q->dim == ix->dim, "query dim differs from the index dim");
     MASK_CHECK(k >= 1 && k <= kMaxBeam, "k must be in [1, 2048]");
     MASK_CHECK(r >= 1 && r <= kMaxBeam, "r must be in [1, 2048]");
@@ -274,8 +374,14 @@ mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, in
     MASK_CHECK(out_ids && out_dist, "output pointer is NULL");
     hipStream_t s = (hipStream_t)hip_stream;
     QueryArgs qa{};
-    qa.Q = q->x;
-    qa.ldq = ld_of(q);
+    if (ix->sparse) {
+      qa.q_ptr = q->indptr;
+      qa.q_col = q->indices;
+      qa.q_val = q->values;
+    } else {
+      qa.Q = q->x;
+      qa.ldq = ld_of(q);
+    }
     qa.nq = q->n;
     qa.k = k;
     qa.r = r;
@@ -388,7 +494,10 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
   try {
     MASK_CHECK(out != nullptr, "out is NULL");
     *out = nullptr;
-    check_dense(data, "data");
+    MASK_CHECK(data != nullptr, "data is NULL");
+    const bool sparse = data->layout == MASK_CSR;
+    if (sparse) check_csr(data, "data");
+    else check_dense(data, "data");
     MASK_CHECK(p != nullptr, "params is NULL");
     MASK_CHECK(p->metric == MASK_L2 || p->metric == MASK_L1, "unknown metric");
     MASK_CHECK(p->precision >= MASK_FP32 && p->precision <= MASK_FP8_E4M3, "unknown precision");
@@ -396,7 +505,10 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
     MASK_CHECK(data->n >= 1 && data->n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
     std::vector<int64_t> sizes;
     check_levels(data->n, p->n_levels, p->levels, sizes);
-    if (data->dim > kMaxDenseDim) throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};
+    if (sparse && (p->metric != MASK_L2 || p->precision != MASK_FP32))
+      throw Error{MASK_ERR_UNSUPPORTED, "CSR data: L2 metric, FP32 form only"};
+    if (!sparse && data->dim > kMaxDenseDim)
+      throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};
     if (p->precision == MASK_FP8_E4M3) throw Error{MASK_ERR_UNSUPPORTED, "FP8 form"};
     if (p->precision == MASK_BF16 && p->metric != MASK_L2)
       throw Error{MASK_ERR_UNSUPPORTED, "BF16 form of L1"};
@@ -414,6 +526,12 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
     ix->rerank_factor = p->rerank_factor > 0 ? p->rerank_factor : 4;
     const int ld = ix->ld;
     const int64_t n = data->n;
+    if (sparse) {
+      ix->sparse = true;
+      build_sparse(*ix, data, p, a, s);
+      *out = ix.release();
+      return MASK_OK;
+    }
 
     Arena scratch(a, s);
     // level-0 order
@@ -522,6 +640,8 @@ mask_status mask_index_info(const mask_index* ix, mask_info* out) {
   for (int l = 1; l <= ix->n_levels; ++l) out->level_size[l - 1] = ix->level_n[l];
   out->device_bytes = (int64_t)ix->mem.bytes();
   out->refined_last_level = ix->refined_last;
+  out->layout = ix->sparse ? MASK_CSR : MASK_DENSE;
+  out->nnz = ix->sp_nnz;
   return MASK_OK;
 }
 
@@ -563,14 +683,17 @@ mask_status mask_import(const mask_matrix* data, int32_t n_levels, const mask_le
   try {
     MASK_CHECK(out != nullptr, "out is NULL");
     *out = nullptr;
-    check_dense(data, "data");
+    MASK_CHECK(data != nullptr, "data is NULL");
+    const bool sparse = data->layout == MASK_CSR;
+    if (sparse) check_csr(data, "data");
+    else check_dense(data, "data");
     MASK_CHECK(data->n >= 1 && data->n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
     MASK_CHECK(protos_host && parents_host, "host arrays are NULL");
     std::vector<int64_t> sizes;
     check_levels(data->n, n_levels, levels, sizes);
     const int metric = p ? p->metric : MASK_L2;
     MASK_CHECK(metric == MASK_L2 || metric == MASK_L1, "unknown metric");
-    if (data->dim > kMaxQueryDim) throw Error{MASK_ERR_UNSUPPORTED, "dim above 4096"};
+    if (!sparse && data->dim > kMaxQueryDim) throw Error{MASK_ERR_UNSUPPORTED, "dim above 4096"};
     for (int l = 0; l < n_levels; ++l) {
       MASK_CHECK(protos_host[l] && parents_host[l], "a level's host array is NULL");
       for (int64_t i = 0; i < sizes[l]; ++i)
@@ -585,14 +708,24 @@ mask_status mask_import(const mask_matrix* data, int32_t n_levels, const mask_le
     ix->metric = metric;
     ix->precision = p ? p->precision : MASK_FP32;
     MASK_CHECK(ix->precision == MASK_FP32 || ix->precision == MASK_BF16, "unsupported precision");
+    if (sparse && (ix->precision != MASK_FP32 || metric != MASK_L2))
+      throw Error{MASK_ERR_UNSUPPORTED, "CSR data: L2 metric, FP32 form only"};
+    ix->sparse = sparse;
     ix->rerank_factor = (p && p->rerank_factor > 0) ? p->rerank_factor : 4;
     ix->n_levels = L;
     ix->levels.assign(levels, levels + L);
     ix->level_n = sizes;
     const int ld = ix->ld, dim = ix->dim;
     Arena scratch(a, s);
-    float* items0 = scratch.alloc<float>(data->n * ld);
-    copy_rows(data->x, ld_of(data), data->n, dim, items0, ld, s);
+    float* items0 = nullptr;
+    Csr view;
+    if (sparse) {
+      validate_csr(data, "data", scratch, s);
+      view = csr_view(data);
+    } else {
+      items0 = scratch.alloc<float>(data->n * ld);
+      copy_rows(data->x, ld_of(data), data->n, dim, items0, ld, s);
+    }
     uint32_t* ident = scratch.alloc<uint32_t>(data->n);
     iota_u32(ident, data->n, s);
     BuildState st;
@@ -611,7 +744,8 @@ mask_status mask_import(const mask_matrix* data, int32_t n_levels, const mask_le
       MASK_HIP(hipMemcpy(st.labels[l], parents_host[l - 1], sizes[l - 1] * sizeof(int32_t),
                          hipMemcpyHostToDevice));
     }
-    finalize_layout(*ix, st.labels, st.protos_cm, items0, ident, scratch, s);
+    finalize_layout(*ix, st.labels, st.protos_cm, items0, ident, scratch, s,
+                    sparse ? &view : nullptr);
     MASK_HIP(hipStreamSynchronize(s));
     *out = ix.release();
     return MASK_OK;
@@ -630,6 +764,30 @@ mask_status mask_kmeans(const mask_matrix* items, int32_t n_chunks, int32_t k, i
                         double* inertia, const mask_allocator* a, void* hip_stream) {
   hipStream_t s = (hipStream_t)hip_stream;
   try {
+    MASK_CHECK(items != nullptr, "items is NULL");
+    if (items->layout == MASK_CSR) {
+      check_csr(items, "items");
+      MASK_CHECK(items->n >= 1 && items->n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
+      MASK_CHECK(n_chunks >= 1 && k >= 1 && iters >= 0, "bad n_chunks, k or iters");
+      MASK_CHECK(items->n / n_chunks >= k, "a chunk holds fewer items than k");
+      MASK_CHECK(centroids && labels, "output pointer is NULL");
+      if (metric != MASK_L2) throw Error{MASK_ERR_UNSUPPORTED, "CSR items: L2 metric only"};
+      const int dim = items->dim, ld = round_up4(dim);
+      const int64_t np = (int64_t)n_chunks * k;
+      Arena scratch(a, s);
+      validate_csr(items, "items", scratch, s);
+      float* P = scratch.alloc<float>(np * ld);
+      float* init_p = nullptr;
+      if (init) {
+        init_p = scratch.alloc<float>(np * ld);
+        copy_rows(init, dim, np, dim, init_p, ld, s);
+      }
+      kmeans_sparse(csr_view(items), ld, n_chunks, k, iters, init_p, P, labels, inertia, scratch,
+                    s);
+      copy_rows(P, ld, np, dim, centroids, dim, s);
+      MASK_HIP(hipStreamSynchronize(s));
+      return MASK_OK;
+    }
     check_dense(items, "items");
     MASK_CHECK(items->n >= 1 && items->n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
     MASK_CHECK(n_chunks >= 1 && k >= 1 && iters >= 0, "bad n_chunks, k or iters");

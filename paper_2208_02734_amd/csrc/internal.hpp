@@ -20,6 +20,7 @@ constexpr int kMaxDenseDim = 256;   // MFMA assignment keeps point rows in regis
 constexpr int kMaxQueryDim = 4096;  // the descent stages one query row in LDS
 constexpr int kMaxBeam = 2048;      // r and k limit of one descent workgroup
 constexpr int kMaxRerank = 2048;    // largest FP32 re-rank set of the BF16 form
+constexpr int kMaxSparseDim = 16384; // CSR columns: the descent scatters a query row in LDS
 
 // ------------------------------------------------------------------ errors
 
@@ -271,15 +272,58 @@ void kmeans_proto_norms(const float* protos, int ld, int64_t n_protos, KmeansWor
 void kmeans_init_first(const float* items, int ld, const ChunkPlan& plan, float* protos,
                        hipStream_t s);
 
+// ------------------------------------------------------------ CSR rows
+// (sparse.hip)
+
+// Device CSR matrix: n rows over `cols` columns, int64 row pointers, column
+// ids distinct within a row, FP32 values.
+struct Csr {
+  int64_t n = 0;
+  int cols = 0;
+  int64_t nnz = 0;
+  int64_t* ptr = nullptr;
+  int32_t* col = nullptr;
+  float* val = nullptr;
+};
+
+// out = rows idx[0..n) of src, in that order (new arrays from `a`).
+void csr_gather(const Csr& src, const uint32_t* idx, int64_t n, Csr& out, Arena& a,
+                Arena& scratch, hipStream_t s);
+// CSR of a dense row-major matrix (n x ld, the first `cols` columns), zeros dropped.
+void csr_from_dense(const float* x, int ld, int64_t n, int cols, Csr& out, Arena& a,
+                    Arena& scratch, hipStream_t s);
+// FP64 squared norm of every CSR row / dense row.
+void csr_norms64(const Csr& x, double* out, hipStream_t s);
+void dense_norms64(const float* x, int ld, int64_t n, int cols, double* out, hipStream_t s);
+// Checks that column ids are in range and strictly increasing within each
+// row and that the row pointers are non-decreasing; flag (device) set to 1
+// on a violation.
+void csr_validate(const int64_t* ptr, const int32_t* col, int64_t n, int cols, int64_t nnz,
+                  uint32_t* flag, hipStream_t s);
+
+// Lloyd on CSR items (chunk-contiguous rows): prototypes dense row-major
+// (n_chunks*k x ld, zero padded; init: device rows of the same shape or null
+// for the first k items of every group), FP64 expanded-form distances, FP64
+// means.  inertia_log: device [iters * n_chunks] or null.
+void kmeans_sparse(const Csr& items, int ld, int n_chunks, int k, int iters, const float* init,
+                   float* protos, int32_t* labels, double* inertia_log, Arena& scratch,
+                   hipStream_t s);
+
 // ------------------------------------------------------------ descent
 // (query.hip)
 
 struct LevelView {
-  const float* protos;       // n x ld, position order
+  const float* protos;       // n x ld, position order (null for CSR data)
   const uint16_t* protos_b;  // n x ldb BF16 copy (BF16 form), position order
   const int32_t* orig;       // position -> chunk-major id (data row id at level 0)
   const int32_t* inv;        // chunk-major id -> position (levels >= 1)
   const uint32_t* child_off; // n + 1 offsets into the level below (levels >= 1)
+  // CSR index: level 0 rows in CSR (leaf order) and the FP64 squared norm of
+  // every row of every level (position order)
+  const int64_t* sp_ptr;
+  const int32_t* sp_col;
+  const float* sp_val;
+  const double* norm64;
   int64_t n;
 };
 
@@ -294,11 +338,16 @@ struct DescentArgs {
   int precision;
   int rerank_factor;
   int64_t max_leaf_children;  // largest child count of a level-1 prototype
+  bool sparse;                // CSR index (dim = number of columns)
 };
 
 struct QueryArgs {
   const float* Q;
   int ldq;
+  // CSR queries (sparse index): row pointers, column ids, values (device)
+  const int64_t* q_ptr;
+  const int32_t* q_col;
+  const float* q_val;
   int64_t nq;
   int k, r;                 // uniform values, or the maxima when k_arr / r_arr are set
   int r_lev[kMaxLevels + 1];  // beam per level (index = level), 0 = use r
@@ -337,5 +386,12 @@ struct mask_index {
   int32_t* inv[mask::kMaxLevels + 1] = {};
   uint32_t* child_off[mask::kMaxLevels + 1] = {};
   int64_t refined_last = 0;
+  // CSR index: data rows in CSR, leaf order; FP64 squared norms per level
+  bool sparse = false;
+  int64_t* sp_ptr = nullptr;
+  int32_t* sp_col = nullptr;
+  float* sp_val = nullptr;
+  int64_t sp_nnz = 0;
+  double* norm64[mask::kMaxLevels + 1] = {};
   explicit mask_index(const mask_allocator* a, hipStream_t s) : mem(a, s) {}
 };

@@ -863,22 +863,26 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_bf16(
   const uint16_t* cbase = protos + (int64_t)chunk * k * ldb;
   const float* nbase = pnorm + (int64_t)chunk * k;
   const int ntiles = (k + TN - 1) / TN;
+  // The next tile's loads are issued before the current tile's MFMA work
+  // and consumed only after it: indexes are clamped instead of branched on
+  // and nothing is computed on a loaded value before the store to LDS, so no
+  // wait for them sits inside the loop.  s_hn holds -|c|^2 / 2 (-inf past k).
   uint4 stage[LOADS];
-  float hstage = INFINITY;
+  float hstage = 0.f;
+  int tile_base = 0;
   auto load_tile = [&](int t) {
+    tile_base = t * TN;
 #pragma unroll
     for (int i = 0; i < LOADS; ++i) {
       const int idx = threadIdx.x + i * kBlock;
       const int row = idx / V_PER_ROW, v8 = idx % V_PER_ROW;
-      const int j = t * TN + row;
-      stage[i] = (j < k && v8 * 8 < ldb)
-                     ? *reinterpret_cast<const uint4*>(cbase + (int64_t)j * ldb + v8 * 8)
-                     : make_uint4(0, 0, 0, 0);
+      const int j = min(t * TN + row, k - 1);
+      const bool in_row = v8 * 8 < ldb;  // rows are ldb wide, the tile DP
+      const uint4 v =
+          *reinterpret_cast<const uint4*>(cbase + (int64_t)j * ldb + (in_row ? v8 * 8 : 0));
+      stage[i] = in_row ? v : make_uint4(0, 0, 0, 0);
     }
-    if (threadIdx.x < TN) {
-      const int j = t * TN + threadIdx.x;
-      hstage = (j < k) ? 0.5f * nbase[j] : INFINITY;
-    }
+    if (threadIdx.x < TN) hstage = nbase[min(t * TN + (int)threadIdx.x, k - 1)];
   };
   auto store_tile = [&](int buf) {
 #pragma unroll
@@ -887,7 +891,8 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_bf16(
       const int row = idx / V_PER_ROW, v8 = idx % V_PER_ROW;
       s_c4[buf][(row * LDW) / 8 + v8] = stage[i];
     }
-    if (threadIdx.x < TN) s_hn[buf][threadIdx.x] = hstage;
+    if (threadIdx.x < TN)
+      s_hn[buf][threadIdx.x] = (tile_base + (int)threadIdx.x < k) ? -0.5f * hstage : -INFINITY;
   };
   load_tile(0);
   store_tile(0);
@@ -908,7 +913,7 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_bf16(
       for (int i = 0; i < 16; ++i) {
         const float hv = s_hn[buf][cb * 32 + 8 * (i >> 2) + 4 * h + (i & 3)];
 #pragma unroll
-        for (int pb = 0; pb < PB; ++pb) acc[pb][i] = -hv;
+        for (int pb = 0; pb < PB; ++pb) acc[pb][i] = hv;
       }
       const uint4* arow = &s_c4[buf][((cb * 32 + col) * LDW + 8 * h) / 8];
 #pragma unroll

@@ -177,9 +177,20 @@ __device__ inline float acc4(float s, float4 x, float4 q) {
 //   TPR lanes per candidate row, NV 16-byte vectors of the row per lane
 //   (0: any number, looped), U rows in flight per lane group; B16: rows are
 //   BF16; CAPB: largest beam / k / re-rank set; CAP: LDS key buffer.
-template <int TPR, int NV, int U, int METRIC, bool B16, int CAPB, int CAP>
+//   SP: CSR index.  The query row is scattered into the dense LDS vector and
+//   its non-zeros are listed in LDS (the first kQList); CSR data rows are
+//   walked against the dense vector, dense prototype rows are gathered at the
+//   query's columns; dot products and |q|^2 + |c|^2 - 2 q.c in FP64.  The
+//   query's norm and a data row's norm are summed on the fly with the same
+//   lane split and order as their dot product, so a data row equal to the
+//   query is at distance exactly 0.
+constexpr int kQList = 1024;
+
+template <int TPR, int NV, int U, int METRIC, bool B16, int CAPB, int CAP, bool SP>
 __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa) {
   extern __shared__ float4 s_q4[];  // ld/4 float4
+  __shared__ int32_t s_qc[SP ? kQList : 1];
+  __shared__ float s_qv[SP ? kQList : 1];
   __shared__ uint64_t s_buf[CAP];
   __shared__ uint64_t s_out[CAPB];
   __shared__ uint32_t s_cnt[CAPB];      // child count of each kept prototype
@@ -197,7 +208,26 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
   const int r = qa.r_arr ? min(max(qa.r_arr[qi], 1), qa.r) : qa.r;
   const int64_t obase = qa.out_off ? qa.out_off[qi] : qi * (int64_t)qa.k;
   float* s_q = reinterpret_cast<float*>(s_q4);
-  for (int c = tid; c < ld; c += kBlock) s_q[c] = (c < a.dim) ? qa.Q[qi * qa.ldq + c] : 0.f;
+  int64_t qb = 0;
+  int nq_e = 0;
+  if constexpr (SP) {
+    qb = qa.q_ptr[qi];
+    nq_e = (int)(qa.q_ptr[qi + 1] - qb);
+    for (int c = tid; c < ld; c += kBlock) s_q[c] = 0.f;
+    __syncthreads();
+    // query rows are not checked by the library: a column id out of range
+    // is dropped (value 0 at column 0) rather than read or written out of
+    // bounds
+    for (int t = tid; t < nq_e; t += kBlock) {
+      int32_t c = qa.q_col[qb + t];
+      float v = qa.q_val[qb + t];
+      if (c < 0 || c >= a.dim) { c = 0; v = 0.f; }
+      if (v != 0.f) s_q[c] = v;
+      if (t < kQList) { s_qc[t] = c; s_qv[t] = v; }
+    }
+  } else {
+    for (int c = tid; c < ld; c += kBlock) s_q[c] = (c < a.dim) ? qa.Q[qi * qa.ldq + c] : 0.f;
+  }
 
   const int L = a.n_levels;
   int n_par = 1;
@@ -205,6 +235,17 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
   __syncthreads();
 
   const int grp = tid / TPR, gl = tid % TPR;
+  // |q|^2 of a CSR query, split over a lane group like a data row's dot product
+  double qn = 0.0;
+  if constexpr (SP) {
+    for (int t = gl; t < nq_e; t += TPR) {
+      double v = t < kQList ? s_qv[t] : qa.q_val[qb + t];
+      if (t >= kQList && (qa.q_col[qb + t] < 0 || qa.q_col[qb + t] >= a.dim)) v = 0.0;
+      qn = fma(v, v, qn);
+    }
+#pragma unroll
+    for (int o = TPR / 2; o >= 1; o >>= 1) qn += __shfl_xor(qn, o);
+  }
   constexpr int kGroups = kBlock / TPR;
   constexpr int NQ = NV > 0 ? NV : 1;
   // query fragment: FP32 rows use 4 dims per vector, BF16 rows 8
@@ -287,7 +328,39 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
 #pragma unroll
         for (int u = 0; u < U; ++u) ids[u] = (uint32_t)V.orig[pos[u]];
         float acc[U];
-        if (B16 && low) {
+        if constexpr (SP) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            double dot = 0.0, cn = 0.0;
+            if (lev == 0) {
+              const int64_t b = V.sp_ptr[pos[u]], e = V.sp_ptr[pos[u] + 1];
+#pragma unroll 4
+              for (int64_t t = b + gl; t < e; t += TPR) {
+                const double v = V.sp_val[t];
+                dot = fma(v, (double)s_q[V.sp_col[t]], dot);
+                cn = fma(v, v, cn);
+              }
+            } else {
+              const float* row = V.protos + pos[u] * ld;
+#pragma unroll 4
+              for (int t = gl; t < nq_e; t += TPR) {
+                const bool in = t < kQList;
+                int32_t c = in ? s_qc[t] : qa.q_col[qb + t];
+                float v = in ? s_qv[t] : qa.q_val[qb + t];
+                if (c < 0 || c >= a.dim) { c = 0; v = 0.f; }
+                dot = fma((double)v, (double)row[c], dot);
+              }
+            }
+#pragma unroll
+            for (int o = TPR / 2; o >= 1; o >>= 1) {
+              dot += __shfl_xor(dot, o);
+              cn += __shfl_xor(cn, o);
+            }
+            if (lev > 0) cn = V.norm64[pos[u]];
+            const double d = qn + cn - 2.0 * dot;
+            acc[u] = d > 0.0 ? (float)d : 0.f;
+          }
+        } else if (B16 && low) {
           const int nb = ldb / 8;
           if constexpr (NV > 0) {
             uint4 x[U][NV];
@@ -356,10 +429,12 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
             acc[u] = s0;
           }
         }
+        if constexpr (!SP) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+          for (int u = 0; u < U; ++u) {
 #pragma unroll
-          for (int o = TPR / 2; o >= 1; o >>= 1) acc[u] += __shfl_xor(acc[u], o);
+            for (int o = TPR / 2; o >= 1; o >>= 1) acc[u] += __shfl_xor(acc[u], o);
+          }
         }
         if (gl == 0) {
 #pragma unroll
@@ -477,30 +552,38 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
   if (qa.rows && tid == 0) atomicAdd(qa.rows, rows_seen);
 }
 
-template <int TPR, int NV, int U, bool B16, int CAPB, int CAP>
+template <int TPR, int NV, int U, bool B16, int CAPB, int CAP, bool SP>
 void launch3(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   const size_t shm = (size_t)a.ld * sizeof(float);
-  if (a.metric == MASK_L2)
-    k_descent<TPR, NV, U, 0, B16, CAPB, CAP><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
+  if (SP)
+    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, SP><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
+  else if (a.metric == MASK_L2)
+    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, SP><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
   else
-    k_descent<TPR, NV, U, 1, B16, CAPB, CAP><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
+    k_descent<TPR, NV, U, 1, B16, CAPB, CAP, SP><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
 }
 
-template <int TPR, int NV, int U, bool B16>
+template <int TPR, int NV, int U, bool B16, bool SP = false>
 void launch2(const DescentArgs& a, const QueryArgs& qa, int need, hipStream_t s) {
-  if (need <= 512) launch3<TPR, NV, U, B16, 512, 2560>(a, qa, s);
-  else launch3<TPR, NV, U, B16, 2048, 4096>(a, qa, s);
+  if (need <= 512) launch3<TPR, NV, U, B16, 512, 2560, SP>(a, qa, s);
+  else launch3<TPR, NV, U, B16, 2048, 4096, SP>(a, qa, s);
 }
 
 }  // namespace
 
 void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   if (qa.nq <= 0) return;
-  ScopedTiming timing(a.precision == MASK_BF16 ? "descent_bf16" : "descent", s);
+  ScopedTiming timing(a.sparse ? "descent_csr"
+                               : (a.precision == MASK_BF16 ? "descent_bf16" : "descent"), s);
   const bool b16 = a.precision == MASK_BF16;
   // LDS class from the beams and k; the BF16 re-rank set fits the class
   int need = qa.k > qa.r ? qa.k : qa.r;
   for (int l = 1; l <= a.n_levels; ++l) need = qa.r_lev[l] > need ? qa.r_lev[l] : need;
+  if (a.sparse) {
+    launch2<16, 0, 1, false, true>(a, qa, need, s);
+    check_launch("descent_csr");
+    return;
+  }
   // Lane groups per row width, measured on MI355X (1M-point mixtures, beams
   // 16/96/160): few lanes per row, each with several 16-byte vectors, and one
   // or two rows in flight per group beat wide groups -- more rows per wave

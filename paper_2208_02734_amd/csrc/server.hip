@@ -316,6 +316,7 @@ mask_status mask_server_create(const mask_index* ix, const mask_server_params* p
                                const mask_allocator* a, mask_server** out) {
   try {
     MASK_CHECK(ix && p && out, "NULL argument");
+    if (ix->sparse) throw Error{MASK_ERR_UNSUPPORTED, "serving a CSR index"};
     MASK_CHECK(p->arena_bytes >= 4096, "arena_bytes too small");
     MASK_CHECK(p->max_batch_queries >= 1, "max_batch_queries < 1");
     MASK_CHECK(p->n_streams >= 1 && p->n_streams <= 16, "n_streams must be in [1, 16]");

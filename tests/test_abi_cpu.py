@@ -75,3 +75,26 @@ def test_unsupported_requests(L):
     p, lv = pk._params([(2, 10)], 5, 0, "l2", "fp32", 4, None)
     st = L.mask_build(ctypes.byref(m), ctypes.byref(p), None, None, ctypes.byref(h))
     assert st == 4
+
+
+def test_csr_arguments_are_checked_before_device_work(L):
+    h = ctypes.c_void_p()
+    m = pk.mask_matrix()
+    m.layout, m.n, m.dim = 1, 1000, 20_000
+    m.indptr, m.indices, m.values, m.nnz = 1234, 1234, 1234, 5000
+    p, lv = pk._params([(2, 10)], 5, 0, "l2", "fp32", 4, None)
+    # more columns than the descent can stage in LDS
+    st = L.mask_build(ctypes.byref(m), ctypes.byref(p), None, None, ctypes.byref(h))
+    assert st == 4 and b"16384" in L.mask_last_error()
+    m.dim = 1000
+    # CSR data: L2 metric and FP32 form only
+    p1, lv1 = pk._params([(2, 10)], 5, 0, "l1", "fp32", 4, None)
+    assert L.mask_build(ctypes.byref(m), ctypes.byref(p1), None, None, ctypes.byref(h)) == 4
+    p2, lv2 = pk._params([(2, 10)], 5, 0, "l2", "bf16", 4, None)
+    assert L.mask_build(ctypes.byref(m), ctypes.byref(p2), None, None, ctypes.byref(h)) == 4
+    # negative nnz and missing arrays are invalid
+    m.nnz = -1
+    assert L.mask_build(ctypes.byref(m), ctypes.byref(p), None, None, ctypes.byref(h)) == 1
+    m.nnz, m.indices = 10, None
+    assert L.mask_build(ctypes.byref(m), ctypes.byref(p), None, None, ctypes.byref(h)) == 1
+    assert h.value is None
