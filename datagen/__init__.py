@@ -181,10 +181,10 @@ def sample_sparse(n_rows: int, n_cols: int, nnz_per_row: int, seed: int,
     cdf /= cdf[-1]
     indices = np.empty((n_rows, nnz_per_row), dtype=np.int32)
     block = 4096
-    draws = 4 * nnz_per_row + 64
     for s in range(0, n_rows, block):
         e = min(n_rows, s + block)
         rows_left = np.arange(s, e)
+        draws = 4 * nnz_per_row + 64  # doubled only for this block's retries
         while rows_left.size:
             m = rows_left.size
             u = g.random((m, draws))

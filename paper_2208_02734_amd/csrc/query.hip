@@ -329,35 +329,48 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
         for (int u = 0; u < U; ++u) ids[u] = (uint32_t)V.orig[pos[u]];
         float acc[U];
         if constexpr (SP) {
+          double dot[U], cn[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-            double dot = 0.0, cn = 0.0;
-            if (lev == 0) {
+          for (int u = 0; u < U; ++u) { dot[u] = 0.0; cn[u] = 0.0; }
+          if (lev == 0) {
+            // CSR data rows against the dense query in LDS
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
               const int64_t b = V.sp_ptr[pos[u]], e = V.sp_ptr[pos[u] + 1];
 #pragma unroll 4
               for (int64_t t = b + gl; t < e; t += TPR) {
                 const double v = V.sp_val[t];
-                dot = fma(v, (double)s_q[V.sp_col[t]], dot);
-                cn = fma(v, v, cn);
-              }
-            } else {
-              const float* row = V.protos + pos[u] * ld;
-#pragma unroll 4
-              for (int t = gl; t < nq_e; t += TPR) {
-                const bool in = t < kQList;
-                int32_t c = in ? s_qc[t] : qa.q_col[qb + t];
-                float v = in ? s_qv[t] : qa.q_val[qb + t];
-                if (c < 0 || c >= a.dim) { c = 0; v = 0.f; }
-                dot = fma((double)v, (double)row[c], dot);
+                dot[u] = fma(v, (double)s_q[V.sp_col[t]], dot[u]);
+                cn[u] = fma(v, v, cn[u]);
               }
             }
+          } else {
+            // dense prototype rows gathered at the query's columns, U rows at once
+            const float* rows[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) rows[u] = V.protos + pos[u] * ld;
+#pragma unroll 2
+            for (int t = gl; t < nq_e; t += TPR) {
+              const bool in = t < kQList;
+              int32_t c = in ? s_qc[t] : qa.q_col[qb + t];
+              float v = in ? s_qv[t] : qa.q_val[qb + t];
+              if (c < 0 || c >= a.dim) { c = 0; v = 0.f; }
+              float x[U];
+#pragma unroll
+              for (int u = 0; u < U; ++u) x[u] = rows[u][c];
+#pragma unroll
+              for (int u = 0; u < U; ++u) dot[u] = fma((double)v, (double)x[u], dot[u]);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
 #pragma unroll
             for (int o = TPR / 2; o >= 1; o >>= 1) {
-              dot += __shfl_xor(dot, o);
-              cn += __shfl_xor(cn, o);
+              dot[u] += __shfl_xor(dot[u], o);
+              cn[u] += __shfl_xor(cn[u], o);
             }
-            if (lev > 0) cn = V.norm64[pos[u]];
-            const double d = qn + cn - 2.0 * dot;
+            const double c2 = lev > 0 ? V.norm64[pos[u]] : cn[u];
+            const double d = qn + c2 - 2.0 * dot[u];
             acc[u] = d > 0.0 ? (float)d : 0.f;
           }
         } else if (B16 && low) {
@@ -580,7 +593,7 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   int need = qa.k > qa.r ? qa.k : qa.r;
   for (int l = 1; l <= a.n_levels; ++l) need = qa.r_lev[l] > need ? qa.r_lev[l] : need;
   if (a.sparse) {
-    launch2<16, 0, 1, false, true>(a, qa, need, s);
+    launch2<16, 0, 4, false, true>(a, qa, need, s);
     check_launch("descent_csr");
     return;
   }

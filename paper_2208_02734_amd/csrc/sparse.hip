@@ -284,45 +284,194 @@ __global__ void k_labels_keys(const int32_t* __restrict__ labels, int64_t n,
   vals[i] = (uint32_t)i;
 }
 
-// One wave per prototype: the FP64 sum of its members over a window of
-// kSumWin columns at a time in LDS (members in item order; a member's
-// columns are distinct, so its lanes never collide, and one wave's LDS
-// accesses complete in program order), then the FP32 mean and the FP64
-// squared norm of the rounded mean.  A prototype with no member keeps its
-// row and norm.
+// Update: FP64 sums of each prototype's members, split into work items of at
+// most S members (S chosen per level from the rows' density), one wave per
+// item.  Item slots are laid out as in the dense update: prototype p owns
+// [p + m0 / S, p + 1 + m1 / S), which holds at least max(1, ceil(cnt / S))
+// slots.  A prototype with one item is finished by it; the items of a larger
+// one write dense FP64 partial sums (rows of a compact buffer numbered by an
+// exclusive scan over the prototypes) that k_update_csr_finish adds in item
+// order.  Sums run over a window of kSumWin columns at a time in LDS; a
+// member's columns are distinct, so its lanes never collide, and one wave's
+// LDS accesses complete in program order, so members add in item order.
 constexpr int kSumWin = 4096;
 
-__global__ __launch_bounds__(kWave) void k_update_csr(
+__global__ void k_sp_slots(const uint32_t* __restrict__ member_off, int64_t n_protos, int S,
+                           int32_t* __restrict__ slot_proto, uint32_t* __restrict__ pcount) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_protos) return;
+  const uint32_t m0 = member_off[p], m1 = member_off[p + 1];
+  const uint32_t cnt = m1 - m0;
+  const int64_t b0 = p + m0 / S, b1 = p + 1 + m1 / S;
+  const int64_t nch = cnt == 0 ? 1 : (cnt + S - 1) / S;
+  for (int64_t t = b0; t < b1; ++t) slot_proto[t] = (t - b0 < nch) ? (int32_t)p : -1;
+  pcount[p] = cnt > (uint32_t)S ? (uint32_t)nch : 0u;
+}
+
+// The item's member entries are staged in LDS first when they fit (all
+// their loads in flight at once), so the per-window passes read LDS only.
+constexpr int kStage = 1024;
+
+__global__ __launch_bounds__(kWave) void k_update_csr_items(
     const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, const uint32_t* __restrict__ members,
-    const uint32_t* __restrict__ member_off, int cols, float* __restrict__ P, int ld,
-    double* __restrict__ pnorm) {
+    const uint32_t* __restrict__ member_off, const int32_t* __restrict__ slot_proto,
+    const uint32_t* __restrict__ pbase, int S, int cols, float* __restrict__ P, int ld,
+    double* __restrict__ pnorm, double* __restrict__ part) {
   __shared__ double acc[kSumWin];
+  __shared__ int32_t s_col[kStage];
+  __shared__ float s_val[kStage];
+  __shared__ uint32_t s_moff[kWave + 1];  // staged entry offset of each member
   const int lane = threadIdx.x;
-  const int64_t p = blockIdx.x;
+  const int64_t t = blockIdx.x;
+  const int32_t p = slot_proto[t];
+  if (p < 0) return;
   const uint32_t m0 = member_off[p], m1 = member_off[p + 1];
-  if (m1 == m0) return;
-  const double inv_n = 1.0 / (double)(m1 - m0);
+  const uint32_t cnt = m1 - m0;
+  if (cnt == 0) return;  // keeps its row and norm
+  const int64_t j = t - ((int64_t)p + m0 / S);
+  const uint32_t a = m0 + (uint32_t)j * S;
+  const uint32_t b = min(m1, a + (uint32_t)S);
+  const bool single = cnt <= (uint32_t)S;
+  const double inv_n = 1.0 / (double)cnt;
+  double* prow = single ? nullptr : part + (int64_t)(pbase[p] + j) * cols;
+
+  // stage when the item has at most 64 members and kStage entries
+  bool staged = false;
+  if (b - a <= (uint32_t)kWave) {
+    const uint32_t mi = a + lane;
+    int64_t beg = 0;
+    uint32_t len = 0;
+    if (mi < b) {
+      const int64_t it = members[mi];
+      beg = ptr[it];
+      len = (uint32_t)(ptr[it + 1] - beg);
+    }
+    uint32_t x = len;  // inclusive scan over the lanes
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    const uint32_t total = __shfl(x, kWave - 1);
+    if (total <= (uint32_t)kStage) {
+      staged = true;
+      s_moff[lane + 1] = x;
+      if (lane == 0) s_moff[0] = 0;
+      const uint32_t nm = b - a;
+      for (uint32_t f = 0; f < nm; ++f) {
+        const int64_t fb = __shfl(beg, (int)f);
+        const uint32_t fl = __shfl(len, (int)f);
+        const uint32_t fo = __shfl(x - len, (int)f);
+        for (uint32_t e = lane; e < fl; e += kWave) {
+          s_col[fo + e] = col[fb + e];
+          s_val[fo + e] = val[fb + e];
+        }
+      }
+    }
+  }
+
   double nrm = 0.0;
   for (int d0 = 0; d0 < cols; d0 += kSumWin) {
     const int w = min(kSumWin, cols - d0);
-    for (int j = lane; j < w; j += kWave) acc[j] = 0.0;
-    for (uint32_t m = m0; m < m1; ++m) {
-      const int64_t it = members[m];
-      for (int64_t e = ptr[it] + lane; e < ptr[it + 1]; e += kWave) {
-        const int cc = col[e] - d0;
-        if (cc >= 0 && cc < w) acc[cc] += (double)val[e];
+    for (int c = lane; c < w; c += kWave) acc[c] = 0.0;
+    if (staged) {
+      for (uint32_t f = 0; f < b - a; ++f) {
+        const uint32_t e0 = s_moff[f], e1 = s_moff[f + 1];
+        for (uint32_t e = e0 + lane; e < e1; e += kWave) {
+          const int cc = s_col[e] - d0;
+          if (cc >= 0 && cc < w) acc[cc] += (double)s_val[e];
+        }
+      }
+    } else {
+      // a member's columns are distinct, so its adds commute: load 4 entries
+      // per lane before adding them
+      for (uint32_t m = a; m < b; ++m) {
+        const int64_t it = members[m];
+        const int64_t eb = ptr[it], ee = ptr[it + 1];
+        for (int64_t e0 = eb; e0 < ee; e0 += 4 * kWave) {
+          int cc[4];
+          float vv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int64_t e = e0 + lane + u * kWave;
+            cc[u] = e < ee ? col[e] - d0 : -1;
+            vv[u] = e < ee ? val[e] : 0.f;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (cc[u] >= 0 && cc[u] < w) acc[cc[u]] += (double)vv[u];
+        }
       }
     }
-    for (int j = lane; j < w; j += kWave) {
-      const float v = (float)(acc[j] * inv_n);
-      P[p * ld + d0 + j] = v;
-      nrm = fma((double)v, (double)v, nrm);
+    if (single) {
+      for (int c = lane; c < w; c += kWave) {
+        const float v = (float)(acc[c] * inv_n);
+        P[(int64_t)p * ld + d0 + c] = v;
+        nrm = fma((double)v, (double)v, nrm);
+      }
+    } else {
+      for (int c = lane; c < w; c += kWave) prow[d0 + c] = acc[c];
     }
+  }
+  if (single) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nrm += __shfl_xor(nrm, o);
+    if (lane == 0) pnorm[p] = nrm;
+  }
+}
+
+// Prototypes with more than one item: one wave per (prototype, block of
+// kFinCols columns) adds the item sums in item order (8 loads in flight, adds
+// in sequence), writes the FP32 mean and the block's FP64 squared norm;
+// k_update_csr_norm adds the blocks in order.
+constexpr int kFinCols = 512;
+
+__global__ __launch_bounds__(kBlock) void k_update_csr_finish(
+    const uint32_t* __restrict__ member_off, int64_t n_protos, int S,
+    const uint32_t* __restrict__ pbase, const double* __restrict__ part, int cols, int nblk,
+    float* __restrict__ P, int ld, double* __restrict__ bnorm) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t wv = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int64_t p = wv / nblk;
+  const int blk = (int)(wv % nblk);
+  if (p >= n_protos) return;
+  const uint32_t cnt = member_off[p + 1] - member_off[p];
+  if (cnt <= (uint32_t)S) return;
+  const int nch = (int)((cnt + S - 1) / S);
+  const double* base = part + (int64_t)pbase[p] * cols;
+  const double inv_n = 1.0 / (double)cnt;
+  double nrm = 0.0;
+  const int c1 = min(cols, (blk + 1) * kFinCols);
+  for (int c = blk * kFinCols + lane; c < c1; c += kWave) {
+    double sum = 0.0;
+    int i = 0;
+    for (; i + 8 <= nch; i += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = base[(int64_t)(i + u) * cols + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sum += v[u];
+    }
+    for (; i < nch; ++i) sum += base[(int64_t)i * cols + c];
+    const float v = (float)(sum * inv_n);
+    P[p * ld + c] = v;
+    nrm = fma((double)v, (double)v, nrm);
   }
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) nrm += __shfl_xor(nrm, o);
-  if (lane == 0) pnorm[p] = nrm;
+  if (lane == 0) bnorm[p * nblk + blk] = nrm;
+}
+
+__global__ void k_update_csr_norm(const uint32_t* __restrict__ member_off, int64_t n_protos,
+                                  int S, const double* __restrict__ bnorm, int nblk,
+                                  double* __restrict__ pnorm) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_protos) return;
+  if (member_off[p + 1] - member_off[p] <= (uint32_t)S) return;
+  double a = 0.0;
+  for (int b = 0; b < nblk; ++b) a += bnorm[p * nblk + b];
+  pnorm[p] = a;
 }
 
 // Inertia of every group: the sum of its items' distances in item order
@@ -440,6 +589,21 @@ void kmeans_sparse(const Csr& items, int ld, int n_chunks, int k, int iters, con
   uint32_t* member_off = scratch.alloc<uint32_t>(np + 1);
   SortWork sw;
   sort_work_alloc(sw, n, false, scratch);
+  // update work items: about 6400 non-zeros each, and at most 256 MB of
+  // partial sums (2n / S item rows of cols doubles bound them)
+  const double avg_nnz = n > 0 ? (double)items.nnz / (double)n : 1.0;
+  int64_t S = std::max<int64_t>(1, (int64_t)(6400.0 / std::max(avg_nnz, 1.0)));
+  const int64_t part_budget = (int64_t)256 << 20;
+  S = std::max<int64_t>(S, (2 * n * (int64_t)cols * 8 + part_budget - 1) / part_budget);
+  S = std::min<int64_t>(S, (int64_t)1 << 20);
+  const int64_t n_slots = np + n / S;
+  const int64_t part_rows = 2 * (n / S) + 2;
+  int32_t* slot_proto = scratch.alloc<int32_t>(n_slots);
+  uint32_t* pbase = scratch.alloc<uint32_t>(np + 1);
+  uint32_t* scan_sums = scratch.alloc<uint32_t>(scan_sums_needed(np));
+  double* part = scratch.alloc<double>(part_rows * cols);
+  const int nblk = (cols + kFinCols - 1) / kFinCols;
+  double* bnorm = scratch.alloc<double>(np * nblk);
   int bits = 0;
   while (bits < 31 && ((int64_t)1 << bits) < np) ++bits;
 
@@ -489,9 +653,20 @@ void kmeans_sparse(const Csr& items, int ld, int n_chunks, int k, int iters, con
     }
     {
       ScopedTiming timing("update_csr", s);
-      k_update_csr<<<(unsigned)np, kWave, 0, s>>>(items.ptr, items.col, items.val, vals,
-                                                  member_off, cols, protos, ld, pnorm);
-      check_launch_sp("update_csr");
+      k_sp_slots<<<grid_for(np, kBlock), kBlock, 0, s>>>(member_off, np, (int)S, slot_proto,
+                                                        pbase);
+      check_launch_sp("sp_slots");
+      exclusive_scan_u32(pbase, np, nullptr, scan_sums, s);
+      k_update_csr_items<<<(unsigned)n_slots, kWave, 0, s>>>(
+          items.ptr, items.col, items.val, vals, member_off, slot_proto, pbase, (int)S, cols,
+          protos, ld, pnorm, part);
+      check_launch_sp("update_csr_items");
+      k_update_csr_finish<<<grid_for(np * nblk * kWave, kBlock), kBlock, 0, s>>>(
+          member_off, np, (int)S, pbase, part, cols, nblk, protos, ld, bnorm);
+      check_launch_sp("update_csr_finish");
+      k_update_csr_norm<<<grid_for(np, kBlock), kBlock, 0, s>>>(member_off, np, (int)S, bnorm,
+                                                               nblk, pnorm);
+      check_launch_sp("update_csr_norm");
     }
     transpose();
   }
