@@ -15,9 +15,10 @@ the device-resident data, then the descent of the 10,000 queries.  ``value``
 is that form's query throughput (queries/s, index resident, median over the
 timed steps); ``build_s`` its median build time.  The serving section runs
 one Poisson request stream (1..512 queries per request, log-uniform; k
-uniform in [1, 100]; r in {8, 32}) through the continuous-batching loop for
-both forms and reports p50/p99 latency (completion minus scheduled arrival)
-and the completed queries/s.  Kernel times come from HIP events the library
+uniform in [1, 100]; r in {8, 32}) at several rates through the continuous-batching
+loop for both forms (replayed by the library's native load generator) and
+reports p50/p99 latency (completion minus scheduled arrival) and the
+completed queries/s.  The csr section builds and queries the CSR workload.  Kernel times come from HIP events the library
 records on its launch stream.
 
 Prints one JSON line.
@@ -50,8 +51,10 @@ def parse():
     ap.add_argument("--recall-sample", type=int, default=500)
     ap.add_argument("--gate", type=float, default=0.95)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--serve-rate", type=float, default=5000.0, help="requests/s")
-    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-rates", type=str, default="2000,10000,40000",
+                    help="comma-separated Poisson request rates (requests/s)")
+    ap.add_argument("--serve-seconds", type=float, default=1.5)
+    ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--form", choices=["auto", "fp32", "bf16"], default="auto")
@@ -63,48 +66,83 @@ def log(msg):
 
 
 def serve_stream(pk, ix, pool, rate, seconds, seed):
-    """Open-loop Poisson arrivals through the serving loop of one index."""
+    """Open-loop Poisson arrivals replayed against the serving loop of one
+    index by the library's native load generator."""
     import numpy as np
     import datagen
     rs = datagen.request_stream(rate, seconds, seed, pool.shape[0])
-    srv = pk.MaskServer(ix, arena_bytes=1 << 30, max_batch_queries=32768, n_streams=3)
-    t = srv.submit(pool[:64], 10, 8)  # first launches and staging outside the measurement
-    while srv.poll(t) is None:
-        pass
-    n = rs.t_arrival.shape[0]
-    t0 = pk.mask_clock() + 0.02
-    lat, order = [], []
-    i = q_done = 0
-    t_last = t0
-    while i < n or order:
-        now = pk.mask_clock()
-        while i < n and t0 + rs.t_arrival[i] <= now:
-            off, nq = int(rs.pool_offset[i]), int(rs.n_queries[i])
-            ta = t0 + float(rs.t_arrival[i])
-            order.append((srv.submit(pool[off:off + nq], int(rs.k[i]), int(rs.r[i]),
-                                     t_arrival=ta), ta, nq))
-            i += 1
-        # batches retire in about arrival order: poll the oldest few
-        j = 0
-        while j < min(8, len(order)):
-            tk, ta, nq = order[j]
-            res = srv.poll(tk)
-            if res is None:
-                j += 1
-                continue
-            lat.append(res[2] - ta)  # completion is stamped by the server's own thread
-            t_last = max(t_last, res[2])
-            q_done += nq
-            order.pop(j)
+    srv = pk.MaskServer(ix, arena_bytes=4 << 30, max_batch_queries=32768, n_streams=3)
+    srv.replay(pool, [0.0], [64], [0], [10], [8])  # first launches outside the measurement
+    lat, span = srv.replay(pool, rs.t_arrival, rs.n_queries, rs.pool_offset, rs.k, rs.r)
     st = srv.stats()
     srv.close()
-    lat = np.asarray(lat) * 1e3
-    return {"rate_req_s": rate, "requests": int(n), "queries": int(q_done),
+    lat = lat * 1e3
+    q = int(rs.n_queries.sum())
+    return {"rate_req_s": rate, "requests": int(rs.t_arrival.shape[0]), "queries": q,
+            "offered_queries_per_s": round(q / seconds, 1),
             "p50_ms": round(float(np.percentile(lat, 50)), 3),
             "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "queries_per_s": round(q_done / max(t_last - t0, 1e-9), 1),
-            "batches": int(st["batches"]),
+            "queries_per_s": round(q / span, 1),
+            "batches": int(st["batches"]) - 1,
             "peak_arena_MiB": round(st["peak_arena_bytes"] / 2**20, 1)}
+
+
+def sparse_section(pk, torch, args, log):
+    """The CSR workload: 200,000 x 10,000 sparse rows (100 non-zeros each,
+    Zipf column popularity, unit rows), levels 20 x 2,000 -> 2,000 -> 50,
+    30 Lloyd iterations, 5,000 CSR queries; recall@10 against exhaustive FP64
+    search over the CSR rows (the oracle) on a 200-query sample."""
+    import numpy as np
+    import datagen
+    from oracle import mask_oracle as mo
+    cfg = datagen.config_sparse()
+    S, QS = cfg.X, cfg.Q
+    Xs = pk.CsrTensor.from_host(S.indptr, S.indices, S.values, S.n_cols)
+    Qs = pk.CsrTensor.from_host(QS.indptr, QS.indices, QS.values, QS.n_cols)
+    g = np.random.default_rng(0)
+    sample = np.sort(g.choice(QS.n_rows, 200, replace=False))
+    D = mo.sparse_pairwise_l2(S.indptr, S.indices, S.values,
+                              QS.to_dense()[sample].astype(np.float64)).T
+    tids = np.argsort(D, axis=1, kind="stable")[:, :10]
+    kth = np.take_along_axis(D, tids[:, -1:], axis=1)[:, 0]
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e1, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e1.record(stream)
+        out = fn()
+        e2.record(stream)
+        torch.cuda.synchronize()
+        return out, e1.elapsed_time(e2)
+
+    def recall(ids):
+        got = ids.cpu().numpy()[sample].astype(np.int64)
+        hit = 0
+        for i in range(sample.size):
+            d_got = D[i, got[i][got[i] >= 0]]
+            hit += int(np.sum(d_got <= kth[i] * (1 + 1e-5)))  # ties at the 10th accepted
+        return hit / (10 * sample.size)
+
+    ix, _ = timed(lambda: pk.mask_build(Xs, cfg.levels, iters=args.iters, seed=1))
+    ix.free()
+    pk.mask_timing_enable(True)
+    ix, b_ms = timed(lambda: pk.mask_build(Xs, cfg.levels, iters=args.iters, seed=1))
+    kt = pk.mask_timing_report()
+    pk.mask_timing_enable(False)
+    out = {"workload": "csr-200k-D10000: 200,000 x 10,000 CSR rows (100 nnz, Zipf 1.1 columns, "
+                       "unit rows), levels 20x2000->2000->50, 30 Lloyd iters, 5,000 queries",
+           "build_s": round(b_ms * 1e-3, 4),
+           "build_kernels": {n: {"launches": c, "total_ms": round(ms, 2)}
+                             for n, (c, ms) in kt.items() if ms > 0},
+           "queries": []}
+    for beams in [(8, 8, 8), (16, 32, 32), (50, 128, 128), (50, 256, 256)]:
+        timed(lambda: pk.mask_query_beams(ix, Qs, 10, beams))
+        (ids, _), q_ms = timed(lambda: pk.mask_query_beams(ix, Qs, 10, beams))
+        out["queries"].append({"beams": list(beams), "recall@10": round(recall(ids), 4),
+                               "queries_per_s": round(QS.n_rows / (q_ms * 1e-3), 1)})
+        log(f"csr beams {beams}: {out['queries'][-1]}")
+    ix.free()
+    return out
 
 
 def main():
@@ -238,11 +276,18 @@ def main():
     serving = None
     if not args.no_serve:
         serving = {}
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
         for f in ("fp32", "bf16"):
             sx = build(f)
-            serving[f] = serve_stream(pk, sx, Q, args.serve_rate, args.serve_seconds, seed=55)
+            serving[f] = []
+            for rate in rates:
+                serving[f].append(serve_stream(pk, sx, Q, rate, args.serve_seconds, seed=55))
+                log(f"serving {f}: {serving[f][-1]}")
             sx.free()
-            log(f"serving {f}: {serving[f]}")
+
+    sparse = None
+    if not args.no_sparse:
+        sparse = sparse_section(pk, torch, args, log)
 
     # ---- CPU baseline: the oracle's FP64 descent on the same index, bounded sample
     cpu = None
@@ -286,8 +331,9 @@ def main():
                    "k": args.k, "beams": list(beams), "form": form},
         "recall@10": round(step_recall, 4),
         "build_s": round(b_med * 1e-3, 4),
-        "latency_ms": None if serving is None else {"p50": serving[form]["p50_ms"],
-                                                    "p99": serving[form]["p99_ms"]},
+        "latency_ms": None if serving is None else {
+            "rate_req_s": serving[form][0]["rate_req_s"], "p50": serving[form][0]["p50_ms"],
+            "p99": serving[form][0]["p99_ms"]},
         "roofline": {"bound": "mfma", "kernel": akey, "achieved": round(assign_tflops, 2),
                      "peak": PEAK[form], "unit": "TFLOP/s",
                      "frac": round(assign_tflops / PEAK[form], 4), "traffic": None},
@@ -296,6 +342,7 @@ def main():
                            "frac": round(desc_gbs / PEAK_HBM_GBS, 4), "traffic": None},
         "forms": forms,
         "serving": serving,
+        "csr": sparse,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

@@ -275,6 +275,20 @@ mask_status mask_server_poll(mask_server* s, uint64_t ticket, int32_t* done, int
 
 mask_status mask_server_stats_get(mask_server* s, mask_server_stats* out);
 
+/* Open-loop load generator for measuring the serving loop: from the calling
+ * thread, submits request i at t0 + t_offset[i] seconds (t0 = the call's
+ * start plus 1 ms; t_offset non-decreasing) with rows pool_off[i] ..
+ * pool_off[i] + n_q[i] - 1 of pool_host (host, pool_rows x dim), k[i] and
+ * r[i], with that scheduled time as its arrival; polls completions in
+ * between (results are discarded) and returns once every request is done.
+ * latency[i] (host double[n_req]) = completion - scheduled arrival in
+ * seconds; *span = last completion - t0 (may be NULL).  Submission errors
+ * (MASK_ERR_BUSY for a request that can never fit) end the replay. */
+mask_status mask_server_replay(mask_server* s, const float* pool_host, int64_t pool_rows,
+                               int64_t n_req, const double* t_offset, const int32_t* n_q,
+                               const int64_t* pool_off, const int32_t* k, const int32_t* r,
+                               double* latency, double* span);
+
 /* Serves every queued request, then stops the scheduler and frees the
  * server.  Requests not polled are dropped. */
 mask_status mask_server_destroy(mask_server* s);

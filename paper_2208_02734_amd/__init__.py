@@ -87,7 +87,7 @@ EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_beams", 
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
             "mask_last_error", "mask_timing_enable", "mask_timing_report", "mask_clock",
             "mask_server_create", "mask_server_submit", "mask_server_poll",
-            "mask_server_stats_get", "mask_server_destroy"]
+            "mask_server_stats_get", "mask_server_replay", "mask_server_destroy"]
 
 
 def lib() -> ctypes.CDLL:
@@ -123,6 +123,8 @@ def lib() -> ctypes.CDLL:
     L.mask_server_poll.argtypes = [VP, ctypes.c_uint64, P(I32), VP, VP, P(ctypes.c_double)]
     L.mask_server_stats_get.argtypes = [VP, P(mask_server_stats)]
     L.mask_server_destroy.argtypes = [VP]
+    L.mask_server_replay.argtypes = [VP, VP, I64, I64, VP, VP, VP, VP, VP, VP,
+                                     P(ctypes.c_double)]
     L.mask_last_error.restype = ctypes.c_char_p
     L.mask_last_error.argtypes = []
     for name in EXPORTED:
@@ -498,6 +500,23 @@ class MaskServer:
         st = mask_server_stats()
         _check(lib().mask_server_stats_get(self.handle, ctypes.byref(st)))
         return {n: getattr(st, n) for n, _ in mask_server_stats._fields_}
+
+    def replay(self, pool: np.ndarray, t_offset, n_q, pool_off, k, r):
+        """Open-loop replay of a request schedule from a native thread (see
+        mask_server_replay); returns (latency seconds per request, span)."""
+        pool = np.ascontiguousarray(pool, dtype=np.float32)
+        t = np.ascontiguousarray(t_offset, dtype=np.float64)
+        nq = np.ascontiguousarray(n_q, dtype=np.int32)
+        off = np.ascontiguousarray(pool_off, dtype=np.int64)
+        kk = np.ascontiguousarray(k, dtype=np.int32)
+        rr = np.ascontiguousarray(r, dtype=np.int32)
+        lat = np.zeros(t.shape[0], dtype=np.float64)
+        span = ctypes.c_double()
+        _check(lib().mask_server_replay(self.handle, pool.ctypes.data, pool.shape[0], t.shape[0],
+                                        t.ctypes.data, nq.ctypes.data, off.ctypes.data,
+                                        kk.ctypes.data, rr.ctypes.data, lat.ctypes.data,
+                                        ctypes.byref(span)))
+        return lat, span.value
 
     def close(self):
         if self.handle and self.handle.value:

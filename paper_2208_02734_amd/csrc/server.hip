@@ -420,6 +420,64 @@ mask_status mask_server_stats_get(mask_server* s, mask_server_stats* out) {
   return MASK_OK;
 }
 
+mask_status mask_server_replay(mask_server* s, const float* pool_host, int64_t pool_rows,
+                               int64_t n_req, const double* t_offset, const int32_t* n_q,
+                               const int64_t* pool_off, const int32_t* k, const int32_t* r,
+                               double* latency, double* span) {
+  try {
+    MASK_CHECK(s && pool_host && t_offset && n_q && pool_off && k && r && latency,
+               "NULL argument");
+    MASK_CHECK(n_req >= 0 && pool_rows >= 1, "bad sizes");
+    const int dim = s->ix->dim;
+    for (int64_t i = 0; i < n_req; ++i) {
+      MASK_CHECK(n_q[i] >= 1 && pool_off[i] >= 0 && pool_off[i] + n_q[i] <= pool_rows,
+                 "request rows outside the pool");
+      MASK_CHECK(i == 0 || t_offset[i] >= t_offset[i - 1], "arrival times must not decrease");
+    }
+    struct Out { uint64_t ticket; int64_t i; double t_arr; };
+    std::deque<Out> outstanding;
+    const double t0 = now_seconds() + 1e-3;
+    double t_last = t0;
+    int64_t next = 0;
+    auto drain = [&](bool all) {
+      while (!outstanding.empty()) {
+        const Out o = outstanding.front();
+        int32_t done = 0;
+        double td = 0;
+        const mask_status st = mask_server_poll(s, o.ticket, &done, nullptr, nullptr, &td);
+        if (st != MASK_OK) throw Error{st, mask_last_error()};
+        if (!done) {
+          if (!all) return;
+          std::this_thread::sleep_for(std::chrono::microseconds(20));
+          continue;
+        }
+        latency[o.i] = td - o.t_arr;
+        t_last = std::max(t_last, td);
+        outstanding.pop_front();
+      }
+    };
+    while (next < n_req) {
+      const double ta = t0 + t_offset[next];
+      if (now_seconds() < ta) {
+        drain(false);
+        if (now_seconds() + 50e-6 < ta) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        continue;
+      }
+      uint64_t ticket = 0;
+      const mask_status st = mask_server_submit(
+          s, pool_host + pool_off[next] * (int64_t)dim, n_q[next], k[next], r[next], ta, &ticket);
+      if (st != MASK_OK) throw Error{st, mask_last_error()};
+      outstanding.push_back({ticket, next, ta});
+      ++next;
+    }
+    drain(true);
+    if (span) *span = t_last - t0;
+    return MASK_OK;
+  } catch (const Error& e) {
+    return fail_server(e);
+  }
+}
+
 mask_status mask_server_destroy(mask_server* s) {
   if (!s) return MASK_OK;
   {

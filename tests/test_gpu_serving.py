@@ -109,3 +109,18 @@ def test_batching_window_holds_partial_batches(setup):
     assert t_done - t0 < 0.05
     i1, _ = pk.mask_query(ix, dev(Q[:64]), 5, 4)
     assert np.array_equal(ids, host(i1))
+
+
+def test_replay_serves_a_schedule(setup):
+    pk, ix, Q = setup
+    rs = datagen.request_stream(2000.0, 0.05, seed=9, pool_rows=Q.shape[0], max_queries=64)
+    n = rs.t_arrival.shape[0]
+    assert n > 20
+    srv = pk.MaskServer(ix, arena_bytes=32 << 20, max_batch_queries=4096, n_streams=2)
+    lat, span = srv.replay(Q, rs.t_arrival, rs.n_queries, rs.pool_offset, rs.k, rs.r)
+    st = srv.stats()
+    srv.close()
+    assert st["completed_requests"] == n
+    assert st["completed_queries"] == int(rs.n_queries.sum())
+    assert np.all(lat > 0) and np.all(lat < 5.0)
+    assert span >= rs.t_arrival[-1]
