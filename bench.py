@@ -36,6 +36,45 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32": 157.3, "bf16": 2500.0}  # dense MFMA TFLOP/s
 PEAK_HBM_GBS = 8000.0
 
+# Bytes moved between L2 and memory per launch, from two rocprofv3 --pmc runs
+# of ``bench.py --pmc-workload`` (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch; profiles/traffic_mixture-1M-d128.md), averaged over the launches
+# the timing aggregates (the assignment: one launch per level and iteration,
+# so the mean of the three levels).  A 1 GiB copy reads FETCH_SIZE 524,318 KiB
+# and writes WRITE_SIZE 1,048,576 KiB, so fetch counts are scaled by
+# 1048576/524318 and write counts by 1.  The figures hold for the kernel
+# source they were taken from (sha256 of the file) and, for the descent, for
+# its beams; otherwise traffic is reported as null.
+FETCH_SCALE = 1048576.0 / 524318.0
+WRITE_SCALE = 1.0
+TRAFFIC = {
+    "assign_bf16_mfma": {"file": "kmeans.hip", "sha256": "f176fa5a64788c6dd90a1befb6f10cf0b167971d995ef874f0cef8ac7fb18739",
+                         "fetch_kib": (139312.7 + 17627.0 + 776.0) / 3,
+                         "write_kib": (3909.0 + 391.0 + 20.0) / 3},
+    "assign_l2_mfma": {"file": "kmeans.hip", "sha256": "f176fa5a64788c6dd90a1befb6f10cf0b167971d995ef874f0cef8ac7fb18739",
+                       "fetch_kib": (285250.7 + 37690.3 + 1528.7) / 3,
+                       "write_kib": (6332.0 + 986.0 + 20.3) / 3},
+    "descent_bf16": {"file": "query.hip", "sha256": "9309e5006b1e074c38508aad3e6704338a403484cc89422b8792f6d072b88d5e", "beams": [16, 96, 176],
+                     "fetch_kib": 6330542.0, "write_kib": 1250.0},
+    "descent": {"file": "query.hip", "sha256": "9309e5006b1e074c38508aad3e6704338a403484cc89422b8792f6d072b88d5e", "beams": [16, 96, 160],
+                "fetch_kib": 13992329.0, "write_kib": 1250.0},
+}
+
+
+def traffic_bytes(kernel, beams=None):
+    """Measured bytes per launch of `kernel`, or None when its source (or
+    the descent's beams) changed since the counters were taken."""
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    path = os.path.join(ROOT, "paper_2208_02734_amd", "csrc", t["file"])
+    if hashlib.sha256(open(path, "rb").read()).hexdigest() != t["sha256"]:
+        return None
+    if "beams" in t and (beams is None or list(beams) != t["beams"]):
+        return None
+    return round((t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0)
+
 # beam candidates (top level first), cheapest first
 BEAMS = [(8, 64, 128), (16, 64, 160), (16, 96, 160), (16, 96, 176), (24, 96, 176),
          (24, 128, 192), (32, 128, 224), (64, 192, 256), (128, 256, 320), (256, 512, 512)]
@@ -58,6 +97,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--form", choices=["auto", "fp32", "bf16"], default="auto")
+    ap.add_argument("--pmc-workload", action="store_true",
+                    help="run only the counter workload: one build (2 Lloyd iterations) and "
+                         "one query batch per form, then a 1 GiB copy for calibration")
     return ap.parse_args()
 
 
@@ -159,6 +201,22 @@ def main():
 
     pk.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.pmc_workload:
+        cfg = datagen.config_scale()
+        Xd = torch.from_numpy(cfg.X).cuda()
+        Qd = torch.from_numpy(cfg.Q).cuda()
+        for prec, beams in (("bf16", (16, 96, 176)), ("fp32", (16, 96, 160))):
+            ix = pk.mask_build(Xd, cfg.levels, iters=2, seed=1, precision=prec)
+            pk.mask_query_beams(ix, Qd, 10, beams)
+            torch.cuda.synchronize()
+            ix.free()
+        a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 1 GiB
+        a.fill_(1.0)
+        b = a.clone()
+        torch.cuda.synchronize()
+        del a, b
+        print("pmc workload done", flush=True)
+        return 0
     t_gen = time.time()
     cfg = datagen.config_scale()
     X, Q = cfg.X, cfg.Q
@@ -336,10 +394,16 @@ def main():
             "p99": serving[form][0]["p99_ms"]},
         "roofline": {"bound": "mfma", "kernel": akey, "achieved": round(assign_tflops, 2),
                      "peak": PEAK[form], "unit": "TFLOP/s",
-                     "frac": round(assign_tflops / PEAK[form], 4), "traffic": None},
+                     "frac": round(assign_tflops / PEAK[form], 4),
+                     "traffic": traffic_bytes(akey), "traffic_unit": "bytes per launch"},
         "roofline_query": {"bound": "hbm", "kernel": dkey, "achieved": round(desc_gbs, 1),
                            "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                           "frac": round(desc_gbs / PEAK_HBM_GBS, 4), "traffic": None},
+                           "frac": round(desc_gbs / PEAK_HBM_GBS, 4),
+                           "traffic": traffic_bytes(dkey, beams),
+                           "traffic_unit": "bytes per launch",
+                           "traffic_gbs": (None if traffic_bytes(dkey, beams) is None or not d_ms
+                                           else round(traffic_bytes(dkey, beams) * d_cnt
+                                                      / (d_ms * 1e-3) / 1e9, 1))},
         "forms": forms,
         "serving": serving,
         "csr": sparse,

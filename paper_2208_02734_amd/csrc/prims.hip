@@ -242,20 +242,29 @@ void gather_rows_t(const float* src, int ld_src, const I* idx, int64_t n, int di
 
 // One thread per row: float32 sum of squares with four interleaved partial
 // sums over the float4 lanes, combined as (s0+s1)+(s2+s3).
+// G lanes per row, each summing its float4s (columns 4*(gl + G*i)) in four
+// partials, then a butterfly over the group: coalesced and in a fixed order.
+template <int G>
 __global__ void k_row_norms(const float* __restrict__ x, int ld, int64_t n,
                             float* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const float4* r = reinterpret_cast<const float4*>(x + i * ld);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = t / G;
+  const int gl = (int)(t % G);
   float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-  for (int c = 0; c < ld / 4; ++c) {
-    float4 v = r[c];
-    s0 = fmaf(v.x, v.x, s0);
-    s1 = fmaf(v.y, v.y, s1);
-    s2 = fmaf(v.z, v.z, s2);
-    s3 = fmaf(v.w, v.w, s3);
+  if (i < n) {
+    const float4* r = reinterpret_cast<const float4*>(x + i * ld);
+    for (int c = gl; c < ld / 4; c += G) {
+      const float4 v = r[c];
+      s0 = fmaf(v.x, v.x, s0);
+      s1 = fmaf(v.y, v.y, s1);
+      s2 = fmaf(v.z, v.z, s2);
+      s3 = fmaf(v.w, v.w, s3);
+    }
   }
-  out[i] = (s0 + s1) + (s2 + s3);
+  float a = (s0 + s1) + (s2 + s3);
+#pragma unroll
+  for (int o = G / 2; o >= 1; o >>= 1) a += __shfl_xor(a, o);
+  if (i < n && gl == 0) out[i] = a;
 }
 
 __global__ void k_offsets_from_sorted(const uint32_t* __restrict__ keys, int64_t n,
@@ -371,7 +380,10 @@ void copy_rows(const float* src, int ld_src, int64_t n, int dim, float* dst, int
 
 void row_norms(const float* x, int ld, int64_t n, float* out, hipStream_t s) {
   if (n <= 0) return;
-  k_row_norms<<<grid_for(n, kBlock), kBlock, 0, s>>>(x, ld, n, out);
+  const int f4 = ld / 4;
+  if (f4 <= 4) k_row_norms<4><<<grid_for(n * 4, kBlock), kBlock, 0, s>>>(x, ld, n, out);
+  else if (f4 <= 8) k_row_norms<8><<<grid_for(n * 8, kBlock), kBlock, 0, s>>>(x, ld, n, out);
+  else k_row_norms<16><<<grid_for(n * 16, kBlock), kBlock, 0, s>>>(x, ld, n, out);
   check_launch("row_norms");
 }
 
