@@ -33,7 +33,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": 157.3, "bf16": 2500.0}  # dense MFMA TFLOP/s
+PEAK = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}  # dense MFMA TFLOP/s
 PEAK_HBM_GBS = 8000.0
 
 # Bytes moved between L2 and memory per launch, from two rocprofv3 --pmc runs
@@ -255,7 +255,7 @@ def main():
 
     # ---- both forms: build, select the cheapest beams that pass the recall gate
     forms = {}
-    for form in ("fp32", "bf16"):
+    for form in ("fp32", "bf16", "fp8"):
         ix, _ = timed(lambda: build(form))
         ix.free()
         ix, b_ms = timed(lambda: build(form))
@@ -278,8 +278,8 @@ def main():
 
     form = args.form
     if form == "auto":
-        form = max(("fp32", "bf16"), key=lambda f: (forms[f]["recall@10"] >= args.gate,
-                                                     forms[f]["queries_per_s"]))
+        form = max(("fp32", "bf16", "fp8"), key=lambda f: (forms[f]["recall@10"] >= args.gate,
+                                                             forms[f]["queries_per_s"]))
     beams = tuple(forms[form]["beams"])
 
     # ---- timed steps: build + query in the selected form
@@ -317,13 +317,17 @@ def main():
         flops_per_build += 2.0 * items * k * d  # every item against its chunk's k prototypes
         items = C * k
     flops_per_build *= (args.iters + 1)
-    akey = "assign_l2_mfma" if form == "fp32" else "assign_bf16_mfma"
+    akey = {"fp32": "assign_l2_mfma", "bf16": "assign_bf16_mfma", "fp8": "assign_fp8_mfma"}[form]
     a_cnt, a_ms = kt.get(akey, (0, 0.0))
     assign_tflops = flops_per_build * args.steps / (a_ms * 1e-3) / 1e12 if a_ms else 0.0
-    dkey = "descent" if form == "fp32" else "descent_bf16"
+    dkey = {"fp32": "descent", "bf16": "descent_bf16", "fp8": "descent_fp8"}[form]
     d_cnt, d_ms = kt.get(dkey, (0, 0.0))
     rows = kt.get("descent_rows", (0, 0.0))[0]
-    row_bytes = ((d + 3) // 4 * 4) * 4 + 4 if form == "fp32" else ((d + 7) // 8 * 8) * 2 + 4
+    # bytes per evaluated row (row + id); FP8 rows carry a 4-byte scale.  For
+    # the FP8 form only the data rows are FP8 (prototype rows are FP32), so
+    # its figure counts every row as FP8: a lower bound of its bytes
+    row_bytes = {"fp32": ((d + 3) // 4 * 4) * 4 + 4, "bf16": ((d + 7) // 8 * 8) * 2 + 4,
+                 "fp8": ((d + 15) // 16 * 16) + 8}[form]
     desc_gbs = rows * row_bytes / (d_ms * 1e-3) / 1e9 if d_ms else 0.0
     counters = ("descent_rows", "refine_small_points", "refine_full_points")
     kernels = {name: {"launches": c, "total_ms": round(ms, 3),
@@ -335,7 +339,7 @@ def main():
     if not args.no_serve:
         serving = {}
         rates = [float(x) for x in args.serve_rates.split(",") if x]
-        for f in ("fp32", "bf16"):
+        for f in ("fp32", "bf16", "fp8"):
             sx = build(f)
             serving[f] = []
             for rate in rates:
@@ -381,7 +385,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if form == "bf16" else "f32",
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[form],
         "data": "synthetic",
         "config": {"workload": "mixture-1M-d128: 1,000,000 x 128 Gaussian mixture "
                                "(1,000 comps), levels 100x1000->5000->100, 30 Lloyd iters, "

@@ -53,7 +53,13 @@ typedef enum {
  * and the Euclidean distance is reported.  L1 ranks and reports sum |a-b|. */
 typedef enum { MASK_L2 = 0, MASK_L1 = 1 } mask_metric;
 
-/* Arithmetic of the distance screening.  MASK_FP32 is the plain form. */
+/* Arithmetic of the distance screening.  MASK_FP32 is the plain form.
+ * MASK_BF16: the build screens on BF16 MFMA; the descent reads BF16 rows at
+ * every level.  MASK_FP8_E4M3: rows quantised to OCP e4m3 with one FP32
+ * scale per row (s = max|x| / 448); the build screens on FP8 MFMA; the
+ * descent reads the data layer in FP8 and prototype levels in FP32.  Both
+ * re-rank the data layer's best candidates in FP32 (see mask_query) and keep
+ * FP64 sums; L2 metric only. */
 typedef enum { MASK_FP32 = 0, MASK_BF16 = 1, MASK_FP8_E4M3 = 2 } mask_precision;
 
 /* Optional device allocator (for instance PyTorch's caching allocator).
@@ -105,7 +111,8 @@ typedef struct {
   const mask_level* levels; /* host array [n_levels], bottom-up */
   int32_t lloyd_iters;   /* Lloyd iterations per level (>= 0) */
   uint64_t seed;         /* seeds the level-0 permutation */
-  int32_t rerank_factor; /* precision forms: FP32 re-rank of rerank_factor*k */
+  int32_t rerank_factor; /* precision forms: FP32 re-rank of rerank_factor*k
+                            candidates; <= 0: 4 for BF16, 48 for FP8 */
   const int32_t* perm;   /* optional device int32[n]: level-0 order; NULL = from seed */
 } mask_build_params;
 
@@ -153,8 +160,9 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
  * (distance, original id).  out_ids: device int32[q->n * k] (original data
  * row ids), out_dist: device float32[q->n * k], rows ascending; slots beyond
  * the candidate count hold id -1 and +inf.  1 <= k <= 2048, 1 <= r <= 2048.
- * Precision form (index built with MASK_BF16): rows are compared in BF16 and
- * the data layer's R = min(rerank_factor * k, C) nearest by BF16 distance
+ * Precision forms (index built with MASK_BF16 or MASK_FP8_E4M3): rows are
+ * compared in the low precision and the data layer's R = min(rerank_factor *
+ * k, C) nearest by that distance
  * are re-ranked in FP32 direct form on the FP32 rows, where C = 512 when k
  * and every beam are at most 512 and 2048 otherwise (all candidates in FP32
  * when they are no more than R, or when R <= k).

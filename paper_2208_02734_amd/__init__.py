@@ -313,7 +313,7 @@ def _params(levels, iters, seed, metric, precision, rerank_factor, perm):
 
 
 def mask_build(data, levels: Sequence[Tuple[int, int]], iters: int = 30, seed: int = 0,
-               metric: str = "l2", precision: str = "fp32", perm=None, rerank_factor: int = 4,
+               metric: str = "l2", precision: str = "fp32", perm=None, rerank_factor: int = 0,
                stream=None, torch_allocator: bool = True) -> Index:
     """Algorithm 1 on a device tensor (n x dim float32) or a CsrTensor;
     returns the index."""
@@ -393,7 +393,7 @@ def mask_free(index: Index):
 
 def mask_import(data, levels: Sequence[Tuple[int, int]], protos: Sequence[np.ndarray],
                 parents: Sequence[np.ndarray], metric: str = "l2", precision: str = "fp32",
-                rerank_factor: int = 4, stream=None, torch_allocator: bool = True) -> Index:
+                rerank_factor: int = 0, stream=None, torch_allocator: bool = True) -> Index:
     """Index from prototypes (chunk-major, per level) and parent ids (per
     level, for the items one level down), e.g. built by another
     implementation."""

@@ -234,6 +234,20 @@ void finalize_layout(mask_index& ix, const std::vector<int32_t*>& labels,
       dense_norms64(ix.protos[l], ld, ix.level_n[l], ix.dim, ix.norm64[l], s);
     }
   }
+  if (ix.precision == MASK_FP8_E4M3) {
+    // FP8 copy and scales of the data layer (prototype levels are read in
+    // FP32), and the data row -> leaf position map used by the FP32 re-rank
+    ix.ldq = fp8_stride(ld);
+    for (int l = 0; l <= 0; ++l) {
+      ix.protos_q[l] = ix.mem.alloc<uint8_t>(ix.level_n[l] * ix.ldq);
+      ix.scale_q[l] = ix.mem.alloc<float>(ix.level_n[l]);
+      quantize_fp8(ix.protos[l], ld, ix.level_n[l], ix.protos_q[l], ix.ldq, ix.scale_q[l],
+                   nullptr, s);
+    }
+    ix.inv0 = ix.mem.alloc<int32_t>(ix.level_n[0]);
+    scatter_iota(reinterpret_cast<const uint32_t*>(ix.orig[0]), ix.level_n[0],
+                 reinterpret_cast<uint32_t*>(ix.inv0), s);
+  }
   if (ix.precision == MASK_BF16) {
     // BF16 copies of every level in position order, and the data row -> leaf
     // position map used by the FP32 re-rank
@@ -270,16 +284,31 @@ void run_level(const float* items, int64_t n_items, int ld, int dim, int C, int 
     w.proto_norms_b = scratch.alloc<float>((int64_t)C * k);
     quantize_bf16(items, ld, n_items, w.items_b, w.ldb, nullptr, s);
   }
+  if (precision == MASK_FP8_E4M3 && metric == MASK_L2) {
+    w.precision = MASK_FP8_E4M3;
+    w.ldq = fp8_stride(ld);
+    const int64_t np = (int64_t)C * k;
+    w.items_q = scratch.alloc<uint8_t>(n_items * w.ldq);
+    w.items_qs = scratch.alloc<float>(n_items);
+    w.protos_q = scratch.alloc<uint8_t>(np * w.ldq);
+    w.protos_qs = scratch.alloc<float>(np);
+    w.proto_norms_q = scratch.alloc<float>(np);
+    quantize_fp8(items, ld, n_items, w.items_q, w.ldq, w.items_qs, nullptr, s);
+  }
   row_norms(items, ld, n_items, w.item_norms, s);
   if (init) copy_rows(init, ld, (int64_t)C * k, ld, protos, ld, s);
   else kmeans_init_first(items, ld, plan, protos, s);
   kmeans_proto_norms(protos, ld, (int64_t)C * k, w, s);
+  auto assign = [&]() {
+    if (w.precision == MASK_FP8_E4M3) kmeans_assign_fp8(ld, plan, protos, labels, w, s);
+    else kmeans_assign(items, ld, dim, plan, protos, labels, w, metric, s);
+  };
   for (int t = 0; t < iters; ++t) {
-    kmeans_assign(items, ld, dim, plan, protos, labels, w, metric, s);
+    assign();
     kmeans_update(items, ld, dim, plan, labels, protos, w, metric,
                   inertia_log ? inertia_log + (int64_t)t * C : nullptr, s);
   }
-  kmeans_assign(items, ld, dim, plan, protos, labels, w, metric, s);
+  assign();
   if (refined) {
     uint32_t cnt = 0;
     MASK_HIP(hipMemcpyAsync(&cnt, w.refine_count, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -337,6 +366,7 @@ DescentArgs descent_args(const mask_index& ix) {
   a.dim = ix.dim;
   a.ld = ix.ld;
   a.ldb = ix.ldb;
+  a.ldq = ix.ldq;
   a.metric = ix.metric;
   a.precision = ix.precision;
   a.rerank_factor = ix.rerank_factor;
@@ -347,6 +377,8 @@ DescentArgs descent_args(const mask_index& ix) {
     a.lv[l].norm64 = ix.norm64[l];
     a.lv[l].protos = ix.protos[l];
     a.lv[l].protos_b = ix.protos_b[l];
+    a.lv[l].protos_q = ix.protos_q[l];
+    a.lv[l].scale_q = ix.scale_q[l];
     a.lv[l].orig = ix.orig[l];
     a.lv[l].inv = ix.inv[l];
     a.lv[l].child_off = ix.child_off[l];
@@ -509,9 +541,8 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
       throw Error{MASK_ERR_UNSUPPORTED, "CSR data: L2 metric, FP32 form only"};
     if (!sparse && data->dim > kMaxDenseDim)
       throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};
-    if (p->precision == MASK_FP8_E4M3) throw Error{MASK_ERR_UNSUPPORTED, "FP8 form"};
-    if (p->precision == MASK_BF16 && p->metric != MASK_L2)
-      throw Error{MASK_ERR_UNSUPPORTED, "BF16 form of L1"};
+    if (p->precision != MASK_FP32 && p->metric != MASK_L2)
+      throw Error{MASK_ERR_UNSUPPORTED, "BF16 / FP8 form of L1"};
 
     auto ix = std::make_unique<mask_index>(a, s);
     const int L = p->n_levels;
@@ -523,7 +554,8 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
     ix->n_levels = L;
     ix->levels.assign(p->levels, p->levels + L);
     ix->level_n = sizes;
-    ix->rerank_factor = p->rerank_factor > 0 ? p->rerank_factor : 4;
+    ix->rerank_factor = p->rerank_factor > 0 ? p->rerank_factor
+                                             : (p->precision == MASK_FP8_E4M3 ? 48 : 4);
     const int ld = ix->ld;
     const int64_t n = data->n;
     if (sparse) {
@@ -707,11 +739,15 @@ mask_status mask_import(const mask_matrix* data, int32_t n_levels, const mask_le
     ix->ld = round_up4(data->dim);
     ix->metric = metric;
     ix->precision = p ? p->precision : MASK_FP32;
-    MASK_CHECK(ix->precision == MASK_FP32 || ix->precision == MASK_BF16, "unsupported precision");
+    MASK_CHECK(ix->precision >= MASK_FP32 && ix->precision <= MASK_FP8_E4M3,
+               "unsupported precision");
+    if (ix->precision != MASK_FP32 && metric != MASK_L2)
+      throw Error{MASK_ERR_UNSUPPORTED, "BF16 / FP8 form of L1"};
     if (sparse && (ix->precision != MASK_FP32 || metric != MASK_L2))
       throw Error{MASK_ERR_UNSUPPORTED, "CSR data: L2 metric, FP32 form only"};
     ix->sparse = sparse;
-    ix->rerank_factor = (p && p->rerank_factor > 0) ? p->rerank_factor : 4;
+    ix->rerank_factor = (p && p->rerank_factor > 0) ? p->rerank_factor
+                        : (ix->precision == MASK_FP8_E4M3 ? 48 : 4);
     ix->n_levels = L;
     ix->levels.assign(levels, levels + L);
     ix->level_n = sizes;

@@ -244,7 +244,26 @@ struct KmeansWork {
   uint16_t* items_b = nullptr;
   uint16_t* protos_b = nullptr;
   float* proto_norms_b = nullptr;
+  // FP8 form: quantised copies (row stride ldq bytes) and per-row scales
+  int ldq = 0;
+  uint8_t* items_q = nullptr;
+  float* items_qs = nullptr;
+  uint8_t* protos_q = nullptr;
+  float* protos_qs = nullptr;
+  float* proto_norms_q = nullptr;  // squared norms of the dequantised prototypes
 };
+
+// FP8 (OCP e4m3) rows with one FP32 scale per row: s = max|x| / 448 (1 for a
+// zero row), q = e4m3(x / s) rounded to nearest; row stride ldq bytes (a
+// multiple of 16), zero padded.  norms (may be null) = FP32 squared norm of
+// the dequantised row s*q.  (fp8.hip)
+int fp8_stride(int ld);
+void quantize_fp8(const float* x, int ld, int64_t n, uint8_t* out, int ldq, float* scale,
+                  float* norms, hipStream_t s);
+// Assignment of the FP8 form: re-quantise the prototypes, then screen on
+// v_mfma_f32_32x32x16_fp8_fp8 (no certification).
+void kmeans_assign_fp8(int ld, const ChunkPlan& plan, const float* protos, int32_t* labels,
+                       KmeansWork& w, hipStream_t s);
 
 // out[i*ldb + c] = bf16(x[i*ld + c]) (round to nearest even), zero padding;
 // norms[i] = FP32 squared norm of the rounded row when norms is not null.
@@ -315,6 +334,8 @@ void kmeans_sparse(const Csr& items, int ld, int n_chunks, int k, int iters, con
 struct LevelView {
   const float* protos;       // n x ld, position order (null for CSR data)
   const uint16_t* protos_b;  // n x ldb BF16 copy (BF16 form), position order
+  const uint8_t* protos_q;   // n x ldq FP8 copy (FP8 form), position order
+  const float* scale_q;      // FP32 scale of each FP8 row
   const int32_t* orig;       // position -> chunk-major id (data row id at level 0)
   const int32_t* inv;        // chunk-major id -> position (levels >= 1)
   const uint32_t* child_off; // n + 1 offsets into the level below (levels >= 1)
@@ -334,6 +355,7 @@ struct DescentArgs {
   int dim;
   int ld;
   int ldb;
+  int ldq;  // FP8 row stride in bytes (FP8 form)
   int metric;
   int precision;
   int rerank_factor;
@@ -378,6 +400,9 @@ struct mask_index {
   // device arrays; index 0 = data in leaf order
   float* protos[mask::kMaxLevels + 1] = {};
   uint16_t* protos_b[mask::kMaxLevels + 1] = {};  // BF16 copies (BF16 form)
+  uint8_t* protos_q[mask::kMaxLevels + 1] = {};   // FP8 copies (FP8 form)
+  float* scale_q[mask::kMaxLevels + 1] = {};
+  int ldq = 0;
   int ldb = 0;
   int rerank_factor = 4;
   int32_t* inv0 = nullptr;  // data row id -> leaf position (BF16 form)

@@ -186,8 +186,12 @@ __device__ inline float acc4(float s, float4 x, float4 q) {
 //   query is at distance exactly 0.
 constexpr int kQList = 1024;
 
-template <int TPR, int NV, int U, int METRIC, bool B16, int CAPB, int CAP, bool SP>
+//   MODE 0: dense rows; 1: CSR index (SP); 2: FP8 data rows with one FP32
+//   scale per row (the FP8 variant of the precision form: prototype levels
+//   in FP32, the data layer in FP8, re-ranked like BF16).
+template <int TPR, int NV, int U, int METRIC, bool B16, int CAPB, int CAP, int MODE>
 __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa) {
+  constexpr bool SP = MODE == 1, F8 = MODE == 2, LOWP = B16 || F8;
   extern __shared__ float4 s_q4[];  // ld/4 float4
   __shared__ int32_t s_qc[SP ? kQList : 1];
   __shared__ float s_qv[SP ? kQList : 1];
@@ -272,9 +276,11 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
     rows_seen += m;
     // the data layer of the BF16 form keeps an oversized set for the FP32 re-rank
     uint32_t want = (lev == 0) ? (uint32_t)k : (uint32_t)(qa.r_lev[lev] > 0 ? qa.r_lev[lev] : r);
-    bool low = B16;  // rows read in BF16 at this level
+    // rows read in BF16 at every level, or in FP8 at the data layer only:
+    // three mantissa bits are too coarse to choose prototypes
+    bool low = B16 || (F8 && lev == 0);
     bool rerank = false;
-    if (lev == 0 && B16) {
+    if (lev == 0 && LOWP) {
       // the re-rank set: rerank_factor * k candidates, at most CAPB
       const int64_t R = min((int64_t)a.rerank_factor * k, (int64_t)CAPB);
       if ((int64_t)m > R && R > k) {
@@ -412,6 +418,44 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
               acc[u] = s0;
             }
           }
+        } else if (F8 && low) {
+          // FP8 rows: 16 dimensions per 16-byte chunk, dequantised with the
+          // row's scale, FP32 direct form against the query in LDS
+          const int nc = a.ldq / 16;
+          const uint4* rowq[U];
+          float rs[U], au[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            rowq[u] = reinterpret_cast<const uint4*>(V.protos_q + pos[u] * (int64_t)a.ldq);
+            rs[u] = V.scale_q[pos[u]];
+            au[u] = 0.f;
+          }
+          for (int c = gl; c < nc; c += TPR) {
+            uint4 x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = rowq[u][c];
+            float4 q[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              q[e] = (4 * c + e < ld4) ? s_q4[4 * c + e] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const uint32_t w[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const float d0 = fmaf(rs[u], __builtin_amdgcn_cvt_f32_fp8((int)w[e], 0), -q[e].x);
+                const float d1 = fmaf(rs[u], __builtin_amdgcn_cvt_f32_fp8((int)w[e], 1), -q[e].y);
+                const float d2 = fmaf(rs[u], __builtin_amdgcn_cvt_f32_fp8((int)w[e], 2), -q[e].z);
+                const float d3 = fmaf(rs[u], __builtin_amdgcn_cvt_f32_fp8((int)w[e], 3), -q[e].w);
+                au[u] = fmaf(d0, d0, au[u]);
+                au[u] = fmaf(d1, d1, au[u]);
+                au[u] = fmaf(d2, d2, au[u]);
+                au[u] = fmaf(d3, d3, au[u]);
+              }
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u) acc[u] = au[u];
         } else if (!B16 && NV > 0) {
           float4 x[U][NQ];
 #pragma unroll
@@ -520,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
         __syncthreads();
       }
     } else {
-      if (B16 && rerank) {
+      if (LOWP && rerank) {
         // FP32 direct form on the FP32 rows of the kept set, then the k nearest
         for (uint32_t j = grp; j < kept; j += kGroups) {
           const uint32_t id = (uint32_t)s_buf[j];
@@ -565,21 +609,21 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
   if (qa.rows && tid == 0) atomicAdd(qa.rows, rows_seen);
 }
 
-template <int TPR, int NV, int U, bool B16, int CAPB, int CAP, bool SP>
+template <int TPR, int NV, int U, bool B16, int CAPB, int CAP, int MODE>
 void launch3(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   const size_t shm = (size_t)a.ld * sizeof(float);
-  if (SP)
-    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, SP><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
+  if constexpr (MODE != 0 || B16)  // CSR, FP8 and BF16 indexes are L2 only
+    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, MODE><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
   else if (a.metric == MASK_L2)
-    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, SP><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
+    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, MODE><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
   else
-    k_descent<TPR, NV, U, 1, B16, CAPB, CAP, SP><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
+    k_descent<TPR, NV, U, 1, B16, CAPB, CAP, MODE><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
 }
 
-template <int TPR, int NV, int U, bool B16, bool SP = false>
+template <int TPR, int NV, int U, bool B16, int MODE = 0>
 void launch2(const DescentArgs& a, const QueryArgs& qa, int need, hipStream_t s) {
-  if (need <= 512) launch3<TPR, NV, U, B16, 512, 2560, SP>(a, qa, s);
-  else launch3<TPR, NV, U, B16, 2048, 4096, SP>(a, qa, s);
+  if (need <= 512) launch3<TPR, NV, U, B16, 512, 2560, MODE>(a, qa, s);
+  else launch3<TPR, NV, U, B16, 2048, 4096, MODE>(a, qa, s);
 }
 
 }  // namespace
@@ -587,14 +631,26 @@ void launch2(const DescentArgs& a, const QueryArgs& qa, int need, hipStream_t s)
 void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   if (qa.nq <= 0) return;
   ScopedTiming timing(a.sparse ? "descent_csr"
-                               : (a.precision == MASK_BF16 ? "descent_bf16" : "descent"), s);
+                               : (a.precision == MASK_BF16       ? "descent_bf16"
+                                  : a.precision == MASK_FP8_E4M3 ? "descent_fp8"
+                                                                 : "descent"),
+                      s);
   const bool b16 = a.precision == MASK_BF16;
   // LDS class from the beams and k; the BF16 re-rank set fits the class
   int need = qa.k > qa.r ? qa.k : qa.r;
   for (int l = 1; l <= a.n_levels; ++l) need = qa.r_lev[l] > need ? qa.r_lev[l] : need;
   if (a.sparse) {
-    launch2<16, 0, 4, false, true>(a, qa, need, s);
+    launch2<16, 0, 4, false, 1>(a, qa, need, s);
     check_launch("descent_csr");
+    return;
+  }
+  if (a.precision == MASK_FP8_E4M3) {
+    const int nc = a.ldq / 16;
+    if (nc <= 2) launch2<2, 0, 2, false, 2>(a, qa, need, s);
+    else if (nc <= 4) launch2<4, 0, 2, false, 2>(a, qa, need, s);
+    else if (nc <= 8) launch2<8, 0, 2, false, 2>(a, qa, need, s);
+    else launch2<16, 0, 2, false, 2>(a, qa, need, s);
+    check_launch("descent_fp8");
     return;
   }
   // Lane groups per row width, measured on MI355X (1M-point mixtures, beams

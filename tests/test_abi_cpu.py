@@ -75,6 +75,11 @@ def test_unsupported_requests(L):
     p, lv = pk._params([(2, 10)], 5, 0, "l2", "fp32", 4, None)
     st = L.mask_build(ctypes.byref(m), ctypes.byref(p), None, None, ctypes.byref(h))
     assert st == 4
+    # the low-precision forms are L2 only
+    m.dim = 16
+    for prec in ("bf16", "fp8"):
+        p2, lv2 = pk._params([(2, 10)], 5, 0, "l1", prec, 4, None)
+        assert L.mask_build(ctypes.byref(m), ctypes.byref(p2), None, None, ctypes.byref(h)) == 4
 
 
 def test_csr_arguments_are_checked_before_device_work(L):

@@ -119,3 +119,78 @@ def test_ragged_rows_equal_single_queries(pk):
         i1, d1 = pk.mask_query(gix, dev(Q[i:i + 1]), int(ks[i]), int(rs[i]))
         assert np.array_equal(ids[off[i]:off[i + 1]], host(i1)[0])
         assert np.array_equal(dist[off[i]:off[i + 1]], host(d1)[0])
+
+
+# --------------------------------------------------------------- FP8 form
+# OCP e4m3 rows with one FP32 scale per row: 3 mantissa bits, so a rounded
+# value is within 2^-4 relative of the original.  The FP8 screening is not
+# certified; the returned distances are FP32 re-ranked and so exact.
+
+def test_fp8_build_is_close_to_fp32(pk):
+    X, _ = _mixture(30_000, 128, 60, seed=328)
+    levels = [(6, 200), (1, 40)]
+    g8 = pk.mask_build(dev(X), levels, iters=10, seed=1, precision="fp8")
+    frac, worst = _nearest_agreement(X, g8, 6, 200)
+    g32 = pk.mask_build(dev(X), levels, iters=10, seed=1)
+
+    def inertia(ix):
+        P, par = ix.export_level(1)
+        return float(((X.astype(np.float64) - P[par]) ** 2).sum())
+    ratio = inertia(g8) / inertia(g32)
+    print(f"fp8 label agreement {frac:.4f}, worst excess {worst:.4f}, inertia ratio {ratio:.4f}")
+    assert frac > 0.9, frac
+    assert ratio <= 1.03, ratio
+    # Rounding bound: x^ = x + dx with |dx| <= 2^-4 |x| (likewise c), so
+    # | |x^ - c^|^2 - |x - c|^2 | <= (2^-3 + 2^-8)(|x| + |c|)^2
+    #                           <= 0.26 (|x|^2 + |c|^2),
+    # and the chosen prototype is at most twice that above the nearest.
+    P, par = g8.export_level(1)
+    X64 = X.astype(np.float64)
+    for c in range(6):
+        members = np.nonzero(par // 200 == c)[0]
+        Pc = P[c * 200:(c + 1) * 200].astype(np.float64)
+        D = mo.pairwise(X[members], Pc)
+        got = D[np.arange(members.size), par[members] - c * 200]
+        bound = 0.52 * ((X64[members] ** 2).sum(1) + (Pc ** 2).sum(1).max())
+        assert np.all(got - D.min(axis=1) <= bound)
+
+
+def test_fp8_query_distances_are_fp32_exact(pk):
+    X, Q = _mixture(20_000, 96, 50, seed=310, nq=100)
+    levels = [(10, 100), (1, 40)]
+    gix = pk.mask_build(dev(X), levels, iters=8, seed=2, precision="fp8")
+    for r in (4, 16):
+        ids, dist = pk.mask_query(gix, dev(Q), 10, r)
+        ids, dist = host(ids).astype(np.int64), host(dist)
+        true = oc.true_distances(X, Q, ids)
+        v = ids >= 0
+        assert np.all(np.abs(dist[v] - true[v]) <= REL * true[v])
+        assert np.all(dist[:, 1:] >= dist[:, :-1])
+
+
+def test_fp8_rerank_of_everything_is_exact(pk):
+    X, Q = _mixture(4000, 32, 20, seed=320, nq=50)
+    levels = [(4, 50), (1, 20)]
+    oix = mo.build(X, levels, 5, seed=3)
+    gix = pk.mask_import(dev(X), levels, oix.protos, oix.parents, precision="fp8",
+                         rerank_factor=1000)
+    ids, dist = pk.mask_query(gix, dev(Q), 10, 2048)
+    tids, tdist = mo.exact_knn(X, Q, 10)
+    true = oc.true_distances(X, Q, host(ids).astype(np.int64))
+    assert oc.check_knn(host(ids), host(dist), tids, tdist, true, REL).ok
+
+
+def test_fp8_recall_close_to_fp32_on_shared_index(pk):
+    X, Q = _mixture(30_000, 64, 80, seed=330, nq=200)
+    levels = [(10, 300), (1, 60)]
+    oix = mo.build(X, levels, 6, seed=4)
+    g32 = pk.mask_import(dev(X), levels, oix.protos, oix.parents)
+    g8 = pk.mask_import(dev(X), levels, oix.protos, oix.parents, precision="fp8")
+    tids, tdist = mo.exact_knn(X, Q, 10)
+    rec = {}
+    for name, ix in (("fp32", g32), ("fp8", g8)):
+        ids, _ = pk.mask_query(ix, dev(Q), 10, 8)
+        ids = host(ids).astype(np.int64)
+        rec[name] = oc.recall_at_k(ids, tids, tdist, oc.true_distances(X, Q, ids), 10)
+    print(rec)
+    assert rec["fp8"] >= rec["fp32"] - 0.05, rec
