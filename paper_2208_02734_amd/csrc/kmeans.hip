@@ -16,6 +16,8 @@
 // sort of the labels), summed in FP64 in that fixed order, and divided by the
 // count; an empty prototype keeps its value.  The inertia of the assignment
 // under the old prototypes is accumulated in FP64 on the same pass.
+#include <cfloat>
+
 #include "internal.hpp"
 
 #include <algorithm>
@@ -892,16 +894,21 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_bf16(
       s_c4[buf][(row * LDW) / 8 + v8] = stage[i];
     }
     if (threadIdx.x < TN)
-      s_hn[buf][threadIdx.x] = (tile_base + (int)threadIdx.x < k) ? -0.5f * hstage : -INFINITY;
+      // past k: the most negative finite value (the index bits below must
+      // not turn the score into a NaN)
+      s_hn[buf][threadIdx.x] = (tile_base + (int)threadIdx.x < k) ? -0.5f * hstage : -FLT_MAX;
   };
   load_tile(0);
   store_tile(0);
   __syncthreads();
 
+  // Running best per lane: the score with the accumulator register's index
+  // in its 4 low mantissa bits (a change of at most 2^-19 relative), and the
+  // first prototype of the 32-row block it came from.
   float b1[PB];
-  int i1[PB];
+  int blk[PB];
 #pragma unroll
-  for (int pb = 0; pb < PB; ++pb) { b1[pb] = -INFINITY; i1[pb] = 0; }
+  for (int pb = 0; pb < PB; ++pb) { b1[pb] = -INFINITY; blk[pb] = 0; }
 
   for (int t = 0; t < ntiles; ++t) {
     const int buf = t & 1;
@@ -923,21 +930,19 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_bf16(
         for (int pb = 0; pb < PB; ++pb)
           acc[pb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bf[pb][s], acc[pb], 0, 0, 0);
       }
-      const int jbase = t * TN + cb * 32 + 4 * h;
+      const int jbase = t * TN + cb * 32;
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          acc[pb][i] = __uint_as_float((__float_as_uint(acc[pb][i]) & ~15u) | (uint32_t)i);
         float m = fmaxf(fmaxf(acc[pb][0], acc[pb][1]), acc[pb][2]);
 #pragma unroll
         for (int i = 3; i < 15; i += 2) m = fmaxf(fmaxf(m, acc[pb][i]), acc[pb][i + 1]);
         m = fmaxf(m, acc[pb][15]);
-        if (m > b1[pb]) {
-          // first register holding the maximum: lowest prototype index
-          int ii = 15;
-#pragma unroll
-          for (int i = 14; i >= 0; --i) ii = (acc[pb][i] == m) ? i : ii;
-          b1[pb] = m;
-          i1[pb] = jbase + 8 * (ii >> 2) + (ii & 3);
-        }
+        const bool better = m > b1[pb];
+        b1[pb] = better ? m : b1[pb];
+        blk[pb] = better ? jbase : blk[pb];
       }
     }
     if (t + 1 < ntiles) store_tile(buf ^ 1);
@@ -945,10 +950,12 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_bf16(
   }
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
+    const uint32_t ii = __float_as_uint(b1[pb]) & 15u;
+    int i1 = blk[pb] + 8 * (int)(ii >> 2) + 4 * h + (int)(ii & 3u);
     const float o = __shfl_xor(b1[pb], 32);
-    const int oi = __shfl_xor(i1[pb], 32);
-    if (o > b1[pb] || (o == b1[pb] && oi < i1[pb])) { b1[pb] = o; i1[pb] = oi; }
-    if (h == 0 && pidx[pb] < c1) labels[pidx[pb]] = chunk * k + i1[pb];
+    const int oi = __shfl_xor(i1, 32);
+    if (o > b1[pb] || (o == b1[pb] && oi < i1)) { b1[pb] = o; i1 = oi; }
+    if (h == 0 && pidx[pb] < c1) labels[pidx[pb]] = chunk * k + i1;
   }
 }
 
