@@ -25,6 +25,9 @@ What it computes, by paper passage:
                          Section 3.3 ("Searching and data insertion"),
                          generalised from the greedy choice to a beam of the
                          r nearest prototypes at every level.
+* ``range_query_one``  - the range search of Algorithm 3: the prototypes
+                         within the radius at every level, then the points
+                         within the radius under them.
 * ``exact_knn``        - the k-nearest-neighbour query of the problem
                          statement (Section 1) by exhaustive search.
 
@@ -360,6 +363,49 @@ def query(index: OracleIndex, Q: np.ndarray, k: int, r: int):
     for i in range(Q.shape[0]):
         ids[i], dist[i] = query_one(index, Q[i], k, r)
     return ids, dist
+
+
+# --------------------------------------------------------------------------
+# Range search (Algorithm 3 and the range-query paragraph of Section 3.3)
+# --------------------------------------------------------------------------
+
+
+def range_query_one(index: OracleIndex, q: np.ndarray, radius: float, max_out: int,
+                    level_cap: int):
+    """Range search for one query.  At the top level, and at every level
+    below among the children of the kept prototypes, keep the prototypes
+    whose distance to q is at most ``radius`` (the ball of the paragraph);
+    at the data layer, the points under the kept level-1 prototypes whose
+    distance is at most ``radius`` are the answer.
+
+    Readings: distances compare as squared L2 against radius^2 (delta <= r);
+    at most ``level_cap`` prototypes are kept per level, the nearest by
+    (distance, id), a bound the paper leaves open; the answer is ranked by
+    (distance, id) and the first ``max_out`` are returned (ids, reported
+    distances) together with the number of points within the radius."""
+    if index.metric != "l2":
+        raise ValueError("range search is written for the l2 metric")
+    L = index.n_levels
+    q = np.asarray(q, dtype=np.float64)[None, :]
+    r2 = float(radius) ** 2
+    kids = [index.children(l) for l in range(L)]
+    cand = np.arange(index.protos[L - 1].shape[0], dtype=np.int64)
+    for l in range(L - 1, -1, -1):
+        d = pairwise(q, index.protos[l][cand], "l2")[0] if cand.size else np.zeros(0)
+        inside = d <= r2
+        cand_in, d_in = cand[inside], d[inside]
+        sel = cand_in[smallest(d_in, cand_in, level_cap)]
+        cand = (np.concatenate([kids[l][p] for p in sel]) if sel.size else
+                np.zeros(0, dtype=np.int64))
+    d = pairwise(q, index.data[cand], "l2")[0] if cand.size else np.zeros(0)
+    inside = d <= r2
+    cand_in, d_in = cand[inside], d[inside]
+    pos = smallest(d_in, cand_in, max_out)
+    ids = np.full(max_out, -1, dtype=np.int64)
+    dist = np.full(max_out, np.inf, dtype=np.float64)
+    ids[:pos.size] = cand_in[pos]
+    dist[:pos.size] = np.sqrt(d_in[pos])
+    return ids, dist, int(cand_in.size)
 
 
 # --------------------------------------------------------------------------

@@ -93,3 +93,23 @@ def test_off_by_one_schedule_is_caught(monkeypatch):
 def test_wrong_splitmix_constant_is_caught(monkeypatch):
     monkeypatch.setattr(mo, "_M2", np.uint64(0x94D049BB133111EA))
     assert _fails(pins.test_splitmix64_known_answers)
+
+
+def test_range_radius_not_squared_is_caught(monkeypatch):
+    # comparing squared distances with the radius itself (not its square)
+    orig = mo.range_query_one
+
+    def bad(index, q, radius, max_out, level_cap):
+        return orig(index, q, float(radius) ** 0.5, max_out, level_cap)
+    monkeypatch.setattr(mo, "range_query_one", bad)
+    assert _fails(pins.test_range_search_on_one_to_one_index_is_exact)
+
+
+def test_range_strict_boundary_drops_the_exact_match(monkeypatch):
+    # a strict "<" at the boundary would lose the point at radius 0
+    orig_pairwise = mo.pairwise
+
+    def bad(A, B, metric="l2", block=256):
+        return orig_pairwise(A, B, metric, block) + 1e-300
+    monkeypatch.setattr(mo, "pairwise", bad)
+    assert _fails(pins.test_range_search_on_one_to_one_index_is_exact)

@@ -336,3 +336,71 @@ def test_recall_counts_ties():
     assert oc.recall_at_k(got, true_ids, true_dist, got_true, 3) == 1.0
     got_true2 = np.array([[1.0, 2.0, 3.5]])
     assert abs(oc.recall_at_k(got, true_ids, true_dist, got_true2, 3) - 2 / 3) < 1e-12
+
+
+# ------------------------------------------------------------ range search
+
+def _ball(X, q, radius):
+    """Points within radius of q from scipy's kd-tree, ranked by (d, id)."""
+    tree = cKDTree(X.astype(np.float64))
+    idx = np.array(sorted(tree.query_ball_point(q, radius)), dtype=np.int64)
+    d = np.sqrt(((X[idx].astype(np.float64) - q) ** 2).sum(1)) if idx.size else np.zeros(0)
+    order = np.lexsort((idx, d))
+    return idx[order], d[order]
+
+
+def test_range_search_with_every_prototype_in_the_ball_is_exhaustive():
+    g = np.random.default_rng(21)
+    X = g.standard_normal((400, 4)).astype(np.float32)
+    ix = mo.build(X, [(4, 12), (1, 6)], 4, seed=2)
+    for q in g.standard_normal((6, 4)):
+        radius = 1.3
+        # a radius that contains every prototype of every level: the search
+        # reaches every leaf, so it answers the query exactly
+        big = 50.0
+        ids, dist, count = mo.range_query_one(ix, q, big, 400, 1000)
+        assert count == 400
+        ids, dist, count = mo.range_query_one(ix, q, radius, 400, 1000)
+        b_ids, b_d = _ball(X, q, radius)
+        # prototypes farther than the radius cut their points off: a subset
+        assert set(ids[ids >= 0].tolist()) <= set(b_ids.tolist())
+        assert count == int(np.sum(ids >= 0))
+
+
+def test_range_search_on_one_to_one_index_is_exact():
+    # one prototype per item at every level (the exact configuration of
+    # Section 5): every point's ancestors are the point itself, so the
+    # search returns exactly the ball
+    g = np.random.default_rng(22)
+    X = g.standard_normal((120, 3)).astype(np.float32)
+    ix = mo.build(X, [(4, 30), (2, 60)], 3, seed=5)
+    for q in g.standard_normal((8, 3)):
+        for radius in (0.4, 0.9, 1.7):
+            ids, dist, count = mo.range_query_one(ix, q, radius, 200, 1000)
+            b_ids, b_d = _ball(X, q, radius)
+            assert count == b_ids.size
+            assert np.array_equal(ids[:count], b_ids)
+            np.testing.assert_allclose(dist[:count], b_d, rtol=1e-12)
+    # a data point at radius 0 finds itself
+    ids, dist, count = mo.range_query_one(ix, X[17].astype(np.float64), 0.0, 5, 1000)
+    assert count == 1 and ids[0] == 17 and dist[0] == 0.0
+
+
+def test_range_search_is_monotone_and_capped():
+    g = np.random.default_rng(23)
+    X = g.standard_normal((600, 5)).astype(np.float32)
+    ix = mo.build(X, [(6, 10), (1, 8)], 4, seed=3)
+    q = g.standard_normal(5)
+    prev = set()
+    for radius in (0.5, 1.0, 1.5, 2.5, 4.0):
+        ids, dist, count = mo.range_query_one(ix, q, radius, 600, 1000)
+        cur = set(ids[ids >= 0].tolist())
+        assert prev <= cur
+        assert np.all(dist[:count] <= radius)
+        prev = cur
+    # the per-level cap keeps the nearest prototypes: cap 1 follows the
+    # greedy path of the k-NN descent
+    ids1, _, _ = mo.range_query_one(ix, q, 50.0, 600, 1)
+    _, _, tr = mo.query_one(ix, q, 3, 1, trace=True)
+    leaf = set(ix.children(0)[tr.selected[-1][0]].tolist())
+    assert set(ids1[ids1 >= 0].tolist()) == leaf
