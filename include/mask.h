@@ -196,6 +196,21 @@ mask_status mask_query_debug(const mask_index* ix, const mask_matrix* q, int32_t
                              int32_t r, int32_t* out_ids, float* out_dist, int32_t* sel,
                              void* hip_stream);
 
+/* Range search (Algorithm 3): for each query, the prototypes within
+ * radius[i] (device float32[q->n]; a negative or NaN radius finds nothing)
+ * are kept at the top level and, among the children of the kept ones, at
+ * every level below (at most level_cap per level: the nearest, by (distance,
+ * id)); the answer is the data points within radius[i] under the kept
+ * level-1 prototypes.  out_ids / out_dist (device, q->n x max_out): the
+ * nearest max_out of them ascending, padded with (-1, +inf); out_count
+ * (device int32[q->n]): how many are within the radius (may exceed
+ * max_out).  Distances compare as squared L2 against radius^2 in float32.
+ * Plain FP32 form (dense or CSR), L2 metric; 1 <= max_out, level_cap <=
+ * 2048.  Asynchronous on hip_stream. */
+mask_status mask_query_range(const mask_index* ix, const mask_matrix* q, const float* radius,
+                             int32_t max_out, int32_t level_cap, int32_t* out_ids,
+                             float* out_dist, int32_t* out_count, void* hip_stream);
+
 /* Releases the index (NULL is allowed).  Must not race with queries. */
 mask_status mask_free(mask_index* ix);
 

@@ -83,6 +83,7 @@ class mask_server_stats(ctypes.Structure):
 _lib = None
 
 EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_beams", "mask_query_ragged",
+            "mask_query_range",
             "mask_query_debug", "mask_free",
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
             "mask_last_error", "mask_timing_enable", "mask_timing_report", "mask_clock",
@@ -106,6 +107,7 @@ def lib() -> ctypes.CDLL:
     L.mask_query_debug.argtypes = [VP, P(mask_matrix), I32, I32, VP, VP, VP, VP]
     L.mask_query_ragged.argtypes = [VP, P(mask_matrix), VP, VP, VP, I32, I32, VP, VP, VP]
     L.mask_query_beams.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP]
+    L.mask_query_range.argtypes = [VP, P(mask_matrix), VP, I32, I32, VP, VP, VP, VP]
     L.mask_free.argtypes = [VP]
     L.mask_index_info.argtypes = [VP, P(mask_info)]
     L.mask_export_level.argtypes = [VP, I32, VP, VP]
@@ -385,6 +387,24 @@ def mask_query_ragged(index: Index, queries, k_i, r_i, stream=None, k_max: int =
                                    off.data_ptr(), k_max, r_max, ids.data_ptr(), dist.data_ptr(),
                                    _stream_handle(stream)))
     return ids[:total], dist[:total], off
+
+
+def mask_query_range(index: Index, queries, radius, max_out: int, level_cap: int, stream=None):
+    """Range search (Algorithm 3); radius: a float or a float32 CUDA tensor
+    of length nq.  Returns (ids (nq x max_out), dist, count) tensors."""
+    torch = _torch()
+    m = _matrix(queries)
+    nq = queries.shape[0]
+    if not isinstance(radius, torch.Tensor):
+        radius = torch.full((nq,), float(radius), dtype=torch.float32, device=queries.device)
+    radius = radius.to(device=queries.device, dtype=torch.float32).contiguous()
+    ids = torch.empty((nq, max_out), dtype=torch.int32, device=queries.device)
+    dist = torch.empty((nq, max_out), dtype=torch.float32, device=queries.device)
+    count = torch.empty(nq, dtype=torch.int32, device=queries.device)
+    _check(lib().mask_query_range(index.handle, ctypes.byref(m), radius.data_ptr(), int(max_out),
+                                  int(level_cap), ids.data_ptr(), dist.data_ptr(),
+                                  count.data_ptr(), _stream_handle(stream)))
+    return ids, dist, count
 
 
 def mask_free(index: Index):

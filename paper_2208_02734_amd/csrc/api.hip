@@ -393,7 +393,8 @@ DescentArgs descent_args(const mask_index& ix) {
 mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
                        const int32_t* k_arr, const int32_t* r_arr, const int64_t* out_off,
                        int32_t* out_ids, float* out_dist, int32_t* sel, void* hip_stream,
-                       const int32_t* r_levels = nullptr) {
+                       const int32_t* r_levels = nullptr, const float* radius = nullptr,
+                       int32_t* out_count = nullptr) {
   try {
     MASK_CHECK(ix != nullptr, "index is NULL");
     if (ix->sparse) check_csr(q, "queries (CSR index)");
@@ -424,6 +425,13 @@ mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, in
     qa.out_dist = out_dist;
     qa.sel = sel;
     qa.rows = timing_row_counter();
+    if (radius) {
+      MASK_CHECK(out_count != nullptr, "out_count is NULL");
+      if (ix->precision != MASK_FP32 || ix->metric != MASK_L2)
+        throw Error{MASK_ERR_UNSUPPORTED, "range search: plain FP32 form, L2 metric"};
+      qa.radius = radius;
+      qa.out_count = out_count;
+    }
     for (int l = 0; l <= kMaxLevels; ++l) qa.r_lev[l] = 0;
     if (r_levels) {
       MASK_CHECK(!sel, "per-level beams are not combined with the debug selections");
@@ -639,6 +647,17 @@ mask_status mask_query_ragged(const mask_index* ix, const mask_matrix* q, const 
   }
   return query_impl(ix, q, k_max, r_max, k_i, r_i, out_off, out_ids, out_dist, nullptr,
                     hip_stream);
+}
+
+mask_status mask_query_range(const mask_index* ix, const mask_matrix* q, const float* radius,
+                             int32_t max_out, int32_t level_cap, int32_t* out_ids,
+                             float* out_dist, int32_t* out_count, void* hip_stream) {
+  if (!radius) {
+    set_error("radius is NULL");
+    return MASK_ERR_INVALID;
+  }
+  return query_impl(ix, q, max_out, level_cap, nullptr, nullptr, nullptr, out_ids, out_dist,
+                    nullptr, hip_stream, nullptr, radius, out_count);
 }
 
 mask_status mask_query_debug(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,

@@ -380,6 +380,10 @@ struct QueryArgs {
   float* out_dist;
   int32_t* sel;
   unsigned long long* rows;
+  // range search: radius per query (device) or null, and the number of data
+  // rows within it per query (device)
+  const float* radius;
+  int32_t* out_count;
 };
 
 void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);

@@ -19,6 +19,7 @@
 // ranks them.
 #include "internal.hpp"
 
+#include <cfloat>
 #include <cmath>
 
 namespace mask {
@@ -29,6 +30,7 @@ constexpr int kBlock = 256;
 struct SelShared {
   uint64_t kmin, kmax, thr;
   uint32_t cnt, n_out, bin, below, bin_cnt;
+  uint32_t in_range;  // range search: data rows within the radius
 };
 
 __device__ inline uint64_t wave_min_u64(uint64_t v) {
@@ -211,6 +213,17 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
   const int k = qa.k_arr ? min(max(qa.k_arr[qi], 1), qa.k) : qa.k;
   const int r = qa.r_arr ? min(max(qa.r_arr[qi], 1), qa.r) : qa.r;
   const int64_t obase = qa.out_off ? qa.out_off[qi] : qi * (int64_t)qa.k;
+  // Range search (Algorithm 3): keys are admitted at every level only when
+  // their squared distance is at most radius^2 (any id), and the per-level
+  // beam becomes a cap; otherwise every key is admitted.
+  const bool range = qa.radius != nullptr;
+  uint64_t thr0 = ~0ull;
+  if (range) {
+    const float rq = qa.radius[qi];
+    thr0 = (rq >= 0.f && rq <= FLT_MAX)
+               ? (((uint64_t)__float_as_uint(rq * rq) << 32) | 0xffffffffull)
+               : 0ull;
+  }
   float* s_q = reinterpret_cast<float*>(s_q4);
   int64_t qb = 0;
   int nq_e = 0;
@@ -295,9 +308,9 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
     // below the threshold and fill the buffer before the next selection.
     const uint32_t round = CAP - want;
     const uint32_t first = min(round, max(2 * want, 256u));
-    if (tid == 0) { sh.cnt = 0; sh.thr = ~0ull; }
+    if (tid == 0) { sh.cnt = 0; sh.thr = thr0; sh.in_range = 0; }
     __syncthreads();
-    uint64_t thr = ~0ull;
+    uint64_t thr = thr0;
     for (uint32_t base = 0; base < m;) {
       const uint32_t len = (base == 0) ? first : round;
       const uint32_t end = (m - base < len) ? m : base + len;
@@ -498,6 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
           for (int u = 0; u < U; ++u) {
             if (!val[u]) continue;
             const uint64_t key = ((uint64_t)__float_as_uint(acc[u]) << 32) | ids[u];
+            if (range && lev == 0 && key < thr0) atomicAdd(&sh.in_range, 1u);
             if (key < thr) {
               const uint32_t slot = atomicAdd(&sh.cnt, 1u);
               if (slot < (uint32_t)CAP) s_buf[slot] = key;  // rounds keep slot < CAP
@@ -604,6 +618,7 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
         qa.out_ids[obase + j] = id;
         qa.out_dist[obase + j] = dist;
       }
+      if (range && tid == 0) qa.out_count[qi] = (int32_t)sh.in_range;
     }
   }
   if (qa.rows && tid == 0) atomicAdd(qa.rows, rows_seen);
