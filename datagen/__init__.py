@@ -267,3 +267,29 @@ def request_stream(rate: float, duration: float, seed: int, pool_rows: int,
     rr = np.asarray(r_choices, dtype=np.int32)[g.integers(0, len(r_choices), size=m)]
     off = g.integers(0, max(1, pool_rows - max_queries), size=m).astype(np.int64)
     return RequestStream(t_arrival=t, n_queries=nq, k=kk, r=rr, pool_offset=off)
+
+
+# Standard deviation of each cloud by degree of overlap.  The eight means sit
+# on a circle of radius 10, so adjacent means are 2 * 10 * sin(pi / 8) = 7.65
+# apart: 15 sigma with no overlap, 3.8 sigma with moderate overlap and 1.9
+# sigma with severe overlap.
+CLOUD_SIGMA = {"none": 0.5, "moderate": 2.0, "severe": 4.0}
+
+
+@dataclasses.dataclass
+class Clouds:
+    X: np.ndarray       # (8 * npc, 2) float32, cloud-major order
+    labels: np.ndarray  # (8 * npc,) int32 cloud index
+
+
+def eight_clouds(npc: int, overlap: str, seed: int) -> Clouds:
+    """The synthetic benchmark of Section 4.2: eight isotropic Gaussian clouds
+    in the plane with npc points each; the paper does not give the means and
+    spreads, so they are the ones stated above."""
+    sigma = CLOUD_SIGMA[overlap]
+    g = _rng(seed)
+    ang = 2.0 * math.pi * np.arange(8) / 8.0
+    means = 10.0 * np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    X = np.repeat(means, npc, axis=0) + sigma * g.standard_normal((8 * npc, 2))
+    labels = np.repeat(np.arange(8, dtype=np.int32), npc)
+    return Clouds(X=X.astype(np.float32), labels=labels)

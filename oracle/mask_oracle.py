@@ -25,6 +25,12 @@ What it computes, by paper passage:
                          Section 3.3 ("Searching and data insertion"),
                          generalised from the greedy choice to a beam of the
                          r nearest prototypes at every level.
+* ``point_query_one``  - the point query of Section 3.3: greedy descent,
+                         then a full scan of the leaf for the nearest point
+                         and for an exact match.
+* ``relocate``         - one relocation step (Sections 4.1-4.2, Table 1):
+                         points not found join the group of the leaf their
+                         point query reached, before the index is rebuilt.
 * ``range_query_one``  - the range search of Algorithm 3: the prototypes
                          within the radius at every level, then the points
                          within the radius under them.
@@ -194,13 +200,19 @@ def lloyd_step(points: np.ndarray, centroids: np.ndarray, metric: str = "l2"):
 def lloyd(points: np.ndarray, k: int, iters: int, metric: str = "l2",
           init: Optional[np.ndarray] = None) -> LloydResult:
     """kmeans(nCentroids, points) of Algorithm 1 as Lloyd's algorithm: the
-    initial prototypes are the first k points of the group, then ``iters``
+    initial prototypes are the first k points of the group (cyclically when
+    the group holds fewer than k), then ``iters``
     rounds of (assign, update), then a final assignment so the labels belong
     to the returned prototypes."""
     points = np.asarray(points, dtype=np.float64)
-    if k < 1 or k > points.shape[0]:
-        raise ValueError("need 1 <= k <= group size")
-    C = np.array(points[:k] if init is None else init, dtype=np.float64, copy=True)
+    m = points.shape[0]
+    if k < 1 or m < 1:
+        raise ValueError("need k >= 1 and a non-empty group")
+    # A group smaller than k (relocation can leave one) starts from its
+    # members taken cyclically; the repeated copies tie with the first copy,
+    # lose the tie (lowest index wins) and so stay empty with their value.
+    first = points[np.arange(k) % m]
+    C = np.array(first if init is None else init, dtype=np.float64, copy=True)
     log = np.empty(iters, dtype=np.float64)
     for t in range(iters):
         _, C, log[t] = lloyd_step(points, C, metric)
@@ -251,11 +263,13 @@ class OracleIndex:
 
 
 def build(X: np.ndarray, levels: Sequence[Tuple[int, int]], iters: int, seed: int,
-          metric: str = "l2", perm: Optional[np.ndarray] = None) -> OracleIndex:
+          metric: str = "l2", perm: Optional[np.ndarray] = None,
+          group_off: Optional[np.ndarray] = None) -> OracleIndex:
     """Algorithm 1 with explicit level sizes [(n_chunks, k)] bottom-up.
 
     Level 0 (the data) is permuted by ``permutation(seed, n)`` (or the given
-    ``perm``) and split into n_chunks contiguous groups; every upper level
+    ``perm``) and split into n_chunks contiguous groups (or at the given
+    ``group_off`` boundaries, as a relocation leaves them); every upper level
     splits the previous level's prototypes, in chunk-major id order, the same
     way without shuffling.  Each group runs ``lloyd`` independently."""
     data = np.asarray(X, dtype=np.float64)
@@ -264,8 +278,14 @@ def build(X: np.ndarray, levels: Sequence[Tuple[int, int]], iters: int, seed: in
     items = data[pi]
     item_ids = pi  # original id of each item in the current order
     protos, parents, inertia = [], [], []
-    for (n_chunks, k) in levels:
-        off = chunk_offsets(items.shape[0], n_chunks)
+    for lev, (n_chunks, k) in enumerate(levels):
+        if lev == 0 and group_off is not None:
+            off = np.asarray(group_off, dtype=np.int64)
+            if off.shape[0] != n_chunks + 1 or off[0] != 0 or off[-1] != n or \
+                    np.any(np.diff(off) < 1):
+                raise ValueError("group_off must rise strictly from 0 to n")
+        else:
+            off = chunk_offsets(items.shape[0], n_chunks)
         P = np.empty((n_chunks * k, data.shape[1]), dtype=np.float64)
         par = np.empty(items.shape[0], dtype=np.int64)
         logs = np.empty((n_chunks, iters), dtype=np.float64)
@@ -363,6 +383,94 @@ def query(index: OracleIndex, Q: np.ndarray, k: int, r: int):
     for i in range(Q.shape[0]):
         ids[i], dist[i] = query_one(index, Q[i], k, r)
     return ids, dist
+
+
+# --------------------------------------------------------------------------
+# Point query (Section 3.3) and relocation (Sections 4.1 and 4.2, Table 1)
+# --------------------------------------------------------------------------
+
+
+def point_query_one(index: OracleIndex, q: np.ndarray):
+    """Point query of Section 3.3 for one query q.  At the top level the
+    prototype nearest to q is chosen; at every level below, the nearest among
+    the children of the prototype chosen above; the chosen level-1 prototype
+    is the leaf.  A full scan of the data points of the leaf gives the answer
+    (the nearest of them, ties to the lower id) and the perfect match sought
+    (the lowest id of a point equal to q coordinate by coordinate, else -1).
+
+    Returns (answer id, reported distance, leaf id, match id); answer and
+    leaf are -1 (distance inf) when the leaf has no points."""
+    metric = index.metric
+    L = index.n_levels
+    q = np.asarray(q, dtype=np.float64)
+    chosen = -1
+    for l in range(L - 1, -1, -1):
+        if l == L - 1:
+            cand = np.arange(index.protos[l].shape[0], dtype=np.int64)
+        else:
+            cand = index.children(l + 1)[chosen]
+        if cand.size == 0:
+            return -1, np.inf, -1, -1
+        d = pairwise(q[None, :], index.protos[l][cand], metric)[0]
+        chosen = int(cand[np.lexsort((cand, d))[0]])
+    leaf = chosen
+    pts = index.children(0)[leaf]
+    if pts.size == 0:
+        return -1, np.inf, leaf, -1
+    d = pairwise(q[None, :], index.data[pts], metric)[0]
+    best = int(np.lexsort((pts, d))[0])
+    equal = pts[np.all(index.data[pts] == q[None, :], axis=1)]
+    match = int(equal.min()) if equal.size else -1
+    return int(pts[best]), float(report_distance(d[best:best + 1], metric)[0]), leaf, match
+
+
+def exhaustive_point_search(index: OracleIndex):
+    """The evaluation of Section 4.1: a point query for every data point.
+    Returns arrays (answer, leaf, match) in data row order."""
+    n = index.data.shape[0]
+    ans = np.empty(n, dtype=np.int64)
+    leaf = np.empty(n, dtype=np.int64)
+    match = np.empty(n, dtype=np.int64)
+    for i in range(n):
+        ans[i], _, leaf[i], match[i] = point_query_one(index, index.data[i])
+    return ans, leaf, match
+
+
+def relocate(perm: np.ndarray, group_off: np.ndarray, k0: int, leaf: np.ndarray,
+             wrong: np.ndarray):
+    """One relocation step (Section 4.1, iterated in Table 1): a data point
+    that its own point query did not find correctly (``wrong``) joins the
+    level-0 group that produced the leaf the query reached (group
+    leaf // k0, the level-1 prototypes being chunk-major); the index is then
+    built again on the new groups.
+
+    ``perm`` is the level-0 order the index was built with (original ids)
+    and ``group_off`` its group boundaries in that order.  Readings: a group
+    keeps the members that stay, in their old order, followed by the points
+    that join it, in their old order; a group left empty is dropped and the
+    rest keep their relative order; a point whose query reached no leaf (an
+    empty prototype on its path, leaf -1) stays.  Returns the new
+    (perm, group_off)."""
+    perm = np.asarray(perm, dtype=np.int64)
+    group_off = np.asarray(group_off, dtype=np.int64)
+    n, C = perm.shape[0], group_off.shape[0] - 1
+    stay = [[] for _ in range(C)]
+    join = [[] for _ in range(C)]
+    for g in range(C):
+        for j in range(group_off[g], group_off[g + 1]):
+            i = int(perm[j])
+            target = int(leaf[i]) // k0 if wrong[i] and leaf[i] >= 0 else g
+            if target >= C:
+                raise ValueError("leaf outside level 1")
+            (stay if target == g else join)[target].append(i)
+    order, off = [], [0]
+    for g in range(C):
+        members = stay[g] + join[g]
+        if members:
+            order.extend(members)
+            off.append(off[-1] + len(members))
+    assert len(order) == n
+    return np.array(order, dtype=np.int64), np.array(off, dtype=np.int64)
 
 
 # --------------------------------------------------------------------------

@@ -113,3 +113,23 @@ def test_range_strict_boundary_drops_the_exact_match(monkeypatch):
         return orig_pairwise(A, B, metric, block) + 1e-300
     monkeypatch.setattr(mo, "pairwise", bad)
     assert _fails(pins.test_range_search_on_one_to_one_index_is_exact)
+
+
+def test_point_query_on_the_wrong_level_is_caught(monkeypatch):
+    # children taken one level too low on the way down
+    orig = mo.OracleIndex.children
+
+    def bad(self, level):
+        return orig(self, max(level - 1, 0))
+    monkeypatch.setattr(mo.OracleIndex, "children", bad)
+    with pytest.raises((AssertionError, IndexError)):
+        pins.test_point_query_is_the_greedy_descent_then_a_leaf_scan()
+
+
+def test_point_query_answering_with_the_farthest_point_is_caught(monkeypatch):
+    orig = mo.pairwise
+
+    def bad(A, B, metric="l2", block=256):
+        return -orig(A, B, metric, block)
+    monkeypatch.setattr(mo, "pairwise", bad)
+    assert _fails(pins.test_point_query_on_one_to_one_level_finds_every_point)

@@ -10,6 +10,7 @@ import pytest
 from scipy.cluster.vq import kmeans2
 from scipy.spatial import cKDTree
 
+import datagen
 from oracle import compare as oc
 from oracle import mask_oracle as mo
 
@@ -404,3 +405,105 @@ def test_range_search_is_monotone_and_capped():
     _, _, tr = mo.query_one(ix, q, 3, 1, trace=True)
     leaf = set(ix.children(0)[tr.selected[-1][0]].tolist())
     assert set(ids1[ids1 >= 0].tolist()) == leaf
+
+
+# -------------------------------------------- point query and relocation
+
+def test_lloyd_group_smaller_than_k_keeps_every_member():
+    # a group of 3 points with k = 5: the members are the first three
+    # prototypes; copies of the first two follow, lose every tie and stay
+    P = np.array([[0.0, 1.0], [2.0, -1.0], [5.0, 5.0]])
+    res = mo.lloyd(P, 5, 4)
+    np.testing.assert_array_equal(res.centroids, P[[0, 1, 2, 0, 1]])
+    np.testing.assert_array_equal(res.labels, [0, 1, 2])
+    np.testing.assert_array_equal(res.inertia, np.zeros(4))
+
+
+def test_point_query_on_one_to_one_level_finds_every_point():
+    # one level with k = group size: the prototypes are the points, so the
+    # nearest prototype of a data point is its own and the scan finds it
+    g = np.random.default_rng(21)
+    X = g.standard_normal((60, 2)).astype(np.float32)
+    ix = mo.build(X, [(3, 20)], 3, seed=2)
+    ans, leaf, match = mo.exhaustive_point_search(ix)
+    assert np.array_equal(ans, np.arange(60))
+    assert np.array_equal(match, np.arange(60))
+    assert np.array_equal(leaf, ix.parents[0])
+
+
+def test_point_query_is_the_greedy_descent_then_a_leaf_scan():
+    X, ix = _small_index()
+    g = np.random.default_rng(22)
+    Q = np.concatenate([X[:25].astype(np.float64), g.standard_normal((15, X.shape[1]))])
+    n_match = 0
+    for q in Q:
+        a, d, leaf, match = mo.point_query_one(ix, q)
+        ids, dist, tr = mo.query_one(ix, q, 1, 1, trace=True)
+        assert leaf == tr.selected[-1][0]
+        assert a == ids[0] and d == dist[0]
+        pts = [i for i in range(X.shape[0]) if ix.parents[0][i] == leaf]
+        eq = [i for i in pts if all(float(X[i, c]) == q[c] for c in range(X.shape[1]))]
+        assert match == (min(eq) if eq else -1)
+        n_match += match >= 0
+    assert n_match >= 1  # some data rows are found, so the match branch is exercised
+
+
+def _cloud_errors(npc, overlap):
+    c = datagen.eight_clouds(npc, overlap, seed=42)
+    ix = mo.build(c.X, mo.plan_levels(8 * npc, 16, 8), 30, seed=1)
+    ans, _, match = mo.exhaustive_point_search(ix)
+    wrong = (ans < 0) | (c.labels[np.maximum(ans, 0)] != c.labels)
+    return wrong.mean(), (match < 0).mean()
+
+
+def test_cloud_benchmark_error_rates():
+    # Section 4.2 with lengthGroup 16 and nCentroids 8 (1,600 points, seven
+    # centroid levels): with well separated clouds nearly every point query
+    # answers with a point of the query's own cloud (the no-overlap table
+    # gives at most 0.11 %), and more overlap gives more errors.  The answer
+    # is rarely the query itself: an exact-match reading of the error rate
+    # would be far from the paper's figures.
+    none, none_miss = _cloud_errors(200, "none")
+    moderate, _ = _cloud_errors(200, "moderate")
+    severe, _ = _cloud_errors(200, "severe")
+    assert none <= 0.002
+    assert none < moderate < severe
+    assert none_miss > 0.5
+
+
+def test_relocation_worked_example():
+    # groups in the old order: g0 = [4, 2], g1 = [0, 5], g2 = [1, 3]; k0 = 2
+    # so leaf p belongs to group p // 2.  Point 0 (wrong, leaf 1) joins g0;
+    # point 2 (wrong, leaf 5) joins g2; point 5 (wrong, leaf 2) is already in
+    # g1; point 3 (wrong, no leaf) stays.
+    perm = np.array([4, 2, 0, 5, 1, 3])
+    off = np.array([0, 2, 4, 6])
+    leaf = np.array([1, 0, 5, -1, 0, 2])
+    wrong = np.array([1, 0, 1, 1, 0, 1], dtype=bool)
+    p2, o2 = mo.relocate(perm, off, 2, leaf, wrong)
+    assert p2.tolist() == [4, 0, 5, 1, 3, 2] and o2.tolist() == [0, 2, 3, 6]
+    # emptying g1 drops it
+    leaf = np.array([0, 0, 0, 0, 0, 4])
+    wrong = np.array([1, 0, 0, 0, 0, 1], dtype=bool)
+    p3, o3 = mo.relocate(perm, off, 2, leaf, wrong)
+    assert p3.tolist() == [4, 2, 0, 1, 3, 5] and o3.tolist() == [0, 3, 6]
+    # nothing wrong: nothing moves
+    p4, o4 = mo.relocate(perm, off, 2, leaf, np.zeros(6, dtype=bool))
+    assert p4.tolist() == perm.tolist() and o4.tolist() == off.tolist()
+
+
+def test_build_on_given_groups():
+    # explicit group boundaries replace the split, including groups smaller
+    # than k; the groups' prototypes are their own k-means
+    g = np.random.default_rng(23)
+    X = g.standard_normal((40, 2)).astype(np.float32)
+    perm = g.permutation(40)
+    off = np.array([0, 3, 20, 22, 40])
+    ix = mo.build(X, [(4, 4), (2, 4)], 5, seed=0, perm=perm, group_off=off)
+    for c in range(4):
+        members = perm[off[c]:off[c + 1]]
+        res = mo.lloyd(X[members], 4, 5)
+        np.testing.assert_array_equal(ix.protos[0][4 * c:4 * c + 4], res.centroids)
+        assert np.array_equal(ix.parents[0][members], 4 * c + res.labels)
+    with pytest.raises(ValueError):
+        mo.build(X, [(4, 4)], 5, seed=0, perm=perm, group_off=np.array([0, 3, 3, 22, 40]))
