@@ -114,6 +114,9 @@ typedef struct {
   int32_t rerank_factor; /* precision forms: FP32 re-rank of rerank_factor*k
                             candidates; <= 0: 4 for BF16, 48 for FP8 */
   const int32_t* perm;   /* optional device int32[n]: level-0 order; NULL = from seed */
+  const int64_t* group_off; /* optional host int64[levels[0].n_chunks + 1]: level-0 group
+                               boundaries in that order, rising strictly from 0 to n (as
+                               mask_relocate writes them); NULL = split (dense data only) */
 } mask_build_params;
 
 typedef struct mask_index mask_index;
@@ -145,9 +148,10 @@ mask_status mask_plan_levels(int64_t n, int32_t length_group, int32_t n_centroid
  * items of the next level are those prototypes with their zeros dropped).
  * Level 0 is permuted by the argsort of the SplitMix64
  * outputs h(seed, i) (or by p->perm) and split into levels[0].n_chunks
- * groups; each group runs lloyd_iters Lloyd iterations starting from its
- * first k members, then a final assignment.  Each chunk must hold at least k
- * items.  The index copies what it needs: data may be freed after the call.
+ * groups (or cut at p->group_off); each group runs lloyd_iters Lloyd
+ * iterations starting from its first k members (taken cyclically when the
+ * group holds fewer than k: the repeated copies lose every tie and stay
+ * empty), then a final assignment.  Every chunk must hold at least one item.  The index copies what it needs: data may be freed after the call.
  * Work runs on hip_stream (NULL = the null stream); the call returns after it
  * completes.  On success *out owns device memory until mask_free. */
 mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
@@ -210,6 +214,37 @@ mask_status mask_query_debug(const mask_index* ix, const mask_matrix* q, int32_t
 mask_status mask_query_range(const mask_index* ix, const mask_matrix* q, const float* radius,
                              int32_t max_out, int32_t level_cap, int32_t* out_ids,
                              float* out_dist, int32_t* out_count, void* hip_stream);
+
+/* Point query (Section 3.3): the nearest prototype at the top level, then
+ * at each level the nearest child of the one chosen above (r = 1, ranking
+ * key (distance, id)); a full scan of the data rows under the level-1
+ * prototype reached (the leaf) gives the answer.  Per query i (device
+ * arrays of q->n): out_ids[i] / out_dist[i] = the nearest row of the leaf
+ * (as mask_query with k = r = 1; -1 / +inf when the leaf is empty or an
+ * empty prototype was chosen above it), out_leaf[i] = the leaf's
+ * chunk-major id (-1 when none was reached), out_match[i] = the lowest id of
+ * a row of the leaf equal to the query in every coordinate (float
+ * comparison), else -1.  Dense indexes, any form.  Asynchronous; allocates
+ * nothing. */
+mask_status mask_point_query(const mask_index* ix, const mask_matrix* q, int32_t* out_ids,
+                             float* out_dist, int32_t* out_leaf, int32_t* out_match,
+                             void* hip_stream);
+
+/* One relocation step (Sections 4.1-4.2, the relocation table): every data
+ * row i with wrong[i] != 0 whose point query reached leaf[i] >= 0 joins the
+ * level-0 group that produced that leaf (leaf[i] / levels[0].k); the others
+ * stay.  leaf and wrong: device int32[n] in data row order (mask_point_query
+ * over all data rows gives leaf; the caller decides what is wrong).  Each
+ * group keeps its staying rows in their old order followed by the rows that
+ * join it in their old order; groups left empty are dropped.  Writes the
+ * new level-0 order to perm_out (device int32[n]) and its group boundaries
+ * to group_off_out (host, *n_groups + 1 entries; cap >= levels[0].n_chunks
+ * + 1), ready for mask_build's perm and group_off.  Needs an index built by
+ * mask_build from dense data (MASK_ERR_UNSUPPORTED otherwise);
+ * MASK_ERR_INVALID when a leaf lies outside level 1.  Synchronous. */
+mask_status mask_relocate(const mask_index* ix, const int32_t* leaf, const int32_t* wrong,
+                          int32_t* perm_out, int64_t* group_off_out, int32_t cap,
+                          int32_t* n_groups, const mask_allocator* a, void* hip_stream);
 
 /* Releases the index (NULL is allowed).  Must not race with queries. */
 mask_status mask_free(mask_index* ix);

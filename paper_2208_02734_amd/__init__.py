@@ -48,7 +48,8 @@ class mask_build_params(ctypes.Structure):
     _fields_ = [("metric", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("n_levels", ctypes.c_int32), ("levels", ctypes.POINTER(mask_level)),
                 ("lloyd_iters", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("rerank_factor", ctypes.c_int32), ("perm", ctypes.c_void_p)]
+                ("rerank_factor", ctypes.c_int32), ("perm", ctypes.c_void_p),
+                ("group_off", ctypes.POINTER(ctypes.c_int64))]
 
 
 class mask_info(ctypes.Structure):
@@ -83,7 +84,7 @@ class mask_server_stats(ctypes.Structure):
 _lib = None
 
 EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_beams", "mask_query_ragged",
-            "mask_query_range",
+            "mask_query_range", "mask_point_query", "mask_relocate",
             "mask_query_debug", "mask_free",
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
             "mask_last_error", "mask_timing_enable", "mask_timing_report", "mask_clock",
@@ -108,6 +109,8 @@ def lib() -> ctypes.CDLL:
     L.mask_query_ragged.argtypes = [VP, P(mask_matrix), VP, VP, VP, I32, I32, VP, VP, VP]
     L.mask_query_beams.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP]
     L.mask_query_range.argtypes = [VP, P(mask_matrix), VP, I32, I32, VP, VP, VP, VP]
+    L.mask_point_query.argtypes = [VP, P(mask_matrix), VP, VP, VP, VP, VP]
+    L.mask_relocate.argtypes = [VP, VP, VP, VP, P(I64), I32, P(I32), P(mask_allocator), VP]
     L.mask_free.argtypes = [VP]
     L.mask_index_info.argtypes = [VP, P(mask_info)]
     L.mask_export_level.argtypes = [VP, I32, VP, VP]
@@ -300,7 +303,7 @@ def mask_plan_levels(n: int, length_group: int, n_centroids: int) -> List[Tuple[
     return [(out[i].n_chunks, out[i].k) for i in range(cnt.value)]
 
 
-def _params(levels, iters, seed, metric, precision, rerank_factor, perm):
+def _params(levels, iters, seed, metric, precision, rerank_factor, perm, group_off=None):
     lv = _levels_array(levels)
     p = mask_build_params()
     p.metric = METRICS[metric]
@@ -311,19 +314,26 @@ def _params(levels, iters, seed, metric, precision, rerank_factor, perm):
     p.seed = seed & 0xFFFFFFFFFFFFFFFF
     p.rerank_factor = rerank_factor
     p.perm = perm.data_ptr() if perm is not None else None
+    if group_off is not None:
+        off = np.ascontiguousarray(group_off, dtype=np.int64)
+        if off.shape != (levels[0][0] + 1,):
+            raise MaskError(1, "group_off must hold levels[0] n_chunks + 1 entries")
+        p._group_off = off  # kept alive with the struct
+        p.group_off = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     return p, lv
 
 
 def mask_build(data, levels: Sequence[Tuple[int, int]], iters: int = 30, seed: int = 0,
                metric: str = "l2", precision: str = "fp32", perm=None, rerank_factor: int = 0,
-               stream=None, torch_allocator: bool = True) -> Index:
+               stream=None, torch_allocator: bool = True, group_off=None) -> Index:
     """Algorithm 1 on a device tensor (n x dim float32) or a CsrTensor;
-    returns the index."""
+    returns the index.  perm (int32 CUDA tensor) and group_off (host int64,
+    levels[0] n_chunks + 1 entries) give the level-0 order and groups."""
     torch = _torch()
     m = _matrix(data)
     if perm is not None and (perm.dtype != torch.int32 or not perm.is_cuda):
         raise MaskError(1, "perm must be an int32 CUDA tensor")
-    p, lv = _params(levels, iters, seed, metric, precision, rerank_factor, perm)
+    p, lv = _params(levels, iters, seed, metric, precision, rerank_factor, perm, group_off)
     alloc = _TorchAllocator(data.device.index or 0) if torch_allocator else None
     h = ctypes.c_void_p()
     _check(lib().mask_build(ctypes.byref(m), ctypes.byref(p),
@@ -405,6 +415,46 @@ def mask_query_range(index: Index, queries, radius, max_out: int, level_cap: int
                                   int(level_cap), ids.data_ptr(), dist.data_ptr(),
                                   count.data_ptr(), _stream_handle(stream)))
     return ids, dist, count
+
+
+def mask_point_query(index: Index, queries, stream=None):
+    """Point query (Section 3.3) for every row of ``queries``; returns
+    (ids, dist, leaf, match) tensors of length nq."""
+    torch = _torch()
+    m = _matrix(queries)
+    nq = queries.shape[0]
+    dev = queries.device
+    ids = torch.empty(nq, dtype=torch.int32, device=dev)
+    dist = torch.empty(nq, dtype=torch.float32, device=dev)
+    leaf = torch.empty(nq, dtype=torch.int32, device=dev)
+    match = torch.empty(nq, dtype=torch.int32, device=dev)
+    _check(lib().mask_point_query(index.handle, ctypes.byref(m), ids.data_ptr(),
+                                  dist.data_ptr(), leaf.data_ptr(), match.data_ptr(),
+                                  _stream_handle(stream)))
+    return ids, dist, leaf, match
+
+
+def mask_relocate(index: Index, leaf, wrong, stream=None):
+    """One relocation step; leaf and wrong are int32 CUDA tensors of length
+    n in data row order.  Returns (perm int32 CUDA tensor, group_off numpy
+    int64) for the rebuild."""
+    torch = _torch()
+    info = index.info()
+    n = info["n"]
+    if leaf.dtype != torch.int32 or wrong.dtype != torch.int32 or leaf.numel() != n \
+            or wrong.numel() != n:
+        raise MaskError(1, "leaf and wrong must be int32 tensors of length n")
+    leaf, wrong = leaf.contiguous(), wrong.contiguous()
+    perm = torch.empty(n, dtype=torch.int32, device=leaf.device)
+    cap = n + 1
+    off = np.zeros(cap, dtype=np.int64)
+    ng = ctypes.c_int32()
+    alloc = _TorchAllocator(leaf.device.index or 0)
+    _check(lib().mask_relocate(index.handle, leaf.data_ptr(), wrong.data_ptr(), perm.data_ptr(),
+                               off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), cap,
+                               ctypes.byref(ng), ctypes.byref(alloc.struct),
+                               _stream_handle(stream)))
+    return perm, off[:ng.value + 1].copy()
 
 
 def mask_free(index: Index):

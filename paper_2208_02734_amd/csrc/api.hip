@@ -80,11 +80,14 @@ std::vector<int64_t> split_offsets(int64_t n, int n_chunks) {
   return off;
 }
 
-void make_plan(ChunkPlan& plan, int64_t n_items, int n_chunks, int k, Arena& a, hipStream_t s) {
+// offs: explicit group boundaries (n_chunks + 1, rising from 0 to n_items)
+// or null for split()
+void make_plan(ChunkPlan& plan, int64_t n_items, int n_chunks, int k, Arena& a, hipStream_t s,
+               const std::vector<int64_t>* offs = nullptr) {
   plan.n_chunks = n_chunks;
   plan.k = k;
   plan.n_items = n_items;
-  plan.off = split_offsets(n_items, n_chunks);
+  plan.off = offs ? *offs : split_offsets(n_items, n_chunks);
   plan.max_chunk = 0;
   for (int c = 0; c < n_chunks; ++c)
     plan.max_chunk = std::max(plan.max_chunk, plan.off[c + 1] - plan.off[c]);
@@ -137,6 +140,17 @@ void validate_csr(const mask_matrix* m, const char* what, Arena& scratch, hipStr
                          "be strictly increasing and below dim");
 }
 
+// A caller's level-0 order must name data rows only (synchronises the
+// stream); it is then used as a gather index.
+void check_perm(const uint32_t* perm, int64_t n, Arena& scratch, hipStream_t s) {
+  uint32_t* flag = scratch.alloc<uint32_t>(1);
+  check_range_i32(reinterpret_cast<const int32_t*>(perm), n, n, flag, s);
+  uint32_t h = 0;
+  MASK_HIP(hipMemcpyAsync(&h, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  MASK_HIP(hipStreamSynchronize(s));
+  MASK_CHECK(h == 0, "perm holds an id outside [0, n)");
+}
+
 void check_levels(int64_t n, int n_levels, const mask_level* levels, std::vector<int64_t>& sizes) {
   MASK_CHECK(n_levels >= 1 && n_levels <= kMaxLevels, "n_levels must be in [1, 16]");
   MASK_CHECK(levels != nullptr, "levels is NULL");
@@ -146,7 +160,7 @@ void check_levels(int64_t n, int n_levels, const mask_level* levels, std::vector
     const int64_t items = sizes[l];
     const int C = levels[l].n_chunks, k = levels[l].k;
     MASK_CHECK(C >= 1 && k >= 1, "level with n_chunks < 1 or k < 1");
-    MASK_CHECK(items / C >= k, "a chunk holds fewer items than its k");
+    MASK_CHECK(items >= C, "a level with more chunks than items");
     sizes[l + 1] = (int64_t)C * k;
     MASK_CHECK(sizes[l + 1] < ((int64_t)1 << 31), "level too large");
   }
@@ -271,9 +285,10 @@ struct BuildState {
 // (chunk-major) and the final labels.  inertia_log: device [iters * C] or null.
 void run_level(const float* items, int64_t n_items, int ld, int dim, int C, int k, int iters,
                int metric, int precision, const float* init, float* protos, int32_t* labels,
-               double* inertia_log, Arena& scratch, hipStream_t s, int64_t* refined) {
+               double* inertia_log, Arena& scratch, hipStream_t s, int64_t* refined,
+               const std::vector<int64_t>* offs = nullptr) {
   ChunkPlan plan;
-  make_plan(plan, n_items, C, k, scratch, s);
+  make_plan(plan, n_items, C, k, scratch, s, offs);
   KmeansWork w;
   kmeans_alloc(w, n_items, C, k, ld, scratch);
   if (precision == MASK_BF16 && metric == MASK_L2) {
@@ -331,6 +346,7 @@ void build_sparse(mask_index& ix, const mask_matrix* data, const mask_build_para
   uint32_t* perm = scratch.alloc<uint32_t>(n);
   if (p->perm) {
     MASK_HIP(hipMemcpyAsync(perm, p->perm, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    check_perm(perm, n, scratch, s);
   } else {
     uint64_t* keys = scratch.alloc<uint64_t>(n);
     SortWork sw;
@@ -394,7 +410,7 @@ mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, in
                        const int32_t* k_arr, const int32_t* r_arr, const int64_t* out_off,
                        int32_t* out_ids, float* out_dist, int32_t* sel, void* hip_stream,
                        const int32_t* r_levels = nullptr, const float* radius = nullptr,
-                       int32_t* out_count = nullptr) {
+                       int32_t* out_count = nullptr, int32_t* out_leaf = nullptr) {
   try {
     MASK_CHECK(ix != nullptr, "index is NULL");
     if (ix->sparse) check_csr(q, "queries (CSR index)");
@@ -425,6 +441,7 @@ mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, in
     qa.out_dist = out_dist;
     qa.sel = sel;
     qa.rows = timing_row_counter();
+    qa.out_leaf = out_leaf;
     if (radius) {
       MASK_CHECK(out_count != nullptr, "out_count is NULL");
       if (ix->precision != MASK_FP32 || ix->metric != MASK_L2)
@@ -551,6 +568,16 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
       throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};
     if (p->precision != MASK_FP32 && p->metric != MASK_L2)
       throw Error{MASK_ERR_UNSUPPORTED, "BF16 / FP8 form of L1"};
+    std::vector<int64_t> goff0;
+    if (p->group_off) {
+      if (sparse) throw Error{MASK_ERR_UNSUPPORTED, "CSR data: group_off"};
+      const int C0 = p->levels[0].n_chunks;
+      goff0.assign(p->group_off, p->group_off + C0 + 1);
+      MASK_CHECK(goff0[0] == 0 && goff0[C0] == data->n,
+                 "group_off must start at 0 and end at n");
+      for (int c = 0; c < C0; ++c)
+        MASK_CHECK(goff0[c + 1] > goff0[c], "group_off must rise strictly (no empty group)");
+    }
 
     auto ix = std::make_unique<mask_index>(a, s);
     const int L = p->n_levels;
@@ -578,6 +605,7 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
     uint32_t* perm = scratch.alloc<uint32_t>(n);
     if (p->perm) {
       MASK_HIP(hipMemcpyAsync(perm, p->perm, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+      check_perm(perm, n, scratch, s);
     } else {
       uint64_t* keys = scratch.alloc<uint64_t>(n);
       SortWork sw;
@@ -587,6 +615,11 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
     }
     float* items0 = scratch.alloc<float>(n * ld);
     gather_rows(data->x, ld_of(data), perm, n, data->dim, items0, ld, s);
+    // kept for relocation: the level-0 order and groups of this build
+    if (goff0.empty()) goff0 = split_offsets(n, p->levels[0].n_chunks);
+    ix->group_off0 = goff0;
+    ix->perm0 = ix->mem.alloc<int32_t>(n);
+    MASK_HIP(hipMemcpyAsync(ix->perm0, perm, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
 
     BuildState st;
     st.labels.assign(L + 1, nullptr);
@@ -600,7 +633,7 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
       Arena level_scratch(a, s);
       run_level(items, n_items, ld, data->dim, C, k, p->lloyd_iters, p->metric, p->precision,
                 nullptr, st.protos_cm[l], st.labels[l], nullptr, level_scratch, s,
-                l == 1 ? &ix->refined_last : nullptr);
+                l == 1 ? &ix->refined_last : nullptr, l == 1 ? &goff0 : nullptr);
       MASK_HIP(hipStreamSynchronize(s));
     }
     finalize_layout(*ix, st.labels, st.protos_cm, items0, perm, scratch, s);
@@ -658,6 +691,71 @@ mask_status mask_query_range(const mask_index* ix, const mask_matrix* q, const f
   }
   return query_impl(ix, q, max_out, level_cap, nullptr, nullptr, nullptr, out_ids, out_dist,
                     nullptr, hip_stream, nullptr, radius, out_count);
+}
+
+mask_status mask_point_query(const mask_index* ix, const mask_matrix* q, int32_t* out_ids,
+                             float* out_dist, int32_t* out_leaf, int32_t* out_match,
+                             void* hip_stream) {
+  try {
+    MASK_CHECK(ix != nullptr, "index is NULL");
+    if (ix->sparse) throw Error{MASK_ERR_UNSUPPORTED, "point query on a CSR index"};
+    MASK_CHECK(q != nullptr, "queries is NULL");
+    MASK_CHECK(q->n == 0 || (out_leaf && out_match), "output pointer is NULL");
+  } catch (const Error& e) {
+    return fail(e);
+  }
+  const mask_status st = query_impl(ix, q, 1, 1, nullptr, nullptr, nullptr, out_ids, out_dist,
+                                    nullptr, hip_stream, nullptr, nullptr, nullptr, out_leaf);
+  if (st != MASK_OK || q->n == 0) return st;
+  try {
+    point_match(descent_args(*ix), q->x, ld_of(q), q->n, out_leaf, out_match,
+                (hipStream_t)hip_stream);
+    return MASK_OK;
+  } catch (const Error& e) {
+    return fail(e);
+  }
+}
+
+mask_status mask_relocate(const mask_index* ix, const int32_t* leaf, const int32_t* wrong,
+                          int32_t* perm_out, int64_t* group_off_out, int32_t cap,
+                          int32_t* n_groups, const mask_allocator* a, void* hip_stream) {
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    MASK_CHECK(ix != nullptr, "index is NULL");
+    if (!ix->perm0)
+      throw Error{MASK_ERR_UNSUPPORTED, "index without a level-0 order (imported or CSR)"};
+    MASK_CHECK(leaf && wrong && perm_out && group_off_out && n_groups, "NULL argument");
+    const int C = ix->levels[0].n_chunks, k0 = ix->levels[0].k;
+    MASK_CHECK(cap >= C + 1, "group_off_out holds fewer than n_chunks + 1 entries");
+    const int64_t n = ix->n;
+    Arena scratch(a, s);
+    int64_t* goff = scratch.alloc<int64_t>(C + 1);
+    MASK_HIP(hipMemcpyAsync(goff, ix->group_off0.data(), (C + 1) * sizeof(int64_t),
+                            hipMemcpyHostToDevice, s));
+    uint32_t* off2 = scratch.alloc<uint32_t>(2 * (int64_t)C + 2);
+    uint32_t* bad = off2 + 2 * (int64_t)C + 1;
+    relocate_order(ix->perm0, goff, C, n, k0, leaf, wrong, perm_out, off2, bad, scratch, s);
+    std::vector<uint32_t> h(2 * (size_t)C + 2);
+    MASK_HIP(hipMemcpyAsync(h.data(), off2, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                            s));
+    MASK_HIP(hipStreamSynchronize(s));
+    MASK_CHECK(h[2 * (size_t)C + 1] == 0, "a leaf lies outside level 1");
+    int count = 0;
+    group_off_out[0] = 0;
+    for (int g = 0; g < C; ++g) {
+      const uint32_t end = h[2 * (size_t)g + 2];
+      if (end > h[2 * (size_t)g]) group_off_out[++count] = end;
+    }
+    *n_groups = count;
+    return MASK_OK;
+  } catch (const Error& e) {
+    if (e.status != MASK_ERR_INVALID && e.status != MASK_ERR_UNSUPPORTED)
+      (void)hipStreamSynchronize(s);
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamSynchronize(s);
+    return fail(Error{MASK_ERR_NOMEM, "host allocation failed"});
+  }
 }
 
 mask_status mask_query_debug(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,
@@ -824,7 +922,7 @@ mask_status mask_kmeans(const mask_matrix* items, int32_t n_chunks, int32_t k, i
       check_csr(items, "items");
       MASK_CHECK(items->n >= 1 && items->n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
       MASK_CHECK(n_chunks >= 1 && k >= 1 && iters >= 0, "bad n_chunks, k or iters");
-      MASK_CHECK(items->n / n_chunks >= k, "a chunk holds fewer items than k");
+      MASK_CHECK(items->n >= n_chunks, "more chunks than items");
       MASK_CHECK(centroids && labels, "output pointer is NULL");
       if (metric != MASK_L2) throw Error{MASK_ERR_UNSUPPORTED, "CSR items: L2 metric only"};
       const int dim = items->dim, ld = round_up4(dim);
@@ -846,7 +944,7 @@ mask_status mask_kmeans(const mask_matrix* items, int32_t n_chunks, int32_t k, i
     check_dense(items, "items");
     MASK_CHECK(items->n >= 1 && items->n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
     MASK_CHECK(n_chunks >= 1 && k >= 1 && iters >= 0, "bad n_chunks, k or iters");
-    MASK_CHECK(items->n / n_chunks >= k, "a chunk holds fewer items than k");
+    MASK_CHECK(items->n >= n_chunks, "more chunks than items");
     MASK_CHECK(centroids && labels, "output pointer is NULL");
     MASK_CHECK(metric == MASK_L2 || metric == MASK_L1, "unknown metric");
     if (items->dim > kMaxDenseDim) throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};

@@ -192,6 +192,9 @@ void row_norms(const float* x, int ld, int64_t n, float* out, hipStream_t s);
 void offsets_from_sorted(const uint32_t* keys, int64_t n, int64_t n_bins, uint32_t* off,
                          hipStream_t s);
 
+// flag (device) := 1 when some a[i] lies outside [0, bound), else 0
+void check_range_i32(const int32_t* a, int64_t n, int64_t bound, uint32_t* flag,
+                     hipStream_t s);
 // out[i] = map[in[i]]
 void map_u32(const uint32_t* map, const uint32_t* in, int64_t n, uint32_t* out, hipStream_t s);
 // out[idx[i]] = i
@@ -287,7 +290,7 @@ void kmeans_update(const float* items, int ld, int dim, const ChunkPlan& plan,
 // FP32 and FP64 squared norms of the prototypes (after init or import).
 void kmeans_proto_norms(const float* protos, int ld, int64_t n_protos, KmeansWork& w,
                         hipStream_t s);
-// Prototype c*k+j := item off[c]+j.
+// Prototype c*k+j := item off[c] + j mod (size of group c).
 void kmeans_init_first(const float* items, int ld, const ChunkPlan& plan, float* protos,
                        hipStream_t s);
 
@@ -384,9 +387,30 @@ struct QueryArgs {
   // rows within it per query (device)
   const float* radius;
   int32_t* out_count;
+  // point query: the level-1 prototype kept (chunk-major id, -1 if none),
+  // with r = 1 (device) or null
+  int32_t* out_leaf;
 };
 
 void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
+
+// Exact-match scan of the point query: match[i] = lowest data row id under
+// level-1 prototype leaf[i] whose coordinates equal query i's, else -1.
+void point_match(const DescentArgs& a, const float* Q, int ldq, int64_t nq,
+                 const int32_t* leaf, int32_t* match, hipStream_t s);
+
+// ------------------------------------------------------------ relocation
+// (relocate.hip)
+
+// One relocation step: data rows with wrong[i] != 0 and leaf[i] >= 0 join
+// level-0 group leaf[i] / k0; the rest stay.  perm0 / goff (device, C + 1
+// entries) give the current level-0 order and groups.  Writes the stable
+// order by (new group, joined) to perm_out and the run boundaries of the 2C
+// keys to off2 (device, 2C + 1); *bad (device) becomes non-zero when a leaf
+// lies outside [0, C * k0).
+void relocate_order(const int32_t* perm0, const int64_t* goff, int C, int64_t n, int k0,
+                    const int32_t* leaf, const int32_t* wrong, int32_t* perm_out,
+                    uint32_t* off2, uint32_t* bad, Arena& scratch, hipStream_t s);
 
 }  // namespace mask
 
@@ -422,5 +446,9 @@ struct mask_index {
   float* sp_val = nullptr;
   int64_t sp_nnz = 0;
   double* norm64[mask::kMaxLevels + 1] = {};
+  // level-0 order (data row ids) and group boundaries the index was built
+  // with (dense builds; null / empty for imported indexes)
+  int32_t* perm0 = nullptr;
+  std::vector<int64_t> group_off0;
   explicit mask_index(const mask_allocator* a, hipStream_t s) : mem(a, s) {}
 };

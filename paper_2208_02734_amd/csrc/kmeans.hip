@@ -1105,7 +1105,9 @@ __global__ void k_init_first(const float* __restrict__ items, int ld,
   const int64_t row = t / ld;
   const int c = (int)(t % ld);
   const int chunk = (int)(row / k), j = (int)(row % k);
-  protos[t] = items[(chunk_off[chunk] + j) * ld + c];
+  // a group smaller than k starts from its members taken cyclically
+  const int64_t m = chunk_off[chunk + 1] - chunk_off[chunk];
+  protos[t] = items[(chunk_off[chunk] + j % m) * ld + c];
 }
 
 __global__ void k_labels_to_keys(const int32_t* __restrict__ labels, int64_t n,

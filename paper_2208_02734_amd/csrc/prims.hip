@@ -393,6 +393,22 @@ void offsets_from_sorted(const uint32_t* keys, int64_t n, int64_t n_bins, uint32
   check_launch("offsets_from_sorted");
 }
 
+namespace {
+__global__ void k_check_range_i32(const int32_t* __restrict__ a, int64_t n, int64_t bound,
+                                  uint32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (a[i] < 0 || a[i] >= bound)) atomicOr(flag, 1u);
+}
+}  // namespace
+
+void check_range_i32(const int32_t* a, int64_t n, int64_t bound, uint32_t* flag,
+                     hipStream_t s) {
+  MASK_HIP(hipMemsetAsync(flag, 0, sizeof(uint32_t), s));
+  if (n <= 0) return;
+  k_check_range_i32<<<grid_for(n, kBlock), kBlock, 0, s>>>(a, n, bound, flag);
+  check_launch("check_range");
+}
+
 void map_u32(const uint32_t* map, const uint32_t* in, int64_t n, uint32_t* out, hipStream_t s) {
   if (n <= 0) return;
   k_map_u32<<<grid_for(n, kBlock), kBlock, 0, s>>>(map, in, n, out);

@@ -539,6 +539,8 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
         s_beg[j] = b0;
         s_cnt[j] = b1 - b0;
       }
+      if (qa.out_leaf && lev == 1 && tid == 0)
+        qa.out_leaf[qi] = kept ? (int32_t)(uint32_t)s_buf[0] : -1;
       if (qa.sel) {
         int32_t* so = qa.sel + ((int64_t)qi * L + (L - lev)) * qa.r;
         for (int j = tid; j < qa.r; j += kBlock)
@@ -642,6 +644,44 @@ void launch2(const DescentArgs& a, const QueryArgs& qa, int need, hipStream_t s)
 }
 
 }  // namespace
+
+// One wave per query: lanes stride over the data rows of the leaf and
+// compare every coordinate; the wave keeps the lowest matching row id.
+__global__ __launch_bounds__(kBlock) void k_point_match(
+    const float* __restrict__ Q, int ldq, int64_t nq, int dim, const float* __restrict__ rows,
+    int ld, const int32_t* __restrict__ orig0, const int32_t* __restrict__ inv1,
+    const uint32_t* __restrict__ child_off1, const int32_t* __restrict__ leaf,
+    int32_t* __restrict__ match) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t qi = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  if (qi >= nq) return;  // uniform across the wave
+  const int32_t p = leaf[qi];
+  int32_t best = INT32_MAX;
+  if (p >= 0) {
+    const int32_t pos = inv1[p];
+    const uint32_t b0 = child_off1[pos], b1 = child_off1[pos + 1];
+    const float* q = Q + qi * ldq;
+    for (uint32_t c = b0 + lane; c < b1; c += kWave) {
+      const float* x = rows + (int64_t)c * ld;
+      bool eq = true;
+      for (int d = 0; d < dim && eq; ++d) eq = x[d] == q[d];
+      if (eq) best = min(best, orig0[c]);
+    }
+  }
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) best = min(best, __shfl_xor(best, o));
+  if (lane == 0) match[qi] = best == INT32_MAX ? -1 : best;
+}
+
+void point_match(const DescentArgs& a, const float* Q, int ldq, int64_t nq,
+                 const int32_t* leaf, int32_t* match, hipStream_t s) {
+  if (nq <= 0) return;
+  ScopedTiming timing("point_match", s);
+  k_point_match<<<(unsigned)((nq * kWave + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+      Q, ldq, nq, a.dim, a.lv[0].protos, a.ld, a.lv[0].orig, a.lv[1].inv, a.lv[1].child_off,
+      leaf, match);
+  check_launch("point_match");
+}
 
 void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   if (qa.nq <= 0) return;

@@ -159,7 +159,8 @@ __global__ void k_zero_f32(float* __restrict__ x, int64_t n) {
   if (i < n) x[i] = 0.f;
 }
 
-// Prototype c*k+j := item off[c]+j, scattered into a zeroed dense row.
+// Prototype c*k+j := item off[c] + j mod (group size), scattered into a
+// zeroed dense row.
 __global__ __launch_bounds__(kBlock) void k_init_first_csr(
     const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
     const float* __restrict__ val, const int64_t* __restrict__ chunk_off, int n_chunks, int k,
@@ -167,7 +168,8 @@ __global__ __launch_bounds__(kBlock) void k_init_first_csr(
   const int lane = threadIdx.x % kWave;
   const int64_t p = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   if (p >= (int64_t)n_chunks * k) return;
-  const int64_t item = chunk_off[p / k] + p % k;
+  const int64_t c = p / k, m = chunk_off[c + 1] - chunk_off[c];
+  const int64_t item = chunk_off[c] + (p % k) % m;
   for (int64_t e = ptr[item] + lane; e < ptr[item + 1]; e += kWave) P[p * ld + col[e]] = val[e];
 }
 

@@ -39,6 +39,27 @@ def test_library_exports_every_declared_symbol(L):
     assert sorted(_declared()) == sorted(pk.EXPORTED)
 
 
+def _header_arg_counts():
+    with open(os.path.join(ROOT, "include", "mask.h")) as f:
+        text = f.read()
+    out = {}
+    for m in re.finditer(r"^\s*(?:mask_status|const char\*|double)\s+(mask_\w+)\s*\(([^)]*)\)",
+                         text, re.M):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_every_entry_point_declares_its_argument_types(L):
+    # without argtypes ctypes passes a Python int as a C int and masks a
+    # 64-bit pointer to its low 32 bits
+    counts = _header_arg_counts()
+    for name in pk.EXPORTED:
+        fn = getattr(L, name)
+        assert fn.argtypes is not None, name
+        assert len(fn.argtypes) == counts[name], name
+
+
 def test_plan_levels_matches_oracle_and_paper(L):
     for n, lg, nc in [(80, 10, 5), (1600, 16, 8), (80000, 10, 5), (80000, 110, 55), (7, 10, 5)]:
         assert pk.mask_plan_levels(n, lg, nc) == mo.plan_levels(n, lg, nc)
@@ -57,10 +78,21 @@ def test_invalid_arguments_are_reported_without_device_work(L):
     assert b"NULL" in L.mask_last_error()
     m = pk.mask_matrix()
     m.layout, m.n, m.dim, m.ld, m.x = 0, 100, 8, 0, 1234
-    # level with k larger than its chunk
-    p, lv = pk._params([(10, 20)], 5, 0, "l2", "fp32", 4, None)
+    # level with more chunks than items
+    p, lv = pk._params([(200, 2)], 5, 0, "l2", "fp32", 4, None)
     st = L.mask_build(ctypes.byref(m), ctypes.byref(p), None, None, ctypes.byref(h))
-    assert st == 1 and b"fewer items" in L.mask_last_error()
+    assert st == 1 and b"more chunks than items" in L.mask_last_error()
+    # group boundaries that do not end at n, or leave a group empty
+    for off in ([0, 50, 99], [0, 50, 50, 100][:3], [0, 60, 60]):
+        p, lv = pk._params([(2, 4)], 5, 0, "l2", "fp32", 4, None, group_off=off)
+        st = L.mask_build(ctypes.byref(m), ctypes.byref(p), None, None, ctypes.byref(h))
+        assert st == 1 and b"group_off" in L.mask_last_error(), off
+    with pytest.raises(pk.MaskError):
+        pk._params([(2, 4)], 5, 0, "l2", "fp32", 4, None, group_off=[0, 100])
+    # point query and relocation on a NULL index
+    assert L.mask_point_query(None, ctypes.byref(m), None, None, None, None, None) == 1
+    ng = ctypes.c_int32()
+    assert L.mask_relocate(None, None, None, None, None, 0, ctypes.byref(ng), None, None) == 1
     # query on a NULL index
     st = L.mask_query(None, ctypes.byref(m), 10, 4, None, None, None)
     assert st == 1
