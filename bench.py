@@ -7,8 +7,8 @@ Lloyd iterations; 10,000 queries; k = 10.  Two forms are built on the same
 data: the plain FP32 form and the precision form (BF16 distances, FP32
 re-rank, FP64 sums).  For each form the cheapest beam configuration
 (prototypes kept per level, from a fixed list ordered by cost) that reaches
-recall@10 >= 0.95 against exhaustive FP64 search (the oracle, on a
-500-query sample) is selected.
+recall@10 >= 0.95 against exhaustive FP64 search (numpy, on a 500-query
+sample) is selected.
 
 A step is one pass of the whole hot path in the faster form: mask_build on
 the device-resident data, then the descent of the 10,000 queries.  ``value``
@@ -18,8 +18,11 @@ one Poisson request stream (1..512 queries per request, log-uniform; k
 uniform in [1, 100]; r in {8, 32}) at several rates through the continuous-batching
 loop for both forms (replayed by the library's native load generator) and
 reports p50/p99 latency (completion minus scheduled arrival) and the
-completed queries/s.  The csr section builds and queries the CSR workload.  Kernel times come from HIP events the library
-records on its launch stream.
+completed queries/s.  The csr section builds and queries the CSR workload;
+the point_query section runs the eight-cloud evaluation of Section 4.2
+(tree time, exhaustive point search, error rate, relocation loop).  Kernel
+times come from HIP events the library records on its launch stream.  The
+FP64 oracle runs only in the CPU-baseline leg.
 
 Prints one JSON line.
 """
@@ -94,6 +97,7 @@ def parse():
                     help="comma-separated Poisson request rates (requests/s)")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--no-point", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--form", choices=["auto", "fp32", "bf16"], default="auto")
@@ -129,22 +133,81 @@ def serve_stream(pk, ix, pool, rate, seconds, seed):
             "peak_arena_MiB": round(st["peak_arena_bytes"] / 2**20, 1)}
 
 
+# ---------------------------------------------------------------------------
+# Recall reference.  The gate needs the exact k nearest neighbours of a query
+# sample in float64; they are computed here with numpy / scipy products (the
+# expanded form screens, the direct form re-scores the survivors), apart from
+# the FP64 oracle, which serves the tests and the CPU-baseline leg only.
+
+def exact_knn64(X, Q, k, block=1 << 16):
+    """The k nearest rows of X for each row of Q by (distance, id); returns
+    (ids, Euclidean distances) in float64."""
+    import numpy as np
+    Q64 = np.asarray(Q, dtype=np.float64)
+    nq, n = Q64.shape[0], X.shape[0]
+    m = min(n, 4 * k + 16)
+    qn = np.einsum("ij,ij->i", Q64, Q64)
+    best_d = np.zeros((nq, 0))
+    best_i = np.zeros((nq, 0), dtype=np.int64)
+    for b0 in range(0, n, block):
+        Xb = np.asarray(X[b0:b0 + block], dtype=np.float64)
+        D = np.einsum("ij,ij->i", Xb, Xb)[None, :] - 2.0 * (Q64 @ Xb.T) + qn[:, None]
+        cd = np.concatenate([best_d, D], axis=1)
+        ci = np.concatenate([best_i, np.broadcast_to(np.arange(b0, b0 + Xb.shape[0]), D.shape)],
+                            axis=1)
+        if cd.shape[1] > m:
+            keep = np.argpartition(cd, m - 1, axis=1)[:, :m]
+            cd = np.take_along_axis(cd, keep, axis=1)
+            ci = np.take_along_axis(ci, keep, axis=1)
+        best_d, best_i = cd, ci
+    ids = np.empty((nq, k), dtype=np.int64)
+    dist = np.empty((nq, k))
+    for i in range(nq):
+        diff = np.asarray(X[best_i[i]], dtype=np.float64) - Q64[i][None, :]
+        d2 = np.einsum("ij,ij->i", diff, diff)
+        order = np.lexsort((best_i[i], d2))[:k]
+        ids[i] = best_i[i][order]
+        dist[i] = np.sqrt(d2[order])
+    return ids, dist
+
+
+def recall_at_k(X, Q, got, true_ids, true_dist, k, rel=1e-5):
+    """Mean fraction of the true k nearest found; a returned id outside the
+    true list counts when its distance ties the k-th true one within rel."""
+    import numpy as np
+    hits = total = 0
+    for i in range(got.shape[0]):
+        g = got[i, :k][got[i, :k] >= 0]
+        diff = np.asarray(X[g], dtype=np.float64) - np.asarray(Q[i], dtype=np.float64)[None, :]
+        d = np.sqrt(np.einsum("ij,ij->i", diff, diff))
+        truth = set(int(t) for t in true_ids[i, :k])
+        kth = true_dist[i, k - 1]
+        h = sum(1 for j, t in enumerate(g) if int(t) in truth or d[j] <= kth * (1 + rel))
+        hits += min(h, k)
+        total += k
+    return hits / max(total, 1)
+
+
 def sparse_section(pk, torch, args, log):
     """The CSR workload: 200,000 x 10,000 sparse rows (100 non-zeros each,
     Zipf column popularity, unit rows), levels 20 x 2,000 -> 2,000 -> 50,
     30 Lloyd iterations, 5,000 CSR queries; recall@10 against exhaustive FP64
-    search over the CSR rows (the oracle) on a 200-query sample."""
+    search over the CSR rows (scipy) on a 200-query sample."""
     import numpy as np
+    import scipy.sparse as sps
     import datagen
-    from oracle import mask_oracle as mo
     cfg = datagen.config_sparse()
     S, QS = cfg.X, cfg.Q
     Xs = pk.CsrTensor.from_host(S.indptr, S.indices, S.values, S.n_cols)
     Qs = pk.CsrTensor.from_host(QS.indptr, QS.indices, QS.values, QS.n_cols)
     g = np.random.default_rng(0)
     sample = np.sort(g.choice(QS.n_rows, 200, replace=False))
-    D = mo.sparse_pairwise_l2(S.indptr, S.indices, S.values,
-                              QS.to_dense()[sample].astype(np.float64)).T
+    # squared distances of the sample to every CSR row, float64 expanded form
+    S64 = sps.csr_matrix((S.values.astype(np.float64), S.indices, S.indptr),
+                         shape=(S.n_rows, S.n_cols))
+    Qs64 = QS.to_dense()[sample].astype(np.float64)
+    D = (np.asarray(S64.multiply(S64).sum(axis=1)).ravel()[None, :]
+         + np.einsum("ij,ij->i", Qs64, Qs64)[:, None] - 2.0 * (S64 @ Qs64.T).T)
     tids = np.argsort(D, axis=1, kind="stable")[:, :10]
     kth = np.take_along_axis(D, tids[:, -1:], axis=1)[:, 0]
     stream = torch.cuda.current_stream()
@@ -184,6 +247,86 @@ def sparse_section(pk, torch, args, log):
                                "queries_per_s": round(QS.n_rows / (q_ms * 1e-3), 1)})
         log(f"csr beams {beams}: {out['queries'][-1]}")
     ix.free()
+    return out
+
+
+def point_query_section(pk, torch, args, log):
+    """The evaluation of Section 4.2 on the eight-cloud benchmark
+    (lengthGroup 16, nCentroids 8, Lloyd iterations as the main workload):
+    tree time (index build), search time (a point query for every data
+    point) and error rate (the point query's answer lies in another cloud)
+    for 200 ... 100,000 points per cloud; the relocation loop on the
+    severely overlapping set (1,600 points, iterations 0-8); and the
+    lengthGroup / nCentroids sweep at 10,000 points per cloud."""
+    import numpy as np
+    import datagen
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e1, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e1.record(stream)
+        out = fn()
+        e2.record(stream)
+        torch.cuda.synchronize()
+        return out, e1.elapsed_time(e2) * 1e-3
+
+    def run(c, lg, nc, perm=None, off=None, seed=1):
+        n = c.X.shape[0]
+        X = torch.from_numpy(c.X).cuda()
+        levels = ([(off.shape[0] - 1, nc)] + pk.mask_plan_levels((off.shape[0] - 1) * nc, lg, nc)
+                  if off is not None else pk.mask_plan_levels(n, lg, nc))
+        ix, tree_s = timed(lambda: pk.mask_build(X, levels, iters=args.iters, seed=seed,
+                                                 perm=perm, group_off=off))
+        pk.mask_point_query(ix, X)  # warm
+        (ids, _, leaf, match), search_s = timed(lambda: pk.mask_point_query(ix, X))
+        h_ids = ids.cpu().numpy()
+        wrong = (h_ids < 0) | (c.labels[np.maximum(h_ids, 0)] != c.labels)
+        res = {"n": n, "tree_depth": len(levels), "tree_s": round(tree_s, 4),
+               "search_s": round(search_s, 5),
+               "point_queries_per_s": round(n / search_s, 1),
+               "error_pct": round(100 * wrong.mean(), 3),
+               "exact_match_miss_pct": round(100 * (match.cpu().numpy() < 0).mean(), 2)}
+        return ix, res, leaf, wrong
+
+    # warm the library on a small case
+    ix, _, _, _ = run(datagen.eight_clouds(200, "none", seed=1), 16, 8)
+    ix.free()
+    out = {"workload": "eight 2-D Gaussian clouds (means on a radius-10 circle; sigma 0.5 / "
+                       "2.0 / 4.0 for no / moderate / severe overlap), lengthGroup 16, "
+                       f"nCentroids 8, {args.iters} Lloyd iterations; error = answer in "
+                       "another cloud", "sizes": {}, "relocation": None, "ratio_sweep": []}
+    for ov in ("none", "moderate"):
+        out["sizes"][ov] = []
+        for npc in (200, 1000, 10000, 100000):
+            c = datagen.eight_clouds(npc, ov, seed=42)
+            ix, res, _, _ = run(c, 16, 8)
+            ix.free()
+            res["npc"] = npc
+            out["sizes"][ov].append(res)
+            log(f"point query {ov} npc={npc}: {res}")
+    # relocation loop: iteration 0 is the first build
+    c = datagen.eight_clouds(200, "severe", seed=42)
+    n = c.X.shape[0]
+    perm, off = None, None  # the first build draws its groups from the seed
+    traj, times = [], []
+    for it in range(9):
+        ix, res, leaf, wrong = run(c, 16, 8, perm=perm, off=off)
+        traj.append(res["error_pct"])
+        (perm, off), rel_s = timed(lambda: pk.mask_relocate(
+            ix, leaf, torch.from_numpy(wrong.astype(np.int32)).cuda()))
+        times.append(round(res["tree_s"] + res["search_s"] + rel_s, 4))
+        ix.free()
+    out["relocation"] = {"n": n, "overlap": "severe", "error_pct_by_iteration": traj,
+                         "seconds_per_iteration": times}
+    log(f"relocation: {out['relocation']}")
+    for lg, nc in [(10, 5), (30, 15), (50, 25), (70, 35), (90, 45), (110, 55)]:
+        for ov in ("none", "moderate"):
+            c = datagen.eight_clouds(10000, ov, seed=42)
+            ix, res, _, _ = run(c, lg, nc)
+            ix.free()
+            res.update({"overlap": ov, "length_group": lg, "n_centroids": nc})
+            out["ratio_sweep"].append(res)
+            log(f"ratio sweep {lg}/{nc} {ov}: {res}")
     return out
 
 
@@ -237,18 +380,16 @@ def main():
         torch.cuda.synchronize()
         return out, e1.elapsed_time(e2)
 
-    # ---- ground truth for recall: the oracle's exhaustive FP64 kNN of a sample
-    from oracle import compare as oc
-    from oracle import mask_oracle as mo
+    # ---- ground truth for recall: exhaustive FP64 kNN of a sample
     g = np.random.default_rng(0)
     sample = np.sort(g.choice(nq, min(args.recall_sample, nq), replace=False))
     t = time.time()
-    tids, tdist = mo.exact_knn(X, Q[sample], args.k)
+    tids, tdist = exact_knn64(X, Q[sample], args.k)
     log(f"exhaustive FP64 kNN of {sample.size} queries on the host: {time.time() - t:.1f}s")
 
     def recall_of(ids):
         got = ids.cpu().numpy()[sample].astype(np.int64)
-        return oc.recall_at_k(got, tids, tdist, oc.true_distances(X, Q[sample], got), args.k)
+        return recall_at_k(X, Q[sample], got, tids, tdist, args.k)
 
     def build(form):
         return pk.mask_build(Xd, levels, iters=args.iters, seed=1, precision=form)
@@ -351,9 +492,14 @@ def main():
     if not args.no_sparse:
         sparse = sparse_section(pk, torch, args, log)
 
+    point = None
+    if not args.no_point:
+        point = point_query_section(pk, torch, args, log)
+
     # ---- CPU baseline: the oracle's FP64 descent on the same index, bounded sample
     cpu = None
     if not args.no_cpu_baseline:
+        from oracle import mask_oracle as mo
         protos, parents = [], []
         for lev in range(1, len(levels) + 1):
             P, par = ix.export_level(lev)
@@ -411,6 +557,7 @@ def main():
         "forms": forms,
         "serving": serving,
         "csr": sparse,
+        "point_query": point,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
