@@ -230,6 +230,25 @@ mask_status mask_point_query(const mask_index* ix, const mask_matrix* q, int32_t
                              float* out_dist, int32_t* out_leaf, int32_t* out_match,
                              void* hip_stream);
 
+/* Dynamic insertion (Section 3.3): each row of points (device, DENSE, dim
+ * as the index) descends greedily -- the nearest prototype at the top
+ * level, then the nearest child at each level, skipping prototypes without
+ * children above level 1 -- and joins the data rows of the level-1
+ * prototype it reaches; out_leaf (device int32[points->n]) receives that
+ * prototype's chunk-major id.  The new rows take ids n, n+1, ... in order
+ * (n = the index's row count before the call) and join the level-0 group of
+ * their leaf, after its members.  When max_leaf > 0, every level-0 group
+ * that then holds a leaf of more than max_leaf rows is built again
+ * locally: the build's lloyd_iters Lloyd iterations over the group's
+ * current rows, starting from its current prototypes, then a final
+ * assignment; the prototypes keep their places in the levels above.
+ * *n_rebuilt = the number of groups rebuilt.  Index built by mask_build
+ * from dense data only (MASK_ERR_UNSUPPORTED otherwise).  Must not race with
+ * queries or with a server on the index.  Synchronous. */
+mask_status mask_insert(mask_index* ix, const mask_matrix* points, int32_t max_leaf,
+                        int32_t* out_leaf, int32_t* n_rebuilt, const mask_allocator* a,
+                        void* hip_stream);
+
 /* One relocation step (Sections 4.1-4.2, the relocation table): every data
  * row i with wrong[i] != 0 whose point query reached leaf[i] >= 0 joins the
  * level-0 group that produced that leaf (leaf[i] / levels[0].k); the others

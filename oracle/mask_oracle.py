@@ -31,6 +31,9 @@ What it computes, by paper passage:
 * ``relocate``         - one relocation step (Sections 4.1-4.2, Table 1):
                          points not found join the group of the leaf their
                          point query reached, before the index is rebuilt.
+* ``insert``           - dynamic insertion (Section 3.3): greedy descent to
+                         a leaf, and the local rebuild of a level-0 group
+                         whose leaf grows beyond a threshold.
 * ``range_query_one``  - the range search of Algorithm 3: the prototypes
                          within the radius at every level, then the points
                          within the radius under them.
@@ -240,6 +243,9 @@ class OracleIndex:
     metric: str
     inertia: List[np.ndarray]  # per level, (n_chunks, iters)
     _kids: Optional[List[List[np.ndarray]]] = None
+    # level-0 order (original ids) and group boundaries of the build
+    perm0: Optional[np.ndarray] = None
+    group_off0: Optional[np.ndarray] = None
 
     @property
     def n_levels(self) -> int:
@@ -278,6 +284,7 @@ def build(X: np.ndarray, levels: Sequence[Tuple[int, int]], iters: int, seed: in
     items = data[pi]
     item_ids = pi  # original id of each item in the current order
     protos, parents, inertia = [], [], []
+    off0 = None
     for lev, (n_chunks, k) in enumerate(levels):
         if lev == 0 and group_off is not None:
             off = np.asarray(group_off, dtype=np.int64)
@@ -286,6 +293,8 @@ def build(X: np.ndarray, levels: Sequence[Tuple[int, int]], iters: int, seed: in
                 raise ValueError("group_off must rise strictly from 0 to n")
         else:
             off = chunk_offsets(items.shape[0], n_chunks)
+        if lev == 0:
+            off0 = off
         P = np.empty((n_chunks * k, data.shape[1]), dtype=np.float64)
         par = np.empty(items.shape[0], dtype=np.int64)
         logs = np.empty((n_chunks, iters), dtype=np.float64)
@@ -300,7 +309,8 @@ def build(X: np.ndarray, levels: Sequence[Tuple[int, int]], iters: int, seed: in
         items = P
         item_ids = np.arange(P.shape[0], dtype=np.int64)
     return OracleIndex(data=data, protos=protos, parents=parents, levels=list(levels),
-                       metric=metric, inertia=inertia)
+                       metric=metric, inertia=inertia, perm0=np.asarray(pi, dtype=np.int64),
+                       group_off0=np.asarray(off0, dtype=np.int64))
 
 
 def index_from_arrays(X: np.ndarray, protos: Sequence[np.ndarray], parents: Sequence[np.ndarray],
@@ -471,6 +481,82 @@ def relocate(perm: np.ndarray, group_off: np.ndarray, k0: int, leaf: np.ndarray,
             off.append(off[-1] + len(members))
     assert len(order) == n
     return np.array(order, dtype=np.int64), np.array(off, dtype=np.int64)
+
+
+# --------------------------------------------------------------------------
+# Dynamic insertion (Section 3.3, the data-insertion procedure and the local
+# rebuild of a partition that grows too large)
+# --------------------------------------------------------------------------
+
+
+def insertion_leaf(index: OracleIndex, x: np.ndarray) -> int:
+    """The leaf a new point joins: the nearest top-level prototype, then at
+    each level the nearest child of the one chosen, down to a level-1
+    prototype.  Reading: above level 1 a prototype without children is
+    skipped (a path through it ends before any leaf); level-1 prototypes are
+    leaves whether or not they hold points.  Ties go to the lower id."""
+    metric = index.metric
+    L = index.n_levels
+    x = np.asarray(x, dtype=np.float64)
+    cand = np.arange(index.protos[L - 1].shape[0], dtype=np.int64)
+    for l in range(L - 1, -1, -1):
+        if l >= 1:
+            kids = index.children(l)
+            cand = np.array([p for p in cand if kids[p].size > 0], dtype=np.int64)
+        d = pairwise(x[None, :], index.protos[l][cand], metric)[0]
+        chosen = int(cand[np.lexsort((cand, d))[0]])
+        if l >= 1:
+            cand = index.children(l)[chosen]
+    return chosen
+
+
+def insert(index: OracleIndex, X_new: np.ndarray, max_leaf: int = 0, iters: int = 0):
+    """Insert the rows of X_new.  Every new point joins the leaf given by
+    ``insertion_leaf`` on the index as it was before the batch (insertion
+    changes no prototype, so the order within the batch does not matter)
+    and takes the next id.  Then every level-0 group holding a leaf with
+    more than ``max_leaf`` points (max_leaf > 0) is built again locally: its
+    Lloyd iterations (``iters`` of them, then the final assignment) run
+    over the group's current members, starting from the group's current
+    prototypes; the levels above keep their structure.
+
+    Readings: a new point joins the level-0 group that produced its leaf
+    (leaf // k0), after that group's members, in batch order; leaf sizes are
+    measured once the whole batch is placed; groups are rebuilt in
+    ascending order.  Returns (new index, leaves of the new points, ids of
+    the rebuilt groups)."""
+    if index.perm0 is None or index.group_off0 is None:
+        raise ValueError("insertion needs the level-0 groups of the build")
+    X_new = np.asarray(X_new, dtype=np.float64)
+    n0 = index.data.shape[0]
+    k0 = index.protos[0].shape[0] // (index.group_off0.shape[0] - 1)
+    leaves = np.array([insertion_leaf(index, x) for x in X_new], dtype=np.int64)
+    data = np.concatenate([index.data, X_new]) if X_new.size else index.data.copy()
+    parents = [p.copy() for p in index.parents]
+    parents[0] = np.concatenate([parents[0], leaves])
+    protos = [p.copy() for p in index.protos]
+    C = index.group_off0.shape[0] - 1
+    members = [list(index.perm0[index.group_off0[g]:index.group_off0[g + 1]]) for g in range(C)]
+    for j, leaf in enumerate(leaves):
+        members[int(leaf) // k0].append(n0 + j)
+    rebuilt = []
+    if max_leaf > 0:
+        sizes = np.bincount(parents[0], minlength=protos[0].shape[0])
+        for g in range(C):
+            if sizes[g * k0:(g + 1) * k0].max() > max_leaf:
+                ids = np.array(members[g], dtype=np.int64)
+                res = lloyd(data[ids], k0, iters, index.metric,
+                            init=protos[0][g * k0:(g + 1) * k0])
+                protos[0][g * k0:(g + 1) * k0] = res.centroids
+                parents[0][ids] = g * k0 + res.labels
+                rebuilt.append(g)
+    perm0 = np.concatenate([np.array(m, dtype=np.int64) for m in members])
+    off0 = np.zeros(C + 1, dtype=np.int64)
+    off0[1:] = np.cumsum([len(m) for m in members])
+    new = OracleIndex(data=data, protos=protos, parents=parents, levels=list(index.levels),
+                      metric=index.metric, inertia=index.inertia, perm0=perm0,
+                      group_off0=off0)
+    return new, leaves, rebuilt
 
 
 # --------------------------------------------------------------------------

@@ -84,7 +84,7 @@ class mask_server_stats(ctypes.Structure):
 _lib = None
 
 EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_beams", "mask_query_ragged",
-            "mask_query_range", "mask_point_query", "mask_relocate",
+            "mask_query_range", "mask_point_query", "mask_relocate", "mask_insert",
             "mask_query_debug", "mask_free",
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
             "mask_last_error", "mask_timing_enable", "mask_timing_report", "mask_clock",
@@ -111,6 +111,7 @@ def lib() -> ctypes.CDLL:
     L.mask_query_range.argtypes = [VP, P(mask_matrix), VP, I32, I32, VP, VP, VP, VP]
     L.mask_point_query.argtypes = [VP, P(mask_matrix), VP, VP, VP, VP, VP]
     L.mask_relocate.argtypes = [VP, VP, VP, VP, P(I64), I32, P(I32), P(mask_allocator), VP]
+    L.mask_insert.argtypes = [VP, P(mask_matrix), I32, VP, P(I32), P(mask_allocator), VP]
     L.mask_free.argtypes = [VP]
     L.mask_index_info.argtypes = [VP, P(mask_info)]
     L.mask_export_level.argtypes = [VP, I32, VP, VP]
@@ -455,6 +456,21 @@ def mask_relocate(index: Index, leaf, wrong, stream=None):
                                ctypes.byref(ng), ctypes.byref(alloc.struct),
                                _stream_handle(stream)))
     return perm, off[:ng.value + 1].copy()
+
+
+def mask_insert(index: Index, points, max_leaf: int = 0, stream=None):
+    """Dynamic insertion of the rows of ``points`` (float32 CUDA tensor);
+    returns (leaf of every new row, number of groups rebuilt).  The new rows
+    take the next ids."""
+    torch = _torch()
+    m = _matrix(points)
+    leaf = torch.empty(points.shape[0], dtype=torch.int32, device=points.device)
+    nr = ctypes.c_int32()
+    alloc = _TorchAllocator(points.device.index or 0)
+    _check(lib().mask_insert(index.handle, ctypes.byref(m), int(max_leaf), leaf.data_ptr(),
+                             ctypes.byref(nr), ctypes.byref(alloc.struct),
+                             _stream_handle(stream)))
+    return leaf, nr.value
 
 
 def mask_free(index: Index):

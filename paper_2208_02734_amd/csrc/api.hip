@@ -618,6 +618,7 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
     // kept for relocation: the level-0 order and groups of this build
     if (goff0.empty()) goff0 = split_offsets(n, p->levels[0].n_chunks);
     ix->group_off0 = goff0;
+    ix->lloyd_iters = p->lloyd_iters;
     ix->perm0 = ix->mem.alloc<int32_t>(n);
     MASK_HIP(hipMemcpyAsync(ix->perm0, perm, n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
 
@@ -713,6 +714,203 @@ mask_status mask_point_query(const mask_index* ix, const mask_matrix* q, int32_t
     return MASK_OK;
   } catch (const Error& e) {
     return fail(e);
+  }
+}
+
+mask_status mask_insert(mask_index* ix, const mask_matrix* points, int32_t max_leaf,
+                        int32_t* out_leaf, int32_t* n_rebuilt, const mask_allocator* a,
+                        void* hip_stream) {
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    MASK_CHECK(ix != nullptr, "index is NULL");
+    if (ix->sparse || !ix->perm0)
+      throw Error{MASK_ERR_UNSUPPORTED, "insertion needs a dense index built by mask_build"};
+    check_dense(points, "points");
+    MASK_CHECK(points->dim == ix->dim, "points dim differs from the index dim");
+    MASK_CHECK(n_rebuilt != nullptr, "n_rebuilt is NULL");
+    *n_rebuilt = 0;
+    const int64_t n = ix->n, m = points->n;
+    if (m == 0) return MASK_OK;
+    MASK_CHECK(out_leaf != nullptr, "out_leaf is NULL");
+    MASK_CHECK(n + m < ((int64_t)1 << 31), "the index would exceed 2^31 rows");
+    const int ld = ix->ld, dim = ix->dim, ldp = ld_of(points);
+    const int C = (int)ix->group_off0.size() - 1, k0 = ix->levels[0].k;
+    const int64_t n1 = ix->level_n[1], n2 = n + m;
+    Arena scratch(a, s);
+
+    // 1. every new point descends to a leaf (prototypes without children
+    //    above level 1 are skipped, so a leaf is always reached)
+    {
+      QueryArgs qa{};
+      qa.Q = points->x;
+      qa.ldq = ldp;
+      qa.nq = m;
+      qa.k = 1;
+      qa.r = 1;
+      qa.out_ids = scratch.alloc<int32_t>(m);
+      qa.out_dist = scratch.alloc<float>(m);
+      qa.out_leaf = out_leaf;
+      qa.skip_empty = true;
+      descent(descent_args(*ix), qa, s);
+      uint32_t* flag = scratch.alloc<uint32_t>(1);
+      check_range_i32(out_leaf, m, n1, flag, s);
+      uint32_t h = 0;
+      MASK_HIP(hipMemcpyAsync(&h, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      MASK_HIP(hipStreamSynchronize(s));
+      if (h != 0) throw Error{MASK_ERR_DEVICE, "insertion descent reached no leaf"};
+    }
+    // 2. level-1 parent of every row, the new ones last
+    int32_t* par1 = scratch.alloc<int32_t>(n2);
+    leaf_parents(ix->child_off[1], n1, ix->orig[1], ix->orig[0], n, par1, s);
+    MASK_HIP(hipMemcpyAsync(par1 + n, out_leaf, m * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    // 3. level-0 groups: a new row joins the group of its leaf, after its members
+    int64_t* goff = scratch.alloc<int64_t>(C + 1);
+    MASK_HIP(hipMemcpyAsync(goff, ix->group_off0.data(), (C + 1) * sizeof(int64_t),
+                            hipMemcpyHostToDevice, s));
+    uint32_t* keys = scratch.alloc<uint32_t>(n2);
+    uint32_t* perm = scratch.alloc<uint32_t>(n2);
+    SortWork sw;
+    sort_work_alloc(sw, n2, false, scratch);
+    insert_group_keys(ix->perm0, goff, C, n, out_leaf, m, k0, keys, perm, s);
+    radix_sort_u32(keys, perm, n2, bits_for(2 * (int64_t)C), sw, s);
+    uint32_t* off2 = scratch.alloc<uint32_t>(2 * (int64_t)C + 1);
+    offsets_from_sorted(keys, n2, 2 * (int64_t)C, off2, s);
+    std::vector<uint32_t> h2(2 * (size_t)C + 1);
+    MASK_HIP(hipMemcpyAsync(h2.data(), off2, h2.size() * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                            s));
+    int32_t* pos0 = scratch.alloc<int32_t>(n);  // data row id -> old leaf-order position
+    scatter_iota(reinterpret_cast<const uint32_t*>(ix->orig[0]), n,
+                 reinterpret_cast<uint32_t*>(pos0), s);
+    MASK_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> goff_new(C + 1);
+    for (int g = 0; g < C; ++g) goff_new[g] = h2[2 * (size_t)g];
+    goff_new[C] = n2;
+
+    // 4. local rebuild of every group holding a leaf above max_leaf: its
+    //    Lloyd iterations over its current members, from its current
+    //    prototypes; the levels above keep their structure
+    std::vector<int32_t> groups;
+    if (max_leaf > 0) {
+      uint32_t* cnt = scratch.alloc<uint32_t>(n1);
+      count_labels(par1, n2, cnt, n1, s);
+      std::vector<uint32_t> hc(n1);
+      MASK_HIP(hipMemcpyAsync(hc.data(), cnt, n1 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      MASK_HIP(hipStreamSynchronize(s));
+      for (int g = 0; g < C; ++g) {
+        uint32_t mx = 0;
+        for (int j = 0; j < k0; ++j) mx = std::max(mx, hc[(size_t)g * k0 + j]);
+        if (mx > (uint32_t)max_leaf) groups.push_back(g);
+      }
+    }
+    if (!groups.empty()) {
+      const int Cf = (int)groups.size();
+      std::vector<int64_t> offs(Cf + 1, 0);
+      for (int c = 0; c < Cf; ++c)
+        offs[c + 1] = offs[c] + (goff_new[groups[c] + 1] - goff_new[groups[c]]);
+      const int64_t M = offs[Cf];
+      uint32_t* mem_ids = scratch.alloc<uint32_t>(M);
+      for (int c = 0; c < Cf; ++c)
+        MASK_HIP(hipMemcpyAsync(mem_ids + offs[c], perm + goff_new[groups[c]],
+                                (offs[c + 1] - offs[c]) * sizeof(uint32_t),
+                                hipMemcpyDeviceToDevice, s));
+      float* items = scratch.alloc<float>(M * ld);
+      gather_two(mem_ids, M, ix->protos[0], pos0, n, points->x, ldp, dim, ld, items, s);
+      std::vector<uint32_t> slots((size_t)Cf * k0);
+      for (int c = 0; c < Cf; ++c)
+        for (int j = 0; j < k0; ++j) slots[(size_t)c * k0 + j] = (uint32_t)(groups[c] * k0 + j);
+      uint32_t* d_slots = scratch.alloc<uint32_t>(slots.size());
+      uint32_t* d_pos = scratch.alloc<uint32_t>(slots.size());
+      int32_t* d_groups = scratch.alloc<int32_t>(Cf);
+      MASK_HIP(hipMemcpyAsync(d_slots, slots.data(), slots.size() * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, s));
+      MASK_HIP(hipMemcpyAsync(d_groups, groups.data(), Cf * sizeof(int32_t),
+                              hipMemcpyHostToDevice, s));
+      map_u32(reinterpret_cast<const uint32_t*>(ix->inv[1]), d_slots, slots.size(), d_pos, s);
+      float* init = scratch.alloc<float>(slots.size() * ld);
+      gather_rows(ix->protos[1], ld, d_pos, slots.size(), ld, init, ld, s);
+      float* protos_new = scratch.alloc<float>(slots.size() * ld);
+      int32_t* labels = scratch.alloc<int32_t>(M);
+      {
+        Arena level_scratch(a, s);
+        run_level(items, M, ld, dim, Cf, k0, ix->lloyd_iters, ix->metric, ix->precision, init,
+                  protos_new, labels, nullptr, level_scratch, s, nullptr, &offs);
+        MASK_HIP(hipStreamSynchronize(s));
+      }
+      scatter_rows(protos_new, d_pos, slots.size(), ld, ix->protos[1], s);
+      relabel(mem_ids, labels, M, d_groups, k0, par1, s);
+      if (ix->precision == MASK_BF16)
+        quantize_bf16(ix->protos[1], ld, n1, ix->protos_b[1], ix->ldb, nullptr, s);
+      *n_rebuilt = Cf;
+    }
+
+    // 5. leaf order of the data: the new group order, stably sorted by the
+    //    position of each row's leaf
+    uint32_t* order = scratch.alloc<uint32_t>(n2);
+    MASK_HIP(hipMemcpyAsync(order, perm, n2 * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    leaf_keys(order, n2, par1, ix->inv[1], keys, s);
+    radix_sort_u32(keys, order, n2, bits_for(n1), sw, s);
+    uint32_t* child_off1 = ix->mem.alloc<uint32_t>(n1 + 1);
+    offsets_from_sorted(keys, n2, n1, child_off1, s);
+    int32_t* orig0 = ix->mem.alloc<int32_t>(n2);
+    MASK_HIP(hipMemcpyAsync(orig0, order, n2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    float* rows0 = ix->mem.alloc<float>(n2 * ld);
+    gather_two(order, n2, ix->protos[0], pos0, n, points->x, ldp, dim, ld, rows0, s);
+    int32_t* perm0 = ix->mem.alloc<int32_t>(n2);
+    MASK_HIP(hipMemcpyAsync(perm0, perm, n2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    uint16_t* rows_b = nullptr;
+    uint8_t* rows_q = nullptr;
+    float* scale_q = nullptr;
+    int32_t* inv0 = nullptr;
+    if (ix->precision == MASK_BF16) {
+      rows_b = ix->mem.alloc<uint16_t>(n2 * ix->ldb);
+      quantize_bf16(rows0, ld, n2, rows_b, ix->ldb, nullptr, s);
+    }
+    if (ix->precision == MASK_FP8_E4M3) {
+      rows_q = ix->mem.alloc<uint8_t>(n2 * ix->ldq);
+      scale_q = ix->mem.alloc<float>(n2);
+      quantize_fp8(rows0, ld, n2, rows_q, ix->ldq, scale_q, nullptr, s);
+    }
+    if (ix->inv0) {
+      inv0 = ix->mem.alloc<int32_t>(n2);
+      scatter_iota(reinterpret_cast<const uint32_t*>(orig0), n2,
+                   reinterpret_cast<uint32_t*>(inv0), s);
+    }
+    std::vector<uint32_t> hoff(n1 + 1);
+    MASK_HIP(hipMemcpyAsync(hoff.data(), child_off1, (n1 + 1) * sizeof(uint32_t),
+                            hipMemcpyDeviceToHost, s));
+    MASK_HIP(hipStreamSynchronize(s));
+    int64_t mx = 0;
+    for (int64_t p = 0; p < n1; ++p) mx = std::max<int64_t>(mx, hoff[p + 1] - hoff[p]);
+
+    // 6. swap the level-0 arrays of the index
+    ix->mem.free_one(ix->child_off[1]);
+    ix->mem.free_one(ix->orig[0]);
+    ix->mem.free_one(ix->protos[0]);
+    ix->mem.free_one(ix->perm0);
+    ix->child_off[1] = child_off1;
+    ix->orig[0] = orig0;
+    ix->protos[0] = rows0;
+    ix->perm0 = perm0;
+    if (rows_b) { ix->mem.free_one(ix->protos_b[0]); ix->protos_b[0] = rows_b; }
+    if (rows_q) {
+      ix->mem.free_one(ix->protos_q[0]);
+      ix->mem.free_one(ix->scale_q[0]);
+      ix->protos_q[0] = rows_q;
+      ix->scale_q[0] = scale_q;
+    }
+    if (inv0) { ix->mem.free_one(ix->inv0); ix->inv0 = inv0; }
+    ix->max_children[1] = mx;
+    ix->n = n2;
+    ix->level_n[0] = n2;
+    ix->group_off0 = goff_new;
+    return MASK_OK;
+  } catch (const Error& e) {
+    if (e.status != MASK_ERR_INVALID && e.status != MASK_ERR_UNSUPPORTED)
+      (void)hipStreamSynchronize(s);
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamSynchronize(s);
+    return fail(Error{MASK_ERR_NOMEM, "host allocation failed"});
   }
 }
 

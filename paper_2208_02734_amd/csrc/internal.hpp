@@ -390,6 +390,9 @@ struct QueryArgs {
   // point query: the level-1 prototype kept (chunk-major id, -1 if none),
   // with r = 1 (device) or null
   int32_t* out_leaf;
+  // insertion descent: above level 1, prototypes without children are not
+  // candidates
+  bool skip_empty;
 };
 
 void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
@@ -398,6 +401,36 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
 // level-1 prototype leaf[i] whose coordinates equal query i's, else -1.
 void point_match(const DescentArgs& a, const float* Q, int ldq, int64_t nq,
                  const int32_t* leaf, int32_t* match, hipStream_t s);
+
+// ------------------------------------------------------------ insertion
+// (relocate.hip)
+
+// par1[orig0[q]] = orig1[p] for every leaf-order position q in the child
+// range of level-1 position p (the level-1 parent of every data row).
+void leaf_parents(const uint32_t* child_off1, int64_t n1, const int32_t* orig1,
+                  const int32_t* orig0, int64_t n0, int32_t* par1, hipStream_t s);
+// Keys of the level-0 order after an insertion: positions j < n of perm0
+// get 2 * (their group), new rows i get 2 * (leaf[i] / k0) + 1 (value n + i).
+void insert_group_keys(const int32_t* perm0, const int64_t* goff, int C, int64_t n,
+                       const int32_t* leaf, int64_t m, int k0, uint32_t* keys, uint32_t* vals,
+                       hipStream_t s);
+// keys[j] = inv1[par1[ids[j]]] (leaf position of every id, in the given order)
+void leaf_keys(const uint32_t* ids, int64_t n, const int32_t* par1, const int32_t* inv1,
+               uint32_t* keys, hipStream_t s);
+// Rows of ids from two sources: id < n0 reads rows0[pos0[id]], else
+// rows1[id - n0] (row stride ld1); out is dense with stride ld.
+void gather_two(const uint32_t* ids, int64_t n, const float* rows0, const int32_t* pos0,
+                int64_t n0, const float* rows1, int ld1, int dim, int ld, float* out,
+                hipStream_t s);
+// dst[pos[t]] = src[t] for rows of stride ld
+void scatter_rows(const float* src, const uint32_t* pos, int64_t n, int ld, float* dst,
+                  hipStream_t s);
+// par1[ids[i]] = group[labels[i] / k0] * k0 + labels[i] % k0
+void relabel(const uint32_t* ids, const int32_t* labels, int64_t n, const int32_t* group, int k0,
+             int32_t* par1, hipStream_t s);
+// counts[par[i]] += 1
+void count_labels(const int32_t* par, int64_t n, uint32_t* counts, int64_t n_bins,
+                  hipStream_t s);
 
 // ------------------------------------------------------------ relocation
 // (relocate.hip)
@@ -450,5 +483,6 @@ struct mask_index {
   // with (dense builds; null / empty for imported indexes)
   int32_t* perm0 = nullptr;
   std::vector<int64_t> group_off0;
+  int lloyd_iters = 0;  // of the build; used by the local rebuild after insertion
   explicit mask_index(const mask_allocator* a, hipStream_t s) : mem(a, s) {}
 };

@@ -510,6 +510,10 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             if (!val[u]) continue;
+            // insertion descent: a prototype above level 1 without children
+            // leads to no leaf and is not a candidate
+            if (qa.skip_empty && lev >= 2 && V.child_off[pos[u] + 1] == V.child_off[pos[u]])
+              continue;
             const uint64_t key = ((uint64_t)__float_as_uint(acc[u]) << 32) | ids[u];
             if (range && lev == 0 && key < thr0) atomicAdd(&sh.in_range, 1u);
             if (key < thr) {

@@ -507,3 +507,77 @@ def test_build_on_given_groups():
         assert np.array_equal(ix.parents[0][members], 4 * c + res.labels)
     with pytest.raises(ValueError):
         mo.build(X, [(4, 4)], 5, seed=0, perm=perm, group_off=np.array([0, 3, 3, 22, 40]))
+
+
+# ------------------------------------------------------- dynamic insertion
+
+def test_insertion_skips_childless_prototypes_above_level_one():
+    # level 1: prototypes at 0 and 10 (children 0, 1 and 9, 11); level 2:
+    # prototype 0 at 4 holds both, prototype 1 at 5 holds nothing.  A point
+    # at 5.2 is nearest to the empty one; insertion passes it by and joins
+    # the nearer level-1 prototype under prototype 0, while the point query
+    # (which does not skip) reaches no leaf.
+    X = np.array([[0.0], [1.0], [9.0], [11.0]])
+    ix = mo.index_from_arrays(X, [np.array([[0.0], [10.0]]), np.array([[4.0], [5.0]])],
+                              [np.array([0, 0, 1, 1]), np.array([0, 0])])
+    assert mo.insertion_leaf(ix, np.array([5.2])) == 1
+    assert mo.point_query_one(ix, np.array([5.2]))[2] == -1
+
+
+def _insert_case(seed=31):
+    g = np.random.default_rng(seed)
+    X = (g.standard_normal((400, 3)) + g.integers(-6, 6, (400, 1))).astype(np.float32)
+    ix = mo.build(X, [(10, 8), (2, 10)], 6, seed=4)
+    Xn = (g.standard_normal((60, 3)) * 2).astype(np.float32)
+    return X, ix, Xn
+
+
+def test_insertion_without_rebuild_places_points_where_their_query_leads():
+    X, ix, Xn = _insert_case()
+    new, leaves, rebuilt = mo.insert(ix, Xn, max_leaf=0)
+    assert rebuilt == []
+    # nothing moves but the new rows, which take the next ids
+    for a, b in zip(new.protos, ix.protos):
+        assert np.array_equal(a, b)
+    assert np.array_equal(new.parents[0][:400], ix.parents[0])
+    assert np.array_equal(new.parents[0][400:], leaves)
+    # each new point joins the level-0 group of its leaf, after its members
+    k0 = 8
+    for g in range(10):
+        members = new.perm0[new.group_off0[g]:new.group_off0[g + 1]]
+        old = ix.perm0[ix.group_off0[g]:ix.group_off0[g + 1]]
+        assert np.array_equal(members[:old.size], old)
+        assert np.array_equal(members[old.size:], 400 + np.nonzero(leaves // k0 == g)[0])
+    # where the point query walks the same path, it finds the inserted point
+    found = 0
+    for j, x in enumerate(Xn):
+        a, d, leaf, match = mo.point_query_one(new, x)
+        if leaf == leaves[j]:
+            assert match == 400 + j and d == 0.0
+            found += 1
+    assert found > 40
+
+
+def test_local_rebuild_is_lloyd_from_the_current_prototypes():
+    X, ix, Xn = _insert_case()
+    new0, leaves, _ = mo.insert(ix, Xn, max_leaf=0)
+    sizes = np.bincount(new0.parents[0], minlength=80)
+    limit = int(np.sort(sizes)[-3])  # a few leaves exceed it
+    new, leaves2, rebuilt = mo.insert(ix, Xn, max_leaf=limit, iters=5)
+    assert np.array_equal(leaves, leaves2)
+    expect = sorted({p // 8 for p in np.nonzero(sizes > limit)[0]})
+    assert rebuilt == expect and len(rebuilt) >= 1
+    data = np.concatenate([X, Xn]).astype(np.float64)
+    for g in range(10):
+        sl = slice(8 * g, 8 * g + 8)
+        members = new.perm0[new.group_off0[g]:new.group_off0[g + 1]]
+        if g in rebuilt:
+            res = mo.lloyd(data[members], 8, 5, init=ix.protos[0][sl])
+            assert np.array_equal(new.protos[0][sl], res.centroids)
+            assert np.array_equal(new.parents[0][members], 8 * g + res.labels)
+        else:
+            assert np.array_equal(new.protos[0][sl], ix.protos[0][sl])
+            assert np.array_equal(new.parents[0][members], new0.parents[0][members])
+    # the levels above keep their structure
+    assert np.array_equal(new.protos[1], ix.protos[1])
+    assert np.array_equal(new.parents[1], ix.parents[1])
