@@ -16,6 +16,8 @@ What it computes, by paper passage:
                          Flood, OOPSLA 2014).
 * ``chunk_offsets``    - ``split(data, ngroups)`` of Algorithm 1: nearly
                          equal contiguous groups (first n mod C get one more).
+* ``kmeanspp_seeds``   - k-means++ seeding (Section 3.1 names it), with a
+                         counter-based SplitMix64 draw per step.
 * ``lloyd``            - ``kmeans(nCentroids, points)`` of Algorithm 1 as
                          Lloyd iterations with the first k group members as
                          initial prototypes.
@@ -96,6 +98,16 @@ def splitmix64_keys(seed: int, n: int) -> np.ndarray:
         z = (z ^ (z >> np.uint64(30))) * _M1
         z = (z ^ (z >> np.uint64(27))) * _M2
     return z ^ (z >> np.uint64(31))
+
+
+def uniform01(seed: int, counter: int) -> float:
+    """A uniform draw in [0, 1) from the SplitMix64 output at ``counter``
+    (the same outputs as ``splitmix64_keys``): its top 53 bits times 2^-53."""
+    z = (int(seed) + (int(counter) + 1) * 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & 0xFFFFFFFFFFFFFFFF
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & 0xFFFFFFFFFFFFFFFF
+    z ^= z >> 31
+    return (z >> 11) * 2.0 ** -53
 
 
 def permutation(seed: int, n: int) -> np.ndarray:
@@ -200,6 +212,46 @@ def lloyd_step(points: np.ndarray, centroids: np.ndarray, metric: str = "l2"):
     return labels, new, inertia
 
 
+KMEANSPP_LEVEL_STRIDE = 1 << 40
+
+
+def kmeanspp_seeds(points: np.ndarray, k: int, seed: int, level: int, chunk: int) -> np.ndarray:
+    """k-means++ seeding (Arthur and Vassilvitskii, SODA 2007), which Section
+    3.1 names as the way to spread the initial prototypes: the first is a
+    member drawn uniformly; every next one is member i with probability
+    D(i)^2 / sum_j D(j)^2, where D(i) is the Euclidean distance of member i
+    to the nearest prototype chosen so far.
+
+    Readings (the paper gives no procedure): draw t of group ``chunk`` at
+    level ``level`` is u_t = uniform01(seed, 2^40 * level + chunk * k + t);
+    draw 0 picks member floor(u_0 * m); draw t picks the first member, in
+    group order, whose running sum of D^2 exceeds u_t * sum D^2 (or, if
+    rounding leaves none, the last member with D^2 > 0); when every D^2 is
+    0 the pick is uniform as for draw 0.  D^2 in float64 direct form.
+    Returns the chosen member indices."""
+    X = np.asarray(points, dtype=np.float64)
+    m = X.shape[0]
+    tag = KMEANSPP_LEVEL_STRIDE * int(level) + int(chunk) * int(k)
+    chosen = np.empty(k, dtype=np.int64)
+    d2 = None
+    for t in range(k):
+        u = uniform01(seed, tag + t)
+        pick = -1
+        if t > 0:
+            total = float(d2.sum())
+            if total > 0.0:
+                run = np.cumsum(d2)
+                above = np.nonzero(run > u * total)[0]
+                pick = int(above[0]) if above.size else int(np.nonzero(d2 > 0)[0][-1])
+        if pick < 0:
+            pick = min(int(u * m), m - 1)
+        chosen[t] = pick
+        diff = X - X[pick][None, :]
+        d = np.einsum("ij,ij->i", diff, diff)
+        d2 = d if d2 is None else np.minimum(d2, d)
+    return chosen
+
+
 def lloyd(points: np.ndarray, k: int, iters: int, metric: str = "l2",
           init: Optional[np.ndarray] = None) -> LloydResult:
     """kmeans(nCentroids, points) of Algorithm 1 as Lloyd's algorithm: the
@@ -270,14 +322,20 @@ class OracleIndex:
 
 def build(X: np.ndarray, levels: Sequence[Tuple[int, int]], iters: int, seed: int,
           metric: str = "l2", perm: Optional[np.ndarray] = None,
-          group_off: Optional[np.ndarray] = None) -> OracleIndex:
+          group_off: Optional[np.ndarray] = None, init: str = "first") -> OracleIndex:
     """Algorithm 1 with explicit level sizes [(n_chunks, k)] bottom-up.
 
     Level 0 (the data) is permuted by ``permutation(seed, n)`` (or the given
     ``perm``) and split into n_chunks contiguous groups (or at the given
     ``group_off`` boundaries, as a relocation leaves them); every upper level
     splits the previous level's prototypes, in chunk-major id order, the same
-    way without shuffling.  Each group runs ``lloyd`` independently."""
+    way without shuffling.  Each group runs ``lloyd`` independently, from
+    its first k members (``init="first"``) or from ``kmeanspp_seeds`` with
+    the build's seed and the level number (``init="kmeans++"``)."""
+    if init not in ("first", "kmeans++"):
+        raise ValueError("init must be 'first' or 'kmeans++'")
+    if init == "kmeans++" and metric != "l2":
+        raise ValueError("k-means++ seeding is defined for the l2 metric")
     data = np.asarray(X, dtype=np.float64)
     n = data.shape[0]
     pi = permutation(seed, n) if perm is None else np.asarray(perm, dtype=np.int64)
@@ -299,7 +357,11 @@ def build(X: np.ndarray, levels: Sequence[Tuple[int, int]], iters: int, seed: in
         par = np.empty(items.shape[0], dtype=np.int64)
         logs = np.empty((n_chunks, iters), dtype=np.float64)
         for c in range(n_chunks):
-            res = lloyd(items[off[c]:off[c + 1]], k, iters, metric)
+            pts = items[off[c]:off[c + 1]]
+            start = None
+            if init == "kmeans++":
+                start = pts[kmeanspp_seeds(pts, k, seed, lev + 1, c)]
+            res = lloyd(pts, k, iters, metric, init=start)
             P[c * k:(c + 1) * k] = res.centroids
             par[item_ids[off[c]:off[c + 1]]] = c * k + res.labels
             logs[c] = res.inertia

@@ -581,3 +581,59 @@ def test_local_rebuild_is_lloyd_from_the_current_prototypes():
     # the levels above keep their structure
     assert np.array_equal(new.protos[1], ix.protos[1])
     assert np.array_equal(new.parents[1], ix.parents[1])
+
+
+# ------------------------------------------------------- k-means++ seeding
+
+def test_uniform01_is_the_splitmix64_output():
+    keys = mo.splitmix64_keys(12345, 5)
+    for i in range(5):
+        assert mo.uniform01(12345, i) == float(int(keys[i]) >> 11) * 2.0 ** -53
+    assert 0.0 <= mo.uniform01(0, 2 ** 45) < 1.0
+
+
+def test_kmeanspp_picks_distinct_members_then_repeats():
+    g = np.random.default_rng(40)
+    P = g.standard_normal((12, 3))
+    s = mo.kmeanspp_seeds(P, 12, seed=3, level=1, chunk=0)
+    assert sorted(s.tolist()) == list(range(12))  # every D^2 > 0 until chosen
+    s2 = mo.kmeanspp_seeds(P[:4], 7, seed=3, level=1, chunk=0)
+    assert sorted(s2[:4].tolist()) == [0, 1, 2, 3]  # then D^2 = 0 everywhere: uniform
+    # identical points: every pick after the first is uniform
+    same = np.ones((5, 2))
+    s3 = mo.kmeanspp_seeds(same, 3, seed=9, level=2, chunk=4)
+    tag = mo.KMEANSPP_LEVEL_STRIDE * 2 + 4 * 3
+    assert s3.tolist() == [int(mo.uniform01(9, tag + t) * 5) for t in range(3)]
+
+
+def test_kmeanspp_draws_with_probability_proportional_to_squared_distance():
+    # four points on a line; over many seeds the second pick given the
+    # first follows D^2 / sum D^2
+    P = np.array([[0.0], [1.0], [3.0], [7.0]])
+    trials = 6000
+    counts = np.zeros((4, 4))
+    for seed in range(trials):
+        s = mo.kmeanspp_seeds(P, 2, seed=seed, level=1, chunk=0)
+        counts[s[0], s[1]] += 1
+    for a in range(4):
+        row = counts[a]
+        d2 = (P[:, 0] - P[a, 0]) ** 2
+        p = d2 / d2.sum()
+        nrow = row.sum()
+        assert abs(nrow / trials - 0.25) < 0.03  # the first pick is uniform
+        sd = np.sqrt(nrow * p * (1 - p)) + 1e-9
+        assert np.all(np.abs(row - nrow * p) <= 5 * sd), (a, row, nrow * p)
+
+
+def test_build_with_kmeanspp_starts_each_group_from_its_seeds():
+    g = np.random.default_rng(41)
+    X = (g.standard_normal((300, 2)) + g.integers(-5, 5, (300, 1))).astype(np.float32)
+    ix = mo.build(X, [(3, 6), (1, 4)], 0, seed=8, init="kmeans++")
+    items = X[mo.permutation(8, 300)].astype(np.float64)
+    off = mo.chunk_offsets(300, 3)
+    for c in range(3):
+        pts = items[off[c]:off[c + 1]]
+        seeds = mo.kmeanspp_seeds(pts, 6, 8, 1, c)
+        np.testing.assert_array_equal(ix.protos[0][6 * c:6 * c + 6], pts[seeds])
+    with pytest.raises(ValueError):
+        mo.build(X, [(3, 6)], 0, seed=8, init="kmeans++", metric="l1")
