@@ -117,7 +117,14 @@ typedef struct {
   const int64_t* group_off; /* optional host int64[levels[0].n_chunks + 1]: level-0 group
                                boundaries in that order, rising strictly from 0 to n (as
                                mask_relocate writes them); NULL = split (dense data only) */
+  int32_t init;             /* mask_init; k-means++ draws use seed and the level number */
 } mask_build_params;
+
+/* Initial prototypes of every group's Lloyd iterations. */
+typedef enum {
+  MASK_INIT_FIRST = 0,    /* the group's first k members (cyclically if fewer) */
+  MASK_INIT_KMEANSPP = 1  /* k-means++ seeding (mask_kmeanspp), dense L2 only */
+} mask_init;
 
 typedef struct mask_index mask_index;
 
@@ -151,7 +158,7 @@ mask_status mask_plan_levels(int64_t n, int32_t length_group, int32_t n_centroid
  * groups (or cut at p->group_off); each group runs lloyd_iters Lloyd
  * iterations starting from its first k members (taken cyclically when the
  * group holds fewer than k: the repeated copies lose every tie and stay
- * empty), then a final assignment.  Every chunk must hold at least one item.  The index copies what it needs: data may be freed after the call.
+ * empty) or from its k-means++ seeds (p->init), then a final assignment.  Every chunk must hold at least one item.  The index copies what it needs: data may be freed after the call.
  * Work runs on hip_stream (NULL = the null stream); the call returns after it
  * completes.  On success *out owns device memory until mask_free. */
 mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
@@ -286,6 +293,23 @@ mask_status mask_import(const mask_matrix* data, int32_t n_levels, const mask_le
                         const float* const* protos_host, const int32_t* const* parents_host,
                         const mask_build_params* p, const mask_allocator* a, void* hip_stream,
                         mask_index** out);
+
+/* k-means++ seeding (Arthur and Vassilvitskii 2007, named in Section 3.1)
+ * of every group: items (device, DENSE, n x dim, dim <= 256) are split into
+ * n_chunks groups as mask_kmeans splits them.  In group c, draw t takes u =
+ * (top 53 bits of the SplitMix64 output at counter level * 2^40 + c * k + t
+ * from state seed) * 2^-53; draw 0 picks member floor(u * m); draw t > 0
+ * picks the first member, in group order, whose running sum of D^2 exceeds
+ * u * sum D^2 (D^2: squared distance to the nearest seed so far, float64
+ * direct form); a zero sum picks uniformly as draw 0, and a target that
+ * rounding leaves unreached picks the last member with D^2 > 0.  Outputs
+ * (device): centroids float32[n_chunks*k*dim] (the chosen rows), chosen
+ * int32[n_chunks*k] (their item indices; may be NULL).  mask_build with
+ * init = MASK_INIT_KMEANSPP seeds level l this way with level = l.
+ * Synchronous. */
+mask_status mask_kmeanspp(const mask_matrix* items, int32_t n_chunks, int32_t k, uint64_t seed,
+                          int32_t level, float* centroids, int32_t* chosen,
+                          const mask_allocator* a, void* hip_stream);
 
 /* The batched per-group k-means of Algorithm 1 on its own (the build's
  * inner loop): items (device, DENSE or CSR, n x dim) are split into n_chunks

@@ -49,7 +49,7 @@ class mask_build_params(ctypes.Structure):
                 ("n_levels", ctypes.c_int32), ("levels", ctypes.POINTER(mask_level)),
                 ("lloyd_iters", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("rerank_factor", ctypes.c_int32), ("perm", ctypes.c_void_p),
-                ("group_off", ctypes.POINTER(ctypes.c_int64))]
+                ("group_off", ctypes.POINTER(ctypes.c_int64)), ("init", ctypes.c_int32)]
 
 
 class mask_info(ctypes.Structure):
@@ -85,6 +85,7 @@ _lib = None
 
 EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_beams", "mask_query_ragged",
             "mask_query_range", "mask_point_query", "mask_relocate", "mask_insert",
+            "mask_kmeanspp",
             "mask_query_debug", "mask_free",
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
             "mask_last_error", "mask_timing_enable", "mask_timing_report", "mask_clock",
@@ -112,6 +113,8 @@ def lib() -> ctypes.CDLL:
     L.mask_point_query.argtypes = [VP, P(mask_matrix), VP, VP, VP, VP, VP]
     L.mask_relocate.argtypes = [VP, VP, VP, VP, P(I64), I32, P(I32), P(mask_allocator), VP]
     L.mask_insert.argtypes = [VP, P(mask_matrix), I32, VP, P(I32), P(mask_allocator), VP]
+    L.mask_kmeanspp.argtypes = [P(mask_matrix), I32, I32, ctypes.c_uint64, I32, VP, VP,
+                                P(mask_allocator), VP]
     L.mask_free.argtypes = [VP]
     L.mask_index_info.argtypes = [VP, P(mask_info)]
     L.mask_export_level.argtypes = [VP, I32, VP, VP]
@@ -304,7 +307,11 @@ def mask_plan_levels(n: int, length_group: int, n_centroids: int) -> List[Tuple[
     return [(out[i].n_chunks, out[i].k) for i in range(cnt.value)]
 
 
-def _params(levels, iters, seed, metric, precision, rerank_factor, perm, group_off=None):
+INITS = {"first": 0, "kmeans++": 1}
+
+
+def _params(levels, iters, seed, metric, precision, rerank_factor, perm, group_off=None,
+            init="first"):
     lv = _levels_array(levels)
     p = mask_build_params()
     p.metric = METRICS[metric]
@@ -315,6 +322,7 @@ def _params(levels, iters, seed, metric, precision, rerank_factor, perm, group_o
     p.seed = seed & 0xFFFFFFFFFFFFFFFF
     p.rerank_factor = rerank_factor
     p.perm = perm.data_ptr() if perm is not None else None
+    p.init = INITS[init]
     if group_off is not None:
         off = np.ascontiguousarray(group_off, dtype=np.int64)
         if off.shape != (levels[0][0] + 1,):
@@ -326,7 +334,8 @@ def _params(levels, iters, seed, metric, precision, rerank_factor, perm, group_o
 
 def mask_build(data, levels: Sequence[Tuple[int, int]], iters: int = 30, seed: int = 0,
                metric: str = "l2", precision: str = "fp32", perm=None, rerank_factor: int = 0,
-               stream=None, torch_allocator: bool = True, group_off=None) -> Index:
+               stream=None, torch_allocator: bool = True, group_off=None,
+               init: str = "first") -> Index:
     """Algorithm 1 on a device tensor (n x dim float32) or a CsrTensor;
     returns the index.  perm (int32 CUDA tensor) and group_off (host int64,
     levels[0] n_chunks + 1 entries) give the level-0 order and groups."""
@@ -334,7 +343,8 @@ def mask_build(data, levels: Sequence[Tuple[int, int]], iters: int = 30, seed: i
     m = _matrix(data)
     if perm is not None and (perm.dtype != torch.int32 or not perm.is_cuda):
         raise MaskError(1, "perm must be an int32 CUDA tensor")
-    p, lv = _params(levels, iters, seed, metric, precision, rerank_factor, perm, group_off)
+    p, lv = _params(levels, iters, seed, metric, precision, rerank_factor, perm, group_off,
+                    init)
     alloc = _TorchAllocator(data.device.index or 0) if torch_allocator else None
     h = ctypes.c_void_p()
     _check(lib().mask_build(ctypes.byref(m), ctypes.byref(p),
@@ -496,6 +506,22 @@ def mask_import(data, levels: Sequence[Tuple[int, int]], protos: Sequence[np.nda
                              ctypes.byref(prm), ctypes.byref(alloc.struct) if alloc else None,
                              _stream_handle(stream), ctypes.byref(h)))
     return Index(h.value, alloc, metric)
+
+
+def mask_kmeanspp(items, n_chunks: int, k: int, seed: int, level: int = 1, stream=None):
+    """k-means++ seeds of every group of a device tensor; returns
+    (centroids (n_chunks*k x dim), chosen item indices int32)."""
+    torch = _torch()
+    m = _matrix(items)
+    np_ = n_chunks * k
+    cent = torch.empty((np_, items.shape[1]), dtype=torch.float32, device=items.device)
+    chosen = torch.empty(np_, dtype=torch.int32, device=items.device)
+    alloc = _TorchAllocator(items.device.index or 0)
+    _check(lib().mask_kmeanspp(ctypes.byref(m), int(n_chunks), int(k),
+                               ctypes.c_uint64(seed & 0xFFFFFFFFFFFFFFFF), int(level),
+                               cent.data_ptr(), chosen.data_ptr(), ctypes.byref(alloc.struct),
+                               _stream_handle(stream)))
+    return cent, chosen
 
 
 def mask_kmeans(items, n_chunks: int, k: int, iters: int, init=None, metric: str = "l2",

@@ -19,7 +19,7 @@ LIB = os.path.join(OUT_DIR, "libmask.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["prims.hip", "kmeans.hip", "fp8.hip", "sparse.hip", "query.hip", "relocate.hip", "api.hip", "server.hip"]
+SOURCES = ["prims.hip", "kmeans.hip", "fp8.hip", "sparse.hip", "query.hip", "relocate.hip", "seeding.hip", "api.hip", "server.hip"]
 
 COMMON = [
     f"--offload-arch={ARCH}",

@@ -286,7 +286,8 @@ struct BuildState {
 void run_level(const float* items, int64_t n_items, int ld, int dim, int C, int k, int iters,
                int metric, int precision, const float* init, float* protos, int32_t* labels,
                double* inertia_log, Arena& scratch, hipStream_t s, int64_t* refined,
-               const std::vector<int64_t>* offs = nullptr) {
+               const std::vector<int64_t>* offs = nullptr, int init_method = MASK_INIT_FIRST,
+               uint64_t seed = 0, int level = 0) {
   ChunkPlan plan;
   make_plan(plan, n_items, C, k, scratch, s, offs);
   KmeansWork w;
@@ -312,6 +313,8 @@ void run_level(const float* items, int64_t n_items, int ld, int dim, int C, int 
   }
   row_norms(items, ld, n_items, w.item_norms, s);
   if (init) copy_rows(init, ld, (int64_t)C * k, ld, protos, ld, s);
+  else if (init_method == MASK_INIT_KMEANSPP)
+    kmeanspp_init(items, ld, dim, plan, seed, level, protos, nullptr, scratch, s);
   else kmeans_init_first(items, ld, plan, protos, s);
   kmeans_proto_norms(protos, ld, (int64_t)C * k, w, s);
   auto assign = [&]() {
@@ -568,6 +571,9 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
       throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};
     if (p->precision != MASK_FP32 && p->metric != MASK_L2)
       throw Error{MASK_ERR_UNSUPPORTED, "BF16 / FP8 form of L1"};
+    MASK_CHECK(p->init == MASK_INIT_FIRST || p->init == MASK_INIT_KMEANSPP, "unknown init");
+    if (p->init == MASK_INIT_KMEANSPP && (sparse || p->metric != MASK_L2))
+      throw Error{MASK_ERR_UNSUPPORTED, "k-means++ seeding: dense data, L2 metric"};
     std::vector<int64_t> goff0;
     if (p->group_off) {
       if (sparse) throw Error{MASK_ERR_UNSUPPORTED, "CSR data: group_off"};
@@ -634,7 +640,8 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
       Arena level_scratch(a, s);
       run_level(items, n_items, ld, data->dim, C, k, p->lloyd_iters, p->metric, p->precision,
                 nullptr, st.protos_cm[l], st.labels[l], nullptr, level_scratch, s,
-                l == 1 ? &ix->refined_last : nullptr, l == 1 ? &goff0 : nullptr);
+                l == 1 ? &ix->refined_last : nullptr, l == 1 ? &goff0 : nullptr, p->init,
+                p->seed, l);
       MASK_HIP(hipStreamSynchronize(s));
     }
     finalize_layout(*ix, st.labels, st.protos_cm, items0, perm, scratch, s);
@@ -1099,6 +1106,44 @@ mask_status mask_import(const mask_matrix* data, int32_t n_levels, const mask_le
                     sparse ? &view : nullptr);
     MASK_HIP(hipStreamSynchronize(s));
     *out = ix.release();
+    return MASK_OK;
+  } catch (const Error& e) {
+    if (e.status != MASK_ERR_INVALID && e.status != MASK_ERR_UNSUPPORTED)
+      (void)hipStreamSynchronize(s);
+    return fail(e);
+  } catch (const std::bad_alloc&) {
+    (void)hipStreamSynchronize(s);
+    return fail(Error{MASK_ERR_NOMEM, "host allocation failed"});
+  }
+}
+
+mask_status mask_kmeanspp(const mask_matrix* items, int32_t n_chunks, int32_t k, uint64_t seed,
+                          int32_t level, float* centroids, int32_t* chosen,
+                          const mask_allocator* a, void* hip_stream) {
+  hipStream_t s = (hipStream_t)hip_stream;
+  try {
+    MASK_CHECK(items != nullptr, "items is NULL");
+    if (items->layout == MASK_CSR)
+      throw Error{MASK_ERR_UNSUPPORTED, "k-means++ seeding: dense items only"};
+    check_dense(items, "items");
+    MASK_CHECK(items->n >= 1 && items->n < ((int64_t)1 << 31), "n must be in [1, 2^31)");
+    MASK_CHECK(n_chunks >= 1 && k >= 1, "bad n_chunks or k");
+    MASK_CHECK(items->n >= n_chunks, "more chunks than items");
+    MASK_CHECK((int64_t)n_chunks * k < ((int64_t)1 << 31), "too many prototypes");
+    MASK_CHECK(level >= 0 && level < (1 << 23), "level must be in [0, 2^23)");
+    MASK_CHECK(centroids != nullptr, "centroids is NULL");
+    if (items->dim > kMaxDenseDim) throw Error{MASK_ERR_UNSUPPORTED, "dense dim above 256"};
+    const int dim = items->dim, ld = round_up4(dim);
+    const int64_t n = items->n, np = (int64_t)n_chunks * k;
+    Arena scratch(a, s);
+    float* x = scratch.alloc<float>(n * ld);
+    copy_rows(items->x, ld_of(items), n, dim, x, ld, s);
+    ChunkPlan plan;
+    make_plan(plan, n, n_chunks, k, scratch, s);
+    float* P = scratch.alloc<float>(np * ld);
+    kmeanspp_init(x, ld, dim, plan, seed, level, P, chosen, scratch, s);
+    copy_rows(P, ld, np, dim, centroids, dim, s);
+    MASK_HIP(hipStreamSynchronize(s));
     return MASK_OK;
   } catch (const Error& e) {
     if (e.status != MASK_ERR_INVALID && e.status != MASK_ERR_UNSUPPORTED)

@@ -402,6 +402,16 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
 void point_match(const DescentArgs& a, const float* Q, int ldq, int64_t nq,
                  const int32_t* leaf, int32_t* match, hipStream_t s);
 
+// ------------------------------------------------------------ seeding
+// (seeding.hip)
+
+// k-means++ seeds of every group of the plan (chunk-major prototypes, row
+// stride ld <= 256); chosen (device int32[C * k], may be null) receives the
+// item index of each seed.  Draw t of group c uses the SplitMix64 output at
+// counter (level << 40) + c * k + t.
+void kmeanspp_init(const float* items, int ld, int dim, const ChunkPlan& plan, uint64_t seed,
+                   int level, float* protos, int32_t* chosen, Arena& scratch, hipStream_t s);
+
 // ------------------------------------------------------------ insertion
 // (relocate.hip)
 

@@ -89,6 +89,14 @@ def test_invalid_arguments_are_reported_without_device_work(L):
         assert st == 1 and b"group_off" in L.mask_last_error(), off
     with pytest.raises(pk.MaskError):
         pk._params([(2, 4)], 5, 0, "l2", "fp32", 4, None, group_off=[0, 100])
+    # unknown init, and k-means++ with L1
+    p, lv = pk._params([(2, 4)], 5, 0, "l2", "fp32", 4, None)
+    p.init = 7
+    st = L.mask_build(ctypes.byref(m), ctypes.byref(p), None, None, ctypes.byref(h))
+    assert st == 1 and b"init" in L.mask_last_error()
+    p, lv = pk._params([(2, 4)], 5, 0, "l1", "fp32", 4, None, init="kmeans++")
+    st = L.mask_build(ctypes.byref(m), ctypes.byref(p), None, None, ctypes.byref(h))
+    assert st == 4
     # point query and relocation on a NULL index
     assert L.mask_point_query(None, ctypes.byref(m), None, None, None, None, None) == 1
     ng = ctypes.c_int32()

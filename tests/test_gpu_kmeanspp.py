@@ -1,0 +1,137 @@
+"""k-means++ seeding on the GPU against the FP64 oracle, called through the
+C ABI.  The draws are the same counter-based SplitMix64 outputs on both
+sides; a pick is an integer decided by a float64 running sum, so the picks
+must agree except where the target falls within 1e-12 (relative to the sum)
+of a running-sum boundary, after which that group's later picks are not
+compared."""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import mask_oracle as mo
+from tests.gpu_helpers import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2208_02734_amd as pk
+    pk.lib()
+    return pk
+
+
+def _mixture(n, d, n_comp, seed):
+    mix = datagen.mixture_params(seed, n_comp, d, sigma_mode="loguniform", sigma_low=0.1,
+                                 sigma_high=3.0)
+    return datagen.sample_mixture(mix, n, seed + 1)
+
+
+def _boundary_pick(pts, picks, t, seed, level, c, k, pick):
+    """True when the GPU's pick at draw t lies on a running-sum boundary of
+    the oracle's computation from the GPU's earlier picks."""
+    X = pts.astype(np.float64)
+    d2 = None
+    for p in picks[:t]:
+        diff = X - X[p][None, :]
+        d = np.einsum("ij,ij->i", diff, diff)
+        d2 = d if d2 is None else np.minimum(d2, d)
+    u = mo.uniform01(seed, mo.KMEANSPP_LEVEL_STRIDE * level + c * k + t)
+    total = d2.sum()
+    run = np.cumsum(d2)
+    target = u * total
+    lo = run[pick - 1] if pick > 0 else 0.0
+    return abs(lo - target) <= 1e-12 * total or abs(run[pick] - target) <= 1e-12 * total
+
+
+def _compare(pts, gpu_picks, seed, level, c, k):
+    ref = mo.kmeanspp_seeds(pts, k, seed, level, c)
+    for t in range(k):
+        if gpu_picks[t] != ref[t]:
+            assert t > 0 and _boundary_pick(pts, gpu_picks, t, seed, level, c, k,
+                                            gpu_picks[t]), (c, t, gpu_picks[t], ref[t])
+            return t
+    return k
+
+
+@pytest.mark.parametrize("d,C,k,level", [(16, 4, 20, 1), (128, 3, 64, 2), (5, 6, 9, 3)])
+def test_seeds_match_oracle(pk, d, C, k, level):
+    n = 3001
+    X = _mixture(n, d, 25, seed=1000 + d)
+    cent, chosen = pk.mask_kmeanspp(dev(X), C, k, seed=77, level=level)
+    cent, chosen = host(cent), host(chosen)
+    off = mo.chunk_offsets(n, C)
+    assert np.array_equal(cent, X[chosen])
+    for c in range(C):
+        pts = X[off[c]:off[c + 1]]
+        picks = chosen[c * k:(c + 1) * k] - off[c]
+        assert np.all((picks >= 0) & (picks < pts.shape[0]))
+        assert _compare(pts, picks, 77, level, c, k) == k  # no boundary case expected
+
+
+def test_small_groups_and_identical_points(pk):
+    X = _mixture(40, 4, 3, seed=1010)
+    X[20:] = X[20]  # the second group: 20 identical points
+    cent, chosen = pk.mask_kmeanspp(dev(X), 2, 25, seed=5, level=1)
+    chosen = host(chosen)
+    for c in range(2):
+        pts = X[20 * c:20 * c + 20]
+        ref = mo.kmeanspp_seeds(pts, 25, 5, 1, c)
+        assert np.array_equal(chosen[25 * c:25 * c + 25] - 20 * c, ref)
+    assert sorted(set((chosen[:20]).tolist())) == list(range(20))  # every member before repeats
+
+
+def _separated(seed, n_per=200, clouds=8):
+    g = np.random.default_rng(seed)
+    ang = np.arange(clouds) * 2 * np.pi / clouds
+    means = np.stack([100 * np.cos(ang), 100 * np.sin(ang)], 1)
+    return np.concatenate([m + g.standard_normal((n_per, 2)) * 3
+                           for m in means]).astype(np.float32)
+
+
+def test_build_with_kmeanspp_matches_oracle(pk):
+    # seed 5: every final assignment of the oracle build has a relative gap
+    # above 0.1
+    X = _separated(5)
+    levels = mo.plan_levels(1600, 16, 8)
+    oix = mo.build(X, levels, 10, seed=5, init="kmeans++")
+    gix = pk.mask_build(dev(X), levels, iters=10, seed=5, init="kmeans++")
+    for lev in range(1, len(levels) + 1):
+        P, par = gix.export_level(lev)
+        assert np.array_equal(par, oix.parents[lev - 1]), lev
+        np.testing.assert_allclose(P, oix.protos[lev - 1], rtol=1e-5, atol=1e-4)
+    gix.free()
+
+
+def test_kmeanspp_starts_from_lower_inertia(pk):
+    # the point of the seeding: on clustered data its initial prototypes
+    # summarise the groups better than the first k members do
+    X = _mixture(20000, 16, 40, seed=1020)
+    C, k = 4, 40
+    seeds, _ = pk.mask_kmeanspp(dev(X), C, k, seed=3, level=1)
+    _, _, in_pp = pk.mask_kmeans(dev(X), C, k, 1, init=seeds)
+    _, _, in_first = pk.mask_kmeans(dev(X), C, k, 1)
+    assert host(in_pp)[0].sum() < 0.8 * host(in_first)[0].sum()
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_precision_forms_build_with_kmeanspp(pk, precision):
+    X = _mixture(8000, 32, 30, seed=1030)
+    levels = [(4, 50), (1, 20)]
+    g = pk.mask_build(dev(X), levels, iters=4, seed=9, precision=precision, init="kmeans++")
+    f = pk.mask_build(dev(X), levels, iters=0, seed=9, init="kmeans++")
+    # both start from the same seeds: with no iterations the FP32 build's
+    # prototypes are the seeds, which the oracle reproduces
+    P0, _ = f.export_level(1)
+    items = X[mo.permutation(9, 8000)]
+    off = mo.chunk_offsets(8000, 4)
+    for c in range(4):
+        pts = items[off[c]:off[c + 1]]
+        np.testing.assert_array_equal(P0[50 * c:50 * c + 50],
+                                      pts[mo.kmeanspp_seeds(pts, 50, 9, 1, c)])
+    ids, dist = pk.mask_query(g, dev(X[:50]), 1, 2048)
+    assert np.all(host(dist)[:, 0] == 0.0)
+    g.free()
+    f.free()
