@@ -98,9 +98,11 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-point", action="store_true")
+    ap.add_argument("--no-insert", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--form", choices=["auto", "fp32", "bf16"], default="auto")
+    ap.add_argument("--form", choices=["auto", "fp32", "bf16", "fp8", "fp32+kmeans++",
+                                       "bf16+kmeans++"], default="auto")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the counter workload: one build (2 Lloyd iterations) and "
                          "one query batch per form, then a 1 GiB copy for calibration")
@@ -391,12 +393,15 @@ def main():
         got = ids.cpu().numpy()[sample].astype(np.int64)
         return recall_at_k(X, Q[sample], got, tids, tdist, args.k)
 
-    def build(form):
-        return pk.mask_build(Xd, levels, iters=args.iters, seed=1, precision=form)
+    def build(key):
+        form, _, init = key.partition("+")
+        return pk.mask_build(Xd, levels, iters=args.iters, seed=1, precision=form,
+                             init=init or "first")
 
-    # ---- both forms: build, select the cheapest beams that pass the recall gate
+    # ---- every form, with the first-k and the k-means++ start: build, then
+    # select the cheapest beams that pass the recall gate
     forms = {}
-    for form in ("fp32", "bf16", "fp8"):
+    for form in ("fp32", "bf16", "fp8", "fp32+kmeans++", "bf16+kmeans++"):
         ix, _ = timed(lambda: build(form))
         ix.free()
         ix, b_ms = timed(lambda: build(form))
@@ -419,9 +424,10 @@ def main():
 
     form = args.form
     if form == "auto":
-        form = max(("fp32", "bf16", "fp8"), key=lambda f: (forms[f]["recall@10"] >= args.gate,
-                                                             forms[f]["queries_per_s"]))
+        form = max(forms, key=lambda f: (forms[f]["recall@10"] >= args.gate,
+                                         forms[f]["queries_per_s"]))
     beams = tuple(forms[form]["beams"])
+    prec = form.partition("+")[0]
 
     # ---- timed steps: build + query in the selected form
     def step():
@@ -458,17 +464,17 @@ def main():
         flops_per_build += 2.0 * items * k * d  # every item against its chunk's k prototypes
         items = C * k
     flops_per_build *= (args.iters + 1)
-    akey = {"fp32": "assign_l2_mfma", "bf16": "assign_bf16_mfma", "fp8": "assign_fp8_mfma"}[form]
+    akey = {"fp32": "assign_l2_mfma", "bf16": "assign_bf16_mfma", "fp8": "assign_fp8_mfma"}[prec]
     a_cnt, a_ms = kt.get(akey, (0, 0.0))
     assign_tflops = flops_per_build * args.steps / (a_ms * 1e-3) / 1e12 if a_ms else 0.0
-    dkey = {"fp32": "descent", "bf16": "descent_bf16", "fp8": "descent_fp8"}[form]
+    dkey = {"fp32": "descent", "bf16": "descent_bf16", "fp8": "descent_fp8"}[prec]
     d_cnt, d_ms = kt.get(dkey, (0, 0.0))
     rows = kt.get("descent_rows", (0, 0.0))[0]
     # bytes per evaluated row (row + id); FP8 rows carry a 4-byte scale.  For
     # the FP8 form only the data rows are FP8 (prototype rows are FP32), so
     # its figure counts every row as FP8: a lower bound of its bytes
     row_bytes = {"fp32": ((d + 3) // 4 * 4) * 4 + 4, "bf16": ((d + 7) // 8 * 8) * 2 + 4,
-                 "fp8": ((d + 15) // 16 * 16) + 8}[form]
+                 "fp8": ((d + 15) // 16 * 16) + 8}[prec]
     desc_gbs = rows * row_bytes / (d_ms * 1e-3) / 1e9 if d_ms else 0.0
     counters = ("descent_rows", "refine_small_points", "refine_full_points")
     kernels = {name: {"launches": c, "total_ms": round(ms, 3),
@@ -518,6 +524,39 @@ def main():
                          f"{done} of the 10,000 queries on the GPU-built index, one thread, "
                          f"{el:.1f}s"}
 
+    # ---- dynamic insertion (Section 3.3) into a fresh index of the selected
+    # form: 100,000 new rows of the same mixture in batches of 10,000, then
+    # recall on the grown index; and once more with local rebuilds of the
+    # groups whose leaves pass 1.2x the largest leaf of the fresh index
+    insertion = None
+    if not args.no_insert:
+        Xn = datagen.scale_insertions(100_000)
+        Xnd = torch.from_numpy(Xn).cuda()
+        X_all = np.concatenate([X, Xn])
+        ins_ids, ins_dist = exact_knn64(X_all, Q[sample], args.k)
+        insertion = {"rows": int(Xn.shape[0]), "batch": 10_000}
+        for label, factor in (("append", 0.0), ("local_rebuild", 1.2)):
+            gx = build(form)
+            max_leaf = 0
+            if factor > 0:
+                _, par = gx.export_level(1)
+                max_leaf = int(factor * np.bincount(par).max())
+            t_ins, rebuilt = 0.0, 0
+            for b0 in range(0, Xn.shape[0], 10_000):
+                (_, nr), ms = timed(lambda: pk.mask_insert(gx, Xnd[b0:b0 + 10_000], max_leaf))
+                t_ins += ms
+                rebuilt += nr
+            (ids, _), q_ms = timed(lambda: pk.mask_query_beams(gx, Qd, args.k, beams))
+            got = ids.cpu().numpy()[sample].astype(np.int64)
+            insertion[label] = {
+                "max_leaf": max_leaf, "groups_rebuilt": rebuilt,
+                "rows_per_s": round(Xn.shape[0] / (t_ins * 1e-3), 1),
+                "recall@10_after": round(recall_at_k(X_all, Q[sample], got, ins_ids, ins_dist,
+                                                     args.k), 4),
+                "queries_per_s_after": round(nq / (q_ms * 1e-3), 1)}
+            log(f"insertion {label}: {insertion[label]}")
+            gx.free()
+
     q_med = statistics.median(query_ms)
     b_med = statistics.median(build_ms)
     out = {
@@ -531,7 +570,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[form],
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[prec],
         "data": "synthetic",
         "config": {"workload": "mixture-1M-d128: 1,000,000 x 128 Gaussian mixture "
                                "(1,000 comps), levels 100x1000->5000->100, 30 Lloyd iters, "
@@ -540,11 +579,11 @@ def main():
         "recall@10": round(step_recall, 4),
         "build_s": round(b_med * 1e-3, 4),
         "latency_ms": None if serving is None else {
-            "rate_req_s": serving[form][0]["rate_req_s"], "p50": serving[form][0]["p50_ms"],
-            "p99": serving[form][0]["p99_ms"]},
+            "rate_req_s": serving[prec][0]["rate_req_s"], "p50": serving[prec][0]["p50_ms"],
+            "p99": serving[prec][0]["p99_ms"]},
         "roofline": {"bound": "mfma", "kernel": akey, "achieved": round(assign_tflops, 2),
-                     "peak": PEAK[form], "unit": "TFLOP/s",
-                     "frac": round(assign_tflops / PEAK[form], 4),
+                     "peak": PEAK[prec], "unit": "TFLOP/s",
+                     "frac": round(assign_tflops / PEAK[prec], 4),
                      "traffic": traffic_bytes(akey), "traffic_unit": "bytes per launch"},
         "roofline_query": {"bound": "hbm", "kernel": dkey, "achieved": round(desc_gbs, 1),
                            "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -558,6 +597,7 @@ def main():
         "serving": serving,
         "csr": sparse,
         "point_query": point,
+        "insertion": insertion,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

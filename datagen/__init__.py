@@ -131,6 +131,15 @@ def config_scale(n: Optional[int] = None, n_queries: Optional[int] = None) -> De
         n_override=n, q_override=n_queries)
 
 
+def scale_insertions(n_new: int) -> np.ndarray:
+    """Fresh rows from the mixture of ``config_scale`` (same components), for
+    dynamic insertion into its index."""
+    seed = DATA_SEED_BASE + 2
+    mix = mixture_params(seed, 1_000, 128, sigma_mode="loguniform", sigma_low=0.1,
+                         sigma_high=3.0)
+    return sample_mixture(mix, n_new, seed + 2 * QUERY_SEED_OFFSET)
+
+
 def config_precision(n: Optional[int] = None, n_queries: Optional[int] = None,
                      levels=None) -> DenseConfig:
     """10,000,000 points, d = 96, 10,000 components, log-uniform sigma in
