@@ -69,23 +69,34 @@ __global__ __launch_bounds__(kWave) void k_pp_pick(
   const int nt = (int)(tile_base[c + 1] - tb);
   int64_t pick = -1;
   if (t > 0) {
+    // every tile sum of the group in registers: lane l holds tiles j * 64 + l
+    constexpr int kRegs = kMaxTiles / kWave;
+    double v[kRegs];
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) {
+      const int b = j * kWave + lane;
+      v[j] = b < nt ? tsum[tb + b] : 0.0;
+    }
     double total = 0.0;
-    for (int b0 = 0; b0 < nt; b0 += kWave)
-      total += wave_sum(b0 + lane < nt ? tsum[tb + b0 + lane] : 0.0);
+#pragma unroll
+    for (int j = 0; j < kRegs; ++j) total += wave_sum(v[j]);
     if (total > 0.0) {
       const double target = u * total;
       double run = 0.0;
       int tile = -1;
-      for (int b0 = 0; b0 < nt && tile < 0; b0 += kWave) {
-        const double v = b0 + lane < nt ? tsum[tb + b0 + lane] : 0.0;
-        const double incl = wave_incl_scan(v, lane);
-        const unsigned long long hit = __ballot(b0 + lane < nt && run + incl > target);
-        if (hit) {
-          const int f = __ffsll((long long)hit) - 1;
-          tile = b0 + f;
-          run += __shfl(incl - v, f);
-        } else {
-          run += __shfl(incl, kWave - 1);
+#pragma unroll
+      for (int j = 0; j < kRegs; ++j) {
+        const double incl = wave_incl_scan(v[j], lane);
+        const unsigned long long hit = __ballot(tile < 0 && run + incl > target);
+        const double excl = __shfl(incl - v[j], hit ? __ffsll((long long)hit) - 1 : 0);
+        const double last = __shfl(incl, kWave - 1);
+        if (tile < 0) {
+          if (hit) {
+            tile = j * kWave + __ffsll((long long)hit) - 1;
+            run += excl;
+          } else {
+            run += last;
+          }
         }
       }
       int64_t lo = c0, hi = c1;  // where the fallback looks
@@ -94,8 +105,8 @@ __global__ __launch_bounds__(kWave) void k_pp_pick(
         hi = min(c1, lo + T);
         for (int64_t i0 = lo; i0 < hi && pick < 0; i0 += kWave) {
           const bool in = i0 + lane < hi;
-          const double v = in ? d2[i0 + lane] : 0.0;
-          const double incl = wave_incl_scan(v, lane);
+          const double dv = in ? d2[i0 + lane] : 0.0;
+          const double incl = wave_incl_scan(dv, lane);
           const unsigned long long hit = __ballot(in && run + incl > target);
           if (hit) pick = i0 + (__ffsll((long long)hit) - 1) - c0;
           else run += __shfl(incl, kWave - 1);
