@@ -50,33 +50,39 @@ PEAK_HBM_GBS = 8000.0
 # its beams; otherwise traffic is reported as null.
 FETCH_SCALE = 1048576.0 / 524318.0
 WRITE_SCALE = 1.0
-TRAFFIC = {
-    "assign_bf16_mfma": {"file": "kmeans.hip", "sha256": "f176fa5a64788c6dd90a1befb6f10cf0b167971d995ef874f0cef8ac7fb18739",
-                         "fetch_kib": (139312.7 + 17627.0 + 776.0) / 3,
-                         "write_kib": (3909.0 + 391.0 + 20.0) / 3},
-    "assign_l2_mfma": {"file": "kmeans.hip", "sha256": "f176fa5a64788c6dd90a1befb6f10cf0b167971d995ef874f0cef8ac7fb18739",
-                       "fetch_kib": (285250.7 + 37690.3 + 1528.7) / 3,
-                       "write_kib": (6332.0 + 986.0 + 20.3) / 3},
-    "descent_bf16": {"file": "query.hip", "sha256": "9309e5006b1e074c38508aad3e6704338a403484cc89422b8792f6d072b88d5e", "beams": [16, 96, 176],
-                     "fetch_kib": 6330542.0, "write_kib": 1250.0},
-    "descent": {"file": "query.hip", "sha256": "9309e5006b1e074c38508aad3e6704338a403484cc89422b8792f6d072b88d5e", "beams": [16, 96, 160],
-                "fetch_kib": 13992329.0, "write_kib": 1250.0},
-}
+TRAFFIC = [
+    {"kernel": "assign_bf16_mfma", "file": "kmeans.hip", "sha256": "c637a8614609f099d6bbf35e2655b7cea2591d2ff5af3282d1ec3ccabc319e06",
+     "fetch_kib": (139239.6 + 17624.5 + 773.0) / 3, "write_kib": (3906.2 + 390.6 + 19.5) / 3},
+    {"kernel": "assign_l2_mfma", "file": "kmeans.hip", "sha256": "c637a8614609f099d6bbf35e2655b7cea2591d2ff5af3282d1ec3ccabc319e06",
+     "fetch_kib": (285148.2 + 37721.8 + 1521.3) / 3, "write_kib": (6326.5 + 983.4 + 20.4) / 3},
+    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "ab6c38d9863649c15c158bc81df9050cb1f506768e2c2e1c632a621ffded5ee9", "init": "first",
+     "beams": [16, 96, 176], "fetch_kib": 6320941.1, "write_kib": 1250.0},
+    {"kernel": "descent", "file": "query.hip", "sha256": "ab6c38d9863649c15c158bc81df9050cb1f506768e2c2e1c632a621ffded5ee9", "init": "first",
+     "beams": [16, 96, 160], "fetch_kib": 13993305.6, "write_kib": 1250.0},
+    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "ab6c38d9863649c15c158bc81df9050cb1f506768e2c2e1c632a621ffded5ee9", "init": "kmeans++",
+     "beams": [8, 64, 128], "fetch_kib": 3296870.0, "write_kib": 1250.0},
+    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "7d17799111bcc27b69658a7ade27974d821bf5961f978b8a0a6f69859066e597",
+     "fetch_kib": (254276428.2 + 127214794.3 + 130721.4) / 3,
+     "write_kib": (9742592.2 + 4240409.9 + 3979.1) / 3},
+]
 
 
-def traffic_bytes(kernel, beams=None):
+def traffic_bytes(kernel, beams=None, init=None):
     """Measured bytes per launch of `kernel`, or None when its source (or
-    the descent's beams) changed since the counters were taken."""
+    the descent's beams or index) changed since the counters were taken."""
     import hashlib
-    t = TRAFFIC.get(kernel)
-    if t is None:
-        return None
-    path = os.path.join(ROOT, "paper_2208_02734_amd", "csrc", t["file"])
-    if hashlib.sha256(open(path, "rb").read()).hexdigest() != t["sha256"]:
-        return None
-    if "beams" in t and (beams is None or list(beams) != t["beams"]):
-        return None
-    return round((t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0)
+    for t in TRAFFIC:
+        if t["kernel"] != kernel:
+            continue
+        if "beams" in t and (beams is None or list(beams) != t["beams"]):
+            continue
+        if "init" in t and init != t["init"]:
+            continue
+        path = os.path.join(ROOT, "paper_2208_02734_amd", "csrc", t["file"])
+        if hashlib.sha256(open(path, "rb").read()).hexdigest() != t["sha256"]:
+            return None
+        return round((t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0)
+    return None
 
 # beam candidates (top level first), cheapest first
 BEAMS = [(8, 64, 128), (16, 64, 160), (16, 96, 160), (16, 96, 176), (24, 96, 176),
@@ -429,7 +435,8 @@ def main():
         form = max(forms, key=lambda f: (forms[f]["recall@10"] >= args.gate,
                                          forms[f]["queries_per_s"]))
     beams = tuple(forms[form]["beams"])
-    prec = form.partition("+")[0]
+    prec, _, init = form.partition("+")
+    init = init or "first"
 
     # ---- timed steps: build + query in the selected form
     def step():
@@ -610,10 +617,11 @@ def main():
         "roofline_query": {"bound": "hbm", "kernel": dkey, "achieved": round(desc_gbs, 1),
                            "peak": PEAK_HBM_GBS, "unit": "GB/s",
                            "frac": round(desc_gbs / PEAK_HBM_GBS, 4),
-                           "traffic": traffic_bytes(dkey, beams),
+                           "traffic": traffic_bytes(dkey, beams, init),
                            "traffic_unit": "bytes per launch",
-                           "traffic_gbs": (None if traffic_bytes(dkey, beams) is None or not d_ms
-                                           else round(traffic_bytes(dkey, beams) * d_cnt
+                           "traffic_gbs": (None if traffic_bytes(dkey, beams, init) is None
+                                           or not d_ms
+                                           else round(traffic_bytes(dkey, beams, init) * d_cnt
                                                       / (d_ms * 1e-3) / 1e9, 1))},
         "forms": forms,
         "serving": serving,
