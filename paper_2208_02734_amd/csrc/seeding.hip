@@ -1,8 +1,8 @@
 // k-means++ seeding (Arthur and Vassilvitskii 2007; Section 3.1 names it as
 // the remedy for initial prototypes placed badly) for every group of a level
 // at once.  The k draws are sequential; each is two launches: a pick (one
-// wave per group) and a D^2 update over every row that also sums D^2 per
-// tile of consecutive members.
+// wave per group) and a D^2 update over every row (one workgroup per tile of
+// consecutive members) that also sums D^2 per tile.
 //
 // Draw t of group c uses u = the top 53 bits of the SplitMix64 output at
 // counter tag + c * k + t.  Draw 0 picks member floor(u * m); draw t > 0 picks
@@ -129,19 +129,21 @@ __global__ __launch_bounds__(kWave) void k_pp_pick(
   if (lane == 0 && chosen) chosen[slot] = (int32_t)pi;
 }
 
-// D^2 after draw t, one wave per tile: G lanes per row (each with U float4
-// columns in flight, FP64 accumulation, butterfly over the lane group),
-// 64 / G rows per pass.  The wave also writes the tile's sum of D^2, added in
-// a fixed order (per row slot over the passes, then across the slots).
+// D^2 after draw t, one workgroup per tile: G lanes per row (each with U
+// float4 columns in flight, FP64 accumulation, butterfly over the lane
+// group), 64 / G rows per wave and pass, the four waves on interleaved rows.
+// The tile's sum of D^2 is added in a fixed order: per row slot over the
+// passes, across the slots of a wave, then across the waves.
 template <int G, int U>
 __global__ __launch_bounds__(kBlock) void k_pp_update(
     const float* __restrict__ items, int ld, const int64_t* __restrict__ chunk_off,
-    const int64_t* __restrict__ tile_base, int n_chunks, int64_t n_tiles, int k, int t,
+    const int64_t* __restrict__ tile_base, int n_chunks, int k, int t,
     const float* __restrict__ protos, double* __restrict__ d2, double* __restrict__ tsum) {
-  constexpr int R = kWave / G;
-  const int lane = threadIdx.x % kWave;
-  const int64_t tile = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  if (tile >= n_tiles) return;  // uniform across the wave
+  constexpr int R = kWave / G;                 // rows per wave and pass
+  constexpr int W = kBlock / kWave;            // waves per tile
+  __shared__ double s_wave[W];
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int64_t tile = blockIdx.x;
   int lo = 0, hi = n_chunks - 1;  // group of the tile
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -154,7 +156,8 @@ __global__ __launch_bounds__(kBlock) void k_pp_update(
   const float4* ctr = reinterpret_cast<const float4*>(protos + ((int64_t)lo * k + t) * ld);
   const int ld4 = ld / 4, slot = lane / G, gl = lane % G;
   double tile_acc = 0.0;
-  for (int64_t i = r0 + slot; i - slot < r1; i += R) {
+  const int64_t first = r0 + wave * R + slot;
+  for (int64_t i = first; i - slot - wave * R < r1; i += (int64_t)R * W) {
     const bool live = i < r1;
     const float4* x = reinterpret_cast<const float4*>(items + (live ? i : r0) * ld);
     double acc = 0.0;
@@ -187,16 +190,23 @@ __global__ __launch_bounds__(kBlock) void k_pp_update(
   }
 #pragma unroll
   for (int o = kWave / 2; o >= G; o >>= 1) tile_acc += __shfl_xor(tile_acc, o);
-  if (lane == 0) tsum[tile] = tile_acc;
+  if (lane == 0) s_wave[wave] = tile_acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) sum += s_wave[w];
+    tsum[tile] = sum;
+  }
 }
 
 template <int G, int U>
 void launch_update(const float* items, int ld, const ChunkPlan& plan, const int64_t* tile_base,
                    int64_t n_tiles, int t, const float* protos, double* d2, double* tsum,
                    hipStream_t s) {
-  const int64_t threads = n_tiles * kWave;
-  k_pp_update<G, U><<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-      items, ld, plan.d_off, tile_base, plan.n_chunks, n_tiles, plan.k, t, protos, d2, tsum);
+  k_pp_update<G, U><<<(unsigned)n_tiles, kBlock, 0, s>>>(items, ld, plan.d_off, tile_base,
+                                                         plan.n_chunks, plan.k, t, protos, d2,
+                                                         tsum);
 }
 
 }  // namespace
