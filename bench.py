@@ -3,14 +3,16 @@
 
 Workload: 1,000,000 x 128 Gaussian mixture (1,000 components, log-uniform
 sigma in [0.1, 3]); index levels 100 chunks x 1,000 -> 5,000 -> 100; 30
-Lloyd iterations; 10,000 queries; k = 10.  Two forms are built on the same
-data: the plain FP32 form and the precision form (BF16 distances, FP32
-re-rank, FP64 sums).  For each form the cheapest beam configuration
-(prototypes kept per level, from a fixed list ordered by cost) that reaches
+Lloyd iterations; 10,000 queries; k = 10.  Five forms are built on the
+same data: the plain FP32 form, the BF16 and FP8 precision forms (low
+precision distances, FP32 re-rank, FP64 sums), each started from the first
+k members of every group, and the FP32 and BF16 forms started from
+k-means++ seeds.  For each form every beam setting of a fixed list
+(prototypes kept per level) is measured and the fastest that reaches
 recall@10 >= 0.95 against exhaustive FP64 search (numpy, on a 500-query
-sample) is selected.
+sample) is kept; the form with the highest such throughput is timed.
 
-A step is one pass of the whole hot path in the faster form: mask_build on
+A step is one pass of the whole hot path in the selected form: mask_build on
 the device-resident data, then the descent of the 10,000 queries.  ``value``
 is that form's query throughput (queries/s, index resident, median over the
 timed steps); ``build_s`` its median build time.  The serving section runs
@@ -84,9 +86,11 @@ def traffic_bytes(kernel, beams=None, init=None):
         return round((t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0)
     return None
 
-# beam candidates (top level first), cheapest first
-BEAMS = [(8, 64, 128), (16, 64, 160), (16, 96, 160), (16, 96, 176), (24, 96, 176),
-         (24, 128, 192), (32, 128, 224), (64, 192, 256), (128, 256, 320), (256, 512, 512)]
+# beam candidates (top level first); every form takes the fastest one that
+# passes the recall gate
+BEAMS = [(4, 32, 96), (4, 32, 112), (4, 32, 128), (4, 48, 128), (8, 64, 128), (8, 64, 144),
+         (16, 64, 160), (16, 96, 160), (16, 96, 176), (24, 96, 176), (24, 128, 192),
+         (32, 128, 224), (64, 192, 256), (128, 256, 320), (256, 512, 512)]
 
 
 def parse():
@@ -420,9 +424,10 @@ def main():
             rec = recall_of(ids)
             tried.append({"beams": list(beams), "recall@10": round(rec, 4),
                           "queries_per_s": round(nq / (q_ms * 1e-3), 1)})
-            chosen = (beams, rec, q_ms)
-            if rec >= args.gate:
-                break
+            # the fastest passing setting; while none passes, the best recall
+            key = (rec >= args.gate, -q_ms if rec >= args.gate else rec)
+            if chosen is None or key > chosen[3]:
+                chosen = (beams, rec, q_ms, key)
         ix.free()
         forms[form] = {"build_s": round(b_ms * 1e-3, 4), "beams": list(chosen[0]),
                        "recall@10": round(chosen[1], 4),
