@@ -171,3 +171,23 @@ def test_insert_edge_cases(pk):
     assert e.value.status == 4
     imp.free()
     gix.free()
+
+
+def test_insert_and_point_query_with_l1(pk):
+    X, _ = _mixture(3000, 8, 15, seed=940)
+    Xn, _ = _mixture(200, 8, 15, seed=945)
+    levels = [(3, 20), (1, 6)]
+    gix = pk.mask_build(dev(X), levels, iters=4, seed=5, metric="l1")
+    oix = _oracle_view(pk, X, gix)
+    oix.metric = "l1"
+    leaves, _ = pk.mask_insert(gix, dev(Xn))
+    new_o, leaves_o, _ = mo.insert(oix, Xn, max_leaf=0)
+    assert np.array_equal(host(leaves), leaves_o)
+    X_all = np.concatenate([X, Xn])
+    new_o2 = oracle_index_from_gpu(X_all, gix, metric="l1")
+    ids, dist, leaf, match = (host(t) for t in pk.mask_point_query(gix, dev(Xn[:50])))
+    for j in range(50):
+        a, d, lf, m = mo.point_query_one(new_o2, Xn[j])
+        assert (ids[j], leaf[j], match[j]) == (a, lf, m)
+        assert abs(dist[j] - d) <= 1e-5 * max(d, 1e-30)
+    gix.free()

@@ -135,3 +135,21 @@ def test_precision_forms_build_with_kmeanspp(pk, precision):
     assert np.all(host(dist)[:, 0] == 0.0)
     g.free()
     f.free()
+
+
+def test_kmeanspp_on_given_groups_matches_oracle(pk):
+    # seeding over ragged groups (as relocation leaves them), some smaller than k
+    import torch
+    X = _separated(9, n_per=60)
+    n = X.shape[0]
+    perm = np.random.default_rng(9).permutation(n)
+    off = np.array([0, 3, 40, 41, 200, 480])
+    levels = [(5, 8), (1, 6)]
+    oix = mo.build(X, levels, 6, seed=4, perm=perm, group_off=off, init="kmeans++")
+    gix = pk.mask_build(dev(X), levels, iters=6, seed=4, init="kmeans++", group_off=off,
+                        perm=torch.from_numpy(perm.astype(np.int32)).cuda())
+    for lev in (1, 2):
+        P, par = gix.export_level(lev)
+        assert np.array_equal(par, oix.parents[lev - 1]), lev
+        np.testing.assert_allclose(P, oix.protos[lev - 1], rtol=1e-5, atol=1e-4)
+    gix.free()
