@@ -307,9 +307,19 @@ def test_query_identical_across_lds_classes_and_runs(pk):
         assert np.array_equal(host(d2), dist)
     ks = torch.full((3000,), 10, dtype=torch.int32)
     rs = torch.full((3000,), 64, dtype=torch.int32)
-    i3, d3, off = pk.mask_query_ragged(gix, dev(Q), ks, rs, k_max=10, r_max=600)
-    assert np.array_equal(host(i3).reshape(3000, 10), ids)
-    assert np.array_equal(host(d3).reshape(3000, 10), dist)
+    for r_max in (200, 400, 600):  # the 512 class as r = 64, and the 2048 class
+        i3, d3, off = pk.mask_query_ragged(gix, dev(Q), ks, rs, k_max=10, r_max=r_max)
+        assert np.array_equal(host(i3).reshape(3000, 10), ids), r_max
+        assert np.array_equal(host(d3).reshape(3000, 10), dist), r_max
+    gix.free()
+    # the precision form: its re-rank set does not depend on the class either
+    g16 = pk.mask_build(dev(X), [(20, 300), (1, 100)], iters=6, seed=4, precision="bf16")
+    ids, dist = (host(t) for t in pk.mask_query(g16, dev(Q), 10, 64))
+    for r_max in (200, 400, 600):
+        i3, d3, off = pk.mask_query_ragged(g16, dev(Q), ks, rs, k_max=10, r_max=r_max)
+        assert np.array_equal(host(i3).reshape(3000, 10), ids), r_max
+        assert np.array_equal(host(d3).reshape(3000, 10), dist), r_max
+    g16.free()
 
 
 def test_build_is_deterministic(pk):
