@@ -42,7 +42,7 @@ PEAK = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}  # dense MFMA TFLOP/s
 PEAK_HBM_GBS = 8000.0
 
 # Bytes moved between L2 and memory per launch, from two rocprofv3 --pmc runs
-# of ``bench.py --pmc-workload`` (FETCH_SIZE, then WRITE_SIZE, KiB per
+# of ``bench.py --pmc-workload --pmc-index`` (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch; profiles/traffic_mixture-1M-d128.md), averaged over the launches
 # the timing aggregates (the assignment: one launch per level and iteration,
 # so the mean of the three levels).  A 1 GiB copy reads FETCH_SIZE 524,318 KiB
@@ -54,18 +54,22 @@ FETCH_SCALE = 1048576.0 / 524318.0
 WRITE_SCALE = 1.0
 TRAFFIC = [
     {"kernel": "assign_bf16_mfma", "file": "kmeans.hip", "sha256": "c637a8614609f099d6bbf35e2655b7cea2591d2ff5af3282d1ec3ccabc319e06",
-     "fetch_kib": (139239.6 + 17624.5 + 773.0) / 3, "write_kib": (3906.2 + 390.6 + 19.5) / 3},
+     "fetch_kib": (139123.0 + 17624.5 + 773.0) / 3,
+     "write_kib": (3908.1 + 390.6 + 19.5) / 3},
     {"kernel": "assign_l2_mfma", "file": "kmeans.hip", "sha256": "c637a8614609f099d6bbf35e2655b7cea2591d2ff5af3282d1ec3ccabc319e06",
-     "fetch_kib": (285148.2 + 37721.8 + 1521.3) / 3, "write_kib": (6326.5 + 983.4 + 20.4) / 3},
+     "fetch_kib": (285132.2 + 37690.0 + 1521.3) / 3,
+     "write_kib": (6403.0 + 978.7 + 20.5) / 3},
     {"kernel": "descent_bf16", "file": "query.hip", "sha256": "ab6c38d9863649c15c158bc81df9050cb1f506768e2c2e1c632a621ffded5ee9", "init": "first",
-     "beams": [16, 96, 176], "fetch_kib": 6320941.1, "write_kib": 1250.0},
+     "beams": [16, 96, 176], "fetch_kib": 6336056.4, "write_kib": 1250.0},
     {"kernel": "descent", "file": "query.hip", "sha256": "ab6c38d9863649c15c158bc81df9050cb1f506768e2c2e1c632a621ffded5ee9", "init": "first",
-     "beams": [16, 96, 160], "fetch_kib": 13993305.6, "write_kib": 1250.0},
+     "beams": [16, 96, 160], "fetch_kib": 13958789.2, "write_kib": 1250.0},
     {"kernel": "descent_bf16", "file": "query.hip", "sha256": "ab6c38d9863649c15c158bc81df9050cb1f506768e2c2e1c632a621ffded5ee9", "init": "kmeans++",
-     "beams": [8, 64, 128], "fetch_kib": 3296870.0, "write_kib": 1250.0},
-    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "7d17799111bcc27b69658a7ade27974d821bf5961f978b8a0a6f69859066e597",
-     "fetch_kib": (254276428.2 + 127214794.3 + 130721.4) / 3,
-     "write_kib": (9742592.2 + 4240409.9 + 3979.1) / 3},
+     "beams": [4, 24, 104], "fetch_kib": 2936033.6, "write_kib": 1250.0},
+    # per level: 21-draw runs at each level's shape, scaled to its k - 1
+    # updates and k picks
+    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "9c34ad05fb03c06a39009a3e818bac2de11b145dcadcb7bd6bcad75c07edaf80",
+     "fetch_kib": (253995810.5 + 127075434.8 + 129923.4) / 3,
+     "write_kib": (8354618.3 + 4152294.9 + 4164.7) / 3},
 ]
 
 
@@ -88,9 +92,10 @@ def traffic_bytes(kernel, beams=None, init=None):
 
 # beam candidates (top level first); every form takes the fastest one that
 # passes the recall gate
-BEAMS = [(4, 32, 96), (4, 32, 112), (4, 32, 128), (4, 48, 128), (8, 64, 128), (8, 64, 144),
-         (16, 64, 160), (16, 96, 160), (16, 96, 176), (24, 96, 176), (24, 128, 192),
-         (32, 128, 224), (64, 192, 256), (128, 256, 320), (256, 512, 512)]
+BEAMS = [(4, 24, 96), (4, 32, 96), (4, 24, 104), (4, 32, 104), (4, 24, 112), (4, 32, 112),
+         (4, 32, 128), (4, 48, 128), (8, 64, 128), (8, 64, 144), (16, 64, 160), (16, 96, 160),
+         (8, 96, 176), (12, 96, 176), (16, 80, 176), (16, 96, 176), (24, 96, 176),
+         (24, 128, 192), (32, 128, 224), (64, 192, 256), (128, 256, 320), (256, 512, 512)]
 
 
 def parse():
@@ -113,6 +118,10 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--form", choices=["auto", "fp32", "bf16", "fp8", "fp32+kmeans++",
                                        "bf16+kmeans++"], default="auto")
+    ap.add_argument("--pmc-export", type=str, default="",
+                    help="build the k-means++ BF16 index and save it (npz) for --pmc-index")
+    ap.add_argument("--pmc-index", type=str, default="",
+                    help="with --pmc-workload: the saved k-means++ index to import and query")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the counter workload: one build (2 Lloyd iterations) and "
                          "one query batch per form, then a 1 GiB copy for calibration")
@@ -356,16 +365,50 @@ def main():
 
     pk.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.pmc_export:
+        # the k-means++ BF16 index of the benchmark, saved for an import under
+        # the counters (its build queues thousands of short dispatches, which
+        # the counter-collection run is kept free of)
+        cfg = datagen.config_scale()
+        Xd = torch.from_numpy(cfg.X).cuda()
+        ix = pk.mask_build(Xd, cfg.levels, iters=2, seed=1, precision="bf16", init="kmeans++")
+        arrays = {}
+        for lev in range(1, len(cfg.levels) + 1):
+            P, par = ix.export_level(lev)
+            arrays[f"protos{lev}"] = P
+            arrays[f"parents{lev}"] = par
+        np.savez(args.pmc_export, **arrays)
+        ix.free()
+        print(f"pmc export: {args.pmc_export} written", flush=True)
+        return 0
     if args.pmc_workload:
         cfg = datagen.config_scale()
         Xd = torch.from_numpy(cfg.X).cuda()
         Qd = torch.from_numpy(cfg.Q).cuda()
-        for prec, init, beams in (("bf16", "first", (16, 96, 176)),
-                                  ("fp32", "first", (16, 96, 160)),
-                                  ("bf16", "kmeans++", (8, 64, 128))):
-            ix = pk.mask_build(Xd, cfg.levels, iters=2, seed=1, precision=prec, init=init)
+        for prec, beams in (("bf16", (16, 96, 176)), ("fp32", (16, 96, 160))):
+            ix = pk.mask_build(Xd, cfg.levels, iters=2, seed=1, precision=prec)
+            torch.cuda.synchronize()
+            print(f"pmc workload: {prec} build done", flush=True)
             pk.mask_query_beams(ix, Qd, 10, beams)
             torch.cuda.synchronize()
+            print(f"pmc workload: descent {beams} done", flush=True)
+            ix.free()
+        if args.pmc_index:
+            # the same k-means++ index, imported: the descent reads the same layout
+            z = np.load(args.pmc_index)
+            L = len(cfg.levels)
+            ix = pk.mask_import(Xd, cfg.levels, [z[f"protos{l}"] for l in range(1, L + 1)],
+                                [z[f"parents{l}"] for l in range(1, L + 1)], precision="bf16")
+            pk.mask_query_beams(ix, Qd, 10, (4, 24, 104))
+            torch.cuda.synchronize()
+            print("pmc workload: k-means++ index descent (4, 24, 104) done", flush=True)
+            # 21 k-means++ draws at the shape of every level (traffic per draw)
+            items = Xd
+            for lev, (C, k) in enumerate(cfg.levels):
+                pk.mask_kmeanspp(items, C, 21, seed=1, level=lev + 1)
+                torch.cuda.synchronize()
+                print(f"pmc workload: 21 k-means++ draws, level {lev + 1} done", flush=True)
+                items = torch.from_numpy(np.ascontiguousarray(z[f"protos{lev + 1}"])).cuda()
             ix.free()
         a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 1 GiB
         a.fill_(1.0)
