@@ -321,10 +321,35 @@ void run_level(const float* items, int64_t n_items, int ld, int dim, int C, int 
     if (w.precision == MASK_FP8_E4M3) kmeans_assign_fp8(ld, plan, protos, labels, w, s);
     else kmeans_assign(items, ld, dim, plan, protos, labels, w, metric, s);
   };
+  // A fixed point ends the iterations early with the same result: when no
+  // label changed since the previous iteration, the update reproduces the
+  // prototypes, and so does every later iteration.  Checked every fourth
+  // iteration (one host synchronisation each).
+  const bool watch = iters >= 2;
+  int32_t* prev = watch ? scratch.alloc<int32_t>(n_items) : nullptr;
+  uint32_t* changed = watch ? scratch.alloc<uint32_t>(iters) : nullptr;
   for (int t = 0; t < iters; ++t) {
     assign();
+    if (watch) {
+      if (t > 0) count_changed(labels, prev, n_items, changed + t, s);
+      MASK_HIP(hipMemcpyAsync(prev, labels, n_items * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                              s));
+    }
     kmeans_update(items, ld, dim, plan, labels, protos, w, metric,
                   inertia_log ? inertia_log + (int64_t)t * C : nullptr, s);
+    if (watch && t > 0 && t % 4 == 0 && t + 1 < iters) {
+      uint32_t h = 1;
+      MASK_HIP(hipMemcpyAsync(&h, changed + t, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      MASK_HIP(hipStreamSynchronize(s));
+      if (h == 0) {
+        // the inertia of every remaining iteration equals this one's
+        if (inertia_log)
+          for (int u = t + 1; u < iters; ++u)
+            MASK_HIP(hipMemcpyAsync(inertia_log + (int64_t)u * C, inertia_log + (int64_t)t * C,
+                                    C * sizeof(double), hipMemcpyDeviceToDevice, s));
+        break;
+      }
+    }
   }
   assign();
   if (refined) {

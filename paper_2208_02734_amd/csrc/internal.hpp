@@ -192,6 +192,9 @@ void row_norms(const float* x, int ld, int64_t n, float* out, hipStream_t s);
 void offsets_from_sorted(const uint32_t* keys, int64_t n, int64_t n_bins, uint32_t* off,
                          hipStream_t s);
 
+// *count (device) := the number of i with a[i] != b[i]
+void count_changed(const int32_t* a, const int32_t* b, int64_t n, uint32_t* count,
+                   hipStream_t s);
 // flag (device) := 1 when some a[i] lies outside [0, bound), else 0
 void check_range_i32(const int32_t* a, int64_t n, int64_t bound, uint32_t* flag,
                      hipStream_t s);

@@ -409,6 +409,24 @@ void check_range_i32(const int32_t* a, int64_t n, int64_t bound, uint32_t* flag,
   check_launch("check_range");
 }
 
+namespace {
+__global__ __launch_bounds__(kBlock) void k_count_changed(const int32_t* __restrict__ a,
+                                                          const int32_t* __restrict__ b,
+                                                          int64_t n, uint32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int c = __syncthreads_count(i < n && a[i] != b[i]);
+  if (threadIdx.x == 0 && c > 0) atomicAdd(count, (uint32_t)c);
+}
+}  // namespace
+
+void count_changed(const int32_t* a, const int32_t* b, int64_t n, uint32_t* count,
+                   hipStream_t s) {
+  MASK_HIP(hipMemsetAsync(count, 0, sizeof(uint32_t), s));
+  if (n <= 0) return;
+  k_count_changed<<<grid_for(n, kBlock), kBlock, 0, s>>>(a, b, n, count);
+  check_launch("count_changed");
+}
+
 void map_u32(const uint32_t* map, const uint32_t* in, int64_t n, uint32_t* out, hipStream_t s) {
   if (n <= 0) return;
   k_map_u32<<<grid_for(n, kBlock), kBlock, 0, s>>>(map, in, n, out);
