@@ -92,7 +92,8 @@ def traffic_bytes(kernel, beams=None, init=None):
 
 # beam candidates (top level first); every form takes the fastest one that
 # passes the recall gate
-BEAMS = [(4, 24, 96), (4, 32, 96), (4, 24, 104), (4, 32, 104), (4, 24, 112), (4, 32, 112),
+BEAMS = [(2, 16, 112), (3, 12, 104), (3, 16, 104), (3, 16, 112), (2, 16, 120),
+         (4, 24, 96), (4, 32, 96), (4, 24, 104), (4, 32, 104), (4, 24, 112), (4, 32, 112),
          (4, 32, 128), (4, 48, 128), (8, 64, 128), (8, 64, 144), (16, 64, 160), (16, 96, 160),
          (8, 96, 176), (12, 96, 176), (16, 80, 176), (16, 96, 176), (24, 96, 176),
          (24, 128, 192), (32, 128, 224), (64, 192, 256), (128, 256, 320), (256, 512, 512)]
