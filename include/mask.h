@@ -189,6 +189,27 @@ mask_status mask_query_beams(const mask_index* ix, const mask_matrix* q, int32_t
                              const int32_t* r_levels, int32_t* out_ids, float* out_dist,
                              void* hip_stream);
 
+/* mask_query_beams for an index in the BF16 form, with the small
+ * prototype levels (at most 16,384 prototypes; usually the top levels)
+ * screened for the whole batch at once: one BF16 MFMA GEMM per such level
+ * gives every query's squared distance to every prototype of the level, as
+ * |q|^2 + |c~|^2 - 2 q.c~ (c~ the BF16 row, q in FP32 split into two BF16
+ * terms, FP32 accumulation, clamped at 0), and the descent reads those
+ * instead of the rows.  Larger levels and the data layer are as in
+ * mask_query_beams.  workspace: device memory of workspace_bytes (256-byte
+ * aligned) that the call owns until it completes on hip_stream; queries are
+ * processed in slices that fit it (mask_screen_bytes gives the bytes per
+ * query; at least one query must fit).  Results are the screened distances'
+ * ranking, not bit-equal to mask_query_beams.  MASK_ERR_UNSUPPORTED for
+ * other forms.  Asynchronous; allocates nothing. */
+mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int32_t k,
+                                const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                                void* workspace, int64_t workspace_bytes, void* hip_stream);
+
+/* Workspace bytes per query of mask_query_screened (0 when nothing is
+ * screened). */
+mask_status mask_screen_bytes(const mask_index* ix, int64_t* bytes_per_query);
+
 /* Ragged batch: query i uses k_i[i] and r_i[i] (device int32[q->n], each in
  * [1, k_max] / [1, r_max]) and writes its k_i[i] results at out_ids +
  * out_off[i] / out_dist + out_off[i] (device int64[q->n]).  k_max, r_max <=

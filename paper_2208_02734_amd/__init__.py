@@ -85,7 +85,7 @@ _lib = None
 
 EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_beams", "mask_query_ragged",
             "mask_query_range", "mask_point_query", "mask_relocate", "mask_insert",
-            "mask_kmeanspp",
+            "mask_kmeanspp", "mask_query_screened", "mask_screen_bytes",
             "mask_query_debug", "mask_free",
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
             "mask_last_error", "mask_timing_enable", "mask_timing_report", "mask_clock",
@@ -115,6 +115,8 @@ def lib() -> ctypes.CDLL:
     L.mask_insert.argtypes = [VP, P(mask_matrix), I32, VP, P(I32), P(mask_allocator), VP]
     L.mask_kmeanspp.argtypes = [P(mask_matrix), I32, I32, ctypes.c_uint64, I32, VP, VP,
                                 P(mask_allocator), VP]
+    L.mask_query_screened.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP, I64, VP]
+    L.mask_screen_bytes.argtypes = [VP, P(I64)]
     L.mask_free.argtypes = [VP]
     L.mask_index_info.argtypes = [VP, P(mask_info)]
     L.mask_export_level.argtypes = [VP, I32, VP, VP]
@@ -384,6 +386,33 @@ def mask_query_beams(index: Index, queries, k: int, beams: Sequence[int], stream
     dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
     _check(lib().mask_query_beams(index.handle, ctypes.byref(m), k, b, ids.data_ptr(),
                                   dist.data_ptr(), _stream_handle(stream)))
+    return ids, dist
+
+
+def mask_screen_bytes(index: Index) -> int:
+    b = ctypes.c_int64()
+    _check(lib().mask_screen_bytes(index.handle, ctypes.byref(b)))
+    return b.value
+
+
+def mask_query_screened(index: Index, queries, k: int, beams: Sequence[int], workspace=None,
+                        stream=None):
+    """mask_query_beams with the small prototype levels screened by a BF16
+    GEMM (BF16 form); workspace: a CUDA tensor (allocated here for the whole
+    batch when None).  Returns (ids, dist) tensors of shape (nq, k)."""
+    torch = _torch()
+    m = _matrix(queries)
+    nq = queries.shape[0]
+    if workspace is None:
+        nbytes = max(256, mask_screen_bytes(index) * nq)
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=queries.device)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    r = (ctypes.c_int32 * len(beams))(*[int(b) for b in beams])
+    _check(lib().mask_query_screened(index.handle, ctypes.byref(m), int(k), r, ids.data_ptr(),
+                                     dist.data_ptr(), workspace.data_ptr(),
+                                     workspace.numel() * workspace.element_size(),
+                                     _stream_handle(stream)))
     return ids, dist
 
 

@@ -68,6 +68,10 @@ int bits_for(int64_t n) {
 }
 
 int round_up4(int d) { return (d + 3) & ~3; }
+
+// Prototype levels up to this size are screened by one BF16 GEMM per query
+// batch in mask_query_screened.
+constexpr int64_t kScreenMax = 16384;
 int bf16_stride(int ld) { return (ld + 7) & ~7; }
 
 // split() of Algorithm 1: n_chunks contiguous groups whose sizes differ by at
@@ -268,7 +272,8 @@ void finalize_layout(mask_index& ix, const std::vector<int32_t*>& labels,
     ix.ldb = bf16_stride(ld);
     for (int l = 0; l <= L; ++l) {
       ix.protos_b[l] = ix.mem.alloc<uint16_t>(ix.level_n[l] * ix.ldb);
-      quantize_bf16(ix.protos[l], ld, ix.level_n[l], ix.protos_b[l], ix.ldb, nullptr, s);
+      if (l >= 1) ix.norm_b[l] = ix.mem.alloc<float>(ix.level_n[l]);
+      quantize_bf16(ix.protos[l], ld, ix.level_n[l], ix.protos_b[l], ix.ldb, ix.norm_b[l], s);
     }
     ix.inv0 = ix.mem.alloc<int32_t>(ix.level_n[0]);
     scatter_iota(reinterpret_cast<const uint32_t*>(ix.orig[0]), ix.level_n[0],
@@ -703,6 +708,81 @@ mask_status mask_query_beams(const mask_index* ix, const mask_matrix* q, int32_t
                     hip_stream, r_levels);
 }
 
+mask_status mask_screen_bytes(const mask_index* ix, int64_t* bytes_per_query) {
+  if (!ix || !bytes_per_query) {
+    set_error("NULL argument");
+    return MASK_ERR_INVALID;
+  }
+  int64_t b = 0;
+  if (ix->precision == MASK_BF16 && !ix->sparse)
+    for (int l = 1; l <= ix->n_levels; ++l)
+      if (ix->level_n[l] <= kScreenMax) b += ix->level_n[l] * (int64_t)sizeof(float);
+  *bytes_per_query = b;
+  return MASK_OK;
+}
+
+mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int32_t k,
+                                const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                                void* workspace, int64_t workspace_bytes, void* hip_stream) {
+  try {
+    MASK_CHECK(ix != nullptr, "index is NULL");
+    if (ix->precision != MASK_BF16 || ix->sparse || ix->metric != MASK_L2)
+      throw Error{MASK_ERR_UNSUPPORTED, "screened descent: BF16 form of dense L2 data"};
+    check_dense(q, "queries");
+    MASK_CHECK(q->dim == ix->dim, "query dim differs from the index dim");
+    MASK_CHECK(r_levels != nullptr, "r_levels is NULL");
+    MASK_CHECK(k >= 1 && k <= kMaxBeam, "k must be in [1, 2048]");
+    MASK_CHECK(q->n < ((int64_t)1 << 31), "too many queries in one call");
+    const int L = ix->n_levels;
+    int rmax = 1;
+    for (int d = 0; d < L; ++d) {
+      MASK_CHECK(r_levels[d] >= 1 && r_levels[d] <= kMaxBeam, "beam must be in [1, 2048]");
+      rmax = std::max(rmax, r_levels[d]);
+    }
+    if (q->n == 0) return MASK_OK;
+    MASK_CHECK(out_ids && out_dist, "output pointer is NULL");
+    int64_t per_query = 0;
+    for (int l = 1; l <= L; ++l)
+      if (ix->level_n[l] <= kScreenMax) per_query += ix->level_n[l];
+    MASK_CHECK(workspace != nullptr || per_query == 0, "workspace is NULL");
+    MASK_CHECK(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
+    const int64_t slice =
+        per_query ? std::min<int64_t>(q->n, workspace_bytes / (per_query * (int64_t)sizeof(float)))
+                  : q->n;
+    MASK_CHECK(slice >= 1, "workspace smaller than one query's screened distances");
+    const int64_t step = std::min<int64_t>(slice, (int64_t)1 << 20);  // grid-size bound
+    hipStream_t s = (hipStream_t)hip_stream;
+    const DescentArgs da = descent_args(*ix);
+    const int ldq = ld_of(q);
+    for (int64_t s0 = 0; s0 < q->n; s0 += step) {
+      const int64_t len = std::min(step, q->n - s0);
+      const float* Qs = q->x + s0 * ldq;
+      QueryArgs qa{};
+      qa.Q = Qs;
+      qa.ldq = ldq;
+      qa.nq = len;
+      qa.k = k;
+      qa.r = rmax;
+      qa.out_ids = out_ids + s0 * k;
+      qa.out_dist = out_dist + s0 * k;
+      qa.rows = timing_row_counter();
+      for (int d = 0; d < L; ++d) qa.r_lev[L - d] = r_levels[d];
+      float* S = static_cast<float*>(workspace);
+      for (int l = 1; l <= L; ++l) {
+        if (ix->level_n[l] > kScreenMax) continue;
+        level_scores(Qs, ldq, len, ix->dim, ix->protos_b[l], ix->ldb, ix->level_n[l],
+                     ix->norm_b[l], S, s);
+        qa.scr[l] = S;
+        S += len * ix->level_n[l];
+      }
+      descent(da, qa, s);
+    }
+    return MASK_OK;
+  } catch (const Error& e) {
+    return fail(e);
+  }
+}
+
 mask_status mask_query_ragged(const mask_index* ix, const mask_matrix* q, const int32_t* k_i,
                               const int32_t* r_i, const int64_t* out_off, int32_t k_max,
                               int32_t r_max, int32_t* out_ids, float* out_dist,
@@ -871,7 +951,7 @@ mask_status mask_insert(mask_index* ix, const mask_matrix* points, int32_t max_l
       scatter_rows(protos_new, d_pos, slots.size(), ld, ix->protos[1], s);
       relabel(mem_ids, labels, M, d_groups, k0, par1, s);
       if (ix->precision == MASK_BF16)
-        quantize_bf16(ix->protos[1], ld, n1, ix->protos_b[1], ix->ldb, nullptr, s);
+        quantize_bf16(ix->protos[1], ld, n1, ix->protos_b[1], ix->ldb, ix->norm_b[1], s);
       *n_rebuilt = Cf;
     }
 

@@ -396,9 +396,20 @@ struct QueryArgs {
   // insertion descent: above level 1, prototypes without children are not
   // candidates
   bool skip_empty;
+  // screened levels (precision form): squared distances of every query of
+  // the launch to every prototype of the level, row-major (query, position);
+  // null = rows are read and compared in the descent
+  const float* scr[kMaxLevels + 1];
 };
 
 void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
+
+// Screening of one prototype level for a batch of queries on
+// v_mfma_f32_32x32x16_bf16: S[i * n + p] = max(0, |q_i|^2 + |c~_p|^2 -
+// 2 q_i . c~_p), c~ the BF16 rows (position order, stride ldb), pn their
+// FP32 squared norms, q_i FP32 (split into two BF16 terms).
+void level_scores(const float* Q, int ldq, int64_t nq, int dim, const uint16_t* protos_b,
+                  int ldb, int64_t n, const float* pn, float* S, hipStream_t s);
 
 // Exact-match scan of the point query: match[i] = lowest data row id under
 // level-1 prototype leaf[i] whose coordinates equal query i's, else -1.
@@ -474,6 +485,7 @@ struct mask_index {
   // device arrays; index 0 = data in leaf order
   float* protos[mask::kMaxLevels + 1] = {};
   uint16_t* protos_b[mask::kMaxLevels + 1] = {};  // BF16 copies (BF16 form)
+  float* norm_b[mask::kMaxLevels + 1] = {};       // their FP32 squared norms (levels >= 1)
   uint8_t* protos_q[mask::kMaxLevels + 1] = {};   // FP8 copies (FP8 form)
   float* scale_q[mask::kMaxLevels + 1] = {};
   int ldq = 0;

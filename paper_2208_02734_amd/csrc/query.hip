@@ -285,8 +285,10 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
 
   for (int lev = L; lev >= 0; --lev) {
     const LevelView V = a.lv[lev];
+    const float* scr = qa.scr[lev];
+    const int64_t sbase = qi * V.n;
     const uint32_t m = s_pre[n_par];
-    rows_seen += m;
+    if (scr == nullptr) rows_seen += m;  // rows read, not screened scores
     // the data layer of the BF16 form keeps an oversized set for the FP32 re-rank
     uint32_t want = (lev == 0) ? (uint32_t)k : (uint32_t)(qa.r_lev[lev] > 0 ? qa.r_lev[lev] : r);
     // rows read in BF16 at every level, or in FP8 at the data layer only:
@@ -314,6 +316,25 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
     for (uint32_t base = 0; base < m;) {
       const uint32_t len = (base == 0) ? first : round;
       const uint32_t end = (m - base < len) ? m : base + len;
+      if (scr != nullptr) {
+        // screened level: the distances were computed for the whole batch, so
+        // every lane takes candidates of its own (a binary search over the
+        // parents' prefix each)
+        for (uint32_t idx = base + tid; idx < end; idx += kBlock) {
+          int lo = 0, hi = n_par - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pre[mid] <= idx) lo = mid; else hi = mid - 1;
+          }
+          const int64_t p = (int64_t)s_beg[lo] + (idx - s_pre[lo]);
+          const uint64_t key = ((uint64_t)__float_as_uint(scr[sbase + p]) << 32) |
+                               (uint32_t)V.orig[p];
+          if (key < thr) {
+            const uint32_t slot = atomicAdd(&sh.cnt, 1u);
+            if (slot < (uint32_t)CAP) s_buf[slot] = key;  // rounds keep slot < CAP
+          }
+        }
+      } else {
       // Each lane group takes a contiguous chunk of kChunk candidates: one
       // binary search over the parents' prefix per chunk, then a forward walk.
       // chunk = ceil(rows / groups) rounded up to U, between U and 8U
@@ -524,6 +545,7 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
         }
       }
       }
+      }  // lane groups
       __syncthreads();
       const uint32_t cnt = sh.cnt < (uint32_t)CAP ? sh.cnt : (uint32_t)CAP;
       if (cnt > want) {
@@ -648,6 +670,99 @@ void launch2(const DescentArgs& a, const QueryArgs& qa, int need, hipStream_t s)
 }
 
 }  // namespace
+
+typedef __bf16 sbf16x8 __attribute__((ext_vector_type(8)));
+typedef float sfloatx16 __attribute__((ext_vector_type(16)));
+
+__device__ inline uint32_t bf16_rne_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// One wave per 32 queries and kTiles blocks of 32 prototypes, four waves per
+// workgroup on neighbouring prototype blocks.  MFMA k-slot (s, h, e) is
+// dimension 16 s + 8 h + e: lane l feeds query row l % 32 (as q = hi + lo,
+// two BF16 terms, converted once per wave and kept in registers) and
+// prototype row l % 32, 8 consecutive dimensions each; output register i of
+// lane l is query 8 (i / 4) + 4 (l / 32) + i % 4, prototype l % 32.
+constexpr int kScoreTiles = 4;
+
+template <int KS>
+__global__ __launch_bounds__(kBlock) void k_level_scores(
+    const float* __restrict__ Q, int ldq, int64_t nq, int dim, const uint16_t* __restrict__ P,
+    int ldb, int64_t n, const float* __restrict__ pn, float* __restrict__ S) {
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int64_t q0 = (int64_t)blockIdx.y * 32;
+  const int64_t pw = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * 32 * kScoreTiles;
+  if (pw >= n) return;  // uniform across the wave; the kernel has no barrier
+  const int r = lane % 32, h = lane / 32;
+  const bool qok = q0 + r < nq;
+  const float* qrow = Q + (qok ? q0 + r : 0) * (int64_t)ldq;
+  sbf16x8 a_hi[KS], a_lo[KS];
+  float qsq = 0.f;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int kk = 16 * ks + 8 * h;
+    uint32_t hw[4], lw[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c0 = kk + 2 * e, c1 = c0 + 1;
+      const float v0 = (qok && c0 < dim) ? qrow[c0] : 0.f;
+      const float v1 = (qok && c1 < dim) ? qrow[c1] : 0.f;
+      qsq = fmaf(v0, v0, qsq);
+      qsq = fmaf(v1, v1, qsq);
+      const uint32_t h0 = bf16_rne_bits(v0), h1 = bf16_rne_bits(v1);
+      const uint32_t l0 = bf16_rne_bits(v0 - __uint_as_float(h0 << 16));
+      const uint32_t l1 = bf16_rne_bits(v1 - __uint_as_float(h1 << 16));
+      hw[e] = h0 | (h1 << 16);
+      lw[e] = l0 | (l1 << 16);
+    }
+    __builtin_memcpy(&a_hi[ks], hw, sizeof(sbf16x8));
+    __builtin_memcpy(&a_lo[ks], lw, sizeof(sbf16x8));
+  }
+  qsq += __shfl_xor(qsq, 32);  // the two halves hold disjoint dimensions of row r
+  for (int t = 0; t < kScoreTiles; ++t) {
+    const int64_t p0 = pw + 32 * t;
+    if (p0 >= n) break;  // uniform across the wave
+    const bool pok = p0 + r < n;
+    const uint16_t* prow = P + (pok ? p0 + r : 0) * (int64_t)ldb;
+    sfloatx16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int kk = 16 * ks + 8 * h;
+      const uint4 bv = (pok && kk < ldb) ? *reinterpret_cast<const uint4*>(prow + kk)
+                                         : make_uint4(0u, 0u, 0u, 0u);
+      sbf16x8 b;
+      __builtin_memcpy(&b, &bv, sizeof(b));
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi[ks], b, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_lo[ks], b, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = 8 * (i / 4) + 4 * h + (i % 4);
+      const float qn = __shfl(qsq, row);
+      const int64_t qq = q0 + row, pp = p0 + r;
+      if (qq < nq && pp < n) S[qq * n + pp] = fmaxf(0.f, qn + pn[pp] - 2.f * acc[i]);
+    }
+  }
+}
+
+void level_scores(const float* Q, int ldq, int64_t nq, int dim, const uint16_t* protos_b,
+                  int ldb, int64_t n, const float* pn, float* S, hipStream_t s) {
+  if (nq <= 0 || n <= 0) return;
+  ScopedTiming timing("level_scores", s);
+  const int64_t per_block = (int64_t)(kBlock / kWave) * 32 * kScoreTiles;
+  const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)((nq + 31) / 32));
+  const int ks = (ldb + 15) / 16;
+  if (ks <= 1) k_level_scores<1><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S);
+  else if (ks <= 2) k_level_scores<2><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S);
+  else if (ks <= 4) k_level_scores<4><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S);
+  else if (ks <= 8) k_level_scores<8><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S);
+  else k_level_scores<16><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S);
+  check_launch("level_scores");
+}
 
 // One wave per query: lanes stride over the data rows of the leaf and
 // compare every coordinate; the wave keeps the lowest matching row id.

@@ -1,0 +1,100 @@
+"""The screened descent of the BF16 form: the small prototype levels are
+scored for the whole query batch by one BF16 MFMA GEMM, and the descent
+reads those scores.  It ranks the same BF16 prototypes as the gathered
+descent with another rounding (expanded form, query split into two BF16
+terms), so the two agree except at near-ties; slicing the batch to fit the
+workspace changes nothing."""
+import numpy as np
+import pytest
+
+import datagen
+from oracle import compare as oc
+from oracle import mask_oracle as mo
+from tests.gpu_helpers import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2208_02734_amd as pk
+    pk.lib()
+    return pk
+
+
+def _mixture(n, d, n_comp, seed, nq=0):
+    mix = datagen.mixture_params(seed, n_comp, d, sigma_mode="loguniform", sigma_low=0.1,
+                                 sigma_high=3.0)
+    X = datagen.sample_mixture(mix, n, seed + 1)
+    Q = datagen.sample_mixture(mix, nq, seed + 2) if nq else None
+    return X, Q
+
+
+@pytest.mark.parametrize("d", [128, 40, 7])
+def test_screened_agrees_with_the_gathered_descent(pk, d):
+    X, Q = _mixture(40_000, d, 80, seed=1100 + d, nq=600)
+    levels = [(20, 200), (1, 400), (1, 40)]  # 4,000 / 400 / 40 prototypes: levels 2 and 3 screened
+    gix = pk.mask_build(dev(X), levels, iters=6, seed=2, precision="bf16")
+    assert pk.mask_screen_bytes(gix) == 4 * (4000 + 400 + 40)
+    beams = [6, 24, 48]
+    i1, d1 = (host(t) for t in pk.mask_query_beams(gix, dev(Q), 10, beams))
+    i2, d2 = (host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, beams))
+    same = np.mean(np.all(i1 == i2, axis=1))
+    assert same >= 0.95, same
+    tids, tdist = mo.exact_knn(X, Q, 10)
+    r1 = oc.recall_at_k(i1.astype(np.int64), tids, tdist,
+                        oc.true_distances(X, Q, i1.astype(np.int64)), 10)
+    r2 = oc.recall_at_k(i2.astype(np.int64), tids, tdist,
+                        oc.true_distances(X, Q, i2.astype(np.int64)), 10)
+    assert abs(r1 - r2) <= 0.01, (r1, r2)
+    # the reported distances are the FP32 re-rank's, exact to FP32 rounding
+    true = oc.true_distances(X, Q, i2.astype(np.int64))
+    ok = i2 >= 0
+    np.testing.assert_allclose(d2[ok], true[ok], rtol=1e-5, atol=1e-6)
+    gix.free()
+
+
+def test_probe_all_screened_is_exact_knn(pk):
+    X, Q = _mixture(2000, 32, 10, seed=1110, nq=50)
+    gix = pk.mask_build(dev(X), [(2, 40), (1, 8)], iters=4, seed=1, precision="bf16",
+                        rerank_factor=256)
+    ids, dist = (host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, [2048, 2048]))
+    tids, tdist = mo.exact_knn(X, Q, 10)
+    true = oc.true_distances(X, Q, ids.astype(np.int64))
+    res = oc.check_knn(ids.astype(np.int64), dist, tids, tdist, true, 1e-5)
+    assert res.ok, res.messages
+    gix.free()
+
+
+def test_slices_change_nothing(pk):
+    import torch
+    X, Q = _mixture(20_000, 64, 40, seed=1120, nq=1000)
+    gix = pk.mask_build(dev(X), [(10, 100), (1, 80)], iters=5, seed=3, precision="bf16")
+    per = pk.mask_screen_bytes(gix)
+    big = torch.empty(per * 1000 + 256, dtype=torch.uint8, device="cuda")
+    small = torch.empty(per * 37, dtype=torch.uint8, device="cuda")  # 28 slices
+    a = [host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, [8, 16], workspace=big)]
+    b = [host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, [8, 16], workspace=small)]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    gix.free()
+
+
+def test_screened_arguments(pk):
+    import torch
+    X, Q = _mixture(3000, 16, 10, seed=1130, nq=10)
+    f32 = pk.mask_build(dev(X), [(2, 20)], iters=2, seed=1)
+    with pytest.raises(pk.MaskError) as e:
+        pk.mask_query_screened(f32, dev(Q), 5, [4])
+    assert e.value.status == 4
+    assert pk.mask_screen_bytes(f32) == 0
+    f32.free()
+    g = pk.mask_build(dev(X), [(2, 20)], iters=2, seed=1, precision="bf16")
+    tiny = torch.empty(256, dtype=torch.uint8, device="cuda")  # below one query (160 B fits)
+    ids, _ = pk.mask_query_screened(g, dev(Q), 5, [4], workspace=tiny)
+    with pytest.raises(pk.MaskError) as e:
+        pk.mask_query_screened(g, dev(Q), 5, [4],
+                               workspace=torch.empty(512, dtype=torch.uint8, device="cuda")[1:])
+    assert e.value.status == 1  # misaligned
+    g.free()
