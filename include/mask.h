@@ -206,8 +206,9 @@ mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int3
                                 const int32_t* r_levels, int32_t* out_ids, float* out_dist,
                                 void* workspace, int64_t workspace_bytes, void* hip_stream);
 
-/* Workspace bytes per query of mask_query_screened (0 when nothing is
- * screened). */
+/* Workspace bytes per query of mask_query_screened: 4 bytes per prototype
+ * of every screened level, each level's count rounded up to a multiple of
+ * 32 (0 when nothing is screened). */
 mask_status mask_screen_bytes(const mask_index* ix, int64_t* bytes_per_query);
 
 /* Ragged batch: query i uses k_i[i] and r_i[i] (device int32[q->n], each in

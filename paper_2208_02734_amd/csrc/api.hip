@@ -72,6 +72,8 @@ int round_up4(int d) { return (d + 3) & ~3; }
 // Prototype levels up to this size are screened by one BF16 GEMM per query
 // batch in mask_query_screened.
 constexpr int64_t kScreenMax = 16384;
+// score rows of a screened level start on 128-byte lines
+inline int64_t screen_ld(int64_t n) { return (n + 31) / 32 * 32; }
 int bf16_stride(int ld) { return (ld + 7) & ~7; }
 
 // split() of Algorithm 1: n_chunks contiguous groups whose sizes differ by at
@@ -716,7 +718,7 @@ mask_status mask_screen_bytes(const mask_index* ix, int64_t* bytes_per_query) {
   int64_t b = 0;
   if (ix->precision == MASK_BF16 && !ix->sparse)
     for (int l = 1; l <= ix->n_levels; ++l)
-      if (ix->level_n[l] <= kScreenMax) b += ix->level_n[l] * (int64_t)sizeof(float);
+      if (ix->level_n[l] <= kScreenMax) b += screen_ld(ix->level_n[l]) * (int64_t)sizeof(float);
   *bytes_per_query = b;
   return MASK_OK;
 }
@@ -743,7 +745,7 @@ mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int3
     MASK_CHECK(out_ids && out_dist, "output pointer is NULL");
     int64_t per_query = 0;
     for (int l = 1; l <= L; ++l)
-      if (ix->level_n[l] <= kScreenMax) per_query += ix->level_n[l];
+      if (ix->level_n[l] <= kScreenMax) per_query += screen_ld(ix->level_n[l]);
     MASK_CHECK(workspace != nullptr || per_query == 0, "workspace is NULL");
     MASK_CHECK(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
     const int64_t slice =
@@ -770,10 +772,12 @@ mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int3
       float* S = static_cast<float*>(workspace);
       for (int l = 1; l <= L; ++l) {
         if (ix->level_n[l] > kScreenMax) continue;
+        const int64_t ldS = screen_ld(ix->level_n[l]);
         level_scores(Qs, ldq, len, ix->dim, ix->protos_b[l], ix->ldb, ix->level_n[l],
-                     ix->norm_b[l], S, s);
+                     ix->norm_b[l], S, ldS, s);
         qa.scr[l] = S;
-        S += len * ix->level_n[l];
+        qa.scr_ld[l] = ldS;
+        S += len * ldS;
       }
       descent(da, qa, s);
     }

@@ -397,9 +397,11 @@ struct QueryArgs {
   // candidates
   bool skip_empty;
   // screened levels (precision form): squared distances of every query of
-  // the launch to every prototype of the level, row-major (query, position);
-  // null = rows are read and compared in the descent
+  // the launch to every prototype of the level, row-major (query, position)
+  // with rows scr_ld[level] floats apart; null = rows are read and compared
+  // in the descent
   const float* scr[kMaxLevels + 1];
+  int64_t scr_ld[kMaxLevels + 1];
 };
 
 void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
@@ -409,7 +411,7 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
 // 2 q_i . c~_p), c~ the BF16 rows (position order, stride ldb), pn their
 // FP32 squared norms, q_i FP32 (split into two BF16 terms).
 void level_scores(const float* Q, int ldq, int64_t nq, int dim, const uint16_t* protos_b,
-                  int ldb, int64_t n, const float* pn, float* S, hipStream_t s);
+                  int ldb, int64_t n, const float* pn, float* S, int64_t ldS, hipStream_t s);
 
 // Exact-match scan of the point query: match[i] = lowest data row id under
 // level-1 prototype leaf[i] whose coordinates equal query i's, else -1.

@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
   for (int lev = L; lev >= 0; --lev) {
     const LevelView V = a.lv[lev];
     const float* scr = qa.scr[lev];
-    const int64_t sbase = qi * V.n;
+    const int64_t sbase = qi * qa.scr_ld[lev];
     const uint32_t m = s_pre[n_par];
     if (scr == nullptr) rows_seen += m;  // rows read, not screened scores
     // the data layer of the BF16 form keeps an oversized set for the FP32 re-rank
@@ -687,10 +687,10 @@ __device__ inline uint32_t bf16_rne_bits(float f) {
 // lane l is query 8 (i / 4) + 4 (l / 32) + i % 4, prototype l % 32.
 constexpr int kScoreTiles = 4;
 
-template <int KS>
+template <int KS, bool V4>
 __global__ __launch_bounds__(kBlock) void k_level_scores(
     const float* __restrict__ Q, int ldq, int64_t nq, int dim, const uint16_t* __restrict__ P,
-    int ldb, int64_t n, const float* __restrict__ pn, float* __restrict__ S) {
+    int ldb, int64_t n, const float* __restrict__ pn, float* __restrict__ S, int64_t ldS) {
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int64_t q0 = (int64_t)blockIdx.y * 32;
   const int64_t pw = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * 32 * kScoreTiles;
@@ -704,11 +704,20 @@ __global__ __launch_bounds__(kBlock) void k_level_scores(
   for (int ks = 0; ks < KS; ++ks) {
     const int kk = 16 * ks + 8 * h;
     uint32_t hw[4], lw[4];
+    float v[8];
+    if constexpr (V4) {  // rows 16-byte aligned, dim a multiple of 8
+      const bool in = qok && kk < dim;
+      const float4 x0 = in ? *reinterpret_cast<const float4*>(qrow + kk) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 x1 = in ? *reinterpret_cast<const float4*>(qrow + kk + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+      v[0] = x0.x; v[1] = x0.y; v[2] = x0.z; v[3] = x0.w;
+      v[4] = x1.x; v[5] = x1.y; v[6] = x1.z; v[7] = x1.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (qok && kk + e < dim) ? qrow[kk + e] : 0.f;
+    }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int c0 = kk + 2 * e, c1 = c0 + 1;
-      const float v0 = (qok && c0 < dim) ? qrow[c0] : 0.f;
-      const float v1 = (qok && c1 < dim) ? qrow[c1] : 0.f;
+      const float v0 = v[2 * e], v1 = v[2 * e + 1];
       qsq = fmaf(v0, v0, qsq);
       qsq = fmaf(v1, v1, qsq);
       const uint32_t h0 = bf16_rne_bits(v0), h1 = bf16_rne_bits(v1);
@@ -744,23 +753,28 @@ __global__ __launch_bounds__(kBlock) void k_level_scores(
       const int row = 8 * (i / 4) + 4 * h + (i % 4);
       const float qn = __shfl(qsq, row);
       const int64_t qq = q0 + row, pp = p0 + r;
-      if (qq < nq && pp < n) S[qq * n + pp] = fmaxf(0.f, qn + pn[pp] - 2.f * acc[i]);
+      if (qq < nq && pp < n) S[qq * ldS + pp] = fmaxf(0.f, qn + pn[pp] - 2.f * acc[i]);
     }
   }
 }
 
 void level_scores(const float* Q, int ldq, int64_t nq, int dim, const uint16_t* protos_b,
-                  int ldb, int64_t n, const float* pn, float* S, hipStream_t s) {
+                  int ldb, int64_t n, const float* pn, float* S, int64_t ldS, hipStream_t s) {
   if (nq <= 0 || n <= 0) return;
   ScopedTiming timing("level_scores", s);
   const int64_t per_block = (int64_t)(kBlock / kWave) * 32 * kScoreTiles;
   const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)((nq + 31) / 32));
   const int ks = (ldb + 15) / 16;
-  if (ks <= 1) k_level_scores<1><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S);
-  else if (ks <= 2) k_level_scores<2><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S);
-  else if (ks <= 4) k_level_scores<4><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S);
-  else if (ks <= 8) k_level_scores<8><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S);
-  else k_level_scores<16><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S);
+  const bool v4 = dim % 8 == 0 && ldq % 4 == 0 && reinterpret_cast<uintptr_t>(Q) % 16 == 0;
+#define MASK_SCORES(K)                                                                     \
+  (v4 ? k_level_scores<K, true><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S, ldS) \
+      : k_level_scores<K, false><<<grid, kBlock, 0, s>>>(Q, ldq, nq, dim, protos_b, ldb, n, pn, S, ldS))
+  if (ks <= 1) MASK_SCORES(1);
+  else if (ks <= 2) MASK_SCORES(2);
+  else if (ks <= 4) MASK_SCORES(4);
+  else if (ks <= 8) MASK_SCORES(8);
+  else MASK_SCORES(16);
+#undef MASK_SCORES
   check_launch("level_scores");
 }
 
