@@ -49,7 +49,10 @@ PEAK_HBM_GBS = 8000.0
 # and writes WRITE_SIZE 1,048,576 KiB, so fetch counts are scaled by
 # 1048576/524318 and write counts by 1.  The figures hold for the kernel
 # source they were taken from (sha256 of the file) and, for the descent, for
-# its beams; otherwise traffic is reported as null.
+# its beams, index and method; otherwise traffic is reported as null.  The
+# k-means++ seeding is measured per level (its whole seeding under the
+# counters); the level-2 seeding, about 15,000 dispatches, stalls the counter
+# collection and has no entry.
 FETCH_SCALE = 1048576.0 / 524318.0
 WRITE_SCALE = 1.0
 TRAFFIC = [
@@ -59,23 +62,29 @@ TRAFFIC = [
     {"kernel": "assign_l2_mfma", "file": "kmeans.hip", "sha256": "c637a8614609f099d6bbf35e2655b7cea2591d2ff5af3282d1ec3ccabc319e06",
      "fetch_kib": (285132.2 + 37690.0 + 1521.3) / 3,
      "write_kib": (6403.0 + 978.7 + 20.5) / 3},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "ab6c38d9863649c15c158bc81df9050cb1f506768e2c2e1c632a621ffded5ee9", "init": "first",
-     "beams": [16, 96, 176], "fetch_kib": 6336056.4, "write_kib": 1250.0},
-    {"kernel": "descent", "file": "query.hip", "sha256": "ab6c38d9863649c15c158bc81df9050cb1f506768e2c2e1c632a621ffded5ee9", "init": "first",
-     "beams": [16, 96, 160], "fetch_kib": 13958789.2, "write_kib": 1250.0},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "ab6c38d9863649c15c158bc81df9050cb1f506768e2c2e1c632a621ffded5ee9", "init": "kmeans++",
-     "beams": [4, 24, 104], "fetch_kib": 2936033.6, "write_kib": 1250.0},
-    # per level: 21-draw runs at each level's shape, scaled to its k - 1
-    # updates and k picks
-    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "9c34ad05fb03c06a39009a3e818bac2de11b145dcadcb7bd6bcad75c07edaf80",
-     "fetch_kib": (253995810.5 + 127075434.8 + 129923.4) / 3,
-     "write_kib": (8354618.3 + 4152294.9 + 4164.7) / 3},
+    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "d4d21e15078100b9b1320f4e6e88f33be2448a056b7ac7557832317470bb0c80", "init": "first",
+     "beams": [16, 96, 176], "method": "gather", "fetch_kib": 6329357.1, "write_kib": 1250.0},
+    {"kernel": "descent", "file": "query.hip", "sha256": "d4d21e15078100b9b1320f4e6e88f33be2448a056b7ac7557832317470bb0c80", "init": "first",
+     "beams": [16, 96, 160], "method": "gather", "fetch_kib": 14017885.4, "write_kib": 1250.0},
+    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "d4d21e15078100b9b1320f4e6e88f33be2448a056b7ac7557832317470bb0c80", "init": "kmeans++",
+     "beams": [3, 12, 104], "method": "gather", "fetch_kib": 2937862.9, "write_kib": 1250.0},
+    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "d4d21e15078100b9b1320f4e6e88f33be2448a056b7ac7557832317470bb0c80", "init": "kmeans++",
+     "beams": [3, 12, 104], "method": "screened", "fetch_kib": 2855013.9, "write_kib": 1250.0},
+    # whole seedings of levels 1 and 3 (1,000 and 100 draws)
+    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "c7509e2fd33490f6c2e0ca7f3d305a09c3dc1f204ed2d6aa489c9143b0d48ad2",
+     "level": 1, "fetch_kib": 107834944.3, "write_kib": 1158482.4},
+    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "c7509e2fd33490f6c2e0ca7f3d305a09c3dc1f204ed2d6aa489c9143b0d48ad2",
+     "level": 3, "fetch_kib": 118307.9, "write_kib": 777.2},
+    # the two screened levels (5,000 and 100 prototypes, 10,000 queries)
+    {"kernel": "level_scores", "file": "query.hip", "sha256": "d4d21e15078100b9b1320f4e6e88f33be2448a056b7ac7557832317470bb0c80",
+     "fetch_kib": (31192.1 + 2713.0) / 2, "write_kib": (195312.5 + 4062.5) / 2},
 ]
 
 
-def traffic_bytes(kernel, beams=None, init=None):
+def traffic_bytes(kernel, beams=None, init=None, method=None, level=None):
     """Measured bytes per launch of `kernel`, or None when its source (or
-    the descent's beams or index) changed since the counters were taken."""
+    the descent's beams, index or method, or the seeding's level) changed
+    since the counters were taken or was not measured."""
     import hashlib
     for t in TRAFFIC:
         if t["kernel"] != kernel:
@@ -84,11 +93,20 @@ def traffic_bytes(kernel, beams=None, init=None):
             continue
         if "init" in t and init != t["init"]:
             continue
+        if "method" in t and method != t["method"]:
+            continue
+        if "level" in t and level != t["level"]:
+            continue
         path = os.path.join(ROOT, "paper_2208_02734_amd", "csrc", t["file"])
         if hashlib.sha256(open(path, "rb").read()).hexdigest() != t["sha256"]:
             return None
         return round((t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0)
     return None
+
+# beams of the k-means++ index's descents under the counters (the setting
+# the benchmark selects)
+PMC_PP_BEAMS = (3, 12, 104)
+
 
 # beam candidates (top level first); every form takes the fastest one that
 # passes the recall gate
@@ -123,6 +141,11 @@ def parse():
                     help="build the k-means++ BF16 index and save it (npz) for --pmc-index")
     ap.add_argument("--pmc-index", type=str, default="",
                     help="with --pmc-workload: the saved k-means++ index to import and query")
+    ap.add_argument("--pmc-seed-levels", type=str, default="1,3",
+                    help="with --pmc-workload --pmc-index: levels whose whole k-means++ "
+                         "seeding runs under the counters")
+    ap.add_argument("--pmc-no-builds", action="store_true",
+                    help="with --pmc-workload: skip the builds and descents")
     ap.add_argument("--pmc-workload", action="store_true",
                     help="run only the counter workload: one build (2 Lloyd iterations) and "
                          "one query batch per form, then a 1 GiB copy for calibration")
@@ -372,7 +395,8 @@ def main():
         # the counter-collection run is kept free of)
         cfg = datagen.config_scale()
         Xd = torch.from_numpy(cfg.X).cuda()
-        ix = pk.mask_build(Xd, cfg.levels, iters=2, seed=1, precision="bf16", init="kmeans++")
+        ix = pk.mask_build(Xd, cfg.levels, iters=args.iters, seed=1, precision="bf16",
+                           init="kmeans++")
         arrays = {}
         for lev in range(1, len(cfg.levels) + 1):
             P, par = ix.export_level(lev)
@@ -387,6 +411,8 @@ def main():
         Xd = torch.from_numpy(cfg.X).cuda()
         Qd = torch.from_numpy(cfg.Q).cuda()
         for prec, beams in (("bf16", (16, 96, 176)), ("fp32", (16, 96, 160))):
+            if args.pmc_no_builds:
+                break
             ix = pk.mask_build(Xd, cfg.levels, iters=2, seed=1, precision=prec)
             torch.cuda.synchronize()
             print(f"pmc workload: {prec} build done", flush=True)
@@ -395,21 +421,33 @@ def main():
             print(f"pmc workload: descent {beams} done", flush=True)
             ix.free()
         if args.pmc_index:
-            # the same k-means++ index, imported: the descent reads the same layout
+            # the benchmark's k-means++ index, imported: the descent reads the
+            # same layout
             z = np.load(args.pmc_index)
             L = len(cfg.levels)
             ix = pk.mask_import(Xd, cfg.levels, [z[f"protos{l}"] for l in range(1, L + 1)],
                                 [z[f"parents{l}"] for l in range(1, L + 1)], precision="bf16")
-            pk.mask_query_beams(ix, Qd, 10, (4, 24, 104))
-            torch.cuda.synchronize()
-            print("pmc workload: k-means++ index descent (4, 24, 104) done", flush=True)
-            # 21 k-means++ draws at the shape of every level (traffic per draw)
-            items = Xd
-            for lev, (C, k) in enumerate(cfg.levels):
-                pk.mask_kmeanspp(items, C, 21, seed=1, level=lev + 1)
+            if not args.pmc_no_builds:
+                pk.mask_query_beams(ix, Qd, 10, PMC_PP_BEAMS)
                 torch.cuda.synchronize()
-                print(f"pmc workload: 21 k-means++ draws, level {lev + 1} done", flush=True)
-                items = torch.from_numpy(np.ascontiguousarray(z[f"protos{lev + 1}"])).cuda()
+                print(f"pmc workload: k-means++ index descent {PMC_PP_BEAMS} done", flush=True)
+                ws = torch.empty(pk.mask_screen_bytes(ix) * Qd.shape[0], dtype=torch.uint8,
+                                 device="cuda")
+                pk.mask_query_screened(ix, Qd, 10, PMC_PP_BEAMS, workspace=ws)
+                torch.cuda.synchronize()
+                del ws
+                print(f"pmc workload: k-means++ index screened descent {PMC_PP_BEAMS} done",
+                      flush=True)
+            # whole k-means++ seedings at the shape of the chosen levels: the
+            # data (level 1) or the exported prototypes of the level below
+            for lev in [int(x) for x in args.pmc_seed_levels.split(",") if x]:
+                C, k = cfg.levels[lev - 1]
+                items = Xd if lev == 1 else torch.from_numpy(
+                    np.ascontiguousarray(z[f"protos{lev - 1}"])).cuda()
+                pk.mask_kmeanspp(items, C, k, seed=1, level=lev)
+                torch.cuda.synchronize()
+                print(f"pmc workload: k-means++ seeding, level {lev} ({C} x {k}) done",
+                      flush=True)
             ix.free()
         a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 1 GiB
         a.fill_(1.0)
@@ -549,32 +587,57 @@ def main():
     row_bytes = {"fp32": ((d + 3) // 4 * 4) * 4 + 4, "bf16": ((d + 7) // 8 * 8) * 2 + 4,
                  "fp8": ((d + 15) // 16 * 16) + 8}[prec]
     desc_gbs = rows * row_bytes / (d_ms * 1e-3) / 1e9 if d_ms else 0.0
-    # k-means++ seeding (one timing scope per level): every draw but the last
-    # reads each item row and reads and writes its D^2
-    ldp = (d + 3) // 4 * 4
-    pp_bytes_per_build, items = 0.0, n
-    for (C, k) in levels:
-        pp_bytes_per_build += (k - 1) * items * (4.0 * ldp + 16.0)
+    # k-means++ seeding, one timing scope per level.  Bytes: the rows the
+    # updates read (counted on the device: every row at draw 0, afterwards
+    # those the triangle inequality does not rule out) and the D^2 and
+    # prototype index written for each row whose D^2 fell (counted); at draws
+    # t >= 1 each member's D^2, prototype index and gathered prototype
+    # distance (20 B), and per group the t earlier prototypes and the new one
+    # read and t FP64 distances written.  Picks (a few KB each) are left out.
+    rb = 4.0 * ((d + 3) // 4 * 4)
+    pp_levels, items = [], n
+    for lev, (C, k) in enumerate(levels, start=1):
+        fixed = 0.0
+        if k > 2:
+            fixed = (k - 2) * items * 20.0
+            fixed += C * (rb * ((k - 1) * k / 2 - 1) + 8.0 * (k - 2) * (k - 1) / 2)
+        cnt, ms = kt.get(f"kmeanspp_level{lev}", (0, 0.0))
+        read = kt.get(f"seeding_rows_read_level{lev}", (0, 0.0))[0]
+        low = kt.get(f"seeding_rows_lowered_level{lev}", (0, 0.0))[0]
+        if cnt:
+            byts = fixed * cnt + read * rb + low * 12.0
+            gbs = byts / (ms * 1e-3) / 1e9
+            pp_levels.append({
+                "level": lev, "launches": cnt, "avg_ms": round(ms / cnt, 3),
+                "achieved": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
+                "algorithmic_bytes_per_launch": round(byts / cnt),
+                "rows_read_frac": round(read / (cnt * (k - 1) * items), 4) if k > 1 else None,
+                "traffic": traffic_bytes("kmeanspp", level=lev)})
         items = C * k
-    p_cnt, p_ms = kt.get("kmeanspp", (0, 0.0))
-    pp_gbs = pp_bytes_per_build * args.steps / (p_ms * 1e-3) / 1e9 if p_ms else 0.0
+    p_ms = sum(kt.get(f"kmeanspp_level{lev}", (0, 0.0))[1] for lev in range(1, len(levels) + 1))
     roof_assign = {"bound": "mfma", "kernel": akey, "achieved": round(assign_tflops, 2),
                    "peak": PEAK[prec], "unit": "TFLOP/s",
                    "frac": round(assign_tflops / PEAK[prec], 4),
                    "traffic": traffic_bytes(akey), "traffic_unit": "bytes per launch"}
     roof_pp = None
-    if p_ms:
-        roof_pp = {"bound": "hbm", "kernel": "kmeanspp", "achieved": round(pp_gbs, 1),
-                   "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(pp_gbs / PEAK_HBM_GBS, 4),
-                   "traffic": traffic_bytes("kmeanspp"),
-                   "traffic_unit": "bytes per launch (one level's seeding)"}
+    if pp_levels:
+        # the longest seeding launch (one level's seeding)
+        top = max(pp_levels, key=lambda e: e["avg_ms"])
+        roof_pp = {"bound": "hbm", "kernel": f"kmeanspp level {top['level']}",
+                   "achieved": top["achieved"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                   "frac": top["frac"],
+                   "algorithmic_bytes_per_launch": top["algorithmic_bytes_per_launch"],
+                   "rows_read_frac": top["rows_read_frac"], "traffic": top["traffic"],
+                   "traffic_unit": "bytes per launch (the level's whole seeding)",
+                   "levels": pp_levels}
     # the dominant kernel of the timed steps: the seeding when the selected
     # form starts from k-means++ seeds and it takes longer than the assignment
     roofline = roof_pp if (roof_pp and p_ms > a_ms) else roof_assign
     counters = ("descent_rows", "refine_small_points", "refine_full_points")
     kernels = {name: {"launches": c, "total_ms": round(ms, 3),
                       "avg_ms": round(ms / c, 4) if c else None}
-               for name, (c, ms) in kt.items() if name not in counters}
+               for name, (c, ms) in kt.items()
+               if name not in counters and not name.startswith("seeding_rows")}
 
     # ---- serving: the same request stream through both forms
     serving = None
@@ -681,11 +744,11 @@ def main():
         "roofline_query": {"bound": "hbm", "kernel": dkey, "achieved": round(desc_gbs, 1),
                            "peak": PEAK_HBM_GBS, "unit": "GB/s",
                            "frac": round(desc_gbs / PEAK_HBM_GBS, 4),
-                           "traffic": traffic_bytes(dkey, beams, init),
+                           "traffic": traffic_bytes(dkey, beams, init, method),
                            "traffic_unit": "bytes per launch",
-                           "traffic_gbs": (None if traffic_bytes(dkey, beams, init) is None
+                           "traffic_gbs": (None if traffic_bytes(dkey, beams, init, method) is None
                                            or not d_ms
-                                           else round(traffic_bytes(dkey, beams, init) * d_cnt
+                                           else round(traffic_bytes(dkey, beams, init, method) * d_cnt
                                                       / (d_ms * 1e-3) / 1e9, 1))},
         "forms": forms,
         "serving": serving,

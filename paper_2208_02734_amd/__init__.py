@@ -580,7 +580,10 @@ def mask_timing_enable(on: bool = True):
 def mask_timing_report() -> dict:
     """{kernel name: (launches, total milliseconds)} of the instrumented
     launches since timing was enabled; "descent_rows" counts the candidate
-    rows the descent evaluated."""
+    rows the descent evaluated; "kmeanspp_level<l>" times the k-means++
+    seeding of level l, and "seeding_rows_read_level<l>" and
+    "seeding_rows_lowered_level<l>" count the rows its updates read (not
+    ruled out by the triangle inequality) and those whose D^2 fell."""
     need = ctypes.c_int64()
     _check(lib().mask_timing_report(None, 0, ctypes.byref(need)))
     buf = ctypes.create_string_buffer(int(need.value) + 1)

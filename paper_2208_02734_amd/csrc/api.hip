@@ -22,8 +22,11 @@ struct TimingState {
   struct Rec { std::string name; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<std::pair<std::string, hipEvent_t>> open;  // started, not yet ended
-  unsigned long long* rows = nullptr;  // [0] descent rows, [1..2] refine counts
+  // [0] descent rows, [1..2] refine counts, [3 + 2 l] rows read and
+  // [4 + 2 l] D^2 lowered by the k-means++ updates of level slot l
+  unsigned long long* rows = nullptr;
 };
+constexpr int kCounters = 3 + 2 * kSeedSlots;
 TimingState& timing() {
   static TimingState t;
   return t;
@@ -57,6 +60,9 @@ void timing_record(const char* name, hipStream_t s, bool start) {
 unsigned long long* timing_row_counter() { return timing().on ? timing().rows : nullptr; }
 unsigned long long* timing_refine_counter() {
   return timing().on && timing().rows ? timing().rows + 1 : nullptr;
+}
+unsigned long long* timing_seed_counter(int slot) {
+  return timing().on && timing().rows ? timing().rows + 3 + 2 * slot : nullptr;
 }
 
 namespace {
@@ -516,8 +522,8 @@ mask_status mask_timing_enable(int32_t on) {
     for (auto& o : t.open) (void)hipEventDestroy(o.second);
     t.recs.clear();
     t.open.clear();
-    if (on && !t.rows) MASK_HIP(hipMalloc(&t.rows, 4 * sizeof(unsigned long long)));
-    if (t.rows) MASK_HIP(hipMemset(t.rows, 0, 4 * sizeof(unsigned long long)));
+    if (on && !t.rows) MASK_HIP(hipMalloc(&t.rows, kCounters * sizeof(unsigned long long)));
+    if (t.rows) MASK_HIP(hipMemset(t.rows, 0, kCounters * sizeof(unsigned long long)));
     t.on = on != 0;
     return MASK_OK;
   } catch (const Error& e) {
@@ -538,13 +544,18 @@ mask_status mask_timing_report(char* buf, int64_t cap, int64_t* needed) {
       a.first += 1;
       a.second += ms;
     }
-    unsigned long long cnt[4] = {0, 0, 0, 0};
+    unsigned long long cnt[kCounters] = {};
     if (t.rows) MASK_HIP(hipMemcpy(cnt, t.rows, sizeof(cnt), hipMemcpyDeviceToHost));
     std::ostringstream os;
     for (auto& kv : agg) os << kv.first << " " << kv.second.first << " " << kv.second.second << "\n";
     os << "descent_rows " << cnt[0] << " 0\n";
     os << "refine_small_points " << cnt[1] << " 0\n";
     os << "refine_full_points " << cnt[2] << " 0\n";
+    for (int l = 0; l < kSeedSlots; ++l) {
+      if (cnt[3 + 2 * l] == 0) continue;
+      os << "seeding_rows_read_level" << l << " " << cnt[3 + 2 * l] << " 0\n";
+      os << "seeding_rows_lowered_level" << l << " " << cnt[4 + 2 * l] << " 0\n";
+    }
     const std::string txt = os.str();
     if (needed) *needed = (int64_t)txt.size() + 1;
     if (buf && cap > 0) {

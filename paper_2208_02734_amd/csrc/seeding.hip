@@ -1,8 +1,11 @@
 // k-means++ seeding (Arthur and Vassilvitskii 2007; Section 3.1 names it as
 // the remedy for initial prototypes placed badly) for every group of a level
 // at once.  The k draws are sequential; each is two launches: a pick (one
-// wave per group) and a D^2 update over every row (one workgroup per tile of
-// consecutive members) that also sums D^2 per tile.
+// wave per group, with further workgroups that repeat it and compute the
+// distances of the new prototype to the group's earlier ones) and a D^2
+// update over the rows the triangle inequality cannot rule out (one
+// workgroup per tile of consecutive members) that also sums D^2 per tile.
+// The skip is exact: the D^2 values are those of reading every row.
 //
 // Draw t of group c uses u = the top 53 bits of the SplitMix64 output at
 // counter tag + c * k + t.  Draw 0 picks member floor(u * m); draw t > 0 picks
@@ -12,6 +15,8 @@
 // for draw 0.  The sums are taken in a fixed tree order (wave sums and
 // scans), so a pick can differ from a sequential running sum only when the
 // target lies within rounding of a member boundary.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace mask {
@@ -42,74 +47,128 @@ __device__ inline double wave_incl_scan(double v, int lane) {
   return v;
 }
 
-// The members of group c are cut into tiles of T_c consecutive members (T_c a
-// multiple of 64, at most kMaxTiles tiles per group); tiles of all groups are
-// numbered consecutively from tile_base[c].
+// The members of group c are cut into tiles of T_c consecutive members: a
+// multiple of 64, at least tmin and large enough for at most kMaxTiles tiles
+// per group.  Tiles of all groups are numbered consecutively from
+// tile_base[c]; tile b covers rows [tile_row[b], tile_row[b + 1]) of group
+// tile_grp[b].
 constexpr int kMaxTiles = 2048;
 
-__device__ inline int64_t tile_len(int64_t m) {
-  return (int64_t)kWave * ((m + (int64_t)kWave * kMaxTiles - 1) / ((int64_t)kWave * kMaxTiles));
+// Shortest tile: 256 members where one draw's rows take 64 MiB or more (the
+// update is bound by bytes, and a long tile keeps many rows in flight per
+// workgroup), else 128 (fewer, shorter round trips per draw).
+constexpr int64_t kLongTileBytes = (int64_t)64 << 20;
+
+__host__ __device__ inline int64_t tile_len(int64_t m, int tmin) {
+  const int64_t T =
+      (int64_t)kWave * ((m + (int64_t)kWave * kMaxTiles - 1) / ((int64_t)kWave * kMaxTiles));
+  return T > tmin ? T : tmin;
 }
 
-// Draw t of every group: one wave per group.  It totals the group's tile
-// sums, finds the first tile whose running sum passes the target and, inside
-// it, the first member, with wave scans.  The chosen row becomes prototype
-// c * k + t.  If rounding leaves the target unreached, the last member with
-// D^2 > 0 of the tile (or of the group) is taken.
-__global__ __launch_bounds__(kWave) void k_pp_pick(
-    const float* __restrict__ items, int ld, const int64_t* __restrict__ chunk_off,
-    const int64_t* __restrict__ tile_base, int k, int t, uint64_t seed, uint64_t tag,
-    const double* __restrict__ d2, const double* __restrict__ tsum,
-    float* __restrict__ protos, int32_t* __restrict__ chosen) {
-  const int c = blockIdx.x, lane = threadIdx.x;
+// Squared distance (FP64, direct form) of FP32 row x to FP32 row y: G lanes
+// per row, U float4 columns each in flight, a butterfly over the lane group.
+// Every lane of the group returns the same value; the order of the sums
+// depends only on (G, U, ld), so every kernel below gets the same bits for
+// the same pair.
+template <int G, int U>
+__device__ inline double row_d2(const float4* __restrict__ x, const float4* __restrict__ y,
+                                int ld4, int gl) {
+  double acc = 0.0;
+  for (int q0 = gl; q0 < ld4; q0 += G * U) {
+    float4 a[U], b[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int q = q0 + j * G;
+      a[j] = q < ld4 ? x[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+      b[j] = q < ld4 ? y[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const double e0 = (double)a[j].x - (double)b[j].x, e1 = (double)a[j].y - (double)b[j].y;
+      const double e2 = (double)a[j].z - (double)b[j].z, e3 = (double)a[j].w - (double)b[j].w;
+      acc = fma(e0, e0, acc);
+      acc = fma(e1, e1, acc);
+      acc = fma(e2, e2, acc);
+      acc = fma(e3, e3, acc);
+    }
+  }
+#pragma unroll
+  for (int o = G / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+  return acc;
+}
+
+// Draw t of group c, by one wave (lane = lane id): returns the item index
+// of the chosen member.  Lane l holds the sums of tiles l R .. l R + R - 1
+// (R = ceil(tiles / 64)); the lane totals, an inclusive wave scan of them and
+// one sequential pass in the lane whose range holds the target find the tile;
+// a wave scan of the tile's D^2 finds the member.  If rounding leaves the
+// target unreached, the last member with D^2 > 0 of that tile (or of the
+// group) is taken.  Deterministic: every wave that runs it gets the same
+// member.
+__device__ int64_t pp_pick(const int64_t* __restrict__ chunk_off,
+                           const int64_t* __restrict__ tile_base, int tmin, int k, int t,
+                           uint64_t seed, uint64_t tag, const double* __restrict__ d2,
+                           const double* __restrict__ tsum, int c, int lane) {
   const int64_t c0 = chunk_off[c], c1 = chunk_off[c + 1], m = c1 - c0;
   const double u = uniform01(seed, tag + (uint64_t)c * (uint64_t)k + (uint64_t)t);
-  const int64_t T = tile_len(m);
+  const int64_t T = tile_len(m, tmin);
   const int64_t tb = tile_base[c];
   const int nt = (int)(tile_base[c + 1] - tb);
   int64_t pick = -1;
   if (t > 0) {
-    // every tile sum of the group in registers: lane l holds tiles j * 64 + l
     constexpr int kRegs = kMaxTiles / kWave;
+    const int R = (nt + kWave - 1) / kWave;
     double v[kRegs];
+    double own = 0.0;
 #pragma unroll
     for (int j = 0; j < kRegs; ++j) {
-      const int b = j * kWave + lane;
-      v[j] = b < nt ? tsum[tb + b] : 0.0;
+      const int b = lane * R + j;
+      v[j] = (j < R && b < nt) ? tsum[tb + b] : 0.0;
+      own += v[j];
     }
-    double total = 0.0;
-#pragma unroll
-    for (int j = 0; j < kRegs; ++j) total += wave_sum(v[j]);
+    const double incl = wave_incl_scan(own, lane);
+    const double total = __shfl(incl, kWave - 1);
     if (total > 0.0) {
       const double target = u * total;
-      double run = 0.0;
-      int tile = -1;
+      const double up = __shfl_up(incl, 1);  // by every lane: a shuffle reads active lanes only
+      const double before = lane > 0 ? up : 0.0;
+      // every lane walks its own range; the hit lane's result is used
+      double run = before;
+      int j_hit = -1, j_pos = -1;
 #pragma unroll
       for (int j = 0; j < kRegs; ++j) {
-        const double incl = wave_incl_scan(v[j], lane);
-        const unsigned long long hit = __ballot(tile < 0 && run + incl > target);
-        const double excl = __shfl(incl - v[j], hit ? __ffsll((long long)hit) - 1 : 0);
-        const double last = __shfl(incl, kWave - 1);
-        if (tile < 0) {
-          if (hit) {
-            tile = j * kWave + __ffsll((long long)hit) - 1;
-            run += excl;
-          } else {
-            run += last;
+        if (j < R && lane * R + j < nt) {
+          if (j_hit < 0) {
+            if (run + v[j] > target) j_hit = j;
+            else run += v[j];
           }
+          if (v[j] > 0.0) j_pos = j;
         }
       }
+      const unsigned long long hit = __ballot(incl > target);
       int64_t lo = c0, hi = c1;  // where the fallback looks
-      if (tile >= 0) {
-        lo = c0 + (int64_t)tile * T;
-        hi = min(c1, lo + T);
+      bool scan = false;
+      if (hit) {
+        const int L = __ffsll((long long)hit) - 1;
+        const int jh = __shfl(j_hit, L), jp = __shfl(j_pos, L);
+        run = __shfl(run, L);
+        // jh < 0 only by rounding: then the last positive member of the
+        // lane's last positive tile, or of the group when it has none
+        if (jh >= 0 || jp >= 0) {
+          const int tile = L * R + (jh >= 0 ? jh : jp);
+          scan = jh >= 0;
+          lo = c0 + (int64_t)tile * T;
+          hi = min(c1, lo + T);
+        }
+      }
+      if (scan) {
         for (int64_t i0 = lo; i0 < hi && pick < 0; i0 += kWave) {
           const bool in = i0 + lane < hi;
           const double dv = in ? d2[i0 + lane] : 0.0;
-          const double incl = wave_incl_scan(dv, lane);
-          const unsigned long long hit = __ballot(in && run + incl > target);
-          if (hit) pick = i0 + (__ffsll((long long)hit) - 1) - c0;
-          else run += __shfl(incl, kWave - 1);
+          const double ci = wave_incl_scan(dv, lane);
+          const unsigned long long h = __ballot(in && run + ci > target);
+          if (h) pick = i0 + (__ffsll((long long)h) - 1) - c0;
+          else run += __shfl(ci, kWave - 1);
         }
       }
       for (int64_t i1 = hi; i1 > lo && pick < 0; i1 -= kWave) {
@@ -123,90 +182,205 @@ __global__ __launch_bounds__(kWave) void k_pp_pick(
     pick = (int64_t)(u * (double)m);
     if (pick >= m) pick = m - 1;
   }
-  const int64_t pi = c0 + pick;
-  const int64_t slot = (int64_t)c * k + t;
-  for (int q = lane; q < ld; q += kWave) protos[slot * ld + q] = items[pi * ld + q];
-  if (lane == 0 && chosen) chosen[slot] = (int32_t)pi;
+  return c0 + pick;
 }
 
-// D^2 after draw t, one workgroup per tile: G lanes per row (each with U
-// float4 columns in flight, FP64 accumulation, butterfly over the lane
-// group), 64 / G rows per wave and pass, the four waves on interleaved rows.
-// The tile's sum of D^2 is added in a fixed order: per row slot over the
-// passes, across the slots of a wave, then across the waves.
+// Draw t of every group, and the distances of the new prototype to the
+// group's earlier ones: cc[c * k + j] = |p_{c,j} - p_{c,t}|^2 for j < t when
+// the launch has more than one workgroup row.  Workgroup (c, 0) makes the
+// pick and copies the chosen row to prototype c * k + t; every workgroup
+// (c, y > 0) repeats the pick (the same member) and computes `passes` times
+// 4 * 64 / G of the distances against the chosen item row (equal to the
+// copy), G lanes per prototype.
+template <int G, int U>
+__global__ __launch_bounds__(kBlock) void k_pp_pick(
+    const float* __restrict__ items, int ld, const int64_t* __restrict__ chunk_off,
+    const int64_t* __restrict__ tile_base, int tmin, int k, int t, uint64_t seed, uint64_t tag,
+    const double* __restrict__ d2, const double* __restrict__ tsum,
+    float* __restrict__ protos, int32_t* __restrict__ chosen, double* __restrict__ cc,
+    int passes) {
+  constexpr int R = kWave / G;
+  __shared__ int64_t s_item;
+  const int c = blockIdx.x, lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  if (wave == 0) {
+    const int64_t pi = pp_pick(chunk_off, tile_base, tmin, k, t, seed, tag, d2, tsum, c, lane);
+    if (blockIdx.y == 0) {
+      const int64_t slot = (int64_t)c * k + t;
+      for (int q = lane; q < ld; q += kWave) protos[slot * ld + q] = items[pi * ld + q];
+      if (lane == 0 && chosen) chosen[slot] = (int32_t)pi;
+    }
+    if (lane == 0) s_item = pi;
+  }
+  if (blockIdx.y == 0) return;  // uniform across the workgroup
+  __syncthreads();
+  const int slot = lane / G, gl = lane % G;
+  const float4* y = reinterpret_cast<const float4*>(items + s_item * ld);
+  for (int ps = 0; ps < passes; ++ps) {
+    const int j = (((blockIdx.y - 1) * passes + ps) * (kBlock / kWave) + wave) * R + slot;
+    const bool live = j < t;
+    const float4* x =
+        reinterpret_cast<const float4*>(protos + ((int64_t)c * k + (live ? j : 0)) * ld);
+    const double acc = row_d2<G, U>(x, y, ld / 4, gl);
+    if (live && gl == 0) cc[(int64_t)c * k + j] = acc;
+  }
+}
+
+// D^2 after draw t, one workgroup per tile, in chunks of 256 members.  Rows
+// are skipped by the triangle inequality: near[i] is the prototype (index in
+// the group) at D^2 of row i, and when |p_near - p_t|^2 exceeds
+// 4 D^2 (1 + 1e-6), |x - p_t| > |x - p_near| holds with room to spare for
+// the rounding of both FP64 sums, so D^2 keeps its value exactly and the row
+// is not read.  A lane group of G lanes computes each remaining row's
+// distance (64 / G rows per wave and pass, the four waves on interleaved
+// rows) and hands the new D^2 to the chunk's thread of that member through
+// LDS; thread j adds members j, j + 256, ... of the tile in turn, then wave
+// sums and the four waves in order give the tile's sum.  Draw 0 reads every
+// row and sets near = 0.
 template <int G, int U>
 __global__ __launch_bounds__(kBlock) void k_pp_update(
-    const float* __restrict__ items, int ld, const int64_t* __restrict__ chunk_off,
-    const int64_t* __restrict__ tile_base, int n_chunks, int k, int t,
-    const float* __restrict__ protos, double* __restrict__ d2, double* __restrict__ tsum) {
+    const float* __restrict__ items, int ld, const int64_t* __restrict__ tile_row,
+    const int32_t* __restrict__ tile_grp, int k, int t, const float* __restrict__ protos,
+    const double* __restrict__ cc, double* __restrict__ d2, int32_t* __restrict__ near,
+    double* __restrict__ tsum, unsigned long long* __restrict__ tile_cnt) {
   constexpr int R = kWave / G;                 // rows per wave and pass
   constexpr int W = kBlock / kWave;            // waves per tile
   __shared__ double s_wave[W];
+  __shared__ double s_val[kBlock];
+  __shared__ int32_t s_rows[kBlock];
+  __shared__ int s_n, s_low;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int64_t tile = blockIdx.x;
-  int lo = 0, hi = n_chunks - 1;  // group of the tile
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tile_base[mid] <= tile) lo = mid;
-    else hi = mid - 1;
-  }
-  const int64_t c0 = chunk_off[lo], c1 = chunk_off[lo + 1];
-  const int64_t T = tile_len(c1 - c0);
-  const int64_t r0 = c0 + (tile - tile_base[lo]) * T, r1 = min(c1, r0 + T);
-  const float4* ctr = reinterpret_cast<const float4*>(protos + ((int64_t)lo * k + t) * ld);
+  const int grp = tile_grp[tile];
+  const int64_t r0 = tile_row[tile], r1 = tile_row[tile + 1];
+  const float4* ctr = reinterpret_cast<const float4*>(protos + ((int64_t)grp * k + t) * ld);
   const int ld4 = ld / 4, slot = lane / G, gl = lane % G;
-  double tile_acc = 0.0;
-  const int64_t first = r0 + wave * R + slot;
-  for (int64_t i = first; i - slot - wave * R < r1; i += (int64_t)R * W) {
-    const bool live = i < r1;
-    const float4* x = reinterpret_cast<const float4*>(items + (live ? i : r0) * ld);
-    double acc = 0.0;
-    for (int q0 = gl; q0 < ld4; q0 += G * U) {
-      float4 a[U], b[U];
-#pragma unroll
-      for (int j = 0; j < U; ++j) {
-        const int q = q0 + j * G;
-        a[j] = q < ld4 ? x[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-        b[j] = q < ld4 ? ctr[q] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
-#pragma unroll
-      for (int j = 0; j < U; ++j) {
-        const double e0 = (double)a[j].x - (double)b[j].x, e1 = (double)a[j].y - (double)b[j].y;
-        const double e2 = (double)a[j].z - (double)b[j].z, e3 = (double)a[j].w - (double)b[j].w;
-        acc = fma(e0, e0, acc);
-        acc = fma(e1, e1, acc);
-        acc = fma(e2, e2, acc);
-        acc = fma(e3, e3, acc);
+  double own = 0.0;
+  unsigned long long n_rows = 0, n_low = 0;  // thread 0 only
+  if (threadIdx.x == 0) s_low = 0;
+  for (int64_t b0 = r0; b0 < r1; b0 += kBlock) {
+    const int64_t i = b0 + threadIdx.x;
+    const bool mine = i < r1;
+    double cur = 0.0;
+    bool read = mine;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    if (mine && t > 0) {
+      cur = d2[i];
+      read = cc[(int64_t)grp * k + near[i]] <= 4.0 * cur * (1.0 + 1e-6);
+    }
+    if (read) s_rows[atomicAdd(&s_n, 1)] = threadIdx.x;
+    __syncthreads();
+    const int n_read = s_n;
+    n_rows += n_read;
+    for (int p0 = 0; p0 < n_read; p0 += R * W) {
+      const int p = p0 + wave * R + slot;
+      const bool live = p < n_read;
+      const int local = live ? s_rows[p] : 0;
+      const int64_t row = b0 + local;
+      const double acc = row_d2<G, U>(reinterpret_cast<const float4*>(items + row * ld), ctr,
+                                      ld4, gl);
+      if (live && gl == 0) {
+        const double old = t > 0 ? d2[row] : acc;
+        const bool lower = t == 0 || acc < old;
+        s_val[local] = lower ? acc : old;
+        if (lower) {
+          d2[row] = acc;
+          near[row] = t;
+          if (tile_cnt) atomicAdd(&s_low, 1);
+        }
       }
     }
-#pragma unroll
-    for (int o = G / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-    if (live) {
-      double v = acc;
-      if (t > 0) v = fmin(d2[i], acc);
-      if (gl == 0) d2[i] = v;
-      tile_acc += v;
-    }
+    __syncthreads();  // s_val complete
+    if (mine) own += read ? s_val[threadIdx.x] : cur;
+    __syncthreads();  // s_val and s_rows are reused
   }
-#pragma unroll
-  for (int o = kWave / 2; o >= G; o >>= 1) tile_acc += __shfl_xor(tile_acc, o);
-  if (lane == 0) s_wave[wave] = tile_acc;
+  own = wave_sum(own);
+  if (lane == 0) s_wave[wave] = own;
   __syncthreads();
   if (threadIdx.x == 0) {
     double sum = 0.0;
 #pragma unroll
     for (int w = 0; w < W; ++w) sum += s_wave[w];
     tsum[tile] = sum;
+    if (tile_cnt) {  // the tile's own slots: no other workgroup writes them
+      tile_cnt[2 * tile] += n_rows;
+      tile_cnt[2 * tile + 1] += (unsigned long long)s_low;
+    }
   }
 }
 
+// Adds the per-tile counts into the two timing counters (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_pp_count(const unsigned long long* __restrict__ tile_cnt,
+                                                     int64_t n_tiles,
+                                                     unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long s_sum[2][kBlock];
+  unsigned long long a = 0, b = 0;
+  for (int64_t i = threadIdx.x; i < n_tiles; i += kBlock) {
+    a += tile_cnt[2 * i];
+    b += tile_cnt[2 * i + 1];
+  }
+  s_sum[0][threadIdx.x] = a;
+  s_sum[1][threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = 1; j < kBlock; ++j) {
+      a += s_sum[0][j];
+      b += s_sum[1][j];
+    }
+    out[0] += a;
+    out[1] += b;
+  }
+}
+
+// Timing scope of one level's seeding: "kmeanspp_level<l>".
+const char* seed_scope_name(int slot) {
+  static const std::vector<std::string> names = [] {
+    std::vector<std::string> v;
+    for (int l = 0; l < kSeedSlots; ++l) v.push_back("kmeanspp_level" + std::to_string(l));
+    return v;
+  }();
+  return names[slot].c_str();
+}
+
+struct SeedBuffers {
+  const float* items;
+  int ld;
+  const ChunkPlan* plan;
+  const int64_t* tile_base;
+  const int64_t* tile_row;
+  const int32_t* tile_grp;
+  int tmin;
+  int64_t n_tiles;
+  float* protos;
+  double* d2;
+  double* tsum;
+  double* cc;
+  int32_t* near;
+  unsigned long long* tile_cnt;  // null unless timing is on
+};
+
+// Draw t: the pick (with the distances the update needs, unless it is the
+// last draw) and the D^2 update.
 template <int G, int U>
-void launch_update(const float* items, int ld, const ChunkPlan& plan, const int64_t* tile_base,
-                   int64_t n_tiles, int t, const float* protos, double* d2, double* tsum,
-                   hipStream_t s) {
-  k_pp_update<G, U><<<(unsigned)n_tiles, kBlock, 0, s>>>(items, ld, plan.d_off, tile_base,
-                                                         plan.n_chunks, plan.k, t, protos, d2,
-                                                         tsum);
+void launch_draw(const SeedBuffers& b, int t, uint64_t seed, uint64_t tag, int32_t* chosen,
+                 hipStream_t s) {
+  const ChunkPlan& p = *b.plan;
+  const bool last = t + 1 == p.k;
+  constexpr int per_pass = (kBlock / kWave) * (kWave / G);
+  // about 2,048 distance workgroups at most (each repeats the pick, and more
+  // would not be resident at once): several passes each when groups are many
+  const int need = (!last && t > 0) ? (t + per_pass - 1) / per_pass : 0;
+  const int cap = std::max(1, 2048 / std::max(1, p.n_chunks));
+  const int passes = need > cap ? (need + cap - 1) / cap : 1;
+  const int rows = (need + passes - 1) / passes;
+  const dim3 grid((unsigned)p.n_chunks, (unsigned)(1 + rows));
+  k_pp_pick<G, U><<<grid, kBlock, 0, s>>>(b.items, b.ld, p.d_off, b.tile_base, b.tmin, p.k, t,
+                                          seed, tag, b.d2, b.tsum, b.protos, chosen, b.cc,
+                                          passes);
+  if (last) return;
+  k_pp_update<G, U><<<(unsigned)b.n_tiles, kBlock, 0, s>>>(
+      b.items, b.ld, b.tile_row, b.tile_grp, p.k, t, b.protos, b.cc, b.d2, b.near, b.tsum,
+      b.tile_cnt);
 }
 
 }  // namespace
@@ -215,35 +389,62 @@ void kmeanspp_init(const float* items, int ld, int dim, const ChunkPlan& plan, u
                    int level, float* protos, int32_t* chosen, Arena& scratch, hipStream_t s) {
   (void)dim;  // rows are zero-padded to ld
   MASK_CHECK(ld <= kMaxDenseDim, "k-means++ seeding: dim above 256");
-  // tiles of every group (the same lengths as tile_len on the device)
-  std::vector<int64_t> base(plan.n_chunks + 1, 0);
+  const int tmin =
+      (int64_t)plan.n_items * ld * (int64_t)sizeof(float) >= kLongTileBytes ? 256 : 128;
+  std::vector<int64_t> base(plan.n_chunks + 1, 0), row;
+  std::vector<int32_t> grp;
   for (int c = 0; c < plan.n_chunks; ++c) {
-    const int64_t m = plan.off[c + 1] - plan.off[c];
-    const int64_t T = (int64_t)kWave * ((m + (int64_t)kWave * kMaxTiles - 1) /
-                                        ((int64_t)kWave * kMaxTiles));
-    base[c + 1] = base[c] + (m + T - 1) / T;
+    const int64_t c0 = plan.off[c], m = plan.off[c + 1] - c0, T = tile_len(m, tmin);
+    for (int64_t r = c0; r < c0 + m; r += T) {
+      row.push_back(r);
+      grp.push_back(c);
+    }
+    base[c + 1] = (int64_t)row.size();
   }
-  const int64_t n_tiles = base[plan.n_chunks];
-  int64_t* tile_base = scratch.alloc<int64_t>(plan.n_chunks + 1);
+  row.push_back(plan.n_items);
+  SeedBuffers b{};
+  b.items = items;
+  b.ld = ld;
+  b.plan = &plan;
+  b.n_tiles = base[plan.n_chunks];
+  b.protos = protos;
+  b.tmin = tmin;
+  int64_t* tile_base = scratch.alloc<int64_t>(base.size());
+  int64_t* tile_row = scratch.alloc<int64_t>(row.size());
+  int32_t* tile_grp = scratch.alloc<int32_t>(std::max<size_t>(grp.size(), 1));
   MASK_HIP(hipMemcpyAsync(tile_base, base.data(), base.size() * sizeof(int64_t),
                           hipMemcpyHostToDevice, s));
-  double* d2 = scratch.alloc<double>(plan.n_items);
-  double* tsum = scratch.alloc<double>(n_tiles);
-  ScopedTiming timing("kmeanspp", s);
+  MASK_HIP(hipMemcpyAsync(tile_row, row.data(), row.size() * sizeof(int64_t),
+                          hipMemcpyHostToDevice, s));
+  if (!grp.empty())
+    MASK_HIP(hipMemcpyAsync(tile_grp, grp.data(), grp.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+  b.tile_base = tile_base;
+  b.tile_row = tile_row;
+  b.tile_grp = tile_grp;
+  b.d2 = scratch.alloc<double>(plan.n_items);
+  b.tsum = scratch.alloc<double>(b.n_tiles);
+  b.cc = scratch.alloc<double>((size_t)plan.n_chunks * plan.k);
+  b.near = scratch.alloc<int32_t>(plan.n_items);
+  const int slot = std::min(std::max(level, 0), kSeedSlots - 1);
+  unsigned long long* counters = timing_seed_counter(slot);
+  if (counters) {
+    b.tile_cnt = scratch.alloc<unsigned long long>(2 * b.n_tiles);
+    MASK_HIP(hipMemsetAsync(b.tile_cnt, 0, 2 * b.n_tiles * sizeof(unsigned long long), s));
+  }
+  ScopedTiming timing(seed_scope_name(slot), s);
   const uint64_t tag = ((uint64_t)level << 40);
   const int f4 = ld / 4;
   for (int t = 0; t < plan.k; ++t) {
-    k_pp_pick<<<(unsigned)plan.n_chunks, kWave, 0, s>>>(items, ld, plan.d_off, tile_base, plan.k,
-                                                       t, seed, tag, d2, tsum, protos, chosen);
-    if (t + 1 == plan.k) break;  // the last draw needs no update
-    if (f4 <= 1) launch_update<1, 1>(items, ld, plan, tile_base, n_tiles, t, protos, d2, tsum, s);
-    else if (f4 <= 2) launch_update<2, 1>(items, ld, plan, tile_base, n_tiles, t, protos, d2, tsum, s);
-    else if (f4 <= 4) launch_update<4, 1>(items, ld, plan, tile_base, n_tiles, t, protos, d2, tsum, s);
-    else if (f4 <= 8) launch_update<8, 1>(items, ld, plan, tile_base, n_tiles, t, protos, d2, tsum, s);
-    else if (f4 <= 16) launch_update<8, 2>(items, ld, plan, tile_base, n_tiles, t, protos, d2, tsum, s);
-    else if (f4 <= 32) launch_update<8, 4>(items, ld, plan, tile_base, n_tiles, t, protos, d2, tsum, s);
-    else launch_update<16, 4>(items, ld, plan, tile_base, n_tiles, t, protos, d2, tsum, s);
+    if (f4 <= 1) launch_draw<1, 1>(b, t, seed, tag, chosen, s);
+    else if (f4 <= 2) launch_draw<2, 1>(b, t, seed, tag, chosen, s);
+    else if (f4 <= 4) launch_draw<4, 1>(b, t, seed, tag, chosen, s);
+    else if (f4 <= 8) launch_draw<8, 1>(b, t, seed, tag, chosen, s);
+    else if (f4 <= 16) launch_draw<8, 2>(b, t, seed, tag, chosen, s);
+    else if (f4 <= 32) launch_draw<8, 4>(b, t, seed, tag, chosen, s);
+    else launch_draw<16, 4>(b, t, seed, tag, chosen, s);
   }
+  if (counters) k_pp_count<<<1, kBlock, 0, s>>>(b.tile_cnt, b.n_tiles, counters);
   check_launch("kmeanspp");
 }
 

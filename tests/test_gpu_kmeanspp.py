@@ -153,3 +153,24 @@ def test_kmeanspp_on_given_groups_matches_oracle(pk):
         assert np.array_equal(par, oix.parents[lev - 1]), lev
         np.testing.assert_allclose(P, oix.protos[lev - 1], rtol=1e-5, atol=1e-4)
     gix.free()
+
+
+@pytest.mark.parametrize("d,m,C,k", [(128, 7_000, 20, 150), (7, 40_000, 55, 30)])
+def test_seeds_at_scale_match_oracle(pk, d, m, C, k):
+    # Levels whose rows take 64 MiB or more (longer tiles), on clustered data
+    # where the triangle inequality skips most rows after the first draws.
+    # Seeds of a group depend only on its members: the first two groups
+    # seeded on their own (a small level, shorter tiles) give the same picks;
+    # other tiles only regroup the FP64 sums, which could move a pick only at
+    # a rounding boundary, and none occurs here.  Every group matches the
+    # oracle.
+    X = _mixture(m * C, d, 60, seed=1200 + d)
+    ld = (d + 3) // 4 * 4
+    assert m * C * ld * 4 >= 64 << 20 and 2 * m * ld * 4 < 64 << 20
+    _, big = pk.mask_kmeanspp(dev(X), C, k, seed=31, level=1)
+    _, small = pk.mask_kmeanspp(dev(X[:2 * m]), 2, k, seed=31, level=1)
+    big, small = host(big), host(small)
+    assert np.array_equal(big[:2 * k], small)
+    for c in range(C):
+        pts = X[c * m:(c + 1) * m]
+        _compare(pts, big[c * k:(c + 1) * k] - c * m, 31, 1, c, k)
