@@ -199,16 +199,19 @@ mask_status mask_query_beams(const mask_index* ix, const mask_matrix* q, int32_t
  * mask_query_beams.  workspace: device memory of workspace_bytes (256-byte
  * aligned) that the call owns until it completes on hip_stream; queries are
  * processed in slices that fit it (mask_screen_bytes gives the bytes per
- * query; at least one query must fit).  Results are the screened distances'
- * ranking, not bit-equal to mask_query_beams.  MASK_ERR_UNSUPPORTED for
- * other forms.  Asynchronous; allocates nothing. */
+ * query; at least one query must fit).  The queries of a slice are
+ * launched in the order of their greedy path through the screened levels,
+ * so that queries in one subtree share the cache of one XCD; each query's
+ * result does not depend on that order.  Results are the screened
+ * distances' ranking, not bit-equal to mask_query_beams.
+ * MASK_ERR_UNSUPPORTED for other forms.  Asynchronous; allocates nothing. */
 mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int32_t k,
                                 const int32_t* r_levels, int32_t* out_ids, float* out_dist,
                                 void* workspace, int64_t workspace_bytes, void* hip_stream);
 
 /* Workspace bytes per query of mask_query_screened: 4 bytes per prototype
  * of every screened level, each level's count rounded up to a multiple of
- * 32 (0 when nothing is screened). */
+ * 32, plus 8 bytes for the launch order (0 when nothing is screened). */
 mask_status mask_screen_bytes(const mask_index* ix, int64_t* bytes_per_query);
 
 /* Ragged batch: query i uses k_i[i] and r_i[i] (device int32[q->n], each in

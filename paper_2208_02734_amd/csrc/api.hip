@@ -730,6 +730,7 @@ mask_status mask_screen_bytes(const mask_index* ix, int64_t* bytes_per_query) {
   if (ix->precision == MASK_BF16 && !ix->sparse)
     for (int l = 1; l <= ix->n_levels; ++l)
       if (ix->level_n[l] <= kScreenMax) b += screen_ld(ix->level_n[l]) * (int64_t)sizeof(float);
+  if (b) b += 8;  // the launch order: a key and a slot per query
   *bytes_per_query = b;
   return MASK_OK;
 }
@@ -759,9 +760,9 @@ mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int3
       if (ix->level_n[l] <= kScreenMax) per_query += screen_ld(ix->level_n[l]);
     MASK_CHECK(workspace != nullptr || per_query == 0, "workspace is NULL");
     MASK_CHECK(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
+    const int64_t query_bytes = per_query ? per_query * (int64_t)sizeof(float) + 8 : 0;
     const int64_t slice =
-        per_query ? std::min<int64_t>(q->n, workspace_bytes / (per_query * (int64_t)sizeof(float)))
-                  : q->n;
+        per_query ? std::min<int64_t>(q->n, workspace_bytes / query_bytes) : q->n;
     MASK_CHECK(slice >= 1, "workspace smaller than one query's screened distances");
     const int64_t step = std::min<int64_t>(slice, (int64_t)1 << 20);  // grid-size bound
     hipStream_t s = (hipStream_t)hip_stream;
@@ -780,7 +781,15 @@ mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int3
       qa.out_dist = out_dist + s0 * k;
       qa.rows = timing_row_counter();
       for (int d = 0; d < L; ++d) qa.r_lev[L - d] = r_levels[d];
+      // score rows of every screened level, then the launch order: queries
+      // near each other in the tree (by their greedy path through the
+      // screened levels) run together on one XCD
       float* S = static_cast<float*>(workspace);
+      int64_t rows = 0;
+      for (int l = 1; l <= L; ++l)
+        if (ix->level_n[l] <= kScreenMax) rows += screen_ld(ix->level_n[l]);
+      uint32_t* keys = reinterpret_cast<uint32_t*>(S + len * rows);
+      uint32_t* order = keys + len;
       for (int l = 1; l <= L; ++l) {
         if (ix->level_n[l] > kScreenMax) continue;
         const int64_t ldS = screen_ld(ix->level_n[l]);
@@ -789,6 +798,22 @@ mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int3
         qa.scr[l] = S;
         qa.scr_ld[l] = ldS;
         S += len * ldS;
+      }
+      if (qa.scr[L]) {  // the screened levels are the top ones
+        ScreenPath sp{};
+        sp.top = L;
+        sp.low = L;
+        while (sp.low > 1 && qa.scr[sp.low - 1]) --sp.low;
+        for (int l = sp.low; l <= L; ++l) {
+          sp.S[l] = qa.scr[l];
+          sp.ld[l] = qa.scr_ld[l];
+          sp.child_off[l] = ix->child_off[l];
+        }
+        sp.n_top = ix->level_n[L];
+        sp.n_low = ix->level_n[sp.low];
+        order_queries(sp, len, keys, order, s);
+        qa.order = order;
+        qa.per_xcd = (len + kXcds - 1) / kXcds;
       }
       descent(da, qa, s);
     }

@@ -406,7 +406,30 @@ struct QueryArgs {
   // in the descent
   const float* scr[kMaxLevels + 1];
   int64_t scr_ld[kMaxLevels + 1];
+  // launch order (null = workgroup b takes query b): workgroup b takes query
+  // order[(b % kXcds) * per_xcd + b / kXcds], so each XCD works through a
+  // contiguous run of `order`
+  const uint32_t* order;
+  int64_t per_xcd;
 };
+
+// XCDs of an MI355X; workgroups are dispatched to them round-robin
+constexpr int kXcds = 8;
+
+// Launch order of a query batch for the descent: queries sorted by the end
+// of their greedy path through the screened levels (top .. low, scores
+// S[l] with rows ld[l] apart, children of level l + 1's position p at
+// child_off[l + 1][p] ..), so queries in one subtree run together on one
+// XCD.  keys, order: device uint32[nq]; n_low <= 16384.
+struct ScreenPath {
+  const float* S[kMaxLevels + 1];
+  int64_t ld[kMaxLevels + 1];
+  const uint32_t* child_off[kMaxLevels + 1];
+  int top, low;
+  int64_t n_top, n_low;
+};
+void order_queries(const ScreenPath& sp, int64_t nq, uint32_t* keys, uint32_t* order,
+                   hipStream_t s);
 
 void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
 

@@ -206,7 +206,12 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
   __shared__ uint64_t s_red[8];
   __shared__ SelShared sh;
 
-  const int64_t qi = blockIdx.x;
+  int64_t qi = blockIdx.x;
+  if (qa.order) {
+    const int64_t pos = (int64_t)(blockIdx.x % kXcds) * qa.per_xcd + blockIdx.x / kXcds;
+    if (pos >= qa.nq) return;
+    qi = qa.order[pos];
+  }
   if (qi >= qa.nq) return;
   const int tid = threadIdx.x, lane = tid % kWave;
   const int ld = a.ld, ld4 = ld / 4, ldb = a.ldb;
@@ -655,12 +660,13 @@ __global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa)
 template <int TPR, int NV, int U, bool B16, int CAPB, int CAP, int MODE>
 void launch3(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   const size_t shm = (size_t)a.ld * sizeof(float);
+  const unsigned grid = (unsigned)(qa.order ? kXcds * qa.per_xcd : qa.nq);
   if constexpr (MODE != 0 || B16)  // CSR, FP8 and BF16 indexes are L2 only
-    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, MODE><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
+    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, MODE><<<grid, kBlock, shm, s>>>(a, qa);
   else if (a.metric == MASK_L2)
-    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, MODE><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
+    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, MODE><<<grid, kBlock, shm, s>>>(a, qa);
   else
-    k_descent<TPR, NV, U, 1, B16, CAPB, CAP, MODE><<<(unsigned)qa.nq, kBlock, shm, s>>>(a, qa);
+    k_descent<TPR, NV, U, 1, B16, CAPB, CAP, MODE><<<grid, kBlock, shm, s>>>(a, qa);
 }
 
 template <int TPR, int NV, int U, bool B16, int MODE = 0>
@@ -776,6 +782,96 @@ void level_scores(const float* Q, int ldq, int64_t nq, int dim, const uint16_t* 
   else MASK_SCORES(16);
 #undef MASK_SCORES
   check_launch("level_scores");
+}
+
+// The smallest score of row[lo .. hi) and its position (the lowest on
+// ties), by one wave.
+__device__ inline int64_t wave_argmin(const float* __restrict__ row, int64_t lo, int64_t hi,
+                                      int lane) {
+  float best = INFINITY;
+  int64_t at = hi;
+  for (int64_t p = lo + lane; p < hi; p += kWave) {
+    const float v = row[p];
+    if (v < best) {
+      best = v;
+      at = p;
+    }
+  }
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    const float ob = __shfl_xor(best, o);
+    const int64_t oa = __shfl_xor(at, o);
+    if (ob < best || (ob == best && oa < at)) {
+      best = ob;
+      at = oa;
+    }
+  }
+  return at < hi ? at : lo;
+}
+
+// Key of every query: the greedy path through the screened levels (the
+// nearest prototype of the top level, then the nearest of its children, down
+// to the lowest screened level), by its scores; one wave per query.
+__global__ __launch_bounds__(kBlock) void k_greedy_key(ScreenPath sp, int64_t nq,
+                                                       uint32_t* __restrict__ keys) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t q = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  if (q >= nq) return;  // uniform across the wave
+  int64_t p = wave_argmin(sp.S[sp.top] + q * sp.ld[sp.top], 0, sp.n_top, lane);
+  for (int l = sp.top - 1; l >= sp.low; --l) {
+    const int64_t lo = sp.child_off[l + 1][p], hi = sp.child_off[l + 1][p + 1];
+    p = hi > lo ? wave_argmin(sp.S[l] + q * sp.ld[l], lo, hi, lane) : lo;
+  }
+  if (lane == 0) keys[q] = (uint32_t)p;
+}
+
+// Counting sort of the queries by key (< n <= 16384) in one workgroup: an
+// LDS histogram, its exclusive scan, then every query takes the next slot of
+// its key.  The order within a key is not fixed; the descent's results do
+// not depend on it.
+constexpr int kOrderBlock = 1024;
+__global__ __launch_bounds__(kOrderBlock) void k_order_by_key(const uint32_t* __restrict__ keys,
+                                                              int64_t nq, int n,
+                                                              uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_cnt[16384];
+  __shared__ uint32_t s_part[kOrderBlock];
+  const int tid = threadIdx.x;
+  for (int j = tid; j < n; j += kOrderBlock) s_cnt[j] = 0;
+  __syncthreads();
+  for (int64_t q = tid; q < nq; q += kOrderBlock) atomicAdd(&s_cnt[min(keys[q], (uint32_t)n - 1)], 1u);
+  __syncthreads();
+  // exclusive scan: thread t owns keys [t * per, (t + 1) * per)
+  const int per = (n + kOrderBlock - 1) / kOrderBlock;
+  uint32_t sum = 0;
+  for (int j = tid * per; j < min(n, (tid + 1) * per); ++j) sum += s_cnt[j];
+  s_part[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < kOrderBlock; o <<= 1) {
+    const uint32_t v = tid >= o ? s_part[tid - o] : 0u;
+    __syncthreads();
+    s_part[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = s_part[tid] - sum;
+  for (int j = tid * per; j < min(n, (tid + 1) * per); ++j) {
+    const uint32_t c = s_cnt[j];
+    s_cnt[j] = run;
+    run += c;
+  }
+  __syncthreads();
+  for (int64_t q = tid; q < nq; q += kOrderBlock)
+    order[atomicAdd(&s_cnt[min(keys[q], (uint32_t)n - 1)], 1u)] = (uint32_t)q;
+}
+
+void order_queries(const ScreenPath& sp, int64_t nq, uint32_t* keys, uint32_t* order,
+                   hipStream_t s) {
+  if (nq <= 0) return;
+  const int64_t n_low = sp.n_low;
+  MASK_CHECK(n_low >= 1 && n_low <= 16384, "order_queries: level above 16384 prototypes");
+  ScopedTiming timing("order_queries", s);
+  k_greedy_key<<<(unsigned)((nq * kWave + kBlock - 1) / kBlock), kBlock, 0, s>>>(sp, nq, keys);
+  k_order_by_key<<<1, kOrderBlock, 0, s>>>(keys, nq, (int)n_low, order);
+  check_launch("order_queries");
 }
 
 // One wave per query: lanes stride over the data rows of the leaf and

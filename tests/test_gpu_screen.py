@@ -37,8 +37,9 @@ def test_screened_agrees_with_the_gathered_descent(pk, d):
     X, Q = _mixture(40_000, d, 80, seed=1100 + d, nq=600)
     levels = [(20, 200), (1, 400), (1, 40)]  # 4,000 / 400 / 40 prototypes: levels 2 and 3 screened
     gix = pk.mask_build(dev(X), levels, iters=6, seed=2, precision="bf16")
-    # score rows are padded to whole 128-byte lines (32 floats)
-    assert pk.mask_screen_bytes(gix) == 4 * (4000 + 416 + 64)
+    # score rows are padded to whole 128-byte lines (32 floats); 8 bytes per
+    # query hold the launch order
+    assert pk.mask_screen_bytes(gix) == 4 * (4000 + 416 + 64) + 8
     beams = [6, 24, 48]
     i1, d1 = (host(t) for t in pk.mask_query_beams(gix, dev(Q), 10, beams))
     i2, d2 = (host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, beams))
@@ -92,7 +93,8 @@ def test_screened_arguments(pk):
     assert pk.mask_screen_bytes(f32) == 0
     f32.free()
     g = pk.mask_build(dev(X), [(2, 20)], iters=2, seed=1, precision="bf16")
-    tiny = torch.empty(256, dtype=torch.uint8, device="cuda")  # one query: 40 scores padded to 64
+    # one query: 40 scores padded to 64, and its launch-order slots
+    tiny = torch.empty(4 * 64 + 8, dtype=torch.uint8, device="cuda")
     ids, _ = pk.mask_query_screened(g, dev(Q), 5, [4], workspace=tiny)
     with pytest.raises(pk.MaskError) as e:
         pk.mask_query_screened(g, dev(Q), 5, [4],
