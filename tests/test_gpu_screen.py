@@ -101,3 +101,20 @@ def test_screened_arguments(pk):
                                workspace=torch.empty(512, dtype=torch.uint8, device="cuda")[1:])
     assert e.value.status == 1  # misaligned
     g.free()
+
+
+def test_mixed_screened_and_gathered_levels(pk):
+    # level 1 has 20,000 prototypes (above the screening limit, gathered);
+    # levels 2 and 3 are screened, as in the benchmark's index
+    X, Q = _mixture(200_000, 16, 300, seed=1140, nq=400)
+    levels = [(20, 1000), (1, 200), (1, 20)]
+    gix = pk.mask_build(dev(X), levels, iters=3, seed=5, precision="bf16")
+    assert pk.mask_screen_bytes(gix) == 4 * (224 + 32) + 8
+    beams = [4, 16, 64]
+    i1, _ = (host(t) for t in pk.mask_query_beams(gix, dev(Q), 10, beams))
+    i2, d2 = (host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, beams))
+    assert np.mean(np.all(i1 == i2, axis=1)) >= 0.95
+    true = oc.true_distances(X, Q, i2.astype(np.int64))
+    ok = i2 >= 0
+    np.testing.assert_allclose(d2[ok], true[ok], rtol=1e-5, atol=1e-6)
+    gix.free()
