@@ -191,8 +191,13 @@ constexpr int kQList = 1024;
 //   MODE 0: dense rows; 1: CSR index (SP); 2: FP8 data rows with one FP32
 //   scale per row (the FP8 variant of the precision form: prototype levels
 //   in FP32, the data layer in FP8, re-ranked like BF16).
+// The BF16 class with rounds of 2,048 candidates is held to 102 VGPRs (a few
+// spill) so that five waves per SIMD fit, as its LDS allows: with the launch
+// order the descent is bound by latency, and the fifth wave is worth more
+// than the spills (measured on MI355X).
 template <int TPR, int NV, int U, int METRIC, bool B16, int CAPB, int CAP, int MODE>
-__global__ __launch_bounds__(kBlock) void k_descent(DescentArgs a, QueryArgs qa) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
+    B16 && CAP == 2048 ? 5 : 1))) void k_descent(DescentArgs a, QueryArgs qa) {
   constexpr bool SP = MODE == 1, F8 = MODE == 2, LOWP = B16 || F8;
   extern __shared__ float4 s_q4[];  // ld/4 float4
   __shared__ int32_t s_qc[SP ? kQList : 1];
@@ -671,7 +676,8 @@ void launch3(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
 
 template <int TPR, int NV, int U, bool B16, int MODE = 0>
 void launch2(const DescentArgs& a, const QueryArgs& qa, int need, hipStream_t s) {
-  if (need <= 512) launch3<TPR, NV, U, B16, 512, 2560, MODE>(a, qa, s);
+  if (B16 && MODE == 0 && need <= 512) launch3<TPR, NV, U, B16, 512, 2048, MODE>(a, qa, s);
+  else if (need <= 512) launch3<TPR, NV, U, B16, 512, 2560, MODE>(a, qa, s);
   else launch3<TPR, NV, U, B16, 2048, 4096, MODE>(a, qa, s);
 }
 
