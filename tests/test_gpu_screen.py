@@ -118,3 +118,19 @@ def test_mixed_screened_and_gathered_levels(pk):
     ok = i2 >= 0
     np.testing.assert_allclose(d2[ok], true[ok], rtol=1e-5, atol=1e-6)
     gix.free()
+
+
+def test_launch_order_changes_nothing(pk):
+    # the screened path launches queries in the order of their greedy paths;
+    # a permuted or partial batch must give every query the same result
+    X, Q = _mixture(30_000, 32, 60, seed=1150, nq=700)
+    gix = pk.mask_build(dev(X), [(15, 200), (1, 300), (1, 30)], iters=4, seed=6,
+                        precision="bf16")
+    beams = [4, 16, 48]
+    ids, dist = (host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, beams))
+    p = np.random.default_rng(3).permutation(700)
+    i2, d2 = (host(t) for t in pk.mask_query_screened(gix, dev(Q[p]), 10, beams))
+    assert np.array_equal(i2, ids[p]) and np.array_equal(d2, dist[p])
+    i3, d3 = (host(t) for t in pk.mask_query_screened(gix, dev(Q[100:137]), 10, beams))
+    assert np.array_equal(i3, ids[100:137]) and np.array_equal(d3, dist[100:137])
+    gix.free()
