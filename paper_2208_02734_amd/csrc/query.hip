@@ -691,23 +691,28 @@ __device__ inline uint32_t bf16_rne_bits(float f) {
   return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
-// One wave per 32 queries and kTiles blocks of 32 prototypes, four waves per
-// workgroup on neighbouring prototype blocks.  MFMA k-slot (s, h, e) is
+// A workgroup scores 128 queries (32 per wave) against kScoreTiles tiles of
+// 32 prototypes: each tile is staged once in LDS (rows padded by 16 bytes)
+// and read by all four waves, and every wave keeps its 32 queries' MFMA
+// fragments in registers across the tiles.  MFMA k-slot (s, h, e) is
 // dimension 16 s + 8 h + e: lane l feeds query row l % 32 (as q = hi + lo,
-// two BF16 terms, converted once per wave and kept in registers) and
-// prototype row l % 32, 8 consecutive dimensions each; output register i of
-// lane l is query 8 (i / 4) + 4 (l / 32) + i % 4, prototype l % 32.
-constexpr int kScoreTiles = 4;
+// two BF16 terms) and prototype row l % 32, 8 consecutive dimensions each;
+// output register i of lane l is query 8 (i / 4) + 4 (l / 32) + i % 4,
+// prototype l % 32.
+constexpr int kScoreTiles = 8;
+constexpr int kScoreLdsRow = 256 + 8;  // BF16 per staged row (dense dims <= 256)
 
 template <int KS, bool V4>
 __global__ __launch_bounds__(kBlock) void k_level_scores(
     const float* __restrict__ Q, int ldq, int64_t nq, int dim, const uint16_t* __restrict__ P,
     int ldb, int64_t n, const float* __restrict__ pn, float* __restrict__ S, int64_t ldS) {
+  __shared__ uint4 s_b4[32 * kScoreLdsRow / 8];
+  uint16_t* s_b = reinterpret_cast<uint16_t*>(s_b4);
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
-  const int64_t q0 = (int64_t)blockIdx.y * 32;
-  const int64_t pw = ((int64_t)blockIdx.x * (kBlock / kWave) + wave) * 32 * kScoreTiles;
-  if (pw >= n) return;  // uniform across the wave; the kernel has no barrier
+  const int64_t q0 = (int64_t)blockIdx.y * 128 + 32 * wave;
+  const int64_t pb = (int64_t)blockIdx.x * 32 * kScoreTiles;
   const int r = lane % 32, h = lane / 32;
+  const int row_ld = ldb + 8;  // staged row stride (BF16)
   const bool qok = q0 + r < nq;
   const float* qrow = Q + (qok ? q0 + r : 0) * (int64_t)ldq;
   sbf16x8 a_hi[KS], a_lo[KS];
@@ -742,19 +747,27 @@ __global__ __launch_bounds__(kBlock) void k_level_scores(
     __builtin_memcpy(&a_lo[ks], lw, sizeof(sbf16x8));
   }
   qsq += __shfl_xor(qsq, 32);  // the two halves hold disjoint dimensions of row r
+  const int c8 = ldb / 8;      // 16-byte chunks per prototype row
   for (int t = 0; t < kScoreTiles; ++t) {
-    const int64_t p0 = pw + 32 * t;
-    if (p0 >= n) break;  // uniform across the wave
-    const bool pok = p0 + r < n;
-    const uint16_t* prow = P + (pok ? p0 + r : 0) * (int64_t)ldb;
+    const int64_t p0 = pb + 32 * t;
+    if (p0 >= n) break;  // uniform across the workgroup
+    __syncthreads();     // the previous tile is no longer read
+    for (int c = threadIdx.x; c < 32 * c8; c += kBlock) {
+      const int row = c / c8, col = c % c8;
+      const uint4 v = p0 + row < n
+                          ? *reinterpret_cast<const uint4*>(P + (p0 + row) * (int64_t)ldb + 8 * col)
+                          : make_uint4(0u, 0u, 0u, 0u);
+      *reinterpret_cast<uint4*>(s_b + row * row_ld + 8 * col) = v;
+    }
+    __syncthreads();
     sfloatx16 acc;
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] = 0.f;
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       const int kk = 16 * ks + 8 * h;
-      const uint4 bv = (pok && kk < ldb) ? *reinterpret_cast<const uint4*>(prow + kk)
-                                         : make_uint4(0u, 0u, 0u, 0u);
+      const uint4 bv = kk < ldb ? *reinterpret_cast<const uint4*>(s_b + r * row_ld + kk)
+                                : make_uint4(0u, 0u, 0u, 0u);
       sbf16x8 b;
       __builtin_memcpy(&b, &bv, sizeof(b));
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi[ks], b, acc, 0, 0, 0);
@@ -774,8 +787,9 @@ void level_scores(const float* Q, int ldq, int64_t nq, int dim, const uint16_t* 
                   int ldb, int64_t n, const float* pn, float* S, int64_t ldS, hipStream_t s) {
   if (nq <= 0 || n <= 0) return;
   ScopedTiming timing("level_scores", s);
-  const int64_t per_block = (int64_t)(kBlock / kWave) * 32 * kScoreTiles;
-  const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)((nq + 31) / 32));
+  MASK_CHECK(ldb <= 256, "level_scores: rows above 256 dimensions");
+  const int64_t per_block = 32 * kScoreTiles;
+  const dim3 grid((unsigned)((n + per_block - 1) / per_block), (unsigned)((nq + 127) / 128));
   const int ks = (ldb + 15) / 16;
   const bool v4 = dim % 8 == 0 && ldq % 4 == 0 && reinterpret_cast<uintptr_t>(Q) % 16 == 0;
 #define MASK_SCORES(K)                                                                     \
