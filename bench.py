@@ -62,26 +62,26 @@ TRAFFIC = [
     {"kernel": "assign_l2_mfma", "file": "kmeans.hip", "sha256": "c637a8614609f099d6bbf35e2655b7cea2591d2ff5af3282d1ec3ccabc319e06",
      "fetch_kib": (285132.2 + 37690.0 + 1521.3) / 3,
      "write_kib": (6403.0 + 978.7 + 20.5) / 3},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "dd2e2880e9f2f281be1ad75bede8c52acc4adfeb7a0e82534dda9ed9e107919b", "init": "first",
-     "beams": [16, 96, 176], "method": "gather", "fetch_kib": 6402816.9, "write_kib": 71250.0},
-    {"kernel": "descent", "file": "query.hip", "sha256": "dd2e2880e9f2f281be1ad75bede8c52acc4adfeb7a0e82534dda9ed9e107919b", "init": "first",
-     "beams": [16, 96, 160], "method": "gather", "fetch_kib": 13986720.8, "write_kib": 1250.0},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "dd2e2880e9f2f281be1ad75bede8c52acc4adfeb7a0e82534dda9ed9e107919b", "init": "kmeans++",
-     "beams": [3, 12, 104], "method": "gather", "fetch_kib": 2988586.7, "write_kib": 71250.0},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "dd2e2880e9f2f281be1ad75bede8c52acc4adfeb7a0e82534dda9ed9e107919b", "init": "kmeans++",
-     "beams": [3, 12, 104], "method": "screened", "fetch_kib": 468873.1, "write_kib": 71253.4},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "dd2e2880e9f2f281be1ad75bede8c52acc4adfeb7a0e82534dda9ed9e107919b", "init": "kmeans++",
-     "beams": [3, 16, 104], "method": "gather", "fetch_kib": 3002369.2, "write_kib": 71250.0},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "dd2e2880e9f2f281be1ad75bede8c52acc4adfeb7a0e82534dda9ed9e107919b", "init": "kmeans++",
-     "beams": [3, 16, 104], "method": "screened", "fetch_kib": 474838.2, "write_kib": 71253.8},
+    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "first",
+     "beams": [16, 96, 176], "method": "gather", "fetch_kib": 6401036.5, "write_kib": 71250.0},
+    {"kernel": "descent", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "first",
+     "beams": [16, 96, 160], "method": "gather", "fetch_kib": 13981720.2, "write_kib": 1250.0},
+    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "kmeans++",
+     "beams": [3, 12, 104], "method": "gather", "fetch_kib": 2990589.6, "write_kib": 71250.0},
+    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "kmeans++",
+     "beams": [3, 12, 104], "method": "screened", "fetch_kib": 467356.0, "write_kib": 71254.4},
+    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "kmeans++",
+     "beams": [3, 16, 104], "method": "gather", "fetch_kib": 3001470.3, "write_kib": 71249.1},
+    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "kmeans++",
+     "beams": [3, 16, 104], "method": "screened", "fetch_kib": 470866.0, "write_kib": 71255.1},
     # whole seedings of levels 1 and 3 (1,000 and 100 draws)
     {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "320d963c19aac1f1b760321be4e34445ec422a86cfcd4cbc76a5ac1a9b8a3311",
-     "level": 1, "fetch_kib": 108341182.4, "write_kib": 1195706.9},
+     "level": 1, "fetch_kib": 108341134.8, "write_kib": 1196181.0},
     {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "320d963c19aac1f1b760321be4e34445ec422a86cfcd4cbc76a5ac1a9b8a3311",
      "level": 3, "fetch_kib": 119607.0, "write_kib": 814.7},
     # the two screened levels (5,000 and 100 prototypes, 10,000 queries)
-    {"kernel": "level_scores", "file": "query.hip", "sha256": "dd2e2880e9f2f281be1ad75bede8c52acc4adfeb7a0e82534dda9ed9e107919b",
-     "fetch_kib": (31221.4 + 2716.5) / 2, "write_kib": (195312.5 + 4062.5) / 2},
+    {"kernel": "level_scores", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811",
+     "fetch_kib": (23713.9 + 2672.5) / 2, "write_kib": (195312.5 + 4062.5) / 2},
 ]
 
 
