@@ -104,7 +104,8 @@ __device__ inline double row_d2(const float4* __restrict__ x, const float4* __re
 // a wave scan of the tile's D^2 finds the member.  If rounding leaves the
 // target unreached, the last member with D^2 > 0 of that tile (or of the
 // group) is taken.  Deterministic: every wave that runs it gets the same
-// member.
+// member.  NR >= R registers per lane hold the tile sums.
+template <int NR>
 __device__ int64_t pp_pick(const int64_t* __restrict__ chunk_off,
                            const int64_t* __restrict__ tile_base, int tmin, int k, int t,
                            uint64_t seed, uint64_t tag, const double* __restrict__ d2,
@@ -116,7 +117,7 @@ __device__ int64_t pp_pick(const int64_t* __restrict__ chunk_off,
   const int nt = (int)(tile_base[c + 1] - tb);
   int64_t pick = -1;
   if (t > 0) {
-    constexpr int kRegs = kMaxTiles / kWave;
+    constexpr int kRegs = NR;
     const int R = (nt + kWave - 1) / kWave;
     double v[kRegs];
     double own = 0.0;
@@ -192,7 +193,7 @@ __device__ int64_t pp_pick(const int64_t* __restrict__ chunk_off,
 // (c, y > 0) repeats the pick (the same member) and computes `passes` times
 // 4 * 64 / G of the distances against the chosen item row (equal to the
 // copy), G lanes per prototype.
-template <int G, int U>
+template <int G, int U, int NR>
 __global__ __launch_bounds__(kBlock) void k_pp_pick(
     const float* __restrict__ items, int ld, const int64_t* __restrict__ chunk_off,
     const int64_t* __restrict__ tile_base, int tmin, int k, int t, uint64_t seed, uint64_t tag,
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_pick(
   __shared__ int64_t s_item;
   const int c = blockIdx.x, lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   if (wave == 0) {
-    const int64_t pi = pp_pick(chunk_off, tile_base, tmin, k, t, seed, tag, d2, tsum, c, lane);
+    const int64_t pi = pp_pick<NR>(chunk_off, tile_base, tmin, k, t, seed, tag, d2, tsum, c, lane);
     if (blockIdx.y == 0) {
       const int64_t slot = (int64_t)c * k + t;
       for (int q = lane; q < ld; q += kWave) protos[slot * ld + q] = items[pi * ld + q];
@@ -357,6 +358,7 @@ struct SeedBuffers {
   double* cc;
   int32_t* near;
   unsigned long long* tile_cnt;  // null unless timing is on
+  int64_t max_tiles;             // tiles of the largest group
 };
 
 // Draw t: the pick (with the distances the update needs, unless it is the
@@ -374,9 +376,16 @@ void launch_draw(const SeedBuffers& b, int t, uint64_t seed, uint64_t tag, int32
   const int passes = need > cap ? (need + cap - 1) / cap : 1;
   const int rows = (need + passes - 1) / passes;
   const dim3 grid((unsigned)p.n_chunks, (unsigned)(1 + rows));
-  k_pp_pick<G, U><<<grid, kBlock, 0, s>>>(b.items, b.ld, p.d_off, b.tile_base, b.tmin, p.k, t,
-                                          seed, tag, b.d2, b.tsum, b.protos, chosen, b.cc,
-                                          passes);
+  // registers for the tile sums: the level's largest group (fewer registers,
+  // more workgroups resident)
+#define MASK_PICK(NR)                                                                       \
+  k_pp_pick<G, U, NR><<<grid, kBlock, 0, s>>>(b.items, b.ld, p.d_off, b.tile_base, b.tmin, \
+                                              p.k, t, seed, tag, b.d2, b.tsum, b.protos,   \
+                                              chosen, b.cc, passes)
+  if (b.max_tiles <= 8 * kWave) MASK_PICK(8);
+  else if (b.max_tiles <= 16 * kWave) MASK_PICK(16);
+  else MASK_PICK(kMaxTiles / kWave);
+#undef MASK_PICK
   if (last) return;
   k_pp_update<G, U><<<(unsigned)b.n_tiles, kBlock, 0, s>>>(
       b.items, b.ld, b.tile_row, b.tile_grp, p.k, t, b.protos, b.cc, b.d2, b.near, b.tsum,
@@ -407,6 +416,7 @@ void kmeanspp_init(const float* items, int ld, int dim, const ChunkPlan& plan, u
   b.ld = ld;
   b.plan = &plan;
   b.n_tiles = base[plan.n_chunks];
+  for (int c = 0; c < plan.n_chunks; ++c) b.max_tiles = std::max(b.max_tiles, base[c + 1] - base[c]);
   b.protos = protos;
   b.tmin = tmin;
   int64_t* tile_base = scratch.alloc<int64_t>(base.size());
