@@ -75,10 +75,10 @@ TRAFFIC = [
     {"kernel": "descent_bf16", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "kmeans++",
      "beams": [3, 16, 104], "method": "screened", "fetch_kib": 470866.0, "write_kib": 71255.1},
     # whole seedings of levels 1 and 3 (1,000 and 100 draws)
-    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "320d963c19aac1f1b760321be4e34445ec422a86cfcd4cbc76a5ac1a9b8a3311",
-     "level": 1, "fetch_kib": 108341134.8, "write_kib": 1196181.0},
-    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "320d963c19aac1f1b760321be4e34445ec422a86cfcd4cbc76a5ac1a9b8a3311",
-     "level": 3, "fetch_kib": 119607.0, "write_kib": 814.7},
+    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "eb63546fce591b126d05f4dc03504815980bf91d1f75d5386d1b47c33dc7444f",
+     "level": 1, "fetch_kib": 108292220.4, "write_kib": 898011.7},
+    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "eb63546fce591b126d05f4dc03504815980bf91d1f75d5386d1b47c33dc7444f",
+     "level": 3, "fetch_kib": 117529.2, "write_kib": 702.2},
     # the two screened levels (5,000 and 100 prototypes, 10,000 queries)
     {"kernel": "level_scores", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811",
      "fetch_kib": (23713.9 + 2672.5) / 2, "write_kib": (195312.5 + 4062.5) / 2},
