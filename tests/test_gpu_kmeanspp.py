@@ -174,3 +174,22 @@ def test_seeds_at_scale_match_oracle(pk, d, m, C, k):
     for c in range(C):
         pts = X[c * m:(c + 1) * m]
         _compare(pts, big[c * k:(c + 1) * k] - c * m, 31, 1, c, k)
+
+
+def test_seeding_row_counters(pk):
+    # the device counts behind the benchmark's seeding roofline: draw 0 reads
+    # and lowers every row; later draws read at most every row, and a row
+    # whose D^2 fell was read
+    X = _mixture(60_000, 32, 50, seed=1300)
+    C, k = 6, 40
+    pk.mask_timing_enable(True)
+    pk.mask_kmeanspp(dev(X), C, k, seed=2, level=1)
+    rep = pk.mask_timing_report()
+    pk.mask_timing_enable(False)
+    n = X.shape[0]
+    read = rep["seeding_rows_read_level1"][0]
+    low = rep["seeding_rows_lowered_level1"][0]
+    assert rep["kmeanspp_level1"][0] == 1
+    assert n <= low <= read <= (k - 1) * n
+    # clustered rows: the triangle inequality rules most of them out
+    assert read < 0.8 * (k - 1) * n
