@@ -209,6 +209,15 @@ mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int3
                                 const int32_t* r_levels, int32_t* out_ids, float* out_dist,
                                 void* workspace, int64_t workspace_bytes, void* hip_stream);
 
+/* mask_query_screened plus the prototypes kept at every level (as
+ * mask_query_beams_debug writes them: sel is device int32[q->n * n_levels *
+ * rmax], rmax the largest beam), so that the screened selections can be
+ * checked against distances computed elsewhere. */
+mask_status mask_query_screened_debug(const mask_index* ix, const mask_matrix* q, int32_t k,
+                                      const int32_t* r_levels, int32_t* out_ids,
+                                      float* out_dist, int32_t* sel, void* workspace,
+                                      int64_t workspace_bytes, void* hip_stream);
+
 /* Workspace bytes per query of mask_query_screened: 4 bytes per prototype
  * of every screened level, each level's count rounded up to a multiple of
  * 32, plus 8 bytes for the launch order (0 when nothing is screened). */
@@ -219,11 +228,21 @@ mask_status mask_screen_bytes(const mask_index* ix, int64_t* bytes_per_query);
  * out_off[i] / out_dist + out_off[i] (device int64[q->n]).  k_max, r_max <=
  * 2048 are host values bounding the per-query ones (they size the launch).
  * Otherwise as mask_query; each query's result equals what mask_query
- * returns for it alone with the same k and r. */
+ * returns for it alone with the same k and r (in the precision forms the
+ * re-rank cap C follows the query's own k_i and r_i). */
 mask_status mask_query_ragged(const mask_index* ix, const mask_matrix* q, const int32_t* k_i,
                               const int32_t* r_i, const int64_t* out_off, int32_t k_max,
                               int32_t r_max, int32_t* out_ids, float* out_dist,
                               void* hip_stream);
+
+/* mask_query_beams plus the prototypes kept at every level: sel is device
+ * int32[q->n * n_levels * rmax] (rmax the largest of r_levels), level-major
+ * from the top level down, each set of chunk-major prototype ids in no
+ * particular order, padded with -1.  Parity checks replay a descent on
+ * these selections (Algorithm 2, the per-level choice). */
+mask_status mask_query_beams_debug(const mask_index* ix, const mask_matrix* q, int32_t k,
+                                   const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                                   int32_t* sel, void* hip_stream);
 
 /* mask_query plus the prototypes kept at every level: sel is device
  * int32[q->n * n_levels * r], level-major from the top level down, each set

@@ -41,6 +41,12 @@ What it computes, by paper passage:
                          within the radius under them.
 * ``exact_knn``        - the k-nearest-neighbour query of the problem
                          statement (Section 1) by exhaustive search.
+* ``quantize_bf16``,
+  ``quantize_fp8``,
+  ``query_one_lowp``   - the precision form (not in the paper): the
+                         rounding of rows to bfloat16 or to OCP e4m3 with a
+                         per-row scale, and the descent on such rows with an
+                         oversized candidate set re-ranked on the full rows.
 
 Readings of silent or garbled passages (each one is listed in the design doc):
 the ranking key at every selection is (distance, original id), so ties go to
@@ -454,6 +460,106 @@ def query(index: OracleIndex, Q: np.ndarray, k: int, r: int):
     dist = np.empty((Q.shape[0], k), dtype=np.float64)
     for i in range(Q.shape[0]):
         ids[i], dist[i] = query_one(index, Q[i], k, r)
+    return ids, dist
+
+
+# --------------------------------------------------------------------------
+# Precision form (not in the paper): rows held in a low precision for the
+# descent, an oversized candidate set re-ranked on the full rows
+# --------------------------------------------------------------------------
+
+
+def quantize_bf16(X: np.ndarray) -> np.ndarray:
+    """Value of every float32 entry of X rounded to bfloat16 (8 significant
+    bits, round to nearest, ties to even), as float64.  Written from the
+    format's definition: the 16 low bits of the float32 encoding are
+    dropped after adding half of their weight, the half going up only when
+    the kept part is odd."""
+    x = np.ascontiguousarray(X, dtype=np.float32)
+    u = x.view(np.uint32).astype(np.uint64)
+    r = ((u + np.uint64(0x7FFF) + ((u >> np.uint64(16)) & np.uint64(1))) >> np.uint64(16)) \
+        << np.uint64(16)
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def round_e4m3(v: np.ndarray) -> np.ndarray:
+    """Nearest value of the OCP float8 e4m3 format (4 exponent bits with
+    bias 7, 3 mantissa bits, largest finite value 448, subnormal step 2^-9),
+    ties to even; inputs must lie in [-448, 448]."""
+    v = np.asarray(v, dtype=np.float64)
+    a = np.abs(v)
+    # spacing of the format at |v|: 2^(e-3) in the binade [2^e, 2^(e+1)),
+    # 2^-9 below the smallest normal 2^-6
+    e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+    step = np.where(a >= 2.0 ** -6, 2.0 ** (e - 3), 2.0 ** -9)
+    return np.sign(v) * np.round(a / step) * step  # np.round: half to even
+
+
+def quantize_fp8(X: np.ndarray):
+    """FP8 rows of the precision form: per row, m = max|x| and scale s =
+    m / 448 (1 for a zero row), both in float32; every entry x times the
+    float32 reciprocal 448 / m (rounded to float32), clamped to [-448, 448]
+    and rounded to e4m3.  Returns (codes as float64 values, s as float64);
+    the row is represented as s * code."""
+    x = np.asarray(X, dtype=np.float32)
+    m = np.abs(x).max(axis=1)
+    pos = m > 0
+    s = np.where(pos, (m / np.float32(448.0)).astype(np.float32), np.float32(1.0))
+    inv = np.where(pos, (np.float32(448.0) / np.where(pos, m, 1)).astype(np.float32),
+                   np.float32(1.0)).astype(np.float32)
+    v = (x * inv[:, None]).astype(np.float32)
+    v = np.clip(v, np.float32(-448.0), np.float32(448.0))
+    return round_e4m3(v), s.astype(np.float64)
+
+
+def rerank_size(k: int, beams: Sequence[int], factor: int) -> int:
+    """Size R of the candidate set the precision form re-ranks on the full
+    rows: factor * k, capped at 512 when k and every beam are at most 512,
+    else at 2048."""
+    cap = 512 if max([int(k)] + [int(b) for b in beams]) <= 512 else 2048
+    return min(int(factor) * int(k), cap)
+
+
+def query_one_lowp(index: OracleIndex, q: np.ndarray, k: int, r, rank_protos,
+                   leaf_rows: np.ndarray, factor: int, forced=None, trace: bool = False):
+    """Descent of the precision form for one query (L2).  At every
+    prototype level the ranking uses ``rank_protos[l]`` (the level's rows in
+    the precision the descent reads them in) instead of the prototypes
+    themselves; the children are those of the index.  At the data layer,
+    with m candidates and R = ``rerank_size(k, beams, factor)``: when m > R
+    and R > k, the R nearest by distance to ``leaf_rows`` (the data rows in
+    low precision, same row order as the data) are kept, ranked by (delta,
+    id), and ranked again by the distance to the full rows; otherwise every
+    candidate is ranked on the full rows.  Returns the k nearest as
+    ``query_one`` does.  ``forced`` replaces each level's selection (top
+    level first); ``trace`` also returns the leaf candidates, their
+    low-precision distances and R."""
+    L = index.n_levels
+    q64 = np.asarray(q, dtype=np.float64)[None, :]
+    kids = [index.children(l) for l in range(L)]
+    beams = [int(r)] * L if np.isscalar(r) else [int(x) for x in r]
+    cand = np.arange(index.protos[L - 1].shape[0], dtype=np.int64)
+    for l in range(L - 1, -1, -1):
+        d = pairwise(q64, np.asarray(rank_protos[l], dtype=np.float64)[cand], "l2")[0]
+        sel = cand[smallest(d, cand, beams[L - 1 - l])]
+        if forced is not None:
+            sel = np.asarray(forced[L - 1 - l], dtype=np.int64)
+        cand = (np.concatenate([kids[l][p] for p in sel]) if sel.size else
+                np.zeros(0, dtype=np.int64))
+    R = rerank_size(k, beams, factor)
+    d_low = (pairwise(q64, np.asarray(leaf_rows, dtype=np.float64)[cand], "l2")[0]
+             if cand.size else np.zeros(0))
+    pool = cand
+    if cand.size > R and R > k:
+        pool = cand[smallest(d_low, cand, R)]
+    d = pairwise(q64, index.data[pool], "l2")[0] if pool.size else np.zeros(0)
+    pos = smallest(d, pool, k)
+    ids = np.full(k, -1, dtype=np.int64)
+    dist = np.full(k, np.inf, dtype=np.float64)
+    ids[:pos.size] = pool[pos]
+    dist[:pos.size] = np.sqrt(d[pos])
+    if trace:
+        return ids, dist, (cand, d_low, R)
     return ids, dist
 
 

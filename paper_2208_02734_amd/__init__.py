@@ -85,7 +85,8 @@ _lib = None
 
 EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_beams", "mask_query_ragged",
             "mask_query_range", "mask_point_query", "mask_relocate", "mask_insert",
-            "mask_kmeanspp", "mask_query_screened", "mask_screen_bytes",
+            "mask_kmeanspp", "mask_query_screened", "mask_query_screened_debug",
+            "mask_query_beams_debug", "mask_screen_bytes",
             "mask_query_debug", "mask_free",
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
             "mask_last_error", "mask_timing_enable", "mask_timing_report", "mask_clock",
@@ -116,6 +117,9 @@ def lib() -> ctypes.CDLL:
     L.mask_kmeanspp.argtypes = [P(mask_matrix), I32, I32, ctypes.c_uint64, I32, VP, VP,
                                 P(mask_allocator), VP]
     L.mask_query_screened.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP, I64, VP]
+    L.mask_query_screened_debug.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP, VP, I64,
+                                            VP]
+    L.mask_query_beams_debug.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP, VP]
     L.mask_screen_bytes.argtypes = [VP, P(I64)]
     L.mask_free.argtypes = [VP]
     L.mask_index_info.argtypes = [VP, P(mask_info)]
@@ -375,15 +379,24 @@ def mask_query(index: Index, queries, k: int, r: int, stream=None, debug: bool =
     return ids, dist
 
 
-def mask_query_beams(index: Index, queries, k: int, beams: Sequence[int], stream=None):
+def mask_query_beams(index: Index, queries, k: int, beams: Sequence[int], stream=None,
+                     debug: bool = False):
     """Descent keeping beams[i] prototypes at level i counted from the top;
-    returns (ids, dist) like mask_query."""
+    returns (ids, dist) like mask_query, plus the kept prototypes per level
+    (nq, n_levels, max(beams)) when ``debug``."""
     torch = _torch()
     m = _matrix(queries)
     nq = queries.shape[0]
     b = (ctypes.c_int32 * len(beams))(*[int(x) for x in beams])
     ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
     dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    if debug:
+        sel = torch.empty((nq, len(beams), max(int(x) for x in beams)), dtype=torch.int32,
+                          device=queries.device)
+        _check(lib().mask_query_beams_debug(index.handle, ctypes.byref(m), k, b,
+                                            ids.data_ptr(), dist.data_ptr(), sel.data_ptr(),
+                                            _stream_handle(stream)))
+        return ids, dist, sel
     _check(lib().mask_query_beams(index.handle, ctypes.byref(m), k, b, ids.data_ptr(),
                                   dist.data_ptr(), _stream_handle(stream)))
     return ids, dist
@@ -396,10 +409,11 @@ def mask_screen_bytes(index: Index) -> int:
 
 
 def mask_query_screened(index: Index, queries, k: int, beams: Sequence[int], workspace=None,
-                        stream=None):
+                        stream=None, debug: bool = False):
     """mask_query_beams with the small prototype levels screened by a BF16
     GEMM (BF16 form); workspace: a CUDA tensor (allocated here for the whole
-    batch when None).  Returns (ids, dist) tensors of shape (nq, k)."""
+    batch when None).  Returns (ids, dist) tensors of shape (nq, k), plus the
+    kept prototypes per level (nq, n_levels, max(beams)) when ``debug``."""
     torch = _torch()
     m = _matrix(queries)
     nq = queries.shape[0]
@@ -409,9 +423,17 @@ def mask_query_screened(index: Index, queries, k: int, beams: Sequence[int], wor
     ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
     dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
     r = (ctypes.c_int32 * len(beams))(*[int(b) for b in beams])
+    ws_bytes = workspace.numel() * workspace.element_size()
+    if debug:
+        sel = torch.empty((nq, len(beams), max(int(x) for x in beams)), dtype=torch.int32,
+                          device=queries.device)
+        _check(lib().mask_query_screened_debug(index.handle, ctypes.byref(m), int(k), r,
+                                               ids.data_ptr(), dist.data_ptr(), sel.data_ptr(),
+                                               workspace.data_ptr(), ws_bytes,
+                                               _stream_handle(stream)))
+        return ids, dist, sel
     _check(lib().mask_query_screened(index.handle, ctypes.byref(m), int(k), r, ids.data_ptr(),
-                                     dist.data_ptr(), workspace.data_ptr(),
-                                     workspace.numel() * workspace.element_size(),
+                                     dist.data_ptr(), workspace.data_ptr(), ws_bytes,
                                      _stream_handle(stream)))
     return ids, dist
 

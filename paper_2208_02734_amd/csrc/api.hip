@@ -492,7 +492,6 @@ mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, in
     }
     for (int l = 0; l <= kMaxLevels; ++l) qa.r_lev[l] = 0;
     if (r_levels) {
-      MASK_CHECK(!sel, "per-level beams are not combined with the debug selections");
       for (int d = 0; d < ix->n_levels; ++d) {
         MASK_CHECK(r_levels[d] >= 1 && r_levels[d] <= kMaxBeam, "beam must be in [1, 2048]");
         qa.r_lev[ix->n_levels - d] = r_levels[d];
@@ -735,9 +734,17 @@ mask_status mask_screen_bytes(const mask_index* ix, int64_t* bytes_per_query) {
   return MASK_OK;
 }
 
-mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int32_t k,
-                                const int32_t* r_levels, int32_t* out_ids, float* out_dist,
-                                void* workspace, int64_t workspace_bytes, void* hip_stream) {
+}  // extern "C"
+
+namespace mask {
+namespace {
+
+// mask_query_screened, with the per-level selections written to sel when it
+// is not NULL (int32[q->n * n_levels * rmax], as mask_query_beams_debug).
+mask_status screened_impl(const mask_index* ix, const mask_matrix* q, int32_t k,
+                          const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                          int32_t* sel, void* workspace, int64_t workspace_bytes,
+                          void* hip_stream) {
   try {
     MASK_CHECK(ix != nullptr, "index is NULL");
     if (ix->precision != MASK_BF16 || ix->sparse || ix->metric != MASK_L2)
@@ -779,6 +786,7 @@ mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int3
       qa.r = rmax;
       qa.out_ids = out_ids + s0 * k;
       qa.out_dist = out_dist + s0 * k;
+      qa.sel = sel ? sel + s0 * (int64_t)L * rmax : nullptr;
       qa.rows = timing_row_counter();
       for (int d = 0; d < L; ++d) qa.r_lev[L - d] = r_levels[d];
       // score rows of every screened level, then the launch order: queries
@@ -821,6 +829,30 @@ mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int3
   } catch (const Error& e) {
     return fail(e);
   }
+}
+
+}  // namespace
+}  // namespace mask
+
+extern "C" {
+
+mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int32_t k,
+                                const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                                void* workspace, int64_t workspace_bytes, void* hip_stream) {
+  return screened_impl(ix, q, k, r_levels, out_ids, out_dist, nullptr, workspace,
+                       workspace_bytes, hip_stream);
+}
+
+mask_status mask_query_screened_debug(const mask_index* ix, const mask_matrix* q, int32_t k,
+                                      const int32_t* r_levels, int32_t* out_ids,
+                                      float* out_dist, int32_t* sel, void* workspace,
+                                      int64_t workspace_bytes, void* hip_stream) {
+  if (!sel) {
+    set_error("sel is NULL");
+    return MASK_ERR_INVALID;
+  }
+  return screened_impl(ix, q, k, r_levels, out_ids, out_dist, sel, workspace, workspace_bytes,
+                       hip_stream);
 }
 
 mask_status mask_query_ragged(const mask_index* ix, const mask_matrix* q, const int32_t* k_i,
@@ -1106,6 +1138,20 @@ mask_status mask_relocate(const mask_index* ix, const int32_t* leaf, const int32
     (void)hipStreamSynchronize(s);
     return fail(Error{MASK_ERR_NOMEM, "host allocation failed"});
   }
+}
+
+mask_status mask_query_beams_debug(const mask_index* ix, const mask_matrix* q, int32_t k,
+                                   const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                                   int32_t* sel, void* hip_stream) {
+  if (!r_levels || !sel) {
+    set_error("r_levels and sel are required");
+    return MASK_ERR_INVALID;
+  }
+  int32_t rmax = 1;
+  if (ix)
+    for (int d = 0; d < ix->n_levels; ++d) rmax = r_levels[d] > rmax ? r_levels[d] : rmax;
+  return query_impl(ix, q, k, rmax, nullptr, nullptr, nullptr, out_ids, out_dist, sel,
+                    hip_stream, r_levels);
 }
 
 mask_status mask_query_debug(const mask_index* ix, const mask_matrix* q, int32_t k, int32_t r,

@@ -292,6 +292,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     }
   }
   unsigned long long rows_seen = 0;
+  // Cap of the precision form's re-rank set, from this query's own k and
+  // beams (512 when none exceeds 512, else 2048), so that a query's result
+  // does not depend on the other queries of a ragged batch; the LDS class
+  // (CAPB) covers the whole batch and so every query's cap.
+  bool big = k > 512 || r > 512;
+  for (int l = 1; l <= L; ++l) big = big || qa.r_lev[l] > 512;
+  const int64_t rerank_cap = big ? 2048 : 512;
 
   for (int lev = L; lev >= 0; --lev) {
     const LevelView V = a.lv[lev];
@@ -306,8 +313,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     bool low = B16 || (F8 && lev == 0);
     bool rerank = false;
     if (lev == 0 && LOWP) {
-      // the re-rank set: rerank_factor * k candidates, at most CAPB
-      const int64_t R = min((int64_t)a.rerank_factor * k, (int64_t)CAPB);
+      // the re-rank set: rerank_factor * k candidates, at most the query's cap
+      const int64_t R = min(min((int64_t)a.rerank_factor * k, rerank_cap), (int64_t)CAPB);
       if ((int64_t)m > R && R > k) {
         want = (uint32_t)R;
         rerank = true;

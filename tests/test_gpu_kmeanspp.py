@@ -193,3 +193,22 @@ def test_seeding_row_counters(pk):
     assert n <= low <= read <= (k - 1) * n
     # clustered rows: the triangle inequality rules most of them out
     assert read < 0.8 * (k - 1) * n
+
+
+@pytest.mark.parametrize("n,C", [(70_001, 1), (280_000, 2)])
+def test_seeds_of_groups_with_many_tiles_match_oracle(pk, n, C):
+    # groups of 70,001 and 140,000 rows at d = 4 are cut into 547 and 1,094
+    # tiles of 128 rows, so the pick keeps 16 and 32 tile sums per lane (the
+    # variants for groups above 512 and 1,024 tiles)
+    X = _mixture(n, 4, 40, seed=1030 + C)
+    k = 24
+    cent, chosen = pk.mask_kmeanspp(dev(X), C, k, seed=91, level=2)
+    cent, chosen = host(cent), host(chosen)
+    off = mo.chunk_offsets(n, C)
+    assert np.array_equal(cent, X[chosen])
+    for c in range(C):
+        pts = X[off[c]:off[c + 1]]
+        assert -(-pts.shape[0] // 128) > (512 if C == 1 else 1024)
+        picks = chosen[c * k:(c + 1) * k] - off[c]
+        assert np.all((picks >= 0) & (picks < pts.shape[0]))
+        assert _compare(pts, picks, 91, 2, c, k) == k

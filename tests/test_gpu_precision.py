@@ -9,7 +9,7 @@ import pytest
 import datagen
 from oracle import compare as oc
 from oracle import mask_oracle as mo
-from tests.gpu_helpers import dev, host, oracle_index_from_gpu
+from tests.gpu_helpers import check_lowp_against_oracle, dev, host, oracle_index_from_gpu
 
 pytestmark = pytest.mark.gpu
 REL = 1e-5
@@ -194,3 +194,57 @@ def test_fp8_recall_close_to_fp32_on_shared_index(pk):
         rec[name] = oc.recall_at_k(ids, tids, tdist, oc.true_distances(X, Q, ids), 10)
     print(rec)
     assert rec["fp8"] >= rec["fp32"] - 0.05, rec
+
+
+def test_fp8_descent_matches_the_oracle(pk):
+    # prototype levels in FP32, the data layer in FP8 with a per-row scale;
+    # 16 leaves of about 20 rows against a re-rank set of 40
+    X, Q = _mixture(20_000, 96, 50, seed=340, nq=300)
+    levels = [(10, 100), (1, 40)]
+    gix = pk.mask_build(dev(X), levels, iters=8, seed=2, precision="fp8", rerank_factor=4)
+    oix = oracle_index_from_gpu(X, gix)
+    code, scale = mo.quantize_fp8(X)
+    leaf = code * scale[:, None]
+    for beams in ([4, 16], [2, 40]):
+        ids, dist, sel = (host(t) for t in pk.mask_query_beams(gix, dev(Q), 10, beams,
+                                                                debug=True))
+        fails = check_lowp_against_oracle(oix, Q, 10, beams, ids, dist, sel, oix.protos,
+                                          leaf, 4)
+        assert not fails, (beams, fails[:3])
+    gix.free()
+
+
+def test_bf16_gathered_descent_matches_the_oracle_at_d96(pk):
+    X, Q = _mixture(20_000, 96, 50, seed=350, nq=300)
+    levels = [(10, 100), (1, 40)]
+    gix = pk.mask_build(dev(X), levels, iters=8, seed=2, precision="bf16")
+    oix = oracle_index_from_gpu(X, gix)
+    rank = [mo.quantize_bf16(P.astype(np.float32)) for P in oix.protos]
+    leaf = mo.quantize_bf16(X)
+    for beams in ([4, 16], [1, 3]):
+        ids, dist, sel = (host(t) for t in pk.mask_query_beams(gix, dev(Q), 10, beams,
+                                                                debug=True))
+        fails = check_lowp_against_oracle(oix, Q, 10, beams, ids, dist, sel, rank, leaf, 4)
+        assert not fails, (beams, fails[:3])
+    gix.free()
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_ragged_rerank_set_follows_each_query(pk, precision):
+    # a query with k above 512 moves the batch to the large LDS class; the
+    # other queries' re-rank sets must stay what they are alone
+    import torch
+    X, Q = _mixture(40_000, 32, 60, seed=360, nq=40)
+    gix = pk.mask_build(dev(X), [(10, 100), (1, 25)], iters=6, seed=5, precision=precision)
+    g = np.random.default_rng(19)
+    ks = g.integers(1, 220, size=40).astype(np.int32)
+    ks[::7] = 600
+    rs = g.choice([8, 32], size=40).astype(np.int32)
+    ids, dist, off = pk.mask_query_ragged(gix, dev(Q), torch.from_numpy(ks),
+                                          torch.from_numpy(rs))
+    ids, dist, off = host(ids), host(dist), host(off)
+    for i in range(40):
+        i1, d1 = pk.mask_query(gix, dev(Q[i:i + 1]), int(ks[i]), int(rs[i]))
+        assert np.array_equal(ids[off[i]:off[i + 1]], host(i1)[0]), i
+        assert np.array_equal(dist[off[i]:off[i + 1]], host(d1)[0]), i
+    gix.free()

@@ -10,7 +10,7 @@ import pytest
 import datagen
 from oracle import compare as oc
 from oracle import mask_oracle as mo
-from tests.gpu_helpers import dev, host
+from tests.gpu_helpers import check_lowp_against_oracle, dev, host, oracle_index_from_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -133,4 +133,73 @@ def test_launch_order_changes_nothing(pk):
     assert np.array_equal(i2, ids[p]) and np.array_equal(d2, dist[p])
     i3, d3 = (host(t) for t in pk.mask_query_screened(gix, dev(Q[100:137]), 10, beams))
     assert np.array_equal(i3, ids[100:137]) and np.array_equal(d3, dist[100:137])
+    gix.free()
+
+
+def _bf16_views(gix, X):
+    """The oracle's view of a BF16 index: the exported prototypes, and every
+    level's rows and the data rows rounded to bfloat16 as the descent reads
+    them."""
+    oix = oracle_index_from_gpu(X, gix)
+    rank = [mo.quantize_bf16(P.astype(np.float32)) for P in oix.protos]
+    return oix, rank, mo.quantize_bf16(X)
+
+
+@pytest.mark.parametrize("d", [128, 40, 7])
+def test_screened_and_gathered_descents_match_the_oracle(pk, d):
+    # every prototype level screened (4,000 / 400 / 40 prototypes)
+    X, Q = _mixture(40_000, d, 80, seed=1100 + d, nq=300)
+    levels = [(20, 200), (1, 400), (1, 40)]
+    gix = pk.mask_build(dev(X), levels, iters=6, seed=2, precision="bf16")
+    oix, rank, leaf = _bf16_views(gix, X)
+    beams = [6, 24, 48]  # 480 leaf candidates against a re-rank set of 40
+    ids, dist, sel = (host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, beams,
+                                                               debug=True))
+    fails = check_lowp_against_oracle(oix, Q, 10, beams, ids, dist, sel, rank, leaf, 4,
+                                      screened_levels=(1, 2, 3))
+    assert not fails, fails[:3]
+    # the debug output does not change the results
+    i0, d0 = (host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, beams))
+    assert np.array_equal(i0, ids) and np.array_equal(d0, dist)
+    # the gathered descent on the same index: every level within 1e-5
+    ids, dist, sel = (host(t) for t in pk.mask_query_beams(gix, dev(Q), 10, beams, debug=True))
+    fails = check_lowp_against_oracle(oix, Q, 10, beams, ids, dist, sel, rank, leaf, 4)
+    assert not fails, fails[:3]
+    gix.free()
+
+
+def test_mixed_screened_and_gathered_levels_match_the_oracle(pk):
+    # level 1 gathered (20,000 prototypes), levels 2 and 3 screened
+    X, Q = _mixture(200_000, 16, 300, seed=1140, nq=300)
+    levels = [(20, 1000), (1, 200), (1, 20)]
+    gix = pk.mask_build(dev(X), levels, iters=3, seed=5, precision="bf16")
+    oix, rank, leaf = _bf16_views(gix, X)
+    beams = [4, 16, 64]
+    ids, dist, sel = (host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, beams,
+                                                               debug=True))
+    fails = check_lowp_against_oracle(oix, Q, 10, beams, ids, dist, sel, rank, leaf, 4,
+                                      screened_levels=(2, 3))
+    assert not fails, fails[:3]
+    gix.free()
+
+
+def test_screened_debug_slices_keep_selections(pk):
+    import torch
+    X, Q = _mixture(20_000, 64, 40, seed=1160, nq=300)
+    gix = pk.mask_build(dev(X), [(10, 100), (1, 80)], iters=5, seed=3, precision="bf16")
+    per = pk.mask_screen_bytes(gix)
+    small = torch.empty(per * 37, dtype=torch.uint8, device="cuda")
+    a = [host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, [8, 16], debug=True)]
+    b = [host(t) for t in pk.mask_query_screened(gix, dev(Q), 10, [8, 16], workspace=small,
+                                                 debug=True)]
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    # each level's selection is a set (its order comes from LDS slot atomics)
+    assert np.array_equal(np.sort(a[2], axis=2), np.sort(b[2], axis=2))
+    # every selection row: the beam's count of distinct ids, then -1 padding
+    sel = a[2]
+    for depth, beam in enumerate([8, 16]):
+        rows = sel[:, depth, :]
+        assert np.all(rows[:, beam:] == -1)
+        assert np.all(rows[:, :beam] >= 0)  # the kept ids fill the first slots
+        assert all(np.unique(r[:beam]).size == beam for r in rows)
     gix.free()

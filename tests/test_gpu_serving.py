@@ -124,3 +124,102 @@ def test_replay_serves_a_schedule(setup):
     assert st["completed_queries"] == int(rs.n_queries.sum())
     assert np.all(lat > 0) and np.all(lat < 5.0)
     assert span >= rs.t_arrival[-1]
+
+
+# ------------------------------------------------ precision forms, served
+
+@pytest.fixture(scope="module")
+def lowp_setup():
+    import torch
+    import paper_2208_02734_amd as pk
+    pk.lib()
+    mix = datagen.mixture_params(310, 60, 32, sigma_mode="loguniform", sigma_low=0.1,
+                                 sigma_high=3.0)
+    X = datagen.sample_mixture(mix, 40_000, 311)
+    Q = datagen.sample_mixture(mix, 3_000, 312)
+    levels = [(10, 100), (1, 25)]  # leaves of about 40 rows
+    ixs = {p: pk.mask_build(dev(X), levels, iters=6, seed=7, precision=p)
+           for p in ("bf16", "fp8")}
+    torch.cuda.synchronize()
+    yield pk, ixs, X, Q
+    for ix in ixs.values():
+        ix.free()
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_lowp_results_in_the_mix_equal_results_alone(lowp_setup, precision):
+    # requests with k above 512 share batches with small ones: every
+    # request's rows must still equal its rows alone (the re-rank set of a
+    # query follows its own k and r, not the batch's)
+    pk, ixs, X, Q = lowp_setup
+    ix = ixs[precision]
+    g = np.random.default_rng(21)
+    srv = pk.MaskServer(ix, arena_bytes=64 << 20, max_batch_queries=2048, n_streams=3,
+                        batch_window_us=20_000)
+    reqs, tickets = [], []
+    pos = 0
+    for j in range(60):
+        n = int(g.integers(1, 24))
+        k = 600 if j % 9 == 4 else int(g.integers(1, 220))
+        r = int(g.choice([8, 32]))
+        reqs.append((pos, n, k, r))
+        tickets.append(srv.submit(Q[pos:pos + n], k, r))
+        pos = (pos + n) % (Q.shape[0] - 32)
+    res = _drain(srv, tickets)
+    st = srv.stats()
+    srv.close()
+    assert st["completed_requests"] == 60 and st["batches"] < 60
+    for (p, n, k, r), t in zip(reqs, tickets):
+        ids, dist, _ = res[t]
+        i1, d1 = pk.mask_query(ix, dev(Q[p:p + n]), k, r)
+        assert np.array_equal(ids, host(i1)), (p, n, k, r)
+        assert np.array_equal(dist, host(d1)), (p, n, k, r)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_served_rows_match_the_oracle(lowp_setup, precision):
+    # served rows against the FP64 oracle on the exported index: each level's
+    # selection (from the same query's debug descent, whose rows must equal
+    # the served ones bit for bit) is a nearest set of the low-precision rows,
+    # and the result is the FP32 re-rank of the R nearest leaf candidates
+    from oracle import mask_oracle as mo
+    from tests.gpu_helpers import check_lowp_against_oracle, oracle_index_from_gpu
+    pk, ixs, X, Q = lowp_setup
+    ix = ixs[precision]
+    oix = oracle_index_from_gpu(X, ix)
+    if precision == "bf16":
+        rank = [mo.quantize_bf16(P.astype(np.float32)) for P in oix.protos]
+        leaf = mo.quantize_bf16(X)
+        factor = 4
+    else:
+        rank = oix.protos
+        code, scale = mo.quantize_fp8(X)
+        leaf = code * scale[:, None]
+        factor = 48
+    g = np.random.default_rng(23)
+    srv = pk.MaskServer(ix, arena_bytes=64 << 20, max_batch_queries=2048, n_streams=3,
+                        batch_window_us=10_000)
+    reqs, tickets = [], []
+    pos = 0
+    for _ in range(30):
+        n = int(g.integers(1, 12))
+        k = int(g.integers(1, 100))
+        r = int(g.choice([8, 32]))
+        reqs.append((pos, n, k, r))
+        tickets.append(srv.submit(Q[pos:pos + n], k, r))
+        pos += n
+    res = _drain(srv, tickets)
+    srv.close()
+    checked = 0
+    for (p, n, k, r), t in zip(reqs, tickets):
+        ids, dist, _ = res[t]
+        ids, dist = ids.reshape(n, k), dist.reshape(n, k)
+        beams = [r] * oix.n_levels
+        i1, d1, sel = (host(x) for x in pk.mask_query_beams(ix, dev(Q[p:p + n]), k, beams,
+                                                             debug=True))
+        assert np.array_equal(ids, i1) and np.array_equal(dist, d1)
+        fails = check_lowp_against_oracle(oix, Q[p:p + n], k, beams, ids, dist, sel, rank,
+                                          leaf, factor)
+        assert not fails, (p, n, k, r, fails[:2])
+        checked += n
+    assert checked >= 100

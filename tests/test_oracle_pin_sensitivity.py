@@ -133,3 +133,96 @@ def test_point_query_answering_with_the_farthest_point_is_caught(monkeypatch):
         return -orig(A, B, metric, block)
     monkeypatch.setattr(mo, "pairwise", bad)
     assert _fails(pins.test_point_query_on_one_to_one_level_finds_every_point)
+
+
+# ---------------------------------------------------- comparator and replay
+
+from oracle import compare as oc  # noqa: E402
+
+
+def test_selection_check_that_accepts_anything_is_caught(monkeypatch):
+    monkeypatch.setattr(oc, "check_selection", lambda *a, **k: None)
+    assert _fails(pins.test_check_selection_accepts_nearest_sets_and_near_ties_only)
+    assert _fails(pins.test_replay_follows_a_tied_selection_and_rejects_a_farther_one)
+
+
+def test_selection_check_without_a_tie_band_is_caught(monkeypatch):
+    orig = oc.check_selection
+
+    def strict(cand, cand_dist, sel, r, rel=1e-5, abs_tol=0.0):
+        return orig(cand, cand_dist, sel, r, 0.0, 0.0)
+    monkeypatch.setattr(oc, "check_selection", strict)
+    assert _fails(pins.test_check_selection_accepts_nearest_sets_and_near_ties_only)
+
+
+def test_replay_that_ignores_the_forced_selection_is_caught(monkeypatch):
+    orig = mo.query_one
+
+    def bad(index, q, k, r, trace=False, forced=None):
+        return orig(index, q, k, r, trace=trace)
+    monkeypatch.setattr(mo, "query_one", bad)
+    assert _fails(pins.test_replay_follows_a_tied_selection_and_rejects_a_farther_one)
+
+
+def test_rerank_check_without_the_low_precision_cut_is_caught(monkeypatch):
+    orig = oc.check_rerank
+
+    def bad(got_ids, got_dist, cand, d_low, d_full, k, R, rel=1e-5):
+        return orig(got_ids, got_dist, cand, d_low, d_full, k, 10 ** 9, rel)
+    monkeypatch.setattr(oc, "check_rerank", bad)
+    assert _fails(pins.test_check_rerank_takes_the_low_precision_cut_then_the_full_ranking)
+
+
+# ----------------------------------------------------------- precision form
+
+def test_truncating_bf16_is_caught(monkeypatch):
+    def trunc(X):
+        x = np.ascontiguousarray(X, dtype=np.float32)
+        u = x.view(np.uint32) & np.uint32(0xFFFF0000)
+        return u.view(np.float32).astype(np.float64)
+    monkeypatch.setattr(mo, "quantize_bf16", trunc)
+    assert _fails(pins.test_bf16_rounding_matches_torch_and_ties_to_even)
+
+
+def test_e4m3_rounding_half_away_from_zero_is_caught(monkeypatch):
+    def away(v):
+        v = np.asarray(v, dtype=np.float64)
+        a = np.abs(v)
+        e = np.floor(np.log2(np.where(a > 0, a, 1.0)))
+        step = np.where(a >= 2.0 ** -6, 2.0 ** (e - 3), 2.0 ** -9)
+        return np.sign(v) * np.floor(a / step + 0.5) * step
+    monkeypatch.setattr(mo, "round_e4m3", away)
+    assert _fails(pins.test_e4m3_rounding_matches_torch_and_keeps_every_code)
+
+
+def test_fp8_scale_off_by_one_step_is_caught(monkeypatch):
+    orig = mo.quantize_fp8
+
+    def bad(X):
+        code, s = orig(X)
+        return code, s * (1 + 2.0 ** -3)
+    monkeypatch.setattr(mo, "quantize_fp8", bad)
+    assert _fails(pins.test_fp8_rows_reconstruct_within_half_a_step)
+
+
+def test_preselection_on_the_full_rows_is_caught(monkeypatch):
+    orig = mo.query_one_lowp
+
+    def bad(index, q, k, r, rank_protos, leaf_rows, factor, forced=None, trace=False):
+        return orig(index, q, k, r, rank_protos, index.data, factor, forced, trace)
+    monkeypatch.setattr(mo, "query_one_lowp", bad)
+    assert _fails(pins.test_lowp_descent_preselects_by_the_low_precision_rows)
+
+
+def test_rerank_cap_ignoring_the_beams_is_caught(monkeypatch):
+    monkeypatch.setattr(mo, "rerank_size", lambda k, beams, factor: min(factor * k, 512))
+    assert _fails(pins.test_rerank_size_caps)
+
+
+def test_screened_bound_without_the_query_split_term_is_caught(monkeypatch):
+    def bad(q, rows):
+        q = np.asarray(q, dtype=np.float64)
+        cmax = float(np.einsum("ij,ij->i", rows, rows).max())
+        return 2.0 ** -24 * (float(q @ q) + cmax)
+    monkeypatch.setattr(oc, "screened_bound", bad)
+    assert _fails(pins.test_screened_bound_covers_the_float32_expanded_form)

@@ -339,6 +339,208 @@ def test_recall_counts_ties():
     assert abs(oc.recall_at_k(got, true_ids, true_dist, got_true2, 3) - 2 / 3) < 1e-12
 
 
+def test_check_selection_accepts_nearest_sets_and_near_ties_only():
+    cand = np.array([10, 11, 12, 13, 14, 15])
+    d = np.array([5.0, 1.0, 3.0, 2.0, 4.0, 6.0])
+    # the three nearest, in any order
+    assert oc.check_selection(cand, d, np.array([13, 11, 12]), 3) is None
+    # leaves out a strictly nearer candidate (12 at 3.0 for 14 at 4.0)
+    why = oc.check_selection(cand, d, np.array([11, 13, 14]), 3)
+    assert why is not None and "not nearest" in why
+    # a near-tie within 1e-6 relative may go either way
+    dt = d.copy()
+    dt[4] = 3.0 * (1 + 1e-6)
+    assert oc.check_selection(cand, dt, np.array([11, 13, 14]), 3) is None
+    # ... but not a gap of 1e-4 relative
+    dt[4] = 3.0 * (1 + 1e-4)
+    assert oc.check_selection(cand, dt, np.array([11, 13, 14]), 3) is not None
+    # an absolute tolerance widens the tie band
+    assert oc.check_selection(cand, d, np.array([11, 13, 14]), 3, abs_tol=1.5) is None
+    assert oc.check_selection(cand, d, np.array([11, 13, 14]), 3, abs_tol=0.5) is not None
+    # wrong count, duplicates, a non-candidate
+    for bad, what in (([11, 13], "expected 3"), ([11, 11, 13], "duplicate"),
+                      ([11, 13, 99], "not a candidate")):
+        why = oc.check_selection(cand, d, np.array(bad), 3)
+        assert why is not None and what in why
+    # r at least the candidate count: every candidate, in any order
+    assert oc.check_selection(cand, d, cand[::-1], 8) is None
+
+
+def _tie_index():
+    """Two top prototypes at the same distance from the query (the origin):
+    A = (-1, 0) with leaf points near it, B = (1, 0) with leaf points near
+    it.  Level 1 holds one prototype per point; the top level two."""
+    pts = np.array([[-1.0, 0.1], [-1.0, -0.2], [-1.1, 0.0],
+                    [1.0, 0.05], [1.2, 0.0], [0.9, -0.3]])
+    lv1 = pts.copy()
+    par1 = np.arange(6)
+    top = np.array([[-1.0, 0.0], [1.0, 0.0]])
+    par2 = np.array([0, 0, 0, 1, 1, 1])
+    return pts, mo.index_from_arrays(pts, [lv1, top], [par1, par2])
+
+
+def test_replay_with_own_selections_reproduces_query_one_bit_for_bit():
+    X, ix = _small_index()
+    g = np.random.default_rng(31)
+    for _ in range(20):
+        q = g.standard_normal(5) * 3
+        for r in (1, 3, [2, 5, 3]):
+            ids, dist, tr = mo.query_one(ix, q, 6, r, trace=True)
+            why, r_ids, r_dist = oc.replay_query(ix, q, 6, r, tr.selected)
+            assert why is None
+            assert np.array_equal(ids, r_ids)
+            assert np.array_equal(dist, r_dist)
+
+
+def test_replay_follows_a_tied_selection_and_rejects_a_farther_one():
+    pts, ix = _tie_index()
+    q = np.zeros(2)
+    ids, _, tr = mo.query_one(ix, q, 2, 1, trace=True)
+    assert tr.selected[0].tolist() == [0]  # the tie goes to the lower id
+    # B ties A: accepted, and the leaf set changes with it
+    # (under B the nearest level-1 prototype is point 5, at 0.9)
+    why, r_ids, _ = oc.replay_query(ix, q, 2, 1, [np.array([1]), np.array([5])])
+    assert why is None
+    assert r_ids.tolist() == [5, -1] and ids.tolist() == [0, -1]
+    # move the query towards A: B is now strictly farther and is rejected
+    why, _, _ = oc.replay_query(ix, np.array([-0.01, 0.0]), 2, 1,
+                                [np.array([1]), np.array([5])])
+    assert why is not None and why.startswith("level 1")
+    # a level-0 selection that is not a child of the kept top prototype
+    why, _, _ = oc.replay_query(ix, q, 2, 1, [np.array([0]), np.array([4])])
+    assert why is not None and "not a candidate" in why
+
+
+def test_check_rerank_takes_the_low_precision_cut_then_the_full_ranking():
+    cand = np.arange(100, 108)
+    d_full = np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0, 8.0]) ** 2
+    # low-precision order puts candidate 100 (nearest in full) last
+    d_low = np.array([9.0, 2.0, 3.0, 4.0, 5.0, 6.0, 7.0, 8.0]) ** 2
+    k, R = 2, 4
+    good_ids = np.array([101, 102])
+    good_d = np.array([2.0, 3.0])
+    assert oc.check_rerank(good_ids, good_d, cand, d_low, d_full, k, R) is None
+    # returning 100 is wrong: it is outside the R nearest by low precision
+    assert oc.check_rerank(np.array([100, 101]), np.array([1.0, 2.0]), cand, d_low,
+                           d_full, k, R) is not None
+    # skipping 102 (in the set, nearer than 103) is wrong
+    assert oc.check_rerank(np.array([101, 103]), np.array([2.0, 4.0]), cand, d_low,
+                           d_full, k, R) is not None
+    # with R >= |cand| every candidate is ranked on the full rows
+    assert oc.check_rerank(np.array([100, 101]), np.array([1.0, 2.0]), cand, d_low,
+                           d_full, k, 8) is None
+    # a candidate tied with the R-th low-precision distance may be in or out
+    d_low2 = d_low.copy()
+    d_low2[0] = d_low[4] * (1 + 1e-7)   # 100 ties the 4th (104)
+    assert oc.check_rerank(np.array([100, 101]), np.array([1.0, 2.0]), cand, d_low2,
+                           d_full, k, R) is None
+    # distances off by 1e-4 relative, or not ascending
+    assert oc.check_rerank(good_ids, good_d * (1 + 1e-4), cand, d_low, d_full, k, R)
+    assert oc.check_rerank(good_ids[::-1], good_d[::-1], cand, d_low, d_full, k, R)
+
+
+# ------------------------------------------------------------ precision form
+
+def test_bf16_rounding_matches_torch_and_ties_to_even():
+    import torch
+    g = np.random.default_rng(40)
+    x = (g.standard_normal(20_000) * 10.0 ** g.integers(-6, 6, 20_000)).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(mo.quantize_bf16(x), ref)
+    # halfway cases: 1 + 2^-8 lies between 1 and 1 + 2^-7 -> 1 (even);
+    # 1 + 3 * 2^-8 lies between 1 + 2^-7 and 1 + 2^-6 -> 1 + 2^-6 (even)
+    h = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8)], dtype=np.float32)
+    assert mo.quantize_bf16(h).tolist() == [1.0, 1 + 2.0 ** -6, -1.0]
+
+
+def test_e4m3_rounding_matches_torch_and_keeps_every_code():
+    import torch
+    # every finite e4m3 value is a fixed point
+    codes = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn).to(torch.float64)
+    vals = codes.numpy()
+    vals = vals[np.isfinite(vals)]
+    assert np.array_equal(mo.round_e4m3(vals), vals)
+    assert vals.max() == 448.0 and np.min(vals[vals > 0]) == 2.0 ** -9
+    g = np.random.default_rng(41)
+    v = np.clip(g.standard_normal(50_000) * 10.0 ** g.integers(-4, 3, 50_000), -448, 448)
+    v = v.astype(np.float32)
+    ref = torch.from_numpy(v).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.array_equal(mo.round_e4m3(v.astype(np.float64)), ref)
+    # halfway between 1 and 1.125 goes to 1 (even), between 1.125 and 1.25 to 1.25
+    assert mo.round_e4m3(np.array([1.0625, 1.1875])).tolist() == [1.0, 1.25]
+
+
+def test_fp8_rows_reconstruct_within_half_a_step():
+    g = np.random.default_rng(42)
+    X = (g.standard_normal((300, 24)) * g.uniform(0.01, 100, (300, 1))).astype(np.float32)
+    X[7] = 0.0
+    code, s = mo.quantize_fp8(X)
+    assert s[7] == 1.0 and np.all(code[7] == 0)
+    # the largest entry of each row lands on 448
+    nz = np.abs(X).max(axis=1) > 0
+    assert np.all(np.abs(code[nz]).max(axis=1) == 448.0)
+    # normal codes carry 3 mantissa bits: |s*code - x| <= 2^-4 |x| (+ subnormal step)
+    err = np.abs(s[:, None] * code - X.astype(np.float64))
+    assert np.all(err <= 2.0 ** -4 * np.abs(X) + s[:, None] * 2.0 ** -10 + 1e-30)
+
+
+def test_rerank_size_caps():
+    assert mo.rerank_size(10, [3, 12, 104], 4) == 40
+    assert mo.rerank_size(200, [3, 12, 104], 4) == 512
+    assert mo.rerank_size(200, [3, 600, 104], 4) == 800
+    assert mo.rerank_size(600, [3], 48) == 2048
+
+
+def test_lowp_descent_on_exact_rows_is_the_plain_descent():
+    X, ix = _small_index()
+    g = np.random.default_rng(43)
+    for _ in range(15):
+        q = g.standard_normal(5) * 3
+        for factor in (1, 2, 4, 1000):
+            a = mo.query_one(ix, q, 6, [2, 4, 3])
+            b = mo.query_one_lowp(ix, q, 6, [2, 4, 3], ix.protos, ix.data, factor)
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_lowp_descent_preselects_by_the_low_precision_rows():
+    pts, ix = _tie_index()
+    q = np.array([-1.0, 0.0])
+    # leaf candidates {0, 1, 2} at full distances 0.1, 0.2, 0.1; the
+    # low-precision copy pushes point 0 far away
+    low = pts.copy()
+    low[0] = [5.0, 5.0]
+    ids, dist = mo.query_one_lowp(ix, q, 1, [1, 3], ix.protos, low, 2)
+    # R = 2 keeps {1, 2} by low distance; the nearest of those on the full
+    # rows is point 2 (0.1)
+    assert ids.tolist() == [2]
+    assert abs(dist[0] - 0.1) < 1e-12
+    # R = k: every candidate is ranked on the full rows (0 and 2 tie at 0.1;
+    # the tie goes to the lower id)
+    ids2, _ = mo.query_one_lowp(ix, q, 1, [1, 3], ix.protos, low, 1)
+    assert ids2.tolist() == [0]
+    ids3, _ = mo.query_one_lowp(ix, q, 2, [1, 3], ix.protos, low, 1)
+    assert ids3.tolist() == [0, 2]
+
+
+def test_screened_bound_covers_the_float32_expanded_form():
+    import torch
+    g = np.random.default_rng(44)
+    for d in (16, 96, 128):
+        Q = (g.uniform(-10, 10, (40, d)) + g.standard_normal((40, d))).astype(np.float32)
+        C = mo.quantize_bf16((g.uniform(-10, 10, (60, d))).astype(np.float32))
+        hi = mo.quantize_bf16(Q)
+        lo = mo.quantize_bf16((Q - hi).astype(np.float32))
+        # float32 evaluation of the expanded form on the two bfloat16 terms
+        qt = torch.from_numpy(Q)
+        ct = torch.from_numpy(C.astype(np.float32))
+        dot = torch.from_numpy(hi.astype(np.float32)) @ ct.T + \
+            torch.from_numpy(lo.astype(np.float32)) @ ct.T
+        s = ((qt * qt).sum(1)[:, None] + (ct * ct).sum(1)[None, :] - 2 * dot).double().numpy()
+        exact = mo.pairwise(Q.astype(np.float64), C)
+        for i in range(Q.shape[0]):
+            assert np.all(np.abs(s[i] - exact[i]) <= oc.screened_bound(Q[i], C))
+
+
 # ------------------------------------------------------------ range search
 
 def _ball(X, q, radius):
