@@ -218,6 +218,27 @@ mask_status mask_query_screened_debug(const mask_index* ix, const mask_matrix* q
                                       float* out_dist, int32_t* sel, void* workspace,
                                       int64_t workspace_bytes, void* hip_stream);
 
+/* Size of the device scratch of mask_query_screened_noalloc: 64 MiB, held
+ * by every GPU the library runs on from its first call there until the
+ * process ends. */
+#define MASK_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+
+/* mask_query_screened for callers that cannot allocate device memory or
+ * take a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the score rows and launch order live
+ * in a static device array of MASK_NOALLOC_SCRATCH_BYTES per GPU, so the
+ * call takes no workspace; queries are processed in slices that fit it.
+ * The caller still passes the queries and the outputs.  The array's
+ * address is looked up once per device, on the first call with that device
+ * current; the call itself allocates nothing.  MASK_ERR_INVALID when one
+ * query's screened scores (mask_screen_bytes) exceed the scratch.  Results
+ * equal mask_query_screened's with any workspace.  Every call on one GPU
+ * shares its array: calls that overlap on one GPU (other streams, other
+ * host threads) race and must be ordered by the caller. */
+mask_status mask_query_screened_noalloc(const mask_index* ix, const mask_matrix* q, int32_t k,
+                                        const int32_t* r_levels, int32_t* out_ids,
+                                        float* out_dist, void* hip_stream);
+
 /* Workspace bytes per query of mask_query_screened: 4 bytes per prototype
  * of every screened level, each level's count rounded up to a multiple of
  * 32, plus 8 bytes for the launch order (0 when nothing is screened). */

@@ -86,6 +86,7 @@ _lib = None
 EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_beams", "mask_query_ragged",
             "mask_query_range", "mask_point_query", "mask_relocate", "mask_insert",
             "mask_kmeanspp", "mask_query_screened", "mask_query_screened_debug",
+            "mask_query_screened_noalloc",
             "mask_query_beams_debug", "mask_screen_bytes",
             "mask_query_debug", "mask_free",
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
@@ -119,6 +120,7 @@ def lib() -> ctypes.CDLL:
     L.mask_query_screened.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP, I64, VP]
     L.mask_query_screened_debug.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP, VP, I64,
                                             VP]
+    L.mask_query_screened_noalloc.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP]
     L.mask_query_beams_debug.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP, VP]
     L.mask_screen_bytes.argtypes = [VP, P(I64)]
     L.mask_free.argtypes = [VP]
@@ -435,6 +437,26 @@ def mask_query_screened(index: Index, queries, k: int, beams: Sequence[int], wor
     _check(lib().mask_query_screened(index.handle, ctypes.byref(m), int(k), r, ids.data_ptr(),
                                      dist.data_ptr(), workspace.data_ptr(), ws_bytes,
                                      _stream_handle(stream)))
+    return ids, dist
+
+
+def mask_query_screened_noalloc(index: Index, queries, k: int, beams: Sequence[int],
+                                stream=None, out=None):
+    """mask_query_screened on the library's static per-GPU scratch: no
+    workspace.  ``out``: optional (ids, dist) tensors of shape (nq, k) to
+    write into (allocated here when None).  Returns (ids, dist)."""
+    torch = _torch()
+    m = _matrix(queries)
+    nq = queries.shape[0]
+    if out is None:
+        ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+        dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    else:
+        ids, dist = out
+    r = (ctypes.c_int32 * len(beams))(*[int(b) for b in beams])
+    _check(lib().mask_query_screened_noalloc(index.handle, ctypes.byref(m), int(k), r,
+                                             ids.data_ptr(), dist.data_ptr(),
+                                             _stream_handle(stream)))
     return ids, dist
 
 

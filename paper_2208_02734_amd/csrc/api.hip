@@ -855,6 +855,66 @@ mask_status mask_query_screened_debug(const mask_index* ix, const mask_matrix* q
                        hip_stream);
 }
 
+}  // extern "C"
+
+// Scratch of mask_query_screened_noalloc: score rows and launch order of one
+// slice of queries.  Host code uses only the per-device address that
+// hipGetSymbolAddress returns (the array's name is a host-side stand-in).
+static __device__ __align__(256) unsigned char scratch[MASK_NOALLOC_SCRATCH_BYTES];
+
+namespace mask {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_at[kMaxDevices] = {};
+
+// The current device's copy of the scratch array, looked up on its first use
+// on that device.
+void* device_scratch() {
+  int dev = -1;
+  MASK_HIP(hipGetDevice(&dev));
+  MASK_CHECK(dev >= 0 && dev < kMaxDevices, "device ordinal beyond the supported range");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw Error{MASK_ERR_DEVICE,
+                  std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    g_scratch_at[dev] = p;
+  }
+  return g_scratch_at[dev];
+}
+
+}  // namespace
+}  // namespace mask
+
+extern "C" {
+
+mask_status mask_query_screened_noalloc(const mask_index* ix, const mask_matrix* q, int32_t k,
+                                        const int32_t* r_levels, int32_t* out_ids,
+                                        float* out_dist, void* hip_stream) {
+  try {
+    if (ix) {
+      int64_t per_query = 0;
+      const mask_status st = mask_screen_bytes(ix, &per_query);
+      if (st != MASK_OK) return st;
+      if (per_query > MASK_NOALLOC_SCRATCH_BYTES) {
+        std::ostringstream m;
+        m << "one query's screened scores take " << per_query << " bytes, more than the "
+          << MASK_NOALLOC_SCRATCH_BYTES << "-byte static scratch";
+        throw Error{MASK_ERR_INVALID, m.str()};
+      }
+    }
+    void* ws = device_scratch();
+    return screened_impl(ix, q, k, r_levels, out_ids, out_dist, nullptr, ws,
+                         MASK_NOALLOC_SCRATCH_BYTES, hip_stream);
+  } catch (const Error& e) {
+    return fail(e);
+  }
+}
+
 mask_status mask_query_ragged(const mask_index* ix, const mask_matrix* q, const int32_t* k_i,
                               const int32_t* r_i, const int64_t* out_off, int32_t k_max,
                               int32_t r_max, int32_t* out_ids, float* out_dist,
