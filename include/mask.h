@@ -96,6 +96,9 @@ typedef struct {
   int64_t nnz;
 } mask_matrix;
 
+/* Most levels an index has. */
+#define MASK_MAX_LEVELS 16
+
 /* One level of the index, bottom-up: the items of the level below (the data
  * for levels[0]) are split into n_chunks contiguous groups of nearly equal
  * size (Algorithm 1, split) and k-means with k prototypes runs in each. */
@@ -112,7 +115,9 @@ typedef struct {
   int32_t lloyd_iters;   /* Lloyd iterations per level (>= 0) */
   uint64_t seed;         /* seeds the level-0 permutation */
   int32_t rerank_factor; /* precision forms: FP32 re-rank of rerank_factor*k
-                            candidates; <= 0: 4 for BF16, 48 for FP8 */
+                            candidates; a negative value -f re-ranks f*k*r1
+                            (r1: the query's level-1 beam, the leaves probed);
+                            0: 4 for BF16, 48 for FP8 */
   const int32_t* perm;   /* optional device int32[n]: level-0 order; NULL = from seed */
   const int64_t* group_off; /* optional host int64[levels[0].n_chunks + 1]: level-0 group
                                boundaries in that order, rising strictly from 0 to n (as
@@ -173,7 +178,8 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
  * the candidate count hold id -1 and +inf.  1 <= k <= 2048, 1 <= r <= 2048.
  * Precision forms (index built with MASK_BF16 or MASK_FP8_E4M3): rows are
  * compared in the low precision and the data layer's R = min(rerank_factor *
- * k, C) nearest by that distance
+ * k, C) nearest by that distance (R = min(f * k * r1, C) for rerank_factor =
+ * -f, r1 the level-1 beam)
  * are re-ranked in FP32 direct form on the FP32 rows, where C = 512 when k
  * and every beam are at most 512 and 2048 otherwise (all candidates in FP32
  * when they are no more than R, or when R <= k).
@@ -248,13 +254,18 @@ mask_status mask_screen_bytes(const mask_index* ix, int64_t* bytes_per_query);
  * [1, k_max] / [1, r_max]) and writes its k_i[i] results at out_ids +
  * out_off[i] / out_dist + out_off[i] (device int64[q->n]).  k_max, r_max <=
  * 2048 are host values bounding the per-query ones (they size the launch).
- * Otherwise as mask_query; each query's result equals what mask_query
- * returns for it alone with the same k and r (in the precision forms the
- * re-rank cap C follows the query's own k_i and r_i). */
+ * beam_eighths: NULL (query i keeps r_i[i] prototypes at every level, as
+ * mask_query), or a beam profile, host int32[n_levels] top level first:
+ * query i keeps ceil(r_i[i] * beam_eighths[d] / 8) prototypes at level d
+ * (0 keeps r_i[i]); each such beam at r_max must be at most 2048.
+ * Otherwise as mask_query; each query's result equals what mask_query (or,
+ * with a profile, mask_query_beams with the query's own beams) returns for
+ * it alone with the same k (in the precision forms the re-rank cap C
+ * follows the query's own k and beams). */
 mask_status mask_query_ragged(const mask_index* ix, const mask_matrix* q, const int32_t* k_i,
                               const int32_t* r_i, const int64_t* out_off, int32_t k_max,
-                              int32_t r_max, int32_t* out_ids, float* out_dist,
-                              void* hip_stream);
+                              int32_t r_max, const int32_t* beam_eighths, int32_t* out_ids,
+                              float* out_dist, void* hip_stream);
 
 /* mask_query_beams plus the prototypes kept at every level: sel is device
  * int32[q->n * n_levels * rmax] (rmax the largest of r_levels), level-major
@@ -398,7 +409,8 @@ const char* mask_last_error(void);
  * block of the device arena (memory admission), and keeps up to n_streams
  * batches in flight, so requests arriving while others run join the next
  * batch as soon as a stream and arena space are free (continuous batching).
- * Each query's result equals mask_query's for it alone with the same k, r. */
+ * Each query's result equals mask_query's for it alone with the same k, r
+ * (with a beam profile, mask_query_beams's with the profile's beams). */
 typedef struct mask_server mask_server;
 
 typedef struct {
@@ -407,6 +419,10 @@ typedef struct {
   int32_t n_streams;         /* batches in flight at once, 1..16 */
   int32_t batch_window_us;   /* a batch that is not full launches once its oldest
                                 request has been queued this long (0: at once) */
+  int32_t beam_eighths[MASK_MAX_LEVELS]; /* beam profile, top level first: a request
+                                with probe width r keeps ceil(r * beam_eighths[d] / 8)
+                                prototypes at level d (0 keeps r); all zero: r at
+                                every level */
 } mask_server_params;
 
 typedef struct {

@@ -514,10 +514,13 @@ def quantize_fp8(X: np.ndarray):
 
 def rerank_size(k: int, beams: Sequence[int], factor: int) -> int:
     """Size R of the candidate set the precision form re-ranks on the full
-    rows: factor * k, capped at 512 when k and every beam are at most 512,
+    rows: R0 = factor * k, or f * k * r1 for factor = -f (r1 = the last beam,
+    the number of leaves probed: the "4 k r" set of the precision form at
+    f = 4); R = R0 capped at 512 when R0, k and every beam are at most 512,
     else at 2048."""
-    cap = 512 if max([int(k)] + [int(b) for b in beams]) <= 512 else 2048
-    return min(int(factor) * int(k), cap)
+    r0 = -int(factor) * int(k) * int(beams[-1]) if int(factor) < 0 else int(factor) * int(k)
+    cap = 512 if max([int(k), r0] + [int(b) for b in beams]) <= 512 else 2048
+    return min(r0, cap)
 
 
 def query_one_lowp(index: OracleIndex, q: np.ndarray, k: int, r, rank_protos,

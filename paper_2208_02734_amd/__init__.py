@@ -71,7 +71,8 @@ class mask_allocator(ctypes.Structure):
 
 class mask_server_params(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_int64), ("max_batch_queries", ctypes.c_int32),
-                ("n_streams", ctypes.c_int32), ("batch_window_us", ctypes.c_int32)]
+                ("n_streams", ctypes.c_int32), ("batch_window_us", ctypes.c_int32),
+                ("beam_eighths", ctypes.c_int32 * MAX_LEVELS)]
 
 
 class mask_server_stats(ctypes.Structure):
@@ -109,7 +110,7 @@ def lib() -> ctypes.CDLL:
     L.mask_build.argtypes = [P(mask_matrix), P(mask_build_params), P(mask_allocator), VP, P(VP)]
     L.mask_query.argtypes = [VP, P(mask_matrix), I32, I32, VP, VP, VP]
     L.mask_query_debug.argtypes = [VP, P(mask_matrix), I32, I32, VP, VP, VP, VP]
-    L.mask_query_ragged.argtypes = [VP, P(mask_matrix), VP, VP, VP, I32, I32, VP, VP, VP]
+    L.mask_query_ragged.argtypes = [VP, P(mask_matrix), VP, VP, VP, I32, I32, VP, VP, VP, VP]
     L.mask_query_beams.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP]
     L.mask_query_range.argtypes = [VP, P(mask_matrix), VP, I32, I32, VP, VP, VP, VP]
     L.mask_point_query.argtypes = [VP, P(mask_matrix), VP, VP, VP, VP, VP]
@@ -461,11 +462,12 @@ def mask_query_screened_noalloc(index: Index, queries, k: int, beams: Sequence[i
 
 
 def mask_query_ragged(index: Index, queries, k_i, r_i, stream=None, k_max: int = 0,
-                      r_max: int = 0):
+                      r_max: int = 0, beam_eighths: Optional[Sequence[int]] = None):
     """Per-query k and r (int32 CUDA tensors of length nq); returns
     (ids, dist, offsets): query i's results are ids[offsets[i]:offsets[i+1]].
     k_max / r_max: bounds passed to the library (raised to the largest k_i /
-    r_i when smaller)."""
+    r_i when smaller).  beam_eighths: optional beam profile (one entry per
+    level, top first): query i keeps ceil(r_i * e / 8) prototypes there."""
     torch = _torch()
     m = _matrix(queries)
     k_i = k_i.to(device=queries.device, dtype=torch.int32).contiguous()
@@ -477,9 +479,12 @@ def mask_query_ragged(index: Index, queries, k_i, r_i, stream=None, k_max: int =
     dist = torch.empty(max(total, 1), dtype=torch.float32, device=queries.device)
     k_max = max(int(k_max), int(k_i.max().item()) if queries.shape[0] else 1)
     r_max = max(int(r_max), int(r_i.max().item()) if queries.shape[0] else 1)
+    prof = None
+    if beam_eighths is not None:
+        prof = (ctypes.c_int32 * len(beam_eighths))(*[int(e) for e in beam_eighths])
     _check(lib().mask_query_ragged(index.handle, ctypes.byref(m), k_i.data_ptr(), r_i.data_ptr(),
-                                   off.data_ptr(), k_max, r_max, ids.data_ptr(), dist.data_ptr(),
-                                   _stream_handle(stream)))
+                                   off.data_ptr(), k_max, r_max, prof, ids.data_ptr(),
+                                   dist.data_ptr(), _stream_handle(stream)))
     return ids[:total], dist[:total], off
 
 
@@ -649,9 +654,14 @@ class MaskServer:
     host results out)."""
 
     def __init__(self, index: Index, arena_bytes: int = 1 << 30, max_batch_queries: int = 65536,
-                 n_streams: int = 2, batch_window_us: int = 0):
+                 n_streams: int = 2, batch_window_us: int = 0,
+                 beam_eighths: Optional[Sequence[int]] = None):
+        prof = [int(e) for e in (beam_eighths or [])]
+        if len(prof) > MAX_LEVELS:
+            raise MaskError(1, "beam profile longer than the level limit")
         p = mask_server_params(int(arena_bytes), int(max_batch_queries), int(n_streams),
-                               int(batch_window_us))
+                               int(batch_window_us),
+                               (ctypes.c_int32 * MAX_LEVELS)(*(prof + [0] * (MAX_LEVELS - len(prof)))))
         h = ctypes.c_void_p()
         _check(lib().mask_server_create(index.handle, ctypes.byref(p), None, ctypes.byref(h)))
         self.handle = h

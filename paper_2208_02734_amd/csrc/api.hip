@@ -451,7 +451,8 @@ mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, in
                        const int32_t* k_arr, const int32_t* r_arr, const int64_t* out_off,
                        int32_t* out_ids, float* out_dist, int32_t* sel, void* hip_stream,
                        const int32_t* r_levels = nullptr, const float* radius = nullptr,
-                       int32_t* out_count = nullptr, int32_t* out_leaf = nullptr) {
+                       int32_t* out_count = nullptr, int32_t* out_leaf = nullptr,
+                       const int32_t* beam_eighths = nullptr) {
   try {
     MASK_CHECK(ix != nullptr, "index is NULL");
     if (ix->sparse) check_csr(q, "queries (CSR index)");
@@ -490,7 +491,16 @@ mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, in
       qa.radius = radius;
       qa.out_count = out_count;
     }
-    for (int l = 0; l <= kMaxLevels; ++l) qa.r_lev[l] = 0;
+    for (int l = 0; l <= kMaxLevels; ++l) qa.r_lev[l] = qa.beam_e8[l] = 0;
+    if (beam_eighths) {
+      MASK_CHECK(r_arr != nullptr, "a beam profile needs per-query r");
+      for (int d = 0; d < ix->n_levels; ++d) {
+        const int64_t e8 = beam_eighths[d];
+        MASK_CHECK(e8 >= 0 && (r * e8 + 7) / 8 <= kMaxBeam,
+                   "beam profile: every level's beam at r_max must be in [1, 2048]");
+        qa.beam_e8[ix->n_levels - d] = (int)e8;
+      }
+    }
     if (r_levels) {
       for (int d = 0; d < ix->n_levels; ++d) {
         MASK_CHECK(r_levels[d] >= 1 && r_levels[d] <= kMaxBeam, "beam must be in [1, 2048]");
@@ -637,7 +647,7 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
     ix->n_levels = L;
     ix->levels.assign(p->levels, p->levels + L);
     ix->level_n = sizes;
-    ix->rerank_factor = p->rerank_factor > 0 ? p->rerank_factor
+    ix->rerank_factor = p->rerank_factor != 0 ? p->rerank_factor
                                              : (p->precision == MASK_FP8_E4M3 ? 48 : 4);
     const int ld = ix->ld;
     const int64_t n = data->n;
@@ -917,14 +927,14 @@ mask_status mask_query_screened_noalloc(const mask_index* ix, const mask_matrix*
 
 mask_status mask_query_ragged(const mask_index* ix, const mask_matrix* q, const int32_t* k_i,
                               const int32_t* r_i, const int64_t* out_off, int32_t k_max,
-                              int32_t r_max, int32_t* out_ids, float* out_dist,
-                              void* hip_stream) {
+                              int32_t r_max, const int32_t* beam_eighths, int32_t* out_ids,
+                              float* out_dist, void* hip_stream) {
   if (!k_i || !r_i || !out_off) {
     set_error("k_i, r_i and out_off are required");
     return MASK_ERR_INVALID;
   }
   return query_impl(ix, q, k_max, r_max, k_i, r_i, out_off, out_ids, out_dist, nullptr,
-                    hip_stream);
+                    hip_stream, nullptr, nullptr, nullptr, nullptr, beam_eighths);
 }
 
 mask_status mask_query_range(const mask_index* ix, const mask_matrix* q, const float* radius,
@@ -1319,7 +1329,7 @@ mask_status mask_import(const mask_matrix* data, int32_t n_levels, const mask_le
     if (sparse && (ix->precision != MASK_FP32 || metric != MASK_L2))
       throw Error{MASK_ERR_UNSUPPORTED, "CSR data: L2 metric, FP32 form only"};
     ix->sparse = sparse;
-    ix->rerank_factor = (p && p->rerank_factor > 0) ? p->rerank_factor
+    ix->rerank_factor = (p && p->rerank_factor != 0) ? p->rerank_factor
                         : (ix->precision == MASK_FP8_E4M3 ? 48 : 4);
     ix->n_levels = L;
     ix->levels.assign(levels, levels + L);

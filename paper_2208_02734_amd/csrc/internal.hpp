@@ -383,6 +383,9 @@ struct QueryArgs {
   int64_t nq;
   int k, r;                 // uniform values, or the maxima when k_arr / r_arr are set
   int r_lev[kMaxLevels + 1];  // beam per level (index = level), 0 = use r
+  // beam profile of a ragged batch (index = level): query i keeps
+  // ceil(r_i * beam_e8[level] / 8) prototypes there; 0 = r_i
+  int beam_e8[kMaxLevels + 1];
   const int32_t* k_arr;     // per-query k (device) or null
   const int32_t* r_arr;     // per-query r (device) or null
   const int64_t* out_off;   // per-query output offset (device) or null: qi * k

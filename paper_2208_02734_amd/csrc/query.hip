@@ -19,6 +19,7 @@
 // ranks them.
 #include "internal.hpp"
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -292,12 +293,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     }
   }
   unsigned long long rows_seen = 0;
-  // Cap of the precision form's re-rank set, from this query's own k and
-  // beams (512 when none exceeds 512, else 2048), so that a query's result
-  // does not depend on the other queries of a ragged batch; the LDS class
-  // (CAPB) covers the whole batch and so every query's cap.
-  bool big = k > 512 || r > 512;
-  for (int l = 1; l <= L; ++l) big = big || qa.r_lev[l] > 512;
+  // This query's beam at level l (top level first in r_lev / the profile).
+  auto beam_at = [&](int l) -> int {
+    if (qa.r_lev[l] > 0) return qa.r_lev[l];
+    if (qa.beam_e8[l] > 0) return min((r * qa.beam_e8[l] + 7) / 8, CAPB);
+    return r;
+  };
+  // Re-rank set of the precision forms: rerank_factor * k candidates, or
+  // with a negative factor f, |f| * k * (the level-1 beam); capped at 512
+  // when it, k and every beam are at most 512, else at 2048, so that a
+  // query's result does not depend on the other queries of a ragged batch
+  // (the LDS class, CAPB, covers the whole batch and so every query's cap).
+  const int64_t R0 = a.rerank_factor > 0
+                         ? (int64_t)a.rerank_factor * k
+                         : (int64_t)(-a.rerank_factor) * k * (int64_t)beam_at(1);
+  bool big = k > 512 || r > 512 || R0 > 512;
+  for (int l = 1; l <= L; ++l) big = big || beam_at(l) > 512;
   const int64_t rerank_cap = big ? 2048 : 512;
 
   for (int lev = L; lev >= 0; --lev) {
@@ -307,14 +318,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     const uint32_t m = s_pre[n_par];
     if (scr == nullptr) rows_seen += m;  // rows read, not screened scores
     // the data layer of the BF16 form keeps an oversized set for the FP32 re-rank
-    uint32_t want = (lev == 0) ? (uint32_t)k : (uint32_t)(qa.r_lev[lev] > 0 ? qa.r_lev[lev] : r);
+    uint32_t want = (lev == 0) ? (uint32_t)k : (uint32_t)beam_at(lev);
     // rows read in BF16 at every level, or in FP8 at the data layer only:
     // three mantissa bits are too coarse to choose prototypes
     bool low = B16 || (F8 && lev == 0);
     bool rerank = false;
     if (lev == 0 && LOWP) {
-      // the re-rank set: rerank_factor * k candidates, at most the query's cap
-      const int64_t R = min(min((int64_t)a.rerank_factor * k, rerank_cap), (int64_t)CAPB);
+      const int64_t R = min(min(R0, rerank_cap), (int64_t)CAPB);
       if ((int64_t)m > R && R > k) {
         want = (uint32_t)R;
         rerank = true;
@@ -949,7 +959,20 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   const bool b16 = a.precision == MASK_BF16;
   // LDS class from the beams and k; the BF16 re-rank set fits the class
   int need = qa.k > qa.r ? qa.k : qa.r;
-  for (int l = 1; l <= a.n_levels; ++l) need = qa.r_lev[l] > need ? qa.r_lev[l] : need;
+  int r1 = qa.r;  // the largest level-1 beam of the launch
+  for (int l = 1; l <= a.n_levels; ++l) {
+    const int pb = qa.r_lev[l] > 0   ? qa.r_lev[l]
+                   : qa.beam_e8[l] > 0 ? (qa.r * qa.beam_e8[l] + 7) / 8  // the profile's largest
+                                       : qa.r;
+    need = pb > need ? pb : need;
+    if (l == 1) r1 = pb;
+  }
+  if (a.precision != MASK_FP32 && !a.sparse) {
+    // the largest re-rank set of the launch (kMaxBeam at most)
+    const int64_t R = a.rerank_factor > 0 ? (int64_t)a.rerank_factor * qa.k
+                                          : (int64_t)(-a.rerank_factor) * qa.k * r1;
+    need = (int)std::max<int64_t>(need, std::min<int64_t>(R, kMaxBeam));
+  }
   if (a.sparse) {
     launch2<16, 0, 4, false, 1>(a, qa, need, s);
     check_launch("descent_csr");

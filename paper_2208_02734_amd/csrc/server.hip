@@ -128,6 +128,7 @@ struct Batch {
 struct mask_server {
   const mask_index* ix = nullptr;
   mask_server_params p{};
+  bool profile = false;  // p.beam_eighths sets per-level beams
   mask::Arena mem;
   char* dev = nullptr;   // device arena
   char* host = nullptr;  // pinned staging, same offsets
@@ -264,7 +265,8 @@ bool launch_one(mask_server* s) {
   const mask_status rc = mask_query_ragged(
       s->ix, &m, reinterpret_cast<const int32_t*>(d + B.L.k_off),
       reinterpret_cast<const int32_t*>(d + B.L.r_off), reinterpret_cast<const int64_t*>(d + B.L.o_off),
-      k_max, r_max, reinterpret_cast<int32_t*>(d + B.L.id_off),
+      k_max, r_max, s->profile ? s->p.beam_eighths : nullptr,
+      reinterpret_cast<int32_t*>(d + B.L.id_off),
       reinterpret_cast<float*>(d + B.L.d_off), st);
   if (rc != MASK_OK) throw Error{rc, std::string("ragged query: ") + mask_last_error()};
   MASK_HIP(hipMemcpyAsync(h + B.L.id_off, d + B.L.id_off, B.L.bytes - B.L.id_off,
@@ -326,6 +328,11 @@ mask_status mask_server_create(const mask_index* ix, const mask_server_params* p
     auto s = std::make_unique<mask_server>(a);
     s->ix = ix;
     s->p = *p;
+    for (int d = 0; d < MASK_MAX_LEVELS; ++d) {
+      MASK_CHECK(p->beam_eighths[d] >= 0 && p->beam_eighths[d] <= 8 * kMaxBeam,
+                 "beam_eighths out of range");
+      s->profile = s->profile || (d < ix->n_levels && p->beam_eighths[d] > 0);
+    }
     s->dev = static_cast<char*>(s->mem.alloc_bytes((size_t)p->arena_bytes));
     void* h = nullptr;
     MASK_HIP(hipHostMalloc(&h, (size_t)p->arena_bytes, hipHostMallocDefault));
@@ -354,6 +361,10 @@ mask_status mask_server_submit(mask_server* s, const float* q_host, int32_t n_q,
     MASK_CHECK(s && q_host && ticket, "NULL argument");
     MASK_CHECK(n_q >= 1, "n_q < 1");
     MASK_CHECK(k >= 1 && k <= kMaxBeam && r >= 1 && r <= kMaxBeam, "k or r out of range");
+    if (s->profile)
+      for (int d = 0; d < s->ix->n_levels; ++d)
+        MASK_CHECK(((int64_t)r * s->p.beam_eighths[d] + 7) / 8 <= kMaxBeam,
+                   "r too large for the server's beam profile");
     const BatchLayout L = layout_for(n_q, (int64_t)n_q * k, s->ix->ld);
     if (L.bytes > (size_t)s->p.arena_bytes || n_q > s->p.max_batch_queries)
       throw Error{MASK_ERR_BUSY, "request can never fit the arena or the batch limit"};

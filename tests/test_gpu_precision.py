@@ -248,3 +248,28 @@ def test_ragged_rerank_set_follows_each_query(pk, precision):
         assert np.array_equal(ids[off[i]:off[i + 1]], host(i1)[0]), i
         assert np.array_equal(dist[off[i]:off[i + 1]], host(d1)[0]), i
     gix.free()
+
+
+@pytest.mark.parametrize("precision", ["fp8", "bf16"])
+def test_rerank_of_4kr_candidates_matches_the_oracle(pk, precision):
+    # rerank_factor -4: the re-rank set is 4 k r1 (r1 = leaves probed), above
+    # 512 for the wider beams (the large LDS class) and below it for the
+    # narrow ones
+    X, Q = _mixture(30_000, 96, 60, seed=370, nq=200)
+    levels = [(10, 150), (1, 50)]  # leaves of about 20 rows
+    gix = pk.mask_build(dev(X), levels, iters=6, seed=2, precision=precision,
+                        rerank_factor=-4)
+    oix = oracle_index_from_gpu(X, gix)
+    if precision == "fp8":
+        code, scale = mo.quantize_fp8(X)
+        leaf, rank = code * scale[:, None], oix.protos
+    else:
+        leaf = mo.quantize_bf16(X)
+        rank = [mo.quantize_bf16(P.astype(np.float32)) for P in oix.protos]
+    for beams in ([4, 8], [6, 24]):  # R = 320, then 960
+        assert mo.rerank_size(10, beams, -4) == 40 * beams[-1]
+        ids, dist, sel = (host(t) for t in pk.mask_query_beams(gix, dev(Q), 10, beams,
+                                                                debug=True))
+        fails = check_lowp_against_oracle(oix, Q, 10, beams, ids, dist, sel, rank, leaf, -4)
+        assert not fails, (beams, fails[:3])
+    gix.free()

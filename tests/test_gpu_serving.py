@@ -223,3 +223,72 @@ def test_served_rows_match_the_oracle(lowp_setup, precision):
         assert not fails, (p, n, k, r, fails[:2])
         checked += n
     assert checked >= 100
+
+
+# ----------------------------------------------- beam profile of a request
+
+PROFILE = [3, 3, 24]  # eighths of r per level, top first: r = 8 -> (3, 3, 24)
+
+
+def _profile_beams(r, n_levels):
+    prof = PROFILE[-n_levels:]
+    return [max(1, (r * e + 7) // 8) for e in prof]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_profile_ragged_equals_beams_alone(precision):
+    # a ragged batch with a beam profile: each query keeps ceil(r_i e / 8)
+    # prototypes per level and equals mask_query_beams alone with those beams
+    import torch
+    import paper_2208_02734_amd as pk
+    pk.lib()
+    mix = datagen.mixture_params(330, 60, 48, sigma_mode="loguniform", sigma_low=0.1,
+                                 sigma_high=3.0)
+    X = datagen.sample_mixture(mix, 50_000, 331)
+    Q = datagen.sample_mixture(mix, 60, 332)
+    ix = pk.mask_build(dev(X), [(10, 200), (1, 200), (1, 20)], iters=5, seed=3,
+                       precision=precision)
+    g = np.random.default_rng(31)
+    ks = g.integers(1, 100, size=60).astype(np.int32)
+    rs = g.choice([8, 32], size=60).astype(np.int32)
+    ids, dist, off = pk.mask_query_ragged(ix, dev(Q), torch.from_numpy(ks),
+                                          torch.from_numpy(rs), beam_eighths=PROFILE)
+    ids, dist, off = host(ids), host(dist), host(off)
+    for i in range(60):
+        beams = _profile_beams(int(rs[i]), 3)
+        i1, d1 = pk.mask_query_beams(ix, dev(Q[i:i + 1]), int(ks[i]), beams)
+        assert np.array_equal(ids[off[i]:off[i + 1]], host(i1)[0]), (i, beams)
+        assert np.array_equal(dist[off[i]:off[i + 1]], host(d1)[0]), (i, beams)
+    with pytest.raises(pk.MaskError) as e:  # a profile beam above 2048 at r_max
+        pk.mask_query_ragged(ix, dev(Q), torch.from_numpy(ks), torch.from_numpy(rs),
+                             r_max=1000, beam_eighths=PROFILE)
+    assert e.value.status == 1
+    ix.free()
+
+
+def test_server_with_a_beam_profile_serves_the_profile_beams(lowp_setup):
+    pk, ixs, X, Q = lowp_setup
+    ix = ixs["bf16"]
+    prof = PROFILE[-2:]  # two levels: r = 8 -> (3, 24), r = 32 -> (12, 96)
+    srv = pk.MaskServer(ix, arena_bytes=64 << 20, max_batch_queries=2048, n_streams=3,
+                        batch_window_us=10_000, beam_eighths=prof)
+    g = np.random.default_rng(37)
+    reqs, tickets = [], []
+    pos = 0
+    for _ in range(40):
+        n = int(g.integers(1, 16))
+        k = int(g.integers(1, 100))
+        r = int(g.choice([8, 32]))
+        reqs.append((pos, n, k, r))
+        tickets.append(srv.submit(Q[pos:pos + n], k, r))
+        pos += n
+    res = _drain(srv, tickets)
+    st = srv.stats()
+    srv.close()
+    assert st["batches"] < 40
+    for (p, n, k, r), t in zip(reqs, tickets):
+        ids, dist, _ = res[t]
+        beams = [max(1, (r * e + 7) // 8) for e in prof]
+        i1, d1 = pk.mask_query_beams(ix, dev(Q[p:p + n]), k, beams)
+        assert np.array_equal(ids, host(i1)), (p, n, k, r)
+        assert np.array_equal(dist, host(d1)), (p, n, k, r)

@@ -226,3 +226,19 @@ def test_screened_bound_without_the_query_split_term_is_caught(monkeypatch):
         return 2.0 ** -24 * (float(q @ q) + cmax)
     monkeypatch.setattr(oc, "screened_bound", bad)
     assert _fails(pins.test_screened_bound_covers_the_float32_expanded_form)
+
+
+def test_rerank_cap_from_k_and_beams_only_is_caught(monkeypatch):
+    # the cap must also rise when the set itself passes 512
+    def bad(k, beams, factor):
+        cap = 512 if max([k] + list(beams)) <= 512 else 2048
+        r0 = -factor * k * beams[-1] if factor < 0 else factor * k
+        return min(r0, cap)
+    monkeypatch.setattr(mo, "rerank_size", bad)
+    assert _fails(pins.test_rerank_size_caps)
+
+
+def test_rerank_set_without_the_leaf_beam_is_caught(monkeypatch):
+    monkeypatch.setattr(mo, "rerank_size",
+                        lambda k, beams, factor: min(abs(factor) * k, 2048))
+    assert _fails(pins.test_rerank_size_caps)

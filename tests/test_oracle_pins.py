@@ -486,9 +486,15 @@ def test_fp8_rows_reconstruct_within_half_a_step():
 
 def test_rerank_size_caps():
     assert mo.rerank_size(10, [3, 12, 104], 4) == 40
-    assert mo.rerank_size(200, [3, 12, 104], 4) == 512
+    # a set above 512 lifts the cap to 2048
+    assert mo.rerank_size(200, [3, 12, 104], 4) == 800
+    assert mo.rerank_size(100, [3, 12, 104], 5) == 500
     assert mo.rerank_size(200, [3, 600, 104], 4) == 800
     assert mo.rerank_size(600, [3], 48) == 2048
+    # -f: f * k * (leaves probed), the "4 k r" set
+    assert mo.rerank_size(10, [3, 3, 24], -4) == 960
+    assert mo.rerank_size(10, [2, 4, 12], -4) == 480
+    assert mo.rerank_size(10, [4, 8, 96], -4) == 2048
 
 
 def test_lowp_descent_on_exact_rows_is_the_plain_descent():
