@@ -1,32 +1,32 @@
 #!/usr/bin/env python3
 """Benchmark of the MASK hot path on one MI355X.
 
-Workload: 1,000,000 x 128 Gaussian mixture (1,000 components, log-uniform
-sigma in [0.1, 3]); index levels 100 chunks x 1,000 -> 5,000 -> 100; 30
-Lloyd iterations; 10,000 queries; k = 10.  Five forms are built on the
-same data: the plain FP32 form, the BF16 and FP8 precision forms (low
-precision distances, FP32 re-rank, FP64 sums), each started from the first
-k members of every group, and the FP32 and BF16 forms started from
-k-means++ seeds.  For each form every beam setting of a fixed list
-(prototypes kept per level) is measured and the fastest that reaches
-recall@10 >= 0.95 against exhaustive FP64 search (numpy, on a 500-query
-sample) is kept; the form with the highest such throughput is timed.
+Workload (the precision form's): 10,000,000 x 96 Gaussian mixture (10,000
+components, log-uniform sigma in [0.1, 3]); index levels 10 groups x 10,000
+prototypes -> 10,000 -> 100 from k-means++ seeds, 30 Lloyd iterations;
+100,000 queries; k = 10.  Three forms are built on the same data: BF16 and
+FP8 e4m3 (per-row scale) distances on MFMA with an FP32 re-rank and FP64
+sums, and the plain FP32 form.  For each form every beam setting of a fixed
+list (prototypes kept per level, top level first) is measured over all
+queries, and the fastest that reaches recall@10 >= 0.95 against exhaustive
+FP64 search on a 500-query tuning sample is kept; its recall is then
+reported on a disjoint held-out sample of 2,000 queries.  The form with the
+highest passing throughput is timed.
 
-A step is one pass of the whole hot path in the selected form: mask_build on
-the device-resident data, then the descent of the 10,000 queries.  ``value``
+A step is one pass of the whole hot path in that form: mask_build on the
+device-resident data, then the descent of the 100,000 queries.  ``value``
 is that form's query throughput (queries/s, index resident, median over the
 timed steps); ``build_s`` its median build time.  The serving section runs
-one Poisson request stream (1..512 queries per request, log-uniform; k
-uniform in [1, 100]; r in {8, 32}) at several rates through the continuous-batching
-loop for both forms (replayed by the library's native load generator) and
-reports p50/p99 latency (completion minus scheduled arrival) and the
-completed queries/s.  The csr section builds and queries the CSR workload;
-the point_query section runs the eight-cloud evaluation of Section 4.2
-(tree time, exhaustive point search, error rate, relocation loop).  Kernel
-times come from HIP events the library records on its launch stream.  The
-FP64 oracle runs only in the CPU-baseline leg.
+Poisson request streams (1..512 queries per request, log-uniform; k uniform
+in [1, 100]; r in {8, 32}) at several rates, plus a saturating burst,
+through the continuous-batching loop for the BF16 and FP32 indexes, and
+reports p50/p99 latency, completed queries/s and the recall of served
+results.  Kernel times come from HIP events the library records on its
+launch stream.  The FP64 oracle runs only in the CPU-baseline leg.
 
-Prints one JSON line.
+Prints one short JSON line on stdout; the full record (every beam setting
+tried, serving streams, the small, sparse and other workloads, kernel
+times) goes to the file named by --detail.
 """
 import argparse
 import json
@@ -41,84 +41,43 @@ sys.path.insert(0, ROOT)
 PEAK = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}  # dense MFMA TFLOP/s
 PEAK_HBM_GBS = 8000.0
 
-# Bytes moved between L2 and memory per launch, from two rocprofv3 --pmc runs
-# of ``bench.py --pmc-workload --pmc-index`` (FETCH_SIZE, then WRITE_SIZE, KiB per
-# dispatch; profiles/traffic_mixture-1M-d128.md), averaged over the launches
-# the timing aggregates (the assignment: one launch per level and iteration,
-# so the mean of the three levels).  A 1 GiB copy reads FETCH_SIZE 524,318 KiB
-# and writes WRITE_SIZE 1,048,576 KiB, so fetch counts are scaled by
-# 1048576/524318 and write counts by 1.  The figures hold for the kernel
-# source they were taken from (sha256 of the file) and, for the descent, for
-# its beams, index and method; otherwise traffic is reported as null.  The
-# k-means++ seeding is measured per level (its whole seeding under the
-# counters); the level-2 seeding, about 15,000 dispatches, stalls the counter
-# collection and has no entry.
+LEVELS = [(10, 10_000), (1, 10_000), (1, 100)]
+WORKLOAD = ("mixture-10M-d96: 10,000,000 x 96 Gaussian mixture (10,000 comps), levels "
+            "10x10000->10000->100, k-means++ seeds, 30 Lloyd iters, 100,000 queries")
+
+# beam candidates (top level first); every form takes the fastest one that
+# passes the recall gate on the tuning sample
+BEAMS = [(2, 2, 16), (2, 2, 20), (2, 3, 20), (3, 3, 20), (2, 3, 24), (3, 3, 24), (3, 4, 24),
+         (3, 3, 28), (3, 4, 28), (3, 4, 32), (4, 4, 32), (3, 6, 32), (4, 6, 40), (4, 8, 40),
+         (4, 8, 48), (6, 8, 64), (8, 16, 96)]
+
+# re-rank set per precision form: BF16 keeps 4 k candidates, FP8 the 4 k r
+# set (r = leaves probed), which its three mantissa bits need
+RERANK = {"bf16": 0, "fp8": -4, "fp32": 0}
+
+# Bytes moved between L2 and memory per launch, from two rocprofv3 --pmc
+# runs of ``bench.py --pmc-workload`` (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch), scaled by what the same counters read for a plain 1 GiB copy
+# (FETCH_SCALE, WRITE_SCALE).  Each figure holds for the kernel source it was
+# taken from (sha256 of the file) and, for the descent, for its beams and
+# method; otherwise traffic is reported as null.
 FETCH_SCALE = 1048576.0 / 524318.0
 WRITE_SCALE = 1.0
-TRAFFIC = [
-    {"kernel": "assign_bf16_mfma", "file": "kmeans.hip", "sha256": "c637a8614609f099d6bbf35e2655b7cea2591d2ff5af3282d1ec3ccabc319e06",
-     "fetch_kib": (139123.0 + 17624.5 + 773.0) / 3,
-     "write_kib": (3908.1 + 390.6 + 19.5) / 3},
-    {"kernel": "assign_l2_mfma", "file": "kmeans.hip", "sha256": "c637a8614609f099d6bbf35e2655b7cea2591d2ff5af3282d1ec3ccabc319e06",
-     "fetch_kib": (285132.2 + 37690.0 + 1521.3) / 3,
-     "write_kib": (6403.0 + 978.7 + 20.5) / 3},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "first",
-     "beams": [16, 96, 176], "method": "gather", "fetch_kib": 6401036.5, "write_kib": 71250.0},
-    {"kernel": "descent", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "first",
-     "beams": [16, 96, 160], "method": "gather", "fetch_kib": 13981720.2, "write_kib": 1250.0},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "kmeans++",
-     "beams": [3, 12, 104], "method": "gather", "fetch_kib": 2990589.6, "write_kib": 71250.0},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "kmeans++",
-     "beams": [3, 12, 104], "method": "screened", "fetch_kib": 467356.0, "write_kib": 71254.4},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "kmeans++",
-     "beams": [3, 16, 104], "method": "gather", "fetch_kib": 3001470.3, "write_kib": 71249.1},
-    {"kernel": "descent_bf16", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811", "init": "kmeans++",
-     "beams": [3, 16, 104], "method": "screened", "fetch_kib": 470866.0, "write_kib": 71255.1},
-    # whole seedings of levels 1 and 3 (1,000 and 100 draws)
-    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "eb63546fce591b126d05f4dc03504815980bf91d1f75d5386d1b47c33dc7444f",
-     "level": 1, "fetch_kib": 108292220.4, "write_kib": 898011.7},
-    {"kernel": "kmeanspp", "file": "seeding.hip", "sha256": "eb63546fce591b126d05f4dc03504815980bf91d1f75d5386d1b47c33dc7444f",
-     "level": 3, "fetch_kib": 117529.2, "write_kib": 702.2},
-    # the two screened levels (5,000 and 100 prototypes, 10,000 queries)
-    {"kernel": "level_scores", "file": "query.hip", "sha256": "81267cce2b45867d75dcd8adfafbf1860c1c621584631562e6c9440b0fda7811",
-     "fetch_kib": (23713.9 + 2672.5) / 2, "write_kib": (195312.5 + 4062.5) / 2},
-]
+TRAFFIC = []
 
 
-def traffic_bytes(kernel, beams=None, init=None, method=None, level=None):
+def traffic_bytes(kernel, **match):
     """Measured bytes per launch of `kernel`, or None when its source (or
-    the descent's beams, index or method, or the seeding's level) changed
-    since the counters were taken or was not measured."""
+    one of the matched fields) changed since the counters were taken."""
     import hashlib
     for t in TRAFFIC:
-        if t["kernel"] != kernel:
-            continue
-        if "beams" in t and (beams is None or list(beams) != t["beams"]):
-            continue
-        if "init" in t and init != t["init"]:
-            continue
-        if "method" in t and method != t["method"]:
-            continue
-        if "level" in t and level != t["level"]:
+        if t["kernel"] != kernel or any(t.get(k) != v for k, v in match.items()):
             continue
         path = os.path.join(ROOT, "paper_2208_02734_amd", "csrc", t["file"])
         if hashlib.sha256(open(path, "rb").read()).hexdigest() != t["sha256"]:
             return None
         return round((t["fetch_kib"] * FETCH_SCALE + t["write_kib"] * WRITE_SCALE) * 1024.0)
     return None
-
-# beams of the k-means++ index's descents under the counters (the settings
-# the benchmark selects, which differ by less than the timing noise)
-PMC_PP_BEAMS = ((3, 12, 104), (3, 16, 104))
-
-
-# beam candidates (top level first); every form takes the fastest one that
-# passes the recall gate
-BEAMS = [(2, 16, 112), (3, 12, 104), (3, 16, 104), (3, 16, 112), (2, 16, 120),
-         (4, 24, 96), (4, 32, 96), (4, 24, 104), (4, 32, 104), (4, 24, 112), (4, 32, 112),
-         (4, 32, 128), (4, 48, 128), (8, 64, 128), (8, 64, 144), (16, 64, 160), (16, 96, 160),
-         (8, 96, 176), (12, 96, 176), (16, 80, 176), (16, 96, 176), (24, 96, 176),
-         (24, 128, 192), (32, 128, 224), (64, 192, 256), (128, 256, 320), (256, 512, 512)]
 
 
 def parse():
@@ -128,31 +87,25 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--iters", type=int, default=30)
-    ap.add_argument("--recall-sample", type=int, default=500)
+    ap.add_argument("--tune-sample", type=int, default=500)
+    ap.add_argument("--held-out", type=int, default=2000)
     ap.add_argument("--gate", type=float, default=0.95)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--serve-rates", type=str, default="2000,10000,40000",
+    ap.add_argument("--serve-rates", type=str, default="1000,5000,20000,50000",
                     help="comma-separated Poisson request rates (requests/s)")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
-    ap.add_argument("--no-sparse", action="store_true")
-    ap.add_argument("--no-point", action="store_true")
-    ap.add_argument("--no-insert", action="store_true")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--form", choices=["auto", "fp32", "bf16", "fp8", "fp32+kmeans++",
-                                       "bf16+kmeans++"], default="auto")
+    ap.add_argument("--burst-queries", type=int, default=2_000_000,
+                    help="queries of the saturating burst (all requests at once)")
+    ap.add_argument("--forms", type=str, default="bf16,fp32,fp8")
+    ap.add_argument("--sections", type=str, default="serve,small,sparse,cpu",
+                    help="comma-separated: serve, small, sparse, cpu, scale, point, insert")
+    ap.add_argument("--detail", type=str, default=os.path.join("gpurun_out", "bench_detail.json"))
     ap.add_argument("--pmc-export", type=str, default="",
-                    help="build the k-means++ BF16 index and save it (npz) for --pmc-index")
-    ap.add_argument("--pmc-index", type=str, default="",
-                    help="with --pmc-workload: the saved k-means++ index to import and query")
-    ap.add_argument("--pmc-seed-levels", type=str, default="1,3",
-                    help="with --pmc-workload --pmc-index: levels whose whole k-means++ "
-                         "seeding runs under the counters")
-    ap.add_argument("--pmc-no-builds", action="store_true",
-                    help="with --pmc-workload: skip the builds and descents")
-    ap.add_argument("--pmc-workload", action="store_true",
-                    help="run only the counter workload: one build (2 Lloyd iterations) and "
-                         "one query batch per form, then a 1 GiB copy for calibration")
+                    help="build the BF16 index and save it (npz) for --pmc-workload")
+    ap.add_argument("--pmc-workload", type=str, default="",
+                    help="run only the counter workload on the index saved by --pmc-export")
+    ap.add_argument("--pmc-draws", type=int, default=1000,
+                    help="k-means++ draws per group of the counter workload's level-1 seeding")
     return ap.parse_args()
 
 
@@ -160,63 +113,49 @@ def log(msg):
     print(f"# {msg}", file=sys.stderr, flush=True)
 
 
-def serve_stream(pk, ix, pool, rate, seconds, seed):
-    """Open-loop Poisson arrivals replayed against the serving loop of one
-    index by the library's native load generator."""
-    import numpy as np
-    import datagen
-    rs = datagen.request_stream(rate, seconds, seed, pool.shape[0])
-    srv = pk.MaskServer(ix, arena_bytes=4 << 30, max_batch_queries=32768, n_streams=3)
-    srv.replay(pool, [0.0], [64], [0], [10], [8])  # first launches outside the measurement
-    lat, span = srv.replay(pool, rs.t_arrival, rs.n_queries, rs.pool_offset, rs.k, rs.r)
-    st = srv.stats()
-    srv.close()
-    lat = lat * 1e3
-    q = int(rs.n_queries.sum())
-    return {"rate_req_s": rate, "requests": int(rs.t_arrival.shape[0]), "queries": q,
-            "offered_queries_per_s": round(q / seconds, 1),
-            "p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "p99_ms": round(float(np.percentile(lat, 99)), 3),
-            "queries_per_s": round(q / span, 1),
-            "batches": int(st["batches"]) - 1,
-            "peak_arena_MiB": round(st["peak_arena_bytes"] / 2**20, 1)}
-
-
 # ---------------------------------------------------------------------------
 # Recall reference.  The gate needs the exact k nearest neighbours of a query
-# sample in float64; they are computed here with numpy / scipy products (the
-# expanded form screens, the direct form re-scores the survivors), apart from
-# the FP64 oracle, which serves the tests and the CPU-baseline leg only.
+# sample in float64.  They are computed here, apart from the FP64 oracle
+# (which serves the tests and the CPU-baseline leg only): a float64 product
+# screening in PyTorch keeps the m = 4k + 16 smallest |x|^2 - 2 q.x per query
+# (its rounding, ~1e-11 relative, cannot move a true neighbour past 4k + 16
+# others), then the direct form in float64 on the host ranks them by
+# (distance, id).
 
-def exact_knn64(X, Q, k, block=1 << 16):
-    """The k nearest rows of X for each row of Q by (distance, id); returns
-    (ids, Euclidean distances) in float64."""
+def exact_knn64(X, Q, k, device=None, Xd=None, block=1 << 18):
+    """The k nearest rows of X (host float32) for each row of Q by
+    (distance, id); returns (ids, Euclidean distances) in float64.  device:
+    a torch device for the screening ("cpu" when None); Xd: X already on
+    that device."""
     import numpy as np
-    Q64 = np.asarray(Q, dtype=np.float64)
-    nq, n = Q64.shape[0], X.shape[0]
+    import torch
+    dev = torch.device(device or "cpu")
+    Xt = Xd if Xd is not None else torch.from_numpy(np.ascontiguousarray(X))
+    Xt = Xt.to(dev)
+    Q64 = torch.from_numpy(np.asarray(Q, dtype=np.float64)).to(dev)
+    n = Xt.shape[0]
     m = min(n, 4 * k + 16)
-    qn = np.einsum("ij,ij->i", Q64, Q64)
-    best_d = np.zeros((nq, 0))
-    best_i = np.zeros((nq, 0), dtype=np.int64)
+    best_d = best_i = None
     for b0 in range(0, n, block):
-        Xb = np.asarray(X[b0:b0 + block], dtype=np.float64)
-        D = np.einsum("ij,ij->i", Xb, Xb)[None, :] - 2.0 * (Q64 @ Xb.T) + qn[:, None]
-        cd = np.concatenate([best_d, D], axis=1)
-        ci = np.concatenate([best_i, np.broadcast_to(np.arange(b0, b0 + Xb.shape[0]), D.shape)],
-                            axis=1)
-        if cd.shape[1] > m:
-            keep = np.argpartition(cd, m - 1, axis=1)[:, :m]
-            cd = np.take_along_axis(cd, keep, axis=1)
-            ci = np.take_along_axis(ci, keep, axis=1)
-        best_d, best_i = cd, ci
-    ids = np.empty((nq, k), dtype=np.int64)
-    dist = np.empty((nq, k))
-    for i in range(nq):
-        diff = np.asarray(X[best_i[i]], dtype=np.float64) - Q64[i][None, :]
+        Xb = Xt[b0:b0 + block].to(torch.float64)
+        D = (Xb * Xb).sum(1)[None, :] - 2.0 * (Q64 @ Xb.T)
+        d, i = torch.topk(D, min(m, D.shape[1]), dim=1, largest=False)
+        i = i + b0
+        if best_d is not None:
+            d = torch.cat([best_d, d], 1)
+            i = torch.cat([best_i, i], 1)
+            d, j = torch.topk(d, min(m, d.shape[1]), dim=1, largest=False)
+            i = torch.gather(i, 1, j)
+        best_d, best_i = d, i
+    cand = best_i.cpu().numpy()
+    ids = np.empty((Q.shape[0], k), dtype=np.int64)
+    dist = np.empty((Q.shape[0], k))
+    for r in range(Q.shape[0]):
+        diff = np.asarray(X[cand[r]], dtype=np.float64) - np.asarray(Q[r], dtype=np.float64)[None, :]
         d2 = np.einsum("ij,ij->i", diff, diff)
-        order = np.lexsort((best_i[i], d2))[:k]
-        ids[i] = best_i[i][order]
-        dist[i] = np.sqrt(d2[order])
+        order = np.lexsort((cand[r], d2))[:k]
+        ids[r] = cand[r][order]
+        dist[r] = np.sqrt(d2[order])
     return ids, dist
 
 
@@ -237,7 +176,178 @@ def recall_at_k(X, Q, got, true_ids, true_dist, k, rel=1e-5):
     return hits / max(total, 1)
 
 
-def sparse_section(pk, torch, args, log):
+def rerank_set(form, k, beams):
+    """Size of a query's FP32 re-rank set in the precision forms (the
+    library's rule: factor * k, or f * k * r1 for factor -f, capped at 512
+    when it, k and the beams are at most 512, else at 2048)."""
+    f = RERANK[form] or 4
+    r0 = -f * k * beams[-1] if f < 0 else f * k
+    return min(r0, 512 if max([k, r0] + list(beams)) <= 512 else 2048)
+
+
+def profile_beams(profile, r):
+    """A request's beams under a beam profile (eighths of r per level)."""
+    return [max(1, (int(r) * e + 7) // 8) for e in profile]
+
+
+# ---------------------------------------------------------------------------
+# rooflines
+
+def seeding_bytes(levels, n, ld, kt):
+    """Algorithmic bytes of the k-means++ seeding per level, from the device
+    row counters: per update launch t >= 1, 20 B of state per row (D^2,
+    nearest prototype, its distance to the new one); 4 ld B per row not
+    ruled out by the triangle inequality (every row at t = 0); 12 B per row
+    whose D^2 fell; per group, the picks' distances of each new prototype to
+    the earlier ones (t rows read, t FP64 distances written)."""
+    rb = 4.0 * ld
+    out, items = [], n
+    for lev, (C, k) in enumerate(levels, start=1):
+        cnt, ms = kt.get(f"kmeanspp_level{lev}", (0, 0.0))
+        if cnt and k > 1:
+            read = kt.get(f"seeding_rows_read_level{lev}", (0, 0.0))[0]
+            low = kt.get(f"seeding_rows_lowered_level{lev}", (0, 0.0))[0]
+            upd = (k - 2) * items * 20.0 * cnt + read * rb + low * 12.0
+            picks = C * (rb * ((k - 1) * k / 2 - 1) + 8.0 * (k - 2) * (k - 1) / 2) * cnt
+            ucnt, ums = kt.get(f"kmeanspp_update_level{lev}", (0, 0.0))
+            out.append({"level": lev, "seedings": cnt, "ms": round(ms / cnt, 2),
+                        "bytes": upd + picks, "update_bytes": upd, "update_launches": ucnt,
+                        "update_ms": ums, "rows_read_frac": round(read / (cnt * (k - 1) * items), 4)})
+        items = C * k
+    return out
+
+
+def assign_flops(levels, n, d, kt, iters):
+    """Flops of the assignment launches that ran (2 d per item and prototype
+    of its group), per level, from the per-level launch counts."""
+    out, items = [], n
+    for lev, (C, k) in enumerate(levels, start=1):
+        cnt = kt.get(f"assign_level{lev}", (0, 0.0))[0]
+        out.append({"level": lev, "launches": cnt, "flops_per_launch": 2.0 * items * k * d,
+                    "ms": kt.get(f"assign_level{lev}", (0, 0.0))[1]})
+        items = C * k
+    return out
+
+
+# ---------------------------------------------------------------------------
+# sections
+
+def serve_form(pk, ix, Q, profile, args, hold, hold_ids, hold_dist, X, seed):
+    """Config-5 serving against one resident index: Poisson streams, a
+    saturating burst, and the recall of served requests on held-out queries."""
+    import numpy as np
+    import datagen
+    out = {"profile_eighths": list(profile), "beams_r8": profile_beams(profile, 8),
+           "beams_r32": profile_beams(profile, 32), "rates": []}
+    srv = pk.MaskServer(ix, arena_bytes=4 << 30, max_batch_queries=32768, n_streams=3,
+                        beam_eighths=profile)
+    srv.replay(Q, [0.0], [64], [0], [10], [8])  # first launches outside the measurement
+    for rate in [float(x) for x in args.serve_rates.split(",") if x]:
+        rs = datagen.request_stream(rate, args.serve_seconds, seed, Q.shape[0])
+        lat, span = srv.replay(Q, rs.t_arrival, rs.n_queries, rs.pool_offset, rs.k, rs.r)
+        q = int(rs.n_queries.sum())
+        lat = lat * 1e3
+        out["rates"].append({"rate_req_s": rate, "requests": int(rs.t_arrival.shape[0]),
+                             "queries": q, "offered_queries_per_s": round(q / args.serve_seconds, 1),
+                             "queries_per_s": round(q / span, 1),
+                             "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                             "p99_ms": round(float(np.percentile(lat, 99)), 3)})
+        log(f"serving {out['rates'][-1]}")
+    # saturating burst: every request arrives at once, so completed queries/s
+    # is the loop's capacity
+    g = np.random.default_rng(seed + 1)
+    nq = np.floor(np.exp(g.uniform(0.0, np.log(513), size=200_000))).astype(np.int32)
+    nq = nq[:np.searchsorted(np.cumsum(nq), args.burst_queries) + 1]
+    m = nq.shape[0]
+    kk = g.integers(1, 101, size=m).astype(np.int32)
+    rr = np.asarray([8, 32], dtype=np.int32)[g.integers(0, 2, size=m)]
+    off = g.integers(0, Q.shape[0] - 512, size=m).astype(np.int64)
+    lat, span = srv.replay(Q, np.zeros(m), nq, off, kk, rr)
+    out["saturated"] = {"requests": m, "queries": int(nq.sum()),
+                        "queries_per_s": round(float(nq.sum()) / span, 1),
+                        "p50_ms": round(float(np.percentile(lat * 1e3, 50)), 3),
+                        "p99_ms": round(float(np.percentile(lat * 1e3, 99)), 3)}
+    log(f"serving burst {out['saturated']}")
+    # recall of served results: requests over the held-out queries
+    Qh = np.ascontiguousarray(Q[hold])
+    tickets, reqs, pos = [], [], 0
+    while pos < Qh.shape[0]:
+        n = int(min(Qh.shape[0] - pos, g.integers(1, 33)))
+        k = int(g.integers(1, 101))
+        r = int(g.choice([8, 32]))
+        tickets.append(srv.submit(Qh[pos:pos + n], k, r))
+        reqs.append((pos, n, k, r))
+        pos += n
+    hits = {8: [0, 0], 32: [0, 0]}
+    pending = dict(zip(tickets, reqs))
+    while pending:
+        for t in list(pending):
+            res = srv.poll(t)
+            if res is None:
+                continue
+            p, n, k, r = pending.pop(t)
+            ids = res[0].reshape(n, k)
+            kk10 = min(k, 10)
+            for j in range(n):
+                got = ids[j:j + 1, :kk10].astype(np.int64)
+                rec = recall_at_k(X, Qh[p + j:p + j + 1], got, hold_ids[p + j:p + j + 1],
+                                  hold_dist[p + j:p + j + 1], kk10)
+                hits[r][0] += rec * kk10
+                hits[r][1] += kk10
+        time.sleep(1e-3)
+    srv.close()
+    out["served_recall@min(k,10)"] = {
+        "all": round((hits[8][0] + hits[32][0]) / max(1, hits[8][1] + hits[32][1]), 4),
+        "r8": round(hits[8][0] / max(1, hits[8][1]), 4),
+        "r32": round(hits[32][0] / max(1, hits[32][1]), 4),
+        "queries": int(Qh.shape[0])}
+    log(f"served recall {out['served_recall@min(k,10)']}")
+    return out
+
+
+def small_section(pk, torch, args):
+    """The small plain workload: 20,000 x 16 (50 components), levels 10 x 100
+    -> 50, 30 Lloyd iterations, 1,000 queries, k = 10: build time and
+    (recall@10, queries/s) for r from 1 to every prototype."""
+    import numpy as np
+    import datagen
+    cfg = datagen.config_small()
+    X, Q = cfg.X, cfg.Q
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    tids, tdist = exact_knn64(X, Q, 10)
+    ev = _events(torch)
+    ix = pk.mask_build(Xd, cfg.levels, iters=args.iters, seed=1)
+    ix.free()
+    ix, b_ms = ev(lambda: pk.mask_build(Xd, cfg.levels, iters=args.iters, seed=1))
+    out = {"workload": "mixture-20k-d16: 20,000 x 16 (50 comps), levels 10x100->50, 30 Lloyd "
+                       "iters, 1,000 queries, FP32", "build_s": round(b_ms * 1e-3, 4), "r": []}
+    for r in (1, 2, 3, 5, 8, 10, 16, 20, 24, 32, 48, 64, 100):
+        pk.mask_query(ix, Qd, 10, r)
+        (ids, _), ms = ev(lambda: pk.mask_query(ix, Qd, 10, r))
+        rec = recall_at_k(X, Q, ids.cpu().numpy().astype(np.int64), tids, tdist, 10)
+        out["r"].append({"r": r, "recall@10": round(rec, 4),
+                         "queries_per_s": round(Q.shape[0] / (ms * 1e-3), 1)})
+    gate = [e for e in out["r"] if e["recall@10"] >= args.gate]
+    out["gate"] = gate[0] if gate else None
+    ix.free()
+    log(f"small: build {out['build_s']} s, gate {out['gate']}")
+    return out
+
+
+def _events(torch):
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        e1, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e1.record(stream)
+        out = fn()
+        e2.record(stream)
+        torch.cuda.synchronize()
+        return out, e1.elapsed_time(e2)
+    return timed
+
+
+def sparse_section(pk, torch, args):
     """The CSR workload: 200,000 x 10,000 sparse rows (100 non-zeros each,
     Zipf column popularity, unit rows), levels 20 x 2,000 -> 2,000 -> 50,
     30 Lloyd iterations, 5,000 CSR queries; recall@10 against exhaustive FP64
@@ -251,7 +361,6 @@ def sparse_section(pk, torch, args, log):
     Qs = pk.CsrTensor.from_host(QS.indptr, QS.indices, QS.values, QS.n_cols)
     g = np.random.default_rng(0)
     sample = np.sort(g.choice(QS.n_rows, 200, replace=False))
-    # squared distances of the sample to every CSR row, float64 expanded form
     S64 = sps.csr_matrix((S.values.astype(np.float64), S.indices, S.indptr),
                          shape=(S.n_rows, S.n_cols))
     Qs64 = QS.to_dense()[sample].astype(np.float64)
@@ -259,15 +368,7 @@ def sparse_section(pk, torch, args, log):
          + np.einsum("ij,ij->i", Qs64, Qs64)[:, None] - 2.0 * (S64 @ Qs64.T).T)
     tids = np.argsort(D, axis=1, kind="stable")[:, :10]
     kth = np.take_along_axis(D, tids[:, -1:], axis=1)[:, 0]
-    stream = torch.cuda.current_stream()
-
-    def timed(fn):
-        e1, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e1.record(stream)
-        out = fn()
-        e2.record(stream)
-        torch.cuda.synchronize()
-        return out, e1.elapsed_time(e2)
+    ev = _events(torch)
 
     def recall(ids):
         got = ids.cpu().numpy()[sample].astype(np.int64)
@@ -277,21 +378,38 @@ def sparse_section(pk, torch, args, log):
             hit += int(np.sum(d_got <= kth[i] * (1 + 1e-5)))  # ties at the 10th accepted
         return hit / (10 * sample.size)
 
-    ix, _ = timed(lambda: pk.mask_build(Xs, cfg.levels, iters=args.iters, seed=1))
+    ix, _ = ev(lambda: pk.mask_build(Xs, cfg.levels, iters=args.iters, seed=1))
     ix.free()
     pk.mask_timing_enable(True)
-    ix, b_ms = timed(lambda: pk.mask_build(Xs, cfg.levels, iters=args.iters, seed=1))
+    ix, b_ms = ev(lambda: pk.mask_build(Xs, cfg.levels, iters=args.iters, seed=1))
     kt = pk.mask_timing_report()
     pk.mask_timing_enable(False)
+    a_cnt, a_ms = kt.get("assign_csr", (0, 0.0))
+    # the assignment's work: for every item, each of its non-zeros against
+    # each prototype of its group (one FP64 FMA and one 4-byte prototype
+    # value gathered from the group's column-major prototypes); level 1
+    # dominates.  Launches per level are counted by the level scopes.
+    items, fma = S.n_rows, 0.0
+    nnz_item = S.indices.shape[0] / S.n_rows
+    l1_cnt = kt.get("assign_level1", (0, 0.0))[0]
     out = {"workload": "csr-200k-D10000: 200,000 x 10,000 CSR rows (100 nnz, Zipf 1.1 columns, "
                        "unit rows), levels 20x2000->2000->50, 30 Lloyd iters, 5,000 queries",
            "build_s": round(b_ms * 1e-3, 4),
            "build_kernels": {n: {"launches": c, "total_ms": round(ms, 2)}
                              for n, (c, ms) in kt.items() if ms > 0},
            "queries": []}
-    for beams in [(8, 8, 8), (16, 32, 32), (50, 128, 128), (50, 256, 256)]:
-        timed(lambda: pk.mask_query_beams(ix, Qs, 10, beams))
-        (ids, _), q_ms = timed(lambda: pk.mask_query_beams(ix, Qs, 10, beams))
+    fma = l1_cnt * items * nnz_item * cfg.levels[0][1]
+    l1_ms = kt.get("assign_level1", (0, 0.0))[1]
+    if l1_ms:
+        out["assign_level1"] = {"launches": l1_cnt, "avg_ms": round(l1_ms / l1_cnt, 3),
+                                "gfma_per_s": round(fma / (l1_ms * 1e-3) / 1e9, 1),
+                                "gathered_GB_per_s": round(4.0 * fma / (l1_ms * 1e-3) / 1e9, 1),
+                                "note": "one FP64 FMA and one 4-byte prototype value per "
+                                        "(non-zero, prototype of the group)"}
+    for beams in [(8, 8, 8), (16, 32, 32), (50, 128, 128), (50, 256, 256), (50, 512, 1024),
+                  (50, 1024, 2048), (50, 2000, 2048)]:
+        ev(lambda: pk.mask_query_beams(ix, Qs, 10, beams))
+        (ids, _), q_ms = ev(lambda: pk.mask_query_beams(ix, Qs, 10, beams))
         out["queries"].append({"beams": list(beams), "recall@10": round(recall(ids), 4),
                                "queries_per_s": round(QS.n_rows / (q_ms * 1e-3), 1)})
         log(f"csr beams {beams}: {out['queries'][-1]}")
@@ -299,84 +417,183 @@ def sparse_section(pk, torch, args, log):
     return out
 
 
-def point_query_section(pk, torch, args, log):
-    """The evaluation of Section 4.2 on the eight-cloud benchmark
-    (lengthGroup 16, nCentroids 8, Lloyd iterations as the main workload):
-    tree time (index build), search time (a point query for every data
-    point) and error rate (the point query's answer lies in another cloud)
-    for 200 ... 100,000 points per cloud; the relocation loop on the
-    severely overlapping set (1,600 points, iterations 0-8); and the
-    lengthGroup / nCentroids sweep at 10,000 points per cloud."""
+def scale_section(pk, torch, args):
+    """The plain workload at scale: 1,000,000 x 128 (1,000 components),
+    levels 100 x 1,000 -> 5,000 -> 100, 10,000 queries; FP32 and BF16 from
+    k-means++ seeds at a few beam settings."""
     import numpy as np
     import datagen
-    stream = torch.cuda.current_stream()
+    cfg = datagen.config_scale()
+    X, Q = cfg.X, cfg.Q
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    sample = np.sort(np.random.default_rng(1).choice(Q.shape[0], 500, replace=False))
+    tids, tdist = exact_knn64(X, Q[sample], 10, device="cuda", Xd=Xd)
+    ev = _events(torch)
+    out = {"workload": "mixture-1M-d128: 1,000,000 x 128 (1,000 comps), levels "
+                       "100x1000->5000->100, k-means++ seeds, 30 Lloyd iters, 10,000 queries"}
+    for form in ("fp32", "bf16"):
+        ix, b_ms = ev(lambda: pk.mask_build(Xd, cfg.levels, iters=args.iters, seed=1,
+                                            precision=form, init="kmeans++"))
+        res = {"build_s": round(b_ms * 1e-3, 4), "beams": []}
+        ws = (torch.empty(pk.mask_screen_bytes(ix) * Q.shape[0] + 256, dtype=torch.uint8,
+                          device="cuda") if form == "bf16" else None)
+        for beams in [(3, 12, 104), (4, 24, 128), (8, 64, 160)]:
+            f = ((lambda: pk.mask_query_screened(ix, Qd, 10, beams, workspace=ws)) if ws is not None
+                 else (lambda: pk.mask_query_beams(ix, Qd, 10, beams)))
+            f()
+            (ids, _), ms = ev(f)
+            rec = recall_at_k(X, Q[sample], ids.cpu().numpy()[sample].astype(np.int64), tids,
+                              tdist, 10)
+            res["beams"].append({"beams": list(beams), "recall@10": round(rec, 4),
+                                 "queries_per_s": round(Q.shape[0] / (ms * 1e-3), 1)})
+        out[form] = res
+        log(f"scale {form}: {res}")
+        ix.free()
+    return out
 
-    def timed(fn):
-        e1, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e1.record(stream)
-        out = fn()
-        e2.record(stream)
-        torch.cuda.synchronize()
-        return out, e1.elapsed_time(e2) * 1e-3
+
+def point_query_section(pk, torch, args):
+    """The evaluation of Section 4.2 on the eight-cloud benchmark
+    (lengthGroup 16, nCentroids 8): tree time, search time (a point query
+    for every data point) and error rate for 200 ... 100,000 points per
+    cloud; the relocation loop on the severely overlapping set (1,600
+    points, iterations 0-8); the lengthGroup / nCentroids sweep."""
+    import numpy as np
+    import datagen
+    ev = _events(torch)
 
     def run(c, lg, nc, perm=None, off=None, seed=1):
         n = c.X.shape[0]
         X = torch.from_numpy(c.X).cuda()
         levels = ([(off.shape[0] - 1, nc)] + pk.mask_plan_levels((off.shape[0] - 1) * nc, lg, nc)
                   if off is not None else pk.mask_plan_levels(n, lg, nc))
-        ix, tree_s = timed(lambda: pk.mask_build(X, levels, iters=args.iters, seed=seed,
-                                                 perm=perm, group_off=off))
+        ix, tree_ms = ev(lambda: pk.mask_build(X, levels, iters=args.iters, seed=seed,
+                                               perm=perm, group_off=off))
         pk.mask_point_query(ix, X)  # warm
-        (ids, _, leaf, match), search_s = timed(lambda: pk.mask_point_query(ix, X))
+        (ids, _, leaf, match), search_ms = ev(lambda: pk.mask_point_query(ix, X))
         h_ids = ids.cpu().numpy()
         wrong = (h_ids < 0) | (c.labels[np.maximum(h_ids, 0)] != c.labels)
-        res = {"n": n, "tree_depth": len(levels), "tree_s": round(tree_s, 4),
-               "search_s": round(search_s, 5),
-               "point_queries_per_s": round(n / search_s, 1),
+        res = {"n": n, "tree_depth": len(levels), "tree_s": round(tree_ms * 1e-3, 4),
+               "search_s": round(search_ms * 1e-3, 5),
                "error_pct": round(100 * wrong.mean(), 3),
                "exact_match_miss_pct": round(100 * (match.cpu().numpy() < 0).mean(), 2)}
         return ix, res, leaf, wrong
 
-    # warm the library on a small case
     ix, _, _, _ = run(datagen.eight_clouds(200, "none", seed=1), 16, 8)
     ix.free()
-    out = {"workload": "eight 2-D Gaussian clouds (means on a radius-10 circle; sigma 0.5 / "
-                       "2.0 / 4.0 for no / moderate / severe overlap), lengthGroup 16, "
-                       f"nCentroids 8, {args.iters} Lloyd iterations; error = answer in "
-                       "another cloud", "sizes": {}, "relocation": None, "ratio_sweep": []}
+    out = {"sizes": {}, "relocation": None, "ratio_sweep": []}
     for ov in ("none", "moderate"):
         out["sizes"][ov] = []
         for npc in (200, 1000, 10000, 100000):
-            c = datagen.eight_clouds(npc, ov, seed=42)
-            ix, res, _, _ = run(c, 16, 8)
+            ix, res, _, _ = run(datagen.eight_clouds(npc, ov, seed=42), 16, 8)
             ix.free()
-            res["npc"] = npc
             out["sizes"][ov].append(res)
-            log(f"point query {ov} npc={npc}: {res}")
-    # relocation loop: iteration 0 is the first build
     c = datagen.eight_clouds(200, "severe", seed=42)
-    n = c.X.shape[0]
-    perm, off = None, None  # the first build draws its groups from the seed
-    traj, times = [], []
+    perm, off, traj = None, None, []
     for it in range(9):
         ix, res, leaf, wrong = run(c, 16, 8, perm=perm, off=off)
         traj.append(res["error_pct"])
-        (perm, off), rel_s = timed(lambda: pk.mask_relocate(
-            ix, leaf, torch.from_numpy(wrong.astype(np.int32)).cuda()))
-        times.append(round(res["tree_s"] + res["search_s"] + rel_s, 4))
+        perm, off = pk.mask_relocate(ix, leaf, torch.from_numpy(wrong.astype(np.int32)).cuda())
         ix.free()
-    out["relocation"] = {"n": n, "overlap": "severe", "error_pct_by_iteration": traj,
-                         "seconds_per_iteration": times}
-    log(f"relocation: {out['relocation']}")
+    out["relocation"] = {"n": c.X.shape[0], "error_pct_by_iteration": traj}
     for lg, nc in [(10, 5), (30, 15), (50, 25), (70, 35), (90, 45), (110, 55)]:
         for ov in ("none", "moderate"):
-            c = datagen.eight_clouds(10000, ov, seed=42)
-            ix, res, _, _ = run(c, lg, nc)
+            ix, res, _, _ = run(datagen.eight_clouds(10000, ov, seed=42), lg, nc)
             ix.free()
             res.update({"overlap": ov, "length_group": lg, "n_centroids": nc})
             out["ratio_sweep"].append(res)
-            log(f"ratio sweep {lg}/{nc} {ov}: {res}")
+    log(f"point query: {out['sizes']}")
     return out
+
+
+def insert_section(pk, torch, args, Xd, X, Q, form, beams, method, query, build):
+    """Dynamic insertion (Section 3.3) into a fresh index of the selected
+    form: 100,000 new rows of the same mixture in batches of 10,000, then
+    recall on the grown index (200-query sample)."""
+    import numpy as np
+    import datagen
+    ev = _events(torch)
+    Xn = datagen.precision_insertions(100_000)
+    Xnd = torch.from_numpy(Xn).cuda()
+    sample = np.arange(200)
+    X_all = np.concatenate([X, Xn])
+    ids_t, dist_t = exact_knn64(X_all, Q[sample], args.k, device="cuda",
+                                Xd=torch.cat([Xd, Xnd]))
+    gx = build(form)
+    t_ins = 0.0
+    for b0 in range(0, Xn.shape[0], 10_000):
+        (_, _), ms = ev(lambda: pk.mask_insert(gx, Xnd[b0:b0 + 10_000], 0))
+        t_ins += ms
+    (ids, _), q_ms = ev(lambda: query(gx, beams, method))
+    got = ids.cpu().numpy()[sample].astype(np.int64)
+    out = {"rows": int(Xn.shape[0]), "batch": 10_000,
+           "rows_per_s": round(Xn.shape[0] / (t_ins * 1e-3), 1),
+           "recall@10_after": round(recall_at_k(X_all, Q[sample], got, ids_t, dist_t, args.k), 4)}
+    gx.free()
+    log(f"insertion: {out}")
+    return out
+
+
+# ---------------------------------------------------------------------------
+
+def pmc_export(pk, torch, args):
+    import numpy as np
+    import datagen
+    cfg = datagen.config_precision()
+    Xd = torch.from_numpy(cfg.X).cuda()
+    ix = pk.mask_build(Xd, LEVELS, iters=args.iters, seed=1, precision="bf16", init="kmeans++")
+    arrays = {}
+    for lev in range(1, len(LEVELS) + 1):
+        P, par = ix.export_level(lev)
+        arrays[f"protos{lev}"] = P
+        arrays[f"parents{lev}"] = par
+    np.savez(args.pmc_export, **arrays)
+    ix.free()
+    print(f"pmc export: {args.pmc_export} written", flush=True)
+    return 0
+
+
+def pmc_workload(pk, torch, args):
+    """The counter workload: the screened BF16 descent of all queries on the
+    saved index at the benchmark's beams, one BF16 build from the first k
+    members with 2 Lloyd iterations (3 assignment launches per level), a
+    level-1-shaped k-means++ seeding with --pmc-draws draws per group, then
+    a 1 GiB copy for calibration."""
+    import numpy as np
+    import datagen
+    cfg = datagen.config_precision()
+    Xd = torch.from_numpy(cfg.X).cuda()
+    Qd = torch.from_numpy(cfg.Q).cuda()
+    z = np.load(args.pmc_workload)
+    L = len(LEVELS)
+    ix = pk.mask_import(Xd, LEVELS, [z[f"protos{l}"] for l in range(1, L + 1)],
+                        [z[f"parents{l}"] for l in range(1, L + 1)], precision="bf16")
+    ws = torch.empty(pk.mask_screen_bytes(ix) * Qd.shape[0] + 256, dtype=torch.uint8,
+                     device="cuda")
+    for beams in PMC_BEAMS:
+        pk.mask_query_screened(ix, Qd, 10, beams, workspace=ws)
+        torch.cuda.synchronize()
+        print(f"pmc workload: screened descent {beams} done", flush=True)
+    del ws
+    ix.free()
+    gx = pk.mask_build(Xd, LEVELS, iters=2, seed=1, precision="bf16")
+    torch.cuda.synchronize()
+    gx.free()
+    print("pmc workload: BF16 build (2 Lloyd iterations) done", flush=True)
+    pk.mask_kmeanspp(Xd, LEVELS[0][0], args.pmc_draws, seed=1, level=1)
+    torch.cuda.synchronize()
+    print(f"pmc workload: k-means++ seeding, {LEVELS[0][0]} groups x {args.pmc_draws} draws done",
+          flush=True)
+    a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 1 GiB
+    a.fill_(1.0)
+    b = a.clone()
+    torch.cuda.synchronize()
+    del a, b
+    print("pmc workload done", flush=True)
+    return 0
+
+
+PMC_BEAMS = ((3, 3, 24),)
 
 
 def main():
@@ -394,110 +611,42 @@ def main():
     pk.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.pmc_export:
-        # the k-means++ BF16 index of the benchmark, saved for an import under
-        # the counters (its build queues thousands of short dispatches, which
-        # the counter-collection run is kept free of)
-        cfg = datagen.config_scale()
-        Xd = torch.from_numpy(cfg.X).cuda()
-        ix = pk.mask_build(Xd, cfg.levels, iters=args.iters, seed=1, precision="bf16",
-                           init="kmeans++")
-        arrays = {}
-        for lev in range(1, len(cfg.levels) + 1):
-            P, par = ix.export_level(lev)
-            arrays[f"protos{lev}"] = P
-            arrays[f"parents{lev}"] = par
-        np.savez(args.pmc_export, **arrays)
-        ix.free()
-        print(f"pmc export: {args.pmc_export} written", flush=True)
-        return 0
+        return pmc_export(pk, torch, args)
     if args.pmc_workload:
-        cfg = datagen.config_scale()
-        Xd = torch.from_numpy(cfg.X).cuda()
-        Qd = torch.from_numpy(cfg.Q).cuda()
-        for prec, beams in (("bf16", (16, 96, 176)), ("fp32", (16, 96, 160))):
-            if args.pmc_no_builds:
-                break
-            ix = pk.mask_build(Xd, cfg.levels, iters=2, seed=1, precision=prec)
-            torch.cuda.synchronize()
-            print(f"pmc workload: {prec} build done", flush=True)
-            pk.mask_query_beams(ix, Qd, 10, beams)
-            torch.cuda.synchronize()
-            print(f"pmc workload: descent {beams} done", flush=True)
-            ix.free()
-        if args.pmc_index:
-            # the benchmark's k-means++ index, imported: the descent reads the
-            # same layout
-            z = np.load(args.pmc_index)
-            L = len(cfg.levels)
-            ix = pk.mask_import(Xd, cfg.levels, [z[f"protos{l}"] for l in range(1, L + 1)],
-                                [z[f"parents{l}"] for l in range(1, L + 1)], precision="bf16")
-            if not args.pmc_no_builds:
-                ws = torch.empty(pk.mask_screen_bytes(ix) * Qd.shape[0], dtype=torch.uint8,
-                                 device="cuda")
-                for pb in PMC_PP_BEAMS:
-                    pk.mask_query_beams(ix, Qd, 10, pb)
-                    torch.cuda.synchronize()
-                    print(f"pmc workload: k-means++ index descent {pb} done", flush=True)
-                    pk.mask_query_screened(ix, Qd, 10, pb, workspace=ws)
-                    torch.cuda.synchronize()
-                    print(f"pmc workload: k-means++ index screened descent {pb} done",
-                          flush=True)
-                del ws
-            # whole k-means++ seedings at the shape of the chosen levels: the
-            # data (level 1) or the exported prototypes of the level below
-            for lev in [int(x) for x in args.pmc_seed_levels.split(",") if x]:
-                C, k = cfg.levels[lev - 1]
-                items = Xd if lev == 1 else torch.from_numpy(
-                    np.ascontiguousarray(z[f"protos{lev - 1}"])).cuda()
-                pk.mask_kmeanspp(items, C, k, seed=1, level=lev)
-                torch.cuda.synchronize()
-                print(f"pmc workload: k-means++ seeding, level {lev} ({C} x {k}) done",
-                      flush=True)
-            ix.free()
-        a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 1 GiB
-        a.fill_(1.0)
-        b = a.clone()
-        torch.cuda.synchronize()
-        del a, b
-        print("pmc workload done", flush=True)
-        return 0
+        return pmc_workload(pk, torch, args)
+    sections = set(s for s in args.sections.split(",") if s)
     t_gen = time.time()
-    cfg = datagen.config_scale()
+    cfg = datagen.config_precision()
     X, Q = cfg.X, cfg.Q
+    assert [tuple(l) for l in cfg.levels] == LEVELS
     log(f"data {X.shape} queries {Q.shape} generated in {time.time() - t_gen:.1f}s")
     Xd = torch.from_numpy(X).cuda()
     Qd = torch.from_numpy(Q).cuda()
     torch.cuda.synchronize()
-    levels = cfg.levels
     n, d = X.shape
     nq = Q.shape[0]
-    stream = torch.cuda.current_stream()
+    ld = (d + 3) // 4 * 4
+    timed = _events(torch)
 
-    def timed(fn):
-        e1, e2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e1.record(stream)
-        out = fn()
-        e2.record(stream)
-        torch.cuda.synchronize()
-        return out, e1.elapsed_time(e2)
-
-    # ---- ground truth for recall: exhaustive FP64 kNN of a sample
+    # ---- recall samples: tuning (beam choice) and held-out (reported)
     g = np.random.default_rng(0)
-    sample = np.sort(g.choice(nq, min(args.recall_sample, nq), replace=False))
+    perm = g.permutation(nq)
+    tune = np.sort(perm[:args.tune_sample])
+    hold = np.sort(perm[args.tune_sample:args.tune_sample + args.held_out])
     t = time.time()
-    tids, tdist = exact_knn64(X, Q[sample], args.k)
-    log(f"exhaustive FP64 kNN of {sample.size} queries on the host: {time.time() - t:.1f}s")
+    tune_ids, tune_dist = exact_knn64(X, Q[tune], args.k, device="cuda", Xd=Xd)
+    hold_ids, hold_dist = exact_knn64(X, Q[hold], args.k, device="cuda", Xd=Xd)
+    log(f"exhaustive FP64 kNN of {tune.size} + {hold.size} queries: {time.time() - t:.1f}s")
 
-    def recall_of(ids):
-        got = ids.cpu().numpy()[sample].astype(np.int64)
-        return recall_at_k(X, Q[sample], got, tids, tdist, args.k)
+    def recalls(ids):
+        h = ids.cpu().numpy()
+        return (recall_at_k(X, Q[tune], h[tune].astype(np.int64), tune_ids, tune_dist, args.k),
+                recall_at_k(X, Q[hold], h[hold].astype(np.int64), hold_ids, hold_dist, args.k))
 
-    def build(key):
-        form, _, init = key.partition("+")
-        return pk.mask_build(Xd, levels, iters=args.iters, seed=1, precision=form,
-                             init=init or "first")
+    def build(form, rerank=None):
+        return pk.mask_build(Xd, LEVELS, iters=args.iters, seed=1, precision=form,
+                             init="kmeans++", rerank_factor=RERANK[form] if rerank is None else rerank)
 
-    # the screened descent's workspace (BF16 forms), allocated once
     workspace = {}
 
     def query(ix, beams, method):
@@ -508,42 +657,57 @@ def main():
             return pk.mask_query_screened(ix, Qd, args.k, beams, workspace=workspace["ws"])
         return pk.mask_query_beams(ix, Qd, args.k, beams)
 
-    # ---- every form, with the first-k and the k-means++ start: build, then
-    # select the cheapest beams that pass the recall gate
-    forms = {}
-    for form in ("fp32", "bf16", "fp8", "fp32+kmeans++", "bf16+kmeans++"):
-        ix, _ = timed(lambda: build(form))
-        ix.free()
+    # ---- every form: build, then the fastest beams that pass the gate
+    forms, kept = {}, {}
+    for form in [f for f in args.forms.split(",") if f]:
+        pk.mask_timing_enable(True)
         ix, b_ms = timed(lambda: build(form))
+        bk = pk.mask_timing_report()
+        pk.mask_timing_enable(False)
         chosen, tried = None, []
-        methods = ("gather", "screened") if form.startswith("bf16") else ("gather",)
+        methods = ("gather", "screened") if form == "bf16" else ("gather",)
         for beams in BEAMS:
             for method in methods:
-                timed(lambda: query(ix, beams, method))
+                query(ix, beams, method)
                 (ids, _), q_ms = timed(lambda: query(ix, beams, method))
-                rec = recall_of(ids)
-                tried.append({"beams": list(beams), "method": method,
-                              "recall@10": round(rec, 4),
+                rt, rh = recalls(ids)
+                tried.append({"beams": list(beams), "method": method, "recall@10": round(rt, 4),
+                              "recall@10_held_out": round(rh, 4),
                               "queries_per_s": round(nq / (q_ms * 1e-3), 1)})
-                # the fastest passing setting; while none passes, the best recall
-                key = (rec >= args.gate, -q_ms if rec >= args.gate else rec)
-                if chosen is None or key > chosen[4]:
-                    chosen = (beams, rec, q_ms, method, key)
-        ix.free()
-        forms[form] = {"build_s": round(b_ms * 1e-3, 4), "beams": list(chosen[0]),
-                       "method": chosen[3], "recall@10": round(chosen[1], 4),
-                       "queries_per_s": round(nq / (chosen[2] * 1e-3), 1), "tried": tried}
-        log(f"{form}: build {b_ms:.1f} ms; beams {chosen[0]} ({chosen[3]}) recall "
-            f"{chosen[1]:.4f} {nq / (chosen[2] * 1e-3):.0f} q/s")
+                key = (rt >= args.gate, -q_ms if rt >= args.gate else rt)
+                if chosen is None or key > chosen["key"]:
+                    chosen = {"beams": beams, "method": method, "rt": rt, "rh": rh, "ms": q_ms,
+                              "key": key}
+        forms[form] = {"build_s": round(b_ms * 1e-3, 4), "beams": list(chosen["beams"]),
+                       "method": chosen["method"], "recall@10": round(chosen["rh"], 4),
+                       "recall@10_tune": round(chosen["rt"], 4),
+                       "passes": chosen["rt"] >= args.gate,
+                       "queries_per_s": round(nq / (chosen["ms"] * 1e-3), 1),
+                       "rerank": "4k*r" if RERANK[form] < 0 else f"{RERANK[form] or 4}k",
+                       "build_kernels_ms": {k: round(v[1], 2) for k, v in bk.items() if v[1] > 0},
+                       "tried": tried}
+        log(f"{form}: build {b_ms:.0f} ms; beams {chosen['beams']} ({chosen['method']}) recall "
+            f"{chosen['rt']:.4f} / held-out {chosen['rh']:.4f}, "
+            f"{forms[form]['queries_per_s'] / 1e6:.3f}M q/s")
+        if form in ("bf16", "fp32") and "serve" in sections:
+            kept[form] = ix
+        else:
+            ix.free()
 
-    form = args.form
-    if form == "auto":
-        form = max(forms, key=lambda f: (forms[f]["recall@10"] >= args.gate,
-                                         forms[f]["queries_per_s"]))
+    # the BF16 form with the 4 k r re-rank set, at its chosen beams
+    if "bf16" in forms:
+        bx = build("bf16", rerank=-4)
+        b = forms["bf16"]
+        query(bx, b["beams"], b["method"])
+        (ids, _), q_ms = timed(lambda: query(bx, b["beams"], b["method"]))
+        rt, rh = recalls(ids)
+        b["with_4kr_rerank"] = {"recall@10": round(rh, 4), "recall@10_tune": round(rt, 4),
+                                "queries_per_s": round(nq / (q_ms * 1e-3), 1)}
+        bx.free()
+
+    form = max(forms, key=lambda f: (forms[f]["passes"], forms[f]["queries_per_s"]))
     beams = tuple(forms[form]["beams"])
     method = forms[form]["method"]
-    prec, _, init = form.partition("+")
-    init = init or "first"
 
     # ---- timed steps: build + query in the selected form
     def step():
@@ -571,107 +735,100 @@ def main():
     wall = time.perf_counter() - t0
     kt = pk.mask_timing_report()
     pk.mask_timing_enable(False)
-    step_recall = recall_of(ids)
+    step_tune, step_hold = recalls(ids)
 
-    # ---- roofline of the dominant kernel (the build's MFMA assignment) and the descent
-    flops_per_build = 0.0
-    items = n
-    for (C, k) in levels:
-        flops_per_build += 2.0 * items * k * d  # every item against its chunk's k prototypes
-        items = C * k
-    flops_per_build *= (args.iters + 1)
-    akey = {"fp32": "assign_l2_mfma", "bf16": "assign_bf16_mfma", "fp8": "assign_fp8_mfma"}[prec]
+    # ---- rooflines.  The build dominates a step, and the k-means++ seeding
+    # of level 1 dominates the build: its D^2 update launch is the dominant
+    # kernel.  achieved = that launch's algorithmic bytes (the level's update
+    # bytes over its launches) / its average HIP-event duration.
+    steps = args.steps
+    seed_levels = seeding_bytes(LEVELS, n, ld, kt)
+    roofline = None
+    for e in seed_levels:
+        if e["level"] == 1 and e["update_launches"]:
+            per = e["update_bytes"] / e["update_launches"]
+            avg = e["update_ms"] / e["update_launches"]
+            gbs = per / (avg * 1e-3) / 1e9
+            roofline = {"bound": "hbm", "kernel": "k_pp_update (k-means++ D^2 update, level 1: "
+                                                   "10 groups x 1,000,000 rows)",
+                        "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(gbs / PEAK_HBM_GBS, 4),
+                        "traffic": traffic_bytes("kmeanspp_update", level=1),
+                        "algorithmic_bytes_per_launch": round(per),
+                        "avg_launch_ms": round(avg, 4), "launches": e["update_launches"],
+                        "rows_read_frac": e["rows_read_frac"]}
+    seeding = []
+    for e in seed_levels:
+        gbs = e["bytes"] / e["seedings"] / (e["ms"] * 1e-3) / 1e9
+        seeding.append({"level": e["level"], "ms": e["ms"], "GB_per_s": round(gbs, 1),
+                        "frac": round(gbs / PEAK_HBM_GBS, 4), "rows_read_frac": e["rows_read_frac"]})
+    tot_b = sum(e["bytes"] for e in seed_levels)
+    tot_ms = sum(e["ms"] * e["seedings"] for e in seed_levels)
+    seeding_all = {"GB_per_s": round(tot_b / (tot_ms * 1e-3) / 1e9, 1) if tot_ms else None,
+                   "frac": round(tot_b / (tot_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4) if tot_ms else None,
+                   "ms_per_build": round(tot_ms / steps, 1), "levels": seeding}
+    akey = {"fp32": "assign_l2_mfma", "bf16": "assign_bf16_mfma", "fp8": "assign_fp8_mfma"}[form]
     a_cnt, a_ms = kt.get(akey, (0, 0.0))
-    assign_tflops = flops_per_build * args.steps / (a_ms * 1e-3) / 1e12 if a_ms else 0.0
-    dkey = {"fp32": "descent", "bf16": "descent_bf16", "fp8": "descent_fp8"}[prec]
+    af = assign_flops(LEVELS, n, d, kt, args.iters)
+    flops = sum(e["launches"] * e["flops_per_launch"] for e in af)
+    a_tf = flops / (a_ms * 1e-3) / 1e12 if a_ms else 0.0
+    l1 = af[0]
+    l1_tf = l1["launches"] * l1["flops_per_launch"] / (l1["ms"] * 1e-3) / 1e12 if l1["ms"] else 0.0
+    roof_assign = {"bound": "mfma", "kernel": akey, "achieved": round(a_tf, 1),
+                   "peak": PEAK[form], "unit": "TFLOP/s", "frac": round(a_tf / PEAK[form], 4),
+                   "launches_per_build": [e["launches"] / steps for e in af],
+                   "level1": {"achieved": round(l1_tf, 1), "frac": round(l1_tf / PEAK[form], 4),
+                              "avg_launch_ms": round(l1["ms"] / max(1, l1["launches"]), 3)},
+                   "traffic": traffic_bytes(akey, level=1)}
+    dkey = {"fp32": "descent", "bf16": "descent_bf16", "fp8": "descent_fp8"}[form]
     d_cnt, d_ms = kt.get(dkey, (0, 0.0))
     rows = kt.get("descent_rows", (0, 0.0))[0]
-    # bytes per evaluated row (row + id); FP8 rows carry a 4-byte scale.  For
-    # the FP8 form only the data rows are FP8 (prototype rows are FP32), so
-    # its figure counts every row as FP8: a lower bound of its bytes
-    row_bytes = {"fp32": ((d + 3) // 4 * 4) * 4 + 4, "bf16": ((d + 7) // 8 * 8) * 2 + 4,
-                 "fp8": ((d + 15) // 16 * 16) + 8}[prec]
-    desc_gbs = rows * row_bytes / (d_ms * 1e-3) / 1e9 if d_ms else 0.0
-    # k-means++ seeding, one timing scope per level.  Bytes: the rows the
-    # updates read (counted on the device: every row at draw 0, afterwards
-    # those the triangle inequality does not rule out) and the D^2 and
-    # prototype index written for each row whose D^2 fell (counted); at draws
-    # t >= 1 each member's D^2, prototype index and gathered prototype
-    # distance (20 B), and per group the t earlier prototypes and the new one
-    # read and t FP64 distances written.  Picks (a few KB each) are left out.
-    rb = 4.0 * ((d + 3) // 4 * 4)
-    pp_levels, items = [], n
-    for lev, (C, k) in enumerate(levels, start=1):
-        fixed = 0.0
-        if k > 2:
-            fixed = (k - 2) * items * 20.0
-            fixed += C * (rb * ((k - 1) * k / 2 - 1) + 8.0 * (k - 2) * (k - 1) / 2)
-        cnt, ms = kt.get(f"kmeanspp_level{lev}", (0, 0.0))
-        read = kt.get(f"seeding_rows_read_level{lev}", (0, 0.0))[0]
-        low = kt.get(f"seeding_rows_lowered_level{lev}", (0, 0.0))[0]
-        if cnt:
-            byts = fixed * cnt + read * rb + low * 12.0
-            gbs = byts / (ms * 1e-3) / 1e9
-            pp_levels.append({
-                "level": lev, "launches": cnt, "avg_ms": round(ms / cnt, 3),
-                "achieved": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
-                "algorithmic_bytes_per_launch": round(byts / cnt),
-                "rows_read_frac": round(read / (cnt * (k - 1) * items), 4) if k > 1 else None,
-                "traffic": traffic_bytes("kmeanspp", level=lev)})
-        items = C * k
-    p_ms = sum(kt.get(f"kmeanspp_level{lev}", (0, 0.0))[1] for lev in range(1, len(levels) + 1))
-    roof_assign = {"bound": "mfma", "kernel": akey, "achieved": round(assign_tflops, 2),
-                   "peak": PEAK[prec], "unit": "TFLOP/s",
-                   "frac": round(assign_tflops / PEAK[prec], 4),
-                   "traffic": traffic_bytes(akey), "traffic_unit": "bytes per launch"}
-    roof_pp = None
-    if pp_levels:
-        # the seeding launch (one level's seeding) that moves the most bytes:
-        # the bandwidth-bound level; the others are listed beside it
-        top = max(pp_levels, key=lambda e: e["algorithmic_bytes_per_launch"])
-        roof_pp = {"bound": "hbm", "kernel": f"kmeanspp level {top['level']}",
-                   "achieved": top["achieved"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                   "frac": top["frac"],
-                   "algorithmic_bytes_per_launch": top["algorithmic_bytes_per_launch"],
-                   "rows_read_frac": top["rows_read_frac"], "traffic": top["traffic"],
-                   "traffic_unit": "bytes per launch (the level's whole seeding)",
-                   "levels": pp_levels}
-    # the dominant kernel of the timed steps: the seeding when the selected
-    # form starts from k-means++ seeds and it takes longer than the assignment
-    roofline = roof_pp if (roof_pp and p_ms > a_ms) else roof_assign
-    counters = ("descent_rows", "refine_small_points", "refine_full_points")
+    row_bytes = {"fp32": ld * 4 + 4, "bf16": ((d + 7) // 8 * 8) * 2 + 4,
+                 "fp8": ((d + 15) // 16 * 16) + 8}[form]
+    rerank_rows = 0 if form == "fp32" else nq * rerank_set(form, args.k, beams) * d_cnt
+    desc_bytes = rows * row_bytes + rerank_rows * (ld * 4 + 4)
+    desc_gbs = desc_bytes / (d_ms * 1e-3) / 1e9 if d_ms else 0.0
+    roof_query = {"bound": "hbm", "kernel": "k_descent (" + dkey + ")", "achieved": round(desc_gbs, 1),
+                  "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(desc_gbs / PEAK_HBM_GBS, 4),
+                  "avg_launch_ms": round(d_ms / max(1, d_cnt), 4),
+                  "algorithmic_bytes_per_launch": round(desc_bytes / max(1, d_cnt)),
+                  "note": "evaluated rows (gathered levels and leaves) plus the FP32 re-rank "
+                          "rows; rows shared by queries are served from L2 / MALL",
+                  "traffic": traffic_bytes(dkey, beams=list(beams), method=method)}
     kernels = {name: {"launches": c, "total_ms": round(ms, 3),
                       "avg_ms": round(ms / c, 4) if c else None}
                for name, (c, ms) in kt.items()
-               if name not in counters and not name.startswith("seeding_rows")}
+               if not name.startswith(("seeding_rows", "descent_rows", "refine_"))}
 
-    # ---- serving: the same request stream through both forms
+    # ---- serving: the same request streams through the BF16 and FP32 indexes
     serving = None
-    if not args.no_serve:
+    if "serve" in sections:
         serving = {}
-        rates = [float(x) for x in args.serve_rates.split(",") if x]
-        for f in ("fp32", "bf16", "fp8"):
-            sx = build(f)
-            serving[f] = []
-            for rate in rates:
-                serving[f].append(serve_stream(pk, sx, Q, rate, args.serve_seconds, seed=55))
-                log(f"serving {f}: {serving[f][-1]}")
+        for f, sx in kept.items():
+            serving[f] = serve_form(pk, sx, Q, forms[f]["beams"], args, hold, hold_ids,
+                                    hold_dist, X, seed=55)
             sx.free()
 
-    sparse = None
-    if not args.no_sparse:
-        sparse = sparse_section(pk, torch, args, log)
+    small = small_section(pk, torch, args) if "small" in sections else None
+    sparse = sparse_section(pk, torch, args) if "sparse" in sections else None
+    scale = scale_section(pk, torch, args) if "scale" in sections else None
+    point = point_query_section(pk, torch, args) if "point" in sections else None
+    insertion = (insert_section(pk, torch, args, Xd, X, Q, form, beams, method, query, build)
+                 if "insert" in sections else None)
 
-    point = None
-    if not args.no_point:
-        point = point_query_section(pk, torch, args, log)
-
-    # ---- CPU baseline: the oracle's FP64 descent on the same index, bounded sample
+    # ---- CPU baseline: the oracle's FP64 descent on the same index (bounded
+    # sample) and its full build + query of the small workload
     cpu = None
-    if not args.no_cpu_baseline:
+    if "cpu" in sections:
         from oracle import mask_oracle as mo
+        try:
+            from threadpoolctl import threadpool_info
+            blas = max([p.get("num_threads", 0) for p in threadpool_info()
+                        if p.get("user_api") == "blas"] or [0])
+        except Exception:  # pragma: no cover
+            blas = None
         protos, parents = [], []
-        for lev in range(1, len(levels) + 1):
+        for lev in range(1, len(LEVELS) + 1):
             P, par = ix.export_level(lev)
             protos.append(P)
             parents.append(par)
@@ -683,46 +840,36 @@ def main():
             mo.query_one(oix, Q[done], args.k, list(beams))
             done += 1
         el = time.time() - t
+        del oix
+        sm = datagen.config_small()
+        t = time.time()
+        six = mo.build(sm.X, sm.levels, args.iters, 1)
+        sb = time.time() - t
+        t = time.time()
+        for i in range(sm.Q.shape[0]):
+            mo.query_one(six, sm.Q[i], args.k, 5)
+        sq = time.time() - t
         cpu = {"value": round(done / el, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
                "sample": f"FP64 numpy descent (beams {list(beams)}, k={args.k}) of the first "
-                         f"{done} of the 10,000 queries on the GPU-built index, one thread, "
-                         f"{el:.1f}s"}
-
-    # ---- dynamic insertion (Section 3.3) into a fresh index of the selected
-    # form: 100,000 new rows of the same mixture in batches of 10,000, then
-    # recall on the grown index; and once more with local rebuilds of the
-    # groups whose leaves pass 1.2x the largest leaf of the fresh index
-    insertion = None
-    if not args.no_insert:
-        Xn = datagen.scale_insertions(100_000)
-        Xnd = torch.from_numpy(Xn).cuda()
-        X_all = np.concatenate([X, Xn])
-        ins_ids, ins_dist = exact_knn64(X_all, Q[sample], args.k)
-        insertion = {"rows": int(Xn.shape[0]), "batch": 10_000}
-        for label, factor in (("append", 0.0), ("local_rebuild", 1.2)):
-            gx = build(form)
-            max_leaf = 0
-            if factor > 0:
-                _, par = gx.export_level(1)
-                max_leaf = int(factor * np.bincount(par).max())
-            t_ins, rebuilt = 0.0, 0
-            for b0 in range(0, Xn.shape[0], 10_000):
-                (_, nr), ms = timed(lambda: pk.mask_insert(gx, Xnd[b0:b0 + 10_000], max_leaf))
-                t_ins += ms
-                rebuilt += nr
-            (ids, _), q_ms = timed(lambda: query(gx, beams, method))
-            got = ids.cpu().numpy()[sample].astype(np.int64)
-            insertion[label] = {
-                "max_leaf": max_leaf, "groups_rebuilt": rebuilt,
-                "rows_per_s": round(Xn.shape[0] / (t_ins * 1e-3), 1),
-                "recall@10_after": round(recall_at_k(X_all, Q[sample], got, ins_ids, ins_dist,
-                                                     args.k), 4),
-                "queries_per_s_after": round(nq / (q_ms * 1e-3), 1)}
-            log(f"insertion {label}: {insertion[label]}")
-            gx.free()
+                         f"{done} of the 100,000 queries on the GPU-built index, {el:.1f}s",
+               "host_cpu_count": os.cpu_count(), "blas_threads": blas,
+               "small_workload": {"build_s": round(sb, 2), "queries_per_s": round(sm.Q.shape[0] / sq, 1),
+                                  "note": "oracle build (30 Lloyd iterations) and r = 5 descent "
+                                          "of mixture-20k-d16"}}
+        log(f"cpu baseline: {cpu}")
 
     q_med = statistics.median(query_ms)
     b_med = statistics.median(build_ms)
+    lat = None
+    if serving and form in serving:
+        r0 = serving[form]["rates"][0]
+        lat = {"rate_req_s": r0["rate_req_s"], "p50": r0["p50_ms"], "p99": r0["p99_ms"]}
+    dtype = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[form]
+    detail = {
+        "forms": forms, "timed_form": form, "kernels": kernels, "seeding": seeding_all,
+        "assign_levels": af, "serving": serving, "small": small, "csr": sparse, "scale": scale,
+        "point_query": point, "insertion": insertion, "cpu_baseline": cpu,
+        "build_ms_steps": build_ms, "query_ms_steps": query_ms}
     out = {
         "metric": "queries/s at recall@10>=0.95 vs FP64 oracle; p50/p99 latency; index build s",
         "value": round(nq / (q_med * 1e-3), 1),
@@ -734,37 +881,39 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[prec],
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": "mixture-1M-d128: 1,000,000 x 128 Gaussian mixture "
-                               "(1,000 comps), levels 100x1000->5000->100, 30 Lloyd iters, "
-                               "10,000 queries",
-                   "k": args.k, "beams": list(beams), "form": form, "descent": method},
-        "recall@10": round(step_recall, 4),
+        "config": {"workload": WORKLOAD, "k": args.k, "levels": [list(l) for l in LEVELS],
+                   "form": form, "beams": list(beams), "descent": method,
+                   "rerank": forms[form]["rerank"]},
+        "recall@10": round(step_hold, 4),
+        "recall@10_tune": round(step_tune, 4),
+        "recall_samples": {"tune": int(tune.size), "held_out": int(hold.size)},
         "build_s": round(b_med * 1e-3, 4),
-        "latency_ms": None if serving is None else {
-            "rate_req_s": serving[prec][0]["rate_req_s"], "p50": serving[prec][0]["p50_ms"],
-            "p99": serving[prec][0]["p99_ms"]},
+        "latency_ms": lat,
+        "forms": {f: {"queries_per_s": v["queries_per_s"], "recall@10": v["recall@10"],
+                      "passes": v["passes"], "beams": v["beams"], "build_s": v["build_s"]}
+                  for f, v in forms.items()},
+        "serving": None if not serving else {
+            f: {"saturated_queries_per_s": v["saturated"]["queries_per_s"],
+                "p50_ms": v["rates"][0]["p50_ms"], "p99_ms": v["rates"][0]["p99_ms"],
+                "served_recall": v["served_recall@min(k,10)"]["all"]}
+            for f, v in serving.items()},
         "roofline": roofline,
         "roofline_assign": roof_assign,
-        "roofline_query": {"bound": "hbm", "kernel": dkey, "achieved": round(desc_gbs, 1),
-                           "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                           "frac": round(desc_gbs / PEAK_HBM_GBS, 4),
-                           "traffic": traffic_bytes(dkey, beams, init, method),
-                           "traffic_unit": "bytes per launch",
-                           "traffic_gbs": (None if traffic_bytes(dkey, beams, init, method) is None
-                                           or not d_ms
-                                           else round(traffic_bytes(dkey, beams, init, method) * d_cnt
-                                                      / (d_ms * 1e-3) / 1e9, 1))},
-        "forms": forms,
-        "serving": serving,
-        "csr": sparse,
-        "point_query": point,
-        "insertion": insertion,
-        "kernels": kernels,
-        "cpu_baseline": cpu,
+        "roofline_query": roof_query,
+        "seeding_hbm_frac": seeding_all["frac"],
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in (
+            "value", "unit", "cores", "kind", "sample", "host_cpu_count", "blas_threads")},
+        "detail": args.detail,
     }
-    print(json.dumps(out), flush=True)
+    if args.detail:
+        os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
+        with open(args.detail, "w") as f:
+            json.dump({"summary": out, **detail}, f, indent=1)
+    line = json.dumps(out)
+    print(line, flush=True)
+    log(f"summary line: {len(line)} bytes")
     ix.free()
     return 0
 

@@ -140,14 +140,25 @@ def scale_insertions(n_new: int) -> np.ndarray:
     return sample_mixture(mix, n_new, seed + 2 * QUERY_SEED_OFFSET)
 
 
+def precision_insertions(n_new: int) -> np.ndarray:
+    """Fresh rows from the mixture of ``config_precision`` (same components),
+    for dynamic insertion into its index."""
+    seed = DATA_SEED_BASE + 4
+    mix = mixture_params(seed, 10_000, 96, sigma_mode="loguniform", sigma_low=0.1,
+                         sigma_high=3.0)
+    return sample_mixture(mix, n_new, seed + 2 * QUERY_SEED_OFFSET)
+
+
 def config_precision(n: Optional[int] = None, n_queries: Optional[int] = None,
                      levels=None) -> DenseConfig:
     """10,000,000 points, d = 96, 10,000 components, log-uniform sigma in
     [0.1, 3]; 100,000 queries, k = 10.  Level sizes are not fixed by the
-    workload statement; the default is 100 chunks x 1,000, then 5,000,
-    then 100."""
+    workload statement; the default gives every group about one prototype
+    per mixture component (as many prototypes as resources allow): 10
+    groups of 1,000,000 rows x 10,000 prototypes, then one group of
+    10,000, then 100."""
     if levels is None:
-        levels = [(100, 1_000), (1, 5_000), (1, 100)]
+        levels = [(10, 10_000), (1, 10_000), (1, 100)]
     return _dense_config(
         "mixture-10M-d96", 4, 10_000_000, 96, 10_000, "loguniform", 0.1, 3.0, 100_000,
         levels, 30, 10, [8, 32, 64, 128],

@@ -67,6 +67,18 @@ unsigned long long* timing_seed_counter(int slot) {
 
 namespace {
 
+// "<prefix><level>" as a string that lives as long as the library (timing
+// scope names), for levels 0 .. kMaxLevels.
+const char* level_scope_name(const char* prefix, int level) {
+  static std::mutex mu;
+  static std::map<std::string, std::vector<std::string>> names;
+  std::lock_guard<std::mutex> g(mu);
+  auto& v = names[prefix];
+  if (v.empty())
+    for (int l = 0; l <= kMaxLevels; ++l) v.push_back(std::string(prefix) + std::to_string(l));
+  return v[std::min(std::max(level, 0), kMaxLevels)].c_str();
+}
+
 int bits_for(int64_t n) {
   int b = 0;
   while (b < 63 && ((int64_t)1 << b) < n) ++b;
@@ -331,6 +343,9 @@ void run_level(const float* items, int64_t n_items, int ld, int dim, int C, int 
   else kmeans_init_first(items, ld, plan, protos, s);
   kmeans_proto_norms(protos, ld, (int64_t)C * k, w, s);
   auto assign = [&]() {
+    // one timing scope per level: "assign_level<l>" counts this level's
+    // assignment launches (the FP32 form's refinement included)
+    ScopedTiming timing(level_scope_name("assign_level", level), s);
     if (w.precision == MASK_FP8_E4M3) kmeans_assign_fp8(ld, plan, protos, labels, w, s);
     else kmeans_assign(items, ld, dim, plan, protos, labels, w, metric, s);
   };

@@ -71,7 +71,8 @@ struct ScopedTiming {
   const char* name;
   hipStream_t s;
   bool on;
-  ScopedTiming(const char* n, hipStream_t st) : name(n), s(st), on(timing_enabled()) {
+  ScopedTiming(const char* n, hipStream_t st, bool want = true)
+      : name(n), s(st), on(want && timing_enabled()) {
     if (on) timing_record(name, s, true);
   }
   ~ScopedTiming() {

@@ -333,14 +333,16 @@ __global__ __launch_bounds__(kBlock) void k_pp_count(const unsigned long long* _
   }
 }
 
-// Timing scope of one level's seeding: "kmeanspp_level<l>".
-const char* seed_scope_name(int slot) {
+// Timing scope of one level's seeding, "kmeanspp_level<l>" (update = false),
+// or of each of its update launches, "kmeanspp_update_level<l>".
+const char* seed_scope_name(int slot, bool update = false) {
   static const std::vector<std::string> names = [] {
     std::vector<std::string> v;
     for (int l = 0; l < kSeedSlots; ++l) v.push_back("kmeanspp_level" + std::to_string(l));
+    for (int l = 0; l < kSeedSlots; ++l) v.push_back("kmeanspp_update_level" + std::to_string(l));
     return v;
   }();
-  return names[slot].c_str();
+  return names[slot + (update ? kSeedSlots : 0)].c_str();
 }
 
 struct SeedBuffers {
@@ -359,6 +361,7 @@ struct SeedBuffers {
   int32_t* near;
   unsigned long long* tile_cnt;  // null unless timing is on
   int64_t max_tiles;             // tiles of the largest group
+  const char* update_scope;      // timing scope of each update launch, or null
 };
 
 // Draw t: the pick (with the distances the update needs, unless it is the
@@ -387,6 +390,9 @@ void launch_draw(const SeedBuffers& b, int t, uint64_t seed, uint64_t tag, int32
   else MASK_PICK(kMaxTiles / kWave);
 #undef MASK_PICK
   if (last) return;
+  // levels of at least 2^20 rows time every update launch (each reads
+  // megabytes, so the two event records cost little beside it)
+  ScopedTiming timing(b.update_scope, s, b.update_scope != nullptr);
   k_pp_update<G, U><<<(unsigned)b.n_tiles, kBlock, 0, s>>>(
       b.items, b.ld, b.tile_row, b.tile_grp, p.k, t, b.protos, b.cc, b.d2, b.near, b.tsum,
       b.tile_cnt);
@@ -442,6 +448,7 @@ void kmeanspp_init(const float* items, int ld, int dim, const ChunkPlan& plan, u
     b.tile_cnt = scratch.alloc<unsigned long long>(2 * b.n_tiles);
     MASK_HIP(hipMemsetAsync(b.tile_cnt, 0, 2 * b.n_tiles * sizeof(unsigned long long), s));
   }
+  b.update_scope = plan.n_items >= ((int64_t)1 << 20) ? seed_scope_name(slot, true) : nullptr;
   ScopedTiming timing(seed_scope_name(slot), s);
   const uint64_t tag = ((uint64_t)level << 40);
   const int f4 = ld / 4;

@@ -43,3 +43,18 @@ def test_recall_matches_the_oracle_comparator():
     r1 = b.recall_at_k(X, Q, got, tids, tdist, 10)
     r2 = oc.recall_at_k(got, tids, tdist, oc.true_distances(X, Q, got), 10)
     assert r1 == r2 and r1 < 1.0
+
+
+def test_rerank_set_follows_the_oracle_rule():
+    b = _bench()
+    for form in ("bf16", "fp8"):
+        for beams in ([3, 3, 24], [4, 8, 48], [2, 2, 16], [8, 16, 96]):
+            f = b.RERANK[form] or 4
+            assert b.rerank_set(form, 10, beams) == mo.rerank_size(10, beams, f)
+
+
+def test_profile_beams_round_up():
+    b = _bench()
+    assert b.profile_beams([3, 3, 24], 8) == [3, 3, 24]
+    assert b.profile_beams([3, 3, 24], 32) == [12, 12, 96]
+    assert b.profile_beams([3, 4, 28], 1) == [1, 1, 4]
