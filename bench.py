@@ -104,6 +104,8 @@ def parse():
                     help="build the BF16 index and save it (npz) for --pmc-workload")
     ap.add_argument("--pmc-workload", type=str, default="",
                     help="run only the counter workload on the index saved by --pmc-export")
+    ap.add_argument("--pmc-forms", type=str, default="bf16",
+                    help="forms the counter workload builds (2 Lloyd iterations each)")
     ap.add_argument("--pmc-draws", type=int, default=1000,
                     help="k-means++ draws per group of the counter workload's level-1 seeding")
     return ap.parse_args()
@@ -576,14 +578,24 @@ def pmc_workload(pk, torch, args):
         print(f"pmc workload: screened descent {beams} done", flush=True)
     del ws
     ix.free()
-    gx = pk.mask_build(Xd, LEVELS, iters=2, seed=1, precision="bf16")
-    torch.cuda.synchronize()
-    gx.free()
-    print("pmc workload: BF16 build (2 Lloyd iterations) done", flush=True)
+    for form in [f for f in args.pmc_forms.split(",") if f]:
+        gx = pk.mask_build(Xd, LEVELS, iters=2, seed=1, precision=form)
+        torch.cuda.synchronize()
+        gx.free()
+        print(f"pmc workload: {form} build (2 Lloyd iterations) done", flush=True)
+    # the device row counters of the seeding (for its algorithmic bytes)
+    pk.mask_timing_enable(True)
     pk.mask_kmeanspp(Xd, LEVELS[0][0], args.pmc_draws, seed=1, level=1)
     torch.cuda.synchronize()
-    print(f"pmc workload: k-means++ seeding, {LEVELS[0][0]} groups x {args.pmc_draws} draws done",
-          flush=True)
+    kt = pk.mask_timing_report()
+    pk.mask_timing_enable(False)
+    C, k = LEVELS[0][0], args.pmc_draws
+    read = kt.get("seeding_rows_read_level1", (0, 0.0))[0]
+    low = kt.get("seeding_rows_lowered_level1", (0, 0.0))[0]
+    rb = 4.0 * ((Xd.shape[1] + 3) // 4 * 4)
+    upd = (k - 2) * Xd.shape[0] * 20.0 + read * rb + low * 12.0
+    print(f"pmc workload: k-means++ seeding, {C} groups x {k} draws done; rows read {read}, "
+          f"lowered {low}; update bytes {upd:.6e} over {k - 1} launches", flush=True)
     a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 1 GiB
     a.fill_(1.0)
     b = a.clone()

@@ -333,15 +333,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
       }
     }
     // The first round is short (2 * want keys, at least 256): its exact
-    // selection sets the threshold cheaply; later rounds append only keys
-    // below the threshold and fill the buffer before the next selection.
-    const uint32_t round = CAP - want;
-    const uint32_t first = min(round, max(2 * want, 256u));
+    // selection sets the threshold cheaply.  Later rounds take as many
+    // candidates as the buffer has room for and append only keys below the
+    // threshold; a selection runs when the buffer has less than 256 slots
+    // left, and after the last round.
+    const uint32_t first = min(CAP - want, max(2 * want, 256u));
     if (tid == 0) { sh.cnt = 0; sh.thr = thr0; sh.in_range = 0; }
     __syncthreads();
     uint64_t thr = thr0;
+    uint32_t held = 0;  // keys in the buffer when a round starts (the same in every thread)
     for (uint32_t base = 0; base < m;) {
-      const uint32_t len = (base == 0) ? first : round;
+      const uint32_t len = (base == 0) ? first : (uint32_t)CAP - held;
       const uint32_t end = (m - base < len) ? m : base + len;
       if (scr != nullptr) {
         // screened level: the distances were computed for the whole batch, so
@@ -575,11 +577,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
       }  // lane groups
       __syncthreads();
       const uint32_t cnt = sh.cnt < (uint32_t)CAP ? sh.cnt : (uint32_t)CAP;
-      if (cnt > want) {
+      if (cnt > want && (base == 0 || end == m || cnt + 256 > (uint32_t)CAP)) {
         block_select(s_buf, cnt, want, s_out, s_hist, sh, s_red);
         if (tid == 0) sh.cnt = want;
         __syncthreads();
         thr = sh.thr;
+        held = want;
+      } else {
+        // every thread has read the count before the next round appends to it
+        __syncthreads();
+        held = cnt;
       }
       base = end;
     }
@@ -1007,6 +1014,7 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
     else if (c8 <= 2) launch2<1, 2, 2, true>(a, qa, need, s);
     else if (c8 <= 4) launch2<1, 4, 1, true>(a, qa, need, s);
     else if (c8 <= 8) launch2<2, 4, 1, true>(a, qa, need, s);
+    else if (c8 <= 12) launch2<4, 3, 1, true>(a, qa, need, s);
     else if (c8 <= 16) launch2<4, 4, 1, true>(a, qa, need, s);
     else if (c8 <= 32) launch2<8, 4, 1, true>(a, qa, need, s);
     else launch2<16, 0, 1, true>(a, qa, need, s);
