@@ -6,6 +6,7 @@
 // |c^_j|^2 / 2 with c^_j = s_j q_j, no certification; sums stay FP64 on
 // the FP32 rows (the update is the plain form's).
 #include <cmath>
+#include <type_traits>
 
 #include "internal.hpp"
 
@@ -90,19 +91,29 @@ __global__ __launch_bounds__(kBlock) void k_quantize_fp8(const float* __restrict
   }
 }
 
+typedef int v8i32 __attribute__((ext_vector_type(8)));
+
 // FP8 screening, same tiling as the BF16 kernel: prototypes are MFMA rows
 // (staged through LDS, TN per tile), points are columns (PB x 32 per wave,
-// held in registers); MFMA k-slot (s, h, e) is dimension 16s + 8h + e, so a
-// lane feeds 8 consecutive bytes of a row.  The accumulators start at 0;
-// the epilogue forms s_i s_j acc - |c^_j|^2/2 and keeps the running best.
+// held in registers).  The accumulators start at 0; the epilogue forms
+// s_i s_j acc - |c^_j|^2/2 and keeps the running best.
+// Rows of 64 bytes or more use the K = 64 shape
+// (v_mfma_scale_f32_32x32x64_f8f6f4, both scales 2^0, twice the FP8 rate of
+// the K = 16 shape): in step s a lane feeds the 32 bytes 64s + 32h .. of its
+// row (h = lane / 32), zero past the row's end.  A and B take their K values
+// from the same lane and register positions, so the product runs over every
+// byte of both rows exactly once.  Shorter rows use
+// v_mfma_f32_32x32x16_fp8_fp8, k-slot (s, h, e) = dimension 16s + 8h + e.
 template <int DP, int PB, int TN, int MINB>
 __global__ __launch_bounds__(kBlock, MINB) void k_assign_fp8(
     const uint8_t* __restrict__ items, const float* __restrict__ iscale, int ldq,
     const uint8_t* __restrict__ protos, const float* __restrict__ pscale,
     const float* __restrict__ pnorm, const int64_t* __restrict__ chunk_off, int k,
     int tiles_per_chunk, int32_t* __restrict__ labels) {
-  constexpr int KS = DP / 16;
-  constexpr int LDW = DP + 16;  // bytes per LDS row (16-byte pad)
+  constexpr bool K64 = DP >= 64;
+  constexpr int KB = K64 ? 64 : 16;           // K of one MFMA
+  constexpr int KS = (DP + KB - 1) / KB;      // MFMA steps per row
+  constexpr int LDW = KS * KB + 16;  // bytes per LDS row (whole K blocks, 16-byte pad)
   constexpr int BM = 4 * 32 * PB;
   constexpr int V_PER_ROW = DP / 16;  // 16-byte vectors per row
   constexpr int LOADS = (TN * V_PER_ROW + kBlock - 1) / kBlock;
@@ -119,7 +130,8 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_fp8(
 
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int h = lane >> 5, col = lane & 31;
-  long bq[PB][KS];
+  using BOp = typename std::conditional<K64, v8i32, long>::type;
+  BOp bq[PB][KS];
   float sx[PB];
   int64_t pidx[PB];
 #pragma unroll
@@ -131,10 +143,21 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_fp8(
     sx[pb] = iscale[ok ? p : c0];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const int c = 16 * s + 8 * h;
-      long v = 0;
-      if (ok && c < ldq) v = *reinterpret_cast<const long*>(row + c);
-      bq[pb][s] = v;
+      if constexpr (K64) {
+        const int c = 64 * s + 32 * h;  // two 16-byte halves, zero past the row
+        uint4 lo = make_uint4(0u, 0u, 0u, 0u), hi = lo;
+        if (ok && c < ldq) lo = *reinterpret_cast<const uint4*>(row + c);
+        if (ok && c + 16 < ldq) hi = *reinterpret_cast<const uint4*>(row + c + 16);
+        v8i32 v;
+        v[0] = (int)lo.x; v[1] = (int)lo.y; v[2] = (int)lo.z; v[3] = (int)lo.w;
+        v[4] = (int)hi.x; v[5] = (int)hi.y; v[6] = (int)hi.z; v[7] = (int)hi.w;
+        bq[pb][s] = v;
+      } else {
+        const int c = 16 * s + 8 * h;
+        long v = 0;
+        if (ok && c < ldq) v = *reinterpret_cast<const long*>(row + c);
+        bq[pb][s] = v;
+      }
     }
   }
   const uint8_t* cbase = protos + (int64_t)chunk * k * ldq;
@@ -196,14 +219,36 @@ __global__ __launch_bounds__(kBlock, MINB) void k_assign_fp8(
       for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[pb][i] = 0.f;
-      const uint8_t* arow =
-          reinterpret_cast<const uint8_t*>(&s_c[buf][0]) + (cb * 32 + col) * LDW + 8 * h;
+      if constexpr (K64) {
+        const uint8_t* arow =
+            reinterpret_cast<const uint8_t*>(&s_c[buf][0]) + (cb * 32 + col) * LDW + 32 * h;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const long a = *reinterpret_cast<const long*>(arow + 16 * s);  // dims 16s + 8h .. +7
+        for (int s = 0; s < KS; ++s) {
+          // bytes 64s + 32h .. + 31 of the prototype row (inside the padded
+          // LDS row), zero past the row's end
+          const int c = 64 * s + 32 * h;
+          uint4 lo = *reinterpret_cast<const uint4*>(arow + 64 * s);
+          uint4 hi = *reinterpret_cast<const uint4*>(arow + 64 * s + 16);
+          if (c >= DP) lo = make_uint4(0u, 0u, 0u, 0u);
+          if (c + 16 >= DP) hi = make_uint4(0u, 0u, 0u, 0u);
+          v8i32 a;
+          a[0] = (int)lo.x; a[1] = (int)lo.y; a[2] = (int)lo.z; a[3] = (int)lo.w;
+          a[4] = (int)hi.x; a[5] = (int)hi.y; a[6] = (int)hi.z; a[7] = (int)hi.w;
 #pragma unroll
-        for (int pb = 0; pb < PB; ++pb)
-          acc[pb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, bq[pb][s], acc[pb], 0, 0, 0);
+          for (int pb = 0; pb < PB; ++pb)
+            acc[pb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, bq[pb][s], acc[pb], 0, 0,
+                                                                     0, 127, 0, 127);
+        }
+      } else {
+        const uint8_t* arow =
+            reinterpret_cast<const uint8_t*>(&s_c[buf][0]) + (cb * 32 + col) * LDW + 8 * h;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const long a = *reinterpret_cast<const long*>(arow + 16 * s);  // dims 16s + 8h .. +7
+#pragma unroll
+          for (int pb = 0; pb < PB; ++pb)
+            acc[pb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a, bq[pb][s], acc[pb], 0, 0, 0);
+        }
       }
       const int jbase = t * TN + cb * 32 + 4 * h;
 #pragma unroll

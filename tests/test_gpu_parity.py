@@ -193,6 +193,22 @@ def test_probe_all_is_exact_knn(pk):
     assert res.ok, res.messages
 
 
+@pytest.mark.parametrize("k", [10, 500])
+def test_many_rounds_at_the_data_layer(pk, k):
+    # 40,000 candidates at the data layer: the key buffer is filled and
+    # selected many times, and most later rounds add few or no keys (the
+    # threshold is tight), so rounds that end without a selection follow
+    # each other; probing every leaf must still give the exact k nearest
+    X, Q = _mixture(40_000, 16, 30, seed=71, nq=24)
+    gix = pk.mask_build(dev(X), [(1, 8)], iters=3, seed=4)
+    ids, dist = pk.mask_query(gix, dev(Q), k, 8)
+    tids, tdist = mo.exact_knn(X, Q, k)
+    true = oc.true_distances(X, Q, host(ids).astype(np.int64))
+    res = oc.check_knn(host(ids), host(dist), tids, tdist, true, REL)
+    assert res.ok, res.messages
+    gix.free()
+
+
 def test_one_to_one_ratio_is_exact(pk):
     # one prototype per item at every level (Section 5: exact search)
     n, d, k = 960, 6, 4

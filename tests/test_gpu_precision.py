@@ -155,6 +155,42 @@ def test_fp8_build_is_close_to_fp32(pk):
         assert np.all(got - D.min(axis=1) <= bound)
 
 
+@pytest.mark.parametrize("d", [40, 96, 128])
+def test_fp8_labels_are_the_argmax_of_the_fp8_scores(pk, d):
+    # The FP8 assignment ranks s_i s_j (q_i . q_j) - |c^_j|^2 / 2 with the
+    # rows and prototypes quantised as the oracle quantises them (OCP e4m3,
+    # one scale per row) and the product accumulated in FP32.  Every label
+    # must be an argmax of that score computed in FP64 here, up to the FP32
+    # accumulation of the products (d terms, each exact).  d = 40 takes the
+    # K = 16 MFMA shape, 96 and 128 the K = 64 one (96 with a half-empty
+    # last block).
+    X, _ = _mixture(20_000, d, 60, seed=380 + d)
+    C, k = 4, 150
+    g8 = pk.mask_build(dev(X), [(C, k)], iters=3, seed=1, precision="fp8")
+    P, par = g8.export_level(1)
+    qx, sx = mo.quantize_fp8(X)
+    qp, sp = mo.quantize_fp8(P)
+    cn = ((qp * sp[:, None]) ** 2).sum(1)
+    exact = 0
+    for c in range(C):
+        members = np.nonzero(par // k == c)[0]
+        Qm = qx[members].astype(np.float64)
+        Pc = qp[c * k:(c + 1) * k].astype(np.float64)
+        dot = Qm @ Pc.T
+        score = sx[members, None] * sp[None, c * k:(c + 1) * k] * dot - 0.5 * cn[None, c * k:(c + 1) * k]
+        absdot = np.abs(Qm) @ np.abs(Pc).T
+        tol = (d * 2.0 ** -24) * sx[members, None] * sp[None, c * k:(c + 1) * k] * absdot
+        got = par[members] - c * k
+        row = np.arange(members.size)
+        best = score.max(axis=1)
+        # the chosen prototype's score reaches the best within both scores' bounds
+        slack = tol[row, got] + tol.max(axis=1) + 1e-6 * np.abs(cn[c * k:(c + 1) * k]).max()
+        assert np.all(score[row, got] >= best - slack), c
+        exact += int(np.sum(score[row, got] == best))
+    assert exact >= 0.99 * X.shape[0], exact
+    g8.free()
+
+
 def test_fp8_query_distances_are_fp32_exact(pk):
     X, Q = _mixture(20_000, 96, 50, seed=310, nq=100)
     levels = [(10, 100), (1, 40)]
