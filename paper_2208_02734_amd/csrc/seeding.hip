@@ -458,6 +458,7 @@ void kmeanspp_init(const float* items, int ld, int dim, const ChunkPlan& plan, u
     else if (f4 <= 4) launch_draw<4, 1>(b, t, seed, tag, chosen, s);
     else if (f4 <= 8) launch_draw<8, 1>(b, t, seed, tag, chosen, s);
     else if (f4 <= 16) launch_draw<8, 2>(b, t, seed, tag, chosen, s);
+    else if (f4 <= 24) launch_draw<8, 2>(b, t, seed, tag, chosen, s);  // measured: 8 lanes beat 16 at d = 96
     else if (f4 <= 32) launch_draw<16, 2>(b, t, seed, tag, chosen, s);
     else launch_draw<16, 4>(b, t, seed, tag, chosen, s);
   }

@@ -56,7 +56,8 @@ def _compare(pts, gpu_picks, seed, level, c, k):
     return k
 
 
-@pytest.mark.parametrize("d,C,k,level", [(16, 4, 20, 1), (128, 3, 64, 2), (5, 6, 9, 3)])
+@pytest.mark.parametrize("d,C,k,level", [(16, 4, 20, 1), (128, 3, 64, 2), (5, 6, 9, 3),
+                                          (96, 3, 40, 1), (70, 2, 30, 2)])
 def test_seeds_match_oracle(pk, d, C, k, level):
     n = 3001
     X = _mixture(n, d, 25, seed=1000 + d)
@@ -155,7 +156,8 @@ def test_kmeanspp_on_given_groups_matches_oracle(pk):
     gix.free()
 
 
-@pytest.mark.parametrize("d,m,C,k", [(128, 7_000, 20, 150), (7, 40_000, 55, 30)])
+@pytest.mark.parametrize("d,m,C,k", [(128, 7_000, 20, 150), (7, 40_000, 55, 30),
+                                     (96, 18_000, 10, 120)])
 def test_seeds_at_scale_match_oracle(pk, d, m, C, k):
     # Levels whose rows take 64 MiB or more (longer tiles), on clustered data
     # where the triangle inequality skips most rows after the first draws.
