@@ -57,18 +57,6 @@ void timing_record(const char* name, hipStream_t s, bool start) {
   }
 }
 
-unsigned long long* timing_row_counter() { return timing().on ? timing().rows : nullptr; }
-unsigned long long* timing_refine_counter() {
-  return timing().on && timing().rows ? timing().rows + 1 : nullptr;
-}
-unsigned long long* timing_seed_counter(int slot) {
-  return timing().on && timing().rows ? timing().rows + 3 + 2 * slot : nullptr;
-}
-
-namespace {
-
-// "<prefix><level>" as a string that lives as long as the library (timing
-// scope names), for levels 0 .. kMaxLevels.
 const char* level_scope_name(const char* prefix, int level) {
   static std::mutex mu;
   static std::map<std::string, std::vector<std::string>> names;
@@ -78,6 +66,16 @@ const char* level_scope_name(const char* prefix, int level) {
     for (int l = 0; l <= kMaxLevels; ++l) v.push_back(std::string(prefix) + std::to_string(l));
   return v[std::min(std::max(level, 0), kMaxLevels)].c_str();
 }
+
+unsigned long long* timing_row_counter() { return timing().on ? timing().rows : nullptr; }
+unsigned long long* timing_refine_counter() {
+  return timing().on && timing().rows ? timing().rows + 1 : nullptr;
+}
+unsigned long long* timing_seed_counter(int slot) {
+  return timing().on && timing().rows ? timing().rows + 3 + 2 * slot : nullptr;
+}
+
+namespace {
 
 int bits_for(int64_t n) {
   int b = 0;
@@ -423,7 +421,7 @@ void build_sparse(mask_index& ix, const mask_matrix* data, const mask_build_para
     {
       Arena level_scratch(a, s);
       kmeans_sparse(items, ld, C, k, p->lloyd_iters, nullptr, st.protos_cm[l], st.labels[l],
-                    nullptr, level_scratch, s);
+                    nullptr, level_scratch, s, level_scope_name("assign_level", l));
       MASK_HIP(hipStreamSynchronize(s));
     }
     if (l < L) csr_from_dense(st.protos_cm[l], ld, sizes[l], ix.dim, items, scratch, scratch, s);

@@ -55,6 +55,9 @@ inline void check_launch(const char* what) {
 // HIP events on their stream; mask_timing_report sums the elapsed times per
 // kernel name.  Disabled, a ScopedTiming costs one branch.
 bool timing_enabled();
+// "<prefix><level>" as a string that lives as long as the library (a
+// timing scope name), for levels 0 .. kMaxLevels.
+const char* level_scope_name(const char* prefix, int level);
 void timing_record(const char* name, hipStream_t s, bool start);
 // Device counter the descent kernel adds its evaluated candidate rows to
 // while timing is enabled (null otherwise).
@@ -337,7 +340,8 @@ void csr_validate(const int64_t* ptr, const int32_t* col, int64_t n, int cols, i
 // means.  inertia_log: device [iters * n_chunks] or null.
 void kmeans_sparse(const Csr& items, int ld, int n_chunks, int k, int iters, const float* init,
                    float* protos, int32_t* labels, double* inertia_log, Arena& scratch,
-                   hipStream_t s);
+                   hipStream_t s,
+                   const char* level_scope = nullptr);
 
 // ------------------------------------------------------------ descent
 // (query.hip)

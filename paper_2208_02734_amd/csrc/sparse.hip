@@ -569,7 +569,7 @@ void csr_validate(const int64_t* ptr, const int32_t* col, int64_t n, int cols, i
 
 void kmeans_sparse(const Csr& items, int ld, int n_chunks, int k, int iters, const float* init,
                    float* protos, int32_t* labels, double* inertia_log, Arena& scratch,
-                   hipStream_t s) {
+                   hipStream_t s, const char* level_scope) {
   const int64_t n = items.n, np = (int64_t)n_chunks * k;
   const int cols = items.cols;
   // group offsets: split() of Algorithm 1
@@ -629,6 +629,7 @@ void kmeans_sparse(const Csr& items, int ld, int n_chunks, int k, int iters, con
   };
   auto assign = [&]() {
     ScopedTiming timing("assign_csr", s);
+    ScopedTiming level_timing(level_scope, s, level_scope != nullptr);
     const unsigned g = grid_for(n * kWave, kBlock);
     if (k <= 256)
       k_assign_csr<4, 4><<<g, kBlock, 0, s>>>(items.ptr, items.col, items.val, xnorm, PT, pnorm,
