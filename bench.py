@@ -63,7 +63,37 @@ RERANK = {"bf16": 0, "fp8": -4, "fp32": 0}
 # method; otherwise traffic is reported as null.
 FETCH_SCALE = 1048576.0 / 524318.0
 WRITE_SCALE = 1.0
-TRAFFIC = []
+TRAFFIC = [
+    {"kernel": "assign_bf16_mfma", "level": 1, "file": "kmeans.hip",
+     "sha256": "c637a8614609f099d6bbf35e2655b7cea2591d2ff5af3282d1ec3ccabc319e06",
+     "fetch_kib": 964578.5, "write_kib": 39062.5},
+    {"kernel": "assign_fp8_mfma", "level": 1, "file": "fp8.hip",
+     "sha256": "6b3f179b87b921c1e52a863e7485dc524324bb065fd6d036bb4445af341496dc",
+     "fetch_kib": 497022.5, "write_kib": 39062.5},
+    {"kernel": "descent_bf16", "beams": [3, 3, 24], "method": "screened", "file": "query.hip",
+     "sha256": "587bfc28cbbc52bd24582ed47c5800f2270f365360f83f4c3dea38d3c5ea0b77",
+     "fetch_kib": 9274825.1, "write_kib": 212503.4},
+]
+# The seeding update's counters were taken on a 1,000-draw level-1 seeding
+# (its launches read more rows than the timed builds' 10,000-draw ones):
+# measured over algorithmic bytes of the same launches.
+SEED_TRAFFIC_CHECK = {"file": "seeding.hip",
+                      "sha256": "081a45b92d3c3e5ba33d3375f4e3f8a54c9a83fc72c8807b7ea8601e6b228b6d",
+                      "measured_bytes": 3.6872e12, "algorithmic_bytes": 3.6716e12,
+                      "launches": 999}
+
+
+def seed_traffic_check():
+    """Measured / algorithmic bytes of the level-1 seeding update on the
+    counter workload, or None once the source changed."""
+    import hashlib
+    t = SEED_TRAFFIC_CHECK
+    path = os.path.join(ROOT, "paper_2208_02734_amd", "csrc", t["file"])
+    if hashlib.sha256(open(path, "rb").read()).hexdigest() != t["sha256"]:
+        return None
+    return {"measured_over_algorithmic": round(t["measured_bytes"] / t["algorithmic_bytes"], 4),
+            "launches": t["launches"],
+            "workload": "level-1 seeding, 1,000 draws per group (rocprofv3 FETCH_SIZE / WRITE_SIZE)"}
 
 
 def traffic_bytes(kernel, **match):
@@ -765,7 +795,8 @@ def main():
                                                    "10 groups x 1,000,000 rows)",
                         "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                         "frac": round(gbs / PEAK_HBM_GBS, 4),
-                        "traffic": traffic_bytes("kmeanspp_update", level=1),
+                        "traffic": None,
+                        "traffic_check": seed_traffic_check(),
                         "algorithmic_bytes_per_launch": round(per),
                         "avg_launch_ms": round(avg, 4), "launches": e["update_launches"],
                         "rows_read_frac": e["rows_read_frac"]}
@@ -791,7 +822,8 @@ def main():
                    "launches_per_build": [e["launches"] / steps for e in af],
                    "level1": {"achieved": round(l1_tf, 1), "frac": round(l1_tf / PEAK[form], 4),
                               "avg_launch_ms": round(l1["ms"] / max(1, l1["launches"]), 3)},
-                   "traffic": traffic_bytes(akey, level=1)}
+                   "traffic": traffic_bytes(akey, level=1),
+                   "traffic_unit": "bytes per level-1 launch"}
     dkey = {"fp32": "descent", "bf16": "descent_bf16", "fp8": "descent_fp8"}[form]
     d_cnt, d_ms = kt.get(dkey, (0, 0.0))
     rows = kt.get("descent_rows", (0, 0.0))[0]
