@@ -60,9 +60,35 @@ __device__ inline uint64_t wave_max_u64(uint64_t v) {
 // p % 3 and clears buffer (p + 1) % 3, which was last read in pass p - 2
 // (before the barrier of pass p - 1) and is next counted into after the
 // barrier of pass p.  hist: 3 * 256 counters.
+// Sets of at most kRankSelect keys are selected by rank instead (measured:
+// above 128 keys the radix passes are faster): every key counts the keys
+// below it (broadcast LDS reads, two keys per read), and a key of rank < want
+// goes to slot `rank` of out (ranks of distinct keys are distinct, so no slot
+// is written twice).  The kept keys come out sorted.
+constexpr uint32_t kRankSelect = 128;
+
 __device__ void block_select(uint64_t* buf, uint32_t m, uint32_t want, uint64_t* out,
                              uint32_t* hist, SelShared& sh, uint64_t* red) {
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  if (m <= kRankSelect) {
+    const uint32_t pairs = m / 2;
+    const ulonglong2* b2 = reinterpret_cast<const ulonglong2*>(buf);  // buf is 16-byte aligned
+    for (uint32_t i = tid; i < m; i += kBlock) {
+      const uint64_t v = buf[i];
+      uint32_t rank = 0;
+      for (uint32_t j = 0; j < pairs; ++j) {
+        const ulonglong2 w = b2[j];
+        rank += (w.x < v) + (w.y < v);
+      }
+      if (m & 1u) rank += buf[m - 1] < v;
+      if (rank < want) out[rank] = v;
+      if (rank == want - 1) sh.thr = v;
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < want; i += kBlock) buf[i] = out[i];
+    __syncthreads();
+    return;
+  }
   uint64_t lo = ~0ull, hi = 0ull;
   for (uint32_t i = tid; i < m; i += kBlock) {
     const uint64_t v = buf[i];
@@ -203,7 +229,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   extern __shared__ float4 s_q4[];  // ld/4 float4
   __shared__ int32_t s_qc[SP ? kQList : 1];
   __shared__ float s_qv[SP ? kQList : 1];
-  __shared__ uint64_t s_buf[CAP];
+  __shared__ __align__(16) uint64_t s_buf[CAP];
   __shared__ uint64_t s_out[CAPB];
   __shared__ uint32_t s_cnt[CAPB];      // child count of each kept prototype
   __shared__ uint32_t s_beg[CAPB];      // first child position of each
