@@ -228,23 +228,28 @@ def profile_beams(profile, r):
 def seeding_bytes(levels, n, ld, kt):
     """Algorithmic bytes of the k-means++ seeding per level, from the device
     row counters: per update launch t >= 1, 20 B of state per row (D^2,
-    nearest prototype, its distance to the new one); 4 ld B per row not
-    ruled out by the triangle inequality (every row at t = 0); 12 B per row
+    nearest prototype, its distance to the new one); 2 ldb B (the BF16 row)
+    per row not ruled out by the triangle inequality, and 4 ld B (the FP32
+    row) per row the BF16 screen leaves (every row at t = 0); 12 B per row
     whose D^2 fell; per group, the picks' distances of each new prototype to
     the earlier ones (t rows read, t FP64 distances written)."""
     rb = 4.0 * ld
+    rbb = 2.0 * ((ld + 7) // 8 * 8)
     out, items = [], n
     for lev, (C, k) in enumerate(levels, start=1):
         cnt, ms = kt.get(f"kmeanspp_level{lev}", (0, 0.0))
         if cnt and k > 1:
             read = kt.get(f"seeding_rows_read_level{lev}", (0, 0.0))[0]
+            exact = kt.get(f"seeding_rows_exact_level{lev}", (0, 0.0))[0]
             low = kt.get(f"seeding_rows_lowered_level{lev}", (0, 0.0))[0]
-            upd = (k - 2) * items * 20.0 * cnt + read * rb + low * 12.0
+            upd = ((k - 2) * items * 20.0 * cnt + (read - items * cnt) * rbb + exact * rb
+                   + low * 12.0)
             picks = C * (rb * ((k - 1) * k / 2 - 1) + 8.0 * (k - 2) * (k - 1) / 2) * cnt
             ucnt, ums = kt.get(f"kmeanspp_update_level{lev}", (0, 0.0))
             out.append({"level": lev, "seedings": cnt, "ms": round(ms / cnt, 2),
                         "bytes": upd + picks, "update_bytes": upd, "update_launches": ucnt,
-                        "update_ms": ums, "rows_read_frac": round(read / (cnt * (k - 1) * items), 4)})
+                        "update_ms": ums, "rows_read_frac": round(read / (cnt * (k - 1) * items), 4),
+                        "rows_exact_frac": round(exact / (cnt * (k - 1) * items), 5)})
         items = C * k
     return out
 
@@ -620,12 +625,13 @@ def pmc_workload(pk, torch, args):
     kt = pk.mask_timing_report()
     pk.mask_timing_enable(False)
     C, k = LEVELS[0][0], args.pmc_draws
-    read = kt.get("seeding_rows_read_level1", (0, 0.0))[0]
-    low = kt.get("seeding_rows_lowered_level1", (0, 0.0))[0]
-    rb = 4.0 * ((Xd.shape[1] + 3) // 4 * 4)
-    upd = (k - 2) * Xd.shape[0] * 20.0 + read * rb + low * 12.0
-    print(f"pmc workload: k-means++ seeding, {C} groups x {k} draws done; rows read {read}, "
-          f"lowered {low}; update bytes {upd:.6e} over {k - 1} launches", flush=True)
+    ld = (Xd.shape[1] + 3) // 4 * 4
+    upd = seeding_bytes([(C, k)], Xd.shape[0], ld, kt)[0]["update_bytes"]
+    print(f"pmc workload: k-means++ seeding, {C} groups x {k} draws done; rows read "
+          f"{kt.get('seeding_rows_read_level1', (0, 0))[0]}, exact "
+          f"{kt.get('seeding_rows_exact_level1', (0, 0))[0]}, lowered "
+          f"{kt.get('seeding_rows_lowered_level1', (0, 0))[0]}; update bytes {upd:.6e} over "
+          f"{k - 1} launches", flush=True)
     a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")  # 1 GiB
     a.fill_(1.0)
     b = a.clone()
@@ -799,7 +805,8 @@ def main():
                         "traffic_check": seed_traffic_check(),
                         "algorithmic_bytes_per_launch": round(per),
                         "avg_launch_ms": round(avg, 4), "launches": e["update_launches"],
-                        "rows_read_frac": e["rows_read_frac"]}
+                        "rows_read_frac": e["rows_read_frac"],
+                        "rows_exact_frac": e["rows_exact_frac"]}
     seeding = []
     for e in seed_levels:
         gbs = e["bytes"] / e["seedings"] / (e["ms"] * 1e-3) / 1e9

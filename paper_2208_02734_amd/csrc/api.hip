@@ -22,11 +22,12 @@ struct TimingState {
   struct Rec { std::string name; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<std::pair<std::string, hipEvent_t>> open;  // started, not yet ended
-  // [0] descent rows, [1..2] refine counts, [3 + 2 l] rows read and
-  // [4 + 2 l] D^2 lowered by the k-means++ updates of level slot l
+  // [0] descent rows, [1..2] refine counts; for level slot l of the
+  // k-means++ updates, [3 + 3 l] rows not ruled out by the triangle
+  // inequality, [4 + 3 l] rows read exactly (FP32), [5 + 3 l] D^2 lowered
   unsigned long long* rows = nullptr;
 };
-constexpr int kCounters = 3 + 2 * kSeedSlots;
+constexpr int kCounters = 3 + 3 * kSeedSlots;
 TimingState& timing() {
   static TimingState t;
   return t;
@@ -72,7 +73,7 @@ unsigned long long* timing_refine_counter() {
   return timing().on && timing().rows ? timing().rows + 1 : nullptr;
 }
 unsigned long long* timing_seed_counter(int slot) {
-  return timing().on && timing().rows ? timing().rows + 3 + 2 * slot : nullptr;
+  return timing().on && timing().rows ? timing().rows + 3 + 3 * slot : nullptr;
 }
 
 namespace {
@@ -574,9 +575,10 @@ mask_status mask_timing_report(char* buf, int64_t cap, int64_t* needed) {
     os << "refine_small_points " << cnt[1] << " 0\n";
     os << "refine_full_points " << cnt[2] << " 0\n";
     for (int l = 0; l < kSeedSlots; ++l) {
-      if (cnt[3 + 2 * l] == 0) continue;
-      os << "seeding_rows_read_level" << l << " " << cnt[3 + 2 * l] << " 0\n";
-      os << "seeding_rows_lowered_level" << l << " " << cnt[4 + 2 * l] << " 0\n";
+      if (cnt[3 + 3 * l] == 0) continue;
+      os << "seeding_rows_read_level" << l << " " << cnt[3 + 3 * l] << " 0\n";
+      os << "seeding_rows_exact_level" << l << " " << cnt[4 + 3 * l] << " 0\n";
+      os << "seeding_rows_lowered_level" << l << " " << cnt[5 + 3 * l] << " 0\n";
     }
     const std::string txt = os.str();
     if (needed) *needed = (int64_t)txt.size() + 1;

@@ -65,8 +65,9 @@ unsigned long long* timing_row_counter();
 // Two device counters (points refined on 2-3 candidates, on the whole group)
 // while timing is enabled, null otherwise.
 unsigned long long* timing_refine_counter();
-// rows read and D^2 lowered by the k-means++ updates of one level (two
-// counters; levels at or above kSeedSlots - 1 share the last slot)
+// rows not ruled out, rows read exactly and D^2 lowered by the k-means++
+// updates of one level (three counters; levels at or above kSeedSlots - 1
+// share the last slot)
 constexpr int kSeedSlots = 16;
 unsigned long long* timing_seed_counter(int slot);
 

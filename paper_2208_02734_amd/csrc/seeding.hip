@@ -226,62 +226,145 @@ __global__ __launch_bounds__(kBlock) void k_pp_pick(
   }
 }
 
+// BF16 rounding bound of the screen below: a row's BF16 copy x~ (round to
+// nearest even, 8 significant bits) is within 2^-8 |x_i| of x in every
+// component, so |x - x~| <= 2^-8 |x| <= 2^-8 |x~| / (1 - 2^-8).
+constexpr double kBf16RelErr = 0.00390625 / (1.0 - 0.00390625);
+
+__device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
 // D^2 after draw t, one workgroup per tile, in chunks of 256 members.  Rows
 // are skipped by the triangle inequality: near[i] is the prototype (index in
 // the group) at D^2 of row i, and when |p_near - p_t|^2 exceeds
 // 4 D^2 (1 + 1e-6), |x - p_t| > |x - p_near| holds with room to spare for
 // the rounding of both FP64 sums, so D^2 keeps its value exactly and the row
-// is not read.  A lane group of G lanes computes each remaining row's
-// distance (64 / G rows per wave and pass, the four waves on interleaved
-// rows) and hands the new D^2 to the chunk's thread of that member through
-// LDS; thread j adds members j, j + 256, ... of the tile in turn, then wave
-// sums and the four waves in order give the tile's sum.  Draw 0 reads every
-// row and sets near = 0.
-template <int G, int U>
+// is not read.  From draw 1 on, a remaining row is screened on its BF16 copy
+// first: |x~ - p_t| (FP32 sums, shrunk by their rounding bound) minus the
+// BF16 rounding bound 2^-8 |x~| / (1 - 2^-8) is a lower bound of |x - p_t|,
+// and when its square exceeds D^2 (1 + 1e-12) the row's D^2 cannot fall (its
+// exact FP64 distance is within 1e-14 of the true one), so its FP32 row is
+// not read.  The other
+// rows (every row at draw 0) get the exact distance: a lane group of G lanes
+// computes each one (64 / G rows per wave and pass, the four waves on
+// interleaved rows) and hands the new D^2 to the chunk's thread of that
+// member through LDS; thread j adds members j, j + 256, ... of the tile in
+// turn, then wave sums and the four waves in order give the tile's sum.
+// Draw 0 reads every row and sets near = 0.  Both skips leave every D^2 as
+// reading every row exactly would.
+template <int G, int U, int SB>
 __global__ __launch_bounds__(kBlock) void k_pp_update(
-    const float* __restrict__ items, int ld, const int64_t* __restrict__ tile_row,
-    const int32_t* __restrict__ tile_grp, int k, int t, const float* __restrict__ protos,
-    const double* __restrict__ cc, double* __restrict__ d2, int32_t* __restrict__ near,
-    double* __restrict__ tsum, unsigned long long* __restrict__ tile_cnt) {
+    const float* __restrict__ items, int ld, const uint16_t* __restrict__ items_b, int ldb,
+    const int64_t* __restrict__ tile_row, const int32_t* __restrict__ tile_grp, int k, int t,
+    const float* __restrict__ protos, const double* __restrict__ cc, double* __restrict__ d2,
+    int32_t* __restrict__ near, double* __restrict__ tsum, unsigned long long* __restrict__ tile_cnt) {
   constexpr int R = kWave / G;                 // rows per wave and pass
   constexpr int W = kBlock / kWave;            // waves per tile
   __shared__ double s_wave[W];
   __shared__ double s_val[kBlock];
+  __shared__ double s_cur[kBlock];
   __shared__ int32_t s_rows[kBlock];
-  __shared__ int s_n, s_low;
+  __shared__ int32_t s_exact[kBlock];
+  __shared__ float4 s_ctr[kMaxDenseDim / 4];  // the new prototype, for the screen
+  __shared__ int s_n, s_ne, s_low;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
   const int64_t tile = blockIdx.x;
   const int grp = tile_grp[tile];
   const int64_t r0 = tile_row[tile], r1 = tile_row[tile + 1];
-  const float4* ctr = reinterpret_cast<const float4*>(protos + ((int64_t)grp * k + t) * ld);
-  const int ld4 = ld / 4, slot = lane / G, gl = lane % G;
+  const float* ctr_row = protos + ((int64_t)grp * k + t) * ld;
+  const float4* ctr = reinterpret_cast<const float4*>(ctr_row);
+  const int ld4 = ld / 4, nb8 = ldb / 8, slot = lane / G, gl = lane % G;
+  const bool screen = t > 0 && items_b != nullptr;
+  // the screen: 4 lanes per row, SB 16-byte BF16 chunks per lane (all of
+  // them in flight at once), the prototype's row from LDS
+  constexpr int GS = 4, RS = kWave / GS;
+  const int sslot = lane / GS, sgl = lane % GS;
+  if (screen)
+    for (int c = threadIdx.x; c < 2 * SB * GS; c += kBlock)
+      s_ctr[c] = 4 * c < ld ? ctr[c] : make_float4(0.f, 0.f, 0.f, 0.f);
   double own = 0.0;
-  unsigned long long n_rows = 0, n_low = 0;  // thread 0 only
+  unsigned long long n_rows = 0, n_exact = 0;  // thread 0 only
   if (threadIdx.x == 0) s_low = 0;
   for (int64_t b0 = r0; b0 < r1; b0 += kBlock) {
     const int64_t i = b0 + threadIdx.x;
     const bool mine = i < r1;
     double cur = 0.0;
     bool read = mine;
-    if (threadIdx.x == 0) s_n = 0;
+    if (threadIdx.x == 0) { s_n = 0; s_ne = 0; }
     __syncthreads();
     if (mine && t > 0) {
       cur = d2[i];
       read = cc[(int64_t)grp * k + near[i]] <= 4.0 * cur * (1.0 + 1e-6);
     }
-    if (read) s_rows[atomicAdd(&s_n, 1)] = threadIdx.x;
+    if (read) {
+      const int at = atomicAdd(&s_n, 1);
+      s_rows[at] = threadIdx.x;
+      s_cur[threadIdx.x] = cur;
+    }
     __syncthreads();
     const int n_read = s_n;
     n_rows += n_read;
-    for (int p0 = 0; p0 < n_read; p0 += R * W) {
+    int n_ex = n_read;
+    const int32_t* exact = s_rows;
+    if (screen) {
+      for (int p0 = 0; p0 < n_read; p0 += RS * W) {
+        const int p = p0 + wave * RS + sslot;
+        const bool live = p < n_read;
+        const int local = live ? s_rows[p] : 0;
+        const uint4* xb = reinterpret_cast<const uint4*>(items_b + (b0 + local) * ldb);
+        uint4 w[SB];
+#pragma unroll
+        for (int j = 0; j < SB; ++j) {
+          const int q = sgl + GS * j;
+          w[j] = q < nb8 ? xb[q] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        // FP32 sums of at most ld + 8 rounded terms each (differences, FMAs,
+        // the butterfly): within 1e-5 relative of the exact sums for ld <= 256
+        float sd = 0.f, sx = 0.f;
+#pragma unroll
+        for (int j = 0; j < SB; ++j) {
+          const int q = sgl + GS * j;  // chunks past the row are zero on both sides
+          const float4 c0 = s_ctr[2 * q], c1 = s_ctr[2 * q + 1];
+          const float x0 = bf16_lo(w[j].x), x1 = bf16_hi(w[j].x), x2 = bf16_lo(w[j].y);
+          const float x3 = bf16_hi(w[j].y), x4 = bf16_lo(w[j].z), x5 = bf16_hi(w[j].z);
+          const float x6 = bf16_lo(w[j].w), x7 = bf16_hi(w[j].w);
+          float e;
+          e = x0 - c0.x; sd = fmaf(e, e, sd); sx = fmaf(x0, x0, sx);
+          e = x1 - c0.y; sd = fmaf(e, e, sd); sx = fmaf(x1, x1, sx);
+          e = x2 - c0.z; sd = fmaf(e, e, sd); sx = fmaf(x2, x2, sx);
+          e = x3 - c0.w; sd = fmaf(e, e, sd); sx = fmaf(x3, x3, sx);
+          e = x4 - c1.x; sd = fmaf(e, e, sd); sx = fmaf(x4, x4, sx);
+          e = x5 - c1.y; sd = fmaf(e, e, sd); sx = fmaf(x5, x5, sx);
+          e = x6 - c1.z; sd = fmaf(e, e, sd); sx = fmaf(x6, x6, sx);
+          e = x7 - c1.w; sd = fmaf(e, e, sd); sx = fmaf(x7, x7, sx);
+        }
+#pragma unroll
+        for (int o = GS / 2; o >= 1; o >>= 1) {
+          sd += __shfl_xor(sd, o);
+          sx += __shfl_xor(sx, o);
+        }
+        if (live && sgl == 0) {
+          const double lb = sqrt((double)sd * (1.0 - 1e-5)) -
+                            sqrt((double)sx * (1.0 + 1e-5)) * kBf16RelErr - 1e-30;
+          const double old = s_cur[local];
+          if (lb > 0.0 && lb * lb > old * (1.0 + 1e-12)) s_val[local] = old;  // settled
+          else s_exact[atomicAdd(&s_ne, 1)] = local;
+        }
+      }
+      __syncthreads();
+      n_ex = s_ne;
+      exact = s_exact;
+    }
+    n_exact += n_ex;
+    for (int p0 = 0; p0 < n_ex; p0 += R * W) {
       const int p = p0 + wave * R + slot;
-      const bool live = p < n_read;
-      const int local = live ? s_rows[p] : 0;
+      const bool live = p < n_ex;
+      const int local = live ? exact[p] : 0;
       const int64_t row = b0 + local;
       const double acc = row_d2<G, U>(reinterpret_cast<const float4*>(items + row * ld), ctr,
                                       ld4, gl);
       if (live && gl == 0) {
-        const double old = t > 0 ? d2[row] : acc;
+        const double old = t > 0 ? s_cur[local] : acc;
         const bool lower = t == 0 || acc < old;
         s_val[local] = lower ? acc : old;
         if (lower) {
@@ -293,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_pp_update(
     }
     __syncthreads();  // s_val complete
     if (mine) own += read ? s_val[threadIdx.x] : cur;
-    __syncthreads();  // s_val and s_rows are reused
+    __syncthreads();  // s_val, s_cur and the row lists are reused
   }
   own = wave_sum(own);
   if (lane == 0) s_wave[wave] = own;
@@ -304,32 +387,29 @@ __global__ __launch_bounds__(kBlock) void k_pp_update(
     for (int w = 0; w < W; ++w) sum += s_wave[w];
     tsum[tile] = sum;
     if (tile_cnt) {  // the tile's own slots: no other workgroup writes them
-      tile_cnt[2 * tile] += n_rows;
-      tile_cnt[2 * tile + 1] += (unsigned long long)s_low;
+      tile_cnt[3 * tile] += n_rows;
+      tile_cnt[3 * tile + 1] += n_exact;
+      tile_cnt[3 * tile + 2] += (unsigned long long)s_low;
     }
   }
 }
 
-// Adds the per-tile counts into the two timing counters (one workgroup).
+// Adds the per-tile counts (rows not ruled out by the triangle inequality,
+// rows read exactly, rows whose D^2 fell) into the three timing counters
+// (one workgroup).
 __global__ __launch_bounds__(kBlock) void k_pp_count(const unsigned long long* __restrict__ tile_cnt,
                                                      int64_t n_tiles,
                                                      unsigned long long* __restrict__ out) {
-  __shared__ unsigned long long s_sum[2][kBlock];
-  unsigned long long a = 0, b = 0;
-  for (int64_t i = threadIdx.x; i < n_tiles; i += kBlock) {
-    a += tile_cnt[2 * i];
-    b += tile_cnt[2 * i + 1];
-  }
-  s_sum[0][threadIdx.x] = a;
-  s_sum[1][threadIdx.x] = b;
+  __shared__ unsigned long long s_sum[3][kBlock];
+  unsigned long long a[3] = {0, 0, 0};
+  for (int64_t i = threadIdx.x; i < n_tiles; i += kBlock)
+    for (int c = 0; c < 3; ++c) a[c] += tile_cnt[3 * i + c];
+  for (int c = 0; c < 3; ++c) s_sum[c][threadIdx.x] = a[c];
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int j = 1; j < kBlock; ++j) {
-      a += s_sum[0][j];
-      b += s_sum[1][j];
-    }
-    out[0] += a;
-    out[1] += b;
+    for (int j = 1; j < kBlock; ++j)
+      for (int c = 0; c < 3; ++c) a[c] += s_sum[c][j];
+    for (int c = 0; c < 3; ++c) out[c] += a[c];
   }
 }
 
@@ -348,6 +428,8 @@ const char* seed_scope_name(int slot, bool update = false) {
 struct SeedBuffers {
   const float* items;
   int ld;
+  const uint16_t* items_b;  // BF16 copy of the rows (stride ldb)
+  int ldb;
   const ChunkPlan* plan;
   const int64_t* tile_base;
   const int64_t* tile_row;
@@ -366,7 +448,7 @@ struct SeedBuffers {
 
 // Draw t: the pick (with the distances the update needs, unless it is the
 // last draw) and the D^2 update.
-template <int G, int U>
+template <int G, int U, int SB>
 void launch_draw(const SeedBuffers& b, int t, uint64_t seed, uint64_t tag, int32_t* chosen,
                  hipStream_t s) {
   const ChunkPlan& p = *b.plan;
@@ -393,9 +475,9 @@ void launch_draw(const SeedBuffers& b, int t, uint64_t seed, uint64_t tag, int32
   // levels of at least 2^20 rows time every update launch (each reads
   // megabytes, so the two event records cost little beside it)
   ScopedTiming timing(b.update_scope, s, b.update_scope != nullptr);
-  k_pp_update<G, U><<<(unsigned)b.n_tiles, kBlock, 0, s>>>(
-      b.items, b.ld, b.tile_row, b.tile_grp, p.k, t, b.protos, b.cc, b.d2, b.near, b.tsum,
-      b.tile_cnt);
+  k_pp_update<G, U, SB><<<(unsigned)b.n_tiles, kBlock, 0, s>>>(
+      b.items, b.ld, b.items_b, b.ldb, b.tile_row, b.tile_grp, p.k, t, b.protos, b.cc, b.d2,
+      b.near, b.tsum, b.tile_cnt);
 }
 
 }  // namespace
@@ -442,25 +524,32 @@ void kmeanspp_init(const float* items, int ld, int dim, const ChunkPlan& plan, u
   b.tsum = scratch.alloc<double>(b.n_tiles);
   b.cc = scratch.alloc<double>((size_t)plan.n_chunks * plan.k);
   b.near = scratch.alloc<int32_t>(plan.n_items);
+  // BF16 copy of the rows for the update's screen
+  b.ldb = (ld + 7) & ~7;
+  uint16_t* items_b = scratch.alloc<uint16_t>(plan.n_items * (int64_t)b.ldb);
+  quantize_bf16(items, ld, plan.n_items, items_b, b.ldb, nullptr, s);
+  b.items_b = items_b;
   const int slot = std::min(std::max(level, 0), kSeedSlots - 1);
   unsigned long long* counters = timing_seed_counter(slot);
   if (counters) {
-    b.tile_cnt = scratch.alloc<unsigned long long>(2 * b.n_tiles);
-    MASK_HIP(hipMemsetAsync(b.tile_cnt, 0, 2 * b.n_tiles * sizeof(unsigned long long), s));
+    b.tile_cnt = scratch.alloc<unsigned long long>(3 * b.n_tiles);
+    MASK_HIP(hipMemsetAsync(b.tile_cnt, 0, 3 * b.n_tiles * sizeof(unsigned long long), s));
   }
   b.update_scope = plan.n_items >= ((int64_t)1 << 20) ? seed_scope_name(slot, true) : nullptr;
   ScopedTiming timing(seed_scope_name(slot), s);
   const uint64_t tag = ((uint64_t)level << 40);
   const int f4 = ld / 4;
   for (int t = 0; t < plan.k; ++t) {
-    if (f4 <= 1) launch_draw<1, 1>(b, t, seed, tag, chosen, s);
-    else if (f4 <= 2) launch_draw<2, 1>(b, t, seed, tag, chosen, s);
-    else if (f4 <= 4) launch_draw<4, 1>(b, t, seed, tag, chosen, s);
-    else if (f4 <= 8) launch_draw<8, 1>(b, t, seed, tag, chosen, s);
-    else if (f4 <= 16) launch_draw<8, 2>(b, t, seed, tag, chosen, s);
-    else if (f4 <= 24) launch_draw<8, 2>(b, t, seed, tag, chosen, s);  // measured: 8 lanes beat 16 at d = 96
-    else if (f4 <= 32) launch_draw<16, 2>(b, t, seed, tag, chosen, s);
-    else launch_draw<16, 4>(b, t, seed, tag, chosen, s);
+    // (G, U) of the exact distances; SB = the screen's chunks per lane,
+    // ceil(ldb / 8 / 4)
+    if (f4 <= 1) launch_draw<1, 1, 1>(b, t, seed, tag, chosen, s);
+    else if (f4 <= 2) launch_draw<2, 1, 1>(b, t, seed, tag, chosen, s);
+    else if (f4 <= 4) launch_draw<4, 1, 1>(b, t, seed, tag, chosen, s);
+    else if (f4 <= 8) launch_draw<8, 1, 1>(b, t, seed, tag, chosen, s);
+    else if (f4 <= 16) launch_draw<8, 2, 2>(b, t, seed, tag, chosen, s);
+    else if (f4 <= 24) launch_draw<8, 2, 3>(b, t, seed, tag, chosen, s);  // measured: 8 lanes beat 16 at d = 96
+    else if (f4 <= 32) launch_draw<16, 2, 4>(b, t, seed, tag, chosen, s);
+    else launch_draw<16, 4, 8>(b, t, seed, tag, chosen, s);
   }
   if (counters) k_pp_count<<<1, kBlock, 0, s>>>(b.tile_cnt, b.n_tiles, counters);
   check_launch("kmeanspp");

@@ -190,11 +190,16 @@ def test_seeding_row_counters(pk):
     pk.mask_timing_enable(False)
     n = X.shape[0]
     read = rep["seeding_rows_read_level1"][0]
+    exact = rep["seeding_rows_exact_level1"][0]
     low = rep["seeding_rows_lowered_level1"][0]
     assert rep["kmeanspp_level1"][0] == 1
-    assert n <= low <= read <= (k - 1) * n
-    # clustered rows: the triangle inequality rules most of them out
+    # draw 0 reads every row exactly; a lowered row was read exactly, and a
+    # row read exactly was not ruled out by the triangle inequality
+    assert n <= low <= exact <= read <= (k - 1) * n
+    # clustered rows: the triangle inequality rules most of them out, and
+    # the BF16 screen settles most of the rest
     assert read < 0.8 * (k - 1) * n
+    assert exact - n < 0.5 * (read - n)
 
 
 @pytest.mark.parametrize("n,C", [(70_001, 1), (280_000, 2)])
