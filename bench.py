@@ -388,7 +388,8 @@ def sparse_section(pk, torch, args):
     """The CSR workload: 200,000 x 10,000 sparse rows (100 non-zeros each,
     Zipf column popularity, unit rows), levels 20 x 2,000 -> 2,000 -> 50,
     30 Lloyd iterations, 5,000 CSR queries; recall@10 against exhaustive FP64
-    search over the CSR rows (scipy) on a 200-query sample."""
+    search over the CSR rows (scipy) on a 200-query sample, and on a second,
+    disjoint 200-query sample for the first beams that pass the gate."""
     import numpy as np
     import scipy.sparse as sps
     import datagen
@@ -397,17 +398,22 @@ def sparse_section(pk, torch, args):
     Xs = pk.CsrTensor.from_host(S.indptr, S.indices, S.values, S.n_cols)
     Qs = pk.CsrTensor.from_host(QS.indptr, QS.indices, QS.values, QS.n_cols)
     g = np.random.default_rng(0)
-    sample = np.sort(g.choice(QS.n_rows, 200, replace=False))
+    both = g.choice(QS.n_rows, 400, replace=False)
+    samples = (np.sort(both[:200]), np.sort(both[200:]))  # tuning, held out
     S64 = sps.csr_matrix((S.values.astype(np.float64), S.indices, S.indptr),
                          shape=(S.n_rows, S.n_cols))
-    Qs64 = QS.to_dense()[sample].astype(np.float64)
-    D = (np.asarray(S64.multiply(S64).sum(axis=1)).ravel()[None, :]
-         + np.einsum("ij,ij->i", Qs64, Qs64)[:, None] - 2.0 * (S64 @ Qs64.T).T)
-    tids = np.argsort(D, axis=1, kind="stable")[:, :10]
-    kth = np.take_along_axis(D, tids[:, -1:], axis=1)[:, 0]
+    x2 = np.asarray(S64.multiply(S64).sum(axis=1)).ravel()
+    Qd = QS.to_dense()
+    ref = []
+    for sample in samples:
+        Qs64 = Qd[sample].astype(np.float64)
+        D = x2[None, :] + np.einsum("ij,ij->i", Qs64, Qs64)[:, None] - 2.0 * (S64 @ Qs64.T).T
+        tids = np.argsort(D, axis=1, kind="stable")[:, :10]
+        ref.append((sample, D, np.take_along_axis(D, tids[:, -1:], axis=1)[:, 0]))
     ev = _events(torch)
 
-    def recall(ids):
+    def recall(ids, which=0):
+        sample, D, kth = ref[which]
         got = ids.cpu().numpy()[sample].astype(np.int64)
         hit = 0
         for i in range(sample.size):
@@ -443,13 +449,17 @@ def sparse_section(pk, torch, args):
                                 "gathered_GB_per_s": round(4.0 * fma / (l1_ms * 1e-3) / 1e9, 1),
                                 "note": "one FP64 FMA and one 4-byte prototype value per "
                                         "(non-zero, prototype of the group)"}
+    # level-1 beams above 2048 use the CSR index's wider class (at most 3072)
     for beams in [(8, 8, 8), (16, 32, 32), (50, 128, 128), (50, 256, 256), (50, 512, 1024),
-                  (50, 1024, 2048), (50, 2000, 2048)]:
+                  (50, 1024, 2048), (50, 2000, 2048), (50, 2000, 2560), (50, 2000, 3072)]:
         ev(lambda: pk.mask_query_beams(ix, Qs, 10, beams))
         (ids, _), q_ms = ev(lambda: pk.mask_query_beams(ix, Qs, 10, beams))
-        out["queries"].append({"beams": list(beams), "recall@10": round(recall(ids), 4),
-                               "queries_per_s": round(QS.n_rows / (q_ms * 1e-3), 1)})
-        log(f"csr beams {beams}: {out['queries'][-1]}")
+        row = {"beams": list(beams), "recall@10": round(recall(ids), 4),
+               "queries_per_s": round(QS.n_rows / (q_ms * 1e-3), 1)}
+        out["queries"].append(row)
+        if "gate" not in out and row["recall@10"] >= args.gate:
+            out["gate"] = dict(row, **{"recall@10_held_out": round(recall(ids, 1), 4)})
+        log(f"csr beams {beams}: {row}")
     ix.free()
     return out
 

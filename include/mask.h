@@ -175,7 +175,9 @@ mask_status mask_build(const mask_matrix* data, const mask_build_params* p,
  * k nearest data points under the kept level-1 prototypes.  Ranking key:
  * (distance, original id).  out_ids: device int32[q->n * k] (original data
  * row ids), out_dist: device float32[q->n * k], rows ascending; slots beyond
- * the candidate count hold id -1 and +inf.  1 <= k <= 2048, 1 <= r <= 2048.
+ * the candidate count hold id -1 and +inf.  1 <= k <= 2048, 1 <= r <= 2048;
+ * on a CSR index of at most 12,288 columns r may reach 3072 (sparse rows need
+ * a larger share of the leaves probed for the same recall).
  * Precision forms (index built with MASK_BF16 or MASK_FP8_E4M3): rows are
  * compared in the low precision and the data layer's R = min(rerank_factor *
  * k, C) nearest by that distance (R = min(f * k * r1, C) for rerank_factor =
@@ -190,7 +192,8 @@ mask_status mask_query(const mask_index* ix, const mask_matrix* q, int32_t k, in
 
 /* mask_query with a beam per level: r_levels (host int32[n_levels], top
  * level first) gives the number of prototypes kept at each level, each in
- * [1, 2048].  The uniform-beam descent is r_levels = {r, ..., r}. */
+ * [1, 2048] (in [1, 3072] on a CSR index of at most 12,288 columns).  The
+ * uniform-beam descent is r_levels = {r, ..., r}. */
 mask_status mask_query_beams(const mask_index* ix, const mask_matrix* q, int32_t k,
                              const int32_t* r_levels, int32_t* out_ids, float* out_dist,
                              void* hip_stream);

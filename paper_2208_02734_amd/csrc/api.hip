@@ -473,7 +473,11 @@ mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, in
     else check_dense(q, "queries");
     MASK_CHECK(q->dim == ix->dim, "query dim differs from the index dim");
     MASK_CHECK(k >= 1 && k <= kMaxBeam, "k must be in [1, 2048]");
-    MASK_CHECK(r >= 1 && r <= kMaxBeam, "r must be in [1, 2048]");
+    // beams above 2048: CSR indexes of at most 12,288 columns only
+    const int max_beam = ix->sparse && ix->dim <= kMaxCsrWideDim ? kMaxBeamCsr : kMaxBeam;
+    MASK_CHECK(r >= 1 && r <= max_beam,
+               ix->sparse ? "r must be in [1, 3072] (in [1, 2048] above 12,288 columns)"
+                          : "r must be in [1, 2048]");
     MASK_CHECK(q->n < ((int64_t)1 << 31), "too many queries in one call");
     if (q->n == 0) return MASK_OK;
     MASK_CHECK(out_ids && out_dist, "output pointer is NULL");
@@ -517,7 +521,9 @@ mask_status query_impl(const mask_index* ix, const mask_matrix* q, int32_t k, in
     }
     if (r_levels) {
       for (int d = 0; d < ix->n_levels; ++d) {
-        MASK_CHECK(r_levels[d] >= 1 && r_levels[d] <= kMaxBeam, "beam must be in [1, 2048]");
+        MASK_CHECK(r_levels[d] >= 1 && r_levels[d] <= max_beam,
+                   ix->sparse ? "beam must be in [1, 3072] (in [1, 2048] above 12,288 columns)"
+                              : "beam must be in [1, 2048]");
         qa.r_lev[ix->n_levels - d] = r_levels[d];
       }
     }

@@ -19,6 +19,11 @@ constexpr int kMaxLevels = 16;
 constexpr int kMaxDenseDim = 256;   // MFMA assignment keeps point rows in registers
 constexpr int kMaxQueryDim = 4096;  // the descent stages one query row in LDS
 constexpr int kMaxBeam = 2048;      // r and k limit of one descent workgroup
+// A CSR index keeps up to 3,072 prototypes per level (a wider LDS class, which
+// fits beside the dense query vector for up to 12,288 columns): sparse rows
+// need a larger share of the leaves probed for the same recall.
+constexpr int kMaxBeamCsr = 3072;
+constexpr int kMaxCsrWideDim = 12288;
 constexpr int kMaxRerank = 2048;    // largest FP32 re-rank set of the BF16 form
 constexpr int kMaxSparseDim = 16384; // CSR columns: the descent scatters a query row in LDS
 

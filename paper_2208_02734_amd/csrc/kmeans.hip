@@ -1275,7 +1275,16 @@ void kmeans_assign(const float* items, int ld, int dim, const ChunkPlan& plan,
     if (dp <= 16) launch_assign_bf16<16, 4, 128, 2>(plan, labels, w, s);
     else if (dp <= 32) launch_assign_bf16<32, 4, 64, 2>(plan, labels, w, s);
     else if (dp <= 64) launch_assign_bf16<64, 2, 64, 2>(plan, labels, w, s);
-    else if (dp <= 96) launch_assign_bf16<96, 2, 64, 2>(plan, labels, w, s);
+    else if (dp <= 96) {
+      // Many rows: 512 per workgroup and tiles of 128 prototypes (fewer LDS
+      // reads and barriers per MFMA; about 4% faster on 10 groups of 1M rows
+      // x 10,000 prototypes, MI355X).  Few rows: smaller workgroups, so that
+      // the grid still covers the chip.
+      const int64_t rows = plan.max_chunk * plan.n_chunks;
+      if (rows >= ((int64_t)1 << 19)) launch_assign_bf16<96, 4, 128, 2>(plan, labels, w, s);
+      else if (rows >= ((int64_t)1 << 16)) launch_assign_bf16<96, 2, 64, 2>(plan, labels, w, s);
+      else launch_assign_bf16<96, 1, 64, 2>(plan, labels, w, s);
+    }
     else if (dp <= 128) launch_assign_bf16<128, 2, 64, 2>(plan, labels, w, s);
     else if (dp <= 256) launch_assign_bf16<256, 1, 64, 2>(plan, labels, w, s);
     else throw Error{MASK_ERR_UNSUPPORTED, "BF16 dimension above 256"};

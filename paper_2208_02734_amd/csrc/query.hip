@@ -1007,7 +1007,10 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
     need = (int)std::max<int64_t>(need, std::min<int64_t>(R, kMaxBeam));
   }
   if (a.sparse) {
-    launch2<16, 0, 4, false, 1>(a, qa, need, s);
+    // beams above 2048 (the library admits them for at most 12,288 columns:
+    // 103 KB of static LDS beside the dense query vector)
+    if (need > kMaxBeam) launch3<16, 0, 4, false, kMaxBeamCsr, 4096, 1>(a, qa, s);
+    else launch2<16, 0, 4, false, 1>(a, qa, need, s);
     check_launch("descent_csr");
     return;
   }

@@ -65,6 +65,39 @@ def test_bf16_build_labels_are_nearly_nearest(pk, d):
     assert inertia(g16) <= inertia(g32) * 1.01
 
 
+@pytest.mark.parametrize("n,d", [(20_000, 96), (100_000, 96), (600_000, 90)])
+def test_bf16_assignment_is_the_argmax_of_bf16_scores(pk, n, d):
+    # The three workgroup shapes of the BF16 assignment at d <= 96 (chosen by
+    # the row count: 128, 256 and 512 rows per workgroup, prototype tiles of
+    # 64 or 128) with a ragged prototype tail (k = 300) and, at d = 90, zero
+    # padding to 96.  Each sampled row's label must maximise
+    # x~.c~ - |c~|^2 / 2 over its group (FP64 on the BF16-rounded values) up
+    # to the kernel's FP32 accumulation and its 4 low bits of index.
+    C, k = 2, 300
+    X, _ = _mixture(n, d, 80, seed=400 + d)
+    gix = pk.mask_build(dev(X), [(C, k)], iters=2, seed=1, precision="bf16")
+    P, par = gix.export_level(1)
+    gix.free()
+    pi = mo.permutation(1, n)
+    off = mo.chunk_offsets(n, C)
+    g = np.random.default_rng(n)
+    Pq = mo.quantize_bf16(P.astype(np.float32))
+    for c in range(C):
+        sample = g.choice(pi[off[c]:off[c + 1]], 2000, replace=False)
+        assert np.all(par[sample] // k == c)
+        xq = mo.quantize_bf16(X[sample])
+        pc = Pq[c * k:(c + 1) * k]
+        p2 = np.sum(pc * pc, axis=1)
+        S = xq @ pc.T - 0.5 * p2[None, :]
+        tol = 2.0 ** -15 * (np.linalg.norm(xq, axis=1)[:, None] * np.sqrt(p2)[None, :]
+                            + p2[None, :]).max(axis=1)
+        got = S[np.arange(sample.size), par[sample] - c * k]
+        gap = S.max(axis=1) - got
+        assert np.all(gap <= tol), (c, float(np.max(gap - tol)), int(np.sum(gap > tol)))
+        # the kernel does pick the maximum, not merely a near one, almost always
+        assert np.mean(gap == 0) > 0.99
+
+
 def test_bf16_query_distances_are_fp32_exact(pk):
     X, Q = _mixture(20_000, 96, 50, seed=210, nq=100)
     levels = [(10, 100), (1, 40)]

@@ -195,3 +195,48 @@ def test_bad_csr_is_rejected(pk):
         pk.MaskServer(gix)
     assert e.value.status == 4
     gix.free()
+
+
+def test_beams_above_2048_on_csr_match_the_oracle(pk):
+    # Level-1 beams of 2,049 .. 3,072 (the CSR index's wider LDS class):
+    # selections and results against the oracle's descent on the same index.
+    n, cols = 24000, 400
+    S, QS = _sparse(n, cols, 12, seed=580, nq=16)
+    X, Q = S.to_dense(), QS.to_dense()
+    gix = pk.mask_build(_csr(pk, S), [(4, 1000), (1, 40)], iters=3, seed=6)
+    oix = oracle_index_from_gpu(X, gix)
+    q = _csr(pk, QS)
+    for beams, k in (([40, 2049], 10), ([40, 3072], 25), ([7, 2600], 1)):
+        ids, dist, sel = pk.mask_query_beams(gix, q, k, beams, debug=True)
+        n_rows, n_rep, fails = check_query_against_oracle(oix, X, Q, k, beams, host(ids),
+                                                          host(dist), host(sel))
+        assert not fails, (beams, k, fails[:3])
+        if beams[0] == 40:  # every level-1 prototype is a candidate: the beam is kept
+            assert np.all((host(sel)[:, 1] >= 0).sum(axis=1) == beams[1])
+    # the uniform beam takes the same limit
+    ids, dist = pk.mask_query(gix, q, 10, 3072)
+    assert host(ids).shape == (16, 10)
+    with pytest.raises(pk.MaskError) as e:
+        pk.mask_query_beams(gix, q, 10, [40, 3073])
+    assert e.value.status == 1
+    with pytest.raises(pk.MaskError):
+        pk.mask_query(gix, q, 2049, 8)  # k stays at most 2048
+    gix.free()
+
+
+def test_beams_above_2048_need_a_csr_index_of_at_most_12288_columns(pk):
+    import torch
+    S, QS = _sparse(3000, 12289, 8, seed=590, nq=4)
+    gix = pk.mask_build(_csr(pk, S), [(2, 30)], iters=1)
+    q = _csr(pk, QS)
+    pk.mask_query(gix, q, 5, 2048)
+    with pytest.raises(pk.MaskError) as e:
+        pk.mask_query(gix, q, 5, 2049)
+    assert e.value.status == 1
+    gix.free()
+    # and a dense index stays at 2048
+    X = torch.randn(500, 8, device="cuda")
+    dix = pk.mask_build(X, [(2, 10)], iters=1)
+    with pytest.raises(pk.MaskError):
+        pk.mask_query(dix, X[:3], 5, 2049)
+    dix.free()
