@@ -65,21 +65,21 @@ FETCH_SCALE = 1048576.0 / 524318.0
 WRITE_SCALE = 1.0
 TRAFFIC = [
     {"kernel": "assign_bf16_mfma", "level": 1, "file": "kmeans.hip",
-     "sha256": "c637a8614609f099d6bbf35e2655b7cea2591d2ff5af3282d1ec3ccabc319e06",
-     "fetch_kib": 964578.5, "write_kib": 39062.5},
+     "sha256": "ca426f8bf86f59511637831119a4e31c181821b1c939228b4355940c3ee06b48",
+     "fetch_kib": 1457505.4, "write_kib": 39062.5},
     {"kernel": "assign_fp8_mfma", "level": 1, "file": "fp8.hip",
      "sha256": "6b3f179b87b921c1e52a863e7485dc524324bb065fd6d036bb4445af341496dc",
      "fetch_kib": 497022.5, "write_kib": 39062.5},
     {"kernel": "descent_bf16", "beams": [3, 3, 24], "method": "screened", "file": "query.hip",
-     "sha256": "587bfc28cbbc52bd24582ed47c5800f2270f365360f83f4c3dea38d3c5ea0b77",
-     "fetch_kib": 9274825.1, "write_kib": 212503.4},
+     "sha256": "821ec197153e4336ba6da39382993eede00c0baae117fa1c4c279932511c144b",
+     "fetch_kib": 6666188.8, "write_kib": 412503.8},
 ]
 # The seeding update's counters were taken on a 1,000-draw level-1 seeding
 # (its launches read more rows than the timed builds' 10,000-draw ones):
 # measured over algorithmic bytes of the same launches.
 SEED_TRAFFIC_CHECK = {"file": "seeding.hip",
-                      "sha256": "081a45b92d3c3e5ba33d3375f4e3f8a54c9a83fc72c8807b7ea8601e6b228b6d",
-                      "measured_bytes": 3.6872e12, "algorithmic_bytes": 3.6716e12,
+                      "sha256": "a6035539bcb20122846f494e342071a76494c8107d69d9867ac1f1a1db568b91",
+                      "measured_bytes": 1.9568e12, "algorithmic_bytes": 1.9647e12,
                       "launches": 999}
 
 
@@ -388,8 +388,8 @@ def sparse_section(pk, torch, args):
     """The CSR workload: 200,000 x 10,000 sparse rows (100 non-zeros each,
     Zipf column popularity, unit rows), levels 20 x 2,000 -> 2,000 -> 50,
     30 Lloyd iterations, 5,000 CSR queries; recall@10 against exhaustive FP64
-    search over the CSR rows (scipy) on a 200-query sample, and on a second,
-    disjoint 200-query sample for the first beams that pass the gate."""
+    search over the CSR rows (scipy) on a 500-query sample, and on a second,
+    disjoint 500-query sample for the first beams that pass the gate there."""
     import numpy as np
     import scipy.sparse as sps
     import datagen
@@ -398,8 +398,8 @@ def sparse_section(pk, torch, args):
     Xs = pk.CsrTensor.from_host(S.indptr, S.indices, S.values, S.n_cols)
     Qs = pk.CsrTensor.from_host(QS.indptr, QS.indices, QS.values, QS.n_cols)
     g = np.random.default_rng(0)
-    both = g.choice(QS.n_rows, 400, replace=False)
-    samples = (np.sort(both[:200]), np.sort(both[200:]))  # tuning, held out
+    both = g.choice(QS.n_rows, 1000, replace=False)
+    samples = (np.sort(both[:500]), np.sort(both[500:]))  # tuning, held out
     S64 = sps.csr_matrix((S.values.astype(np.float64), S.indices, S.indptr),
                          shape=(S.n_rows, S.n_cols))
     x2 = np.asarray(S64.multiply(S64).sum(axis=1)).ravel()
@@ -451,7 +451,8 @@ def sparse_section(pk, torch, args):
                                         "(non-zero, prototype of the group)"}
     # level-1 beams above 2048 use the CSR index's wider class (at most 3072)
     for beams in [(8, 8, 8), (16, 32, 32), (50, 128, 128), (50, 256, 256), (50, 512, 1024),
-                  (50, 1024, 2048), (50, 2000, 2048), (50, 2000, 2560), (50, 2000, 3072)]:
+                  (50, 1024, 2048), (50, 2000, 2048), (50, 2000, 2560), (50, 2000, 2816),
+                  (50, 2000, 3072)]:
         ev(lambda: pk.mask_query_beams(ix, Qs, 10, beams))
         (ids, _), q_ms = ev(lambda: pk.mask_query_beams(ix, Qs, 10, beams))
         row = {"beams": list(beams), "recall@10": round(recall(ids), 4),
