@@ -205,7 +205,8 @@ __device__ inline float acc4(float s, float4 x, float4 q) {
 // Descent of one query per workgroup.
 //   TPR lanes per candidate row, NV 16-byte vectors of the row per lane
 //   (0: any number, looped), U rows in flight per lane group; B16: rows are
-//   BF16; CAPB: largest beam / k / re-rank set; CAP: LDS key buffer.
+//   BF16; BEAMB: largest prototype beam; CAPB: largest beam / k / re-rank
+//   set; CAP: LDS key buffer.
 //   SP: CSR index.  The query row is scattered into the dense LDS vector and
 //   its non-zeros are listed in LDS (the first kQList); CSR data rows are
 //   walked against the dense vector, dense prototype rows are gathered at the
@@ -222,7 +223,7 @@ constexpr int kQList = 1024;
 // spill) so that five waves per SIMD fit, as its LDS allows: with the launch
 // order the descent is bound by latency, and the fifth wave is worth more
 // than the spills (measured on MI355X).
-template <int TPR, int NV, int U, int METRIC, bool B16, int CAPB, int CAP, int MODE>
+template <int TPR, int NV, int U, int METRIC, bool B16, int BEAMB, int CAPB, int CAP, int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     B16 && CAP == 2048 ? 5 : 1))) void k_descent(DescentArgs a, QueryArgs qa) {
   constexpr bool SP = MODE == 1, F8 = MODE == 2, LOWP = B16 || F8;
@@ -231,9 +232,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   __shared__ float s_qv[SP ? kQList : 1];
   __shared__ __align__(16) uint64_t s_buf[CAP];
   __shared__ uint64_t s_out[CAPB];
-  __shared__ uint32_t s_cnt[CAPB];      // child count of each kept prototype
-  __shared__ uint32_t s_beg[CAPB];      // first child position of each
-  __shared__ uint32_t s_pre[CAPB + 1];  // prefix of child counts
+  __shared__ uint32_t s_cnt[BEAMB];      // child count of each kept prototype
+  __shared__ uint32_t s_beg[BEAMB];      // first child position of each
+  __shared__ uint32_t s_pre[BEAMB + 1];  // prefix of child counts
   __shared__ uint32_t s_hist[3 * 256];
   __shared__ uint64_t s_red[8];
   __shared__ SelShared sh;
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   // This query's beam at level l (top level first in r_lev / the profile).
   auto beam_at = [&](int l) -> int {
     if (qa.r_lev[l] > 0) return qa.r_lev[l];
-    if (qa.beam_e8[l] > 0) return min((r * qa.beam_e8[l] + 7) / 8, CAPB);
+    if (qa.beam_e8[l] > 0) return min((r * qa.beam_e8[l] + 7) / 8, BEAMB);
     return r;
   };
   // Re-rank set of the precision forms: rerank_factor * k candidates, or
@@ -634,7 +635,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
       }
       __syncthreads();
       if (tid < kWave) {
-        constexpr int P = CAPB / kWave;
+        constexpr int P = BEAMB / kWave;
         uint32_t c[P], s = 0;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
@@ -712,23 +713,28 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   if (qa.rows && tid == 0) atomicAdd(qa.rows, rows_seen);
 }
 
-template <int TPR, int NV, int U, bool B16, int CAPB, int CAP, int MODE>
+template <int TPR, int NV, int U, bool B16, int BEAMB, int CAPB, int CAP, int MODE>
 void launch3(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   const size_t shm = (size_t)a.ld * sizeof(float);
   const unsigned grid = (unsigned)(qa.order ? kXcds * qa.per_xcd : qa.nq);
   if constexpr (MODE != 0 || B16)  // CSR, FP8 and BF16 indexes are L2 only
-    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, MODE><<<grid, kBlock, shm, s>>>(a, qa);
+    k_descent<TPR, NV, U, 0, B16, BEAMB, CAPB, CAP, MODE><<<grid, kBlock, shm, s>>>(a, qa);
   else if (a.metric == MASK_L2)
-    k_descent<TPR, NV, U, 0, B16, CAPB, CAP, MODE><<<grid, kBlock, shm, s>>>(a, qa);
+    k_descent<TPR, NV, U, 0, B16, BEAMB, CAPB, CAP, MODE><<<grid, kBlock, shm, s>>>(a, qa);
   else
-    k_descent<TPR, NV, U, 1, B16, CAPB, CAP, MODE><<<grid, kBlock, shm, s>>>(a, qa);
+    k_descent<TPR, NV, U, 1, B16, BEAMB, CAPB, CAP, MODE><<<grid, kBlock, shm, s>>>(a, qa);
 }
 
+// LDS classes: everything at most 512; k or the re-rank set above 512 with
+// prototype beams of at most 512 (the per-prototype arrays stay small, so
+// three workgroups fit a CU instead of one); beams above 512.
 template <int TPR, int NV, int U, bool B16, int MODE = 0>
-void launch2(const DescentArgs& a, const QueryArgs& qa, int need, hipStream_t s) {
-  if (B16 && MODE == 0 && need <= 512) launch3<TPR, NV, U, B16, 512, 2048, MODE>(a, qa, s);
-  else if (need <= 512) launch3<TPR, NV, U, B16, 512, 2560, MODE>(a, qa, s);
-  else launch3<TPR, NV, U, B16, 2048, 4096, MODE>(a, qa, s);
+void launch2(const DescentArgs& a, const QueryArgs& qa, int need, int need_beam,
+             hipStream_t s) {
+  if (B16 && MODE == 0 && need <= 512) launch3<TPR, NV, U, B16, 512, 512, 2048, MODE>(a, qa, s);
+  else if (need <= 512) launch3<TPR, NV, U, B16, 512, 512, 2560, MODE>(a, qa, s);
+  else if (need_beam <= 512) launch3<TPR, NV, U, B16, 512, 2048, 3072, MODE>(a, qa, s);
+  else launch3<TPR, NV, U, B16, 2048, 2048, 4096, MODE>(a, qa, s);
 }
 
 }  // namespace
@@ -991,15 +997,16 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
                       s);
   const bool b16 = a.precision == MASK_BF16;
   // LDS class from the beams and k; the BF16 re-rank set fits the class
-  int need = qa.k > qa.r ? qa.k : qa.r;
-  int r1 = qa.r;  // the largest level-1 beam of the launch
+  int need_beam = qa.r;  // the largest prototype beam of the launch
+  int r1 = qa.r;         // the largest level-1 beam of the launch
   for (int l = 1; l <= a.n_levels; ++l) {
     const int pb = qa.r_lev[l] > 0   ? qa.r_lev[l]
                    : qa.beam_e8[l] > 0 ? (qa.r * qa.beam_e8[l] + 7) / 8  // the profile's largest
                                        : qa.r;
-    need = pb > need ? pb : need;
+    need_beam = pb > need_beam ? pb : need_beam;
     if (l == 1) r1 = pb;
   }
+  int need = qa.k > need_beam ? qa.k : need_beam;
   if (a.precision != MASK_FP32 && !a.sparse) {
     // the largest re-rank set of the launch (kMaxBeam at most)
     const int64_t R = a.rerank_factor > 0 ? (int64_t)a.rerank_factor * qa.k
@@ -1009,17 +1016,17 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   if (a.sparse) {
     // beams above 2048 (the library admits them for at most 12,288 columns:
     // 103 KB of static LDS beside the dense query vector)
-    if (need > kMaxBeam) launch3<16, 0, 4, false, kMaxBeamCsr, 4096, 1>(a, qa, s);
-    else launch2<16, 0, 4, false, 1>(a, qa, need, s);
+    if (need > kMaxBeam) launch3<16, 0, 4, false, kMaxBeamCsr, kMaxBeamCsr, 4096, 1>(a, qa, s);
+    else launch2<16, 0, 4, false, 1>(a, qa, need, need_beam, s);
     check_launch("descent_csr");
     return;
   }
   if (a.precision == MASK_FP8_E4M3) {
     const int nc = a.ldq / 16;
-    if (nc <= 2) launch2<2, 0, 2, false, 2>(a, qa, need, s);
-    else if (nc <= 4) launch2<4, 0, 2, false, 2>(a, qa, need, s);
-    else if (nc <= 8) launch2<8, 0, 2, false, 2>(a, qa, need, s);
-    else launch2<16, 0, 2, false, 2>(a, qa, need, s);
+    if (nc <= 2) launch2<2, 0, 2, false, 2>(a, qa, need, need_beam, s);
+    else if (nc <= 4) launch2<4, 0, 2, false, 2>(a, qa, need, need_beam, s);
+    else if (nc <= 8) launch2<8, 0, 2, false, 2>(a, qa, need, need_beam, s);
+    else launch2<16, 0, 2, false, 2>(a, qa, need, need_beam, s);
     check_launch("descent_fp8");
     return;
   }
@@ -1029,24 +1036,24 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
   // means more independent loads in flight and less per-row bookkeeping.
   if (!b16) {
     const int f4 = a.ld / 4;
-    if (f4 <= 1) launch2<1, 1, 4, false>(a, qa, need, s);
-    else if (f4 <= 2) launch2<1, 2, 2, false>(a, qa, need, s);
-    else if (f4 <= 4) launch2<1, 4, 1, false>(a, qa, need, s);
-    else if (f4 <= 8) launch2<2, 4, 2, false>(a, qa, need, s);
-    else if (f4 <= 16) launch2<4, 4, 2, false>(a, qa, need, s);
-    else if (f4 <= 32) launch2<8, 4, 2, false>(a, qa, need, s);
-    else if (f4 <= 64) launch2<8, 8, 1, false>(a, qa, need, s);
-    else launch2<16, 0, 1, false>(a, qa, need, s);
+    if (f4 <= 1) launch2<1, 1, 4, false>(a, qa, need, need_beam, s);
+    else if (f4 <= 2) launch2<1, 2, 2, false>(a, qa, need, need_beam, s);
+    else if (f4 <= 4) launch2<1, 4, 1, false>(a, qa, need, need_beam, s);
+    else if (f4 <= 8) launch2<2, 4, 2, false>(a, qa, need, need_beam, s);
+    else if (f4 <= 16) launch2<4, 4, 2, false>(a, qa, need, need_beam, s);
+    else if (f4 <= 32) launch2<8, 4, 2, false>(a, qa, need, need_beam, s);
+    else if (f4 <= 64) launch2<8, 8, 1, false>(a, qa, need, need_beam, s);
+    else launch2<16, 0, 1, false>(a, qa, need, need_beam, s);
   } else {
     const int c8 = a.ldb / 8;
-    if (c8 <= 1) launch2<1, 1, 4, true>(a, qa, need, s);
-    else if (c8 <= 2) launch2<1, 2, 2, true>(a, qa, need, s);
-    else if (c8 <= 4) launch2<1, 4, 1, true>(a, qa, need, s);
-    else if (c8 <= 8) launch2<2, 4, 1, true>(a, qa, need, s);
-    else if (c8 <= 12) launch2<4, 3, 1, true>(a, qa, need, s);
-    else if (c8 <= 16) launch2<4, 4, 1, true>(a, qa, need, s);
-    else if (c8 <= 32) launch2<8, 4, 1, true>(a, qa, need, s);
-    else launch2<16, 0, 1, true>(a, qa, need, s);
+    if (c8 <= 1) launch2<1, 1, 4, true>(a, qa, need, need_beam, s);
+    else if (c8 <= 2) launch2<1, 2, 2, true>(a, qa, need, need_beam, s);
+    else if (c8 <= 4) launch2<1, 4, 1, true>(a, qa, need, need_beam, s);
+    else if (c8 <= 8) launch2<2, 4, 1, true>(a, qa, need, need_beam, s);
+    else if (c8 <= 12) launch2<4, 3, 1, true>(a, qa, need, need_beam, s);
+    else if (c8 <= 16) launch2<4, 4, 1, true>(a, qa, need, need_beam, s);
+    else if (c8 <= 32) launch2<8, 4, 1, true>(a, qa, need, need_beam, s);
+    else launch2<16, 0, 1, true>(a, qa, need, need_beam, s);
   }
   check_launch("descent");
 }

@@ -193,7 +193,7 @@ def test_probe_all_is_exact_knn(pk):
     assert res.ok, res.messages
 
 
-@pytest.mark.parametrize("k", [10, 500])
+@pytest.mark.parametrize("k", [10, 500, 1000])
 def test_many_rounds_at_the_data_layer(pk, k):
     # 40,000 candidates at the data layer: the key buffer is filled and
     # selected many times, and most later rounds add few or no keys (the
@@ -327,14 +327,19 @@ def test_query_identical_across_lds_classes_and_runs(pk):
         i3, d3, off = pk.mask_query_ragged(gix, dev(Q), ks, rs, k_max=10, r_max=r_max)
         assert np.array_equal(host(i3).reshape(3000, 10), ids), r_max
         assert np.array_equal(host(d3).reshape(3000, 10), dist), r_max
+    # k_max above 512 with beams of at most 512: the class with small
+    # per-prototype arrays and a 2,048-key output
+    i3, d3, off = pk.mask_query_ragged(gix, dev(Q), ks, rs, k_max=600, r_max=64)
+    assert np.array_equal(host(i3).reshape(3000, 10), ids)
+    assert np.array_equal(host(d3).reshape(3000, 10), dist)
     gix.free()
     # the precision form: its re-rank set does not depend on the class either
     g16 = pk.mask_build(dev(X), [(20, 300), (1, 100)], iters=6, seed=4, precision="bf16")
     ids, dist = (host(t) for t in pk.mask_query(g16, dev(Q), 10, 64))
-    for r_max in (200, 400, 600):
-        i3, d3, off = pk.mask_query_ragged(g16, dev(Q), ks, rs, k_max=10, r_max=r_max)
-        assert np.array_equal(host(i3).reshape(3000, 10), ids), r_max
-        assert np.array_equal(host(d3).reshape(3000, 10), dist), r_max
+    for k_max, r_max in ((10, 200), (10, 400), (10, 600), (600, 64)):
+        i3, d3, off = pk.mask_query_ragged(g16, dev(Q), ks, rs, k_max=k_max, r_max=r_max)
+        assert np.array_equal(host(i3).reshape(3000, 10), ids), (k_max, r_max)
+        assert np.array_equal(host(d3).reshape(3000, 10), dist), (k_max, r_max)
     g16.free()
 
 
