@@ -260,11 +260,13 @@ __global__ __launch_bounds__(kBlock) void k_pp_update(
     int32_t* __restrict__ near, double* __restrict__ tsum, unsigned long long* __restrict__ tile_cnt) {
   constexpr int R = kWave / G;                 // rows per wave and pass
   constexpr int W = kBlock / kWave;            // waves per tile
+  constexpr int RT = 2;                        // rows per thread and round
+  constexpr int TR = kBlock * RT;              // rows per round
   __shared__ double s_wave[W];
-  __shared__ double s_val[kBlock];
-  __shared__ double s_cur[kBlock];
-  __shared__ int32_t s_rows[kBlock];
-  __shared__ int32_t s_exact[kBlock];
+  __shared__ double s_val[TR];
+  __shared__ double s_cur[TR];
+  __shared__ int32_t s_rows[TR];
+  __shared__ int32_t s_exact[TR];
   __shared__ float4 s_ctr[kMaxDenseDim / 4];  // the new prototype, for the screen
   __shared__ int s_n, s_ne, s_low;
   const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
@@ -285,22 +287,44 @@ __global__ __launch_bounds__(kBlock) void k_pp_update(
   double own = 0.0;
   unsigned long long n_rows = 0, n_exact = 0;  // thread 0 only
   if (threadIdx.x == 0) s_low = 0;
-  for (int64_t b0 = r0; b0 < r1; b0 += kBlock) {
-    const int64_t i = b0 + threadIdx.x;
-    const bool mine = i < r1;
-    double cur = 0.0;
-    bool read = mine;
+  // A round covers TR rows; thread x owns rows x and x + kBlock of it (the
+  // order in which it adds their D^2 into the tile sum).
+  for (int64_t b0 = r0; b0 < r1; b0 += TR) {
     if (threadIdx.x == 0) { s_n = 0; s_ne = 0; }
     __syncthreads();
-    if (mine && t > 0) {
-      cur = d2[i];
-      read = cc[(int64_t)grp * k + near[i]] <= 4.0 * cur * (1.0 + 1e-6);
+    double cur[RT];
+    bool read[RT];
+    if (t > 0) {
+      // every row's state loads are in flight together (indexes clamped to
+      // the tile, values selected afterwards), then the prototype distances
+      int32_t nr[RT];
+#pragma unroll
+      for (int j = 0; j < RT; ++j) {
+        const int64_t i = b0 + threadIdx.x + j * kBlock;
+        const int64_t ic = i < r1 ? i : r0;
+        cur[j] = d2[ic];
+        nr[j] = near[ic];
+      }
+#pragma unroll
+      for (int j = 0; j < RT; ++j) {
+        const bool mine = b0 + threadIdx.x + j * kBlock < r1;
+        read[j] = mine && cc[(int64_t)grp * k + nr[j]] <= 4.0 * cur[j] * (1.0 + 1e-6);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < RT; ++j) {
+        cur[j] = 0.0;
+        read[j] = b0 + threadIdx.x + j * kBlock < r1;
+      }
     }
-    if (read) {
-      const int at = atomicAdd(&s_n, 1);
-      s_rows[at] = threadIdx.x;
-      s_cur[threadIdx.x] = cur;
-    }
+#pragma unroll
+    for (int j = 0; j < RT; ++j)
+      if (read[j]) {
+        const int local = threadIdx.x + j * kBlock;
+        const int at = atomicAdd(&s_n, 1);
+        s_rows[at] = local;
+        s_cur[local] = cur[j];
+      }
     __syncthreads();
     const int n_read = s_n;
     n_rows += n_read;
@@ -375,7 +399,9 @@ __global__ __launch_bounds__(kBlock) void k_pp_update(
       }
     }
     __syncthreads();  // s_val complete
-    if (mine) own += read ? s_val[threadIdx.x] : cur;
+#pragma unroll
+    for (int j = 0; j < RT; ++j)
+      if (b0 + threadIdx.x + j * kBlock < r1) own += read[j] ? s_val[threadIdx.x + j * kBlock] : cur[j];
     __syncthreads();  // s_val, s_cur and the row lists are reused
   }
   own = wave_sum(own);
