@@ -101,7 +101,8 @@ __device__ inline double row_d2(const float4* __restrict__ x, const float4* __re
 // of the chosen member.  Lane l holds the sums of tiles l R .. l R + R - 1
 // (R = ceil(tiles / 64)); the lane totals, an inclusive wave scan of them and
 // one sequential pass in the lane whose range holds the target find the tile;
-// a wave scan of the tile's D^2 finds the member.  If rounding leaves the
+// in the tile, each lane sums 8 consecutive members, a wave scan of those
+// sums finds the lane and a walk through its 8 members the member.  If rounding leaves the
 // target unreached, the last member with D^2 > 0 of that tile (or of the
 // group) is taken.  Deterministic: every wave that runs it gets the same
 // member.  NR >= R registers per lane hold the tile sums.
@@ -163,13 +164,42 @@ __device__ int64_t pp_pick(const int64_t* __restrict__ chunk_off,
         }
       }
       if (scan) {
-        for (int64_t i0 = lo; i0 < hi && pick < 0; i0 += kWave) {
-          const bool in = i0 + lane < hi;
-          const double dv = in ? d2[i0 + lane] : 0.0;
-          const double ci = wave_incl_scan(dv, lane);
-          const unsigned long long h = __ballot(in && run + ci > target);
-          if (h) pick = i0 + (__ffsll((long long)h) - 1) - c0;
-          else run += __shfl(ci, kWave - 1);
+        // the tile's D^2 in spans of 64 x kSpan members, one load of kSpan
+        // consecutive members per lane (all in flight together): lane sums,
+        // a wave scan of them, then a walk through the hit lane's members
+        constexpr int kSpan = 8;
+        for (int64_t i0 = lo; i0 < hi && pick < 0; i0 += kWave * kSpan) {
+          const int64_t l0 = i0 + (int64_t)lane * kSpan;
+          double dv[kSpan];
+          double lsum = 0.0;
+#pragma unroll
+          for (int e = 0; e < kSpan; ++e) {
+            dv[e] = l0 + e < hi ? d2[l0 + e < hi ? l0 + e : lo] : 0.0;
+            lsum += dv[e];
+          }
+          const double ci = wave_incl_scan(lsum, lane);
+          const unsigned long long h = __ballot(run + ci > target);
+          if (h) {
+            const int L = __ffsll((long long)h) - 1;
+            const double up2 = __shfl_up(ci, 1);
+            double acc = run + (lane > 0 ? up2 : 0.0);
+            int e_hit = -1, e_pos = -1;
+#pragma unroll
+            for (int e = 0; e < kSpan; ++e) {
+              if (e_hit < 0) {
+                if (acc + dv[e] > target) e_hit = e;
+                else acc += dv[e];
+              }
+              if (dv[e] > 0.0) e_pos = e;
+            }
+            // by rounding the walk can end short of the target: then the
+            // lane's last member with D^2 > 0 (it has one: its sum moved the
+            // scan past the target)
+            const int e = __shfl(e_hit >= 0 ? e_hit : e_pos, L);
+            if (e >= 0) pick = i0 + (int64_t)L * kSpan + e - c0;
+          } else {
+            run += __shfl(ci, kWave - 1);
+          }
         }
       }
       for (int64_t i1 = hi; i1 > lo && pick < 0; i1 -= kWave) {
@@ -234,7 +264,8 @@ constexpr double kBf16RelErr = 0.00390625 / (1.0 - 0.00390625);
 __device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
-// D^2 after draw t, one workgroup per tile, in chunks of 256 members.  Rows
+// D^2 after draw t, one workgroup per tile, in rounds of 512 members (two
+// per thread, whose state loads are in flight together).  Rows
 // are skipped by the triangle inequality: near[i] is the prototype (index in
 // the group) at D^2 of row i, and when |p_near - p_t|^2 exceeds
 // 4 D^2 (1 + 1e-6), |x - p_t| > |x - p_near| holds with room to spare for
@@ -249,7 +280,7 @@ __device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0
 // computes each one (64 / G rows per wave and pass, the four waves on
 // interleaved rows) and hands the new D^2 to the chunk's thread of that
 // member through LDS; thread j adds members j, j + 256, ... of the tile in
-// turn, then wave sums and the four waves in order give the tile's sum.
+// turn (the same order whatever the round length), then wave sums and the four waves in order give the tile's sum.
 // Draw 0 reads every row and sets near = 0.  Both skips leave every D^2 as
 // reading every row exactly would.
 template <int G, int U, int SB>
