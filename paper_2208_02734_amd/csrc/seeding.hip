@@ -16,6 +16,7 @@
 // scans), so a pick can differ from a sequential running sum only when the
 // target lies within rounding of a member boundary.
 #include <algorithm>
+#include <cfloat>
 
 #include "internal.hpp"
 
@@ -402,7 +403,9 @@ __global__ __launch_bounds__(kBlock) void k_pp_update(
           const double lb = sqrt((double)sd * (1.0 - 1e-5)) -
                             sqrt((double)sx * (1.0 + 1e-5)) * kBf16RelErr - 1e-30;
           const double old = s_cur[local];
-          if (lb > 0.0 && lb * lb > old * (1.0 + 1e-12)) s_val[local] = old;  // settled
+          // an FP32 sum that overflowed settles nothing
+          if (sd <= FLT_MAX && lb > 0.0 && lb * lb > old * (1.0 + 1e-12))
+            s_val[local] = old;  // settled
           else s_exact[atomicAdd(&s_ne, 1)] = local;
         }
       }

@@ -72,6 +72,30 @@ def test_seeds_match_oracle(pk, d, C, k, level):
         assert _compare(pts, picks, 77, level, c, k) == k  # no boundary case expected
 
 
+def test_seeds_match_oracle_when_float32_distances_overflow(pk):
+    # Three clouds along the first coordinate: A spread over [-1.5e19,
+    # 1.5e19], B near +3e19, C near -6e19.  The draws (seed 20) take C, then
+    # B: at that draw most rows of A must fall from their distance to C to
+    # their distance to B, but the FP32 sums of their BF16 screen overflow.
+    # Such a row must be read exactly; settling it would keep its distance
+    # to C and move the next pick.
+    g = np.random.default_rng(5)
+    m, d, k = 700, 96, 4
+    A = g.standard_normal((m, d)).astype(np.float32)
+    A[:, 0] = g.uniform(-1.5e19, 1.5e19, m)
+    B = g.standard_normal((m, d)).astype(np.float32)
+    B[:, 0] = 3e19 + 1e17 * g.standard_normal(m)
+    C = g.standard_normal((m, d)).astype(np.float32)
+    C[:, 0] = -6e19 + 1e17 * g.standard_normal(m)
+    perm = g.permutation(3 * m)
+    X = np.concatenate([A, B, C])[perm].astype(np.float32)
+    cloud = np.repeat([0, 1, 2], m)[perm]
+    ref = mo.kmeanspp_seeds(X, k, 20, 1, 0)
+    assert list(cloud[ref[:3]]) == [2, 1, 0]  # the case described above
+    cent, chosen = pk.mask_kmeanspp(dev(X), 1, k, seed=20, level=1)
+    assert np.array_equal(host(chosen).astype(np.int64), ref)
+
+
 def test_small_groups_and_identical_points(pk):
     X = _mixture(40, 4, 3, seed=1010)
     X[20:] = X[20]  # the second group: 20 identical points
