@@ -233,7 +233,7 @@ def check_lowp_query(index: "mo.OracleIndex", q: np.ndarray, k: int, beams,
     q64 = np.asarray(q, dtype=np.float64)[None, :]
     cand = np.arange(index.protos[L - 1].shape[0], dtype=np.int64)
     for depth, l in enumerate(range(L - 1, -1, -1)):
-        rows = np.asarray(rank_protos[l], dtype=np.float64)[cand]
+        rows = np.asarray(rank_protos[l][cand], dtype=np.float64)
         d = mo.pairwise(q64, rows, "l2")[0]
         tol = 0.0 if abs_tol is None or abs_tol[depth] is None else float(abs_tol[depth])
         why = check_selection(cand, d, selections[depth], beams[depth], rel, tol)
@@ -243,7 +243,7 @@ def check_lowp_query(index: "mo.OracleIndex", q: np.ndarray, k: int, beams,
         sel = np.asarray(selections[depth], dtype=np.int64)
         cand = np.concatenate([kids[p] for p in sel]) if sel.size else np.zeros(0, np.int64)
     R = mo.rerank_size(k, beams, factor)
-    d_low = mo.pairwise(q64, np.asarray(leaf_rows, dtype=np.float64)[cand], "l2")[0] \
+    d_low = mo.pairwise(q64, np.asarray(leaf_rows[cand], dtype=np.float64), "l2")[0] \
         if cand.size else np.zeros(0)
     d_full = mo.pairwise(q64, index.data[cand], "l2")[0] if cand.size else np.zeros(0)
     why = check_rerank(got_ids, got_dist, cand, d_low, d_full, k, R, rel)
