@@ -8,7 +8,9 @@ one: sampled queries against the oracle's descent on the exported index
 (every level's selection a nearest set by FP64 distance to the rows as the
 descent reads them, the result the FP32 re-rank of an R-nearest set), and
 sampled level-1 BF16 assignments against the FP64 scores of the
-BF16-rounded rows and prototypes of their group.
+BF16-rounded rows and prototypes of their group; and the serving loop with
+the benchmark's server on the same index (rows in the mix equal rows alone,
+and a sample passes the oracle's check).
 The oracle reads the data rows it needs one query at a time (rows are
 converted when indexed), so no FP64 copy of the 10M rows is made."""
 import numpy as np
@@ -129,3 +131,55 @@ def test_fullsize_fp8_sampled_queries(built):
     fails = check_lowp_against_oracle(foix, Q, 10, beams, ids, dist, sel, fprotos, _Fp8Rows(X),
                                       -4, rows=rows)
     assert not fails, fails[:3]
+
+
+def test_fullsize_serving_in_the_mix_equals_alone_and_the_oracle(built):
+    # The serving form on the full-size BF16 index with the benchmark's
+    # server (4 GiB arena, batches of up to 32,768 queries, three streams,
+    # beam profile 3/3/24 eighths of r): requests of 1-512 queries
+    # (log-uniform), k in [1, 100], r in {8, 32}, submitted back to back.
+    # Every request's rows equal the same queries' descent alone at the
+    # profile's beams, and a sample of them passes the oracle's check.
+    import time
+    pk, X, Q, gix, oix, protos = built
+    profile = [3, 3, 24]
+    srv = pk.MaskServer(gix, arena_bytes=4 << 30, max_batch_queries=32768, n_streams=3,
+                        batch_window_us=5_000, beam_eighths=profile)
+    g = np.random.default_rng(12)
+    reqs, tickets = [], []
+    pos = 0
+    for _ in range(40):
+        n = int(np.floor(np.exp(g.uniform(0.0, np.log(513)))))
+        k = int(g.integers(1, 101))
+        r = int(g.choice([8, 32]))
+        reqs.append((pos, n, k, r))
+        tickets.append(srv.submit(Q[pos:pos + n], k, r))
+        pos += n
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t not in out:
+                res = srv.poll(t)
+                if res is not None:
+                    out[t] = res
+        assert time.time() - t0 < 120, "requests did not finish"
+    st = srv.stats()
+    srv.close()
+    assert st["completed_requests"] == 40
+    rank = [mo.quantize_bf16(P.astype(np.float32)) for P in protos]
+    leaf = _Bf16Rows(X)
+    checked = 0
+    for j, ((p, n, k, r), t) in enumerate(zip(reqs, tickets)):
+        ids, dist, _ = out[t]
+        beams = [max(1, (r * e + 7) // 8) for e in profile]
+        i1, d1, sel = (host(x) for x in pk.mask_query_beams(gix, dev(Q[p:p + n]), k, beams,
+                                                             debug=True))
+        assert np.array_equal(ids, i1) and np.array_equal(dist, d1), (p, n, k, r)
+        if j % 4 == 0:  # the oracle on the first two queries of every fourth request
+            rows = range(min(n, 2))
+            fails = check_lowp_against_oracle(oix, Q[p:p + n], k, beams, ids, dist, sel, rank,
+                                              leaf, 4, rows=rows)
+            assert not fails, (p, n, k, r, fails[:2])
+            checked += len(rows)
+    assert checked >= 10
