@@ -714,6 +714,13 @@ def main():
                 workspace["ws"] = torch.empty(max(256, pk.mask_screen_bytes(ix) * nq),
                                               dtype=torch.uint8, device="cuda")
             return pk.mask_query_screened(ix, Qd, args.k, beams, workspace=workspace["ws"])
+        if method == "batched":
+            need = pk.mask_batched_bytes(ix, beams, nq)
+            if workspace.get("wb") is None or workspace["wb"].numel() < need:
+                workspace["wb"] = None
+                torch.cuda.empty_cache()
+                workspace["wb"] = torch.empty(need, dtype=torch.uint8, device="cuda")
+            return pk.mask_query_batched(ix, Qd, args.k, beams, workspace=workspace["wb"])
         return pk.mask_query_beams(ix, Qd, args.k, beams)
 
     # ---- every form: build, then the fastest beams that pass the gate
@@ -724,7 +731,7 @@ def main():
         bk = pk.mask_timing_report()
         pk.mask_timing_enable(False)
         chosen, tried = None, []
-        methods = ("gather", "screened") if form == "bf16" else ("gather",)
+        methods = ("gather", "screened", "batched") if form == "bf16" else ("gather",)
         for beams in BEAMS:
             for method in methods:
                 query(ix, beams, method)
@@ -857,10 +864,29 @@ def main():
                   "note": "evaluated rows (gathered levels and leaves) plus the FP32 re-rank "
                           "rows; rows shared by queries are served from L2 / MALL",
                   "traffic": traffic_bytes(dkey, beams=list(beams), method=method)}
+    if method == "batched":
+        # the data layer runs in k_leaf_scan: per (query, row) pair of the kept
+        # leaves, a difference, a product and a sum per dimension on the FP32
+        # vector units; the two descent launches per call (levels, then the
+        # re-rank set from those distances) are reported beside it
+        l_cnt, l_ms = kt.get("leaf_scan", (0, 0.0))
+        pairs = kt.get("leaf_scan_pairs", (0, 0.0))[0]
+        tfs = pairs * 3.0 * d / (l_ms * 1e-3) / 1e12 if l_ms else 0.0
+        roof_query = {"bound": "alu", "kernel": "k_leaf_scan (leaf-batched data layer)",
+                      "achieved": round(tfs, 2), "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                      "frac": round(tfs / PEAK["fp32"], 4),
+                      "avg_launch_ms": round(l_ms / max(1, l_cnt), 4),
+                      "algorithmic_flops_per_launch": round(pairs * 3.0 * d / max(1, l_cnt)),
+                      "pairs_per_launch": round(pairs / max(1, l_cnt)),
+                      "note": "FP32 direct form on the BF16 rows, 3 flops per dimension of every "
+                              "(query, row) pair; packed FP32 instructions are not used, so the "
+                              "issue limit is half the peak",
+                      "descent": {"launches": d_cnt, "avg_launch_ms": round(d_ms / max(1, d_cnt), 4)},
+                      "traffic": None}
     kernels = {name: {"launches": c, "total_ms": round(ms, 3),
                       "avg_ms": round(ms / c, 4) if c else None}
                for name, (c, ms) in kt.items()
-               if not name.startswith(("seeding_rows", "descent_rows", "refine_"))}
+               if not name.startswith(("seeding_rows", "descent_rows", "refine_", "leaf_scan_pairs"))}
 
     # ---- serving: the same request streams through the BF16 and FP32 indexes
     serving = None

@@ -227,6 +227,39 @@ mask_status mask_query_screened_debug(const mask_index* ix, const mask_matrix* q
                                       float* out_dist, int32_t* sel, void* workspace,
                                       int64_t workspace_bytes, void* hip_stream);
 
+/* mask_query_screened with the data layer (Algorithm 2's scan of the kept
+ * leaves) evaluated leaf by leaf, for an index in the BF16 form with dim at
+ * most 256: a first descent keeps each query's level-1 prototypes; the
+ * (leaf, query) pairs are sorted by leaf; one workgroup per leaf computes
+ * the BF16 distance of each of its rows to each query that kept it (the
+ * descent's own arithmetic), so a leaf's rows are read once per slice
+ * instead of once per query; a second descent ranks those distances (the
+ * re-rank set, the FP32 re-rank, the k nearest).  Results equal
+ * mask_query_screened's bit for bit.  workspace: device memory of
+ * workspace_bytes (256-byte aligned) that the call owns until it completes
+ * on hip_stream; queries are processed in slices that fit it
+ * (mask_batched_bytes gives the bytes of a slice; one query must fit).
+ * MASK_ERR_UNSUPPORTED for other forms or dim above 256.  Asynchronous;
+ * allocates nothing. */
+mask_status mask_query_batched(const mask_index* ix, const mask_matrix* q, int32_t k,
+                               const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                               void* workspace, int64_t workspace_bytes, void* hip_stream);
+
+/* mask_query_batched plus the prototypes kept at every level, as
+ * mask_query_screened_debug writes them. */
+mask_status mask_query_batched_debug(const mask_index* ix, const mask_matrix* q, int32_t k,
+                                     const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                                     int32_t* sel, void* workspace, int64_t workspace_bytes,
+                                     void* hip_stream);
+
+/* Workspace bytes of mask_query_batched for one slice of n_queries queries
+ * (in [1, 2^20]) at beams r_levels (top level first): the screened scores
+ * and launch order, r1 kept-leaf slots per query and the distances of at
+ * most the rows of the index's r1 largest leaves per query (r1 the level-1
+ * beam), and the buffers of the pair sort. */
+mask_status mask_batched_bytes(const mask_index* ix, const int32_t* r_levels,
+                               int64_t n_queries, int64_t* bytes);
+
 /* Size of the device scratch of mask_query_screened_noalloc: 64 MiB, held
  * by every GPU the library runs on from its first call there until the
  * process ends. */

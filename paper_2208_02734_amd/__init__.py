@@ -87,7 +87,8 @@ _lib = None
 EXPORTED = ["mask_plan_levels", "mask_build", "mask_query", "mask_query_beams", "mask_query_ragged",
             "mask_query_range", "mask_point_query", "mask_relocate", "mask_insert",
             "mask_kmeanspp", "mask_query_screened", "mask_query_screened_debug",
-            "mask_query_screened_noalloc",
+            "mask_query_screened_noalloc", "mask_query_batched", "mask_query_batched_debug",
+            "mask_batched_bytes",
             "mask_query_beams_debug", "mask_screen_bytes",
             "mask_query_debug", "mask_free",
             "mask_index_info", "mask_export_level", "mask_import", "mask_kmeans",
@@ -122,6 +123,9 @@ def lib() -> ctypes.CDLL:
     L.mask_query_screened_debug.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP, VP, I64,
                                             VP]
     L.mask_query_screened_noalloc.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP]
+    L.mask_query_batched.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP, I64, VP]
+    L.mask_query_batched_debug.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP, VP, I64, VP]
+    L.mask_batched_bytes.argtypes = [VP, VP, I64, P(I64)]
     L.mask_query_beams_debug.argtypes = [VP, P(mask_matrix), I32, VP, VP, VP, VP, VP]
     L.mask_screen_bytes.argtypes = [VP, P(I64)]
     L.mask_free.argtypes = [VP]
@@ -438,6 +442,44 @@ def mask_query_screened(index: Index, queries, k: int, beams: Sequence[int], wor
     _check(lib().mask_query_screened(index.handle, ctypes.byref(m), int(k), r, ids.data_ptr(),
                                      dist.data_ptr(), workspace.data_ptr(), ws_bytes,
                                      _stream_handle(stream)))
+    return ids, dist
+
+
+def mask_batched_bytes(index: Index, beams: Sequence[int], n_queries: int) -> int:
+    """Workspace bytes of mask_query_batched for one slice of n_queries."""
+    b = ctypes.c_int64()
+    r = (ctypes.c_int32 * len(beams))(*[int(x) for x in beams])
+    _check(lib().mask_batched_bytes(index.handle, r, int(n_queries), ctypes.byref(b)))
+    return b.value
+
+
+def mask_query_batched(index: Index, queries, k: int, beams: Sequence[int], workspace=None,
+                       stream=None, debug: bool = False):
+    """mask_query_screened with the data layer evaluated leaf by leaf (BF16
+    form, dim <= 256); the same results.  workspace: a CUDA tensor
+    (allocated here for the whole batch, or 2^20 queries, when None).
+    Returns (ids, dist), plus the kept prototypes per level when ``debug``."""
+    torch = _torch()
+    m = _matrix(queries)
+    nq = queries.shape[0]
+    if workspace is None:
+        nbytes = mask_batched_bytes(index, beams, max(1, min(nq, 1 << 20)))
+        workspace = torch.empty(nbytes, dtype=torch.uint8, device=queries.device)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+    dist = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    r = (ctypes.c_int32 * len(beams))(*[int(b) for b in beams])
+    ws_bytes = workspace.numel() * workspace.element_size()
+    if debug:
+        sel = torch.empty((nq, len(beams), max(int(x) for x in beams)), dtype=torch.int32,
+                          device=queries.device)
+        _check(lib().mask_query_batched_debug(index.handle, ctypes.byref(m), int(k), r,
+                                              ids.data_ptr(), dist.data_ptr(), sel.data_ptr(),
+                                              workspace.data_ptr(), ws_bytes,
+                                              _stream_handle(stream)))
+        return ids, dist, sel
+    _check(lib().mask_query_batched(index.handle, ctypes.byref(m), int(k), r, ids.data_ptr(),
+                                    dist.data_ptr(), workspace.data_ptr(), ws_bytes,
+                                    _stream_handle(stream)))
     return ids, dist
 
 

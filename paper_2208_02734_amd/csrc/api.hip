@@ -2,6 +2,7 @@
 // level loop of Algorithm 1, the layout of the finished index, and the
 // entry points.
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -22,12 +23,13 @@ struct TimingState {
   struct Rec { std::string name; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<std::pair<std::string, hipEvent_t>> open;  // started, not yet ended
-  // [0] descent rows, [1..2] refine counts; for level slot l of the
-  // k-means++ updates, [3 + 3 l] rows not ruled out by the triangle
-  // inequality, [4 + 3 l] rows read exactly (FP32), [5 + 3 l] D^2 lowered
+  // [0] descent rows, [1..2] refine counts, [3] (query, row) pairs of the
+  // leaf-batched data layer; for level slot l of the k-means++ updates,
+  // [4 + 3 l] rows not ruled out by the triangle inequality, [5 + 3 l] rows
+  // read exactly (FP32), [6 + 3 l] D^2 lowered
   unsigned long long* rows = nullptr;
 };
-constexpr int kCounters = 3 + 3 * kSeedSlots;
+constexpr int kCounters = 4 + 3 * kSeedSlots;
 TimingState& timing() {
   static TimingState t;
   return t;
@@ -73,7 +75,10 @@ unsigned long long* timing_refine_counter() {
   return timing().on && timing().rows ? timing().rows + 1 : nullptr;
 }
 unsigned long long* timing_seed_counter(int slot) {
-  return timing().on && timing().rows ? timing().rows + 3 + 3 * slot : nullptr;
+  return timing().on && timing().rows ? timing().rows + 4 + 3 * slot : nullptr;
+}
+unsigned long long* timing_leaf_counter() {
+  return timing().on && timing().rows ? timing().rows + 3 : nullptr;
 }
 
 namespace {
@@ -200,6 +205,17 @@ mask_status fail(const Error& e) {
 // labels[l] (l = 1..L) holds the chunk-major parent id of every item of level
 // l-1 in that level's build order; items0_orig maps level-0 build order to
 // data row ids; protos_cm[l] are the chunk-major prototypes.
+// leaf_top from a host copy of the level-1 child offsets.
+void set_leaf_top(mask_index& ix, const std::vector<uint32_t>& off) {
+  const int64_t n1 = (int64_t)off.size() - 1;
+  std::vector<int64_t> sz((size_t)std::max<int64_t>(n1, 0));
+  for (int64_t p = 0; p < n1; ++p) sz[p] = (int64_t)off[p + 1] - off[p];
+  const int64_t m = std::min<int64_t>(n1, kMaxBeamCsr);
+  std::partial_sort(sz.begin(), sz.begin() + m, sz.end(), std::greater<int64_t>());
+  ix.leaf_top.assign((size_t)m + 1, 0);
+  for (int64_t j = 0; j < m; ++j) ix.leaf_top[j + 1] = ix.leaf_top[j] + sz[j];
+}
+
 void finalize_layout(mask_index& ix, const std::vector<int32_t*>& labels,
                      const std::vector<float*>& protos_cm, const float* items0,
                      const uint32_t* items0_orig, Arena& scratch, hipStream_t s,
@@ -240,6 +256,7 @@ void finalize_layout(mask_index& ix, const std::vector<int32_t*>& labels,
       int64_t mx = 0;
       for (int64_t p = 0; p < n_par; ++p) mx = std::max<int64_t>(mx, off[p + 1] - off[p]);
       ix.max_children[l] = mx;
+      if (l == 1) set_leaf_top(ix, off);
     }
     ix.orig[l - 1] = ix.mem.alloc<int32_t>(n_items);
     if (l - 1 >= 1 || !items0_csr) ix.protos[l - 1] = ix.mem.alloc<float>(n_items * ld);
@@ -580,11 +597,12 @@ mask_status mask_timing_report(char* buf, int64_t cap, int64_t* needed) {
     os << "descent_rows " << cnt[0] << " 0\n";
     os << "refine_small_points " << cnt[1] << " 0\n";
     os << "refine_full_points " << cnt[2] << " 0\n";
+    if (cnt[3]) os << "leaf_scan_pairs " << cnt[3] << " 0\n";
     for (int l = 0; l < kSeedSlots; ++l) {
-      if (cnt[3 + 3 * l] == 0) continue;
-      os << "seeding_rows_read_level" << l << " " << cnt[3 + 3 * l] << " 0\n";
-      os << "seeding_rows_exact_level" << l << " " << cnt[4 + 3 * l] << " 0\n";
-      os << "seeding_rows_lowered_level" << l << " " << cnt[5 + 3 * l] << " 0\n";
+      if (cnt[4 + 3 * l] == 0) continue;
+      os << "seeding_rows_read_level" << l << " " << cnt[4 + 3 * l] << " 0\n";
+      os << "seeding_rows_exact_level" << l << " " << cnt[5 + 3 * l] << " 0\n";
+      os << "seeding_rows_lowered_level" << l << " " << cnt[6 + 3 * l] << " 0\n";
     }
     const std::string txt = os.str();
     if (needed) *needed = (int64_t)txt.size() + 1;
@@ -770,6 +788,41 @@ mask_status mask_screen_bytes(const mask_index* ix, int64_t* bytes_per_query) {
 namespace mask {
 namespace {
 
+// Score rows of every screened level for the n queries at Qs (laid out as
+// mask_screen_bytes counts them, from S), then the launch order: queries
+// near each other in the tree (by their greedy path through the screened
+// levels) run together on one XCD.  Sets qa.scr, qa.scr_ld, qa.order and
+// qa.per_xcd.
+void screen_batch(const mask_index& ix, const float* Qs, int ldq, int64_t n, float* S,
+                  uint32_t* keys, uint32_t* order, QueryArgs& qa, hipStream_t s) {
+  const int L = ix.n_levels;
+  for (int l = 1; l <= L; ++l) {
+    if (ix.level_n[l] > kScreenMax) continue;
+    const int64_t ldS = screen_ld(ix.level_n[l]);
+    level_scores(Qs, ldq, n, ix.dim, ix.protos_b[l], ix.ldb, ix.level_n[l], ix.norm_b[l], S,
+                 ldS, s);
+    qa.scr[l] = S;
+    qa.scr_ld[l] = ldS;
+    S += n * ldS;
+  }
+  if (qa.scr[L]) {  // the screened levels are the top ones
+    ScreenPath sp{};
+    sp.top = L;
+    sp.low = L;
+    while (sp.low > 1 && qa.scr[sp.low - 1]) --sp.low;
+    for (int l = sp.low; l <= L; ++l) {
+      sp.S[l] = qa.scr[l];
+      sp.ld[l] = qa.scr_ld[l];
+      sp.child_off[l] = ix.child_off[l];
+    }
+    sp.n_top = ix.level_n[L];
+    sp.n_low = ix.level_n[sp.low];
+    order_queries(sp, n, keys, order, s);
+    qa.order = order;
+    qa.per_xcd = (n + kXcds - 1) / kXcds;
+  }
+}
+
 // mask_query_screened, with the per-level selections written to sel when it
 // is not NULL (int32[q->n * n_levels * rmax], as mask_query_beams_debug).
 mask_status screened_impl(const mask_index* ix, const mask_matrix* q, int32_t k,
@@ -820,40 +873,158 @@ mask_status screened_impl(const mask_index* ix, const mask_matrix* q, int32_t k,
       qa.sel = sel ? sel + s0 * (int64_t)L * rmax : nullptr;
       qa.rows = timing_row_counter();
       for (int d = 0; d < L; ++d) qa.r_lev[L - d] = r_levels[d];
-      // score rows of every screened level, then the launch order: queries
-      // near each other in the tree (by their greedy path through the
-      // screened levels) run together on one XCD
       float* S = static_cast<float*>(workspace);
-      int64_t rows = 0;
-      for (int l = 1; l <= L; ++l)
-        if (ix->level_n[l] <= kScreenMax) rows += screen_ld(ix->level_n[l]);
-      uint32_t* keys = reinterpret_cast<uint32_t*>(S + len * rows);
-      uint32_t* order = keys + len;
-      for (int l = 1; l <= L; ++l) {
-        if (ix->level_n[l] > kScreenMax) continue;
-        const int64_t ldS = screen_ld(ix->level_n[l]);
-        level_scores(Qs, ldq, len, ix->dim, ix->protos_b[l], ix->ldb, ix->level_n[l],
-                     ix->norm_b[l], S, ldS, s);
-        qa.scr[l] = S;
-        qa.scr_ld[l] = ldS;
-        S += len * ldS;
-      }
-      if (qa.scr[L]) {  // the screened levels are the top ones
-        ScreenPath sp{};
-        sp.top = L;
-        sp.low = L;
-        while (sp.low > 1 && qa.scr[sp.low - 1]) --sp.low;
-        for (int l = sp.low; l <= L; ++l) {
-          sp.S[l] = qa.scr[l];
-          sp.ld[l] = qa.scr_ld[l];
-          sp.child_off[l] = ix->child_off[l];
-        }
-        sp.n_top = ix->level_n[L];
-        sp.n_low = ix->level_n[sp.low];
-        order_queries(sp, len, keys, order, s);
-        qa.order = order;
-        qa.per_xcd = (len + kXcds - 1) / kXcds;
-      }
+      uint32_t* keys = reinterpret_cast<uint32_t*>(S + len * per_query);
+      screen_batch(*ix, Qs, ldq, len, S, keys, keys + len, qa, s);
+      descent(da, qa, s);
+    }
+    return MASK_OK;
+  } catch (const Error& e) {
+    return fail(e);
+  }
+}
+
+// Workspace of the leaf-batched descent for a slice of n queries at a
+// level-1 beam of cap: the screened scores and launch order, the kept-leaf
+// slots, the per-query counts and their scan, the pair sort and the
+// candidates' distances (at most the rows of the cap largest leaves per
+// query).  Every part 256-byte aligned.
+struct BatchedLayout {
+  float* S;
+  uint32_t* keys;
+  uint32_t* order;
+  uint32_t* leaf[5];  // b0, cnt, off, key, val
+  uint32_t* n_kept;
+  uint32_t* n_cand;
+  uint32_t* scan_sums;
+  float* cand;
+  SortWork sw;
+  int64_t bytes;
+};
+
+int64_t batched_cand_bound(const mask_index& ix, int cap) {
+  if (ix.leaf_top.empty()) return 0;
+  return ix.leaf_top[(size_t)std::min<int64_t>(cap, (int64_t)ix.leaf_top.size() - 1)];
+}
+
+BatchedLayout batched_layout(const mask_index& ix, int cap, int64_t n, void* base) {
+  BatchedLayout Lo{};
+  char* b = static_cast<char*>(base);
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) -> void* {
+    void* p = b ? b + off : nullptr;
+    off += (bytes + 255) & ~int64_t(255);
+    return p;
+  };
+  int64_t per_scores = 0;
+  for (int l = 1; l <= ix.n_levels; ++l)
+    if (ix.level_n[l] <= kScreenMax) per_scores += screen_ld(ix.level_n[l]);
+  const int64_t slots = n * cap;
+  Lo.S = static_cast<float*>(take(n * per_scores * 4));
+  Lo.keys = static_cast<uint32_t*>(take(n * 4));
+  Lo.order = static_cast<uint32_t*>(take(n * 4));
+  for (int i = 0; i < 5; ++i) Lo.leaf[i] = static_cast<uint32_t*>(take(slots * 4));
+  Lo.n_kept = static_cast<uint32_t*>(take(n * 4));
+  Lo.n_cand = static_cast<uint32_t*>(take(n * 4));
+  Lo.scan_sums = static_cast<uint32_t*>(take(scan_sums_needed(n) * 4));
+  Lo.cand = static_cast<float*>(take(std::max<int64_t>(n * batched_cand_bound(ix, cap), 1) * 4));
+  off += sort_work_carve(Lo.sw, b ? b + off : nullptr, slots, false);
+  Lo.bytes = off;
+  return Lo;
+}
+
+void check_batched(const mask_index* ix, const int32_t* r_levels) {
+  MASK_CHECK(ix != nullptr, "index is NULL");
+  if (ix->precision != MASK_BF16 || ix->sparse || ix->metric != MASK_L2)
+    throw Error{MASK_ERR_UNSUPPORTED, "leaf-batched descent: BF16 form of dense L2 data"};
+  if (ix->ld > kMaxBatchedLd)
+    throw Error{MASK_ERR_UNSUPPORTED, "leaf-batched descent: dim above 256"};
+  MASK_CHECK(r_levels != nullptr, "r_levels is NULL");
+  for (int d = 0; d < ix->n_levels; ++d)
+    MASK_CHECK(r_levels[d] >= 1 && r_levels[d] <= kMaxBeam, "beam must be in [1, 2048]");
+}
+
+// The screened descent with the data layer evaluated leaf by leaf: a first
+// descent stops after level 1 and lists each query's kept leaves; the
+// (leaf, query) pairs are sorted by leaf; one workgroup per leaf computes
+// the BF16 distance of each of its rows to each query that kept it (the
+// descent's own arithmetic); a second descent runs the data layer (the
+// re-rank set, the FP32 re-rank, the k nearest) on those distances.
+// Results equal mask_query_screened's bit for bit.
+mask_status batched_impl(const mask_index* ix, const mask_matrix* q, int32_t k,
+                         const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                         int32_t* sel, void* workspace, int64_t workspace_bytes,
+                         void* hip_stream) {
+  try {
+    check_batched(ix, r_levels);
+    check_dense(q, "queries");
+    MASK_CHECK(q->dim == ix->dim, "query dim differs from the index dim");
+    MASK_CHECK(k >= 1 && k <= kMaxBeam, "k must be in [1, 2048]");
+    MASK_CHECK(q->n < ((int64_t)1 << 31), "too many queries in one call");
+    const int L = ix->n_levels;
+    int rmax = 1;
+    for (int d = 0; d < L; ++d) rmax = std::max(rmax, r_levels[d]);
+    if (q->n == 0) return MASK_OK;
+    MASK_CHECK(out_ids && out_dist, "output pointer is NULL");
+    MASK_CHECK(workspace != nullptr, "workspace is NULL");
+    MASK_CHECK(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
+    const int cap = r_levels[L - 1];  // the level-1 beam
+    const int64_t cb = std::max<int64_t>(batched_cand_bound(*ix, cap), 1);
+    // the largest slice that fits the workspace, with 32-bit candidate and
+    // pair indexes
+    int64_t hi = std::min<int64_t>({q->n, (int64_t)1 << 20, INT32_MAX / cb,
+                                    INT32_MAX / std::max(cap, 1)});
+    int64_t lo = 1;
+    MASK_CHECK(hi >= 1 && batched_layout(*ix, cap, 1, nullptr).bytes <= workspace_bytes,
+               "workspace smaller than one query's leaf-batched descent (mask_batched_bytes)");
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) / 2;
+      if (batched_layout(*ix, cap, mid, nullptr).bytes <= workspace_bytes) lo = mid;
+      else hi = mid - 1;
+    }
+    const int64_t step = lo;
+    hipStream_t s = (hipStream_t)hip_stream;
+    const DescentArgs da = descent_args(*ix);
+    const int ldq = ld_of(q);
+    const int64_t n1 = ix->level_n[1];
+    for (int64_t s0 = 0; s0 < q->n; s0 += step) {
+      const int64_t len = std::min(step, q->n - s0);
+      const float* Qs = q->x + s0 * ldq;
+      BatchedLayout W = batched_layout(*ix, cap, len, workspace);
+      QueryArgs qa{};
+      qa.Q = Qs;
+      qa.ldq = ldq;
+      qa.nq = len;
+      qa.k = k;
+      qa.r = rmax;
+      qa.out_ids = out_ids + s0 * k;
+      qa.out_dist = out_dist + s0 * k;
+      qa.sel = sel ? sel + s0 * (int64_t)L * rmax : nullptr;
+      qa.rows = timing_row_counter();
+      for (int d = 0; d < L; ++d) qa.r_lev[L - d] = r_levels[d];
+      screen_batch(*ix, Qs, ldq, len, W.S, W.keys, W.order, qa, s);
+      // 1. the prototype levels: each query's kept leaves
+      qa.leaf_mode = 1;
+      qa.leaf_cap = cap;
+      qa.leaf_b0 = W.leaf[0];
+      qa.leaf_cnt = W.leaf[1];
+      qa.leaf_off = W.leaf[2];
+      qa.leaf_key = W.leaf[3];
+      qa.leaf_val = W.leaf[4];
+      qa.n_kept = W.n_kept;
+      qa.n_cand = W.n_cand;
+      descent(da, qa, s);
+      // 2. candidate offsets; the pairs grouped by leaf
+      exclusive_scan_u32(W.n_cand, len, nullptr, W.scan_sums, s);
+      radix_sort_u32(qa.leaf_key, qa.leaf_val, len * cap, bits_for(n1 + 1), W.sw, s);
+      // 3. the BF16 distances, leaf by leaf
+      leaf_scan(da, qa.leaf_key, qa.leaf_val, len * cap, cap, qa.leaf_off, W.n_cand, Qs, ldq,
+                W.cand, s);
+      // 4. the data layer on them
+      qa.leaf_mode = 2;
+      qa.sel = nullptr;
+      qa.cand_off = W.n_cand;
+      qa.cand = W.cand;
       descent(da, qa, s);
     }
     return MASK_OK;
@@ -872,6 +1043,40 @@ mask_status mask_query_screened(const mask_index* ix, const mask_matrix* q, int3
                                 void* workspace, int64_t workspace_bytes, void* hip_stream) {
   return screened_impl(ix, q, k, r_levels, out_ids, out_dist, nullptr, workspace,
                        workspace_bytes, hip_stream);
+}
+
+mask_status mask_query_batched(const mask_index* ix, const mask_matrix* q, int32_t k,
+                               const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                               void* workspace, int64_t workspace_bytes, void* hip_stream) {
+  return mask::batched_impl(ix, q, k, r_levels, out_ids, out_dist, nullptr, workspace,
+                            workspace_bytes, hip_stream);
+}
+
+mask_status mask_query_batched_debug(const mask_index* ix, const mask_matrix* q, int32_t k,
+                                     const int32_t* r_levels, int32_t* out_ids, float* out_dist,
+                                     int32_t* sel, void* workspace, int64_t workspace_bytes,
+                                     void* hip_stream) {
+  if (!sel) {
+    mask::set_error("sel is NULL");
+    return MASK_ERR_INVALID;
+  }
+  return mask::batched_impl(ix, q, k, r_levels, out_ids, out_dist, sel, workspace,
+                            workspace_bytes, hip_stream);
+}
+
+mask_status mask_batched_bytes(const mask_index* ix, const int32_t* r_levels, int64_t n_queries,
+                               int64_t* bytes) {
+  try {
+    mask::check_batched(ix, r_levels);
+    MASK_CHECK(bytes != nullptr, "bytes is NULL");
+    MASK_CHECK(n_queries >= 1 && n_queries <= ((int64_t)1 << 20),
+               "n_queries must be in [1, 2^20]");
+    const int cap = r_levels[ix->n_levels - 1];
+    *bytes = mask::batched_layout(*ix, cap, n_queries, nullptr).bytes;
+    return MASK_OK;
+  } catch (const mask::Error& e) {
+    return mask::fail(e);
+  }
 }
 
 mask_status mask_query_screened_debug(const mask_index* ix, const mask_matrix* q, int32_t k,
@@ -1175,6 +1380,7 @@ mask_status mask_insert(mask_index* ix, const mask_matrix* points, int32_t max_l
     }
     if (inv0) { ix->mem.free_one(ix->inv0); ix->inv0 = inv0; }
     ix->max_children[1] = mx;
+    set_leaf_top(*ix, hoff);
     ix->n = n2;
     ix->level_n[0] = n2;
     ix->group_off0 = goff_new;

@@ -67,6 +67,8 @@ void timing_record(const char* name, hipStream_t s, bool start);
 // Device counter the descent kernel adds its evaluated candidate rows to
 // while timing is enabled (null otherwise).
 unsigned long long* timing_row_counter();
+// (query, row) pairs the leaf-batched data layer evaluates, or null
+unsigned long long* timing_leaf_counter();
 // Two device counters (points refined on 2-3 candidates, on the whole group)
 // while timing is enabled, null otherwise.
 unsigned long long* timing_refine_counter();
@@ -171,6 +173,9 @@ struct SortWork {
   bool wide = false;
 };
 void sort_work_alloc(SortWork& w, int64_t n, bool wide, Arena& a);
+// The same buffers carved out of caller memory at base (256-byte aligned);
+// returns the bytes they take (base may be null to size them only).
+int64_t sort_work_carve(SortWork& w, void* base, int64_t n, bool wide);
 
 // Stable LSD radix sort of (key, value) pairs on bits [0, key_bits), in place.
 void radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int key_bits, SortWork& w,
@@ -425,6 +430,22 @@ struct QueryArgs {
   // contiguous run of `order`
   const uint32_t* order;
   int64_t per_xcd;
+  // Leaf-batched data layer (BF16 form, k-NN): leaf_mode 1 stops after the
+  // level-1 selection and writes each query's kept leaves (leaf_cap slots
+  // per query); leaf_mode 2 starts at the data layer from them and reads the
+  // candidates' BF16 distances from cand (query i's list at cand_off[i], in
+  // the order of its kept leaves) instead of evaluating the rows.
+  int leaf_mode;
+  int leaf_cap;
+  uint32_t* leaf_b0;         // first data-row position (leaf order) of the leaf
+  uint32_t* leaf_cnt;        // its rows
+  uint32_t* leaf_off;        // its first candidate in the query's list
+  uint32_t* leaf_key;        // its level-1 position (n_1 for an empty slot)
+  uint32_t* leaf_val;        // query * leaf_cap + slot
+  uint32_t* n_kept;          // leaves kept per query
+  uint32_t* n_cand;          // candidates per query (mode 1)
+  const uint32_t* cand_off;  // exclusive prefix of n_cand (mode 2)
+  const float* cand;
 };
 
 // XCDs of an MI355X; workgroups are dispatched to them round-robin
@@ -446,6 +467,17 @@ void order_queries(const ScreenPath& sp, int64_t nq, uint32_t* keys, uint32_t* o
                    hipStream_t s);
 
 void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
+// BF16 distances of every (query, kept leaf) pair: the n_pairs pairs sorted
+// by leaf (pair_key: the leaf's position, n_1 for an empty slot; pair_val:
+// query * cap + slot) in chunks of 32 per workgroup: the distance of row r
+// of the leaf to query q goes to cand[cand_off[q] + leaf_off[q * cap + slot]
+// + r], bit for bit the value the descent's data layer computes for it.
+void leaf_scan(const DescentArgs& a, const uint32_t* pair_key, const uint32_t* pair_val,
+               int64_t n_pairs, int cap, const uint32_t* leaf_off, const uint32_t* cand_off,
+               const float* Q, int ldq, float* cand, hipStream_t s);
+// Largest FP32 row stride of the leaf-batched data layer (its queries are
+// staged in LDS).
+constexpr int kMaxBatchedLd = 256;
 
 // Screening of one prototype level for a batch of queries on
 // v_mfma_f32_32x32x16_bf16: S[i * n + p] = max(0, |q_i|^2 + |c~_p|^2 -
@@ -536,6 +568,9 @@ struct mask_index {
   int rerank_factor = 4;
   int32_t* inv0 = nullptr;  // data row id -> leaf position (BF16 form)
   int64_t max_children[mask::kMaxLevels + 1] = {};  // per level, largest child count
+  // leaf_top[j]: data rows in the j largest level-1 leaves (j <= kMaxBeam),
+  // the bound of one query's candidates at a level-1 beam of j
+  std::vector<int64_t> leaf_top;
   int32_t* orig[mask::kMaxLevels + 1] = {};
   int32_t* inv[mask::kMaxLevels + 1] = {};
   uint32_t* child_off[mask::kMaxLevels + 1] = {};

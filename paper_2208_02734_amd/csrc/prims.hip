@@ -350,6 +350,24 @@ void sort_work_alloc(SortWork& w, int64_t n, bool wide, Arena& a) {
   w.sums = a.alloc<uint32_t>(scan_sums_needed(256 * n_waves));
 }
 
+int64_t sort_work_carve(SortWork& w, void* base, int64_t n, bool wide) {
+  const int64_t n_waves = (n + kRsTile - 1) / kRsTile;
+  char* b = static_cast<char*>(base);
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) {
+    void* p = b ? b + off : nullptr;
+    off += (bytes + 255) & ~int64_t(255);
+    return p;
+  };
+  w.cap_n = n;
+  w.wide = wide;
+  w.keys2 = take(n * (wide ? 8 : 4));
+  w.vals2 = static_cast<uint32_t*>(take(n * 4));
+  w.hist = static_cast<uint32_t*>(take(256 * n_waves * 4));
+  w.sums = static_cast<uint32_t*>(take(scan_sums_needed(256 * n_waves) * 4));
+  return off;
+}
+
 void radix_sort_u32(uint32_t* keys, uint32_t* vals, int64_t n, int key_bits, SortWork& w,
                     hipStream_t s) {
   radix_sort_t<uint32_t>(keys, vals, n, key_bits, w, s);

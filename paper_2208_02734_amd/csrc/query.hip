@@ -202,6 +202,29 @@ __device__ inline float acc4(float s, float4 x, float4 q) {
   return s;
 }
 
+// Butterfly step within a lane group: lane ^ O.  Within a quad (O = 1, 2)
+// a DPP quad permutation on the vector unit; otherwise a cross-lane shuffle.
+// Both move the value exactly, so sums equal the __shfl_xor butterfly's.
+template <int O>
+__device__ inline float xor_lane(float v) {
+  if constexpr (O == 1)  // quad_perm(1, 0, 3, 2)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+  else if constexpr (O == 2)  // quad_perm(2, 3, 0, 1)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+  else
+    return __shfl_xor(v, O);
+}
+
+// Sum over a lane group of TPR lanes (the butterfly from the widest step).
+template <int TPR>
+__device__ inline float group_sum(float v) {
+  if constexpr (TPR >= 16) v += xor_lane<8>(v);
+  if constexpr (TPR >= 8) v += xor_lane<4>(v);
+  if constexpr (TPR >= 4) v += xor_lane<2>(v);
+  if constexpr (TPR >= 2) v += xor_lane<1>(v);
+  return v;
+}
+
 // Descent of one query per workgroup.
 //   TPR lanes per candidate row, NV 16-byte vectors of the row per lane
 //   (0: any number, looped), U rows in flight per lane group; B16: rows are
@@ -286,7 +309,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
 
   const int L = a.n_levels;
   int n_par = 1;
-  if (tid == 0) { s_beg[0] = 0; s_pre[0] = 0; s_pre[1] = (uint32_t)a.lv[L].n; }
+  int lev_first = L;
+  if (qa.leaf_mode == 2) {
+    // the data layer only, from the leaves the first launch kept (slot
+    // order), with the candidate offsets it wrote
+    const int64_t lb = qi * (int64_t)qa.leaf_cap;
+    const int nk = min((int)qa.n_kept[qi], qa.leaf_cap);
+    for (int j = tid; j < nk; j += kBlock) {
+      s_beg[j] = qa.leaf_b0[lb + j];
+      s_cnt[j] = qa.leaf_cnt[lb + j];
+      s_pre[j] = qa.leaf_off[lb + j];
+    }
+    if (tid == 0) {
+      if (nk > 0) {
+        s_pre[nk] = qa.leaf_off[lb + nk - 1] + qa.leaf_cnt[lb + nk - 1];
+      } else {  // one empty range
+        s_beg[0] = 0; s_pre[0] = 0; s_pre[1] = 0;
+      }
+    }
+    n_par = nk > 0 ? nk : 1;
+    lev_first = 0;
+  } else if (tid == 0) {
+    s_beg[0] = 0; s_pre[0] = 0; s_pre[1] = (uint32_t)a.lv[L].n;
+  }
   __syncthreads();
 
   const int grp = tid / TPR, gl = tid % TPR;
@@ -338,12 +383,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
   for (int l = 1; l <= L; ++l) big = big || beam_at(l) > 512;
   const int64_t rerank_cap = big ? 2048 : 512;
 
-  for (int lev = L; lev >= 0; --lev) {
+  for (int lev = lev_first; lev >= 0; --lev) {
     const LevelView V = a.lv[lev];
     const float* scr = qa.scr[lev];
     const int64_t sbase = qi * qa.scr_ld[lev];
     const uint32_t m = s_pre[n_par];
-    if (scr == nullptr) rows_seen += m;  // rows read, not screened scores
     // the data layer of the BF16 form keeps an oversized set for the FP32 re-rank
     uint32_t want = (lev == 0) ? (uint32_t)k : (uint32_t)beam_at(lev);
     // rows read in BF16 at every level, or in FP8 at the data layer only:
@@ -359,6 +403,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         low = false;
       }
     }
+    // the data layer of the leaf-batched descent: the BF16 distances are read
+    const bool from_cand = qa.leaf_mode == 2 && lev == 0 && B16 && low;
+    const int64_t cbase = from_cand ? (int64_t)qa.cand_off[qi] : 0;
+    if (scr == nullptr && !from_cand) rows_seen += m;  // rows read, not scores
     // The first round is short (2 * want keys, at least 256): its exact
     // selection sets the threshold cheaply.  Later rounds take as many
     // candidates as the buffer has room for and append only keys below the
@@ -372,10 +420,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
     for (uint32_t base = 0; base < m;) {
       const uint32_t len = (base == 0) ? first : (uint32_t)CAP - held;
       const uint32_t end = (m - base < len) ? m : base + len;
-      if (scr != nullptr) {
-        // screened level: the distances were computed for the whole batch, so
-        // every lane takes candidates of its own (a binary search over the
-        // parents' prefix each)
+      if (scr != nullptr || from_cand) {
+        // screened level (or the leaf-batched data layer): the distances were
+        // computed for the whole batch, so every lane takes candidates of its
+        // own (a binary search over the parents' prefix each)
         for (uint32_t idx = base + tid; idx < end; idx += kBlock) {
           int lo = 0, hi = n_par - 1;
           while (lo < hi) {
@@ -383,8 +431,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
             if (s_pre[mid] <= idx) lo = mid; else hi = mid - 1;
           }
           const int64_t p = (int64_t)s_beg[lo] + (idx - s_pre[lo]);
-          const uint64_t key = ((uint64_t)__float_as_uint(scr[sbase + p]) << 32) |
-                               (uint32_t)V.orig[p];
+          const float dv = from_cand ? qa.cand[cbase + idx] : scr[sbase + p];
+          const uint64_t key = ((uint64_t)__float_as_uint(dv) << 32) | (uint32_t)V.orig[p];
           if (key < thr) {
             const uint32_t slot = atomicAdd(&sh.cnt, 1u);
             if (slot < (uint32_t)CAP) s_buf[slot] = key;  // rounds keep slot < CAP
@@ -578,10 +626,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         }
         if constexpr (!SP) {
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int o = TPR / 2; o >= 1; o >>= 1) acc[u] += __shfl_xor(acc[u], o);
-          }
+          for (int u = 0; u < U; ++u) acc[u] = group_sum<TPR>(acc[u]);
         }
         if (gl == 0) {
 #pragma unroll
@@ -666,6 +711,31 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         if (tid == 0) { s_beg[0] = 0; s_pre[0] = 0; s_pre[1] = 0; }
         __syncthreads();
       }
+      if (qa.leaf_mode == 1 && lev == 1) {
+        // the kept leaves, in slot order, for the leaf-by-leaf data layer
+        const int64_t lb = qi * (int64_t)qa.leaf_cap;
+        const uint32_t nk = min(kept, (uint32_t)qa.leaf_cap);
+        for (uint32_t j = tid; j < (uint32_t)qa.leaf_cap; j += kBlock) {
+          uint32_t key = (uint32_t)V.n, b0 = 0, cnt = 0, off = 0;
+          if (j < nk) {
+            b0 = s_beg[j];
+            cnt = s_cnt[j];
+            off = s_pre[j];
+            if (cnt > 0) key = (uint32_t)V.inv[(uint32_t)s_buf[j]];
+          }
+          qa.leaf_b0[lb + j] = b0;
+          qa.leaf_cnt[lb + j] = cnt;
+          qa.leaf_off[lb + j] = off;
+          qa.leaf_key[lb + j] = key;
+          qa.leaf_val[lb + j] = (uint32_t)(lb + j);
+        }
+        if (tid == 0) {
+          qa.n_kept[qi] = nk;
+          qa.n_cand[qi] = nk > 0 ? s_pre[nk] : 0u;
+          if (qa.rows) atomicAdd(qa.rows, rows_seen);
+        }
+        return;  // every thread of the workgroup
+      }
     } else {
       if (LOWP && rerank) {
         // FP32 direct form on the FP32 rows of the kept set, then the k nearest
@@ -675,8 +745,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
           const float4* row = reinterpret_cast<const float4*>(V.protos + pos * ld);
           float s0 = 0.f;
           for (int c4 = gl; c4 < ld4; c4 += TPR) s0 = acc4<METRIC>(s0, row[c4], s_q4[c4]);
-#pragma unroll
-          for (int o = TPR / 2; o >= 1; o >>= 1) s0 += __shfl_xor(s0, o);
+          s0 = group_sum<TPR>(s0);
           if (gl == 0) s_out[j] = ((uint64_t)__float_as_uint(s0) << 32) | id;
         }
         __syncthreads();
@@ -735,6 +804,128 @@ void launch2(const DescentArgs& a, const QueryArgs& qa, int need, int need_beam,
   else if (need <= 512) launch3<TPR, NV, U, B16, 512, 512, 2560, MODE>(a, qa, s);
   else if (need_beam <= 512) launch3<TPR, NV, U, B16, 512, 2048, 3072, MODE>(a, qa, s);
   else launch3<TPR, NV, U, B16, 2048, 2048, 4096, MODE>(a, qa, s);
+}
+
+// The leaf-batched data layer: the (leaf, query) pairs sorted by leaf are
+// cut into chunks of kQStage, one workgroup per chunk; for each run of pairs
+// of one leaf in its chunk, the workgroup computes the BF16 distance of every
+// row of the leaf to each of those queries, so a leaf's rows are read once
+// per chunk instead of once per query, and no workgroup holds more than
+// kQStage queries of a popular leaf.  The lane split (TPR lanes per row,
+// 16-byte chunks gl, gl + TPR, ... with the low then the high half of each,
+// then the butterfly) and the query's zero padding are those of the
+// descent's BF16 row evaluation for the same row width, so every distance is
+// bit for bit the descent's.  Each lane group keeps two rows in registers
+// across the run's queries.
+constexpr int kQStage = 32;
+
+template <int TPR, int NV>
+__global__ __launch_bounds__(kBlock) void k_leaf_scan(
+    const uint16_t* __restrict__ rows_b, int ldb, const uint32_t* __restrict__ child_off1,
+    int64_t n1, const uint32_t* __restrict__ pair_key, const uint32_t* __restrict__ pair_val,
+    int64_t n_pairs, int cap, const uint32_t* __restrict__ leaf_off,
+    const uint32_t* __restrict__ cand_off, const float* __restrict__ Q, int ldq, int dim,
+    int ld, float* __restrict__ cand, unsigned long long* __restrict__ n_eval) {
+  constexpr int kGroups = kBlock / TPR;
+  constexpr int kRows = 2;  // rows per lane group and pass
+  extern __shared__ float4 s_q4[];  // kQStage rows of ld floats
+  __shared__ int64_t s_base[kQStage];
+  __shared__ int64_t s_qrow[kQStage];
+  __shared__ uint32_t s_leaf[kQStage];
+  const int tid = threadIdx.x, grp = tid / TPR, gl = tid % TPR;
+  const int64_t c0 = (int64_t)blockIdx.x * kQStage;
+  const int nqs = (int)min<int64_t>(kQStage, n_pairs - c0);
+  if (nqs <= 0) return;
+  const int nb = ldb / 8, ld4 = ld / 4;
+  float* s_q = reinterpret_cast<float*>(s_q4);
+  if (tid < nqs) {
+    const uint32_t v = pair_val[c0 + tid];
+    const int64_t qi = v / (uint32_t)cap;
+    s_qrow[tid] = qi * ldq;
+    s_base[tid] = (int64_t)cand_off[qi] + leaf_off[v];
+    s_leaf[tid] = pair_key[c0 + tid];
+  }
+  __syncthreads();
+  // the chunk's queries (zero past dim, as the descent stages them), many
+  // loads in flight per thread
+  const int per = (nqs * ld + kBlock - 1) / kBlock;
+#pragma unroll 4
+  for (int i = 0; i < per; ++i) {
+    const int e = tid + i * kBlock;
+    if (e < nqs * ld) {
+      const int qq = e / ld, c = e - qq * ld;
+      s_q[e] = c < dim ? Q[s_qrow[qq] + c] : 0.f;
+    }
+  }
+  __syncthreads();
+  unsigned long long evals = 0;
+  for (int j0 = 0; j0 < nqs;) {
+    // the run of pairs of one leaf
+    const uint32_t leaf = s_leaf[j0];
+    int j1 = j0 + 1;
+    while (j1 < nqs && s_leaf[j1] == leaf) ++j1;
+    if (leaf < n1) {
+      const uint32_t b0 = child_off1[leaf], b1 = child_off1[leaf + 1];
+      evals += (unsigned long long)(b1 - b0) * (unsigned long long)(j1 - j0);
+      for (uint32_t r0 = b0; r0 < b1; r0 += kRows * kGroups) {
+        // the chunks of the descent's class (NV per lane; chunks past the row
+        // are zero on both sides there and here), widened to FP32 once for
+        // all the run's queries
+        float4 x[kRows][NV][2];
+        bool live[kRows];
+#pragma unroll
+        for (int u = 0; u < kRows; ++u) {
+          const uint32_t r = r0 + grp + u * kGroups;
+          live[u] = r < b1;
+          const uint4* row =
+              reinterpret_cast<const uint4*>(rows_b + (int64_t)(live[u] ? r : b0) * ldb);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const int c = gl + v * TPR;
+            const uint4 t = row[c < nb ? c : 0];
+            const uint4 w = c < nb ? t : make_uint4(0, 0, 0, 0);
+            x[u][v][0] = bf16_lo4(make_uint2(w.x, w.y));
+            x[u][v][1] = bf16_lo4(make_uint2(w.z, w.w));
+          }
+        }
+        // every chunk of the class inside the row and the query (the usual
+        // case): no selects on the query
+        const bool full = NV * TPR == nb && 2 * NV * TPR <= ld4;
+        for (int qq = j0; qq < j1; ++qq) {
+          const float4* qr = s_q4 + qq * ld4;
+          float acc[kRows];
+#pragma unroll
+          for (int u = 0; u < kRows; ++u) acc[u] = 0.f;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const int c = gl + v * TPR;
+            float4 qa0, qa1;
+            if (full) {
+              qa0 = qr[2 * c];
+              qa1 = qr[2 * c + 1];
+            } else {
+              const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+              const float4 t0 = qr[min(2 * c, ld4 - 1)], t1 = qr[min(2 * c + 1, ld4 - 1)];
+              qa0 = 2 * c < ld4 ? t0 : z;
+              qa1 = 2 * c + 1 < ld4 ? t1 : z;
+            }
+#pragma unroll
+            for (int u = 0; u < kRows; ++u) {
+              acc[u] = acc4<0>(acc[u], x[u][v][0], qa0);
+              acc[u] = acc4<0>(acc[u], x[u][v][1], qa1);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < kRows; ++u) {
+            acc[u] = group_sum<TPR>(acc[u]);
+            if (gl == 0 && live[u]) cand[s_base[qq] + (r0 + grp + u * kGroups - b0)] = acc[u];
+          }
+        }
+      }
+    }
+    j0 = j1;
+  }
+  if (n_eval && tid == 0) atomicAdd(n_eval, evals);
 }
 
 }  // namespace
@@ -1056,6 +1247,36 @@ void descent(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
     else launch2<16, 0, 1, true>(a, qa, need, need_beam, s);
   }
   check_launch("descent");
+}
+
+void leaf_scan(const DescentArgs& a, const uint32_t* pair_key, const uint32_t* pair_val,
+               int64_t n_pairs, int cap, const uint32_t* leaf_off, const uint32_t* cand_off,
+               const float* Q, int ldq, float* cand, hipStream_t s) {
+  if (n_pairs <= 0 || a.lv[1].n <= 0) return;
+  if (a.ld > kMaxBatchedLd) throw Error{MASK_ERR_UNSUPPORTED, "leaf-batched descent: dim above 256"};
+  ScopedTiming timing("leaf_scan", s);
+  const unsigned grid = (unsigned)((n_pairs + kQStage - 1) / kQStage);
+  const uint16_t* rows = a.lv[0].protos_b;
+  const uint32_t* co = a.lv[1].child_off;
+  const int64_t n1 = a.lv[1].n;
+  // the lanes per row and chunks per lane of the descent's BF16 class for
+  // this row width
+  const int c8 = a.ldb / 8;
+  const size_t shm = (size_t)kQStage * a.ld * sizeof(float);
+  unsigned long long* n_eval = timing_leaf_counter();
+#define MASK_LEAF_SCAN(T, NV)                                                             \
+  k_leaf_scan<T, NV><<<grid, kBlock, shm, s>>>(rows, a.ldb, co, n1, pair_key, pair_val,     \
+                                              n_pairs, cap, leaf_off, cand_off, Q, ldq, a.dim, \
+                                              a.ld, cand, n_eval)
+  if (c8 <= 1) MASK_LEAF_SCAN(1, 1);
+  else if (c8 <= 2) MASK_LEAF_SCAN(1, 2);
+  else if (c8 <= 4) MASK_LEAF_SCAN(1, 4);
+  else if (c8 <= 8) MASK_LEAF_SCAN(2, 4);
+  else if (c8 <= 12) MASK_LEAF_SCAN(4, 3);
+  else if (c8 <= 16) MASK_LEAF_SCAN(4, 4);
+  else MASK_LEAF_SCAN(8, 4);
+#undef MASK_LEAF_SCAN
+  check_launch("leaf_scan");
 }
 
 }  // namespace mask
