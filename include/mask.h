@@ -230,11 +230,12 @@ mask_status mask_query_screened_debug(const mask_index* ix, const mask_matrix* q
 /* mask_query_screened with the data layer (Algorithm 2's scan of the kept
  * leaves) evaluated leaf by leaf, for an index in the BF16 form with dim at
  * most 256: a first descent keeps each query's level-1 prototypes; the
- * (leaf, query) pairs are sorted by leaf; one workgroup per leaf computes
- * the BF16 distance of each of its rows to each query that kept it (the
- * descent's own arithmetic), so a leaf's rows are read once per slice
- * instead of once per query; a second descent ranks those distances (the
- * re-rank set, the FP32 re-rank, the k nearest).  Results equal
+ * (leaf, query) pairs are sorted by leaf, and a workgroup takes 32 of them
+ * at a time and computes the BF16 distance of every row of each leaf to
+ * each of its queries there (the descent's own arithmetic), so a leaf's
+ * rows are read once per 32 queries that kept it instead of once per
+ * query; a second descent ranks those distances (the re-rank set, the FP32
+ * re-rank, the k nearest).  Results equal
  * mask_query_screened's bit for bit.  workspace: device memory of
  * workspace_bytes (256-byte aligned) that the call owns until it completes
  * on hip_stream; queries are processed in slices that fit it
