@@ -970,10 +970,10 @@ mask_status batched_impl(const mask_index* ix, const mask_matrix* q, int32_t k,
     MASK_CHECK(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
     const int cap = r_levels[L - 1];  // the level-1 beam
     const int64_t cb = std::max<int64_t>(batched_cand_bound(*ix, cap), 1);
-    // the largest slice that fits the workspace, with 32-bit candidate and
-    // pair indexes
-    int64_t hi = std::min<int64_t>({q->n, (int64_t)1 << 20, INT32_MAX / cb,
-                                    INT32_MAX / std::max(cap, 1)});
+    // the largest slice that fits the workspace, with 32-bit (unsigned)
+    // candidate offsets and pair indexes
+    int64_t hi = std::min<int64_t>({q->n, (int64_t)1 << 20, (int64_t)UINT32_MAX / cb,
+                                    (int64_t)UINT32_MAX / std::max(cap, 1)});
     int64_t lo = 1;
     MASK_CHECK(hi >= 1 && batched_layout(*ix, cap, 1, nullptr).bytes <= workspace_bytes,
                "workspace smaller than one query's leaf-batched descent (mask_batched_bytes)");
