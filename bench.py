@@ -602,8 +602,8 @@ def pmc_export(pk, torch, args):
 
 
 def pmc_workload(pk, torch, args):
-    """The counter workload: the screened BF16 descent of all queries on the
-    saved index at the benchmark's beams, one BF16 build from the first k
+    """The counter workload: the screened and the leaf-batched BF16 descents
+    of all queries on the saved index at the benchmark's beams, one BF16 build from the first k
     members with 2 Lloyd iterations (3 assignment launches per level), a
     level-1-shaped k-means++ seeding with --pmc-draws draws per group, then
     a 1 GiB copy for calibration."""
@@ -623,6 +623,13 @@ def pmc_workload(pk, torch, args):
         torch.cuda.synchronize()
         print(f"pmc workload: screened descent {beams} done", flush=True)
     del ws
+    for beams in PMC_BEAMS:
+        wb = torch.empty(pk.mask_batched_bytes(ix, beams, Qd.shape[0]), dtype=torch.uint8,
+                         device="cuda")
+        pk.mask_query_batched(ix, Qd, 10, beams, workspace=wb)
+        torch.cuda.synchronize()
+        del wb
+        print(f"pmc workload: leaf-batched descent {beams} done", flush=True)
     ix.free()
     for form in [f for f in args.pmc_forms.split(",") if f]:
         gx = pk.mask_build(Xd, LEVELS, iters=2, seed=1, precision=form)
@@ -867,9 +874,11 @@ def main():
     if method == "batched":
         # the data layer runs in k_leaf_scan: per (query, row) pair of the kept
         # leaves, a difference, a product and a sum per dimension on the FP32
-        # vector units; the two descent launches per call (levels, then the
-        # re-rank set from those distances) are reported beside it
+        # vector units; the descent launch of the prototype levels and the
+        # data layer's launch (the re-rank set from those distances, one wave
+        # per query) are reported beside it
         l_cnt, l_ms = kt.get("leaf_scan", (0, 0.0))
+        s_cnt, s_ms = kt.get("leaf_select", (0, 0.0))
         pairs = kt.get("leaf_scan_pairs", (0, 0.0))[0]
         tfs = pairs * 3.0 * d / (l_ms * 1e-3) / 1e12 if l_ms else 0.0
         roof_query = {"bound": "alu", "kernel": "k_leaf_scan (leaf-batched data layer)",
@@ -882,7 +891,10 @@ def main():
                               "(query, row) pair; packed FP32 instructions are not used, so the "
                               "issue limit is half the peak",
                       "descent": {"launches": d_cnt, "avg_launch_ms": round(d_ms / max(1, d_cnt), 4)},
-                      "traffic": None}
+                      "leaf_select": {"launches": s_cnt,
+                                      "avg_launch_ms": round(s_ms / max(1, s_cnt), 4)},
+                      "traffic": traffic_bytes("leaf_scan", beams=list(beams), method=method),
+                      "traffic_unit": "bytes per launch"}
     kernels = {name: {"launches": c, "total_ms": round(ms, 3),
                       "avg_ms": round(ms / c, 4) if c else None}
                for name, (c, ms) in kt.items()

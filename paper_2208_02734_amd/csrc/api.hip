@@ -1025,7 +1025,7 @@ mask_status batched_impl(const mask_index* ix, const mask_matrix* q, int32_t k,
       qa.sel = nullptr;
       qa.cand_off = W.n_cand;
       qa.cand = W.cand;
-      descent(da, qa, s);
+      if (!leaf_select(da, qa, s)) descent(da, qa, s);
     }
     return MASK_OK;
   } catch (const Error& e) {

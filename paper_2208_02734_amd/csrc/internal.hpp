@@ -478,6 +478,11 @@ void leaf_scan(const DescentArgs& a, const uint32_t* pair_key, const uint32_t* p
 // Largest FP32 row stride of the leaf-batched data layer (its queries are
 // staged in LDS).
 constexpr int kMaxBatchedLd = 256;
+// The data layer of the leaf-batched descent (leaf_mode 2 arguments) with
+// one wave per query, for uniform k and re-rank sets of at most 192 and
+// level-1 beams of at most 128 on an L2 BF16 index; false (nothing
+// launched) otherwise.  Results equal descent()'s bit for bit.
+bool leaf_select(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
 
 // Screening of one prototype level for a batch of queries on
 // v_mfma_f32_32x32x16_bf16: S[i * n + p] = max(0, |q_i|^2 + |c~_p|^2 -

@@ -928,6 +928,266 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan(
   if (n_eval && tid == 0) atomicAdd(n_eval, evals);
 }
 
+// The data layer of the leaf-batched descent with one wave per query (four
+// queries per workgroup, no workgroup barriers).  The query's candidates
+// (the BF16 distances of its kept leaves' rows, in the order of its kept
+// leaves) stream through a buffer of kSelBuf keys in the wave's LDS that
+// takes only keys below the current threshold; whenever the buffer runs
+// short of room, a bitwise radix selection keeps the W smallest and lowers
+// the threshold.  The re-rank set then gets its FP32 distances with the lane
+// split and butterfly of the descent's class, and the k nearest are written
+// in order.  Keys (distance bits, id) are distinct, so every selected set,
+// and with it the result, is the one the workgroup-per-query data layer
+// takes.  When the re-rank set would hold every candidate (or is not larger
+// than k) the FP32 distances of all candidates are ranked instead, as there.
+constexpr int kSelBuf = 512;     // keys per wave
+constexpr int kSelMax = 192;     // largest re-rank set and k
+constexpr int kSelLeaves = 128;  // largest level-1 beam
+constexpr int kSelWaves = kBlock / kWave;
+
+// lanes below this one whose bit is set in mask
+__device__ inline uint32_t lanes_below(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Orders the wave's LDS accesses: LDS operations of one wave complete in
+// order; the fences keep the compiler from moving accesses across.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int o) {
+  const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), o);
+  const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, o);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <bool MAX>
+__device__ inline uint64_t wave_reduce_u64(uint64_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    const uint64_t w = shfl_xor_u64(v, o);
+    v = MAX ? (w > v ? w : v) : (w < v ? w : v);
+  }
+  return v;
+}
+
+// Keeps the w smallest of the n keys at buf[0, n) (2 <= n <= kSelBuf,
+// 1 <= w < n, keys distinct) at buf[0, w), in no particular order, and
+// returns the largest of them.  Every lane of the wave calls it with the same
+// arguments.  The w-th smallest key is found bit by bit from the highest bit
+// in which the keys differ; the search stops as soon as the keys sharing the
+// bits found so far are exactly the ones still needed.
+__device__ uint64_t wave_keep_smallest(uint64_t* buf, uint32_t n, uint32_t w, int lane) {
+  constexpr int P = kSelBuf / kWave;
+  uint64_t key[P];
+  bool ok[P];
+  uint64_t kmin = ~0ull, kmax = 0;
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const uint32_t i = lane + j * kWave;
+    ok[j] = i < n;
+    key[j] = 0;
+    if (ok[j]) {
+      key[j] = buf[i];
+      kmin = key[j] < kmin ? key[j] : kmin;
+      kmax = key[j] > kmax ? key[j] : kmax;
+    }
+  }
+  kmin = wave_reduce_u64<false>(kmin);
+  kmax = wave_reduce_u64<true>(kmax);
+  const int np = (int)((n + kWave - 1) / kWave);
+  // the highest bit in which the keys differ; bits above it are common
+  int b = kmin == kmax ? 0 : 63 - __clzll((long long)(kmin ^ kmax));
+  uint64_t prefix = kmin == kmax ? kmin : b >= 63 ? 0ull : (kmin >> (b + 1)) << (b + 1);
+  uint32_t need = w, in_s = kmin == kmax ? w : n;  // keys sharing the prefix's bits above b
+  for (; b > 0; --b) {
+    const uint64_t hi = prefix >> b;  // bit b clear
+    uint32_t c0 = 0;
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+      if (j < np) c0 += (uint32_t)__popcll(__ballot(ok[j] && (key[j] >> b) == hi));
+    if (c0 >= need) {
+      in_s = c0;
+    } else {
+      need -= c0;
+      in_s -= c0;
+      prefix |= 1ull << b;
+    }
+    if (in_s == need) break;
+  }
+  // kept: the keys whose bits at and above b do not exceed the prefix's
+  // (exactly w of them; at b = 0 the w-th smallest key itself bounds them)
+  if (b == 0 && in_s != need) {
+    uint32_t c0 = 0;
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+      if (j < np) c0 += (uint32_t)__popcll(__ballot(ok[j] && key[j] == prefix));
+    if (c0 < need) prefix |= 1ull;
+  }
+  const uint64_t lim = prefix >> b;
+  uint32_t base = 0;
+  uint64_t top = 0;
+  wave_sync();
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    if (j < np) {
+      const bool sel = ok[j] && (key[j] >> b) <= lim;
+      const uint64_t m = __ballot(sel);
+      const uint32_t slot = base + lanes_below(m);
+      if (sel && slot < w) {
+        buf[slot] = key[j];
+        top = key[j] > top ? key[j] : top;
+      }
+      base += (uint32_t)__popcll(m);
+    }
+  }
+  wave_sync();
+  return wave_reduce_u64<true>(top);
+}
+
+template <int TPR>
+__global__ __launch_bounds__(kBlock) void k_leaf_select(DescentArgs a, QueryArgs qa,
+                                                        int rerank) {
+  __shared__ uint64_t s_buf[kSelWaves][kSelBuf];
+  __shared__ float4 s_q4w[kSelWaves][kMaxBatchedLd / 4];
+  __shared__ uint32_t s_b0[kSelWaves][kSelLeaves + 1];
+  __shared__ uint32_t s_lo[kSelWaves][kSelLeaves + 1];
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  // queries in launch order; each XCD takes a contiguous run of workgroups
+  const int64_t n_wg = (qa.nq + kSelWaves - 1) / kSelWaves;
+  const int64_t per_xcd = (n_wg + kXcds - 1) / kXcds;
+  const int64_t run = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+  const int64_t pos = run * kSelWaves + wv;
+  if (run >= n_wg || pos >= qa.nq) return;  // the whole wave
+  const int64_t qi = qa.order ? (int64_t)qa.order[pos] : pos;
+  uint64_t* buf = s_buf[wv];
+  float4* sq4 = s_q4w[wv];
+  float* sq = reinterpret_cast<float*>(sq4);
+  uint32_t* sb0 = s_b0[wv];
+  uint32_t* slo = s_lo[wv];
+  const int ld = a.ld, ld4 = ld / 4;
+  const int k = qa.k;
+  const int64_t obase = qi * (int64_t)k;
+  for (int c = lane; c < ld; c += kWave) sq[c] = c < a.dim ? qa.Q[qi * qa.ldq + c] : 0.f;
+  const int64_t lb = qi * (int64_t)qa.leaf_cap;
+  const int nk = min((int)qa.n_kept[qi], qa.leaf_cap);
+  for (int j = lane; j < nk; j += kWave) {
+    sb0[j] = qa.leaf_b0[lb + j];
+    slo[j] = qa.leaf_off[lb + j];
+  }
+  const uint32_t m = nk > 0 ? qa.leaf_off[lb + nk - 1] + qa.leaf_cnt[lb + nk - 1] : 0u;
+  if (lane == 0) slo[nk] = m;
+  wave_sync();
+  const LevelView V = a.lv[0];
+  const bool low = (int64_t)m > rerank && rerank > k;
+  const uint32_t want = low ? (uint32_t)rerank : (uint32_t)k;
+  const int grp = lane / TPR, gl = lane % TPR;
+  constexpr int kGroups = kWave / TPR;
+  uint64_t thr = ~0ull;
+  uint32_t cnt = 0;
+  int lo = 0;  // this lane's leaf (candidates are walked forward)
+  if (low) {
+    // the BF16 distances the leaf scan wrote: four candidates per lane and step
+    const int64_t cbase = (int64_t)qa.cand_off[qi];
+    for (uint32_t base = 0; base < m; base += 4 * kWave) {
+      if (cnt > kSelBuf - 4 * kWave) {
+        thr = wave_keep_smallest(buf, cnt, want, lane);
+        cnt = want;
+      }
+      uint32_t idx[4];
+      int64_t p[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        idx[u] = base + lane + u * kWave;
+        const uint32_t ic = idx[u] < m ? idx[u] : m - 1;
+        while (lo + 1 < nk && slo[lo + 1] <= ic) ++lo;
+        p[u] = (int64_t)sb0[lo] + (ic - slo[lo]);
+      }
+      float dv[4];
+      int32_t id[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        dv[u] = qa.cand[cbase + (idx[u] < m ? idx[u] : m - 1)];
+        id[u] = V.orig[p[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint64_t key = ((uint64_t)__float_as_uint(dv[u]) << 32) | (uint32_t)id[u];
+        const bool pass = idx[u] < m && key < thr;
+        const uint64_t mk = __ballot(pass);
+        if (pass) buf[cnt + lanes_below(mk)] = key;
+        cnt += (uint32_t)__popcll(mk);
+      }
+    }
+  } else {
+    // FP32 distances of every candidate row
+    for (uint32_t base = 0; base < m; base += kGroups) {
+      if (cnt > kSelBuf - kGroups) {
+        thr = wave_keep_smallest(buf, cnt, want, lane);
+        cnt = want;
+      }
+      const uint32_t idx = base + grp;
+      const uint32_t ic = idx < m ? idx : m - 1;
+      while (lo + 1 < nk && slo[lo + 1] <= ic) ++lo;
+      const int64_t p = (int64_t)sb0[lo] + (ic - slo[lo]);
+      const float4* row = reinterpret_cast<const float4*>(V.protos + p * ld);
+      float s0 = 0.f;
+      for (int c4 = gl; c4 < ld4; c4 += TPR) s0 = acc4<0>(s0, row[c4], sq4[c4]);
+      s0 = group_sum<TPR>(s0);
+      const uint64_t key = ((uint64_t)__float_as_uint(s0) << 32) | (uint32_t)V.orig[p];
+      const bool pass = gl == 0 && idx < m && key < thr;
+      const uint64_t mk = __ballot(pass);
+      if (pass) buf[cnt + lanes_below(mk)] = key;
+      cnt += (uint32_t)__popcll(mk);
+    }
+    if (qa.rows && lane == 0) atomicAdd(qa.rows, (unsigned long long)m);
+  }
+  wave_sync();
+  if (cnt > want) {
+    thr = wave_keep_smallest(buf, cnt, want, lane);
+    cnt = want;
+  }
+  uint64_t* fin = buf;
+  if (low) {
+    // FP32 direct form on the FP32 rows of the re-rank set (at buf[cnt, 2 cnt))
+    for (uint32_t j0 = 0; j0 < cnt; j0 += kGroups) {
+      const uint32_t j = j0 + grp;
+      const uint32_t id = (uint32_t)buf[j < cnt ? j : 0];
+      const int64_t p = a.inv0[id];
+      const float4* row = reinterpret_cast<const float4*>(V.protos + p * ld);
+      float s0 = 0.f;
+      for (int c4 = gl; c4 < ld4; c4 += TPR) s0 = acc4<0>(s0, row[c4], sq4[c4]);
+      s0 = group_sum<TPR>(s0);
+      if (gl == 0 && j < cnt) buf[cnt + j] = ((uint64_t)__float_as_uint(s0) << 32) | id;
+    }
+    wave_sync();
+    fin = buf + cnt;
+    if (cnt > (uint32_t)k) {
+      wave_keep_smallest(fin, cnt, (uint32_t)k, lane);
+      cnt = (uint32_t)k;
+    }
+  }
+  // rank the kept keys and write the result row
+  const uint32_t kept = cnt < (uint32_t)k ? cnt : (uint32_t)k;
+  for (uint32_t j = lane; j < (uint32_t)k; j += kWave) {
+    if (j < kept) {
+      const uint64_t v = fin[j];
+      uint32_t rank = 0;
+      for (uint32_t t = 0; t < kept; ++t) rank += fin[t] < v;
+      qa.out_ids[obase + rank] = (int32_t)(uint32_t)v;
+      qa.out_dist[obase + rank] = sqrtf(__uint_as_float((uint32_t)(v >> 32)));
+    } else {
+      qa.out_ids[obase + j] = -1;
+      qa.out_dist[obase + j] = INFINITY;
+    }
+  }
+}
+
 }  // namespace
 
 typedef __bf16 sbf16x8 __attribute__((ext_vector_type(8)));
@@ -1277,6 +1537,28 @@ void leaf_scan(const DescentArgs& a, const uint32_t* pair_key, const uint32_t* p
   else MASK_LEAF_SCAN(8, 4);
 #undef MASK_LEAF_SCAN
   check_launch("leaf_scan");
+}
+
+bool leaf_select(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
+  if (a.precision != MASK_BF16 || a.sparse || a.metric != MASK_L2 || qa.k_arr || qa.r_arr ||
+      qa.radius || qa.sel || qa.out_leaf || qa.out_off || a.ld > kMaxBatchedLd)
+    return false;
+  const int64_t r1 = qa.r_lev[1] > 0 ? qa.r_lev[1] : qa.r;
+  const int64_t R = a.rerank_factor > 0 ? (int64_t)a.rerank_factor * qa.k
+                                        : (int64_t)(-a.rerank_factor) * qa.k * r1;
+  if (qa.k > kSelMax || R > kSelMax || qa.leaf_cap > kSelLeaves) return false;
+  if (qa.nq <= 0) return true;
+  ScopedTiming timing("leaf_select", s);
+  const int64_t n_wg = (qa.nq + kSelWaves - 1) / kSelWaves;
+  const unsigned grid = (unsigned)(kXcds * ((n_wg + kXcds - 1) / kXcds));
+  const int c8 = a.ldb / 8;
+  // the lanes per row of the descent's BF16 class for this row width
+  if (c8 <= 4) k_leaf_select<1><<<grid, kBlock, 0, s>>>(a, qa, (int)R);
+  else if (c8 <= 8) k_leaf_select<2><<<grid, kBlock, 0, s>>>(a, qa, (int)R);
+  else if (c8 <= 16) k_leaf_select<4><<<grid, kBlock, 0, s>>>(a, qa, (int)R);
+  else k_leaf_select<8><<<grid, kBlock, 0, s>>>(a, qa, (int)R);
+  check_launch("leaf_select");
+  return true;
 }
 
 }  // namespace mask

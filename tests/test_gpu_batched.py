@@ -58,6 +58,18 @@ def test_batched_without_a_rerank_and_with_large_k(pk):
     _same(pk, gix, Q, 10, [1, 1])     # about 10 candidates, R = 40: no re-rank
     _same(pk, gix, Q, 600, [20, 80])  # k = 600
     _same(pk, gix, Q, 10, [50, 300])  # every leaf
+    # the one-wave-per-query data layer takes re-rank sets and k up to 192 and
+    # level-1 beams up to 128; beyond either, the workgroup-per-query one
+    _same(pk, gix, Q, 48, [8, 128])   # R = 192, 128 leaves
+    _same(pk, gix, Q, 49, [8, 100])   # R = 196
+    _same(pk, gix, Q, 10, [8, 129])   # 129 leaves
+    _same(pk, gix, Q, 192, [8, 120])  # k = 192, R = 768
+    gix.free()
+    # a re-rank set of 4 k r (factor -4): R = 96 at k = 1, above 192 at k = 10
+    gix = pk.mask_build(dev(X), [(10, 300), (1, 50)], iters=4, seed=3, precision="bf16",
+                        rerank_factor=-4)
+    _same(pk, gix, Q, 1, [4, 24])
+    _same(pk, gix, Q, 10, [4, 24])
     gix.free()
 
 
