@@ -1013,7 +1013,7 @@ mask_status batched_impl(const mask_index* ix, const mask_matrix* q, int32_t k,
       qa.leaf_val = W.leaf[4];
       qa.n_kept = W.n_kept;
       qa.n_cand = W.n_cand;
-      descent(da, qa, s);
+      if (!level_select(da, qa, s)) descent(da, qa, s);
       // 2. candidate offsets; the pairs grouped by leaf
       exclusive_scan_u32(W.n_cand, len, nullptr, W.scan_sums, s);
       radix_sort_u32(qa.leaf_key, qa.leaf_val, len * cap, bits_for(n1 + 1), W.sw, s);

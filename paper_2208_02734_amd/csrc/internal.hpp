@@ -483,6 +483,12 @@ constexpr int kMaxBatchedLd = 256;
 // level-1 beams of at most 128 on an L2 BF16 index; false (nothing
 // launched) otherwise.  Results equal descent()'s bit for bit.
 bool leaf_select(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
+// The prototype levels of the leaf-batched descent (leaf_mode 1 arguments)
+// with one wave per query, for uniform beams of at most 192 per level and a
+// level-1 beam (leaf_cap) of at most 128 on an L2 BF16 index; false (nothing
+// launched) otherwise.  The kept sets equal descent()'s; their slot order may
+// differ.
+bool level_select(const DescentArgs& a, const QueryArgs& qa, hipStream_t s);
 
 // Screening of one prototype level for a batch of queries on
 // v_mfma_f32_32x32x16_bf16: S[i * n + p] = max(0, |q_i|^2 + |c~_p|^2 -

@@ -1188,6 +1188,214 @@ __global__ __launch_bounds__(kBlock) void k_leaf_select(DescentArgs a, QueryArgs
   }
 }
 
+// The prototype levels of the leaf-batched descent with one wave per query
+// (four per workgroup, no workgroup barriers).  At each level the children
+// of the kept prototypes stream through the wave's key buffer -- a screened
+// level's keys from the batch's scores, another level's from its BF16 rows
+// with the lane split and arithmetic of the descent's class -- and the
+// beam's nearest are kept; after level 1 the kept leaves are written for the
+// leaf scan.  Keys are distinct, so every kept set equals the
+// workgroup-per-query descent's; only the slot order may differ.
+constexpr int kSelSlots = (kSelMax + kWave - 1) / kWave;  // kept slots per lane
+
+template <int TPR, int NV>
+__global__ __launch_bounds__(kBlock) void k_level_select(DescentArgs a, QueryArgs qa) {
+  __shared__ uint64_t s_buf[kSelWaves][kSelBuf];
+  __shared__ float4 s_q4w[kSelWaves][kMaxBatchedLd / 4];
+  __shared__ uint32_t s_b0[kSelWaves][kSelMax + 1];
+  __shared__ uint32_t s_lo[kSelWaves][kSelMax + 1];
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const int64_t n_wg = (qa.nq + kSelWaves - 1) / kSelWaves;
+  const int64_t per_xcd = (n_wg + kXcds - 1) / kXcds;
+  const int64_t run = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+  const int64_t pos = run * kSelWaves + wv;
+  if (run >= n_wg || pos >= qa.nq) return;  // the whole wave
+  const int64_t qi = qa.order ? (int64_t)qa.order[pos] : pos;
+  uint64_t* buf = s_buf[wv];
+  float4* sq4 = s_q4w[wv];
+  float* sq = reinterpret_cast<float*>(sq4);
+  uint32_t* sb0 = s_b0[wv];
+  uint32_t* slo = s_lo[wv];
+  const int ld = a.ld, ld4 = ld / 4, ldb = a.ldb, nb = ldb / 8;
+  const int L = a.n_levels;
+  for (int c = lane; c < ld; c += kWave) sq[c] = c < a.dim ? qa.Q[qi * qa.ldq + c] : 0.f;
+  if (lane == 0) {
+    sb0[0] = 0;
+    slo[0] = 0;
+    slo[1] = (uint32_t)a.lv[L].n;
+  }
+  wave_sync();
+  const int grp = lane / TPR, gl = lane % TPR;
+  constexpr int kGroups = kWave / TPR;
+  float4 qv[NV][2];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int c = gl + v * TPR;
+    qv[v][0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    qv[v][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (2 * c < ld4) qv[v][0] = sq4[2 * c];
+    if (2 * c + 1 < ld4) qv[v][1] = sq4[2 * c + 1];
+  }
+  unsigned long long rows_seen = 0;
+  int n_par = 1;
+  for (int lev = L; lev >= 1; --lev) {
+    const LevelView V = a.lv[lev];
+    const float* scr = qa.scr[lev];
+    const int64_t sbase = qi * qa.scr_ld[lev];
+    const uint32_t m = slo[n_par];
+    const uint32_t want = (uint32_t)qa.r_lev[lev];
+    uint64_t thr = ~0ull;
+    uint32_t cnt = 0;
+    int lo = 0;  // this lane's parent (candidates are walked forward)
+    if (scr != nullptr) {
+      for (uint32_t base = 0; base < m; base += 4 * kWave) {
+        if (cnt > kSelBuf - 4 * kWave) {
+          thr = wave_keep_smallest(buf, cnt, want, lane);
+          cnt = want;
+        }
+        uint32_t idx[4];
+        int64_t p[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          idx[u] = base + lane + u * kWave;
+          const uint32_t ic = idx[u] < m ? idx[u] : m - 1;
+          while (lo + 1 < n_par && slo[lo + 1] <= ic) ++lo;
+          p[u] = (int64_t)sb0[lo] + (ic - slo[lo]);
+        }
+        float dv[4];
+        int32_t id[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          dv[u] = scr[sbase + p[u]];
+          id[u] = V.orig[p[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint64_t key = ((uint64_t)__float_as_uint(dv[u]) << 32) | (uint32_t)id[u];
+          const bool pass = idx[u] < m && key < thr;
+          const uint64_t mk = __ballot(pass);
+          if (pass) buf[cnt + lanes_below(mk)] = key;
+          cnt += (uint32_t)__popcll(mk);
+        }
+      }
+    } else {
+      rows_seen += m;
+      for (uint32_t base = 0; base < m; base += kGroups) {
+        if (cnt > kSelBuf - kGroups) {
+          thr = wave_keep_smallest(buf, cnt, want, lane);
+          cnt = want;
+        }
+        const uint32_t idx = base + grp;
+        const uint32_t ic = idx < m ? idx : m - 1;
+        while (lo + 1 < n_par && slo[lo + 1] <= ic) ++lo;
+        const int64_t p = (int64_t)sb0[lo] + (ic - slo[lo]);
+        const uint4* row = reinterpret_cast<const uint4*>(V.protos_b + p * ldb);
+        uint4 x[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const int c = gl + v * TPR;
+          const uint4 t = row[c < nb ? c : 0];
+          x[v] = c < nb ? t : make_uint4(0, 0, 0, 0);
+        }
+        const int32_t id = V.orig[p];
+        float s0 = 0.f;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          s0 = acc4<0>(s0, bf16_lo4(make_uint2(x[v].x, x[v].y)), qv[v][0]);
+          s0 = acc4<0>(s0, bf16_lo4(make_uint2(x[v].z, x[v].w)), qv[v][1]);
+        }
+        s0 = group_sum<TPR>(s0);
+        const uint64_t key = ((uint64_t)__float_as_uint(s0) << 32) | (uint32_t)id;
+        const bool pass = gl == 0 && idx < m && key < thr;
+        const uint64_t mk = __ballot(pass);
+        if (pass) buf[cnt + lanes_below(mk)] = key;
+        cnt += (uint32_t)__popcll(mk);
+      }
+    }
+    wave_sync();
+    if (cnt > want) {
+      wave_keep_smallest(buf, cnt, want, lane);
+      cnt = want;
+    }
+    const uint32_t kept = cnt;
+    if (qa.sel) {
+      int32_t* so = qa.sel + ((int64_t)qi * L + (L - lev)) * qa.r;
+      for (int j = lane; j < qa.r; j += kWave)
+        so[j] = (uint32_t)j < kept ? (int32_t)(uint32_t)buf[j] : -1;
+    }
+    // the kept prototypes' children: counts, first positions, prefix
+    uint32_t c[kSelSlots], b0v[kSelSlots], pv[kSelSlots], off[kSelSlots], sum = 0;
+#pragma unroll
+    for (int t = 0; t < kSelSlots; ++t) {
+      const uint32_t e = lane * kSelSlots + t;
+      c[t] = 0;
+      b0v[t] = 0;
+      pv[t] = (uint32_t)V.n;
+      if (e < kept) {
+        const int32_t q = V.inv[(uint32_t)buf[e]];
+        b0v[t] = V.child_off[q];
+        c[t] = V.child_off[q + 1] - b0v[t];
+        pv[t] = (uint32_t)q;
+      }
+      sum += c[t];
+    }
+    uint32_t x = sum;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    const uint32_t total = __shfl(x, kWave - 1);
+    uint32_t acc = x - sum;
+#pragma unroll
+    for (int t = 0; t < kSelSlots; ++t) {
+      off[t] = acc;
+      acc += c[t];
+    }
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < kSelSlots; ++t) {
+      const uint32_t e = lane * kSelSlots + t;
+      if (e < kept) {
+        sb0[e] = b0v[t];
+        slo[e] = off[t];
+      }
+    }
+    if (lane == 0) {
+      if (kept > 0) {
+        slo[kept] = total;
+      } else {  // one empty range
+        sb0[0] = 0;
+        slo[0] = 0;
+        slo[1] = 0;
+      }
+    }
+    n_par = kept > 0 ? (int)kept : 1;
+    wave_sync();
+    if (lev == 1) {
+      // the kept leaves for the leaf-by-leaf data layer
+      const int64_t lb = qi * (int64_t)qa.leaf_cap;
+#pragma unroll
+      for (int t = 0; t < kSelSlots; ++t) {
+        const uint32_t e = lane * kSelSlots + t;
+        if (e < (uint32_t)qa.leaf_cap) {
+          const bool in = e < kept;
+          qa.leaf_b0[lb + e] = in ? b0v[t] : 0u;
+          qa.leaf_cnt[lb + e] = in ? c[t] : 0u;
+          qa.leaf_off[lb + e] = in ? off[t] : 0u;
+          qa.leaf_key[lb + e] = in && c[t] > 0 ? pv[t] : (uint32_t)V.n;
+          qa.leaf_val[lb + e] = (uint32_t)(lb + e);
+        }
+      }
+      if (lane == 0) {
+        qa.n_kept[qi] = kept;
+        qa.n_cand[qi] = kept > 0 ? total : 0u;
+        if (qa.rows) atomicAdd(qa.rows, rows_seen);
+      }
+    }
+  }
+}
+
 }  // namespace
 
 typedef __bf16 sbf16x8 __attribute__((ext_vector_type(8)));
@@ -1537,6 +1745,31 @@ void leaf_scan(const DescentArgs& a, const uint32_t* pair_key, const uint32_t* p
   else MASK_LEAF_SCAN(8, 4);
 #undef MASK_LEAF_SCAN
   check_launch("leaf_scan");
+}
+
+bool level_select(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
+  if (a.precision != MASK_BF16 || a.sparse || a.metric != MASK_L2 || qa.k_arr || qa.r_arr ||
+      qa.radius || qa.out_leaf || qa.out_off || qa.skip_empty || qa.leaf_mode != 1 ||
+      a.ld > kMaxBatchedLd || qa.leaf_cap > kSelLeaves || qa.r_lev[1] != qa.leaf_cap)
+    return false;
+  for (int l = 1; l <= a.n_levels; ++l)
+    if (qa.r_lev[l] < 1 || qa.r_lev[l] > kSelMax || qa.beam_e8[l] != 0) return false;
+  if (qa.nq <= 0) return true;
+  ScopedTiming timing("level_select", s);
+  const int64_t n_wg = (qa.nq + kSelWaves - 1) / kSelWaves;
+  const unsigned grid = (unsigned)(kXcds * ((n_wg + kXcds - 1) / kXcds));
+  // the descent's BF16 class for this row width (lanes per row, 16-byte
+  // chunks per lane)
+  const int c8 = a.ldb / 8;
+  if (c8 <= 1) k_level_select<1, 1><<<grid, kBlock, 0, s>>>(a, qa);
+  else if (c8 <= 2) k_level_select<1, 2><<<grid, kBlock, 0, s>>>(a, qa);
+  else if (c8 <= 4) k_level_select<1, 4><<<grid, kBlock, 0, s>>>(a, qa);
+  else if (c8 <= 8) k_level_select<2, 4><<<grid, kBlock, 0, s>>>(a, qa);
+  else if (c8 <= 12) k_level_select<4, 3><<<grid, kBlock, 0, s>>>(a, qa);
+  else if (c8 <= 16) k_level_select<4, 4><<<grid, kBlock, 0, s>>>(a, qa);
+  else k_level_select<8, 4><<<grid, kBlock, 0, s>>>(a, qa);
+  check_launch("level_select");
+  return true;
 }
 
 bool leaf_select(const DescentArgs& a, const QueryArgs& qa, hipStream_t s) {
