@@ -891,11 +891,15 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan(
         // every chunk of the class inside the row and the query (the usual
         // case): no selects on the query
         const bool full = NV * TPR == nb && 2 * NV * TPR <= ld4;
+        // when no group of this wave has a second row in the leaf, the wave
+        // evaluates one row per group
+        const bool two = __any(live[1]);
         for (int qq = j0; qq < j1; ++qq) {
           const float4* qr = s_q4 + qq * ld4;
           float acc[kRows];
 #pragma unroll
           for (int u = 0; u < kRows; ++u) acc[u] = 0.f;
+          if (two) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             const int c = gl + v * TPR;
@@ -919,6 +923,26 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan(
           for (int u = 0; u < kRows; ++u) {
             acc[u] = group_sum<TPR>(acc[u]);
             if (gl == 0 && live[u]) cand[s_base[qq] + (r0 + grp + u * kGroups - b0)] = acc[u];
+          }
+          } else {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const int c = gl + v * TPR;
+            float4 qa0, qa1;
+            if (full) {
+              qa0 = qr[2 * c];
+              qa1 = qr[2 * c + 1];
+            } else {
+              const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+              const float4 t0 = qr[min(2 * c, ld4 - 1)], t1 = qr[min(2 * c + 1, ld4 - 1)];
+              qa0 = 2 * c < ld4 ? t0 : z;
+              qa1 = 2 * c + 1 < ld4 ? t1 : z;
+            }
+            acc[0] = acc4<0>(acc[0], x[0][v][0], qa0);
+            acc[0] = acc4<0>(acc[0], x[0][v][1], qa1);
+          }
+          acc[0] = group_sum<TPR>(acc[0]);
+          if (gl == 0 && live[0]) cand[s_base[qq] + (r0 + grp - b0)] = acc[0];
           }
         }
       }
@@ -1414,7 +1438,7 @@ __device__ inline uint32_t bf16_rne_bits(float f) {
 // two BF16 terms) and prototype row l % 32, 8 consecutive dimensions each;
 // output register i of lane l is query 8 (i / 4) + 4 (l / 32) + i % 4,
 // prototype l % 32.
-constexpr int kScoreTiles = 8;
+constexpr int kScoreTiles = 16;
 constexpr int kScoreLdsRow = 256 + 8;  // BF16 per staged row (dense dims <= 256)
 
 template <int KS, bool V4>
