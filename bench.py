@@ -874,11 +874,12 @@ def main():
     if method == "batched":
         # the data layer runs in k_leaf_scan: per (query, row) pair of the kept
         # leaves, a difference, a product and a sum per dimension on the FP32
-        # vector units; the descent launch of the prototype levels and the
-        # data layer's launch (the re-rank set from those distances, one wave
-        # per query) are reported beside it
+        # vector units; the launches of the prototype levels and of the data
+        # layer (the re-rank set from those distances), one wave per query,
+        # are reported beside it
         l_cnt, l_ms = kt.get("leaf_scan", (0, 0.0))
         s_cnt, s_ms = kt.get("leaf_select", (0, 0.0))
+        v_cnt, v_ms = kt.get("level_select", (0, 0.0))
         pairs = kt.get("leaf_scan_pairs", (0, 0.0))[0]
         tfs = pairs * 3.0 * d / (l_ms * 1e-3) / 1e12 if l_ms else 0.0
         roof_query = {"bound": "alu", "kernel": "k_leaf_scan (leaf-batched data layer)",
@@ -890,7 +891,8 @@ def main():
                       "note": "FP32 direct form on the BF16 rows, 3 flops per dimension of every "
                               "(query, row) pair; packed FP32 instructions are not used, so the "
                               "issue limit is half the peak",
-                      "descent": {"launches": d_cnt, "avg_launch_ms": round(d_ms / max(1, d_cnt), 4)},
+                      "level_select": {"launches": v_cnt,
+                                       "avg_launch_ms": round(v_ms / max(1, v_cnt), 4)},
                       "leaf_select": {"launches": s_cnt,
                                       "avg_launch_ms": round(s_ms / max(1, s_cnt), 4)},
                       "traffic": traffic_bytes("leaf_scan", beams=list(beams), method=method),
