@@ -23,13 +23,17 @@ struct TimingState {
   struct Rec { std::string name; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<std::pair<std::string, hipEvent_t>> open;  // started, not yet ended
-  // [0] descent rows, [1..2] refine counts, [3] (query, row) pairs of the
-  // leaf-batched data layer; for level slot l of the k-means++ updates,
+  // [1..2] refine counts; for level slot l of the k-means++ updates,
   // [4 + 3 l] rows not ruled out by the triangle inequality, [5 + 3 l] rows
-  // read exactly (FP32), [6 + 3 l] D^2 lowered
+  // read exactly (FP32), [6 + 3 l] D^2 lowered; then the shards of the
+  // descent rows and of the (query, row) pairs of the leaf-batched data
+  // layer ([0] and [3] unused)
   unsigned long long* rows = nullptr;
 };
 constexpr int kCounters = 4 + 3 * kSeedSlots;
+constexpr int kRowShards0 = kCounters;                   // descent rows
+constexpr int kLeafShards0 = kCounters + kCounterShards;  // leaf-scan pairs
+constexpr int kCounterSlots = kCounters + 2 * kCounterShards;
 TimingState& timing() {
   static TimingState t;
   return t;
@@ -70,7 +74,9 @@ const char* level_scope_name(const char* prefix, int level) {
   return v[std::min(std::max(level, 0), kMaxLevels)].c_str();
 }
 
-unsigned long long* timing_row_counter() { return timing().on ? timing().rows : nullptr; }
+unsigned long long* timing_row_counter() {
+  return timing().on && timing().rows ? timing().rows + kRowShards0 : nullptr;
+}
 unsigned long long* timing_refine_counter() {
   return timing().on && timing().rows ? timing().rows + 1 : nullptr;
 }
@@ -78,7 +84,7 @@ unsigned long long* timing_seed_counter(int slot) {
   return timing().on && timing().rows ? timing().rows + 4 + 3 * slot : nullptr;
 }
 unsigned long long* timing_leaf_counter() {
-  return timing().on && timing().rows ? timing().rows + 3 : nullptr;
+  return timing().on && timing().rows ? timing().rows + kLeafShards0 : nullptr;
 }
 
 namespace {
@@ -568,8 +574,8 @@ mask_status mask_timing_enable(int32_t on) {
     for (auto& o : t.open) (void)hipEventDestroy(o.second);
     t.recs.clear();
     t.open.clear();
-    if (on && !t.rows) MASK_HIP(hipMalloc(&t.rows, kCounters * sizeof(unsigned long long)));
-    if (t.rows) MASK_HIP(hipMemset(t.rows, 0, kCounters * sizeof(unsigned long long)));
+    if (on && !t.rows) MASK_HIP(hipMalloc(&t.rows, kCounterSlots * sizeof(unsigned long long)));
+    if (t.rows) MASK_HIP(hipMemset(t.rows, 0, kCounterSlots * sizeof(unsigned long long)));
     t.on = on != 0;
     return MASK_OK;
   } catch (const Error& e) {
@@ -590,8 +596,12 @@ mask_status mask_timing_report(char* buf, int64_t cap, int64_t* needed) {
       a.first += 1;
       a.second += ms;
     }
-    unsigned long long cnt[kCounters] = {};
+    unsigned long long cnt[kCounterSlots] = {};
     if (t.rows) MASK_HIP(hipMemcpy(cnt, t.rows, sizeof(cnt), hipMemcpyDeviceToHost));
+    for (int i = 0; i < kCounterShards; ++i) {
+      cnt[0] += cnt[kRowShards0 + i];
+      cnt[3] += cnt[kLeafShards0 + i];
+    }
     std::ostringstream os;
     for (auto& kv : agg) os << kv.first << " " << kv.second.first << " " << kv.second.second << "\n";
     os << "descent_rows " << cnt[0] << " 0\n";

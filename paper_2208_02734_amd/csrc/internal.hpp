@@ -64,7 +64,11 @@ bool timing_enabled();
 // timing scope name), for levels 0 .. kMaxLevels.
 const char* level_scope_name(const char* prefix, int level);
 void timing_record(const char* name, hipStream_t s, bool start);
-// Device counter the descent kernel adds its evaluated candidate rows to
+// The two counters below are kCounterShards device slots each (a workgroup
+// adds to slot blockIdx.x % kCounterShards, so that one launch's workgroups
+// do not all wait on one address); the report sums them.
+constexpr int kCounterShards = 64;
+// Device counter the descent kernels add their evaluated candidate rows to
 // while timing is enabled (null otherwise).
 unsigned long long* timing_row_counter();
 // (query, row) pairs the leaf-batched data layer evaluates, or null

@@ -732,7 +732,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
         if (tid == 0) {
           qa.n_kept[qi] = nk;
           qa.n_cand[qi] = nk > 0 ? s_pre[nk] : 0u;
-          if (qa.rows) atomicAdd(qa.rows, rows_seen);
+          if (qa.rows) atomicAdd(qa.rows + blockIdx.x % kCounterShards, rows_seen);
         }
         return;  // every thread of the workgroup
       }
@@ -779,7 +779,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(
       if (range && tid == 0) qa.out_count[qi] = (int32_t)sh.in_range;
     }
   }
-  if (qa.rows && tid == 0) atomicAdd(qa.rows, rows_seen);
+  if (qa.rows && tid == 0) atomicAdd(qa.rows + blockIdx.x % kCounterShards, rows_seen);
 }
 
 template <int TPR, int NV, int U, bool B16, int BEAMB, int CAPB, int CAP, int MODE>
@@ -949,7 +949,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan(
     }
     j0 = j1;
   }
-  if (n_eval && tid == 0) atomicAdd(n_eval, evals);
+  if (n_eval && tid == 0) atomicAdd(n_eval + blockIdx.x % kCounterShards, evals);
 }
 
 // The data layer of the leaf-batched descent with one wave per query (four
@@ -1169,7 +1169,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_select(DescentArgs a, QueryArgs
       if (pass) buf[cnt + lanes_below(mk)] = key;
       cnt += (uint32_t)__popcll(mk);
     }
-    if (qa.rows && lane == 0) atomicAdd(qa.rows, (unsigned long long)m);
+    if (qa.rows && lane == 0) atomicAdd(qa.rows + blockIdx.x % kCounterShards, (unsigned long long)m);
   }
   wave_sync();
   if (cnt > want) {
@@ -1414,7 +1414,7 @@ __global__ __launch_bounds__(kBlock) void k_level_select(DescentArgs a, QueryArg
       if (lane == 0) {
         qa.n_kept[qi] = kept;
         qa.n_cand[qi] = kept > 0 ? total : 0u;
-        if (qa.rows) atomicAdd(qa.rows, rows_seen);
+        if (qa.rows) atomicAdd(qa.rows + blockIdx.x % kCounterShards, rows_seen);
       }
     }
   }
