@@ -71,14 +71,17 @@ TRAFFIC = [
      "sha256": "6b3f179b87b921c1e52a863e7485dc524324bb065fd6d036bb4445af341496dc",
      "fetch_kib": 497022.5, "write_kib": 39062.5},
     {"kernel": "descent_bf16", "beams": [3, 3, 24], "method": "screened", "file": "query.hip",
-     "sha256": "3036c2fe098111a2f3683330032ae760dccee6889ebd26333a0df844abdf25f6",
-     "fetch_kib": 6683187.3, "write_kib": 412503.2},
+     "sha256": "e0f7a2b94c30862438ef1501408fc7c31b2dc50e366719a7dd1b30fa90e5585b",
+     "fetch_kib": 6637585.9, "write_kib": 212504.2},
+    {"kernel": "leaf_scan", "beams": [3, 3, 24], "method": "batched", "file": "query.hip",
+     "sha256": "e0f7a2b94c30862438ef1501408fc7c31b2dc50e366719a7dd1b30fa90e5585b",
+     "fetch_kib": 2081616.3, "write_kib": 1500024.9},
 ]
 # The seeding update's counters were taken on a 1,000-draw level-1 seeding
 # (its launches read more rows than the timed builds' 10,000-draw ones):
 # measured over algorithmic bytes of the same launches.
 SEED_TRAFFIC_CHECK = {"file": "seeding.hip",
-                      "sha256": "e4cad6fbc462ac13f0e284e668290057ca3f40ba699c13ce9307dc5f54e599ad",
+                      "sha256": "f7efebaa341afc233e8a3f70c9115b687b29d873f52445c966f67a955b4c81ea",
                       "measured_bytes": 1.9577e12, "algorithmic_bytes": 1.9647e12,
                       "launches": 999}
 
