@@ -125,3 +125,32 @@ def test_batched_arguments(pk):
     ids, dist = pk.mask_query_batched(g, dev(Q[:0]), 5, [4])  # no queries
     assert ids.shape == (0, 5)
     g.free()
+
+
+def test_batched_row_counters(pk):
+    # the device counts behind the benchmark's query roofline, summed over
+    # their per-workgroup slots: the (query, row) pairs the leaf scan
+    # evaluates are the rows of every query's kept leaves, and the rows the
+    # levels read are the gathered level's candidates (the children of the
+    # kept level-2 prototypes) plus the data rows of the queries whose
+    # candidates are all ranked in FP32 (no re-rank set)
+    X, Q = _mixture(60_000, 48, 120, seed=1250, nq=3000)
+    gix = pk.mask_build(dev(X), [(20, 1000), (1, 400), (1, 40)], iters=4, seed=2,
+                        precision="bf16")
+    _, par0 = gix.export_level(1)
+    _, par1 = gix.export_level(2)
+    rows = np.bincount(par0, minlength=20_000)
+    kids = np.bincount(par1, minlength=20_000)
+    k, beams = 10, [3, 3, 24]
+    pk.mask_timing_enable(True)
+    ids, dist, sel = (host(t) for t in pk.mask_query_batched(gix, dev(Q), k, beams, debug=True))
+    rep = pk.mask_timing_report()
+    pk.mask_timing_enable(False)
+    s2, s1 = sel[:, 1, :3], sel[:, 2, :24]
+    m = np.where(s1 >= 0, rows[np.maximum(s1, 0)], 0).sum(axis=1)
+    assert rep["leaf_scan_pairs"][0] == int(m.sum())
+    gathered = int(np.where(s2 >= 0, kids[np.maximum(s2, 0)], 0).sum())
+    fp32_rows = int(m[m <= 4 * k].sum())  # default re-rank set 4 k
+    assert rep["descent_rows"][0] == gathered + fp32_rows
+    assert rep["leaf_scan"][0] == 1 and rep["leaf_select"][0] == 1 and rep["level_select"][0] == 1
+    gix.free()
