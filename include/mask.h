@@ -229,14 +229,16 @@ mask_status mask_query_screened_debug(const mask_index* ix, const mask_matrix* q
 
 /* mask_query_screened with the data layer (Algorithm 2's scan of the kept
  * leaves) evaluated leaf by leaf, for an index in the BF16 form with dim at
- * most 256: a first descent keeps each query's level-1 prototypes; the
- * (leaf, query) pairs are sorted by leaf, and a workgroup takes 32 of them
- * at a time and computes the BF16 distance of every row of each leaf to
- * each of its queries there (the descent's own arithmetic), so a leaf's
- * rows are read once per 32 queries that kept it instead of once per
- * query; a second descent ranks those distances (the re-rank set, the FP32
- * re-rank, the k nearest).  Results equal
- * mask_query_screened's bit for bit.  workspace: device memory of
+ * most 256: the prototype levels are descended first and keep each query's
+ * level-1 prototypes; the (leaf, query) pairs are sorted by leaf, and a
+ * workgroup takes 32 of them at a time and computes the BF16 distance of
+ * every row of each leaf to each of its queries there (the descent's own
+ * arithmetic), so a leaf's rows are read once per 32 queries that kept it
+ * instead of once per query; a last pass ranks those distances (the
+ * re-rank set, the FP32 re-rank, the k nearest).  The level and ranking
+ * passes take one wave per query when k and the re-rank set are at most 192
+ * and every beam at most 192 (the level-1 beam at most 128), else a
+ * workgroup per query.  Results equal mask_query_screened's bit for bit.  workspace: device memory of
  * workspace_bytes (256-byte aligned) that the call owns until it completes
  * on hip_stream; queries are processed in slices that fit it
  * (mask_batched_bytes gives the bytes of a slice; one query must fit).
@@ -246,8 +248,9 @@ mask_status mask_query_batched(const mask_index* ix, const mask_matrix* q, int32
                                const int32_t* r_levels, int32_t* out_ids, float* out_dist,
                                void* workspace, int64_t workspace_bytes, void* hip_stream);
 
-/* mask_query_batched plus the prototypes kept at every level, as
- * mask_query_screened_debug writes them. */
+/* mask_query_batched plus the prototypes kept at every level, laid out as
+ * mask_query_screened_debug writes them: the same sets, each in an order of
+ * its own. */
 mask_status mask_query_batched_debug(const mask_index* ix, const mask_matrix* q, int32_t k,
                                      const int32_t* r_levels, int32_t* out_ids, float* out_dist,
                                      int32_t* sel, void* workspace, int64_t workspace_bytes,
