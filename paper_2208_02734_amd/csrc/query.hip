@@ -1537,7 +1537,9 @@ void level_scores(const float* Q, int ldq, int64_t nq, int dim, const uint16_t* 
   if (ks <= 1) MASK_SCORES(1);
   else if (ks <= 2) MASK_SCORES(2);
   else if (ks <= 4) MASK_SCORES(4);
+  else if (ks <= 6) MASK_SCORES(6);
   else if (ks <= 8) MASK_SCORES(8);
+  else if (ks <= 12) MASK_SCORES(12);
   else MASK_SCORES(16);
 #undef MASK_SCORES
   check_launch("level_scores");
