@@ -894,7 +894,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan(
         // when no group of this wave has a second row in the leaf, the wave
         // evaluates one row per group
         const bool two = __any(live[1]);
-        for (int qq = j0; qq < j1; ++qq) {
+        // a wave with no row of the leaf in this pass has nothing to evaluate
+        const bool one = __any(live[0]);
+        for (int qq = j0; one && qq < j1; ++qq) {
           const float4* qr = s_q4 + qq * ld4;
           float acc[kRows];
 #pragma unroll
