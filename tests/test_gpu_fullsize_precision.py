@@ -1,8 +1,8 @@
 """Parity of the precision form at its full benchmark size (10,000,000 x 96
 Gaussian mixture, levels 10 x 10,000 -> 10,000 -> 100 from k-means++ seeds,
 30 Lloyd iterations; 100,000 queries), in the launch configurations the
-benchmark times: BF16 through the screened descent at beams 3/3/24 with the
-4k re-rank, and FP8 (per-row scale) through the gathered descent at 3/3/28
+benchmark times: BF16 through the leaf-batched descent (equal to the
+screened descent bit for bit) at beams 3/3/24 with the 4k re-rank, and FP8 (per-row scale) through the gathered descent at 3/3/28
 with the 4·k·r re-rank.  Checked on outputs the oracle can check one by
 one: sampled queries against the oracle's descent on the exported index
 (every level's selection a nearest set by FP64 distance to the rows as the
@@ -83,6 +83,15 @@ def test_fullsize_precision_sampled_queries(built):
                                       4, screened_levels=(2, 3), rows=rows)
     assert not fails, fails[:3]
     assert np.all(ids >= 0) and np.all(dist[:, 1:] >= dist[:, :-1])
+    # the leaf-batched descent the benchmark times (all 100,000 queries in one
+    # slice): the same rows and kept sets, and the oracle's check on its own
+    # selections
+    ib, db, sb = (host(t) for t in pk.mask_query_batched(gix, dev(Q), 10, BEAMS, debug=True))
+    assert np.array_equal(ib, ids) and np.array_equal(db, dist)
+    assert np.array_equal(np.sort(sb, axis=2), np.sort(sel, axis=2))
+    fails = check_lowp_against_oracle(oix, Q, 10, BEAMS, ib, db, sb, rank, _Bf16Rows(X),
+                                      4, screened_levels=(2, 3), rows=rows[:16])
+    assert not fails, fails[:3]
 
 
 def test_fullsize_precision_sampled_assignments(built):
