@@ -132,7 +132,8 @@ def parse():
     ap.add_argument("--forms", type=str, default="bf16,fp32,fp8")
     ap.add_argument("--sections", type=str, default="serve,small,sparse,cpu",
                     help="comma-separated: serve, small, sparse, cpu, scale, point, insert")
-    ap.add_argument("--detail", type=str, default=os.path.join("gpurun_out", "bench_detail.json"))
+    ap.add_argument("--detail", type=str, default="bench_detail.json",
+                    help="file for the full record (sweeps, serving, kernels); empty: none")
     ap.add_argument("--pmc-export", type=str, default="",
                     help="build the BF16 index and save it (npz) for --pmc-workload")
     ap.add_argument("--pmc-workload", type=str, default="",
