@@ -154,3 +154,24 @@ def test_batched_row_counters(pk):
     assert rep["descent_rows"][0] == gathered + fp32_rows
     assert rep["leaf_scan"][0] == 1 and rep["leaf_select"][0] == 1 and rep["level_select"][0] == 1
     gix.free()
+
+
+def test_batched_with_empty_leaves(pk):
+    # groups of 100 rows with 150 prototypes each: the first-k start repeats
+    # rows, so a third of the leaves end up empty; kept empty leaves (and
+    # queries whose kept leaves hold no row at all) give the same rows as the
+    # screened descent, -1 / inf past the candidates found
+    X, Q = _mixture(3000, 24, 30, seed=1260, nq=400)
+    gix = pk.mask_build(dev(X), [(30, 150), (1, 100)], iters=3, seed=6, precision="bf16")
+    _, par0 = gix.export_level(1)
+    assert np.sum(np.bincount(par0, minlength=4500) == 0) > 1000
+    for k, beams in ((10, [2, 3]), (10, [1, 1]), (5, [4, 40]), (60, [8, 120])):
+        ids, dist = _same(pk, gix, Q, k, beams)
+        assert np.all((ids >= 0) == np.isfinite(dist))
+    # empty leaves are among the kept ones (a repeated prototype ties with its
+    # twin, which owns the rows)
+    _, _, sel = (host(t) for t in pk.mask_query_batched(gix, dev(Q), 5, [4, 40], debug=True))
+    kept = sel[:, 1, :40]
+    sizes = np.bincount(par0, minlength=4500)
+    assert np.any(sizes[kept[kept >= 0]] == 0)
+    gix.free()
