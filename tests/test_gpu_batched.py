@@ -124,6 +124,9 @@ def test_batched_arguments(pk):
     assert pk.mask_batched_bytes(g, [4], 10) > pk.mask_batched_bytes(g, [4], 1) > 0
     ids, dist = pk.mask_query_batched(g, dev(Q[:0]), 5, [4])  # no queries
     assert ids.shape == (0, 5)
+    # one level: the leaves are the top level
+    _same(pk, g, Q, 5, [4])
+    _same(pk, g, Q, 3, [40])  # every leaf
     g.free()
 
 
