@@ -847,14 +847,28 @@ __global__ __launch_bounds__(kBlock) void k_leaf_scan(
   }
   __syncthreads();
   // the chunk's queries (zero past dim, as the descent stages them), many
-  // loads in flight per thread
-  const int per = (nqs * ld + kBlock - 1) / kBlock;
+  // loads in flight per thread; 16-byte loads when the rows allow them
+  if (dim % 4 == 0 && ldq % 4 == 0 && reinterpret_cast<uintptr_t>(Q) % 16 == 0) {
+    const int d4 = dim / 4;
+    const int per = (nqs * ld4 + kBlock - 1) / kBlock;
 #pragma unroll 4
-  for (int i = 0; i < per; ++i) {
-    const int e = tid + i * kBlock;
-    if (e < nqs * ld) {
-      const int qq = e / ld, c = e - qq * ld;
-      s_q[e] = c < dim ? Q[s_qrow[qq] + c] : 0.f;
+    for (int i = 0; i < per; ++i) {
+      const int e = tid + i * kBlock;
+      if (e < nqs * ld4) {
+        const int qq = e / ld4, c = e - qq * ld4;
+        s_q4[e] = c < d4 ? *reinterpret_cast<const float4*>(Q + s_qrow[qq] + 4 * c)
+                         : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+  } else {
+    const int per = (nqs * ld + kBlock - 1) / kBlock;
+#pragma unroll 4
+    for (int i = 0; i < per; ++i) {
+      const int e = tid + i * kBlock;
+      if (e < nqs * ld) {
+        const int qq = e / ld, c = e - qq * ld;
+        s_q[e] = c < dim ? Q[s_qrow[qq] + c] : 0.f;
+      }
     }
   }
   __syncthreads();
