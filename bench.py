@@ -71,11 +71,11 @@ TRAFFIC = [
      "sha256": "6b3f179b87b921c1e52a863e7485dc524324bb065fd6d036bb4445af341496dc",
      "fetch_kib": 497022.5, "write_kib": 39062.5},
     {"kernel": "descent_bf16", "beams": [3, 3, 24], "method": "screened", "file": "query.hip",
-     "sha256": "aa454e177d38bd353fb6a99cb57b2289e7705fe7e1ff557c6262a77e9a48e098",
-     "fetch_kib": 6631877.6, "write_kib": 212503.6},
+     "sha256": "7f72c9f96c2cd4ccdc312291938196b5f619c5f88db82a1fd898892ef4d7909a",
+     "fetch_kib": 6638924.3, "write_kib": 212504.0},
     {"kernel": "leaf_scan", "beams": [3, 3, 24], "method": "batched", "file": "query.hip",
-     "sha256": "aa454e177d38bd353fb6a99cb57b2289e7705fe7e1ff557c6262a77e9a48e098",
-     "fetch_kib": 2081776.0, "write_kib": 1525387.3},
+     "sha256": "7f72c9f96c2cd4ccdc312291938196b5f619c5f88db82a1fd898892ef4d7909a",
+     "fetch_kib": 2084434.9, "write_kib": 1530908.8},
 ]
 # The seeding update's counters were taken on a 1,000-draw level-1 seeding
 # (its launches read more rows than the timed builds' 10,000-draw ones):
