@@ -1502,6 +1502,15 @@ __global__ __launch_bounds__(kBlock) void k_level_scores(
     __builtin_memcpy(&a_lo[ks], lw, sizeof(sbf16x8));
   }
   qsq += __shfl_xor(qsq, 32);  // the two halves hold disjoint dimensions of row r
+  // |q|^2 of the 16 output rows of this lane, and their offsets in S
+  float qn_row[16];
+  int64_t so_row[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = 8 * (i / 4) + 4 * h + (i % 4);
+    qn_row[i] = __shfl(qsq, row);
+    so_row[i] = (q0 + row) * ldS;
+  }
   const int c8 = ldb / 8;      // 16-byte chunks per prototype row
   for (int t = 0; t < kScoreTiles; ++t) {
     const int64_t p0 = pb + 32 * t;
@@ -1528,12 +1537,12 @@ __global__ __launch_bounds__(kBlock) void k_level_scores(
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi[ks], b, acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_lo[ks], b, acc, 0, 0, 0);
     }
+    const int64_t pp = p0 + r;
+    const float pnp = pp < n ? pn[pp] : 0.f;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int row = 8 * (i / 4) + 4 * h + (i % 4);
-      const float qn = __shfl(qsq, row);
-      const int64_t qq = q0 + row, pp = p0 + r;
-      if (qq < nq && pp < n) S[qq * ldS + pp] = fmaxf(0.f, qn + pn[pp] - 2.f * acc[i]);
+      if (q0 + row < nq && pp < n) S[so_row[i] + pp] = fmaxf(0.f, qn_row[i] + pnp - 2.f * acc[i]);
     }
   }
 }
