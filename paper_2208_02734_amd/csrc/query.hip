@@ -1131,6 +1131,10 @@ __global__ __launch_bounds__(kBlock) void k_leaf_select(DescentArgs a, QueryArgs
   uint64_t thr = ~0ull;
   uint32_t cnt = 0;
   int lo = 0;  // this lane's leaf (candidates are walked forward)
+  // the first candidate of the next leaf, and position - candidate index in
+  // this one (modulo 2^32)
+  uint32_t nxt = nk > 1 ? slo[1] : UINT32_MAX;
+  uint32_t shift = nk > 0 ? sb0[0] - slo[0] : 0u;
   if (low) {
     // the BF16 distances the leaf scan wrote: four candidates per lane and step
     const int64_t cbase = (int64_t)qa.cand_off[qi];
@@ -1145,8 +1149,12 @@ __global__ __launch_bounds__(kBlock) void k_leaf_select(DescentArgs a, QueryArgs
       for (int u = 0; u < 4; ++u) {
         idx[u] = base + lane + u * kWave;
         const uint32_t ic = idx[u] < m ? idx[u] : m - 1;
-        while (lo + 1 < nk && slo[lo + 1] <= ic) ++lo;
-        p[u] = (int64_t)sb0[lo] + (ic - slo[lo]);
+        while (ic >= nxt) {
+          ++lo;
+          shift = sb0[lo] - slo[lo];
+          nxt = lo + 1 < nk ? slo[lo + 1] : UINT32_MAX;
+        }
+        p[u] = (int64_t)(uint32_t)(shift + ic);
       }
       float dv[4];
       int32_t id[4];
@@ -1173,8 +1181,12 @@ __global__ __launch_bounds__(kBlock) void k_leaf_select(DescentArgs a, QueryArgs
       }
       const uint32_t idx = base + grp;
       const uint32_t ic = idx < m ? idx : m - 1;
-      while (lo + 1 < nk && slo[lo + 1] <= ic) ++lo;
-      const int64_t p = (int64_t)sb0[lo] + (ic - slo[lo]);
+      while (ic >= nxt) {
+        ++lo;
+        shift = sb0[lo] - slo[lo];
+        nxt = lo + 1 < nk ? slo[lo + 1] : UINT32_MAX;
+      }
+      const int64_t p = (int64_t)(uint32_t)(shift + ic);
       const float4* row = reinterpret_cast<const float4*>(V.protos + p * ld);
       float s0 = 0.f;
       for (int c4 = gl; c4 < ld4; c4 += TPR) s0 = acc4<0>(s0, row[c4], sq4[c4]);
@@ -1287,6 +1299,10 @@ __global__ __launch_bounds__(kBlock) void k_level_select(DescentArgs a, QueryArg
     uint64_t thr = ~0ull;
     uint32_t cnt = 0;
     int lo = 0;  // this lane's parent (candidates are walked forward)
+    // the first candidate of the next parent, and position - candidate index
+    // in this one (modulo 2^32)
+    uint32_t nxt = n_par > 1 ? slo[1] : UINT32_MAX;
+    uint32_t shift = sb0[0] - slo[0];
     if (scr != nullptr) {
       for (uint32_t base = 0; base < m; base += 4 * kWave) {
         if (cnt > kSelBuf - 4 * kWave) {
@@ -1299,8 +1315,12 @@ __global__ __launch_bounds__(kBlock) void k_level_select(DescentArgs a, QueryArg
         for (int u = 0; u < 4; ++u) {
           idx[u] = base + lane + u * kWave;
           const uint32_t ic = idx[u] < m ? idx[u] : m - 1;
-          while (lo + 1 < n_par && slo[lo + 1] <= ic) ++lo;
-          p[u] = (int64_t)sb0[lo] + (ic - slo[lo]);
+          while (ic >= nxt) {
+            ++lo;
+            shift = sb0[lo] - slo[lo];
+            nxt = lo + 1 < n_par ? slo[lo + 1] : UINT32_MAX;
+          }
+          p[u] = (int64_t)(uint32_t)(shift + ic);
         }
         float dv[4];
         int32_t id[4];
@@ -1327,8 +1347,12 @@ __global__ __launch_bounds__(kBlock) void k_level_select(DescentArgs a, QueryArg
         }
         const uint32_t idx = base + grp;
         const uint32_t ic = idx < m ? idx : m - 1;
-        while (lo + 1 < n_par && slo[lo + 1] <= ic) ++lo;
-        const int64_t p = (int64_t)sb0[lo] + (ic - slo[lo]);
+        while (ic >= nxt) {
+          ++lo;
+          shift = sb0[lo] - slo[lo];
+          nxt = lo + 1 < n_par ? slo[lo + 1] : UINT32_MAX;
+        }
+        const int64_t p = (int64_t)(uint32_t)(shift + ic);
         const uint4* row = reinterpret_cast<const uint4*>(V.protos_b + p * ldb);
         uint4 x[NV];
 #pragma unroll
