@@ -71,11 +71,11 @@ TRAFFIC = [
      "sha256": "6b3f179b87b921c1e52a863e7485dc524324bb065fd6d036bb4445af341496dc",
      "fetch_kib": 497022.5, "write_kib": 39062.5},
     {"kernel": "descent_bf16", "beams": [3, 3, 24], "method": "screened", "file": "query.hip",
-     "sha256": "1e26f4a2aba4078e947d7aeceb305bff09cf375bb6f49acb7f8505f317d0a2de",
-     "fetch_kib": 6634839.4, "write_kib": 212504.1},
+     "sha256": "0de2e4d1f860ef08422d70edcca2f2bd961b745395e82ff69006c81f55d78fc2",
+     "fetch_kib": 6641703.1, "write_kib": 212503.9},
     {"kernel": "leaf_scan", "beams": [3, 3, 24], "method": "batched", "file": "query.hip",
-     "sha256": "1e26f4a2aba4078e947d7aeceb305bff09cf375bb6f49acb7f8505f317d0a2de",
-     "fetch_kib": 2085249.8, "write_kib": 1530929.6},
+     "sha256": "0de2e4d1f860ef08422d70edcca2f2bd961b745395e82ff69006c81f55d78fc2",
+     "fetch_kib": 2083902.9, "write_kib": 1530912.2},
 ]
 # The seeding update's counters were taken on a 1,000-draw level-1 seeding
 # (its launches read more rows than the timed builds' 10,000-draw ones):
